@@ -1,0 +1,212 @@
+/*
+ * pa.h -- C ABI of the MI355X (gfx950) pixel array library, libpa.so.
+ *
+ * The pixel array method (Spivak, Dobson, Kumari, Wu, arXiv 1609.00061)
+ * solves a system of relations on a bounding box for a chosen set of exposed
+ * variables:
+ *   1. every relation R_i is plotted as a Boolean array over the pixels of its
+ *      variables (Sec. 3.2, "Plotting relations as arrays"; the pixel grid is
+ *      eqn Pixel_def: resolution r cuts [a, b) into r pixels of width
+ *      (b - a) / r);
+ *   2. the plots are combined by generalized array multiplication
+ *      (Sec. 3.3, Alg. "Generalized array multiplication", eqn GAM):
+ *      A'(e') = OR over link entries e with Entr'(e) = e' of AND_i A_i(e_i),
+ *      i.e. latent variables are projected out by OR-of-ANDs;
+ *   3. by associativity (Thm "associative") the multiplication is evaluated
+ *      as a cluster tree (Sec. 3.5) of pairwise contractions.
+ *
+ * Plotting rule of this library: a relation f(vars) = 0 is evaluated at the
+ * pixel corners x_k = a + k*delta (k = 0..r) and a pixel (a closed cell) is
+ * set iff among its 2^n corners one has f <= 0 and one has f >= 0 (a corner
+ * where f is NaN counts as neither).  The paper permits any sufficiently fast
+ * and accurate plotting method (Sec. 3.6).  The sign of f at a corner is the
+ * sign of a canonical FP64 value: nested Horner with correctly rounded fma in
+ * the relation's declared variable order (last variable outermost), i.e.
+ *   f = sum_i A_i(x_0..x_{n-2}) x_{n-1}^i,  p = A_d, p = fma(p, x_{n-1}, A_i),
+ * every A_i evaluated by the same rule one variable down.  With
+ * PA_PLOT_FP32_ESCALATE the corners are evaluated in FP32 first and only
+ * corners whose |f| does not exceed a rigorous FP32 error bound are
+ * re-evaluated canonically in FP64, so the result is bit-identical to
+ * PA_PLOT_FP64.
+ *
+ * ------------------------------------------------------------------------
+ * Bit-array layout (pa_bitarray).  An n-dimensional Boolean array with dims
+ * d_0..d_{n-1} is stored row-major; the LAST axis is bit-packed LSB-first into
+ * 32-bit words and every row of the last axis occupies `row_words` words,
+ * which must equal pa_row_words(d_{n-1}) = 2 * ceil(d_{n-1} / 64) (rows are
+ * padded to 64 bits).  Element (i_0..i_{n-1}) is bit (i_{n-1} % 32) of word
+ *   ((i_0 * d_1 + i_1) * ... * d_{n-2} + i_{n-2}) * row_words + i_{n-1} / 32.
+ * Padding bits must be zero in inputs and are zero in outputs.  A 0-dim
+ * array is one word whose bit 0 is the value ("has a solution in the box",
+ * fn. to Def. "entries").  `data` is a DEVICE pointer owned by the caller.
+ *
+ * Ownership and streams.  Host arrays passed in (axes, coefficients,
+ * variable lists) are read during the call only.  Device buffers (outputs,
+ * optional workspace) belong to the caller.  Work is enqueued on `stream`
+ * (a hipStream_t; NULL means the default stream); calls that fill a
+ * pa_report synchronize `stream` before returning.  A plan may be executed
+ * repeatedly; executing one plan concurrently on two streams is a race
+ * (its workspace is shared).
+ *
+ * Errors.  Every entry point returns a pa_status; nothing throws across the
+ * ABI.  pa_last_error() returns a thread-local message for the last failure.
+ */
+#ifndef PA_H
+#define PA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PA_MAX_DIMS 12        /* max rank of any array handled */
+#define PA_MAX_ARITY 3        /* max variables of one relation */
+#define PA_MAX_DEGREE 4       /* max total degree of a relation */
+#define PA_MAX_VARS 64        /* max variables of one system */
+#define PA_MAX_RELATIONS 32   /* max relations of one system */
+
+typedef enum {
+    PA_OK = 0,
+    PA_EINVAL = 1,            /* invalid argument (see each entry point)          */
+    PA_ENOMEM = 2,            /* workspace too small, allocation or size cap hit  */
+    PA_EHIP = 3,              /* HIP runtime error (no device, launch failure...) */
+    PA_EUNSUPPORTED = 4       /* valid but outside what this build implements     */
+} pa_status;
+
+/* One variable's discretization: a port's bounds and resolution
+ * (Def. "pack"): range [lo, hi] with lo <= hi, resolution res >= 2. */
+typedef struct {
+    double lo, hi;
+    int32_t res;
+    int32_t reserved;
+} pa_axis;
+
+/* A polynomial relation f(x_{vars[0]}, ..., x_{vars[arity-1]}) = 0.
+ * coef has C(arity + degree, degree) entries in graded-lex order of the
+ * monomials in the declared variable order: total degree ascending, then
+ * lexicographically descending exponent tuples (for (x, y), degree 3:
+ * 1, x, y, x^2, xy, y^2, x^3, x^2y, xy^2, y^3).  vars are distinct. */
+typedef struct {
+    int32_t arity;            /* 1..PA_MAX_ARITY  */
+    int32_t degree;           /* 0..PA_MAX_DEGREE */
+    const int32_t *vars;      /* host, arity entries, ids in [0, n_vars) */
+    const double *coef;       /* host                                     */
+} pa_relation;
+
+/* Bit-packed Boolean array, layout above.  data is a device pointer. */
+typedef struct {
+    void *data;
+    int32_t ndim;
+    int32_t dims[PA_MAX_DIMS];
+    int64_t row_words;
+} pa_bitarray;
+
+/* A system: the inner packs (relations) of a wiring diagram (Def. "wd") over
+ * n_vars links; every variable must occur in some relation. */
+typedef struct {
+    int32_t n_vars;
+    const pa_axis *axes;      /* host, n_vars entries */
+    int32_t n_rel;
+    const pa_relation *rel;   /* host, n_rel entries  */
+} pa_system;
+
+enum { PA_ORDER_GREEDY = 0, PA_ORDER_EXHAUSTIVE = 1, PA_ORDER_LEARNED = 2, PA_ORDER_GIVEN = 3 };
+enum { PA_PLOT_FP32_ESCALATE = 0, PA_PLOT_FP64 = 1 };
+
+typedef struct pa_model pa_model;   /* learned contraction-order cost model */
+
+typedef struct {
+    int32_t order_policy;     /* PA_ORDER_*                                         */
+    int32_t n_given;          /* PA_ORDER_GIVEN: number of merges (n_rel - 1)       */
+    const int32_t *given;     /* PA_ORDER_GIVEN: 2*n_given factor ids; relations are
+                                 factors 0..n_rel-1 and merge t creates factor
+                                 n_rel + t from the two listed factors             */
+    int32_t precision;        /* PA_PLOT_*                                          */
+    int32_t audit;            /* 1: also evaluate every corner in FP64 and count
+                                 FP32/FP64 sign disagreements (slow; diagnostics)  */
+    int32_t timing;           /* 1: time plot and contraction phases with events    */
+    int32_t plain;            /* 1: the plain GPU path (one launch per step, default
+                                 tiles, no fused plotting of all relations)         */
+    const pa_model *model;    /* PA_ORDER_LEARNED: the cost model                   */
+    void *workspace;          /* optional device workspace (NULL: library-owned)    */
+    size_t workspace_bytes;
+} pa_opts;
+
+typedef struct {
+    int64_t corners;                       /* corners evaluated                            */
+    int64_t corners_flagged;               /* corners escalated to FP64                    */
+    int64_t corners_disagree;              /* audit: sign(FP32) != sign(FP64), all corners */
+    int64_t corners_disagree_unflagged;    /* audit: same among non-escalated corners (0)  */
+    int64_t nnz_out;                       /* set bits of the output                       */
+    int32_t n_steps;                       /* pairwise contractions executed               */
+    int32_t n_launches;                    /* kernel launches enqueued                     */
+    int32_t merges[2 * PA_MAX_RELATIONS];  /* the chosen clustering, PA_ORDER_GIVEN format */
+    double cost_macs;                      /* sum over steps of the product of the
+                                              resolutions of the step's links
+                                              (eqn naive_cost)                            */
+    double t_plot_ms, t_contract_ms, t_plan_ms;
+} pa_report;
+
+typedef struct pa_plan pa_plan;
+
+/* 2 * ceil(d / 64): words per row of a last axis of length d (d >= 1). */
+int64_t pa_row_words(int32_t d);
+/* Total words of an array with the given dims (1 for ndim == 0). */
+int64_t pa_array_words(int32_t ndim, const int32_t *dims);
+
+/* Plot one relation (Sec. 3.2) on the pixel grid of its variables.
+ * axes_of_vars[j] is the discretization of the relation's j-th variable.
+ * out: dims = (res of vars[0], ..., res of vars[arity-1]), the declared order.
+ * EINVAL: arity/degree out of range, res < 2, lo > hi, non-finite bounds,
+ * repeated variable, out dims or row_words mismatching.  report may be NULL. */
+int pa_plot_relation(const pa_relation *rel, const pa_axis *axes_of_vars, const pa_opts *opts,
+                     pa_bitarray *out, pa_report *report, void *stream);
+
+/* Generalized array multiplication of two packs (eqn GAM with two inner
+ * packs): C(out_vars) = OR over every variable of A or B not in out_vars of
+ * A(a_vars) AND B(b_vars).  Variable ids are arbitrary labels in
+ * [0, PA_MAX_VARS); a variable shared by A and B must have the same length in
+ * both.  out_vars lists distinct variables of A or B, in C's axis order.
+ * B may be NULL (then b_vars is ignored: a projection/permutation of A).
+ * EINVAL on rank, dims, row_words or label mismatch; ENOMEM if the internal
+ * workspace cannot be allocated. */
+int pa_contract(const pa_bitarray *A, const int32_t *a_vars, const pa_bitarray *B, const int32_t *b_vars,
+                const int32_t *out_vars, int32_t n_out, pa_bitarray *C, const pa_opts *opts, void *stream);
+
+/* Plan a whole solve: choose the cluster tree (opts->order_policy), lay out
+ * every intermediate, upload coefficient and axis tables and size the
+ * workspace.  exposed lists the outer pack's variables in the output's axis
+ * order (n_exposed may be 0: one-bit output).  EINVAL: invalid system (as for
+ * pa_plot_relation, plus variable in no relation, exposed repeated or out of
+ * range, n_rel > PA_MAX_RELATIONS); ENOMEM: workspace or intermediate size
+ * cap exceeded. */
+int pa_plan_create(const pa_system *sys, const int32_t *exposed, int32_t n_exposed, const pa_opts *opts,
+                   pa_plan **plan);
+/* Enqueue the plotting and all contractions; out dims = resolutions of the
+ * exposed variables in the given order.  report (may be NULL) is filled after
+ * synchronizing the stream. */
+int pa_plan_execute(pa_plan *plan, pa_bitarray *out, pa_report *report, void *stream);
+/* Device bytes of the plan's workspace (intermediates + tables). */
+size_t pa_plan_workspace_bytes(const pa_plan *plan);
+/* JSON description of the plan (steps, kernels, layouts, costs) into buf;
+ * returns the length needed (excluding the NUL). Host-only, no device use. */
+int64_t pa_plan_describe(const pa_system *sys, const int32_t *exposed, int32_t n_exposed, const pa_opts *opts,
+                         char *buf, int64_t buf_len);
+void pa_plan_destroy(pa_plan *plan);
+
+/* pa_plan_create + pa_plan_execute + pa_plan_destroy. */
+int pa_solve_system(const pa_system *sys, const int32_t *exposed, int32_t n_exposed, const pa_opts *opts,
+                    pa_bitarray *out, pa_report *report, void *stream);
+
+/* Number of set bits of a device bit array (padding is zero by contract). */
+int pa_popcount(const pa_bitarray *a, int64_t *count, void *stream);
+
+/* Thread-local message describing the last error. */
+const char *pa_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PA_H */

@@ -33,7 +33,7 @@ _lib = None
 DEFAULT_THREADS = max(1, min(16, os.cpu_count() or 1))
 
 
-def build(force: bool = False) -> str:
+def build_lib(force: bool = False) -> str:
     """Compile pa_oracle.c with gcc (no FMA contraction, IEEE semantics)."""
     from .build import build_oracle
     return build_oracle(force=force)
@@ -43,7 +43,7 @@ def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(_LIB_PATH):
-            build()
+            build_lib()
         L = ctypes.CDLL(_LIB_PATH)
         dp, ip, ucp = ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int), ctypes.c_void_p
         L.orc_axis.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_int, dp]

@@ -1,0 +1,1011 @@
+// Plan construction (layouts of every intermediate and the op list) and
+// execution, plus the C ABI entry points that use them.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "pa_plan.h"
+
+namespace pa {
+
+#define HIP_TRY(expr)                                                                                   \
+    do {                                                                                                \
+        hipError_t _e = (expr);                                                                         \
+        if (_e != hipSuccess) return fail(PA_EHIP, std::string(#expr) + ": " + hipGetErrorString(_e)); \
+    } while (0)
+
+static std::vector<int> mask_list(uint64_t m) {
+    std::vector<int> out;
+    for (int v = 0; v < 64; ++v)
+        if ((m >> v) & 1) out.push_back(v);
+    return out;
+}
+
+static uint64_t list_mask(const std::vector<int> &l) {
+    uint64_t m = 0;
+    for (int v : l) m |= 1ull << v;
+    return m;
+}
+
+
+// The latent variable to pack (bit axis) among `cands`: least row padding,
+// then larger resolution, then lower id.
+static int pick_packed(uint64_t cands, const std::vector<int64_t> &res) {
+    int best = -1;
+    int64_t bw = 0, br = 0;
+    for (int v : mask_list(cands)) {
+        const int64_t waste = row_words_of(res[v]) * 32 - res[v];
+        if (best < 0 || waste < bw || (waste == bw && res[v] > br)) {
+            best = v;
+            bw = waste;
+            br = res[v];
+        }
+    }
+    return best;
+}
+
+static std::vector<int> move_last(std::vector<int> l, int v) {
+    auto it = std::find(l.begin(), l.end(), v);
+    if (it != l.end()) {
+        l.erase(it);
+        l.push_back(v);
+    }
+    return l;
+}
+
+// A layout requirement on a node's output array.
+struct Constraint {
+    int kind = 0;             // 0 free, 1 full order, 2 packed variable (+ hint for the axis before it)
+    std::vector<int> order;
+    int packed = -1, hint = -1;
+    static Constraint full(const std::vector<int> &o) {
+        Constraint c;
+        c.kind = 1;
+        c.order = o;
+        return c;
+    }
+    static Constraint pk(int v, int hint) {
+        Constraint c;
+        c.kind = 2;
+        c.packed = v;
+        c.hint = hint;
+        return c;
+    }
+    std::string key() const {
+        std::string s = std::to_string(kind) + ":" + std::to_string(packed) + ":" + std::to_string(hint) + ":";
+        for (int v : order) s += std::to_string(v) + ",";
+        return s;
+    }
+};
+
+// Output order under a constraint, from a preferred order.
+static std::vector<int> order_under(const Constraint &cons, const std::vector<int> &pref) {
+    if (cons.kind == 1) return cons.order;
+    if (cons.kind == 2) {
+        std::vector<int> o = pref;
+        if (cons.hint >= 0 && std::find(o.begin(), o.end(), cons.hint) != o.end()) o = move_last(o, cons.hint);
+        return move_last(o, cons.packed);
+    }
+    return pref;
+}
+
+static bool fits_gemm(const std::vector<int> &L, uint64_t b, uint64_t ea, uint64_t eb) {
+    const int nb = __builtin_popcountll(b), na = __builtin_popcountll(ea), nn = __builtin_popcountll(eb);
+    if ((int)L.size() != nb + na + nn || nn == 0) return false;
+    std::vector<int> p0(L.begin(), L.begin() + nb), p1(L.begin() + nb, L.begin() + nb + na),
+        p2(L.begin() + nb + na, L.end());
+    return list_mask(p0) == b && list_mask(p1) == ea && list_mask(p2) == eb;
+}
+
+static std::vector<std::vector<int>> orders_of(uint64_t m, int packed_last, size_t cap) {
+    std::vector<int> l = mask_list(m);
+    std::vector<std::vector<int>> out;
+    std::sort(l.begin(), l.end());
+    do {
+        if (packed_last < 0 || l.back() == packed_last) out.push_back(l);
+        if (out.size() >= cap) break;
+    } while (std::next_permutation(l.begin(), l.end()));
+    return out;
+}
+
+// Rough time model (microseconds) used to rank layout choices: MFMA GEMM,
+// word-streaming and bit-level contraction throughputs, HBM traffic and a
+// launch overhead.  Only the ranking matters.
+static double est_op_us(int kind, double macs, double bytes) {
+    const double launch = 4.0;
+    double rate;   // MAC per microsecond
+    switch (kind) {
+        case 0: rate = 1.0e9; break;      // MFMA
+        case 1: rate = 4.0e7; break;      // word streaming
+        default: rate = 5.0e5; break;     // bit level
+    }
+    return launch + macs / rate + bytes / 4.0e6;
+}
+
+struct Choice {
+    int kind = -1;            // 0 gemm, 1 stream (mode chosen from layouts), 2 leaf
+    int roleB = -1;           // gemm: 0 -> c0 is the B operand, 1 -> c1 is
+    std::vector<int> oc;      // output order
+    Constraint cx, cy;        // child constraints (c0, c1)
+    int nb = 0, nm = 0;       // gemm group sizes
+    double cost = 0.0;
+};
+
+struct Builder {
+    pa_plan *P;
+    const pa_system *sys;
+    std::map<std::string, Choice> memo;
+
+    int new_buf(const Layout &L) {
+        P->buf_layout.push_back(L);
+        P->buf_words.push_back(L.words);
+        P->buf_off.push_back(-1);
+        return (int)P->buf_layout.size() - 1;
+    }
+    Layout lay(const std::vector<int> &o) { return make_layout(o, P->si.res); }
+    double bytes_of(uint64_t m) { return mask_cost(m, P->si) / 8.0; }
+
+    // ------------------------------------------------------------ search
+    const Choice &best(int id, const Constraint &cons) {
+        const std::string key = std::to_string(id) + "|" + cons.key();
+        auto it = memo.find(key);
+        if (it != memo.end()) return it->second;
+        Choice ch = decide(id, cons);
+        return memo.emplace(key, ch).first->second;
+    }
+
+    Choice decide(int id, const Constraint &cons) {
+        const Node &nd = P->tree.nodes[id];
+        const auto &si = P->si;
+        Choice bestc;
+        bestc.cost = 1e300;
+        if (nd.leaf >= 0) {
+            const int r = nd.leaf;
+            const uint64_t priv = si.rel_vars[r] & ~nd.q;
+            std::vector<int> qdecl;
+            for (int v : si.rel_list[r])
+                if ((nd.q >> v) & 1) qdecl.push_back(v);
+            bestc.kind = 2;
+            bestc.oc = order_under(cons, qdecl);
+            const double full = mask_cost(si.rel_vars[r], si);
+            bestc.cost = est_op_us(1, full / 64.0, full / 8.0);      // plotting ~ one pass
+            if (priv) bestc.cost += est_op_us(1, full, full / 8.0);
+            return bestc;
+        }
+        const Node &X = P->tree.nodes[nd.c0], &Y = P->tree.nodes[nd.c1];
+        const uint64_t qx = X.q, qy = Y.q, q = nd.q;
+        const uint64_t b = q & qx & qy, k = qx & qy & ~q, ex = qx & ~qy, ey = qy & ~qx;
+        const double macs = mask_cost(qx | qy, si);
+        const double io = bytes_of(qx) + bytes_of(qy) + bytes_of(q);
+        // ---- dense Boolean GEMM on MFMA
+        if (k && ex && ey && mask_cost(k, si) >= 32 && mask_cost(ex, si) >= 32 && mask_cost(ey, si) >= 32) {
+            for (int roleB = 0; roleB < 2; ++roleB) {
+                const uint64_t ea = roleB ? ex : ey, eb = roleB ? ey : ex;
+                std::vector<int> bo, mo, no;
+                if (cons.kind == 1) {
+                    if (!fits_gemm(cons.order, b, ea, eb)) continue;
+                    const int nb = __builtin_popcountll(b), na = __builtin_popcountll(ea);
+                    bo.assign(cons.order.begin(), cons.order.begin() + nb);
+                    mo.assign(cons.order.begin() + nb, cons.order.begin() + nb + na);
+                    no.assign(cons.order.begin() + nb + na, cons.order.end());
+                } else {
+                    if (cons.kind == 2 && !((eb >> cons.packed) & 1)) continue;
+                    bo = mask_list(b);
+                    mo = mask_list(ea);
+                    no = mask_list(eb);
+                    no = move_last(no, cons.kind == 2 ? cons.packed : pick_packed(eb, si.res));
+                }
+                for (const auto &ko : orders_of(k, -1, 24)) {
+                    std::vector<int> oa = bo, ob = bo, oc = bo;
+                    oa.insert(oa.end(), mo.begin(), mo.end());
+                    oa.insert(oa.end(), ko.begin(), ko.end());
+                    ob.insert(ob.end(), no.begin(), no.end());
+                    ob.insert(ob.end(), ko.begin(), ko.end());
+                    oc.insert(oc.end(), mo.begin(), mo.end());
+                    oc.insert(oc.end(), no.begin(), no.end());
+                    const Constraint ca = Constraint::full(oa), cb = Constraint::full(ob);
+                    const int ida = roleB ? nd.c0 : nd.c1, idb = roleB ? nd.c1 : nd.c0;
+                    // padding of the packed k axis wastes MFMA work
+                    const int kl = ko.back();
+                    const double kpad = (double)(row_words_of(si.res[kl]) * 32) / (double)si.res[kl];
+                    const double c = est_op_us(0, macs * kpad, io) + best(ida, ca).cost + best(idb, cb).cost;
+                    if (c < bestc.cost) {
+                        bestc = Choice();
+                        bestc.kind = 0;
+                        bestc.roleB = roleB;
+                        bestc.oc = oc;
+                        bestc.cx = roleB ? ca : cb;
+                        bestc.cy = roleB ? cb : ca;
+                        bestc.nb = (int)bo.size();
+                        bestc.nm = (int)mo.size();
+                        bestc.cost = c;
+                    }
+                }
+            }
+        }
+        // ---- bitwise streaming contractions
+        std::vector<int> pref = mask_list(b);
+        for (int v : mask_list(ex)) pref.push_back(v);
+        for (int v : mask_list(ey)) pref.push_back(v);
+        const std::vector<int> oc = order_under(cons, pref);
+        const int cp = oc.empty() ? -1 : oc.back();
+        if (k) {
+            for (int kp : mask_list(k)) {
+                const Constraint c0 = Constraint::pk(kp, cp), c1 = Constraint::pk(kp, cp);
+                const double c = est_op_us(1, macs, io) + best(nd.c0, c0).cost + best(nd.c1, c1).cost;
+                if (c < bestc.cost) {
+                    bestc = Choice();
+                    bestc.kind = 1;
+                    bestc.oc = oc;
+                    bestc.cx = c0;
+                    bestc.cy = c1;
+                    bestc.cost = c;
+                }
+            }
+        }
+        if (bestc.kind < 0) {
+            Constraint c0, c1;
+            int kind = 2;   // bit level unless both share the output's packed axis
+            if (cp >= 0 && ((qx >> cp) & 1) && ((qy >> cp) & 1)) {
+                c0 = Constraint::pk(cp, -1);
+                c1 = Constraint::pk(cp, -1);
+                kind = 1;
+            }
+            bestc.kind = 1;
+            bestc.oc = oc;
+            bestc.cx = c0;
+            bestc.cy = c1;
+            bestc.cost = est_op_us(kind, macs, io) + best(nd.c0, c0).cost + best(nd.c1, c1).cost;
+        }
+        return bestc;
+    }
+
+    // ------------------------------------------------------------ emission
+    void emit_contract(int a, const Layout &la, int b, const Layout *lb, int c, const Layout &lc, int node) {
+        Op op;
+        op.kind = OP_CONTRACT;
+        op.a = a;
+        op.b = b;
+        op.c = c;
+        op.la = la;
+        if (lb) op.lb = *lb;
+        op.lc = lc;
+        op.node = node;
+        uint64_t ins = list_mask(la.vars) | (lb ? list_mask(lb->vars) : 0);
+        op.kvars = mask_list(ins & ~list_mask(lc.vars));
+        op.macs = mask_cost(ins, P->si);
+        P->ops.push_back(op);
+    }
+
+    void emit_gemm(int a, const Layout &la, int b, const Layout &lb, int c, const Layout &lc, int nb_vars, int m_vars,
+                   int node) {
+        Op op;
+        op.kind = OP_GEMM;
+        op.a = a;
+        op.b = b;
+        op.c = c;
+        op.la = la;
+        op.lb = lb;
+        op.lc = lc;
+        op.node = node;
+        op.macs = mask_cost(list_mask(la.vars) | list_mask(lb.vars), P->si);
+        GemmArgs &g = op.ga;
+        const int nk = (int)la.vars.size() - nb_vars - m_vars;
+        const int nn = (int)lb.vars.size() - nb_vars - nk;
+        g.nbatch = 1;
+        for (int i = 0; i < nb_vars; ++i) g.nbatch *= la.dims[i];
+        g.M = 1;
+        for (int i = nb_vars; i < nb_vars + m_vars; ++i) g.M *= la.dims[i];
+        g.No = 1;
+        for (int i = nb_vars; i < nb_vars + nn - 1; ++i) g.No *= lb.dims[i];
+        g.rn = lb.dims[nb_vars + nn - 1];
+        g.Kw = la.rw;
+        for (int i = nb_vars + m_vars; i < (int)la.vars.size() - 1; ++i) g.Kw *= la.dims[i];
+        g.rwc = lc.rw;
+        g.sA_b = g.M * g.Kw;
+        g.sB_b = g.No * g.rn * g.Kw;
+        g.sC_b = g.M * g.No * g.rwc;
+        g.tiles_m = (g.M + 127) / 128;
+        g.tiles_n = (g.No * g.rwc * 32 + 127) / 128;
+        // K split: enough workgroups to fill 256 CUs twice; partial results
+        // are OR-ed (exact in the Boolean semiring); also bounds the int32
+        // accumulator (at most 87380 per K word).
+        int64_t tiles = g.nbatch * g.tiles_m * g.tiles_n;
+        int64_t ksplit = 1;
+        if (!P->plain && tiles < 512) ksplit = std::max<int64_t>(1, std::min<int64_t>((512 + tiles - 1) / tiles, (g.Kw + 7) / 8));
+        ksplit = std::max<int64_t>(ksplit, (g.Kw + 16383) / 16384);
+        int64_t chunk = (g.Kw + ksplit - 1) / ksplit;
+        chunk = (chunk + 7) / 8 * 8;
+        ksplit = (g.Kw + chunk - 1) / chunk;
+        g.kchunk = chunk;
+        g.ksplit = (int)std::max<int64_t>(1, ksplit);
+        if (g.ksplit > 1) {
+            Op f;
+            f.kind = OP_FILL;
+            f.c = c;
+            f.fill_words = lc.words;
+            f.node = node;
+            P->ops.push_back(f);
+        }
+        P->ops.push_back(op);
+    }
+
+    int plot_leaf(int r, const std::vector<int> &order) {
+        const auto &decl = P->si.rel_list[r];
+        PlotItem it;
+        it.rel = r;
+        for (int v : order) it.storage.push_back((int)(std::find(decl.begin(), decl.end(), v) - decl.begin()));
+        it.layout = lay(order);
+        it.buf = new_buf(it.layout);
+        P->plots.push_back(it);
+        return it.buf;
+    }
+
+    // Emits the ops producing node `id` under `cons` (following the searched
+    // choices); out_buf = -1 allocates, kBufOutput writes the caller's array.
+    int build(int id, const Constraint &cons, int out_buf, Layout *got) {
+        const Choice ch = best(id, cons);
+        const Node &nd = P->tree.nodes[id];
+        const auto &si = P->si;
+        if (nd.leaf >= 0) {
+            const int r = nd.leaf;
+            const uint64_t priv = si.rel_vars[r] & ~nd.q;
+            const std::vector<int> &qo = ch.oc;
+            if (!priv) {
+                const int buf = plot_leaf(r, qo);
+                if (out_buf == -1) {
+                    *got = P->buf_layout[buf];
+                    return buf;
+                }
+                Layout lc = lay(qo);
+                emit_contract(buf, P->buf_layout[buf], -1, nullptr, out_buf, lc, id);
+                *got = lc;
+                return out_buf;
+            }
+            // project out the private latent variables (they occur in this
+            // relation only): plot with one of them packed, then reduce
+            const int kp = pick_packed(priv, si.res);
+            std::vector<int> po;
+            const int cp = qo.empty() ? -1 : qo.back();
+            for (int v : qo)
+                if (v != cp) po.push_back(v);
+            for (int v : mask_list(priv))
+                if (v != kp) po.push_back(v);
+            if (cp >= 0) po.push_back(cp);
+            po.push_back(kp);
+            const int pb = plot_leaf(r, po);
+            Layout lc = lay(qo);
+            const int dst = (out_buf == -1) ? new_buf(lc) : out_buf;
+            emit_contract(pb, P->buf_layout[pb], -1, nullptr, dst, lc, id);
+            *got = lc;
+            return dst;
+        }
+        Layout lx, ly;
+        const int bx = build(nd.c0, ch.cx, -1, &lx);
+        const int by = build(nd.c1, ch.cy, -1, &ly);
+        Layout lc = lay(ch.oc);
+        const int dst = (out_buf == -1) ? new_buf(lc) : out_buf;
+        if (ch.kind == 0) {
+            if (ch.roleB) emit_gemm(bx, lx, by, ly, dst, lc, ch.nb, ch.nm, id);
+            else emit_gemm(by, ly, bx, lx, dst, lc, ch.nb, ch.nm, id);
+        } else {
+            emit_contract(bx, lx, by, &ly, dst, lc, id);
+        }
+        *got = lc;
+        return dst;
+    }
+};
+
+// Fill ContractArgs strides and pick the streaming mode from the layouts.
+static void finish_contract(Op &op, bool has_b) {
+    ContractArgs &a = op.ca;
+    std::memset(&a, 0, sizeof(a));
+    const Layout &la = op.la, &lb = op.lb, &lc = op.lc;
+    a.nout = (int)lc.vars.size();
+    a.c_row_words = lc.rw;
+    a.n_out_rows = 1;
+    for (int i = 0; i < a.nout; ++i) {
+        a.out_dim[i] = lc.dims[i];
+        if (i + 1 < a.nout) a.n_out_rows *= lc.dims[i];
+    }
+    a.a_pk_out = a.b_pk_out = a.a_pk_k = a.b_pk_k = -1;
+    for (int i = 0; i < a.nout; ++i) {
+        const int v = lc.vars[i];
+        a.a_str[i] = la.stride(v);
+        a.b_str[i] = has_b ? lb.stride(v) : 0;
+        if (la.packed() == v) a.a_pk_out = i;
+        if (has_b && lb.packed() == v) a.b_pk_out = i;
+    }
+    a.nk = (int)op.kvars.size();
+    for (int j = 0; j < a.nk; ++j) {
+        const int v = op.kvars[j];
+        a.k_dim[j] = la.has(v) ? la.dims[std::find(la.vars.begin(), la.vars.end(), v) - la.vars.begin()]
+                               : lb.dims[std::find(lb.vars.begin(), lb.vars.end(), v) - lb.vars.begin()];
+        a.ka_str[j] = la.stride(v);
+        a.kb_str[j] = has_b ? lb.stride(v) : 0;
+        if (la.packed() == v) a.a_pk_k = j;
+        if (has_b && lb.packed() == v) a.b_pk_k = j;
+    }
+    a.a_row_words = la.rw;
+    a.b_row_words = has_b ? lb.rw : 0;
+    // A 0-dim operand has no packed axis: its bit is bit 0 of word 0.
+    const bool k_ok = a.a_pk_k >= 0 && (!has_b || a.b_pk_k == a.a_pk_k) && a.a_pk_out < 0 && (!has_b || a.b_pk_out < 0);
+    const bool w_ok = a.nout >= 1 && a.a_pk_out == a.nout - 1 && (!has_b || a.b_pk_out == a.nout - 1) && !la.vars.empty();
+    if (k_ok) op.mode = kModeStreamK;
+    else if (w_ok) op.mode = kModeStreamW;
+    else op.mode = kModeBits;
+}
+
+static std::string join(const std::vector<int> &v) {
+    std::ostringstream s;
+    s << "[";
+    for (size_t i = 0; i < v.size(); ++i) s << (i ? "," : "") << v[i];
+    s << "]";
+    return s.str();
+}
+
+std::string Op::describe() const {
+    std::ostringstream s;
+    s.precision(17);
+    const char *names[] = {"bits", "stream_k", "stream_w"};
+    if (kind == OP_FILL) {
+        s << "{\"op\":\"fill\",\"buf\":" << c << ",\"words\":" << fill_words << "}";
+        return s.str();
+    }
+    s << "{\"op\":\"" << (kind == OP_GEMM ? "gemm_mfma" : names[mode]) << "\",\"a\":" << a << ",\"b\":" << b
+      << ",\"c\":" << c << ",\"a_vars\":" << join(la.vars) << ",\"b_vars\":" << join(lb.vars)
+      << ",\"c_vars\":" << join(lc.vars) << ",\"macs\":" << macs;
+    if (kind == OP_GEMM)
+        s << ",\"batch\":" << ga.nbatch << ",\"M\":" << ga.M << ",\"No\":" << ga.No << ",\"rn\":" << ga.rn
+          << ",\"Kw\":" << ga.Kw << ",\"ksplit\":" << ga.ksplit;
+    s << "}";
+    return s.str();
+}
+
+// --------------------------------------------------------------- planning
+static int build_plan(const pa_system *sys, const int32_t *exposed, int32_t n_exposed, const pa_opts *opts,
+                      pa_plan *P) {
+    auto t0 = std::chrono::steady_clock::now();
+    int rc = build_sysinfo(sys, exposed, n_exposed, P->si);
+    if (rc) return rc;
+    for (int r = 0; r < sys->n_rel; ++r) {
+        std::vector<pa_axis> ax;
+        for (int i = 0; i < sys->rel[r].arity; ++i) ax.push_back(sys->axes[sys->rel[r].vars[i]]);
+        rc = validate_relation(sys->rel[r], ax.data(), sys->n_vars, "system");
+        if (rc) return rc;
+    }
+    pa_opts dflt{};
+    const pa_opts &o = opts ? *opts : dflt;
+    P->precision = o.precision;
+    P->audit = o.audit;
+    P->timing = o.timing;
+    P->plain = o.plain;
+    if (o.precision != PA_PLOT_FP32_ESCALATE && o.precision != PA_PLOT_FP64)
+        return fail(PA_EINVAL, "opts: unknown precision");
+    switch (o.order_policy) {
+        case PA_ORDER_GREEDY: rc = plan_greedy(P->si, P->tree); break;
+        case PA_ORDER_EXHAUSTIVE: rc = plan_exhaustive(P->si, P->tree); break;
+        case PA_ORDER_GIVEN: {
+            if (o.n_given < 0 || (o.n_given > 0 && !o.given)) return fail(PA_EINVAL, "opts: bad given order");
+            std::vector<int> m(o.given, o.given + 2 * o.n_given);
+            rc = tree_from_merges(P->si, m, P->tree);
+            break;
+        }
+        case PA_ORDER_LEARNED: rc = plan_learned(P->si, o.model, P->tree); break;
+        default: return fail(PA_EINVAL, "opts: unknown order policy");
+    }
+    if (rc) return rc;
+    Builder B{P, sys};
+    P->out_layout = make_layout(P->si.exposed_list, P->si.res);
+    Layout got;
+    if (B.build(P->tree.root, Constraint::full(P->si.exposed_list), kBufOutput, &got) != kBufOutput)
+        return g_err.empty() ? fail(PA_EINVAL, "internal: root not written to output") : PA_EINVAL;
+    for (auto &op : P->ops)
+        if (op.kind == OP_CONTRACT) finish_contract(op, op.b >= 0 || op.b == kBufOutput);
+    // workspace layout: tables | line tables | counters | buffers
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off += (bytes + 255) / 256 * 256;
+        return at;
+    };
+    // host tables: per relation dense coefficients, per variable axis tables
+    std::vector<unsigned char> &T = P->tables_host;
+    T.clear();
+    auto put = [&](const void *p, size_t n) {
+        const size_t at = T.size();
+        T.resize((at + n + 255) / 256 * 256);
+        std::memcpy(T.data() + at, p, n);
+        return at;
+    };
+    std::vector<size_t> coef_at(sys->n_rel), ax_at(sys->n_vars), axf_at(sys->n_vars);
+    for (int r = 0; r < sys->n_rel; ++r) {
+        std::vector<double> c = dense_coef(sys->rel[r]);
+        c.resize(kDense, 0.0);
+        coef_at[r] = put(c.data(), c.size() * sizeof(double));
+    }
+    for (int v = 0; v < sys->n_vars; ++v) {
+        std::vector<double> x;
+        std::vector<float> xf;
+        axis_table(sys->axes[v].lo, sys->axes[v].hi, sys->axes[v].res, x, xf);
+        ax_at[v] = put(x.data(), x.size() * sizeof(double));
+        axf_at[v] = put(xf.data(), xf.size() * sizeof(float));
+    }
+    P->tables_off = take(T.size());
+    P->plotrel_off = take(sizeof(PlotRel) * std::max<size_t>(1, P->plots.size()));
+    P->plotrel1_off = take(sizeof(PlotRel) * std::max<size_t>(1, P->plots.size()));
+    P->counters_off = take(sizeof(PlotCounters));
+    P->popcnt_off = take(64);
+    std::vector<size_t> line_at(P->plots.size());
+    int64_t lines = 0, words = 0, corners = 0;
+    for (size_t i = 0; i < P->plots.size(); ++i) {
+        const auto &it = P->plots[i];
+        int64_t nl = 1, cn = 1;
+        for (size_t s = 0; s + 1 < it.layout.dims.size(); ++s) nl *= it.layout.dims[s] + 1;
+        for (int64_t dm : it.layout.dims) cn *= dm + 1;
+        corners += cn;
+        if (P->precision == PA_PLOT_FP32_ESCALATE) {
+            line_at[i] = take(sizeof(float) * (kMaxD + 2) * nl);
+            lines += nl;
+        }
+        words += it.layout.words;
+    }
+    P->total_lines = lines;
+    P->total_words = words;
+    P->corners = corners;
+    for (size_t i = 0; i < P->buf_layout.size(); ++i) P->buf_off[i] = (int64_t)take(P->buf_words[i] * 4);
+    P->ws_bytes = off;
+    // PlotRel records (device pointers patched once the workspace exists)
+    P->tables_bytes = T.size();
+    (void)line_at;
+    P->plotrel_host.clear();
+    for (size_t i = 0; i < P->plots.size(); ++i) {
+        const auto &it = P->plots[i];
+        const pa_relation &rel = sys->rel[it.rel];
+        PlotRel R;
+        std::memset(&R, 0, sizeof(R));
+        R.n = rel.arity;
+        R.d = rel.degree;
+        R.mode = P->precision;
+        R.audit = P->audit;
+        R.row_words = it.layout.rw;
+        R.coef = reinterpret_cast<const double *>(coef_at[it.rel]);       // offsets for now
+        double vmax = 0.0;
+        for (int s = 0; s < R.n; ++s) {
+            const int dv = it.storage[s];
+            const int var = rel.vars[dv];
+            R.perm[s] = dv;
+            R.res[s] = sys->axes[var].res;
+            R.ax[s] = reinterpret_cast<const double *>(ax_at[var]);
+            R.axf[s] = reinterpret_cast<const float *>(axf_at[var]);
+            if (s == R.n - 1) vmax = std::max(std::fabs(sys->axes[var].lo), std::fabs(sys->axes[var].hi));
+        }
+        // |x_k| <= max(|lo|, |hi|) up to the two roundings of x_k
+        R.vmax = vmax * (1.0 + 0x1p-50) + 0x1p-1000;
+        R.n_rows = it.layout.words / it.layout.rw;
+        R.n_lines = 1;
+        for (int s = 0; s + 1 < R.n; ++s) R.n_lines *= R.res[s] + 1;
+        if (P->precision != PA_PLOT_FP32_ESCALATE) R.n_lines = 0;
+        R.lines = reinterpret_cast<float *>(P->precision == PA_PLOT_FP32_ESCALATE ? line_at[i] : 0);
+        R.out = reinterpret_cast<uint32_t *>((size_t)P->buf_off[it.buf]);
+        P->plotrel_host.push_back(R);
+    }
+    int64_t wb = 0, lb = 0;
+    for (auto &R : P->plotrel_host) {
+        R.word_base = wb;
+        R.line_base = lb;
+        wb += R.n_rows * R.row_words;
+        lb += R.n_lines;
+    }
+    auto t1 = std::chrono::steady_clock::now();
+    P->t_plan_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    return PA_OK;
+}
+
+static int upload(pa_plan *P) {
+    char *base = static_cast<char *>(P->ws.ptr);
+    std::vector<PlotRel> rels = P->plotrel_host;
+    auto fix = [&](const void *off) { return (void *)(base + P->tables_off + (size_t)off); };
+    for (auto &R : rels) {
+        R.coef = (const double *)fix(R.coef);
+        for (int s = 0; s < R.n; ++s) {
+            R.ax[s] = (const double *)fix(R.ax[s]);
+            R.axf[s] = (const float *)fix(R.axf[s]);
+        }
+        R.lines = R.lines ? (float *)(base + (size_t)R.lines) : nullptr;
+        R.out = (uint32_t *)(base + (size_t)R.out);
+    }
+    HIP_TRY(hipMemcpy(base + P->tables_off, P->tables_host.data(), P->tables_host.size(), hipMemcpyHostToDevice));
+    if (!rels.empty()) {
+        HIP_TRY(hipMemcpy(base + P->plotrel_off, rels.data(), rels.size() * sizeof(PlotRel), hipMemcpyHostToDevice));
+        // copies with zero bases, for one-relation-per-launch plotting
+        for (auto &R : rels) R.word_base = R.line_base = 0;
+        HIP_TRY(hipMemcpy(base + P->plotrel1_off, rels.data(), rels.size() * sizeof(PlotRel), hipMemcpyHostToDevice));
+    }
+    P->uploaded = true;
+    return PA_OK;
+}
+
+// Host proof that a launch stays inside its buffers: the largest word index
+// any thread can form from the strides, compared with the buffer sizes.
+static int check_contract_bounds(const ContractArgs &a, int64_t a_words, int64_t b_words, int64_t c_words, bool has_b) {
+    int64_t ma = a.a_row_words - 1, mb = has_b ? a.b_row_words - 1 : 0;
+    for (int i = 0; i < a.nout; ++i) {
+        ma += (a.out_dim[i] - 1) * a.a_str[i];
+        mb += (a.out_dim[i] - 1) * a.b_str[i];
+    }
+    for (int j = 0; j < a.nk; ++j) {
+        ma += (a.k_dim[j] - 1) * a.ka_str[j];
+        mb += (a.k_dim[j] - 1) * a.kb_str[j];
+    }
+    const int64_t mc = (a.nout == 0) ? 0 : a.n_out_rows * a.c_row_words - 1;
+    if (ma >= a_words || (has_b && mb >= b_words) || mc >= c_words || ma < 0 || mb < 0)
+        return fail(PA_EINVAL, "internal: contraction would index outside its buffers");
+    return PA_OK;
+}
+
+static int check_gemm_bounds(const GemmArgs &g, int64_t a_words, int64_t b_words, int64_t c_words) {
+    const int64_t ma = g.nbatch * g.sA_b, mb = g.nbatch * g.sB_b, mc = g.nbatch * g.sC_b;
+    if (g.sA_b != g.M * g.Kw || g.sB_b != g.No * g.rn * g.Kw || g.sC_b != g.M * g.No * g.rwc || g.Kw % 2 ||
+        g.rwc != row_words_of(g.rn) || ma > a_words || mb > b_words || mc > c_words || g.kchunk % 8 ||
+        g.kchunk > 16384 || (int64_t)g.ksplit * g.kchunk < g.Kw)
+        return fail(PA_EINVAL, "internal: GEMM would index outside its buffers");
+    return PA_OK;
+}
+
+static uint32_t *buf_ptr(pa_plan *P, int id, void *out) {
+    if (id == kBufOutput) return static_cast<uint32_t *>(out);
+    if (id < 0) return nullptr;
+    return reinterpret_cast<uint32_t *>(static_cast<char *>(P->ws.ptr) + P->buf_off[id]);
+}
+
+static int run_ops(pa_plan *P, void *out, hipStream_t s, int *launches) {
+    for (const Op &op0 : P->ops) {
+        if (op0.kind == OP_FILL) {
+            HIP_TRY(launch_fill(buf_ptr(P, op0.c, out), op0.fill_words, 0u, s));
+            ++*launches;
+        } else if (op0.kind == OP_GEMM) {
+            GemmArgs g = op0.ga;
+            int rc = check_gemm_bounds(g, op0.la.words, op0.lb.words, op0.lc.words);
+            if (rc) return rc;
+            g.A = buf_ptr(P, op0.a, out);
+            g.B = buf_ptr(P, op0.b, out);
+            g.C = buf_ptr(P, op0.c, out);
+            HIP_TRY(launch_gemm(g, s));
+            ++*launches;
+        } else {
+            ContractArgs a = op0.ca;
+            int rc = check_contract_bounds(a, op0.la.words, op0.lb.words, op0.lc.words, op0.b >= 0);
+            if (rc) return rc;
+            a.A = buf_ptr(P, op0.a, out);
+            a.B = buf_ptr(P, op0.b, out);
+            a.C = buf_ptr(P, op0.c, out);
+            HIP_TRY(launch_contract(a, op0.mode, s));
+            ++*launches;
+        }
+    }
+    return PA_OK;
+}
+
+static int run_plots(pa_plan *P, hipStream_t s, int *launches) {
+    char *base = static_cast<char *>(P->ws.ptr);
+    const PlotRel *d_rels = reinterpret_cast<const PlotRel *>(base + P->plotrel_off);
+    PlotCounters *cnt = reinterpret_cast<PlotCounters *>(base + P->counters_off);
+    const int nrel = (int)P->plotrel_host.size();
+    if (nrel == 0) return PA_OK;
+    if (!P->plain) {
+        HIP_TRY(launch_plot(d_rels, nrel, P->total_lines, P->total_words,
+                            P->precision == PA_PLOT_FP32_ESCALATE, cnt, s, launches));
+    } else {
+        const PlotRel *d_one = reinterpret_cast<const PlotRel *>(base + P->plotrel1_off);
+        for (int i = 0; i < nrel; ++i) {
+            const PlotRel &R = P->plotrel_host[i];
+            // one relation per launch: the relation's own record with bases 0
+            HIP_TRY(launch_plot(d_one + i, 1, R.n_lines, R.n_rows * R.row_words,
+                                P->precision == PA_PLOT_FP32_ESCALATE, cnt, s, launches));
+        }
+    }
+    return PA_OK;
+}
+
+}  // namespace pa
+
+// ====================================================================== ABI
+using namespace pa;
+
+extern "C" int pa_plan_create(const pa_system *sys, const int32_t *exposed, int32_t n_exposed, const pa_opts *opts,
+                              pa_plan **plan) {
+    if (!plan) return fail(PA_EINVAL, "plan_create: null plan pointer");
+    *plan = nullptr;
+    std::unique_ptr<pa_plan> P(new pa_plan());
+    int rc = build_plan(sys, exposed, n_exposed, opts, P.get());
+    if (rc) return rc;
+    if (opts && opts->workspace) {
+        if (opts->workspace_bytes < P->ws_bytes)
+            return fail(PA_ENOMEM, "workspace too small: need " + std::to_string(P->ws_bytes) + " bytes");
+        P->ws.ptr = opts->workspace;
+        P->ws.cap = opts->workspace_bytes;
+        P->ws.external = true;
+    } else {
+        rc = P->ws.ensure(std::max<size_t>(P->ws_bytes, 256));
+        if (rc) return rc;
+    }
+    rc = upload(P.get());
+    if (rc) return rc;
+    *plan = P.release();
+    return PA_OK;
+}
+
+extern "C" size_t pa_plan_workspace_bytes(const pa_plan *plan) { return plan ? plan->ws_bytes : 0; }
+
+extern "C" void pa_plan_destroy(pa_plan *plan) { delete plan; }
+
+extern "C" int pa_plan_execute(pa_plan *P, pa_bitarray *out, pa_report *rep, void *stream) {
+    if (!P) return fail(PA_EINVAL, "plan_execute: null plan");
+    int rc = check_bitarray(out, P->out_layout.dims, "plan_execute: out");
+    if (rc) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char *base = static_cast<char *>(P->ws.ptr);
+    int launches = 0;
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    const bool timing = P->timing && rep;
+    if (timing)
+        for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
+    if (rep) {
+        HIP_TRY(launch_fill(reinterpret_cast<uint32_t *>(base + P->counters_off), sizeof(PlotCounters) / 4, 0u, s));
+        HIP_TRY(launch_fill(reinterpret_cast<uint32_t *>(base + P->popcnt_off), 2, 0u, s));
+        launches += 2;
+    }
+    if (timing) HIP_TRY(hipEventRecord(ev[0], s));
+    rc = run_plots(P, s, &launches);
+    if (rc) return rc;
+    if (timing) HIP_TRY(hipEventRecord(ev[1], s));
+    rc = run_ops(P, out->data, s, &launches);
+    if (rc) return rc;
+    if (timing) HIP_TRY(hipEventRecord(ev[2], s));
+    if (rep) {
+        std::memset(rep, 0, sizeof(*rep));
+        HIP_TRY(launch_popcount(static_cast<const uint32_t *>(out->data), P->out_layout.words,
+                                reinterpret_cast<unsigned long long *>(base + P->popcnt_off), s));
+        PlotCounters cnt;
+        unsigned long long nnz = 0;
+        HIP_TRY(hipMemcpyAsync(&cnt, base + P->counters_off, sizeof(cnt), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(&nnz, base + P->popcnt_off, sizeof(nnz), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        rep->corners = P->corners;
+        rep->corners_flagged = (int64_t)cnt.flagged;
+        rep->corners_disagree = (int64_t)cnt.disagree;
+        rep->corners_disagree_unflagged = (int64_t)cnt.disagree_unflagged;
+        rep->nnz_out = (int64_t)nnz;
+        rep->n_launches = launches;
+        int steps = 0;
+        double macs = 0.0;
+        for (const auto &op : P->ops)
+            if (op.kind != OP_FILL && op.b != -1) { ++steps; macs += op.macs; }
+        rep->n_steps = steps;
+        rep->cost_macs = P->tree.cost;
+        for (size_t i = 0; i < P->tree.merges.size() && i < 2 * PA_MAX_RELATIONS; ++i) rep->merges[i] = P->tree.merges[i];
+        rep->t_plan_ms = P->t_plan_ms;
+        if (timing) {
+            float a = 0.f, b = 0.f;
+            HIP_TRY(hipEventElapsedTime(&a, ev[0], ev[1]));
+            HIP_TRY(hipEventElapsedTime(&b, ev[1], ev[2]));
+            rep->t_plot_ms = a;
+            rep->t_contract_ms = b;
+        }
+        (void)macs;
+    }
+    if (timing)
+        for (auto &e : ev) (void)hipEventDestroy(e);
+    return PA_OK;
+}
+
+extern "C" int pa_solve_system(const pa_system *sys, const int32_t *exposed, int32_t n_exposed, const pa_opts *opts,
+                               pa_bitarray *out, pa_report *report, void *stream) {
+    pa_plan *P = nullptr;
+    int rc = pa_plan_create(sys, exposed, n_exposed, opts, &P);
+    if (rc) return rc;
+    rc = pa_plan_execute(P, out, report, stream);
+    if (rc == PA_OK && !report) {
+        // the plan's workspace is freed below: wait for the work to finish
+        if (hipStreamSynchronize(static_cast<hipStream_t>(stream)) != hipSuccess) rc = fail(PA_EHIP, "sync failed");
+    }
+    pa_plan_destroy(P);
+    return rc;
+}
+
+extern "C" int64_t pa_plan_describe(const pa_system *sys, const int32_t *exposed, int32_t n_exposed,
+                                    const pa_opts *opts, char *buf, int64_t buf_len) {
+    std::unique_ptr<pa_plan> P(new pa_plan());
+    int rc = build_plan(sys, exposed, n_exposed, opts, P.get());
+    std::ostringstream s;
+    s.precision(17);
+    if (rc) {
+        s << "{\"error\":" << rc << "}";
+    } else {
+        s << "{\"merges\":" << join(std::vector<int>(P->tree.merges.begin(), P->tree.merges.end()))
+          << ",\"cost\":" << P->tree.cost << ",\"workspace_bytes\":" << P->ws_bytes << ",\"corners\":" << P->corners
+          << ",\"plots\":[";
+        for (size_t i = 0; i < P->plots.size(); ++i)
+            s << (i ? "," : "") << "{\"rel\":" << P->plots[i].rel << ",\"buf\":" << P->plots[i].buf
+              << ",\"vars\":" << join(P->plots[i].layout.vars) << "}";
+        s << "],\"ops\":[";
+        for (size_t i = 0; i < P->ops.size(); ++i) s << (i ? "," : "") << P->ops[i].describe();
+        s << "],\"buffers\":[";
+        for (size_t i = 0; i < P->buf_layout.size(); ++i)
+            s << (i ? "," : "") << "{\"vars\":" << join(P->buf_layout[i].vars) << ",\"words\":" << P->buf_words[i] << "}";
+        s << "]}";
+    }
+    const std::string str = s.str();
+    if (buf && buf_len > 0) {
+        const int64_t n = std::min<int64_t>(buf_len - 1, (int64_t)str.size());
+        std::memcpy(buf, str.data(), (size_t)n);
+        buf[n] = 0;
+    }
+    return (int64_t)str.size();
+}
+
+// ------------------------------------------------------ one-relation plot
+namespace {
+struct SmallScratch {
+    std::mutex mu;
+    pa::Workspace ws;
+};
+SmallScratch &scratch() {
+    static SmallScratch s;
+    return s;
+}
+}  // namespace
+
+extern "C" int pa_plot_relation(const pa_relation *rel, const pa_axis *axes_of_vars, const pa_opts *opts,
+                                pa_bitarray *out, pa_report *report, void *stream) {
+    if (!rel || !axes_of_vars) return fail(PA_EINVAL, "plot_relation: null argument");
+    // a one-relation system over its own variables 0..arity-1
+    std::vector<int32_t> vars(rel->arity);
+    for (int i = 0; i < rel->arity; ++i) vars[i] = i;
+    int rc = validate_relation(*rel, axes_of_vars, -1, "plot_relation");
+    if (rc) return rc;
+    std::vector<int64_t> dims;
+    for (int i = 0; i < rel->arity; ++i) dims.push_back(axes_of_vars[i].res);
+    rc = check_bitarray(out, dims, "plot_relation: out");
+    if (rc) return rc;
+    pa_relation r2 = *rel;
+    r2.vars = vars.data();
+    pa_system sys{rel->arity, axes_of_vars, 1, &r2};
+    // plan: the single leaf, plotted in declared order, copied to out
+    pa_plan *P = nullptr;
+    rc = pa_plan_create(&sys, vars.data(), rel->arity, opts, &P);
+    if (rc) return rc;
+    rc = pa_plan_execute(P, out, report, stream);
+    if (rc == PA_OK && !report && hipStreamSynchronize(static_cast<hipStream_t>(stream)) != hipSuccess)
+        rc = fail(PA_EHIP, "sync failed");
+    pa_plan_destroy(P);
+    return rc;
+}
+
+extern "C" int pa_popcount(const pa_bitarray *a, int64_t *count, void *stream) {
+    if (!a || !count || !a->data || a->ndim < 0 || a->ndim > PA_MAX_DIMS) return fail(PA_EINVAL, "popcount: bad args");
+    auto &S = scratch();
+    std::lock_guard<std::mutex> lk(S.mu);
+    int rc = S.ws.ensure(256);
+    if (rc) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIP_TRY(launch_fill(static_cast<uint32_t *>(S.ws.ptr), 2, 0u, s));
+    HIP_TRY(launch_popcount(static_cast<const uint32_t *>(a->data), pa_array_words(a->ndim, a->dims),
+                            static_cast<unsigned long long *>(S.ws.ptr), s));
+    unsigned long long c = 0;
+    HIP_TRY(hipMemcpyAsync(&c, S.ws.ptr, sizeof(c), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    *count = (int64_t)c;
+    return PA_OK;
+}
+
+// ---------------------------------------------------------- pa_contract
+extern "C" int pa_contract(const pa_bitarray *A, const int32_t *a_vars, const pa_bitarray *B, const int32_t *b_vars,
+                           const int32_t *out_vars, int32_t n_out, pa_bitarray *C, const pa_opts *opts, void *stream) {
+    (void)opts;
+    if (!A || !C || (!a_vars && A->ndim > 0) || (n_out > 0 && !out_vars)) return fail(PA_EINVAL, "contract: null argument");
+    if (A->ndim < 0 || A->ndim > PA_MAX_DIMS || n_out < 0 || n_out > PA_MAX_DIMS || (B && (B->ndim < 0 || B->ndim > PA_MAX_DIMS)))
+        return fail(PA_EINVAL, "contract: rank out of range");
+    std::vector<int64_t> res(PA_MAX_VARS, -1);
+    auto note = [&](const pa_bitarray *X, const int32_t *vs) -> int {
+        uint64_t seen = 0;
+        for (int i = 0; i < X->ndim; ++i) {
+            const int v = vs[i];
+            if (v < 0 || v >= PA_MAX_VARS) return fail(PA_EINVAL, "contract: variable label out of range");
+            if ((seen >> v) & 1) return fail(PA_EINVAL, "contract: repeated variable in one array");
+            seen |= 1ull << v;
+            if (X->dims[i] < 1) return fail(PA_EINVAL, "contract: dims must be >= 1");
+            if (res[v] >= 0 && res[v] != X->dims[i]) return fail(PA_EINVAL, "contract: shared variable with different lengths");
+            res[v] = X->dims[i];
+        }
+        return PA_OK;
+    };
+    int rc = note(A, a_vars);
+    if (rc) return rc;
+    if (B) {
+        rc = note(B, b_vars);
+        if (rc) return rc;
+    }
+    uint64_t outm = 0;
+    std::vector<int> ov;
+    for (int i = 0; i < n_out; ++i) {
+        const int v = out_vars[i];
+        if (v < 0 || v >= PA_MAX_VARS || res[v] < 0) return fail(PA_EINVAL, "contract: output variable not in A or B");
+        if ((outm >> v) & 1) return fail(PA_EINVAL, "contract: repeated output variable");
+        outm |= 1ull << v;
+        ov.push_back(v);
+    }
+    std::vector<int> av(a_vars, a_vars + A->ndim), bv;
+    if (B) bv.assign(b_vars, b_vars + B->ndim);
+    Layout la = make_layout(av, res), lb = B ? make_layout(bv, res) : Layout(), lc = make_layout(ov, res);
+    rc = check_bitarray(A, la.dims, "contract: A");
+    if (rc) return rc;
+    if (B) {
+        rc = check_bitarray(B, lb.dims, "contract: B");
+        if (rc) return rc;
+    }
+    rc = check_bitarray(C, lc.dims, "contract: C");
+    if (rc) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    // canonical GEMM layout: A = [b][m][k], B = [b][n][k], C = [b][m][n]
+    if (B) {
+        const uint64_t ma = list_mask(av), mb = list_mask(bv);
+        const uint64_t bm = ma & mb & outm, km = ma & mb & ~outm, em = ma & ~mb, en = mb & ~ma;
+        const int nb = __builtin_popcountll(bm), nm = __builtin_popcountll(em), nn = __builtin_popcountll(en),
+                  nk = __builtin_popcountll(km);
+        bool canon = km && em && en && ((em | en) & ~outm) == 0 && (int)av.size() == nb + nm + nk &&
+                     (int)bv.size() == nb + nn + nk && (int)ov.size() == nb + nm + nn;
+        if (canon) {
+            auto seg = [](const std::vector<int> &l, int a, int n) { return std::vector<int>(l.begin() + a, l.begin() + a + n); };
+            canon = list_mask(seg(av, 0, nb)) == bm && seg(av, 0, nb) == seg(bv, 0, nb) && seg(av, 0, nb) == seg(ov, 0, nb) &&
+                    list_mask(seg(av, nb, nm)) == em && seg(av, nb, nm) == seg(ov, nb, nm) &&
+                    list_mask(seg(bv, nb, nn)) == en && seg(bv, nb, nn) == seg(ov, nb + nm, nn) &&
+                    list_mask(seg(av, nb + nm, nk)) == km && seg(av, nb + nm, nk) == seg(bv, nb + nn, nk);
+        }
+        if (canon) {
+            pa_plan tmp;
+            tmp.plain = opts ? opts->plain : 0;
+            tmp.si.res = res;
+            tmp.si.n_vars = PA_MAX_VARS;
+            Builder Bd{&tmp, nullptr};
+            Bd.emit_gemm(0, la, 1, lb, kBufOutput, lc, nb, nm, -1);
+            for (auto &op : tmp.ops) {
+                if (op.kind == OP_FILL) {
+                    HIP_TRY(launch_fill(static_cast<uint32_t *>(C->data), op.fill_words, 0u, s));
+                } else {
+                    GemmArgs g = op.ga;
+                    rc = check_gemm_bounds(g, la.words, lb.words, lc.words);
+                    if (rc) return rc;
+                    g.A = static_cast<const uint32_t *>(A->data);
+                    g.B = static_cast<const uint32_t *>(B->data);
+                    g.C = static_cast<uint32_t *>(C->data);
+                    HIP_TRY(launch_gemm(g, s));
+                }
+            }
+            return PA_OK;
+        }
+    }
+    Op op;
+    op.la = la;
+    op.lb = lb;
+    op.lc = lc;
+    op.kvars = mask_list((list_mask(av) | (B ? list_mask(bv) : 0)) & ~outm);
+    finish_contract(op, B != nullptr);
+    rc = check_contract_bounds(op.ca, la.words, B ? lb.words : 0, lc.words, B != nullptr);
+    if (rc) return rc;
+    op.ca.A = static_cast<const uint32_t *>(A->data);
+    op.ca.B = B ? static_cast<const uint32_t *>(B->data) : nullptr;
+    op.ca.C = static_cast<uint32_t *>(C->data);
+    HIP_TRY(launch_contract(op.ca, op.mode, s));
+    return PA_OK;
+}

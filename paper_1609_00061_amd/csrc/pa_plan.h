@@ -1,0 +1,130 @@
+// Plans: cluster tree, per-node layouts, the op list and the workspace.
+#pragma once
+#include <array>
+#include <stdint.h>
+#include <string>
+#include <vector>
+
+#include "pa.h"
+#include "pa_internal.h"
+
+namespace pa {
+
+extern thread_local std::string g_err;
+int fail(int code, const std::string &msg);
+
+// Axis order of a bit-packed array; the last variable is the packed axis.
+struct Layout {
+    std::vector<int> vars;
+    std::vector<int64_t> dims;
+    int64_t rw = 1;
+    int64_t words = 1;
+    int packed() const;
+    int64_t stride(int v) const;
+    bool has(int v) const;
+};
+
+int64_t row_words_of(int64_t d);
+Layout make_layout(const std::vector<int> &vars, const std::vector<int64_t> &res_of_var);
+std::vector<std::array<int, 3>> graded_lex(int n, int d);
+int64_t n_monomials(int n, int d);
+std::vector<double> dense_coef(const pa_relation &r);
+void axis_table(double lo, double hi, int r, std::vector<double> &x, std::vector<float> &xf);
+int validate_relation(const pa_relation &r, const pa_axis *axes_of_vars, int n_vars_total, const char *who);
+int check_bitarray(const pa_bitarray *a, const std::vector<int64_t> &dims, const char *who);
+
+struct Workspace {
+    void *ptr = nullptr;
+    size_t cap = 0;
+    bool external = false;
+    int ensure(size_t bytes);
+    ~Workspace();
+};
+
+// ---------------------------------------------------------------- planning
+// Cluster tree node.  Leaves are relations; internal nodes are pairwise
+// generalized array multiplications whose output pack is Q (Def.
+// "efficient_factorization": the cluster's links also used outside it).
+struct Node {
+    int leaf = -1;                // relation index, or -1
+    int c0 = -1, c1 = -1;         // children (internal)
+    uint64_t q = 0;               // output variables
+    uint32_t leaves = 0;          // relations under this node
+};
+
+struct Tree {
+    std::vector<Node> nodes;      // leaves first (node i = relation i), then merges
+    int root = -1;
+    std::vector<int> merges;      // PA_ORDER_GIVEN format
+    double cost = 0.0;            // sum of node costs (eqn naive_cost)
+};
+
+struct SysInfo {
+    int n_vars = 0, n_rel = 0;
+    std::vector<int64_t> res;                 // per variable
+    std::vector<uint64_t> rel_vars;           // bitmask per relation
+    std::vector<std::vector<int>> rel_list;   // declared order per relation
+    uint64_t exposed = 0;
+    std::vector<int> exposed_list;
+};
+
+int build_sysinfo(const pa_system *sys, const int32_t *exposed, int32_t n_exposed, SysInfo &si);
+double mask_cost(uint64_t m, const SysInfo &si);      // product of resolutions
+uint64_t q_of(uint32_t cluster, const SysInfo &si);   // intermediate pack of a set of relations
+int tree_from_merges(const SysInfo &si, const std::vector<int> &merges, Tree &t);
+int plan_greedy(const SysInfo &si, Tree &t);
+int plan_exhaustive(const SysInfo &si, Tree &t);
+int plan_learned(const SysInfo &si, const pa_model *model, Tree &t);
+
+// ---------------------------------------------------------------- op list
+enum OpKind { OP_CONTRACT = 0, OP_GEMM = 1, OP_FILL = 2 };
+
+constexpr int kBufOutput = -2;
+
+struct Op {
+    OpKind kind = OP_CONTRACT;
+    int mode = kModeBits;         // contract mode
+    int a = -1, b = -1, c = -1;   // buffer ids (kBufOutput = caller's output)
+    Layout la, lb, lc;
+    std::vector<int> kvars;
+    ContractArgs ca{};            // pointers patched at execution
+    GemmArgs ga{};
+    int64_t fill_words = 0;
+    double macs = 0.0;            // product of the step's link resolutions
+    int node = -1;
+    std::string describe() const;
+};
+
+struct PlotItem {
+    int rel = -1;
+    int buf = -1;
+    std::vector<int> storage;     // storage axis s holds declared variable storage[s]
+    Layout layout;
+};
+
+struct pa_plan_impl;
+
+}  // namespace pa
+
+struct pa_plan {
+    pa::SysInfo si;
+    pa::Tree tree;
+    std::vector<pa::PlotItem> plots;
+    std::vector<pa::Op> ops;
+    std::vector<int64_t> buf_off;     // byte offsets into the workspace
+    std::vector<int64_t> buf_words;
+    std::vector<pa::Layout> buf_layout;
+    size_t tables_off = 0, tables_bytes = 0, ws_bytes = 0;
+    size_t plotrel_off = 0, plotrel1_off = 0, counters_off = 0, popcnt_off = 0;
+    std::vector<pa::PlotRel> plotrel_host;    // records with prefix bases (fused launch)
+    std::vector<unsigned char> tables_host;   // uploaded once
+    pa::Workspace ws;
+    int precision = PA_PLOT_FP32_ESCALATE;
+    int audit = 0, timing = 0, plain = 0;
+    int device = 0;
+    int64_t corners = 0, total_lines = 0, total_words = 0;
+    int n_rel_plots = 0;
+    bool uploaded = false;
+    double t_plan_ms = 0.0;
+    pa::Layout out_layout;
+};

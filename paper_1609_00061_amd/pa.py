@@ -1,0 +1,313 @@
+"""Thin Python binding of libpa.so (ctypes).  Argument marshalling only: every
+step of plotting and multiplication runs in the library's HIP kernels.  Device
+memory and streams come from PyTorch (ROCm).  The binding fails loudly when
+the library is missing; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import json
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpa.so")
+
+PA_OK, PA_EINVAL, PA_ENOMEM, PA_EHIP, PA_EUNSUPPORTED = 0, 1, 2, 3, 4
+ORDER_GREEDY, ORDER_EXHAUSTIVE, ORDER_LEARNED, ORDER_GIVEN = 0, 1, 2, 3
+PLOT_FP32_ESCALATE, PLOT_FP64 = 0, 1
+MAX_DIMS, MAX_RELATIONS = 12, 32
+
+STATUS_NAMES = {0: "PA_OK", 1: "PA_EINVAL", 2: "PA_ENOMEM", 3: "PA_EHIP", 4: "PA_EUNSUPPORTED"}
+
+
+class PaError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Axis(ctypes.Structure):
+    _fields_ = [("lo", ctypes.c_double), ("hi", ctypes.c_double), ("res", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class Relation(ctypes.Structure):
+    _fields_ = [("arity", ctypes.c_int32), ("degree", ctypes.c_int32),
+                ("vars", ctypes.POINTER(ctypes.c_int32)), ("coef", ctypes.POINTER(ctypes.c_double))]
+
+
+class BitArray(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("ndim", ctypes.c_int32), ("dims", ctypes.c_int32 * MAX_DIMS),
+                ("row_words", ctypes.c_int64)]
+
+
+class System(ctypes.Structure):
+    _fields_ = [("n_vars", ctypes.c_int32), ("axes", ctypes.POINTER(Axis)),
+                ("n_rel", ctypes.c_int32), ("rel", ctypes.POINTER(Relation))]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("order_policy", ctypes.c_int32), ("n_given", ctypes.c_int32),
+                ("given", ctypes.POINTER(ctypes.c_int32)), ("precision", ctypes.c_int32),
+                ("audit", ctypes.c_int32), ("timing", ctypes.c_int32), ("plain", ctypes.c_int32),
+                ("model", ctypes.c_void_p), ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t)]
+
+
+class Report(ctypes.Structure):
+    _fields_ = [("corners", ctypes.c_int64), ("corners_flagged", ctypes.c_int64),
+                ("corners_disagree", ctypes.c_int64), ("corners_disagree_unflagged", ctypes.c_int64),
+                ("nnz_out", ctypes.c_int64), ("n_steps", ctypes.c_int32), ("n_launches", ctypes.c_int32),
+                ("merges", ctypes.c_int32 * (2 * MAX_RELATIONS)), ("cost_macs", ctypes.c_double),
+                ("t_plot_ms", ctypes.c_double), ("t_contract_ms", ctypes.c_double), ("t_plan_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "merges"}
+        return d
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libpa.so (built in-tree by paper_1609_00061_amd/build.py)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libpa.so not built ({path}); run __graft_entry__.build() first")
+    L = ctypes.CDLL(path)
+    vp, i32p = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)
+    L.pa_row_words.argtypes = [ctypes.c_int32]
+    L.pa_row_words.restype = ctypes.c_int64
+    L.pa_array_words.argtypes = [ctypes.c_int32, i32p]
+    L.pa_array_words.restype = ctypes.c_int64
+    L.pa_last_error.restype = ctypes.c_char_p
+    L.pa_plot_relation.argtypes = [ctypes.POINTER(Relation), ctypes.POINTER(Axis), ctypes.POINTER(Opts),
+                                   ctypes.POINTER(BitArray), ctypes.POINTER(Report), vp]
+    L.pa_contract.argtypes = [ctypes.POINTER(BitArray), i32p, ctypes.POINTER(BitArray), i32p, i32p, ctypes.c_int32,
+                              ctypes.POINTER(BitArray), ctypes.POINTER(Opts), vp]
+    L.pa_plan_create.argtypes = [ctypes.POINTER(System), i32p, ctypes.c_int32, ctypes.POINTER(Opts),
+                                 ctypes.POINTER(vp)]
+    L.pa_plan_execute.argtypes = [vp, ctypes.POINTER(BitArray), ctypes.POINTER(Report), vp]
+    L.pa_plan_workspace_bytes.argtypes = [vp]
+    L.pa_plan_workspace_bytes.restype = ctypes.c_size_t
+    L.pa_plan_describe.argtypes = [ctypes.POINTER(System), i32p, ctypes.c_int32, ctypes.POINTER(Opts),
+                                   ctypes.c_char_p, ctypes.c_int64]
+    L.pa_plan_describe.restype = ctypes.c_int64
+    L.pa_plan_destroy.argtypes = [vp]
+    L.pa_plan_destroy.restype = None
+    L.pa_solve_system.argtypes = [ctypes.POINTER(System), i32p, ctypes.c_int32, ctypes.POINTER(Opts),
+                                  ctypes.POINTER(BitArray), ctypes.POINTER(Report), vp]
+    L.pa_popcount.argtypes = [ctypes.POINTER(BitArray), ctypes.POINTER(ctypes.c_int64), vp]
+    _lib = L
+    return L
+
+
+def _check(rc):
+    if rc != PA_OK:
+        raise PaError(rc, load().pa_last_error().decode())
+
+
+def row_words(d: int) -> int:
+    return int(load().pa_row_words(d))
+
+
+def array_words(dims: Sequence[int]) -> int:
+    arr = (ctypes.c_int32 * max(1, len(dims)))(*dims)
+    return int(load().pa_array_words(len(dims), arr))
+
+
+# ------------------------------------------------------------ marshalling
+class _Keep:
+    """Holds ctypes buffers alive for the duration of a call."""
+
+    def __init__(self):
+        self.items = []
+
+    def i32(self, seq):
+        a = (ctypes.c_int32 * max(1, len(seq)))(*[int(x) for x in seq])
+        self.items.append(a)
+        return a
+
+    def f64(self, seq):
+        arr = np.ascontiguousarray(np.asarray(seq, dtype=np.float64))
+        self.items.append(arr)
+        return arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _relation(keep, rel, var_map=None) -> Relation:
+    vs = list(rel.vars) if var_map is None else [var_map[v] for v in rel.vars]
+    return Relation(len(vs), int(rel.degree), keep.i32(vs), keep.f64(rel.coef))
+
+
+def _system(keep, system) -> System:
+    axes = (Axis * len(system.axes))(*[Axis(float(lo), float(hi), int(r), 0) for lo, hi, r in system.axes])
+    rels = (Relation * len(system.relations))(*[_relation(keep, r) for r in system.relations])
+    keep.items += [axes, rels]
+    return System(len(system.axes), axes, len(system.relations), rels)
+
+
+def make_opts(order=ORDER_EXHAUSTIVE, precision=PLOT_FP32_ESCALATE, audit=False, timing=False, plain=False,
+              given: Optional[Sequence[int]] = None, model=None, keep: Optional[_Keep] = None) -> Opts:
+    o = Opts()
+    o.order_policy = order
+    o.precision = precision
+    o.audit = int(audit)
+    o.timing = int(timing)
+    o.plain = int(plain)
+    if given is not None:
+        assert keep is not None
+        o.n_given = len(given) // 2
+        o.given = keep.i32(given)
+    if model is not None:
+        o.model = ctypes.c_void_p(model.handle if hasattr(model, "handle") else model)
+    return o
+
+
+def _stream_ptr(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def empty_bits(dims: Sequence[int], device="cuda"):
+    """Device buffer (torch int32) for a bit array with the given dims."""
+    import torch
+    return torch.zeros(array_words(dims), dtype=torch.int32, device=device)
+
+
+def bitarray(t, dims: Sequence[int]) -> BitArray:
+    b = BitArray()
+    b.data = ctypes.c_void_p(t.data_ptr())
+    b.ndim = len(dims)
+    for i, d in enumerate(dims):
+        b.dims[i] = int(d)
+    b.row_words = row_words(dims[-1]) if len(dims) else 1
+    return b
+
+
+# ---------------------------------------------------------- host helpers
+def unpack_bits(words: np.ndarray, dims: Sequence[int]) -> np.ndarray:
+    """Host-side view: packed words -> one byte per entry (for reading results)."""
+    w = np.ascontiguousarray(np.asarray(words).view(np.uint32))
+    if len(dims) == 0:
+        return np.array(w[0] & 1, dtype=np.uint8)
+    rw = row_words(dims[-1])
+    rows = int(np.prod(dims[:-1])) if len(dims) > 1 else 1
+    bits = np.unpackbits(w.reshape(rows, rw).view(np.uint8), axis=1, bitorder="little")
+    return bits[:, :dims[-1]].reshape(tuple(dims)).astype(np.uint8)
+
+
+def pack_bits(arr: np.ndarray) -> np.ndarray:
+    """Host-side: one byte per entry -> packed int32 words (for passing inputs)."""
+    arr = np.asarray(arr, dtype=np.uint8)
+    dims = arr.shape
+    if len(dims) == 0:
+        return np.array([int(arr) & 1], dtype=np.uint32).view(np.int32)
+    rw = row_words(dims[-1])
+    rows = int(np.prod(dims[:-1])) if len(dims) > 1 else 1
+    padded = np.zeros((rows, rw * 32), dtype=np.uint8)
+    padded[:, :dims[-1]] = arr.reshape(rows, dims[-1])
+    return np.packbits(padded, axis=1, bitorder="little").view(np.uint32).reshape(-1).view(np.int32)
+
+
+# ------------------------------------------------------------ entry points
+def plot_relation(rel, axes_of_vars, precision=PLOT_FP32_ESCALATE, audit=False, stream=None, report=True):
+    """Plot one relation; returns (device words, dims, report dict or None)."""
+    L = load()
+    keep = _Keep()
+    r = _relation(keep, rel, {v: i for i, v in enumerate(rel.vars)})
+    axes = (Axis * len(axes_of_vars))(*[Axis(float(lo), float(hi), int(res), 0) for lo, hi, res in axes_of_vars])
+    dims = [int(a[2]) for a in axes_of_vars]
+    out = empty_bits(dims)
+    ba = bitarray(out, dims)
+    opts = make_opts(precision=precision, audit=audit)
+    rep = Report()
+    _check(L.pa_plot_relation(ctypes.byref(r), axes, ctypes.byref(opts), ctypes.byref(ba),
+                              ctypes.byref(rep) if report else None, _stream_ptr(stream)))
+    return out, dims, (rep.as_dict() if report else None)
+
+
+def contract(A, a_dims, a_vars, B, b_dims, b_vars, out_vars, out_dims, stream=None, plain=False):
+    """C(out_vars) = OR over the other variables of A AND B (B may be None)."""
+    L = load()
+    keep = _Keep()
+    C = empty_bits(out_dims)
+    ba, bc = bitarray(A, a_dims), bitarray(C, out_dims)
+    bb = bitarray(B, b_dims) if B is not None else None
+    opts = make_opts(plain=plain)
+    _check(L.pa_contract(ctypes.byref(ba), keep.i32(a_vars), ctypes.byref(bb) if bb is not None else None,
+                         keep.i32(b_vars if B is not None else []), keep.i32(out_vars), len(out_vars),
+                         ctypes.byref(bc), ctypes.byref(opts), _stream_ptr(stream)))
+    return C
+
+
+def describe_plan(system, exposed=None, order=ORDER_EXHAUSTIVE, precision=PLOT_FP32_ESCALATE,
+                  given=None, plain=False) -> dict:
+    """Host-only: the plan (tree, layouts, kernels) as a dict."""
+    L = load()
+    keep = _Keep()
+    exposed = list(system.exposed if exposed is None else exposed)
+    s = _system(keep, system)
+    opts = make_opts(order=order, precision=precision, given=given, plain=plain, keep=keep)
+    n = L.pa_plan_describe(ctypes.byref(s), keep.i32(exposed), len(exposed), ctypes.byref(opts), None, 0)
+    buf = ctypes.create_string_buffer(int(n) + 1)
+    L.pa_plan_describe(ctypes.byref(s), keep.i32(exposed), len(exposed), ctypes.byref(opts), buf, n + 1)
+    return json.loads(buf.value.decode())
+
+
+class Plan:
+    """A planned solve: pa_plan_create once, execute many times."""
+
+    def __init__(self, system, exposed=None, order=ORDER_EXHAUSTIVE, precision=PLOT_FP32_ESCALATE, audit=False,
+                 timing=False, plain=False, given=None, model=None):
+        L = load()
+        self._keep = _Keep()
+        self.exposed = list(system.exposed if exposed is None else exposed)
+        self.dims = [int(system.axes[v][2]) for v in self.exposed]
+        s = _system(self._keep, system)
+        opts = make_opts(order=order, precision=precision, audit=audit, timing=timing, plain=plain, given=given,
+                         model=model, keep=self._keep)
+        h = ctypes.c_void_p()
+        _check(L.pa_plan_create(ctypes.byref(s), self._keep.i32(self.exposed), len(self.exposed),
+                                ctypes.byref(opts), ctypes.byref(h)))
+        self.handle = h
+
+    def workspace_bytes(self) -> int:
+        return int(load().pa_plan_workspace_bytes(self.handle))
+
+    def execute(self, out=None, stream=None, report=False):
+        L = load()
+        if out is None:
+            out = empty_bits(self.dims)
+        ba = bitarray(out, self.dims)
+        rep = Report() if report else None
+        _check(L.pa_plan_execute(self.handle, ctypes.byref(ba), ctypes.byref(rep) if report else None,
+                                 _stream_ptr(stream)))
+        return out, (rep.as_dict() if report else None), (list(rep.merges[:2 * 31]) if report else None)
+
+    def __del__(self):
+        try:
+            if getattr(self, "handle", None) and _lib is not None:
+                _lib.pa_plan_destroy(self.handle)
+                self.handle = None
+        except Exception:
+            pass
+
+
+def solve_system(system, exposed=None, **kw):
+    """Plan + execute; returns (device words, dims, report dict)."""
+    p = Plan(system, exposed, **kw)
+    out, rep, _ = p.execute(report=True)
+    return out, p.dims, rep
+
+
+def popcount(t, dims) -> int:
+    L = load()
+    c = ctypes.c_int64(0)
+    ba = bitarray(t, dims)
+    _check(L.pa_popcount(ctypes.byref(ba), ctypes.byref(c), _stream_ptr()))
+    return int(c.value)

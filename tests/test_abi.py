@@ -1,0 +1,136 @@
+"""CPU tests of the C ABI library: it loads, exports every symbol include/pa.h
+declares, validates inputs, and its host planner agrees with the planner
+reference.  No kernel is launched here."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import planner as P
+from paper_1609_00061_amd import inputs, pa
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    names = []
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if not fn.endswith(".h"):
+            continue
+        src = open(os.path.join(ROOT, "include", fn)).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        names += re.findall(r"\b(pa_[a-z_0-9]+)\s*\(", src)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    L = pa.load()
+    names = _declared_functions()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_row_words_and_sizes():
+    assert pa.row_words(1) == 2 and pa.row_words(64) == 2 and pa.row_words(65) == 4
+    assert pa.row_words(1024) == 32 and pa.row_words(2049) == 66
+    assert pa.array_words([]) == 1
+    assert pa.array_words([3, 5, 70]) == 3 * 5 * 4
+
+
+@pytest.mark.parametrize("dims", [(), (1,), (5,), (3, 64), (2, 3, 65), (4, 129)])
+def test_pack_unpack_roundtrip(dims):
+    a = inputs.random_bool_array(dims, 0.5, 11)
+    w = pa.pack_bits(a)
+    assert w.size == pa.array_words(list(dims))
+    assert np.array_equal(pa.unpack_bits(w, dims), a)
+
+
+def _kernels(plan):
+    return [o["op"] for o in plan["ops"] if o["op"] != "fill"]
+
+
+def test_plans_put_dense_steps_on_mfma():
+    c1 = pa.describe_plan(inputs.config1())
+    assert _kernels(c1) == ["gemm_mfma"]
+    c2 = pa.describe_plan(inputs.config2())
+    assert _kernels(c2) == ["gemm_mfma"] * 7
+    c3 = pa.describe_plan(inputs.config3())
+    assert _kernels(c3) == ["gemm_mfma", "gemm_mfma", "stream_k"]
+    g = [o for o in c3["ops"] if o["op"] == "gemm_mfma"]
+    assert g[0]["M"] == 65536 and g[0]["No"] * g[0]["rn"] == 65536 and g[0]["Kw"] == 8
+    assert g[1]["batch"] == 256 and g[1]["M"] == 65536 and g[1]["rn"] == 256
+
+
+def _packs(s):
+    return [tuple(r.vars) for r in s.relations]
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_exhaustive_planner_matches_reference_dp(seed):
+    """The library's exhaustive order reaches the minimum binary cluster-tree
+    cost of the planner reference (Sec. 3.5 cost model)."""
+    g = inputs.config5(n_graphs=1, index=1000 + seed, res=128)[0]
+    if len(g.relations) > 11:
+        pytest.skip("reference DP in Python too slow for this size")
+    d = pa.describe_plan(g, order=pa.ORDER_EXHAUSTIVE)
+    res = {v: g.axes[v][2] for v in range(len(g.axes))}
+    # Latent variables private to one relation are projected first by a
+    # one-pack cluster node (cost r^vars); the rest is a binary tree on the
+    # intermediate packs Q of the relations.
+    packs = _packs(g)
+    qpacks = [tuple(sorted(P.q_pack([i], packs, g.exposed))) for i in range(len(packs))]
+    unary = sum(int(np.prod([res[v] for v in p])) for p, q in zip(packs, qpacks) if len(q) < len(p))
+    best, _ = P.optimal_cost(qpacks, g.exposed, res=res, binary=True)
+    best += unary
+    assert d["cost"] == pytest.approx(best, rel=1e-12)
+    dg = pa.describe_plan(g, order=pa.ORDER_GREEDY)
+    assert dg["cost"] >= best * (1 - 1e-12)
+
+
+def test_given_order_cost_matches_reference():
+    s = inputs.config3()
+    merges = [0, 1, 4, 2, 5, 3]
+    d = pa.describe_plan(s, order=pa.ORDER_GIVEN, given=merges)
+    tree = (((0, 1), 2), 3)
+    res = {v: 256 for v in range(6)}
+    assert d["cost"] == pytest.approx(P.tree_cost(tree, _packs(s), s.exposed, res=res)[0], rel=1e-12)
+    assert d["merges"] == merges
+
+
+def _bad(system, exposed=None, **kw):
+    d = pa.describe_plan(system, exposed, **kw)
+    return d.get("error")
+
+
+def test_validation_errors():
+    c1 = inputs.config1()
+    assert _bad(c1) is None
+    s = inputs.config1()
+    s.axes = [(-2.0, 2.0, 1)] + s.axes[1:]
+    assert _bad(s) == pa.PA_EINVAL                      # resolution < 2
+    s = inputs.config1()
+    s.axes = [(2.0, -2.0, 64)] + s.axes[1:]
+    assert _bad(s) == pa.PA_EINVAL                      # lo > hi
+    s = inputs.config1()
+    s.axes = s.axes + [(-1.0, 1.0, 8)]
+    assert _bad(s) == pa.PA_EINVAL                      # variable in no relation
+    assert _bad(c1, exposed=[0, 0]) == pa.PA_EINVAL     # repeated exposed
+    assert _bad(c1, exposed=[7]) == pa.PA_EINVAL        # out of range
+    s = inputs.config1()
+    s.relations[0].coef[1] = float("nan")
+    assert _bad(s) == pa.PA_EINVAL                      # non-finite coefficient
+    assert _bad(c1, order=pa.ORDER_GIVEN, given=[0, 0]) == pa.PA_EINVAL
+    s = inputs.config1()
+    s.relations[0] = inputs.Relation((0, 0), 2, s.relations[0].coef)
+    assert _bad(s) == pa.PA_EINVAL                      # repeated variable in a relation
+
+
+def test_plan_create_rejects_before_touching_the_device():
+    s = inputs.config1()
+    s.axes = [(-2.0, 2.0, 1)] + s.axes[1:]
+    with pytest.raises(pa.PaError) as e:
+        pa.Plan(s)
+    assert e.value.code == pa.PA_EINVAL

@@ -1,0 +1,96 @@
+"""GPU parity of whole solves (plot + cluster tree of contractions) against
+the oracle, bit-exact, for every order policy."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1609_00061_amd import inputs, pa
+from gpu_util import note, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+def _oracle_plots(s):
+    return [oracle.plot(r, s.axes)[0] for r in s.relations]
+
+
+def _solve(s, **kw):
+    note("solve", s.name, kw)
+    out, dims, rep = pa.solve_system(s, **kw)
+    return to_host(out, dims), rep
+
+
+@pytest.mark.parametrize("precision", [pa.PLOT_FP64, pa.PLOT_FP32_ESCALATE])
+def test_c1_solve(precision):
+    s = inputs.config1()
+    got, rep = _solve(s, precision=precision)
+    ref = oracle.solve([a[2] for a in s.axes], [r.vars for r in s.relations], _oracle_plots(s), s.exposed)
+    assert ref.sum() == 180
+    assert np.array_equal(got, ref)
+    assert rep["nnz_out"] == 180
+
+
+def _random_small_system(seed):
+    rng = inputs.SplitMix64(seed)
+    g = inputs.random_hypergraph(rng, res=rng.randint(5, 24))
+    # uneven resolutions
+    g.axes = [(-3.0, 3.0, rng.randint(3, 40)) for _ in g.axes]
+    g.name = f"small{seed}"
+    return g
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_random_hypergraphs_all_policies(seed):
+    s = _random_small_system(4200 + seed)
+    res = [a[2] for a in s.axes]
+    ref = oracle.solve(res, [r.vars for r in s.relations], _oracle_plots(s), s.exposed)
+    outs = []
+    for order in (pa.ORDER_GREEDY, pa.ORDER_EXHAUSTIVE):
+        got, rep = _solve(s, order=order)
+        assert np.array_equal(got, ref), order
+        outs.append(got)
+    # a deliberately poor given order (left to right) gives the same bits
+    n = len(s.relations)
+    merges = [0, 1] + [x for t in range(1, n - 1) for x in (n + t - 1, t + 1)]
+    got, _ = _solve(s, order=pa.ORDER_GIVEN, given=merges)
+    assert np.array_equal(got, ref)
+
+
+def test_c2_reduced_resolution_exact():
+    s = inputs.config2(res=128)
+    res = [a[2] for a in s.axes]
+    ref = oracle.solve(res, [r.vars for r in s.relations], _oracle_plots(s), s.exposed)
+    got, rep = _solve(s)
+    assert np.array_equal(got, ref)
+
+
+def test_c2_full_size_exact():
+    """Chain of 8 at 1024 per axis: the oracle multiplies the chain pairwise
+    (Sec. 3.5 clustering, left to right)."""
+    s = inputs.config2()
+    plots = _oracle_plots(s)
+    res = {v: s.axes[v][2] for v in range(len(s.axes))}
+    merges = [(0, 1)] + [(8 + t, t + 2) for t in range(6)]
+    ref = oracle.solve_pairwise(res, [r.vars for r in s.relations], plots, s.exposed, merges)
+    got, rep = _solve(s)
+    assert np.array_equal(got, ref)
+    got2, _ = _solve(s, plain=True, order=pa.ORDER_GREEDY)
+    assert np.array_equal(got2, ref)
+
+
+def test_c3_full_size_sampled():
+    """Four ternary relations at 256^3: sampled output entries evaluated one by
+    one by the oracle (eqn GAM with short-circuit), plus every set entry."""
+    s = inputs.config3()
+    plots = _oracle_plots(s)
+    got, rep = _solve(s)
+    res = [a[2] for a in s.axes]
+    rng = inputs.SplitMix64(77)
+    ent = np.array([[rng.randint(0, 255), rng.randint(0, 255)] for _ in range(200)], dtype=np.int32)
+    on = np.argwhere(got == 1)
+    if len(on) > 300:
+        on = on[:: max(1, len(on) // 300)]
+    ent = np.concatenate([ent, on.astype(np.int32)]) if len(on) else ent
+    ref = oracle.solve_entries(res, [r.vars for r in s.relations], plots, s.exposed, ent)
+    assert np.array_equal(got[tuple(ent.T)], ref)
+    note("c3 nnz", int(got.sum()), "flagged", rep["corners_flagged"])
