@@ -126,7 +126,8 @@ typedef struct {
     int32_t precision;        /* PA_PLOT_*                                          */
     int32_t audit;            /* 1: also evaluate every corner in FP64 and count
                                  FP32/FP64 sign disagreements (slow; diagnostics)  */
-    int32_t timing;           /* 1: time plot and contraction phases with events    */
+    int32_t timing;           /* 1: time plot and contraction phases with events;
+                                 2: also time every op (see pa_plan_op_times)       */
     int32_t plain;            /* 1: the plain GPU path (one launch per step, default
                                  tiles, no fused plotting of all relations)         */
     const pa_model *model;    /* PA_ORDER_LEARNED: the cost model                   */
@@ -195,6 +196,16 @@ size_t pa_plan_workspace_bytes(const pa_plan *plan);
 int64_t pa_plan_describe(const pa_system *sys, const int32_t *exposed, int32_t n_exposed, const pa_opts *opts,
                          char *buf, int64_t buf_len);
 void pa_plan_destroy(pa_plan *plan);
+
+/* Per-op kernel durations of the last pa_plan_execute of a plan created with
+ * opts->timing == 2, measured with HIP events recorded on the execution
+ * stream around each op.  Fills up to cap entries: ms[i] (milliseconds),
+ * kind[i] (PA_OPKIND_*) and macs[i] (product of the op's link resolutions,
+ * eqn naive_cost; 0 for plots and fills).  Waits for the events.  Returns
+ * the number of ops, or -1 if the plan does not record op timings. */
+enum { PA_OPKIND_BITS = 0, PA_OPKIND_STREAM_K = 1, PA_OPKIND_STREAM_W = 2, PA_OPKIND_GEMM = 10,
+       PA_OPKIND_FILL = 20, PA_OPKIND_PLOT = 30 };
+int32_t pa_plan_op_times(pa_plan *plan, double *ms, int32_t *kind, double *macs, int32_t cap);
 
 /* pa_plan_create + pa_plan_execute + pa_plan_destroy. */
 int pa_solve_system(const pa_system *sys, const int32_t *exposed, int32_t n_exposed, const pa_opts *opts,

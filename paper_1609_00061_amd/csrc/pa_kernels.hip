@@ -13,6 +13,14 @@
 namespace pa {
 
 // ------------------------------------------------------------------ helpers
+// Blocks for `total` threads, capped (the kernels loop over the rest).
+static dim3 grid_for(int64_t total) {
+    int64_t blocks = (total + 255) / 256;
+    if (blocks > (1 << 20)) blocks = 1 << 20;
+    if (blocks < 1) blocks = 1;
+    return dim3((unsigned)blocks);
+}
+
 __device__ __forceinline__ int find_by_base(const PlotRel *rels, int nrel, int64_t idx, bool lines) {
     int lo = 0, hi = nrel - 1;
     while (lo < hi) {
@@ -82,11 +90,11 @@ __device__ double canon_eval(const double *__restrict__ c, int n, int d, const d
 // A corner is escalated unless E < |p^| <= FLT_MAX; otherwise
 // |f_exact| > E - gamma S >= |f64 - f_exact|, so sign(p^) = sign(f64) != 0.
 __global__ void k_plot_lines(const PlotRel *__restrict__ rels, int nrel, int64_t total_lines) {
-    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gid >= total_lines) return;
+  for (int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gid < total_lines;
+       gid += (int64_t)gridDim.x * blockDim.x) {
     const PlotRel &R = rels[find_by_base(rels, nrel, gid, true)];
     const int64_t L = gid - R.line_base;
-    if (L >= R.n_lines) return;
+    if (L >= R.n_lines) continue;
     const int n = R.n, d = R.d, D1 = d + 1;
     const int pk = R.perm[n - 1];                 // declared index of the packed variable
     double xd[kMaxA] = {0.0, 0.0, 0.0};
@@ -128,16 +136,20 @@ __global__ void k_plot_lines(const PlotRel *__restrict__ rels, int nrel, int64_t
     float *dst = R.lines + L * (kMaxD + 2);
     for (int t = 0; t <= d; ++t) dst[t] = (float)a[t];
     dst[kMaxD + 1] = Ef;
+  }
 }
 
 // ------------------------------------------------------------ plot: cells
 // One thread per output word: 32 cells along the packed axis at fixed cell
 // indices on the other axes.  The cell is set iff its 2^n corners include
 // f <= 0 and f >= 0 (closed cells; a NaN corner counts as neither).
+// A corner is evaluated by every thread whose cells touch it; only its owner
+// counts it (lower cell on every axis, or the last cell where there is none).
 __global__ void k_plot_cells(const PlotRel *__restrict__ rels, int nrel, int64_t total_words,
                              PlotCounters *__restrict__ counters) {
-    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    unsigned long long nflag = 0, ndis = 0, ndis_unf = 0;
+  unsigned long long nflag = 0, ndis = 0, ndis_unf = 0;
+  for (int64_t g0 = (int64_t)blockIdx.x * blockDim.x; g0 < total_words; g0 += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t gid = g0 + threadIdx.x;
     if (gid < total_words) {
         const PlotRel &R = rels[find_by_base(rels, nrel, gid, false)];
         const int64_t local = gid - R.word_base;
@@ -162,7 +174,11 @@ __global__ void k_plot_cells(const PlotRel *__restrict__ rels, int nrel, int64_t
                     L = L * (R.res[s] + 1) + li[s];
                 }
                 double xdec[kMaxA] = {0.0, 0.0, 0.0};
-                for (int s = 0; s < n - 1; ++s) xdec[R.perm[s]] = R.ax[s][li[s]];
+                bool line_owned = true;
+                for (int s = 0; s < n - 1; ++s) {
+                    xdec[R.perm[s]] = R.ax[s][li[s]];
+                    line_owned &= (((dl >> s) & 1) == 0) || (li[s] == R.res[s]);
+                }
                 const int pk = R.perm[n - 1];
                 uint64_t LE = 0, GE = 0;
                 if (R.mode == PA_PLOT_FP32_ESCALATE) {
@@ -176,6 +192,7 @@ __global__ void k_plot_cells(const PlotRel *__restrict__ rels, int nrel, int64_t
                         for (int t = d - 1; t >= 0; --t) f = fmaf(f, x, ca[t]);
                         const float af = fabsf(f);
                         const bool ok = (af > E) && (af <= FLT_MAX);
+                        const bool own = line_owned && (kk < kmax || k0 + kk == rp);
                         bool le, ge;
                         if (ok && !R.audit) {
                             le = f < 0.0f;
@@ -189,12 +206,12 @@ __global__ void k_plot_cells(const PlotRel *__restrict__ rels, int nrel, int64_t
                                 const int s32 = (f > 0.0f) - (f < 0.0f);
                                 const int s64 = (f64 > 0.0) - (f64 < 0.0);
                                 const bool dis = (s32 != s64) || (f != f) || (f64 != f64);
-                                ndis += dis;
-                                if (ok) ndis_unf += dis;
+                                ndis += dis && own;
+                                if (ok) ndis_unf += dis && own;
                                 if (ok) { le = f < 0.0f; ge = f > 0.0f; }
                             }
                         }
-                        nflag += !ok;
+                        nflag += (!ok) && own;
                         LE |= (uint64_t)le << kk;
                         GE |= (uint64_t)ge << kk;
                     }
@@ -214,6 +231,7 @@ __global__ void k_plot_cells(const PlotRel *__restrict__ rels, int nrel, int64_t
         }
         R.out[local] = word;
     }
+  }
     // counters: one atomic per wave, only when something was counted
     const unsigned long long any = __ballot(nflag != 0 || ndis != 0 || ndis_unf != 0);
     if (any && counters) {
@@ -226,15 +244,13 @@ __global__ void k_plot_cells(const PlotRel *__restrict__ rels, int nrel, int64_t
 hipError_t launch_plot(const PlotRel *d_rels, int nrel, int64_t total_lines, int64_t total_words,
                        int mode_any_fp32, PlotCounters *d_counters, hipStream_t s, int *n_launches) {
     if (mode_any_fp32 && total_lines > 0) {
-        const int64_t blocks = (total_lines + 255) / 256;
-        hipLaunchKernelGGL(k_plot_lines, dim3((unsigned)blocks), dim3(256), 0, s, d_rels, nrel, total_lines);
+        hipLaunchKernelGGL(k_plot_lines, grid_for(total_lines), dim3(256), 0, s, d_rels, nrel, total_lines);
         if (n_launches) ++*n_launches;
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     if (total_words > 0) {
-        const int64_t blocks = (total_words + 255) / 256;
-        hipLaunchKernelGGL(k_plot_cells, dim3((unsigned)blocks), dim3(256), 0, s, d_rels, nrel, total_words,
+        hipLaunchKernelGGL(k_plot_cells, grid_for(total_words), dim3(256), 0, s, d_rels, nrel, total_words,
                            d_counters);
         if (n_launches) ++*n_launches;
     }
@@ -250,8 +266,10 @@ __device__ __forceinline__ void decode_out(const ContractArgs &a, int64_t row, i
 
 // General mode: one thread per output bit; every latent entry visited bit by
 // bit (any layouts).
-__global__ void k_contract_bits(ContractArgs a) {
-    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void k_contract_bits(ContractArgs a, int64_t total) {
+  // grid-stride over whole blocks: every wave keeps 64 consecutive bits
+  for (int64_t g0 = (int64_t)blockIdx.x * blockDim.x; g0 < total; g0 += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t gid = g0 + threadIdx.x;
     const int64_t rowbits = a.c_row_words * 32;
     const int64_t row = gid / rowbits, bit = gid % rowbits;
     bool valid;
@@ -297,13 +315,15 @@ __global__ void k_contract_bits(ContractArgs a) {
             dst[1] = (uint32_t)(bits >> 32);
         }
     }
+  }
 }
 
 // Stream mode K: A and B are both bit-packed along the same latent variable;
 // words are AND-ed along it (16 bytes at a time when rows allow).
 template <bool VEC4>
-__global__ void k_contract_stream_k(ContractArgs a) {
-    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void k_contract_stream_k(ContractArgs a, int64_t total) {
+  for (int64_t g0 = (int64_t)blockIdx.x * blockDim.x; g0 < total; g0 += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t gid = g0 + threadIdx.x;
     const int64_t rowbits = a.c_row_words * 32;
     const int64_t row = gid / rowbits, bit = gid % rowbits;
     bool valid;
@@ -367,15 +387,15 @@ __global__ void k_contract_stream_k(ContractArgs a) {
             dst[1] = (uint32_t)(bits >> 32);
         }
     }
+  }
 }
 
 // Stream mode W: A, B and C share the packed variable (an output variable);
 // one thread per output word ORs the AND of whole words over the latent
 // entries.
-__global__ void k_contract_stream_w(ContractArgs a) {
-    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t total = a.n_out_rows * a.c_row_words;
-    if (gid >= total) return;
+__global__ void k_contract_stream_w(ContractArgs a, int64_t total) {
+  for (int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gid < total;
+       gid += (int64_t)gridDim.x * blockDim.x) {
     const int64_t row = gid / a.c_row_words, wc = gid % a.c_row_words;
     const int64_t last = a.out_dim[a.nout - 1];
     uint32_t acc = 0;
@@ -404,6 +424,7 @@ __global__ void k_contract_stream_w(ContractArgs a) {
         }
     }
     a.C[row * a.c_row_words + wc] = acc;
+  }
 }
 
 hipError_t launch_contract(const ContractArgs &a, int mode, hipStream_t s) {
@@ -411,19 +432,19 @@ hipError_t launch_contract(const ContractArgs &a, int mode, hipStream_t s) {
     if (mode == kModeStreamW) {
         const int64_t total = a.n_out_rows * a.c_row_words;
         if (total == 0) return hipSuccess;
-        hipLaunchKernelGGL(k_contract_stream_w, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, a);
+        hipLaunchKernelGGL(k_contract_stream_w, grid_for(total), dim3(256), 0, s, a, total);
         return hipGetLastError();
     }
     const int64_t total = (a.nout == 0) ? 64 : a.n_out_rows * rowbits;
     if (total == 0) return hipSuccess;
-    const dim3 grid((unsigned)((total + 255) / 256));
+    const dim3 grid = grid_for(total);
     if (mode == kModeStreamK) {
         if (a.a_row_words % 4 == 0)
-            hipLaunchKernelGGL(k_contract_stream_k<true>, grid, dim3(256), 0, s, a);
+            hipLaunchKernelGGL(k_contract_stream_k<true>, grid, dim3(256), 0, s, a, total);
         else
-            hipLaunchKernelGGL(k_contract_stream_k<false>, grid, dim3(256), 0, s, a);
+            hipLaunchKernelGGL(k_contract_stream_k<false>, grid, dim3(256), 0, s, a, total);
     } else {
-        hipLaunchKernelGGL(k_contract_bits, grid, dim3(256), 0, s, a);
+        hipLaunchKernelGGL(k_contract_bits, grid, dim3(256), 0, s, a, total);
     }
     return hipGetLastError();
 }

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -669,7 +670,10 @@ static uint32_t *buf_ptr(pa_plan *P, int id, void *out) {
 }
 
 static int run_ops(pa_plan *P, void *out, hipStream_t s, int *launches) {
-    for (const Op &op0 : P->ops) {
+    const bool per_op = !P->op_events.empty();
+    for (size_t oi = 0; oi < P->ops.size(); ++oi) {
+        const Op &op0 = P->ops[oi];
+        if (per_op) HIP_TRY(hipEventRecord(P->op_events[2 + 2 * oi], s));
         if (op0.kind == OP_FILL) {
             HIP_TRY(launch_fill(buf_ptr(P, op0.c, out), op0.fill_words, 0u, s));
             ++*launches;
@@ -692,6 +696,7 @@ static int run_ops(pa_plan *P, void *out, hipStream_t s, int *launches) {
             HIP_TRY(launch_contract(a, op0.mode, s));
             ++*launches;
         }
+        if (per_op) HIP_TRY(hipEventRecord(P->op_events[3 + 2 * oi], s));
     }
     return PA_OK;
 }
@@ -736,13 +741,53 @@ extern "C" int pa_plan_create(const pa_system *sys, const int32_t *exposed, int3
         P->ws.cap = opts->workspace_bytes;
         P->ws.external = true;
     } else {
+        // refuse plans whose intermediates cannot fit instead of attempting
+        // an allocation the device cannot satisfy
+        size_t free_b = 0, total_b = 0;
+        if (hipMemGetInfo(&free_b, &total_b) != hipSuccess)
+            return fail(PA_EHIP, "plan_create: no usable HIP device");
+        size_t cap = free_b > ((size_t)1 << 30) ? free_b - ((size_t)1 << 30) : 0;
+        if (const char *env = std::getenv("PA_MAX_WORKSPACE_BYTES")) cap = std::min<size_t>(cap, std::strtoull(env, nullptr, 10));
+        if (P->ws_bytes > cap)
+            return fail(PA_ENOMEM, "plan needs " + std::to_string(P->ws_bytes) + " bytes of workspace, " +
+                                       std::to_string(cap) + " available (choose another order)");
         rc = P->ws.ensure(std::max<size_t>(P->ws_bytes, 256));
         if (rc) return rc;
     }
     rc = upload(P.get());
     if (rc) return rc;
+    if (opts && opts->timing == 2) {
+        P->op_events.resize(2 + 2 * P->ops.size());
+        for (auto &e : P->op_events) HIP_TRY(hipEventCreate(&e));
+    }
     *plan = P.release();
     return PA_OK;
+}
+
+pa_plan::~pa_plan() {
+    for (auto &e : op_events)
+        if (e) (void)hipEventDestroy(e);
+}
+
+extern "C" int32_t pa_plan_op_times(pa_plan *P, double *ms, int32_t *kind, double *macs, int32_t cap) {
+    if (!P || P->op_events.empty() || !P->op_events_recorded) return fail(PA_EINVAL, "op_times: no op timings"), -1;
+    const int32_t n = 1 + (int32_t)P->ops.size();
+    if (hipEventSynchronize(P->op_events.back()) != hipSuccess) return fail(PA_EHIP, "op_times: sync"), -1;
+    for (int32_t i = 0; i < n && i < cap; ++i) {
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, P->op_events[2 * i], P->op_events[2 * i + 1]) != hipSuccess) t = -1.f;
+        if (ms) ms[i] = t;
+        int k = PA_OPKIND_PLOT;
+        double mc = 0.0;
+        if (i > 0) {
+            const Op &op = P->ops[i - 1];
+            k = op.kind == OP_GEMM ? PA_OPKIND_GEMM : op.kind == OP_FILL ? PA_OPKIND_FILL : op.mode;
+            mc = op.kind == OP_FILL ? 0.0 : op.macs;
+        }
+        if (kind) kind[i] = k;
+        if (macs) macs[i] = mc;
+    }
+    return n;
 }
 
 extern "C" size_t pa_plan_workspace_bytes(const pa_plan *plan) { return plan ? plan->ws_bytes : 0; }
@@ -766,8 +811,13 @@ extern "C" int pa_plan_execute(pa_plan *P, pa_bitarray *out, pa_report *rep, voi
         launches += 2;
     }
     if (timing) HIP_TRY(hipEventRecord(ev[0], s));
+    if (!P->op_events.empty()) HIP_TRY(hipEventRecord(P->op_events[0], s));
     rc = run_plots(P, s, &launches);
     if (rc) return rc;
+    if (!P->op_events.empty()) {
+        HIP_TRY(hipEventRecord(P->op_events[1], s));
+        P->op_events_recorded = true;
+    }
     if (timing) HIP_TRY(hipEventRecord(ev[1], s));
     rc = run_ops(P, out->data, s, &launches);
     if (rc) return rc;

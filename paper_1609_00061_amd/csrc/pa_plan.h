@@ -127,4 +127,7 @@ struct pa_plan {
     bool uploaded = false;
     double t_plan_ms = 0.0;
     pa::Layout out_layout;
+    std::vector<hipEvent_t> op_events;     // timing == 2: 2 per op + 2 for plotting
+    bool op_events_recorded = false;
+    ~pa_plan();
 };

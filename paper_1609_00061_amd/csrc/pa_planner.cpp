@@ -117,7 +117,9 @@ int tree_from_merges(const SysInfo &si, const std::vector<int> &merges, Tree &t)
 }
 
 // Greedy: repeatedly multiply the pair of current factors whose node is the
-// cheapest (ties: lowest factor ids).
+// cheapest among pairs sharing a variable (a pair without one is a Kronecker
+// product and is taken only when no factors share anything); ties: smaller
+// output pack, then lowest factor ids.
 int plan_greedy(const SysInfo &si, Tree &t) {
     const int n = si.n_rel;
     std::vector<int> alive(n);
@@ -132,12 +134,23 @@ int plan_greedy(const SysInfo &si, Tree &t) {
     int next = n;
     std::vector<int> ids(alive);
     while (ids.size() > 1) {
-        double best = std::numeric_limits<double>::infinity();
+        double best = std::numeric_limits<double>::infinity(), best_out = 0.0;
         int bi = -1, bj = -1;
+        bool best_shares = false;
         for (size_t i = 0; i < ids.size(); ++i)
             for (size_t j = i + 1; j < ids.size(); ++j) {
+                const bool shares = (q[i] & q[j]) != 0;
                 const double c = mask_cost(q[i] | q[j], si);
-                if (c < best) { best = c; bi = (int)i; bj = (int)j; }
+                const double out = mask_cost(q_of(leaves[i] | leaves[j], si), si);
+                const bool better = (shares && !best_shares) ||
+                                    (shares == best_shares && (c < best || (c == best && out < best_out)));
+                if (bi < 0 || better) {
+                    best = c;
+                    best_out = out;
+                    best_shares = shares;
+                    bi = (int)i;
+                    bj = (int)j;
+                }
             }
         merges.push_back(ids[bi]);
         merges.push_back(ids[bj]);

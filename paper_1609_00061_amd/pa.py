@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libpa.so")
 
 PA_OK, PA_EINVAL, PA_ENOMEM, PA_EHIP, PA_EUNSUPPORTED = 0, 1, 2, 3, 4
 ORDER_GREEDY, ORDER_EXHAUSTIVE, ORDER_LEARNED, ORDER_GIVEN = 0, 1, 2, 3
+OPKIND_BITS, OPKIND_STREAM_K, OPKIND_STREAM_W, OPKIND_GEMM, OPKIND_FILL, OPKIND_PLOT = 0, 1, 2, 10, 20, 30
 PLOT_FP32_ESCALATE, PLOT_FP64 = 0, 1
 MAX_DIMS, MAX_RELATIONS = 12, 32
 
@@ -102,6 +103,9 @@ def load(path: str = LIB_PATH):
     L.pa_solve_system.argtypes = [ctypes.POINTER(System), i32p, ctypes.c_int32, ctypes.POINTER(Opts),
                                   ctypes.POINTER(BitArray), ctypes.POINTER(Report), vp]
     L.pa_popcount.argtypes = [ctypes.POINTER(BitArray), ctypes.POINTER(ctypes.c_int64), vp]
+    L.pa_plan_op_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32),
+                                   ctypes.POINTER(ctypes.c_double), ctypes.c_int32]
+    L.pa_plan_op_times.restype = ctypes.c_int32
     _lib = L
     return L
 
@@ -288,6 +292,18 @@ class Plan:
         _check(L.pa_plan_execute(self.handle, ctypes.byref(ba), ctypes.byref(rep) if report else None,
                                  _stream_ptr(stream)))
         return out, (rep.as_dict() if report else None), (list(rep.merges[:2 * 31]) if report else None)
+
+    def op_times(self):
+        """[(kind, ms, macs)] of the last execute (plan created with timing=2)."""
+        L = load()
+        cap = 256
+        ms = (ctypes.c_double * cap)()
+        kd = (ctypes.c_int32 * cap)()
+        mc = (ctypes.c_double * cap)()
+        n = L.pa_plan_op_times(self.handle, ms, kd, mc, cap)
+        if n < 0:
+            _check(PA_EINVAL)
+        return [(int(kd[i]), float(ms[i]), float(mc[i])) for i in range(min(n, cap))]
 
     def __del__(self):
         try:

@@ -14,9 +14,20 @@ def _oracle_plots(s):
     return [oracle.plot(r, s.axes)[0] for r in s.relations]
 
 
-def _solve(s, **kw):
+def _solve(s, max_workspace=None, **kw):
     note("solve", s.name, kw)
-    out, dims, rep = pa.solve_system(s, **kw)
+    import os
+    old = os.environ.get("PA_MAX_WORKSPACE_BYTES")
+    if max_workspace is not None:
+        os.environ["PA_MAX_WORKSPACE_BYTES"] = str(max_workspace)
+    try:
+        out, dims, rep = pa.solve_system(s, **kw)
+    finally:
+        if max_workspace is not None:
+            if old is None:
+                os.environ.pop("PA_MAX_WORKSPACE_BYTES")
+            else:
+                os.environ["PA_MAX_WORKSPACE_BYTES"] = old
     return to_host(out, dims), rep
 
 
@@ -49,9 +60,31 @@ def test_random_hypergraphs_all_policies(seed):
         got, rep = _solve(s, order=order)
         assert np.array_equal(got, ref), order
         outs.append(got)
-    # a deliberately poor given order (left to right) gives the same bits
+    # a deliberately poor given order (left to right) gives the same bits,
+    # or is refused with PA_ENOMEM when its intermediates cannot fit
     n = len(s.relations)
     merges = [0, 1] + [x for t in range(1, n - 1) for x in (n + t - 1, t + 1)]
+    need = pa.describe_plan(s, order=pa.ORDER_GIVEN, given=merges)["workspace_bytes"]
+    if need < 2 ** 30:
+        got, _ = _solve(s, order=pa.ORDER_GIVEN, given=merges)
+        assert np.array_equal(got, ref)
+    else:
+        with pytest.raises(pa.PaError) as e:
+            _solve(s, order=pa.ORDER_GIVEN, given=merges, max_workspace=2 ** 30)
+        assert e.value.code == pa.PA_ENOMEM
+
+
+def test_huge_intermediate_with_grid_stride():
+    """A Kronecker-heavy order whose intermediate has more than 2^32 bits:
+    every contraction kernel loops over its output (grid-stride), so the
+    result stays exact."""
+    s = _random_small_system(4200)
+    n = len(s.relations)
+    merges = [0, 1] + [x for t in range(1, n - 1) for x in (n + t - 1, t + 1)]
+    need = pa.describe_plan(s, order=pa.ORDER_GIVEN, given=merges)["workspace_bytes"]
+    assert 2 ** 32 / 8 < need < 16 * 2 ** 30
+    res = [a[2] for a in s.axes]
+    ref = oracle.solve(res, [r.vars for r in s.relations], _oracle_plots(s), s.exposed)
     got, _ = _solve(s, order=pa.ORDER_GIVEN, given=merges)
     assert np.array_equal(got, ref)
 
