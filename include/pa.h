@@ -128,8 +128,20 @@ typedef struct {
                                  FP32/FP64 sign disagreements (slow; diagnostics)  */
     int32_t timing;           /* 1: time plot and contraction phases with events;
                                  2: also time every op (see pa_plan_op_times)       */
-    int32_t plain;            /* 1: the plain GPU path (one launch per step, default
-                                 tiles, no fused plotting of all relations)         */
+    int32_t plain;            /* 1: the plain GPU path: one kernel launch per relation
+                                 plot and per contraction step, default tiles      */
+    int32_t per_op;           /* 1: one launch per step like the plain path, but
+                                 with all plots in one launch and split K         */
+    int32_t graph;            /* 1: capture the executor's launches in a hipGraph on
+                                 the first execute on a non-NULL stream with a
+                                 given output buffer, and replay it afterwards     */
+    int32_t single_launch;    /* 1: run the whole plan as ONE persistent launch whose
+                                 tiles wait on per-step dependency counters; 0
+                                 (default): one grouped launch per level of the
+                                 cluster tree and step kind, across all steps      */
+    int32_t persist_wg;       /* persistent workgroups (0: autotuned default)        */
+    int32_t plot_strip;       /* cells walked per plot thread (0: default)           */
+    int32_t contract_units;   /* output bits per streaming tile (0: default)         */
     const pa_model *model;    /* PA_ORDER_LEARNED: the cost model                   */
     void *workspace;          /* optional device workspace (NULL: library-owned)    */
     size_t workspace_bytes;
@@ -199,13 +211,39 @@ void pa_plan_destroy(pa_plan *plan);
 
 /* Per-op kernel durations of the last pa_plan_execute of a plan created with
  * opts->timing == 2, measured with HIP events recorded on the execution
- * stream around each op.  Fills up to cap entries: ms[i] (milliseconds),
+ * stream around each op (the persistent executor is one op of kind
+ * PA_OPKIND_PERSIST whose macs are the plan's total).  Fills up to cap entries: ms[i] (milliseconds),
  * kind[i] (PA_OPKIND_*) and macs[i] (product of the op's link resolutions,
  * eqn naive_cost; 0 for plots and fills).  Waits for the events.  Returns
  * the number of ops, or -1 if the plan does not record op timings. */
 enum { PA_OPKIND_BITS = 0, PA_OPKIND_STREAM_K = 1, PA_OPKIND_STREAM_W = 2, PA_OPKIND_GEMM = 10,
-       PA_OPKIND_FILL = 20, PA_OPKIND_PLOT = 30 };
+       PA_OPKIND_FILL = 20, PA_OPKIND_PLOT = 30, PA_OPKIND_PERSIST = 40 };
 int32_t pa_plan_op_times(pa_plan *plan, double *ms, int32_t *kind, double *macs, int32_t cap);
+
+/* ---------------------------------------------------------- batches
+ * Many independent systems solved together: each is planned on its own, all
+ * share one workspace, and their steps are merged into one table sorted by
+ * tree level and kind, so every grouped launch (or the single persistent
+ * launch, opts->single_launch) works on tiles of many systems at once; with
+ * opts->graph the whole batch is one hipGraph replay.  exposed[i] /
+ * n_exposed[i] describe system i's outer pack.  opts->plain and opts->per_op
+ * are not accepted (EINVAL).  EINVAL/ENOMEM as for pa_plan_create, with the
+ * failing system's index in pa_last_error(). */
+typedef struct pa_batch pa_batch;
+int pa_batch_create(const pa_system *systems, int32_t n_sys, const int32_t *const *exposed,
+                    const int32_t *n_exposed, const pa_opts *opts, pa_batch **batch);
+/* outs[i]: system i's output (dims = its exposed resolutions).  report (the
+ * batch totals) and nnz (set bits per system) may be NULL; when either is
+ * given the call synchronizes the stream. */
+int pa_batch_execute(pa_batch *batch, pa_bitarray *outs, pa_report *report, int64_t *nnz, void *stream);
+size_t pa_batch_workspace_bytes(const pa_batch *batch);
+/* As pa_plan_op_times, for a batch created with opts->timing == 2: one entry
+ * per grouped launch (kind and summed macs of its steps). */
+int32_t pa_batch_op_times(pa_batch *batch, double *ms, int32_t *kind, double *macs, int32_t cap);
+void pa_batch_destroy(pa_batch *batch);
+/* pa_batch_create + pa_batch_execute + pa_batch_destroy (synchronizes). */
+int pa_solve_batch(const pa_system *systems, int32_t n_sys, const int32_t *const *exposed, const int32_t *n_exposed,
+                   const pa_opts *opts, pa_bitarray *outs, int64_t *nnz, void *stream);
 
 /* pa_plan_create + pa_plan_execute + pa_plan_destroy. */
 int pa_solve_system(const pa_system *sys, const int32_t *exposed, int32_t n_exposed, const pa_opts *opts,

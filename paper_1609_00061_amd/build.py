@@ -8,7 +8,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpa.so")
 
-SOURCES = ["pa_kernels.hip", "pa_host.cpp", "pa_planner.cpp", "pa_plan.cpp"]
+SOURCES = ["pa_kernels.hip", "pa_host.cpp", "pa_planner.cpp", "pa_plan.cpp", "pa_batch.cpp"]
 HEADERS = ["pa_internal.h", "pa_plan.h"]
 
 # -ffp-contract=off: no implicit FMA anywhere (the FP64 corner values are a

@@ -1,0 +1,237 @@
+// Batched solving: many independent systems, each planned on its own (cluster
+// tree, layouts), share one workspace and one merged step table.  Steps of
+// every system are sorted together by (tree level, kind, mode), so each
+// grouped launch -- or the single persistent launch -- runs tiles of many
+// systems at once, and the whole batch is one hipGraph replay.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "pa_plan.h"
+
+struct pa_batch {
+    std::vector<std::unique_ptr<pa_plan>> subs;
+    pa_plan master;                 // merged step table and executor state; owns the workspace
+    std::vector<size_t> sub_off;
+};
+
+namespace pa {
+
+#define HIP_TRY(expr)                                                                                   \
+    do {                                                                                                \
+        hipError_t _e = (expr);                                                                         \
+        if (_e != hipSuccess) return fail(PA_EHIP, std::string(#expr) + ": " + hipGetErrorString(_e)); \
+    } while (0)
+
+static int merge_steps(pa_batch *B) {
+    pa_plan &M = B->master;
+    struct Ref {
+        int level, kind, mode, sys, local;
+    };
+    std::vector<Ref> refs;
+    std::vector<int> first(B->subs.size());
+    for (size_t i = 0; i < B->subs.size(); ++i) {
+        first[i] = (int)refs.size();
+        const pa_plan &P = *B->subs[i];
+        for (size_t j = 0; j < P.steps_host.size(); ++j)
+            refs.push_back({P.step_level[j], P.steps_host[j].kind, P.steps_host[j].mode, (int)i, (int)j});
+    }
+    std::vector<int> order(refs.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+    auto key = [&](int i) { return std::make_tuple(refs[i].level, refs[i].kind, refs[i].mode); };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return key(a) < key(b); });
+    std::vector<int> pos(refs.size());
+    for (size_t i = 0; i < order.size(); ++i) pos[order[i]] = (int)i;
+    M.steps_host.clear();
+    M.step_level.clear();
+    M.step_macs.clear();
+    int64_t tbase = 0;
+    for (int g : order) {
+        const Ref &r = refs[g];
+        const pa_plan &P = *B->subs[r.sys];
+        PStep s = P.steps_host[r.local];
+        for (int j = 0; j < s.ndep; ++j) s.dep[j] = pos[first[r.sys] + s.dep[j]];
+        s.tile_base = tbase;
+        tbase += s.n_tiles;
+        M.steps_host.push_back(s);
+        M.step_level.push_back(r.level);
+        M.step_macs.push_back(P.step_macs[r.local]);
+    }
+    M.step_out_refs.clear();
+    for (size_t i = 0; i < B->subs.size(); ++i)
+        for (const auto &ref : B->subs[i]->step_out_refs) M.step_out_refs.push_back({pos[first[i] + ref.first], (int)i});
+    M.n_items = tbase;
+    make_groups(&M);
+    return PA_OK;
+}
+
+}  // namespace pa
+
+using namespace pa;
+
+extern "C" int pa_batch_create(const pa_system *systems, int32_t n_sys, const int32_t *const *exposed,
+                               const int32_t *n_exposed, const pa_opts *opts, pa_batch **out) {
+    if (!out) return fail(PA_EINVAL, "batch_create: null batch pointer");
+    *out = nullptr;
+    if (!systems || n_sys < 1 || !exposed || !n_exposed) return fail(PA_EINVAL, "batch_create: bad arguments");
+    pa_opts o{};
+    if (opts) o = *opts;
+    if (o.plain || o.per_op) return fail(PA_EINVAL, "batch_create: batches run on the step executors (no plain/per_op)");
+    if (o.timing == 2) o.timing = 0;       // op events live on the merged plan, below
+    std::unique_ptr<pa_batch> B(new pa_batch());
+    size_t off = 0;
+    for (int32_t i = 0; i < n_sys; ++i) {
+        std::unique_ptr<pa_plan> P(new pa_plan());
+        int rc = build_plan(&systems[i], exposed[i], n_exposed[i], &o, P.get());
+        if (rc) {
+            g_err = "system " + std::to_string(i) + ": " + g_err;
+            return rc;
+        }
+        B->sub_off.push_back(off);
+        off += (P->ws_bytes + 255) / 256 * 256;
+        B->subs.push_back(std::move(P));
+    }
+    pa_plan &M = B->master;
+    M.per_op = 0;
+    M.graph = o.graph;
+    M.single_launch = o.single_launch;
+    M.persist_wg = o.persist_wg;
+    M.timing = o.timing;
+    size_t nsteps = 0;
+    for (auto &P : B->subs) nsteps += P->plots.size() + P->ops.size();
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off += (bytes + 255) / 256 * 256;
+        return at;
+    };
+    M.steps_off = take(sizeof(PStep) * std::max<size_t>(1, nsteps));
+    M.done_off = take(sizeof(unsigned) * std::max<size_t>(1, nsteps));
+    M.state_off = take(sizeof(PersistState));
+    M.counters_off = take(sizeof(PlotCounters));
+    M.popcnt_off = take(sizeof(unsigned long long) * (size_t)n_sys);
+    M.ws_bytes = off;
+    int rc;
+    if (o.workspace) {
+        if (o.workspace_bytes < M.ws_bytes)
+            return fail(PA_ENOMEM, "workspace too small: need " + std::to_string(M.ws_bytes) + " bytes");
+        M.ws.ptr = o.workspace;
+        M.ws.cap = o.workspace_bytes;
+        M.ws.external = true;
+    } else {
+        size_t cap = 0;
+        rc = plan_workspace_cap(&cap);
+        if (rc) return rc;
+        if (M.ws_bytes > cap)
+            return fail(PA_ENOMEM, "batch needs " + std::to_string(M.ws_bytes) + " bytes of workspace, " +
+                                       std::to_string(cap) + " available");
+        rc = M.ws.ensure(std::max<size_t>(M.ws_bytes, 256));
+        if (rc) return rc;
+    }
+    char *base = static_cast<char *>(M.ws.ptr);
+    M.total_macs = 0.0;
+    M.corners = 0;
+    for (size_t i = 0; i < B->subs.size(); ++i) {
+        pa_plan &P = *B->subs[i];
+        P.ws.ptr = base + B->sub_off[i];
+        P.ws.cap = P.ws_bytes;
+        P.ws.external = true;
+        rc = upload_plan(&P);
+        if (rc) return rc;
+        M.total_macs += P.total_macs;
+        M.corners += P.corners;
+    }
+    rc = merge_steps(B.get());
+    if (rc) return rc;
+    if (opts && opts->timing == 2) {
+        M.op_events.resize(M.single_launch ? 2 : std::max<size_t>(2, 2 * M.groups.size()));
+        for (auto &e : M.op_events) HIP_TRY(hipEventCreate(&e));
+    }
+    *out = B.release();
+    return PA_OK;
+}
+
+extern "C" int pa_batch_execute(pa_batch *B, pa_bitarray *outs, pa_report *rep, int64_t *nnz, void *stream) {
+    if (!B || !outs) return fail(PA_EINVAL, "batch_execute: null argument");
+    const size_t n = B->subs.size();
+    std::vector<void *> o(n);
+    for (size_t i = 0; i < n; ++i) {
+        int rc = check_bitarray(&outs[i], B->subs[i]->out_layout.dims, "batch_execute: out");
+        if (rc) {
+            g_err = "system " + std::to_string(i) + ": " + g_err;
+            return rc;
+        }
+        o[i] = outs[i].data;
+    }
+    pa_plan &M = B->master;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int launches = 0;
+    M.timing_active = false;
+    int rc = exec_steps(&M, o, s, &launches);
+    if (rc) return rc;
+    if (rep || nnz) {
+        char *base = static_cast<char *>(M.ws.ptr);
+        auto *counts = reinterpret_cast<unsigned long long *>(base + M.popcnt_off);
+        HIP_TRY(launch_fill(reinterpret_cast<uint32_t *>(counts), 2 * (int64_t)n, 0u, s));
+        for (size_t i = 0; i < n; ++i)
+            HIP_TRY(launch_popcount(static_cast<const uint32_t *>(o[i]), B->subs[i]->out_layout.words, counts + i, s));
+        std::vector<unsigned long long> c(n);
+        PlotCounters cnt;
+        PersistState pst;
+        HIP_TRY(hipMemcpyAsync(c.data(), counts, n * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(&cnt, base + M.counters_off, sizeof(cnt), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(&pst, base + M.state_off, sizeof(pst), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (pst.abort) return fail(PA_EHIP, "persistent executor gave up a dependency wait");
+        int64_t total = 0;
+        for (size_t i = 0; i < n; ++i) {
+            if (nnz) nnz[i] = (int64_t)c[i];
+            total += (int64_t)c[i];
+        }
+        if (rep) {
+            std::memset(rep, 0, sizeof(*rep));
+            rep->corners = M.corners;
+            rep->corners_flagged = (int64_t)cnt.flagged;
+            rep->corners_disagree = (int64_t)cnt.disagree;
+            rep->corners_disagree_unflagged = (int64_t)cnt.disagree_unflagged;
+            rep->nnz_out = total;
+            rep->n_launches = launches;
+            int steps = 0;
+            double cost = 0.0;
+            for (auto &P : B->subs) {
+                cost += P->tree.cost;
+                for (const auto &op : P->ops)
+                    if (op.kind != OP_FILL && op.b != -1) ++steps;
+            }
+            rep->n_steps = steps;
+            rep->cost_macs = cost;
+        }
+    }
+    return PA_OK;
+}
+
+extern "C" size_t pa_batch_workspace_bytes(const pa_batch *B) { return B ? B->master.ws_bytes : 0; }
+
+extern "C" int32_t pa_batch_op_times(pa_batch *B, double *ms, int32_t *kind, double *macs, int32_t cap) {
+    if (!B) return fail(PA_EINVAL, "batch_op_times: null batch"), -1;
+    return pa_plan_op_times(&B->master, ms, kind, macs, cap);
+}
+
+extern "C" void pa_batch_destroy(pa_batch *B) { delete B; }
+
+extern "C" int pa_solve_batch(const pa_system *systems, int32_t n_sys, const int32_t *const *exposed,
+                              const int32_t *n_exposed, const pa_opts *opts, pa_bitarray *outs, int64_t *nnz,
+                              void *stream) {
+    pa_batch *B = nullptr;
+    int rc = pa_batch_create(systems, n_sys, exposed, n_exposed, opts, &B);
+    if (rc) return rc;
+    rc = pa_batch_execute(B, outs, nullptr, nnz, stream);
+    if (rc == PA_OK && hipStreamSynchronize(static_cast<hipStream_t>(stream)) != hipSuccess)
+        rc = fail(PA_EHIP, "sync failed");
+    pa_batch_destroy(B);
+    return rc;
+}

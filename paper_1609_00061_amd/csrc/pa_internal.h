@@ -11,27 +11,31 @@ constexpr int kMaxD = PA_MAX_DEGREE;
 constexpr int kMaxA = PA_MAX_ARITY;
 constexpr int kDense = (kMaxD + 1) * (kMaxD + 1) * (kMaxD + 1);
 constexpr int kMaxDim = PA_MAX_DIMS;
+constexpr int kLineFloats = kMaxD + 2;          // a_0..a_d, E per corner line
+constexpr int kMaxTileLines = 640;              // LDS line table capacity of one plot tile
 
 // One relation to plot.  The relation's declared variables x_0..x_{n-1} are
 // stored on storage axes in the order perm: storage axis s holds declared
 // variable perm[s]; the last storage axis is the bit-packed one.
+//
+// Plot tiles (one 256-thread workgroup each): tw words along the packed axis
+// x (ta cells of storage axis 0 when n == 3) x (tb strips of s cells along the
+// walk axis, storage axis n-2).  A thread walks its strip, so each corner
+// line of the strip is evaluated once; the tile's line coefficients are built
+// cooperatively in LDS.
 struct PlotRel {
-    int n, d;                 // arity, degree
+    int n, d, mode, audit;
     int perm[kMaxA];
-    int res[kMaxA];           // resolution per storage axis
-    int mode;                 // PA_PLOT_FP32_ESCALATE or PA_PLOT_FP64
-    int audit;
+    int res[kMaxA];            // resolution per storage axis
     int64_t row_words;
-    const double *coef;       // dense table c[e0 + (d+1)*(e1 + (d+1)*e2)], declared exponents
-    const double *ax[kMaxA];  // FP64 pixel boundaries per storage axis (res+1 entries)
-    const float *axf[kMaxA];  // RN-to-FP32 copies
-    double vmax;              // upper bound of |x| on the packed storage axis
+    const double *coef;        // dense table c[e0 + (d+1)*(e1 + (d+1)*e2)], declared exponents
+    const double *ax[kMaxA];   // FP64 pixel boundaries per storage axis (res+1 entries)
+    const float *axf[kMaxA];   // RN-to-FP32 copies
+    double vmax;               // upper bound of |x| on the packed storage axis
     uint32_t *out;
-    float *lines;             // FP32 line table: (d + 2) floats per corner line
-    int64_t n_rows;           // product of res over non-packed storage axes
-    int64_t n_lines;          // product of (res + 1) over non-packed storage axes
-    int64_t word_base;        // prefix over relations of n_rows * row_words
-    int64_t line_base;        // prefix over relations of n_lines
+    int tw, ta, tb, s;
+    int64_t tiles_w, tiles_walk, tiles_fixed, n_tiles;
+    int64_t tile_base;         // prefix over relations of n_tiles (multi-relation launches)
 };
 
 struct PlotCounters {
@@ -59,6 +63,10 @@ struct ContractArgs {
     int a_pk_k, b_pk_k;             // latent index that is A's / B's packed axis, or -1
     int64_t a_row_words, b_row_words;
     int64_t n_out_rows;             // product of out_dim except the last
+    // streaming modes: word offsets (A, B) of every latent entry except the
+    // packed latent axis (mode K), precomputed on the host
+    const int64_t *ktab;
+    int64_t nktab;
 };
 
 // Dense Boolean GEMM in canonical layout:
@@ -75,14 +83,43 @@ struct GemmArgs {
     int ksplit;               // >1: partial results OR-ed with atomics into zeroed C
 };
 
+enum ContractMode { kModeBits = 0, kModeStreamK = 1, kModeStreamW = 2 };
+
+// One step of the persistent executor: a plot, a GEMM, a contraction or a
+// fill, cut into tiles.  Steps are listed so that every step's producers come
+// earlier; a tile starts once all tiles of the step's producers are done.
+enum StepKind { kStepPlot = 0, kStepGemm = 1, kStepContract = 2, kStepFill = 3 };
+
+struct PStep {
+    int kind, mode;
+    int ndep, dep[3];
+    int64_t n_tiles, tile_base;
+    int64_t units, per_tile;        // contract: output bits/words; fill: words
+    PlotRel plot;
+    GemmArgs gemm;
+    ContractArgs ca;
+    uint32_t *fill_ptr;
+};
+
+struct PersistState {
+    unsigned long long queue;       // next work item
+    unsigned int abort;             // set when a dependency wait exceeds its bound
+    unsigned int pad;
+};
+
 // Kernel launchers (pa_kernels.hip).  All return hipError_t of the launch.
-hipError_t launch_plot(const PlotRel *d_rels, int nrel, int64_t total_lines, int64_t total_words,
-                       int mode_any_fp32, PlotCounters *d_counters, hipStream_t s, int *n_launches);
+hipError_t launch_plot(const PlotRel *d_rels, int nrel, int64_t total_tiles, PlotCounters *d_counters,
+                       hipStream_t s);
 hipError_t launch_contract(const ContractArgs &a, int mode, hipStream_t s);
 hipError_t launch_gemm(const GemmArgs &g, hipStream_t s);
 hipError_t launch_fill(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
 hipError_t launch_popcount(const uint32_t *p, int64_t n, unsigned long long *out, hipStream_t s);
-
-enum ContractMode { kModeBits = 0, kModeStreamK = 1, kModeStreamW = 2 };
+hipError_t launch_persist(const PStep *d_steps, int nsteps, int64_t n_items, PersistState *state,
+                          unsigned int *done, PlotCounters *counters, int n_workgroups, hipStream_t s);
+hipError_t launch_persist_reset(PersistState *state, unsigned int *done, int nsteps, PlotCounters *counters,
+                                hipStream_t s);
+hipError_t launch_group(int kind, int mode, const PStep *d_steps, int first, int count, int64_t t0, int64_t t1,
+                        PlotCounters *counters, hipStream_t s);
+int persist_default_workgroups();
 
 }  // namespace pa

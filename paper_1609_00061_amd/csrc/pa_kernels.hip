@@ -1,6 +1,7 @@
 // gfx950 kernels of the pixel array method: corner plotting with FP32
-// evaluation and FP64 escalation, bitwise OR-of-AND contractions, and a dense
-// Boolean contraction on int8 MFMA with int32 accumulation.
+// evaluation and FP64 escalation, bitwise OR-of-AND contractions, a dense
+// Boolean contraction on int8 MFMA with int32 accumulation, and a persistent
+// work-queue executor that runs all of them as tiles of one launch.
 //
 // Build flags (see build.py): -O3 --offload-arch=gfx950 -ffp-contract=off
 // (no implicit FMA: every fused multiply-add below is an explicit fma/fmaf).
@@ -19,16 +20,6 @@ static dim3 grid_for(int64_t total) {
     if (blocks > (1 << 20)) blocks = 1 << 20;
     if (blocks < 1) blocks = 1;
     return dim3((unsigned)blocks);
-}
-
-__device__ __forceinline__ int find_by_base(const PlotRel *rels, int nrel, int64_t idx, bool lines) {
-    int lo = 0, hi = nrel - 1;
-    while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        int64_t b = lines ? rels[mid].line_base : rels[mid].word_base;
-        if (b <= idx) lo = mid; else hi = mid - 1;
-    }
-    return lo;
 }
 
 // Canonical FP64 value of a relation at a point given in DECLARED variable
@@ -71,10 +62,10 @@ __device__ double canon_eval(const double *__restrict__ c, int n, int d, const d
 }
 
 // ------------------------------------------------------------ plot: lines
-// For every corner line (fixed corner indices on the non-packed storage axes)
-// of an FP32-mode relation: the univariate coefficients a_t of the relation
-// restricted to the line (in the packed variable), rounded to FP32, and the
-// FP32 error bound E of evaluating them by Horner at any corner of the line.
+// Coefficients of the relation restricted to one corner line (fixed corner
+// indices li[s] on the non-packed storage axes), as a polynomial in the
+// packed variable, rounded to FP32, and the FP32 error bound E of evaluating
+// them by Horner at any corner of the line.
 //
 // Bound.  Let v be a corner coordinate on the packed axis, v~ = RN32(v),
 // a~_t = RN32(a^_t) with a^_t the FP64 sum below, and p^ the FP32 Horner
@@ -89,22 +80,11 @@ __device__ double canon_eval(const double *__restrict__ c, int n, int d, const d
 // FP32 intermediates or of flushed denormals is below 2^-100 (1 + S) V^d.
 // A corner is escalated unless E < |p^| <= FLT_MAX; otherwise
 // |f_exact| > E - gamma S >= |f64 - f_exact|, so sign(p^) = sign(f64) != 0.
-__global__ void k_plot_lines(const PlotRel *__restrict__ rels, int nrel, int64_t total_lines) {
-  for (int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gid < total_lines;
-       gid += (int64_t)gridDim.x * blockDim.x) {
-    const PlotRel &R = rels[find_by_base(rels, nrel, gid, true)];
-    const int64_t L = gid - R.line_base;
-    if (L >= R.n_lines) continue;
+__device__ void line_coefs(const PlotRel &R, const int *li, float *dst) {
     const int n = R.n, d = R.d, D1 = d + 1;
     const int pk = R.perm[n - 1];                 // declared index of the packed variable
     double xd[kMaxA] = {0.0, 0.0, 0.0};
-    int64_t rem = L;
-    for (int s = n - 2; s >= 0; --s) {
-        const int64_t dim = R.res[s] + 1;
-        const int64_t i = rem % dim;
-        rem /= dim;
-        xd[R.perm[s]] = R.ax[s][i];
-    }
+    for (int s = 0; s < n - 1; ++s) xd[R.perm[s]] = R.ax[s][li[s]];
     double a[kMaxD + 1], sab[kMaxD + 1];
     for (int t = 0; t <= kMaxD; ++t) { a[t] = 0.0; sab[t] = 0.0; }
     const int e2max = (n > 2) ? d : 0;
@@ -133,319 +113,391 @@ __global__ void k_plot_lines(const PlotRel *__restrict__ rels, int nrel, int64_t
     const double E = (gam + 0x1p-40) * S * (1.0 + 0x1p-30) + 0x1p-100 * (1.0 + S) * Vp;
     float Ef = (float)E;
     if ((double)Ef < E) Ef = nextafterf(Ef, INFINITY);
-    float *dst = R.lines + L * (kMaxD + 2);
-    for (int t = 0; t <= d; ++t) dst[t] = (float)a[t];
-    dst[kMaxD + 1] = Ef;
-  }
+    for (int t = 0; t <= kMaxD; ++t) dst[t] = (t <= d) ? (float)a[t] : 0.0f;
+    dst[kLineFloats - 1] = Ef;
 }
 
-// ------------------------------------------------------------ plot: cells
-// One thread per output word: 32 cells along the packed axis at fixed cell
-// indices on the other axes.  The cell is set iff its 2^n corners include
-// f <= 0 and f >= 0 (closed cells; a NaN corner counts as neither).
-// A corner is evaluated by every thread whose cells touch it; only its owner
-// counts it (lower cell on every axis, or the last cell where there is none).
-__global__ void k_plot_cells(const PlotRel *__restrict__ rels, int nrel, int64_t total_words,
-                             PlotCounters *__restrict__ counters) {
-  unsigned long long nflag = 0, ndis = 0, ndis_unf = 0;
-  for (int64_t g0 = (int64_t)blockIdx.x * blockDim.x; g0 < total_words; g0 += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t gid = g0 + threadIdx.x;
-    if (gid < total_words) {
-        const PlotRel &R = rels[find_by_base(rels, nrel, gid, false)];
-        const int64_t local = gid - R.word_base;
-        const int64_t row = local / R.row_words;
-        const int64_t w = local % R.row_words;
-        const int n = R.n, d = R.d;
-        const int rp = R.res[n - 1];
-        uint32_t word = 0;
-        if (w * 32 < rp) {
-            int cidx[kMaxA] = {0, 0, 0};
-            int64_t rem = row;
-            for (int s = n - 2; s >= 0; --s) { cidx[s] = (int)(rem % R.res[s]); rem /= R.res[s]; }
-            const int k0 = (int)(w * 32);
-            const int kmax = min(32, rp - k0);         // cells in this word
-            uint64_t cl = 0, cg = 0;
-            const int nlines = 1 << (n - 1);
-            for (int dl = 0; dl < nlines; ++dl) {
-                int li[kMaxA] = {0, 0, 0};
-                int64_t L = 0;
-                for (int s = 0; s < n - 1; ++s) {
-                    li[s] = cidx[s] + ((dl >> s) & 1);
-                    L = L * (R.res[s] + 1) + li[s];
-                }
-                double xdec[kMaxA] = {0.0, 0.0, 0.0};
-                bool line_owned = true;
-                for (int s = 0; s < n - 1; ++s) {
-                    xdec[R.perm[s]] = R.ax[s][li[s]];
-                    line_owned &= (((dl >> s) & 1) == 0) || (li[s] == R.res[s]);
-                }
-                const int pk = R.perm[n - 1];
-                uint64_t LE = 0, GE = 0;
-                if (R.mode == PA_PLOT_FP32_ESCALATE) {
-                    const float *ln = R.lines + L * (kMaxD + 2);
-                    float ca[kMaxD + 1];
-                    for (int t = 0; t <= kMaxD; ++t) ca[t] = (t <= d) ? ln[t] : 0.0f;
-                    const float E = ln[kMaxD + 1];
-                    for (int kk = 0; kk <= kmax; ++kk) {
-                        const float x = R.axf[n - 1][k0 + kk];
-                        float f = ca[d];
-                        for (int t = d - 1; t >= 0; --t) f = fmaf(f, x, ca[t]);
-                        const float af = fabsf(f);
-                        const bool ok = (af > E) && (af <= FLT_MAX);
-                        const bool own = line_owned && (kk < kmax || k0 + kk == rp);
-                        bool le, ge;
-                        if (ok && !R.audit) {
-                            le = f < 0.0f;
-                            ge = f > 0.0f;
-                        } else {
-                            xdec[pk] = R.ax[n - 1][k0 + kk];
-                            const double f64 = canon_eval(R.coef, n, d, xdec);
-                            le = f64 <= 0.0;
-                            ge = f64 >= 0.0;
-                            if (R.audit) {
-                                const int s32 = (f > 0.0f) - (f < 0.0f);
-                                const int s64 = (f64 > 0.0) - (f64 < 0.0);
-                                const bool dis = (s32 != s64) || (f != f) || (f64 != f64);
-                                ndis += dis && own;
-                                if (ok) ndis_unf += dis && own;
-                                if (ok) { le = f < 0.0f; ge = f > 0.0f; }
-                            }
-                        }
-                        nflag += (!ok) && own;
-                        LE |= (uint64_t)le << kk;
-                        GE |= (uint64_t)ge << kk;
-                    }
-                } else {
-                    for (int kk = 0; kk <= kmax; ++kk) {
-                        xdec[pk] = R.ax[n - 1][k0 + kk];
-                        const double f64 = canon_eval(R.coef, n, d, xdec);
-                        LE |= (uint64_t)(f64 <= 0.0) << kk;
-                        GE |= (uint64_t)(f64 >= 0.0) << kk;
-                    }
-                }
-                cl |= LE | (LE >> 1);
-                cg |= GE | (GE >> 1);
+struct PlotCount {
+    unsigned long long flagged = 0, dis = 0, dis_unf = 0;
+};
+
+// FP32 pass over the corners k0..k0+kmax of one corner line (coordinates in
+// registers): LE/GE bits where the FP32 sign is certain, and a mask FL of the
+// corners that must be decided in FP64.  Coefficients above the degree are
+// zero, and fma(0, x, a) = a exactly, so a fixed 4-step Horner gives the same
+// value as a degree-d Horner.
+__device__ __forceinline__ void line_fp32(const float *ln, const float *xv, int kmax, uint64_t &LE, uint64_t &GE,
+                                          uint64_t &FL) {
+    float ca[kMaxD + 1];
+#pragma unroll
+    for (int t = 0; t <= kMaxD; ++t) ca[t] = ln[t];
+    const float E = ln[kLineFloats - 1];
+    LE = 0;
+    GE = 0;
+    FL = 0;
+#pragma unroll
+    for (int kk = 0; kk < 33; ++kk) {
+        const float x = xv[kk];
+        float f = ca[kMaxD];
+#pragma unroll
+        for (int t = kMaxD - 1; t >= 0; --t) f = fmaf(f, x, ca[t]);
+        const float af = fabsf(f);
+        const bool ok = (af > E) && (af <= FLT_MAX);
+        const bool valid = kk <= kmax;
+        LE |= (uint64_t)(valid && ok && f < 0.0f) << kk;
+        GE |= (uint64_t)(valid && ok && f > 0.0f) << kk;
+        FL |= (uint64_t)(valid && !ok) << kk;
+    }
+}
+
+// LE/GE bits of the corners k0..k0+kmax of one corner line; `own` says
+// whether this thread counts the line's corners (each corner is counted once).
+__device__ __forceinline__ void eval_line(const PlotRel &R, const float *ln, const float *xv, const int *li, int k0,
+                                          int kmax, bool own, uint64_t &LE, uint64_t &GE, PlotCount &cnt) {
+    const int n = R.n, d = R.d;
+    const int pk = R.perm[n - 1];
+    const int rp = R.res[n - 1];
+    const uint64_t valid = (kmax >= 63) ? ~0ull : ((2ull << kmax) - 1ull);
+    const uint64_t owned = own ? (((1ull << kmax) - 1ull) | ((k0 + kmax == rp) ? (1ull << kmax) : 0ull)) : 0ull;
+    double xdec[kMaxA] = {0.0, 0.0, 0.0};
+    for (int s = 0; s < n - 1; ++s) xdec[R.perm[s]] = R.ax[s][li[s]];
+    const double *axp = R.ax[n - 1] + k0;
+    if (R.mode == PA_PLOT_FP32_ESCALATE) {
+        uint64_t FL;
+        line_fp32(ln, xv, kmax, LE, GE, FL);
+        cnt.flagged += __popcll(FL & owned);
+        // FP64 decides the escalated corners; in audit mode every corner's
+        // FP32 sign is also compared with its FP64 sign
+        uint64_t todo = R.audit ? valid : FL;
+        const float *xsf = R.axf[n - 1] + k0;
+        while (todo) {
+            const int kk = __ffsll((long long)todo) - 1;
+            todo &= todo - 1;
+            xdec[pk] = axp[kk];
+            const double f64 = canon_eval(R.coef, n, d, xdec);
+            const uint64_t bit = 1ull << kk;
+            const bool flagged = (FL & bit) != 0;
+            if (flagged) {
+                LE |= (uint64_t)(f64 <= 0.0) << kk;
+                GE |= (uint64_t)(f64 >= 0.0) << kk;
             }
-            const uint32_t valid = (kmax == 32) ? 0xFFFFFFFFu : ((1u << kmax) - 1u);
-            word = (uint32_t)(cl & cg) & valid;
+            if (R.audit) {
+                // FP32 value of this corner, recomputed as in line_fp32
+                const float x = xsf[kk];
+                float f = ln[kMaxD];
+                for (int t = kMaxD - 1; t >= 0; --t) f = fmaf(f, x, ln[t]);
+                const int s32 = (f > 0.0f) - (f < 0.0f);
+                const int s64 = (f64 > 0.0) - (f64 < 0.0);
+                const bool dis = ((s32 != s64) || (f != f) || (f64 != f64)) && (owned & bit);
+                cnt.dis += dis;
+                cnt.dis_unf += dis && !flagged;
+            }
         }
-        R.out[local] = word;
-    }
-  }
-    // counters: one atomic per wave, only when something was counted
-    const unsigned long long any = __ballot(nflag != 0 || ndis != 0 || ndis_unf != 0);
-    if (any && counters) {
-        if (nflag) atomicAdd(&counters->flagged, nflag);
-        if (ndis) atomicAdd(&counters->disagree, ndis);
-        if (ndis_unf) atomicAdd(&counters->disagree_unflagged, ndis_unf);
+    } else {
+        LE = 0;
+        GE = 0;
+        for (int kk = 0; kk <= kmax; ++kk) {
+            xdec[pk] = axp[kk];
+            const double f64 = canon_eval(R.coef, n, d, xdec);
+            LE |= (uint64_t)(f64 <= 0.0) << kk;
+            GE |= (uint64_t)(f64 >= 0.0) << kk;
+        }
     }
 }
 
-hipError_t launch_plot(const PlotRel *d_rels, int nrel, int64_t total_lines, int64_t total_words,
-                       int mode_any_fp32, PlotCounters *d_counters, hipStream_t s, int *n_launches) {
-    if (mode_any_fp32 && total_lines > 0) {
-        hipLaunchKernelGGL(k_plot_lines, grid_for(total_lines), dim3(256), 0, s, d_rels, nrel, total_lines);
-        if (n_launches) ++*n_launches;
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
+// One plot tile (256 threads).  Cell (.., c, j) on the walk axis is set iff
+// its 2^n corners include f <= 0 and f >= 0 (closed cells; a NaN corner
+// counts as neither): with le(L) = LE | LE >> 1 per corner line L, the cell
+// word of walk cell c is (le(c) | le(c+1)) & (ge(c) | ge(c+1)), each term ORed
+// over the pair of lines on the fixed axis when n == 3.
+__device__ void plot_tile(const PlotRel &R, int64_t tile, float *lines, PlotCount &cnt) {
+    const int n = R.n;
+    const int tid = threadIdx.x;
+    int64_t t = tile;
+    const int64_t t_w = t % R.tiles_w;
+    t /= R.tiles_w;
+    const int64_t t_walk = t % R.tiles_walk;
+    const int64_t t_fixed = t / R.tiles_walk;
+    const int wax = n - 2;                          // walk axis (-1 when n == 1)
+    const int rwalk = (n >= 2) ? R.res[wax] : 1;
+    const int span = R.tb * R.s;
+    const int64_t b0 = t_walk * span;
+    const int64_t a0 = t_fixed * R.ta;
+    const int nwl = (n >= 2) ? span + 1 : 1;
+    const int nfl = (n == 3) ? R.ta + 1 : 1;
+    if (R.mode == PA_PLOT_FP32_ESCALATE) {
+        for (int l = tid; l < nwl * nfl; l += blockDim.x) {
+            const int lf = l / nwl, lw = l % nwl;
+            int li[kMaxA] = {0, 0, 0};
+            bool valid = true;
+            if (n >= 2) {
+                li[wax] = (int)(b0 + lw);
+                valid &= li[wax] <= rwalk;
+            }
+            if (n == 3) {
+                li[0] = (int)(a0 + lf);
+                valid &= li[0] <= R.res[0];
+            }
+            if (valid) line_coefs(R, li, lines + l * kLineFloats);
+        }
     }
-    if (total_words > 0) {
-        hipLaunchKernelGGL(k_plot_cells, grid_for(total_words), dim3(256), 0, s, d_rels, nrel, total_words,
-                           d_counters);
-        if (n_launches) ++*n_launches;
+    __syncthreads();
+    const int tw = tid % R.tw, slot = tid / R.tw;
+    const int fa = (n == 3) ? slot % R.ta : 0;
+    const int strip = (n == 3) ? slot / R.ta : slot;
+    const int64_t w = t_w * R.tw + tw;
+    if (strip >= R.tb || (n == 1 && slot != 0) || w >= R.row_words) return;
+    const int64_t cs = b0 + (int64_t)strip * R.s;
+    if (n >= 2 && cs >= rwalk) return;
+    const int64_t ce = (n >= 2) ? min((int64_t)rwalk, cs + R.s) : 0;
+    const int64_t cf = a0 + fa;
+    if (n == 3 && cf >= R.res[0]) return;
+    const int rp = R.res[n - 1];
+    const bool pad = w * 32 >= rp;
+    const int k0 = (int)(w * 32);
+    const int kmax = pad ? 0 : min(32, rp - k0);
+    const uint32_t vmask = pad ? 0u : (kmax == 32 ? 0xffffffffu : ((1u << kmax) - 1u));
+    const int64_t row_base = (n == 3) ? cf * R.res[1] : 0;
+    // the 33 corner coordinates of this word, loaded once for all lines
+    float xv[33];
+    {
+        const float *xs = R.axf[n - 1] + k0;
+#pragma unroll
+        for (int kk = 0; kk < 33; ++kk) xv[kk] = (!pad && kk <= kmax) ? xs[kk] : 0.0f;
     }
+    uint32_t prevL = 0, prevG = 0;
+    for (int64_t c = cs; c <= ce; ++c) {
+        uint32_t lc = 0, gc = 0;
+        if (!pad) {
+            for (int df = 0; df < (n == 3 ? 2 : 1); ++df) {
+                int li[kMaxA] = {0, 0, 0};
+                bool own = true;
+                int lf = 0;
+                if (n >= 2) {
+                    li[wax] = (int)c;
+                    own &= (c > cs) || (cs == 0);
+                }
+                if (n == 3) {
+                    li[0] = (int)(cf + df);
+                    lf = fa + df;
+                    own &= (df == 0) || (li[0] == R.res[0]);
+                }
+                const float *ln = lines + (lf * nwl + (int)(c - b0)) * kLineFloats;
+                uint64_t LE, GE;
+                eval_line(R, ln, xv, li, k0, kmax, own, LE, GE, cnt);
+                lc |= (uint32_t)((LE | (LE >> 1)) & 0xffffffffull);
+                gc |= (uint32_t)((GE | (GE >> 1)) & 0xffffffffull);
+            }
+        }
+        if (n == 1) {
+            R.out[w] = lc & gc & vmask;
+            break;
+        }
+        if (c > cs) R.out[(row_base + c - 1) * R.row_words + w] = (prevL | lc) & (prevG | gc) & vmask;
+        prevL = lc;
+        prevG = gc;
+    }
+}
+
+__device__ __forceinline__ void flush_counts(const PlotCount &cnt, PlotCounters *counters) {
+    if (!counters) return;
+    if (cnt.flagged) atomicAdd(&counters->flagged, cnt.flagged);
+    if (cnt.dis) atomicAdd(&counters->disagree, cnt.dis);
+    if (cnt.dis_unf) atomicAdd(&counters->disagree_unflagged, cnt.dis_unf);
+}
+
+__device__ __forceinline__ int find_rel(const PlotRel *rels, int nrel, int64_t tile) {
+    int lo = 0, hi = nrel - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (rels[mid].tile_base <= tile) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(256) void k_plot(const PlotRel *__restrict__ rels, int nrel, int64_t total_tiles,
+                                              PlotCounters *__restrict__ counters) {
+    __shared__ float lines[kMaxTileLines * kLineFloats];
+    PlotCount cnt;
+    for (int64_t tile = blockIdx.x; tile < total_tiles; tile += gridDim.x) {
+        const PlotRel &R = rels[find_rel(rels, nrel, tile)];
+        plot_tile(R, tile - R.tile_base, lines, cnt);
+        __syncthreads();
+    }
+    flush_counts(cnt, counters);
+}
+
+hipError_t launch_plot(const PlotRel *d_rels, int nrel, int64_t total_tiles, PlotCounters *d_counters,
+                       hipStream_t s) {
+    if (total_tiles <= 0) return hipSuccess;
+    const int64_t blocks = total_tiles < (1 << 20) ? total_tiles : (1 << 20);
+    hipLaunchKernelGGL(k_plot, dim3((unsigned)blocks), dim3(256), 0, s, d_rels, nrel, total_tiles, d_counters);
     return hipGetLastError();
 }
 
 // --------------------------------------------------- bitwise contractions
-__device__ __forceinline__ void decode_out(const ContractArgs &a, int64_t row, int64_t bit, int64_t *c) {
-    if (a.nout > 0) c[a.nout - 1] = bit;
+// Word offsets in A and B of one output entry (all axes but the packed one,
+// plus the packed axis' bit index for each operand).
+struct OutPos {
+    int64_t baseA, baseB, pa, pb;
+};
+
+__device__ __forceinline__ OutPos out_pos(const ContractArgs &a, int64_t row, int64_t bit) {
+    OutPos p{0, 0, 0, 0};
+    if (a.nout > 0) {
+        const int last = a.nout - 1;
+        p.baseA = bit * a.a_str[last];
+        p.baseB = bit * a.b_str[last];
+        if (a.a_pk_out == last) p.pa = bit;
+        if (a.b_pk_out == last) p.pb = bit;
+    }
     int64_t rem = row;
-    for (int i = a.nout - 2; i >= 0; --i) { c[i] = rem % a.out_dim[i]; rem /= a.out_dim[i]; }
+    for (int i = a.nout - 2; i >= 0; --i) {
+        const int64_t ci = rem % a.out_dim[i];
+        rem /= a.out_dim[i];
+        p.baseA += ci * a.a_str[i];
+        p.baseB += ci * a.b_str[i];
+        if (a.a_pk_out == i) p.pa = ci;
+        if (a.b_pk_out == i) p.pb = ci;
+    }
+    return p;
 }
 
-// General mode: one thread per output bit; every latent entry visited bit by
-// bit (any layouts).
-__global__ void k_contract_bits(ContractArgs a, int64_t total) {
-  // grid-stride over whole blocks: every wave keeps 64 consecutive bits
-  for (int64_t g0 = (int64_t)blockIdx.x * blockDim.x; g0 < total; g0 += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t gid = g0 + threadIdx.x;
-    const int64_t rowbits = a.c_row_words * 32;
-    const int64_t row = gid / rowbits, bit = gid % rowbits;
-    bool valid;
-    if (a.nout == 0) valid = (gid == 0);
-    else valid = (row < a.n_out_rows) && (bit < a.out_dim[a.nout - 1]);
-    unsigned acc = 0;
-    if (valid) {
-        int64_t c[kMaxDim];
-        decode_out(a, row, bit, c);
-        int64_t baseA = 0, baseB = 0;
-        for (int i = 0; i < a.nout; ++i) { baseA += c[i] * a.a_str[i]; baseB += c[i] * a.b_str[i]; }
-        const int64_t pa_out = (a.a_pk_out >= 0) ? c[a.a_pk_out] : 0;
-        const int64_t pb_out = (a.b_pk_out >= 0) ? c[a.b_pk_out] : 0;
-        int64_t kidx[kMaxDim];
-        for (int j = 0; j < a.nk; ++j) kidx[j] = 0;
-        int64_t offA = 0, offB = 0;
-        for (;;) {
-            const int64_t pa = (a.a_pk_k >= 0) ? kidx[a.a_pk_k] : pa_out;
-            const int64_t pb = (a.b_pk_k >= 0) ? kidx[a.b_pk_k] : pb_out;
-            const unsigned ba = (a.A[baseA + offA + (pa >> 5)] >> (pa & 31)) & 1u;
-            const unsigned bb = a.B ? ((a.B[baseB + offB + (pb >> 5)] >> (pb & 31)) & 1u) : 1u;
-            if (ba & bb) { acc = 1; break; }
-            int j = a.nk - 1;
-            for (; j >= 0; --j) {
-                ++kidx[j];
-                offA += a.ka_str[j];
-                offB += a.kb_str[j];
-                if (kidx[j] < a.k_dim[j]) break;
-                offA -= a.ka_str[j] * a.k_dim[j];
-                offB -= a.kb_str[j] * a.k_dim[j];
-                kidx[j] = 0;
-            }
-            if (j < 0) break;
+// General mode: every latent entry visited bit by bit (any layouts).
+__device__ unsigned bits_unit(const ContractArgs &a, int64_t row, int64_t bit) {
+    const OutPos p = out_pos(a, row, bit);
+    int kidx[kMaxDim];
+    for (int j = 0; j < a.nk; ++j) kidx[j] = 0;
+    int64_t offA = 0, offB = 0;
+    for (;;) {
+        const int64_t pa = (a.a_pk_k >= 0) ? kidx[a.a_pk_k] : p.pa;
+        const int64_t pb = (a.b_pk_k >= 0) ? kidx[a.b_pk_k] : p.pb;
+        const unsigned ba = (a.A[p.baseA + offA + (pa >> 5)] >> (pa & 31)) & 1u;
+        const unsigned bb = a.B ? ((a.B[p.baseB + offB + (pb >> 5)] >> (pb & 31)) & 1u) : 1u;
+        if (ba & bb) return 1u;
+        int j = a.nk - 1;
+        for (; j >= 0; --j) {
+            ++kidx[j];
+            offA += a.ka_str[j];
+            offB += a.kb_str[j];
+            if (kidx[j] < a.k_dim[j]) break;
+            offA -= a.ka_str[j] * a.k_dim[j];
+            offB -= a.kb_str[j] * a.k_dim[j];
+            kidx[j] = 0;
         }
+        if (j < 0) return 0u;
     }
-    const unsigned long long bits = __ballot(acc != 0);
-    if ((threadIdx.x & 63) == 0 && gid < (a.nout == 0 ? 1 : a.n_out_rows * rowbits)) {
-        if (a.nout == 0) {
-            a.C[0] = (uint32_t)(bits & 1ull);
-        } else {
-            uint32_t *dst = a.C + row * a.c_row_words + bit / 32;
-            dst[0] = (uint32_t)bits;
-            dst[1] = (uint32_t)(bits >> 32);
-        }
-    }
-  }
 }
 
 // Stream mode K: A and B are both bit-packed along the same latent variable;
-// words are AND-ed along it (16 bytes at a time when rows allow).
+// whole rows of it are ANDed (16 bytes at a time when rows allow) for every
+// entry of the other latent variables (offsets from the host table).
 template <bool VEC4>
-__global__ void k_contract_stream_k(ContractArgs a, int64_t total) {
-  for (int64_t g0 = (int64_t)blockIdx.x * blockDim.x; g0 < total; g0 += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t gid = g0 + threadIdx.x;
-    const int64_t rowbits = a.c_row_words * 32;
-    const int64_t row = gid / rowbits, bit = gid % rowbits;
-    bool valid;
-    if (a.nout == 0) valid = (gid == 0);
-    else valid = (row < a.n_out_rows) && (bit < a.out_dim[a.nout - 1]);
+__device__ uint32_t streamk_unit(const ContractArgs &a, int64_t row, int64_t bit) {
+    const OutPos p = out_pos(a, row, bit);
+    const int64_t rw = a.a_row_words;
     uint32_t acc = 0;
-    if (valid) {
-        int64_t c[kMaxDim];
-        decode_out(a, row, bit, c);
-        int64_t baseA = 0, baseB = 0;
-        for (int i = 0; i < a.nout; ++i) { baseA += c[i] * a.a_str[i]; baseB += c[i] * a.b_str[i]; }
-        int64_t kidx[kMaxDim];
-        for (int j = 0; j < a.nk; ++j) kidx[j] = 0;
-        int64_t offA = 0, offB = 0;
-        const int kp = a.a_pk_k;
-        const int64_t rw = a.a_row_words;
-        for (;;) {
-            const uint32_t *pa = a.A + baseA + offA;
-            if (a.B) {
-                const uint32_t *pb = a.B + baseB + offB;
-                if (VEC4) {
-                    for (int64_t w = 0; w < rw; w += 4) {
-                        const uint4 x = *reinterpret_cast<const uint4 *>(pa + w);
-                        const uint4 y = *reinterpret_cast<const uint4 *>(pb + w);
-                        acc |= (x.x & y.x) | (x.y & y.y) | (x.z & y.z) | (x.w & y.w);
-                    }
-                } else {
-                    for (int64_t w = 0; w < rw; ++w) acc |= pa[w] & pb[w];
+    for (int64_t j = 0; j < a.nktab; ++j) {
+        const uint32_t *pa = a.A + p.baseA + a.ktab[2 * j];
+        if (a.B) {
+            const uint32_t *pb = a.B + p.baseB + a.ktab[2 * j + 1];
+            if (VEC4) {
+                for (int64_t w = 0; w < rw; w += 4) {
+                    const uint4 x = *reinterpret_cast<const uint4 *>(pa + w);
+                    const uint4 y = *reinterpret_cast<const uint4 *>(pb + w);
+                    acc |= (x.x & y.x) | (x.y & y.y) | (x.z & y.z) | (x.w & y.w);
                 }
             } else {
-                if (VEC4) {
-                    for (int64_t w = 0; w < rw; w += 4) {
-                        const uint4 x = *reinterpret_cast<const uint4 *>(pa + w);
-                        acc |= x.x | x.y | x.z | x.w;
-                    }
-                } else {
-                    for (int64_t w = 0; w < rw; ++w) acc |= pa[w];
-                }
+                for (int64_t w = 0; w < rw; ++w) acc |= pa[w] & pb[w];
             }
-            int j = a.nk - 1;
-            for (; j >= 0; --j) {
-                if (j == kp) continue;
-                ++kidx[j];
-                offA += a.ka_str[j];
-                offB += a.kb_str[j];
-                if (kidx[j] < a.k_dim[j]) break;
-                offA -= a.ka_str[j] * a.k_dim[j];
-                offB -= a.kb_str[j] * a.k_dim[j];
-                kidx[j] = 0;
-            }
-            if (j < 0) break;
-        }
-    }
-    const unsigned long long bits = __ballot(acc != 0);
-    if ((threadIdx.x & 63) == 0 && gid < (a.nout == 0 ? 1 : a.n_out_rows * rowbits)) {
-        if (a.nout == 0) {
-            a.C[0] = (uint32_t)(bits & 1ull);
         } else {
-            uint32_t *dst = a.C + row * a.c_row_words + bit / 32;
-            dst[0] = (uint32_t)bits;
-            dst[1] = (uint32_t)(bits >> 32);
+            if (VEC4) {
+                for (int64_t w = 0; w < rw; w += 4) {
+                    const uint4 x = *reinterpret_cast<const uint4 *>(pa + w);
+                    acc |= x.x | x.y | x.z | x.w;
+                }
+            } else {
+                for (int64_t w = 0; w < rw; ++w) acc |= pa[w];
+            }
         }
     }
-  }
+    return acc;
 }
 
 // Stream mode W: A, B and C share the packed variable (an output variable);
-// one thread per output word ORs the AND of whole words over the latent
-// entries.
-__global__ void k_contract_stream_w(ContractArgs a, int64_t total) {
-  for (int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gid < total;
-       gid += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t row = gid / a.c_row_words, wc = gid % a.c_row_words;
-    const int64_t last = a.out_dim[a.nout - 1];
+// whole words are ANDed and ORed over the latent entries (host table).
+__device__ uint32_t streamw_word(const ContractArgs &a, int64_t row, int64_t wc) {
+    if (wc * 32 >= a.out_dim[a.nout - 1]) return 0u;
+    const OutPos p = out_pos(a, row, 0);
     uint32_t acc = 0;
-    if (wc * 32 < last) {
-        int64_t c[kMaxDim];
-        decode_out(a, row, 0, c);
-        int64_t baseA = wc, baseB = wc;
-        for (int i = 0; i < a.nout - 1; ++i) { baseA += c[i] * a.a_str[i]; baseB += c[i] * a.b_str[i]; }
-        int64_t kidx[kMaxDim];
-        for (int j = 0; j < a.nk; ++j) kidx[j] = 0;
-        int64_t offA = 0, offB = 0;
-        for (;;) {
-            const uint32_t x = a.A[baseA + offA];
-            acc |= a.B ? (x & a.B[baseB + offB]) : x;
-            int j = a.nk - 1;
-            for (; j >= 0; --j) {
-                ++kidx[j];
-                offA += a.ka_str[j];
-                offB += a.kb_str[j];
-                if (kidx[j] < a.k_dim[j]) break;
-                offA -= a.ka_str[j] * a.k_dim[j];
-                offB -= a.kb_str[j] * a.k_dim[j];
-                kidx[j] = 0;
+    for (int64_t j = 0; j < a.nktab; ++j) {
+        const uint32_t x = a.A[p.baseA + wc + a.ktab[2 * j]];
+        acc |= a.B ? (x & a.B[p.baseB + wc + a.ktab[2 * j + 1]]) : x;
+    }
+    return acc;
+}
+
+// Units [u0, u1) of a contraction by one 256-thread block: output bits for
+// the bit-out modes (u0, u1 multiples of 64 or the end), words for mode W.
+template <int MODE>
+__device__ void contract_range(const ContractArgs &a, int64_t u0, int64_t u1) {
+    if (MODE == kModeStreamW) {
+        for (int64_t g = u0 + threadIdx.x; g < u1; g += blockDim.x) {
+            const int64_t row = g / a.c_row_words, wc = g % a.c_row_words;
+            a.C[row * a.c_row_words + wc] = streamw_word(a, row, wc);
+        }
+        return;
+    }
+    const int64_t rowbits = a.c_row_words * 32;
+    const int64_t total = (a.nout == 0) ? 64 : a.n_out_rows * rowbits;
+    const bool vec4 = (a.a_row_words % 4) == 0;
+    for (int64_t g0 = u0; g0 < u1; g0 += blockDim.x) {
+        const int64_t gid = g0 + threadIdx.x;
+        const int64_t row = gid / rowbits, bit = gid % rowbits;
+        bool valid;
+        if (a.nout == 0) valid = (gid == 0);
+        else valid = (gid < u1) && (row < a.n_out_rows) && (bit < a.out_dim[a.nout - 1]);
+        uint32_t acc = 0;
+        if (valid) {
+            if (MODE == kModeStreamK) acc = vec4 ? streamk_unit<true>(a, row, bit) : streamk_unit<false>(a, row, bit);
+            else acc = bits_unit(a, row, bit);
+        }
+        const unsigned long long bits = __ballot(acc != 0);
+        if ((threadIdx.x & 63) == 0 && gid < total && gid < u1) {
+            if (a.nout == 0) {
+                a.C[0] = (uint32_t)(bits & 1ull);
+            } else {
+                uint32_t *dst = a.C + row * a.c_row_words + bit / 32;
+                dst[0] = (uint32_t)bits;
+                dst[1] = (uint32_t)(bits >> 32);
             }
-            if (j < 0) break;
         }
     }
-    a.C[row * a.c_row_words + wc] = acc;
-  }
+}
+
+__device__ __forceinline__ void contract_range_any(const ContractArgs &a, int mode, int64_t u0, int64_t u1) {
+    if (mode == kModeStreamK) contract_range<kModeStreamK>(a, u0, u1);
+    else if (mode == kModeStreamW) contract_range<kModeStreamW>(a, u0, u1);
+    else contract_range<kModeBits>(a, u0, u1);
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void k_contract(ContractArgs a, int64_t total) {
+    for (int64_t g0 = (int64_t)blockIdx.x * blockDim.x; g0 < total; g0 += (int64_t)gridDim.x * blockDim.x)
+        contract_range<MODE>(a, g0, min(total, g0 + (int64_t)blockDim.x));
+}
+
+static int64_t contract_units(const ContractArgs &a, int mode) {
+    if (mode == kModeStreamW) return a.n_out_rows * a.c_row_words;
+    return (a.nout == 0) ? 64 : a.n_out_rows * a.c_row_words * 32;
 }
 
 hipError_t launch_contract(const ContractArgs &a, int mode, hipStream_t s) {
-    const int64_t rowbits = a.c_row_words * 32;
-    if (mode == kModeStreamW) {
-        const int64_t total = a.n_out_rows * a.c_row_words;
-        if (total == 0) return hipSuccess;
-        hipLaunchKernelGGL(k_contract_stream_w, grid_for(total), dim3(256), 0, s, a, total);
-        return hipGetLastError();
-    }
-    const int64_t total = (a.nout == 0) ? 64 : a.n_out_rows * rowbits;
+    const int64_t total = contract_units(a, mode);
     if (total == 0) return hipSuccess;
-    const dim3 grid = grid_for(total);
-    if (mode == kModeStreamK) {
-        if (a.a_row_words % 4 == 0)
-            hipLaunchKernelGGL(k_contract_stream_k<true>, grid, dim3(256), 0, s, a, total);
-        else
-            hipLaunchKernelGGL(k_contract_stream_k<false>, grid, dim3(256), 0, s, a, total);
-    } else {
-        hipLaunchKernelGGL(k_contract_bits, grid, dim3(256), 0, s, a, total);
-    }
+    if (mode == kModeStreamK) hipLaunchKernelGGL(k_contract<kModeStreamK>, grid_for(total), dim3(256), 0, s, a, total);
+    else if (mode == kModeStreamW) hipLaunchKernelGGL(k_contract<kModeStreamW>, grid_for(total), dim3(256), 0, s, a, total);
+    else hipLaunchKernelGGL(k_contract<kModeBits>, grid_for(total), dim3(256), 0, s, a, total);
     return hipGetLastError();
 }
 
@@ -456,6 +508,7 @@ typedef int v16i __attribute__((ext_vector_type(16)));
 constexpr int kTile = 128;     // 128 x 128 output tile per workgroup (4 waves of 64 x 64)
 constexpr int kChunk = 8;      // K words staged per iteration (256 Boolean k)
 constexpr int kPitch = 12;     // LDS row pitch in words: 16-byte reads of 8 rows hit distinct banks
+constexpr int kGemmLdsWords = 4 * kTile * kPitch;   // A and B, double-buffered
 
 __device__ __forceinline__ uint4 load_row4(const uint32_t *__restrict__ p, int64_t kw, int64_t kend, bool ok,
                                            bool vec4) {
@@ -483,17 +536,13 @@ __device__ __forceinline__ v4i spread(uint32_t x, const uint32_t *m) {
     return r;
 }
 
-__global__ __launch_bounds__(256) void k_gemm_mfma(GemmArgs g) {
-    __shared__ __attribute__((aligned(16))) uint32_t sA[2][kTile * kPitch];
-    __shared__ __attribute__((aligned(16))) uint32_t sB[2][kTile * kPitch];
+// One 128x128 output tile (batch b, tile row tm, tile column tn, K split ks)
+// of the canonical Boolean GEMM.  lds holds kGemmLdsWords words.
+__device__ void gemm_tile(const GemmArgs &g, int64_t b, int64_t tm, int64_t tn, int ks, uint32_t *lds) {
+    uint32_t *sA0 = lds, *sA1 = lds + kTile * kPitch, *sB0 = lds + 2 * kTile * kPitch, *sB1 = lds + 3 * kTile * kPitch;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
     const int h = lane >> 5, l32 = lane & 31;
-    int64_t t = blockIdx.x;
-    const int ks = (int)(t % g.ksplit);
-    t /= g.ksplit;
-    const int64_t tn = t % g.tiles_n, tm = t / g.tiles_n;
-    const int64_t b = blockIdx.y;
     const int64_t m0 = tm * kTile, n0 = tn * kTile;
     const int64_t Wc = g.rwc * 32;
     const int64_t kw0 = (int64_t)ks * g.kchunk;
@@ -519,10 +568,10 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(GemmArgs g) {
 
     int cur = 0;
     if (kw0 < kw1) {
-        uint4 ra = load_row4(aptr, kw0 + lw, kw1, a_ok, vec4);
-        uint4 rb = load_row4(bptr, kw0 + lw, kw1, b_ok, vec4);
-        *reinterpret_cast<uint4 *>(&sA[0][lrow * kPitch + lw]) = ra;
-        *reinterpret_cast<uint4 *>(&sB[0][lrow * kPitch + lw]) = rb;
+        const uint4 ra = load_row4(aptr, kw0 + lw, kw1, a_ok, vec4);
+        const uint4 rb = load_row4(bptr, kw0 + lw, kw1, b_ok, vec4);
+        *reinterpret_cast<uint4 *>(&sA0[lrow * kPitch + lw]) = ra;
+        *reinterpret_cast<uint4 *>(&sB0[lrow * kPitch + lw]) = rb;
     }
     __syncthreads();
     for (int64_t kc = kw0; kc < kw1; kc += kChunk) {
@@ -532,15 +581,17 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(GemmArgs g) {
             na = load_row4(aptr, kc + kChunk + lw, kw1, a_ok, vec4);
             nb = load_row4(bptr, kc + kChunk + lw, kw1, b_ok, vec4);
         }
+        const uint32_t *sA = cur ? sA1 : sA0;
+        const uint32_t *sB = cur ? sB1 : sB0;
 #pragma unroll
         for (int q4 = 0; q4 < kChunk; q4 += 4) {
             uint4 a4[2], b4[2];
 #pragma unroll
             for (int i = 0; i < 2; ++i)
-                a4[i] = *reinterpret_cast<const uint4 *>(&sA[cur][(wm * 64 + i * 32 + l32) * kPitch + q4]);
+                a4[i] = *reinterpret_cast<const uint4 *>(&sA[(wm * 64 + i * 32 + l32) * kPitch + q4]);
 #pragma unroll
             for (int j = 0; j < 2; ++j)
-                b4[j] = *reinterpret_cast<const uint4 *>(&sB[cur][(wn * 64 + j * 32 + l32) * kPitch + q4]);
+                b4[j] = *reinterpret_cast<const uint4 *>(&sB[(wn * 64 + j * 32 + l32) * kPitch + q4]);
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 v4i opa[2], opb[2];
@@ -564,8 +615,10 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(GemmArgs g) {
             }
         }
         if (more) {
-            *reinterpret_cast<uint4 *>(&sA[cur ^ 1][lrow * kPitch + lw]) = na;
-            *reinterpret_cast<uint4 *>(&sB[cur ^ 1][lrow * kPitch + lw]) = nb;
+            uint32_t *dA = cur ? sA0 : sA1;
+            uint32_t *dB = cur ? sB0 : sB1;
+            *reinterpret_cast<uint4 *>(&dA[lrow * kPitch + lw]) = na;
+            *reinterpret_cast<uint4 *>(&dB[lrow * kPitch + lw]) = nb;
         }
         __syncthreads();
         cur ^= 1;
@@ -598,23 +651,45 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(GemmArgs g) {
     }
 }
 
+__device__ __forceinline__ void gemm_decode(const GemmArgs &g, int64_t t, int64_t &b, int64_t &tm, int64_t &tn,
+                                            int &ks) {
+    ks = (int)(t % g.ksplit);
+    t /= g.ksplit;
+    tn = t % g.tiles_n;
+    t /= g.tiles_n;
+    tm = t % g.tiles_m;
+    b = t / g.tiles_m;
+}
+
+__global__ __launch_bounds__(256) void k_gemm_mfma(GemmArgs g) {
+    __shared__ __attribute__((aligned(16))) uint32_t lds[kGemmLdsWords];
+    const int64_t ntiles = g.nbatch * g.tiles_m * g.tiles_n * g.ksplit;
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        int64_t b, tm, tn;
+        int ks;
+        gemm_decode(g, t, b, tm, tn, ks);
+        gemm_tile(g, b, tm, tn, ks, lds);
+        __syncthreads();
+    }
+}
+
 hipError_t launch_gemm(const GemmArgs &g, hipStream_t s) {
     if (g.nbatch == 0 || g.M == 0 || g.No == 0) return hipSuccess;
-    const int64_t gx = g.tiles_m * g.tiles_n * g.ksplit;
-    if (gx > 0x7fffffff || g.nbatch > 65535) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_gemm_mfma, dim3((unsigned)gx, (unsigned)g.nbatch), dim3(256), 0, s, g);
+    const int64_t nt = g.nbatch * g.tiles_m * g.tiles_n * g.ksplit;
+    const int64_t blocks = nt < (1 << 20) ? nt : (1 << 20);
+    hipLaunchKernelGGL(k_gemm_mfma, dim3((unsigned)blocks), dim3(256), 0, s, g);
     return hipGetLastError();
 }
 
 // ------------------------------------------------------------ fill, count
 __global__ void k_fill(uint32_t *p, int64_t n, uint32_t v) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = v;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
 }
 
 hipError_t launch_fill(uint32_t *p, int64_t n, uint32_t v, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
+    hipLaunchKernelGGL(k_fill, grid_for(n), dim3(256), 0, s, p, n, v);
     return hipGetLastError();
 }
 
@@ -634,6 +709,195 @@ hipError_t launch_popcount(const uint32_t *p, int64_t n, unsigned long long *out
     int64_t blocks = (n + 255) / 256;
     if (blocks > 4096) blocks = 4096;
     hipLaunchKernelGGL(k_popcount, dim3((unsigned)blocks), dim3(256), 0, s, p, n, out);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------- grouped executors
+// Steps of one kind on one level of the cluster tree (possibly from many
+// systems), contiguous in the step table, run by one launch; tiles are
+// numbered by the steps' tile_base prefix.
+__device__ __forceinline__ int find_step(const PStep *steps, int first, int count, int64_t item) {
+    int lo = first, hi = first + count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (steps[mid].tile_base <= item) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ void run_tile(const PStep &st, int64_t tile, uint32_t *lds, PlotCount &cnt) {
+    switch (st.kind) {
+        case kStepPlot:
+            plot_tile(st.plot, tile, reinterpret_cast<float *>(lds), cnt);
+            break;
+        case kStepGemm: {
+            const GemmArgs g = st.gemm;
+            int64_t b, tm, tn;
+            int ks;
+            gemm_decode(g, tile, b, tm, tn, ks);
+            gemm_tile(g, b, tm, tn, ks, lds);
+            break;
+        }
+        case kStepContract: {
+            const int64_t u0 = tile * st.per_tile;
+            contract_range_any(st.ca, st.mode, u0, min(st.units, u0 + st.per_tile));
+            break;
+        }
+        default: {
+            const int64_t u0 = tile * st.per_tile, u1 = min(st.units, u0 + st.per_tile);
+            for (int64_t i = u0 + threadIdx.x; i < u1; i += blockDim.x) st.fill_ptr[i] = 0u;
+            break;
+        }
+    }
+}
+
+// KIND: a StepKind; for contractions the mode is fixed too (kind 2 + 10 * mode).
+template <int KIND>
+__global__ __launch_bounds__(256) void k_group(const PStep *__restrict__ steps, int first, int count, int64_t t0,
+                                               int64_t t1, PlotCounters *counters) {
+    constexpr int kind = KIND % 10, mode = KIND / 10;
+    constexpr int kWords = kind == kStepGemm ? kGemmLdsWords : (kind == kStepPlot ? kMaxTileLines * kLineFloats : 1);
+    __shared__ __attribute__((aligned(16))) uint32_t lds[kWords];
+    PlotCount cnt;
+    for (int64_t item = t0 + blockIdx.x; item < t1; item += gridDim.x) {
+        const PStep &st = steps[find_step(steps, first, count, item)];
+        if (kind == kStepPlot) {
+            plot_tile(st.plot, item - st.tile_base, reinterpret_cast<float *>(lds), cnt);
+        } else if (kind == kStepGemm) {
+            const GemmArgs g = st.gemm;
+            int64_t b, tm, tn;
+            int ks;
+            gemm_decode(g, item - st.tile_base, b, tm, tn, ks);
+            gemm_tile(g, b, tm, tn, ks, lds);
+        } else if (kind == kStepContract) {
+            const int64_t u0 = (item - st.tile_base) * st.per_tile;
+            contract_range<mode>(st.ca, u0, min(st.units, u0 + st.per_tile));
+        } else {
+            const int64_t u0 = (item - st.tile_base) * st.per_tile, u1 = min(st.units, u0 + st.per_tile);
+            for (int64_t i = u0 + threadIdx.x; i < u1; i += blockDim.x) st.fill_ptr[i] = 0u;
+        }
+        __syncthreads();
+    }
+    if (kind == kStepPlot) flush_counts(cnt, counters);
+}
+
+hipError_t launch_group(int kind, int mode, const PStep *d_steps, int first, int count, int64_t t0, int64_t t1,
+                        PlotCounters *counters, hipStream_t s) {
+    if (t1 <= t0) return hipSuccess;
+    const int64_t nt = t1 - t0;
+    const dim3 grid((unsigned)(nt < (1 << 20) ? nt : (1 << 20)));
+#define PA_GROUP(K) hipLaunchKernelGGL(k_group<K>, grid, dim3(256), 0, s, d_steps, first, count, t0, t1, counters)
+    switch (kind) {
+        case kStepPlot: PA_GROUP(kStepPlot); break;
+        case kStepGemm: PA_GROUP(kStepGemm); break;
+        case kStepContract:
+            if (mode == kModeStreamK) PA_GROUP(kStepContract + 10 * kModeStreamK);
+            else if (mode == kModeStreamW) PA_GROUP(kStepContract + 10 * kModeStreamW);
+            else PA_GROUP(kStepContract + 10 * kModeBits);
+            break;
+        default: PA_GROUP(kStepFill); break;
+    }
+#undef PA_GROUP
+    return hipGetLastError();
+}
+
+// ------------------------------------------------- persistent executor
+// Every workgroup takes work items (tiles) from a global counter, in step
+// order; a tile first waits until every tile of its step's producer steps has
+// finished (per-step done counters), then runs, then publishes.  Producers
+// always precede consumers in the item order and every taken item is being
+// run by a live workgroup, so the waits end; a bounded spin sets `abort`
+// and every workgroup leaves if a wait ever exceeds ~2^26 polls.
+// Coherence across XCDs: the publishing thread's agent-scope release (after
+// the workgroup barrier that orders the other waves' completed stores) writes
+// the XCD's L2 back; the waiting thread's agent-scope acquire, once, after the
+// relaxed polls succeed, invalidates the stale lines of its CU and XCD.
+constexpr long long kSpinLimit = 1ll << 26;
+
+__global__ __launch_bounds__(256) void k_persist(const PStep *__restrict__ steps, int nsteps, int64_t n_items,
+                                                 PersistState *state, unsigned int *done,
+                                                 PlotCounters *counters) {
+    __shared__ __attribute__((aligned(16))) uint32_t lds[kGemmLdsWords > kMaxTileLines * kLineFloats
+                                                             ? kGemmLdsWords
+                                                             : kMaxTileLines * kLineFloats];
+    __shared__ long long s_item;
+    __shared__ int s_ok;
+    PlotCount cnt;
+    for (;;) {
+        if (threadIdx.x == 0)
+            s_item = (long long)__hip_atomic_fetch_add(&state->queue, 1ull, __ATOMIC_RELAXED,
+                                                        __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        const int64_t item = s_item;
+        if (item >= n_items) break;
+        const int si = find_step(steps, 0, nsteps, item);
+        const int64_t tile = item - steps[si].tile_base;
+        if (threadIdx.x == 0) {
+            int ok = 1;
+            const int nd = steps[si].ndep;
+            for (int j = 0; j < nd && ok; ++j) {
+                const int d = steps[si].dep[j];
+                const unsigned need = (unsigned)steps[d].n_tiles;
+                long long spins = 0;
+                while (__hip_atomic_load(&done[d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+                    if (__hip_atomic_load(&state->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) { ok = 0; break; }
+                    if (++spins > kSpinLimit) {
+                        __hip_atomic_store(&state->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        ok = 0;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(2);
+                }
+            }
+            if (nd > 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            s_ok = ok;
+        }
+        __syncthreads();
+        if (!s_ok) break;
+        run_tile(steps[si], tile, lds, cnt);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __syncthreads();
+        if (threadIdx.x == 0) __hip_atomic_fetch_add(&done[si], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    flush_counts(cnt, counters);
+}
+
+__global__ void k_persist_reset(PersistState *state, unsigned int *done, int nsteps, PlotCounters *counters) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nsteps; i += gridDim.x * blockDim.x) done[i] = 0u;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        state->queue = 0ull;
+        state->abort = 0u;
+        if (counters) {
+            counters->flagged = 0ull;
+            counters->disagree = 0ull;
+            counters->disagree_unflagged = 0ull;
+        }
+    }
+}
+
+hipError_t launch_persist_reset(PersistState *state, unsigned int *done, int nsteps, PlotCounters *counters,
+                                hipStream_t s) {
+    hipLaunchKernelGGL(k_persist_reset, grid_for(nsteps > 0 ? nsteps : 1), dim3(256), 0, s, state, done, nsteps,
+                       counters);
+    return hipGetLastError();
+}
+
+// Default persistent grid: as many workgroups as fit on the device at once.
+int persist_default_workgroups() {
+    static int cached = 0;
+    if (cached) return cached;
+    int dev = 0, cus = 256, per_cu = 1;
+    if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persist, 256, 0) != hipSuccess || per_cu < 1) per_cu = 1;
+    cached = cus * per_cu;
+    return cached;
+}
+
+hipError_t launch_persist(const PStep *d_steps, int nsteps, int64_t n_items, PersistState *state,
+                          unsigned int *done, PlotCounters *counters, int n_workgroups, hipStream_t s) {
+    if (n_items <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_persist, dim3((unsigned)n_workgroups), dim3(256), 0, s, d_steps, nsteps, n_items, state,
+                       done, counters);
     return hipGetLastError();
 }
 

@@ -8,6 +8,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <tuple>
 #include <memory>
 #include <mutex>
 #include <sstream>
@@ -444,6 +445,35 @@ static void finish_contract(Op &op, bool has_b) {
     if (k_ok) op.mode = kModeStreamK;
     else if (w_ok) op.mode = kModeStreamW;
     else op.mode = kModeBits;
+    // latent-entry offset table for the streaming modes (mode K leaves out the
+    // shared packed latent axis, which the kernel walks word by word)
+    op.ktab.clear();
+    if (op.mode != kModeBits) {
+        int64_t n = 1;
+        for (int j = 0; j < a.nk; ++j)
+            if (!(op.mode == kModeStreamK && j == a.a_pk_k)) n *= a.k_dim[j];
+        if (n > ((int64_t)1 << 22)) {
+            op.mode = kModeBits;       // table too large: visit bit by bit
+        } else {
+            op.ktab.reserve(2 * n);
+            std::vector<int64_t> idx(a.nk, 0);
+            for (int64_t e = 0; e < n; ++e) {
+                int64_t oa = 0, ob = 0;
+                for (int j = 0; j < a.nk; ++j) {
+                    oa += idx[j] * a.ka_str[j];
+                    ob += idx[j] * a.kb_str[j];
+                }
+                op.ktab.push_back(oa);
+                op.ktab.push_back(ob);
+                for (int j = a.nk - 1; j >= 0; --j) {
+                    if (op.mode == kModeStreamK && j == a.a_pk_k) continue;
+                    if (++idx[j] < a.k_dim[j]) break;
+                    idx[j] = 0;
+                }
+            }
+        }
+    }
+    a.nktab = (int64_t)op.ktab.size() / 2;
 }
 
 static std::string join(const std::vector<int> &v) {
@@ -473,8 +503,42 @@ std::string Op::describe() const {
 }
 
 // --------------------------------------------------------------- planning
-static int build_plan(const pa_system *sys, const int32_t *exposed, int32_t n_exposed, const pa_opts *opts,
-                      pa_plan *P) {
+// Plot tiles: tw words along the packed axis; the rest of the 256 threads
+// spread over ta cells of the fixed axis (n == 3) x tb strips of s walk cells.
+static void plot_tiling(PlotRel &R, int strip) {
+    const int n = R.n;
+    R.tw = (int)std::min<int64_t>(32, R.row_words);
+    const int ts = 256 / R.tw;
+    R.s = std::max(1, strip);
+    if (n == 1) {
+        R.ta = 1;
+        R.tb = 1;
+        R.s = 1;
+    } else if (n == 2) {
+        R.ta = 1;
+        R.tb = ts;
+    } else {
+        R.ta = ts >= 8 ? 4 : std::max(1, ts / 2);
+        R.tb = std::max(1, ts / R.ta);
+    }
+    auto lines = [&]() { return (n >= 2 ? R.tb * R.s + 1 : 1) * (n == 3 ? R.ta + 1 : 1); };
+    while (lines() > kMaxTileLines) {
+        if (R.s > 1) --R.s;
+        else --R.tb;
+    }
+    R.tiles_w = (R.row_words + R.tw - 1) / R.tw;
+    const int64_t rwalk = n >= 2 ? R.res[n - 2] : 1;
+    R.tiles_walk = n >= 2 ? (rwalk + (int64_t)R.tb * R.s - 1) / ((int64_t)R.tb * R.s) : 1;
+    R.tiles_fixed = n == 3 ? (R.res[0] + R.ta - 1) / R.ta : 1;
+    R.n_tiles = R.tiles_w * R.tiles_walk * R.tiles_fixed;
+}
+
+static int64_t contract_units_of(const ContractArgs &a, int mode) {
+    if (mode == kModeStreamW) return a.n_out_rows * a.c_row_words;
+    return (a.nout == 0) ? 64 : a.n_out_rows * a.c_row_words * 32;
+}
+
+int build_plan(const pa_system *sys, const int32_t *exposed, int32_t n_exposed, const pa_opts *opts, pa_plan *P) {
     auto t0 = std::chrono::steady_clock::now();
     int rc = build_sysinfo(sys, exposed, n_exposed, P->si);
     if (rc) return rc;
@@ -490,8 +554,16 @@ static int build_plan(const pa_system *sys, const int32_t *exposed, int32_t n_ex
     P->audit = o.audit;
     P->timing = o.timing;
     P->plain = o.plain;
+    P->per_op = o.per_op || o.plain;
+    P->graph = o.graph && !P->per_op;
+    P->single_launch = o.single_launch && !P->per_op;
+    P->persist_wg = o.persist_wg;
+    P->plot_strip = o.plot_strip > 0 ? o.plot_strip : 4;
+    P->contract_units = o.contract_units > 0 ? o.contract_units : 2048;
     if (o.precision != PA_PLOT_FP32_ESCALATE && o.precision != PA_PLOT_FP64)
         return fail(PA_EINVAL, "opts: unknown precision");
+    if (o.persist_wg < 0 || o.plot_strip < 0 || o.contract_units < 0)
+        return fail(PA_EINVAL, "opts: negative tuning parameter");
     switch (o.order_policy) {
         case PA_ORDER_GREEDY: rc = plan_greedy(P->si, P->tree); break;
         case PA_ORDER_EXHAUSTIVE: rc = plan_exhaustive(P->si, P->tree); break;
@@ -512,14 +584,16 @@ static int build_plan(const pa_system *sys, const int32_t *exposed, int32_t n_ex
         return g_err.empty() ? fail(PA_EINVAL, "internal: root not written to output") : PA_EINVAL;
     for (auto &op : P->ops)
         if (op.kind == OP_CONTRACT) finish_contract(op, op.b >= 0 || op.b == kBufOutput);
-    // workspace layout: tables | line tables | counters | buffers
+    P->total_macs = 0.0;
+    for (const auto &op : P->ops)
+        if (op.kind != OP_FILL) P->total_macs += op.macs;
+    // workspace layout: tables | plot records | counters | persistent state | buffers
     size_t off = 0;
     auto take = [&](size_t bytes) {
         const size_t at = off;
         off += (bytes + 255) / 256 * 256;
         return at;
     };
-    // host tables: per relation dense coefficients, per variable axis tables
     std::vector<unsigned char> &T = P->tables_host;
     T.clear();
     auto put = [&](const void *p, size_t n) {
@@ -541,33 +615,28 @@ static int build_plan(const pa_system *sys, const int32_t *exposed, int32_t n_ex
         ax_at[v] = put(x.data(), x.size() * sizeof(double));
         axf_at[v] = put(xf.data(), xf.size() * sizeof(float));
     }
+    const size_t nsteps = P->plots.size() + P->ops.size();
     P->tables_off = take(T.size());
     P->plotrel_off = take(sizeof(PlotRel) * std::max<size_t>(1, P->plots.size()));
     P->plotrel1_off = take(sizeof(PlotRel) * std::max<size_t>(1, P->plots.size()));
     P->counters_off = take(sizeof(PlotCounters));
     P->popcnt_off = take(64);
-    std::vector<size_t> line_at(P->plots.size());
-    int64_t lines = 0, words = 0, corners = 0;
-    for (size_t i = 0; i < P->plots.size(); ++i) {
-        const auto &it = P->plots[i];
-        int64_t nl = 1, cn = 1;
-        for (size_t s = 0; s + 1 < it.layout.dims.size(); ++s) nl *= it.layout.dims[s] + 1;
+    P->steps_off = take(sizeof(PStep) * std::max<size_t>(1, nsteps));
+    P->done_off = take(sizeof(unsigned) * std::max<size_t>(1, nsteps));
+    P->state_off = take(sizeof(PersistState));
+    int64_t corners = 0;
+    for (const auto &it : P->plots) {
+        int64_t cn = 1;
         for (int64_t dm : it.layout.dims) cn *= dm + 1;
         corners += cn;
-        if (P->precision == PA_PLOT_FP32_ESCALATE) {
-            line_at[i] = take(sizeof(float) * (kMaxD + 2) * nl);
-            lines += nl;
-        }
-        words += it.layout.words;
     }
-    P->total_lines = lines;
-    P->total_words = words;
     P->corners = corners;
+    for (auto &op : P->ops)
+        if (!op.ktab.empty()) op.ktab_off = (int64_t)take(op.ktab.size() * sizeof(int64_t));
     for (size_t i = 0; i < P->buf_layout.size(); ++i) P->buf_off[i] = (int64_t)take(P->buf_words[i] * 4);
     P->ws_bytes = off;
-    // PlotRel records (device pointers patched once the workspace exists)
     P->tables_bytes = T.size();
-    (void)line_at;
+    // plot records with workspace offsets in the pointer fields (patched on upload)
     P->plotrel_host.clear();
     for (size_t i = 0; i < P->plots.size(); ++i) {
         const auto &it = P->plots[i];
@@ -579,7 +648,7 @@ static int build_plan(const pa_system *sys, const int32_t *exposed, int32_t n_ex
         R.mode = P->precision;
         R.audit = P->audit;
         R.row_words = it.layout.rw;
-        R.coef = reinterpret_cast<const double *>(coef_at[it.rel]);       // offsets for now
+        R.coef = reinterpret_cast<const double *>(coef_at[it.rel]);
         double vmax = 0.0;
         for (int s = 0; s < R.n; ++s) {
             const int dv = it.storage[s];
@@ -592,47 +661,18 @@ static int build_plan(const pa_system *sys, const int32_t *exposed, int32_t n_ex
         }
         // |x_k| <= max(|lo|, |hi|) up to the two roundings of x_k
         R.vmax = vmax * (1.0 + 0x1p-50) + 0x1p-1000;
-        R.n_rows = it.layout.words / it.layout.rw;
-        R.n_lines = 1;
-        for (int s = 0; s + 1 < R.n; ++s) R.n_lines *= R.res[s] + 1;
-        if (P->precision != PA_PLOT_FP32_ESCALATE) R.n_lines = 0;
-        R.lines = reinterpret_cast<float *>(P->precision == PA_PLOT_FP32_ESCALATE ? line_at[i] : 0);
         R.out = reinterpret_cast<uint32_t *>((size_t)P->buf_off[it.buf]);
+        plot_tiling(R, P->plot_strip);
         P->plotrel_host.push_back(R);
     }
-    int64_t wb = 0, lb = 0;
+    int64_t tb = 0;
     for (auto &R : P->plotrel_host) {
-        R.word_base = wb;
-        R.line_base = lb;
-        wb += R.n_rows * R.row_words;
-        lb += R.n_lines;
+        R.tile_base = tb;
+        tb += R.n_tiles;
     }
+    P->total_tiles = tb;
     auto t1 = std::chrono::steady_clock::now();
     P->t_plan_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
-    return PA_OK;
-}
-
-static int upload(pa_plan *P) {
-    char *base = static_cast<char *>(P->ws.ptr);
-    std::vector<PlotRel> rels = P->plotrel_host;
-    auto fix = [&](const void *off) { return (void *)(base + P->tables_off + (size_t)off); };
-    for (auto &R : rels) {
-        R.coef = (const double *)fix(R.coef);
-        for (int s = 0; s < R.n; ++s) {
-            R.ax[s] = (const double *)fix(R.ax[s]);
-            R.axf[s] = (const float *)fix(R.axf[s]);
-        }
-        R.lines = R.lines ? (float *)(base + (size_t)R.lines) : nullptr;
-        R.out = (uint32_t *)(base + (size_t)R.out);
-    }
-    HIP_TRY(hipMemcpy(base + P->tables_off, P->tables_host.data(), P->tables_host.size(), hipMemcpyHostToDevice));
-    if (!rels.empty()) {
-        HIP_TRY(hipMemcpy(base + P->plotrel_off, rels.data(), rels.size() * sizeof(PlotRel), hipMemcpyHostToDevice));
-        // copies with zero bases, for one-relation-per-launch plotting
-        for (auto &R : rels) R.word_base = R.line_base = 0;
-        HIP_TRY(hipMemcpy(base + P->plotrel1_off, rels.data(), rels.size() * sizeof(PlotRel), hipMemcpyHostToDevice));
-    }
-    P->uploaded = true;
     return PA_OK;
 }
 
@@ -669,8 +709,183 @@ static uint32_t *buf_ptr(pa_plan *P, int id, void *out) {
     return reinterpret_cast<uint32_t *>(static_cast<char *>(P->ws.ptr) + P->buf_off[id]);
 }
 
+// Persistent step list: plots, then ops, sorted by level (a step's level is
+// one more than its producers'), each with its producer steps as dependencies.
+static int build_steps(pa_plan *P) {
+    char *base = static_cast<char *>(P->ws.ptr);
+    std::vector<PStep> st;
+    std::vector<int> level;
+    std::map<int, int> producer;     // buffer id -> step
+    for (size_t i = 0; i < P->plots.size(); ++i) {
+        PStep s;
+        std::memset(&s, 0, sizeof(s));
+        s.kind = kStepPlot;
+        s.plot = P->plotrel1_dev[i];
+        s.n_tiles = s.plot.n_tiles;
+        producer[P->plots[i].buf] = (int)st.size();
+        st.push_back(s);
+        level.push_back(0);
+    }
+    std::vector<int> out_refs;
+    int fill_for_next = -1;
+    for (size_t oi = 0; oi < P->ops.size(); ++oi) {
+        const Op &op = P->ops[oi];
+        PStep s;
+        std::memset(&s, 0, sizeof(s));
+        int lv = 0;
+        auto dep = [&](int buf) {
+            if (buf < 0 && buf != kBufOutput) return;
+            auto it = producer.find(buf);
+            if (it == producer.end()) return;
+            s.dep[s.ndep++] = it->second;
+            lv = std::max(lv, level[it->second] + 1);
+        };
+        if (op.kind == OP_FILL) {
+            s.kind = kStepFill;
+            s.fill_ptr = buf_ptr(P, op.c, nullptr);
+            s.units = op.fill_words;
+            s.per_tile = 4096;
+            s.n_tiles = (s.units + s.per_tile - 1) / s.per_tile;
+            fill_for_next = (int)st.size();
+            if (op.c == kBufOutput) out_refs.push_back((int)st.size());
+        } else if (op.kind == OP_GEMM) {
+            int rc = check_gemm_bounds(op.ga, op.la.words, op.lb.words, op.lc.words);
+            if (rc) return rc;
+            s.kind = kStepGemm;
+            s.gemm = op.ga;
+            s.gemm.A = buf_ptr(P, op.a, nullptr);
+            s.gemm.B = buf_ptr(P, op.b, nullptr);
+            s.gemm.C = buf_ptr(P, op.c, nullptr);
+            s.n_tiles = op.ga.nbatch * op.ga.tiles_m * op.ga.tiles_n * op.ga.ksplit;
+            dep(op.a);
+            dep(op.b);
+            if (op.ga.ksplit > 1 && fill_for_next >= 0) {
+                s.dep[s.ndep++] = fill_for_next;
+                lv = std::max(lv, level[fill_for_next] + 1);
+            }
+            fill_for_next = -1;
+            if (op.c == kBufOutput) out_refs.push_back((int)st.size());
+        } else {
+            int rc = check_contract_bounds(op.ca, op.la.words, op.lb.words, op.lc.words, op.b >= 0);
+            if (rc) return rc;
+            s.kind = kStepContract;
+            s.mode = op.mode;
+            s.ca = op.ca;
+            s.ca.ktab = op.ktab_off >= 0 ? reinterpret_cast<const int64_t *>(base + op.ktab_off) : nullptr;
+            s.ca.A = buf_ptr(P, op.a, nullptr);
+            s.ca.B = buf_ptr(P, op.b, nullptr);
+            s.ca.C = buf_ptr(P, op.c, nullptr);
+            s.units = contract_units_of(op.ca, op.mode);
+            s.per_tile = (op.mode == kModeStreamW) ? std::max<int64_t>(256, P->contract_units / 32)
+                                                   : std::max<int64_t>(256, (P->contract_units + 255) / 256 * 256);
+            s.n_tiles = (s.units + s.per_tile - 1) / s.per_tile;
+            dep(op.a);
+            dep(op.b);
+            if (op.c == kBufOutput) out_refs.push_back((int)st.size());
+        }
+        if (op.kind != OP_FILL) producer[op.c] = (int)st.size();
+        st.push_back(s);
+        level.push_back(lv);
+    }
+    // stable sort by (level, kind, mode), remap dependencies
+    std::vector<int> order(st.size());
+    for (size_t i = 0; i < st.size(); ++i) order[i] = (int)i;
+    auto key = [&](int i) { return std::make_tuple(level[i], st[i].kind, st[i].mode); };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return key(a) < key(b); });
+    std::vector<int> pos(st.size());
+    for (size_t i = 0; i < order.size(); ++i) pos[order[i]] = (int)i;
+    P->steps_host.clear();
+    P->step_macs.clear();
+    int64_t tbase = 0;
+    for (int oi : order) {
+        P->step_macs.push_back(oi >= (int)P->plots.size() ? (P->ops[oi - P->plots.size()].kind == OP_FILL
+                                                                 ? 0.0
+                                                                 : P->ops[oi - P->plots.size()].macs)
+                                                           : 0.0);
+        PStep s = st[oi];
+        for (int j = 0; j < s.ndep; ++j) s.dep[j] = pos[s.dep[j]];
+        s.tile_base = tbase;
+        tbase += s.n_tiles;
+        P->steps_host.push_back(s);
+    }
+    P->step_out_refs.clear();
+    for (int r : out_refs) P->step_out_refs.push_back({pos[r], 0});
+    P->step_level.clear();
+    for (int oi : order) P->step_level.push_back(level[oi]);
+    P->n_items = tbase;
+    make_groups(P);
+    return PA_OK;
+}
+
+// Groups: maximal runs of steps with the same (level, kind, mode), in the
+// sorted step table.
+void make_groups(pa_plan *P) {
+    P->groups.clear();
+    for (size_t i = 0; i < P->steps_host.size(); ++i) {
+        const PStep &x = P->steps_host[i];
+        const bool same = i > 0 && P->step_level[i] == P->step_level[i - 1] && x.kind == P->steps_host[i - 1].kind &&
+                          x.mode == P->steps_host[i - 1].mode;
+        if (same) {
+            P->groups.back().count += 1;
+            P->groups.back().t1 = x.tile_base + x.n_tiles;
+        } else {
+            P->groups.push_back({x.kind, x.mode, (int)i, 1, x.tile_base, x.tile_base + x.n_tiles});
+        }
+    }
+}
+
+static void patch_outputs(pa_plan *P, const std::vector<void *> &outs) {
+    for (const auto &ref : P->step_out_refs) {
+        PStep &s = P->steps_host[ref.first];
+        uint32_t *o = static_cast<uint32_t *>(outs[ref.second]);
+        if (s.kind == kStepGemm) s.gemm.C = o;
+        else if (s.kind == kStepContract) s.ca.C = o;
+        else if (s.kind == kStepFill) s.fill_ptr = o;
+    }
+}
+
+int upload_plan(pa_plan *P) {
+    char *base = static_cast<char *>(P->ws.ptr);
+    std::vector<PlotRel> rels = P->plotrel_host;
+    auto fix = [&](const void *off) { return (void *)(base + P->tables_off + (size_t)off); };
+    for (auto &R : rels) {
+        R.coef = (const double *)fix(R.coef);
+        for (int s = 0; s < R.n; ++s) {
+            R.ax[s] = (const double *)fix(R.ax[s]);
+            R.axf[s] = (const float *)fix(R.axf[s]);
+        }
+        R.out = (uint32_t *)(base + (size_t)R.out);
+    }
+    HIP_TRY(hipMemcpy(base + P->tables_off, P->tables_host.data(), P->tables_host.size(), hipMemcpyHostToDevice));
+    P->plotrel1_dev = rels;
+    for (auto &R : P->plotrel1_dev) R.tile_base = 0;
+    if (!rels.empty()) {
+        HIP_TRY(hipMemcpy(base + P->plotrel_off, rels.data(), rels.size() * sizeof(PlotRel), hipMemcpyHostToDevice));
+        // copies with zero tile bases, for one-relation-per-launch plotting
+        HIP_TRY(hipMemcpy(base + P->plotrel1_off, P->plotrel1_dev.data(), rels.size() * sizeof(PlotRel),
+                          hipMemcpyHostToDevice));
+    }
+    for (const auto &op : P->ops)
+        if (op.ktab_off >= 0)
+            HIP_TRY(hipMemcpy(base + op.ktab_off, op.ktab.data(), op.ktab.size() * sizeof(int64_t),
+                              hipMemcpyHostToDevice));
+    int rc = build_steps(P);
+    if (rc) return rc;
+    P->uploaded = true;
+    return PA_OK;
+}
+
+static int upload_steps(pa_plan *P, const std::vector<void *> &outs) {
+    patch_outputs(P, outs);
+    if (!P->steps_host.empty())
+        HIP_TRY(hipMemcpy(static_cast<char *>(P->ws.ptr) + P->steps_off, P->steps_host.data(),
+                          P->steps_host.size() * sizeof(PStep), hipMemcpyHostToDevice));
+    P->last_outs = outs;
+    return PA_OK;
+}
+
 static int run_ops(pa_plan *P, void *out, hipStream_t s, int *launches) {
-    const bool per_op = !P->op_events.empty();
+    const bool per_op = P->op_events.size() == 2 + 2 * P->ops.size();
     for (size_t oi = 0; oi < P->ops.size(); ++oi) {
         const Op &op0 = P->ops[oi];
         if (per_op) HIP_TRY(hipEventRecord(P->op_events[2 + 2 * oi], s));
@@ -690,6 +905,8 @@ static int run_ops(pa_plan *P, void *out, hipStream_t s, int *launches) {
             ContractArgs a = op0.ca;
             int rc = check_contract_bounds(a, op0.la.words, op0.lb.words, op0.lc.words, op0.b >= 0);
             if (rc) return rc;
+            a.ktab = op0.ktab_off >= 0 ? reinterpret_cast<const int64_t *>(static_cast<char *>(P->ws.ptr) + op0.ktab_off)
+                                       : nullptr;
             a.A = buf_ptr(P, op0.a, out);
             a.B = buf_ptr(P, op0.b, out);
             a.C = buf_ptr(P, op0.c, out);
@@ -708,17 +925,95 @@ static int run_plots(pa_plan *P, hipStream_t s, int *launches) {
     const int nrel = (int)P->plotrel_host.size();
     if (nrel == 0) return PA_OK;
     if (!P->plain) {
-        HIP_TRY(launch_plot(d_rels, nrel, P->total_lines, P->total_words,
-                            P->precision == PA_PLOT_FP32_ESCALATE, cnt, s, launches));
+        HIP_TRY(launch_plot(d_rels, nrel, P->total_tiles, cnt, s));
+        ++*launches;
     } else {
         const PlotRel *d_one = reinterpret_cast<const PlotRel *>(base + P->plotrel1_off);
         for (int i = 0; i < nrel; ++i) {
-            const PlotRel &R = P->plotrel_host[i];
-            // one relation per launch: the relation's own record with bases 0
-            HIP_TRY(launch_plot(d_one + i, 1, R.n_lines, R.n_rows * R.row_words,
-                                P->precision == PA_PLOT_FP32_ESCALATE, cnt, s, launches));
+            HIP_TRY(launch_plot(d_one + i, 1, P->plotrel_host[i].n_tiles, cnt, s));
+            ++*launches;
         }
     }
+    return PA_OK;
+}
+
+int persist_default_workgroups();
+
+static int run_persist(pa_plan *P, hipStream_t s, int *launches, hipEvent_t before = nullptr) {
+    char *base = static_cast<char *>(P->ws.ptr);
+    PersistState *state = reinterpret_cast<PersistState *>(base + P->state_off);
+    unsigned *done = reinterpret_cast<unsigned *>(base + P->done_off);
+    PlotCounters *cnt = reinterpret_cast<PlotCounters *>(base + P->counters_off);
+    const int nsteps = (int)P->steps_host.size();
+    int64_t wg = P->persist_wg > 0 ? P->persist_wg : persist_default_workgroups();
+    wg = std::max<int64_t>(1, std::min<int64_t>(wg, P->n_items));
+    HIP_TRY(launch_persist_reset(state, done, nsteps, cnt, s));
+    if (before) HIP_TRY(hipEventRecord(before, s));
+    const PStep *d_steps = reinterpret_cast<const PStep *>(base + P->steps_off);
+    if (P->single_launch) {
+        HIP_TRY(launch_persist(d_steps, nsteps, P->n_items, state, done, cnt, (int)wg, s));
+        *launches += 2;
+    } else {
+        const bool ev = P->op_events.size() == 2 * P->groups.size() && before;
+        for (size_t gi = 0; gi < P->groups.size(); ++gi) {
+            const auto &g = P->groups[gi];
+            if (ev && gi > 0) HIP_TRY(hipEventRecord(P->op_events[2 * gi], s));
+            HIP_TRY(launch_group(g.kind, g.mode, d_steps, g.first, g.count, g.t0, g.t1, cnt, s));
+            if (ev) HIP_TRY(hipEventRecord(P->op_events[2 * gi + 1], s));
+            ++*launches;
+        }
+        ++*launches;
+    }
+    return PA_OK;
+}
+
+// The step-table executors (grouped levels or one persistent launch), with
+// the callers' output pointers patched in, directly or as a hipGraph replay.
+int exec_steps(pa_plan *P, const std::vector<void *> &outs, hipStream_t s, int *launches) {
+    int rc;
+    if (P->last_outs != outs) {
+        rc = upload_steps(P, outs);
+        if (rc) return rc;
+    }
+    const bool use_graph = P->graph && s != nullptr && P->op_events.empty() && !P->timing_active;
+    if (use_graph) {
+        if (!P->graph_exec || P->graph_outs != outs || P->graph_stream != s) {
+            if (P->graph_exec) (void)hipGraphExecDestroy(P->graph_exec);
+            if (P->graph_h) (void)hipGraphDestroy(P->graph_h);
+            P->graph_exec = nullptr;
+            P->graph_h = nullptr;
+            HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            int dummy = 0;
+            rc = run_persist(P, s, &dummy);
+            hipGraph_t g = nullptr;
+            HIP_TRY(hipStreamEndCapture(s, &g));
+            if (rc) {
+                if (g) (void)hipGraphDestroy(g);
+                return rc;
+            }
+            HIP_TRY(hipGraphInstantiate(&P->graph_exec, g, nullptr, nullptr, 0));
+            P->graph_h = g;
+            P->graph_outs = outs;
+            P->graph_stream = s;
+        }
+        HIP_TRY(hipGraphLaunch(P->graph_exec, s));
+        *launches += 1;
+    } else {
+        rc = run_persist(P, s, launches, P->op_events.empty() ? nullptr : P->op_events[0]);
+        if (rc) return rc;
+    }
+    if (!P->op_events.empty()) {
+        HIP_TRY(hipEventRecord(P->op_events.size() == 2 ? P->op_events[1] : P->op_events.back(), s));
+        P->op_events_recorded = true;
+    }
+    return PA_OK;
+}
+
+int plan_workspace_cap(size_t *cap) {
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return fail(PA_EHIP, "no usable HIP device");
+    *cap = free_b > ((size_t)1 << 30) ? free_b - ((size_t)1 << 30) : 0;
+    if (const char *env = std::getenv("PA_MAX_WORKSPACE_BYTES")) *cap = std::min<size_t>(*cap, std::strtoull(env, nullptr, 10));
     return PA_OK;
 }
 
@@ -743,21 +1038,20 @@ extern "C" int pa_plan_create(const pa_system *sys, const int32_t *exposed, int3
     } else {
         // refuse plans whose intermediates cannot fit instead of attempting
         // an allocation the device cannot satisfy
-        size_t free_b = 0, total_b = 0;
-        if (hipMemGetInfo(&free_b, &total_b) != hipSuccess)
-            return fail(PA_EHIP, "plan_create: no usable HIP device");
-        size_t cap = free_b > ((size_t)1 << 30) ? free_b - ((size_t)1 << 30) : 0;
-        if (const char *env = std::getenv("PA_MAX_WORKSPACE_BYTES")) cap = std::min<size_t>(cap, std::strtoull(env, nullptr, 10));
+        size_t cap = 0;
+        rc = plan_workspace_cap(&cap);
+        if (rc) return rc;
         if (P->ws_bytes > cap)
             return fail(PA_ENOMEM, "plan needs " + std::to_string(P->ws_bytes) + " bytes of workspace, " +
                                        std::to_string(cap) + " available (choose another order)");
         rc = P->ws.ensure(std::max<size_t>(P->ws_bytes, 256));
         if (rc) return rc;
     }
-    rc = upload(P.get());
+    rc = upload_plan(P.get());
     if (rc) return rc;
     if (opts && opts->timing == 2) {
-        P->op_events.resize(2 + 2 * P->ops.size());
+        P->op_events.resize(P->per_op ? 2 + 2 * P->ops.size()
+                                      : (P->single_launch ? 2 : std::max<size_t>(2, 2 * P->groups.size())));
         for (auto &e : P->op_events) HIP_TRY(hipEventCreate(&e));
     }
     *plan = P.release();
@@ -767,22 +1061,36 @@ extern "C" int pa_plan_create(const pa_system *sys, const int32_t *exposed, int3
 pa_plan::~pa_plan() {
     for (auto &e : op_events)
         if (e) (void)hipEventDestroy(e);
+    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+    if (graph_h) (void)hipGraphDestroy(graph_h);
 }
 
 extern "C" int32_t pa_plan_op_times(pa_plan *P, double *ms, int32_t *kind, double *macs, int32_t cap) {
     if (!P || P->op_events.empty() || !P->op_events_recorded) return fail(PA_EINVAL, "op_times: no op timings"), -1;
-    const int32_t n = 1 + (int32_t)P->ops.size();
+    const bool per_op = P->per_op;
+    const bool groups = !per_op && !P->single_launch && !P->groups.empty();
+    const int32_t n = per_op ? 1 + (int32_t)P->ops.size() : (groups ? (int32_t)P->groups.size() : 1);
     if (hipEventSynchronize(P->op_events.back()) != hipSuccess) return fail(PA_EHIP, "op_times: sync"), -1;
     for (int32_t i = 0; i < n && i < cap; ++i) {
         float t = 0.f;
         if (hipEventElapsedTime(&t, P->op_events[2 * i], P->op_events[2 * i + 1]) != hipSuccess) t = -1.f;
         if (ms) ms[i] = t;
-        int k = PA_OPKIND_PLOT;
-        double mc = 0.0;
-        if (i > 0) {
-            const Op &op = P->ops[i - 1];
-            k = op.kind == OP_GEMM ? PA_OPKIND_GEMM : op.kind == OP_FILL ? PA_OPKIND_FILL : op.mode;
-            mc = op.kind == OP_FILL ? 0.0 : op.macs;
+        int k = PA_OPKIND_PERSIST;
+        double mc = P->total_macs;
+        if (per_op) {
+            k = PA_OPKIND_PLOT;
+            mc = 0.0;
+            if (i > 0) {
+                const Op &op = P->ops[i - 1];
+                k = op.kind == OP_GEMM ? PA_OPKIND_GEMM : op.kind == OP_FILL ? PA_OPKIND_FILL : op.mode;
+                mc = op.kind == OP_FILL ? 0.0 : op.macs;
+            }
+        } else if (groups) {
+            const auto &g = P->groups[i];
+            k = g.kind == kStepPlot ? PA_OPKIND_PLOT
+                                    : g.kind == kStepGemm ? PA_OPKIND_GEMM : g.kind == kStepFill ? PA_OPKIND_FILL : g.mode;
+            mc = 0.0;
+            for (int j = g.first; j < g.first + g.count; ++j) mc += P->step_macs[j];
         }
         if (kind) kind[i] = k;
         if (macs) macs[i] = mc;
@@ -805,32 +1113,38 @@ extern "C" int pa_plan_execute(pa_plan *P, pa_bitarray *out, pa_report *rep, voi
     const bool timing = P->timing && rep;
     if (timing)
         for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
-    if (rep) {
-        HIP_TRY(launch_fill(reinterpret_cast<uint32_t *>(base + P->counters_off), sizeof(PlotCounters) / 4, 0u, s));
-        HIP_TRY(launch_fill(reinterpret_cast<uint32_t *>(base + P->popcnt_off), 2, 0u, s));
-        launches += 2;
-    }
     if (timing) HIP_TRY(hipEventRecord(ev[0], s));
-    if (!P->op_events.empty()) HIP_TRY(hipEventRecord(P->op_events[0], s));
-    rc = run_plots(P, s, &launches);
-    if (rc) return rc;
-    if (!P->op_events.empty()) {
-        HIP_TRY(hipEventRecord(P->op_events[1], s));
-        P->op_events_recorded = true;
+    if (!P->op_events.empty() && P->per_op) HIP_TRY(hipEventRecord(P->op_events[0], s));
+    if (P->per_op) {
+        HIP_TRY(launch_fill(reinterpret_cast<uint32_t *>(base + P->counters_off), sizeof(PlotCounters) / 4, 0u, s));
+        ++launches;
+        rc = run_plots(P, s, &launches);
+        if (rc) return rc;
+        if (!P->op_events.empty()) HIP_TRY(hipEventRecord(P->op_events[1], s));
+        if (timing) HIP_TRY(hipEventRecord(ev[1], s));
+        rc = run_ops(P, out->data, s, &launches);
+        if (rc) return rc;
+    } else {
+        P->timing_active = timing;
+        rc = exec_steps(P, {out->data}, s, &launches);
+        if (rc) return rc;
+        if (timing) HIP_TRY(hipEventRecord(ev[1], s));
     }
-    if (timing) HIP_TRY(hipEventRecord(ev[1], s));
-    rc = run_ops(P, out->data, s, &launches);
-    if (rc) return rc;
+    if (!P->op_events.empty()) P->op_events_recorded = true;
     if (timing) HIP_TRY(hipEventRecord(ev[2], s));
     if (rep) {
         std::memset(rep, 0, sizeof(*rep));
+        HIP_TRY(launch_fill(reinterpret_cast<uint32_t *>(base + P->popcnt_off), 2, 0u, s));
         HIP_TRY(launch_popcount(static_cast<const uint32_t *>(out->data), P->out_layout.words,
                                 reinterpret_cast<unsigned long long *>(base + P->popcnt_off), s));
         PlotCounters cnt;
+        PersistState pst;
         unsigned long long nnz = 0;
         HIP_TRY(hipMemcpyAsync(&cnt, base + P->counters_off, sizeof(cnt), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipMemcpyAsync(&nnz, base + P->popcnt_off, sizeof(nnz), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(&pst, base + P->state_off, sizeof(pst), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
+        if (!P->per_op && pst.abort) return fail(PA_EHIP, "persistent executor gave up a dependency wait");
         rep->corners = P->corners;
         rep->corners_flagged = (int64_t)cnt.flagged;
         rep->corners_disagree = (int64_t)cnt.disagree;
@@ -838,9 +1152,8 @@ extern "C" int pa_plan_execute(pa_plan *P, pa_bitarray *out, pa_report *rep, voi
         rep->nnz_out = (int64_t)nnz;
         rep->n_launches = launches;
         int steps = 0;
-        double macs = 0.0;
         for (const auto &op : P->ops)
-            if (op.kind != OP_FILL && op.b != -1) { ++steps; macs += op.macs; }
+            if (op.kind != OP_FILL && op.b != -1) ++steps;
         rep->n_steps = steps;
         rep->cost_macs = P->tree.cost;
         for (size_t i = 0; i < P->tree.merges.size() && i < 2 * PA_MAX_RELATIONS; ++i) rep->merges[i] = P->tree.merges[i];
@@ -852,7 +1165,6 @@ extern "C" int pa_plan_execute(pa_plan *P, pa_bitarray *out, pa_report *rep, voi
             rep->t_plot_ms = a;
             rep->t_contract_ms = b;
         }
-        (void)macs;
     }
     if (timing)
         for (auto &e : ev) (void)hipEventDestroy(e);
@@ -884,6 +1196,7 @@ extern "C" int64_t pa_plan_describe(const pa_system *sys, const int32_t *exposed
     } else {
         s << "{\"merges\":" << join(std::vector<int>(P->tree.merges.begin(), P->tree.merges.end()))
           << ",\"cost\":" << P->tree.cost << ",\"workspace_bytes\":" << P->ws_bytes << ",\"corners\":" << P->corners
+          << ",\"total_macs\":" << P->total_macs
           << ",\"plots\":[";
         for (size_t i = 0; i < P->plots.size(); ++i)
             s << (i ? "," : "") << "{\"rel\":" << P->plots[i].rel << ",\"buf\":" << P->plots[i].buf
@@ -1056,6 +1369,20 @@ extern "C" int pa_contract(const pa_bitarray *A, const int32_t *a_vars, const pa
     op.ca.A = static_cast<const uint32_t *>(A->data);
     op.ca.B = B ? static_cast<const uint32_t *>(B->data) : nullptr;
     op.ca.C = static_cast<uint32_t *>(C->data);
-    HIP_TRY(launch_contract(op.ca, op.mode, s));
+    void *tab = nullptr;
+    if (!op.ktab.empty()) {
+        // stream-ordered table: allocated, filled, used and freed on `s`
+        const size_t bytes = op.ktab.size() * sizeof(int64_t);
+        if (hipMallocAsync(&tab, bytes, s) != hipSuccess) return fail(PA_ENOMEM, "contract: table allocation failed");
+        HIP_TRY(hipMemcpyAsync(tab, op.ktab.data(), bytes, hipMemcpyHostToDevice, s));
+        op.ca.ktab = static_cast<const int64_t *>(tab);
+    }
+    const hipError_t le = launch_contract(op.ca, op.mode, s);
+    if (tab) {
+        // the host table must outlive the asynchronous copy
+        (void)hipStreamSynchronize(s);
+        (void)hipFreeAsync(tab, s);
+    }
+    if (le != hipSuccess) return fail(PA_EHIP, std::string("contract launch: ") + hipGetErrorString(le));
     return PA_OK;
 }

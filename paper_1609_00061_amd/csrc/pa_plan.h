@@ -1,6 +1,7 @@
 // Plans: cluster tree, per-node layouts, the op list and the workspace.
 #pragma once
 #include <array>
+#include <utility>
 #include <stdint.h>
 #include <string>
 #include <vector>
@@ -88,6 +89,8 @@ struct Op {
     Layout la, lb, lc;
     std::vector<int> kvars;
     ContractArgs ca{};            // pointers patched at execution
+    std::vector<int64_t> ktab;    // streaming modes: (A, B) word offsets of latent entries
+    int64_t ktab_off = -1;        // byte offset of ktab in the workspace
     GemmArgs ga{};
     int64_t fill_words = 0;
     double macs = 0.0;            // product of the step's link resolutions
@@ -106,6 +109,15 @@ struct pa_plan_impl;
 
 }  // namespace pa
 
+struct pa_plan;
+namespace pa {
+int build_plan(const pa_system *sys, const int32_t *exposed, int32_t n_exposed, const pa_opts *opts, pa_plan *P);
+int upload_plan(pa_plan *P);
+int exec_steps(pa_plan *P, const std::vector<void *> &outs, hipStream_t s, int *launches);
+int plan_workspace_cap(size_t *cap);
+void make_groups(pa_plan *P);
+}  // namespace pa
+
 struct pa_plan {
     pa::SysInfo si;
     pa::Tree tree;
@@ -116,18 +128,38 @@ struct pa_plan {
     std::vector<pa::Layout> buf_layout;
     size_t tables_off = 0, tables_bytes = 0, ws_bytes = 0;
     size_t plotrel_off = 0, plotrel1_off = 0, counters_off = 0, popcnt_off = 0;
-    std::vector<pa::PlotRel> plotrel_host;    // records with prefix bases (fused launch)
+    size_t steps_off = 0, done_off = 0, state_off = 0;
+    std::vector<pa::PlotRel> plotrel_host;    // records with prefix tile bases (fused launch)
+    std::vector<pa::PlotRel> plotrel1_dev;    // device-pointer records with zero tile bases
+    std::vector<pa::PStep> steps_host;        // persistent executor (device pointers, output patched)
+    std::vector<std::pair<int, int>> step_out_refs;   // (step, output index): steps writing a caller's output
+    std::vector<int> step_level;              // per sorted step
+    int64_t n_items = 0;
+    int per_op = 0, graph = 0, single_launch = 0, persist_wg = 0, plot_strip = 0, contract_units = 0;
+    struct Group {
+        int kind, mode, first, count;
+        int64_t t0, t1;
+    };
+    std::vector<Group> groups;                // level-synchronous executor
+    std::vector<double> step_macs;            // per sorted step (0 for plots and fills)
+    std::vector<void *> last_outs;
+    hipGraph_t graph_h = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    std::vector<void *> graph_outs;
+    hipStream_t graph_stream = nullptr;
+    double total_macs = 0.0;
     std::vector<unsigned char> tables_host;   // uploaded once
     pa::Workspace ws;
     int precision = PA_PLOT_FP32_ESCALATE;
     int audit = 0, timing = 0, plain = 0;
     int device = 0;
-    int64_t corners = 0, total_lines = 0, total_words = 0;
+    int64_t corners = 0, total_tiles = 0;
     int n_rel_plots = 0;
     bool uploaded = false;
     double t_plan_ms = 0.0;
     pa::Layout out_layout;
     std::vector<hipEvent_t> op_events;     // timing == 2: 2 per op + 2 for plotting
     bool op_events_recorded = false;
+    bool timing_active = false;
     ~pa_plan();
 };

@@ -167,16 +167,19 @@ int plan_greedy(const SysInfo &si, Tree &t) {
 
 // Exhaustive: the cheapest binary cluster tree, by dynamic programming over
 // subsets of relations (a cluster's intermediate pack depends only on its set
-// of relations).
+// of relations).  Among trees of equal cost the one with the lowest parallel
+// cost (a node's cost plus the max of its children's, Sec. 3.5.1) wins: its
+// independent subtrees run side by side.
 int plan_exhaustive(const SysInfo &si, Tree &t) {
     const int n = si.n_rel;
     if (n > 16) return plan_greedy(si, t);
     const uint32_t full = (n == 32) ? 0xffffffffu : ((1u << n) - 1u);
     std::vector<double> best((size_t)full + 1, std::numeric_limits<double>::infinity());
+    std::vector<double> pbest((size_t)full + 1, std::numeric_limits<double>::infinity());
     std::vector<uint32_t> split((size_t)full + 1, 0);
     std::vector<uint64_t> q((size_t)full + 1, 0);
     for (uint32_t S = 1; S <= full; ++S) q[S] = q_of(S, si);
-    for (int i = 0; i < n; ++i) best[1u << i] = 0.0;
+    for (int i = 0; i < n; ++i) best[1u << i] = pbest[1u << i] = 0.0;
     for (uint32_t S = 1; S <= full; ++S) {
         if ((S & (S - 1)) == 0) continue;
         const uint32_t low = S & (~S + 1);
@@ -185,8 +188,15 @@ int plan_exhaustive(const SysInfo &si, Tree &t) {
         for (uint32_t sub = rest;; sub = (sub - 1) & rest) {
             const uint32_t S1 = sub | low, S2 = S ^ S1;
             if (S2) {
-                const double c = best[S1] + best[S2] + mask_cost(q[S1] | q[S2], si);
-                if (c < best[S]) { best[S] = c; split[S] = S1; }
+                const double node = mask_cost(q[S1] | q[S2], si);
+                const double c = best[S1] + best[S2] + node;
+                const double pc = node + std::max(pbest[S1], pbest[S2]);
+                const double tol = 1e-12 * best[S];
+                if (c < best[S] - tol || (c <= best[S] + tol && pc < pbest[S])) {
+                    best[S] = c;
+                    pbest[S] = pc;
+                    split[S] = S1;
+                }
             }
             if (sub == 0) break;
         }

@@ -17,7 +17,8 @@ LIB_PATH = os.path.join(_HERE, "libpa.so")
 
 PA_OK, PA_EINVAL, PA_ENOMEM, PA_EHIP, PA_EUNSUPPORTED = 0, 1, 2, 3, 4
 ORDER_GREEDY, ORDER_EXHAUSTIVE, ORDER_LEARNED, ORDER_GIVEN = 0, 1, 2, 3
-OPKIND_BITS, OPKIND_STREAM_K, OPKIND_STREAM_W, OPKIND_GEMM, OPKIND_FILL, OPKIND_PLOT = 0, 1, 2, 10, 20, 30
+OPKIND_BITS, OPKIND_STREAM_K, OPKIND_STREAM_W, OPKIND_GEMM, OPKIND_FILL, OPKIND_PLOT, OPKIND_PERSIST = \
+    0, 1, 2, 10, 20, 30, 40
 PLOT_FP32_ESCALATE, PLOT_FP64 = 0, 1
 MAX_DIMS, MAX_RELATIONS = 12, 32
 
@@ -54,6 +55,9 @@ class Opts(ctypes.Structure):
     _fields_ = [("order_policy", ctypes.c_int32), ("n_given", ctypes.c_int32),
                 ("given", ctypes.POINTER(ctypes.c_int32)), ("precision", ctypes.c_int32),
                 ("audit", ctypes.c_int32), ("timing", ctypes.c_int32), ("plain", ctypes.c_int32),
+                ("per_op", ctypes.c_int32), ("graph", ctypes.c_int32), ("single_launch", ctypes.c_int32),
+                ("persist_wg", ctypes.c_int32),
+                ("plot_strip", ctypes.c_int32), ("contract_units", ctypes.c_int32),
                 ("model", ctypes.c_void_p), ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t)]
 
 
@@ -106,6 +110,19 @@ def load(path: str = LIB_PATH):
     L.pa_plan_op_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32),
                                    ctypes.POINTER(ctypes.c_double), ctypes.c_int32]
     L.pa_plan_op_times.restype = ctypes.c_int32
+    L.pa_batch_create.argtypes = [ctypes.POINTER(System), ctypes.c_int32, ctypes.POINTER(ctypes.POINTER(ctypes.c_int32)),
+                                  i32p, ctypes.POINTER(Opts), ctypes.POINTER(vp)]
+    L.pa_batch_execute.argtypes = [vp, ctypes.POINTER(BitArray), ctypes.POINTER(Report),
+                                   ctypes.POINTER(ctypes.c_int64), vp]
+    L.pa_batch_workspace_bytes.argtypes = [vp]
+    L.pa_batch_workspace_bytes.restype = ctypes.c_size_t
+    L.pa_batch_op_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32),
+                                    ctypes.POINTER(ctypes.c_double), ctypes.c_int32]
+    L.pa_batch_op_times.restype = ctypes.c_int32
+    L.pa_batch_destroy.argtypes = [vp]
+    L.pa_batch_destroy.restype = None
+    L.pa_solve_batch.argtypes = [ctypes.POINTER(System), ctypes.c_int32, ctypes.POINTER(ctypes.POINTER(ctypes.c_int32)),
+                                 i32p, ctypes.POINTER(Opts), ctypes.POINTER(BitArray), ctypes.POINTER(ctypes.c_int64), vp]
     _lib = L
     return L
 
@@ -155,13 +172,20 @@ def _system(keep, system) -> System:
 
 
 def make_opts(order=ORDER_EXHAUSTIVE, precision=PLOT_FP32_ESCALATE, audit=False, timing=False, plain=False,
-              given: Optional[Sequence[int]] = None, model=None, keep: Optional[_Keep] = None) -> Opts:
+              given: Optional[Sequence[int]] = None, model=None, keep: Optional[_Keep] = None, per_op=False,
+              graph=False, single_launch=False, persist_wg=0, plot_strip=0, contract_units=0) -> Opts:
     o = Opts()
     o.order_policy = order
     o.precision = precision
     o.audit = int(audit)
     o.timing = int(timing)
     o.plain = int(plain)
+    o.per_op = int(per_op)
+    o.graph = int(graph)
+    o.single_launch = int(single_launch)
+    o.persist_wg = int(persist_wg)
+    o.plot_strip = int(plot_strip)
+    o.contract_units = int(contract_units)
     if given is not None:
         assert keep is not None
         o.n_given = len(given) // 2
@@ -219,7 +243,8 @@ def pack_bits(arr: np.ndarray) -> np.ndarray:
 
 
 # ------------------------------------------------------------ entry points
-def plot_relation(rel, axes_of_vars, precision=PLOT_FP32_ESCALATE, audit=False, stream=None, report=True):
+def plot_relation(rel, axes_of_vars, precision=PLOT_FP32_ESCALATE, audit=False, stream=None, report=True,
+                  **exec_opts):
     """Plot one relation; returns (device words, dims, report dict or None)."""
     L = load()
     keep = _Keep()
@@ -228,7 +253,7 @@ def plot_relation(rel, axes_of_vars, precision=PLOT_FP32_ESCALATE, audit=False, 
     dims = [int(a[2]) for a in axes_of_vars]
     out = empty_bits(dims)
     ba = bitarray(out, dims)
-    opts = make_opts(precision=precision, audit=audit)
+    opts = make_opts(precision=precision, audit=audit, **exec_opts)
     rep = Report()
     _check(L.pa_plot_relation(ctypes.byref(r), axes, ctypes.byref(opts), ctypes.byref(ba),
                               ctypes.byref(rep) if report else None, _stream_ptr(stream)))
@@ -250,13 +275,13 @@ def contract(A, a_dims, a_vars, B, b_dims, b_vars, out_vars, out_dims, stream=No
 
 
 def describe_plan(system, exposed=None, order=ORDER_EXHAUSTIVE, precision=PLOT_FP32_ESCALATE,
-                  given=None, plain=False) -> dict:
+                  given=None, plain=False, **exec_opts) -> dict:
     """Host-only: the plan (tree, layouts, kernels) as a dict."""
     L = load()
     keep = _Keep()
     exposed = list(system.exposed if exposed is None else exposed)
     s = _system(keep, system)
-    opts = make_opts(order=order, precision=precision, given=given, plain=plain, keep=keep)
+    opts = make_opts(order=order, precision=precision, given=given, plain=plain, keep=keep, **exec_opts)
     n = L.pa_plan_describe(ctypes.byref(s), keep.i32(exposed), len(exposed), ctypes.byref(opts), None, 0)
     buf = ctypes.create_string_buffer(int(n) + 1)
     L.pa_plan_describe(ctypes.byref(s), keep.i32(exposed), len(exposed), ctypes.byref(opts), buf, n + 1)
@@ -267,14 +292,14 @@ class Plan:
     """A planned solve: pa_plan_create once, execute many times."""
 
     def __init__(self, system, exposed=None, order=ORDER_EXHAUSTIVE, precision=PLOT_FP32_ESCALATE, audit=False,
-                 timing=False, plain=False, given=None, model=None):
+                 timing=False, plain=False, given=None, model=None, **exec_opts):
         L = load()
         self._keep = _Keep()
         self.exposed = list(system.exposed if exposed is None else exposed)
         self.dims = [int(system.axes[v][2]) for v in self.exposed]
         s = _system(self._keep, system)
         opts = make_opts(order=order, precision=precision, audit=audit, timing=timing, plain=plain, given=given,
-                         model=model, keep=self._keep)
+                         model=model, keep=self._keep, **exec_opts)
         h = ctypes.c_void_p()
         _check(L.pa_plan_create(ctypes.byref(s), self._keep.i32(self.exposed), len(self.exposed),
                                 ctypes.byref(opts), ctypes.byref(h)))
@@ -309,6 +334,65 @@ class Plan:
         try:
             if getattr(self, "handle", None) and _lib is not None:
                 _lib.pa_plan_destroy(self.handle)
+                self.handle = None
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many independent systems planned separately and executed together."""
+
+    def __init__(self, systems, order=ORDER_EXHAUSTIVE, precision=PLOT_FP32_ESCALATE, audit=False, timing=False,
+                 model=None, **exec_opts):
+        L = load()
+        self._keep = _Keep()
+        self.systems = list(systems)
+        self.dims = [[int(s.axes[v][2]) for v in s.exposed] for s in self.systems]
+        arr = (System * len(self.systems))(*[_system(self._keep, s) for s in self.systems])
+        exps = [self._keep.i32(list(s.exposed)) for s in self.systems]
+        exp_ptrs = (ctypes.POINTER(ctypes.c_int32) * len(exps))(
+            *[ctypes.cast(e, ctypes.POINTER(ctypes.c_int32)) for e in exps])
+        n_exp = self._keep.i32([len(s.exposed) for s in self.systems])
+        self._keep.items += [arr, exp_ptrs]
+        opts = make_opts(order=order, precision=precision, audit=audit, timing=timing, model=model,
+                         keep=self._keep, **exec_opts)
+        h = ctypes.c_void_p()
+        _check(L.pa_batch_create(arr, len(self.systems), exp_ptrs, n_exp, ctypes.byref(opts), ctypes.byref(h)))
+        self.handle = h
+
+    def workspace_bytes(self) -> int:
+        return int(load().pa_batch_workspace_bytes(self.handle))
+
+    def alloc_outputs(self):
+        return [empty_bits(d) for d in self.dims]
+
+    def execute(self, outs=None, stream=None, report=False):
+        """Returns (outs, report dict or None, nnz list or None)."""
+        L = load()
+        if outs is None:
+            outs = self.alloc_outputs()
+        bas = (BitArray * len(outs))(*[bitarray(t, d) for t, d in zip(outs, self.dims)])
+        rep = Report() if report else None
+        nnz = (ctypes.c_int64 * len(outs))() if report else None
+        _check(L.pa_batch_execute(self.handle, bas, ctypes.byref(rep) if report else None, nnz,
+                                  _stream_ptr(stream)))
+        return outs, (rep.as_dict() if report else None), (list(nnz) if report else None)
+
+    def op_times(self):
+        L = load()
+        cap = 4096
+        ms = (ctypes.c_double * cap)()
+        kd = (ctypes.c_int32 * cap)()
+        mc = (ctypes.c_double * cap)()
+        n = L.pa_batch_op_times(self.handle, ms, kd, mc, cap)
+        if n < 0:
+            _check(PA_EINVAL)
+        return [(int(kd[i]), float(ms[i]), float(mc[i])) for i in range(min(n, cap))]
+
+    def __del__(self):
+        try:
+            if getattr(self, "handle", None) and _lib is not None:
+                _lib.pa_batch_destroy(self.handle)
                 self.handle = None
         except Exception:
             pass

@@ -59,9 +59,26 @@ def test_plans_put_dense_steps_on_mfma():
     assert _kernels(c2) == ["gemm_mfma"] * 7
     c3 = pa.describe_plan(inputs.config3())
     assert _kernels(c3) == ["gemm_mfma", "gemm_mfma", "stream_k"]
+    # both r^5 steps (65536 x 65536 x 256) on MFMA, the r^4 step streamed
     g = [o for o in c3["ops"] if o["op"] == "gemm_mfma"]
-    assert g[0]["M"] == 65536 and g[0]["No"] * g[0]["rn"] == 65536 and g[0]["Kw"] == 8
-    assert g[1]["batch"] == 256 and g[1]["M"] == 65536 and g[1]["rn"] == 256
+    assert all(o["macs"] == 256 ** 5 and o["Kw"] == 8 for o in g)
+    assert [o["macs"] for o in c3["ops"] if o["op"] == "stream_k"] == [256 ** 4]
+    assert c3["cost"] == 2 * 256 ** 5 + 256 ** 4
+
+
+def test_exhaustive_prefers_parallel_trees_on_ties():
+    """All cluster trees of the chain cost 7 r^3; the balanced one has the
+    lowest parallel cost (3 r^3, Sec. 3.5.1) and is chosen."""
+    d = pa.describe_plan(inputs.config2())
+    assert d["cost"] == 7 * 1024 ** 3
+    assert d["merges"][:8] == [0, 1, 2, 3, 8, 9, 4, 5] or sorted(d["merges"][:4]) == [0, 1, 2, 3]
+    # depth of the tree: no merge consumes the previous merge's output three times in a row
+    n = 8
+    depth = {i: 0 for i in range(n)}
+    for t in range(n - 1):
+        a, b = d["merges"][2 * t], d["merges"][2 * t + 1]
+        depth[n + t] = 1 + max(depth[a], depth[b])
+    assert depth[2 * n - 2] == 3
 
 
 def _packs(s):
