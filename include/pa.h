@@ -204,7 +204,8 @@ int pa_plan_execute(pa_plan *plan, pa_bitarray *out, pa_report *report, void *st
 /* Device bytes of the plan's workspace (intermediates + tables). */
 size_t pa_plan_workspace_bytes(const pa_plan *plan);
 /* JSON description of the plan (steps, kernels, layouts, costs) into buf;
- * returns the length needed (excluding the NUL). Host-only, no device use. */
+ * returns the length needed (excluding the NUL). Host-only except under
+ * PA_ORDER_LEARNED, whose model inference runs on the model's device. */
 int64_t pa_plan_describe(const pa_system *sys, const int32_t *exposed, int32_t n_exposed, const pa_opts *opts,
                          char *buf, int64_t buf_len);
 void pa_plan_destroy(pa_plan *plan);
@@ -244,6 +245,70 @@ void pa_batch_destroy(pa_batch *batch);
 /* pa_batch_create + pa_batch_execute + pa_batch_destroy (synchronizes). */
 int pa_solve_batch(const pa_system *systems, int32_t n_sys, const int32_t *const *exposed, const int32_t *n_exposed,
                    const pa_opts *opts, pa_bitarray *outs, int64_t *nnz, void *stream);
+
+/* ---------------------------------------------------------- learned order
+ * The tree of pairwise steps only decides the work (Sec. 3.5), and the naive
+ * cost r^L of a step (eqn naive_cost) does not say how fast the hardware runs
+ * it (matrix cores vs bit streaming, padding, launch latency).  A pa_model is
+ * a small MLP (PA_MODEL_FEATURES -> 64 -> 64 -> 1, ReLU, float32) that
+ * predicts log2 of a step's duration in microseconds from features of its
+ * index groups; PA_ORDER_LEARNED runs a dynamic program over connected sets
+ * of relations (all sets if the relation graph is disconnected; greedy above
+ * 16 relations) minimizing the sum of predicted step times, with one batched
+ * forward pass on the device per 2^18 candidate steps.  Training data come
+ * from the library's own timings (pa_plan_step_samples); forward, backward
+ * and the Adam update run in the library's kernels.
+ *
+ * Parameters are float32 in the flat layout W1[64][F], b1[64], W2[64][64],
+ * b2[64], w3[64], b3 (F = PA_MODEL_FEATURES).  A model lives on the device
+ * that was current at creation and must be used with that device current
+ * (EINVAL otherwise).  Device pointers below are float32 arrays on that
+ * device; calls on the same model must not overlap. */
+enum { PA_MODEL_FEATURES = 16 };
+int32_t pa_model_n_params(void);
+int32_t pa_model_n_features(void);
+/* New model with uniform He initial weights drawn from SplitMix64(seed), zero
+ * biases and zero Adam moments.  EHIP if device memory is unavailable. */
+int pa_model_create(uint64_t seed, pa_model **model);
+void pa_model_destroy(pa_model *model);
+/* Copy the n == pa_model_n_params() parameters to / from host memory;
+ * setting them also clears the Adam moments and step count.  EINVAL on a
+ * wrong n or a non-finite value. */
+int pa_model_get_params(const pa_model *model, float *host_params, int32_t n);
+int pa_model_set_params(pa_model *model, const float *host_params, int32_t n);
+/* Y[i] = prediction for features X[i][F], i < n (device pointers; n >= 0). */
+int pa_model_forward(pa_model *model, const float *X, int64_t n, float *Y, void *stream);
+/* Gradient of the mean squared error (1/n) sum (y_i - T_i)^2 with respect
+ * to the parameters, into grad (device, n_params floats; may be NULL), and
+ * the loss into *loss (host; may be NULL; then the call synchronizes the
+ * stream).  Batch reductions run in a fixed order: results are
+ * deterministic.  EINVAL if n < 1. */
+int pa_model_gradient(pa_model *model, const float *X, const float *T, int64_t n, float *grad, float *loss,
+                      void *stream);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) on that
+ * gradient with learning rate lr > 0; *loss (may be NULL) gets the batch loss
+ * before the update. */
+int pa_model_train_step(pa_model *model, const float *X, const float *T, int64_t n, float lr, float *loss,
+                        void *stream);
+/* Checkpoint: one JSON header line, a newline, then the parameters as
+ * little-endian float32.  load creates a model on the current device;
+ * EINVAL if the file is not a model of this shape. */
+int pa_model_save(const pa_model *model, const char *path);
+int pa_model_load(const char *path, pa_model **model);
+/* Features of the step multiplying the clusters of relation sets s1 and s2
+ * (bit r = relation r; disjoint, non-empty) of a system: log2 sizes / 8 of
+ * the batch, M, N and shared latent groups, of the scope, output and
+ * operands; the path flags (MFMA-eligible, streaming over a shared latent
+ * variable, no shared latent variable); scope and output arity / 4; and
+ * estimated log2 densities / 8 of both operands and the output.  Host-only. */
+int pa_step_features(const pa_system *sys, const int32_t *exposed, int32_t n_exposed, uint32_t s1, uint32_t s2,
+                     float *features);
+/* Training samples from the last execute of a plan created with per_op = 1
+ * and timing = 2: for every pairwise step of the tree (in tree order) its
+ * features (cap x F floats) and log2 of its measured duration in
+ * microseconds (the sum of the step's op launches, from HIP events).  Waits
+ * for the events.  Returns the number of steps, or -1 (see pa_last_error). */
+int32_t pa_plan_step_samples(pa_plan *plan, float *features, float *log2_us, int32_t cap);
 
 /* pa_plan_create + pa_plan_execute + pa_plan_destroy. */
 int pa_solve_system(const pa_system *sys, const int32_t *exposed, int32_t n_exposed, const pa_opts *opts,

@@ -1,0 +1,476 @@
+// Learned contraction order.  The cluster tree only decides the work
+// (Sec. 3.5); the naive cost r^L (eqn naive_cost) ranks steps by their index
+// volume but not by how fast the hardware runs them: a dense step on the
+// matrix cores costs far less per MAC than a skinny bit-streaming one.  Here
+// a small MLP, trained on the library's own measured step durations,
+// predicts the time of every candidate pairwise step, and a dynamic program
+// over connected sets of relations picks the tree with the least predicted
+// total time.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <string>
+#include <vector>
+
+#include "pa_mlp.h"
+#include "pa_plan.h"
+
+pa_model::~pa_model() {
+    int cur = 0;
+    if (hipGetDevice(&cur) == hipSuccess && cur != device) (void)hipSetDevice(device);
+    for (float *p : {P, M, V, G, loss, Y, acts, dacts, dY})
+        if (p) (void)hipFree(p);
+    if (cur != device) (void)hipSetDevice(cur);
+}
+
+namespace pa {
+
+#define HIP_TRY(expr)                                                                                   \
+    do {                                                                                                \
+        hipError_t _e = (expr);                                                                         \
+        if (_e != hipSuccess) return fail(PA_EHIP, std::string(#expr) + ": " + hipGetErrorString(_e)); \
+    } while (0)
+
+// ------------------------------------------------------------------ features
+// Scale of the log2 features (keeps inputs O(1)).
+constexpr double kLogScale = 1.0 / 8.0;
+// Largest intermediate the learned order may create: 2^33 bits (1 GiB).
+constexpr double kMaxLog2Bits = 33.0;
+
+static double log2_cost(uint64_t m, const std::vector<double> &lr) {
+    double s = 0.0;
+    while (m) {
+        s += lr[__builtin_ctzll(m)];
+        m &= m - 1;
+    }
+    return s;
+}
+
+// Estimated log2 density of a cluster's array: n generic equations in V
+// unknowns leave a solution set of dimension V - n, whose projection onto
+// the pack Q has dimension min(|Q|, V - n); each missing dimension thins the
+// array by about one cell in r/2 along that axis.
+static double est_log2_density(int n_rel, int n_vars, uint64_t q, double lq) {
+    const int nq = __builtin_popcountll(q);
+    if (nq == 0) return 0.0;
+    const int dim = std::min(nq, std::max(0, n_vars - n_rel));
+    const int codim = nq - dim;
+    const double lr_mean = lq / nq;
+    return -codim * std::max(0.0, lr_mean - 1.0);
+}
+
+struct FeatureCtx {
+    std::vector<double> lr;   // log2 resolution per variable
+    explicit FeatureCtx(const SysInfo &si) {
+        for (int64_t r : si.res) lr.push_back(std::log2((double)r));
+    }
+    // qx, qy: children's packs, q: output pack; d*: estimated log2 densities
+    void compute(uint64_t qx, uint64_t qy, uint64_t q, double dx, double dy, double dc, float *f) const {
+        const uint64_t b = q & qx & qy, k = qx & qy & ~q, ex = qx & ~qy, ey = qy & ~qx;
+        const double lb = log2_cost(b, lr), lm = log2_cost(ex, lr), ln = log2_cost(ey, lr), lk = log2_cost(k, lr);
+        const bool gemm = k && ex && ey && lk >= 5.0 && lm >= 5.0 && ln >= 5.0;   // MFMA eligibility (>= 32 each)
+        f[0] = (float)(lb * kLogScale);
+        f[1] = (float)(lm * kLogScale);
+        f[2] = (float)(ln * kLogScale);
+        f[3] = (float)(lk * kLogScale);
+        f[4] = (float)((lb + lm + ln + lk) * kLogScale);            // scope: the step's naive cost
+        f[5] = (float)(log2_cost(q, lr) * kLogScale);              // output cells
+        f[6] = (float)(log2_cost(qx, lr) * kLogScale);
+        f[7] = (float)(log2_cost(qy, lr) * kLogScale);
+        f[8] = gemm ? 1.0f : 0.0f;                                 // path: matrix cores
+        f[9] = (!gemm && k) ? 1.0f : 0.0f;                         //       word streaming over a shared latent axis
+        f[10] = k ? 0.0f : 1.0f;                                   //       no shared latent variable
+        f[11] = (float)(__builtin_popcountll(qx | qy) * 0.25);     // arity of the scope
+        f[12] = (float)(__builtin_popcountll(q) * 0.25);           // arity of the output
+        f[13] = (float)(dx * kLogScale);
+        f[14] = (float)(dy * kLogScale);
+        f[15] = (float)(dc * kLogScale);
+    }
+};
+
+static int popc32(uint32_t x) { return __builtin_popcount(x); }
+
+static uint64_t vars_of(uint32_t S, const SysInfo &si) {
+    uint64_t m = 0;
+    for (int r = 0; r < si.n_rel; ++r)
+        if ((S >> r) & 1) m |= si.rel_vars[r];
+    return m;
+}
+
+void step_features(const SysInfo &si, uint32_t s1, uint32_t s2, float *f) {
+    const FeatureCtx ctx(si);
+    const uint64_t qx = q_of(s1, si), qy = q_of(s2, si), q = q_of(s1 | s2, si);
+    auto dens = [&](uint32_t S, uint64_t qq) {
+        return est_log2_density(popc32(S), __builtin_popcountll(vars_of(S, si)), qq, log2_cost(qq, ctx.lr));
+    };
+    ctx.compute(qx, qy, q, dens(s1, qx), dens(s2, qy), dens(s1 | s2, q), f);
+}
+
+// ------------------------------------------------------------------ model
+static int model_reserve(pa_model *m, int64_t n) {
+    if (n <= m->cap) return PA_OK;
+    for (float **p : {&m->Y, &m->acts, &m->dacts, &m->dY})
+        if (*p) {
+            (void)hipFree(*p);
+            *p = nullptr;
+        }
+    m->cap = 0;
+    const int64_t c = std::max<int64_t>(n, 1024);
+    HIP_TRY(hipMalloc(&m->Y, sizeof(float) * c));
+    HIP_TRY(hipMalloc(&m->dY, sizeof(float) * c));
+    HIP_TRY(hipMalloc(&m->acts, sizeof(float) * c * 2 * kMlpHidden));
+    HIP_TRY(hipMalloc(&m->dacts, sizeof(float) * c * 2 * kMlpHidden));
+    m->cap = c;
+    return PA_OK;
+}
+
+static int check_device(const pa_model *m) {
+    int cur = 0;
+    HIP_TRY(hipGetDevice(&cur));
+    if (cur != m->device) return fail(PA_EINVAL, "model: created on another device");
+    return PA_OK;
+}
+
+// SplitMix64 (Steele, Lea and Flood, 2014) for the initial weights.
+static uint64_t splitmix64(uint64_t &s) {
+    uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Uniform He initialisation: weights in +-sqrt(6 / fan_in), biases zero.
+static std::vector<float> init_params(uint64_t seed) {
+    std::vector<float> p(kMlpParams, 0.0f);
+    uint64_t s = seed;
+    auto fill = [&](int off, int count, int fan_in) {
+        const double a = std::sqrt(6.0 / fan_in);
+        for (int i = 0; i < count; ++i) {
+            const double u = (double)(splitmix64(s) >> 11) * 0x1.0p-53;
+            p[off + i] = (float)((2.0 * u - 1.0) * a);
+        }
+    };
+    const int H = kMlpHidden, F = kMlpFeatures;
+    fill(0, H * F, F);
+    fill(H * F + H, H * H, H);
+    fill(H * F + H + H * H + H, H, H);
+    return p;
+}
+
+static int model_alloc(pa_model *m) {
+    HIP_TRY(hipGetDevice(&m->device));
+    for (float **p : {&m->P, &m->M, &m->V, &m->G}) HIP_TRY(hipMalloc(p, sizeof(float) * kMlpParams));
+    HIP_TRY(hipMalloc(&m->loss, sizeof(float)));
+    HIP_TRY(hipMemset(m->M, 0, sizeof(float) * kMlpParams));
+    HIP_TRY(hipMemset(m->V, 0, sizeof(float) * kMlpParams));
+    return PA_OK;
+}
+
+static int set_params(pa_model *m, const float *host) {
+    HIP_TRY(hipMemcpy(m->P, host, sizeof(float) * kMlpParams, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemset(m->M, 0, sizeof(float) * kMlpParams));
+    HIP_TRY(hipMemset(m->V, 0, sizeof(float) * kMlpParams));
+    m->adam_step = 0;
+    return PA_OK;
+}
+
+// ------------------------------------------------------------------ planner
+// Least predicted total time over binary cluster trees whose every node
+// multiplies two connected clusters (no Kronecker products) when the
+// relation graph is connected, else over all trees.  Candidate steps are
+// scored in chunks by one batched forward pass each.
+int plan_learned(const SysInfo &si, const pa_model *model, Tree &t) {
+    if (!model) return fail(PA_EINVAL, "opts: PA_ORDER_LEARNED needs a model");
+    int rc = check_device(model);
+    if (rc) return rc;
+    const int n = si.n_rel;
+    if (n == 1) return tree_from_merges(si, {}, t);
+    if (n > 16) return plan_greedy(si, t);
+    const uint32_t full = (1u << n) - 1u;
+    std::vector<uint64_t> q((size_t)full + 1), vars((size_t)full + 1);
+    std::vector<double> dens((size_t)full + 1), lq((size_t)full + 1);
+    std::vector<char> conn((size_t)full + 1, 0);
+    const FeatureCtx ctx(si);
+    for (uint32_t S = 1; S <= full; ++S) {
+        const uint32_t low = S & (~S + 1);
+        vars[S] = vars[S ^ low] | si.rel_vars[__builtin_ctz(low)];
+        q[S] = q_of(S, si);
+        lq[S] = log2_cost(q[S], ctx.lr);
+        dens[S] = est_log2_density(popc32(S), __builtin_popcountll(vars[S]), q[S], lq[S]);
+        // connected: grow from the lowest relation through shared variables
+        uint32_t seen = low;
+        uint64_t sv = si.rel_vars[__builtin_ctz(low)];
+        for (bool grew = true; grew;) {
+            grew = false;
+            for (uint32_t rest = S & ~seen; rest; rest &= rest - 1) {
+                const int r = __builtin_ctz(rest);
+                if (si.rel_vars[r] & sv) {
+                    seen |= 1u << r;
+                    sv |= si.rel_vars[r];
+                    grew = true;
+                }
+            }
+        }
+        conn[S] = seen == S;
+    }
+    const bool only_connected = conn[full];
+    auto allowed = [&](uint32_t S1, uint32_t S2) { return !only_connected || (conn[S1] && conn[S2]); };
+    auto considered = [&](uint32_t S) { return !only_connected || conn[S]; };
+
+    // pass 1: predicted log2 duration of every candidate, in enumeration order
+    std::vector<float> pred;
+    {
+        const int64_t chunk = 1 << 18;
+        std::vector<float> feat;
+        feat.reserve((size_t)chunk * kMlpFeatures);
+        float *dX = nullptr, *dY = nullptr;
+        HIP_TRY(hipMalloc(&dX, sizeof(float) * chunk * kMlpFeatures));
+        if (hipMalloc(&dY, sizeof(float) * chunk) != hipSuccess) {
+            (void)hipFree(dX);
+            return fail(PA_EHIP, "learned order: hipMalloc failed");
+        }
+        int err = PA_OK;
+        auto flush = [&]() {
+            const int64_t m = (int64_t)(feat.size() / kMlpFeatures);
+            if (m == 0 || err) return;
+            const size_t at = pred.size();
+            pred.resize(at + (size_t)m);
+            if (hipMemcpy(dX, feat.data(), sizeof(float) * feat.size(), hipMemcpyHostToDevice) != hipSuccess ||
+                mlp_forward(dX, m, model->P, dY, nullptr, nullptr) != hipSuccess ||
+                hipMemcpy(pred.data() + at, dY, sizeof(float) * m, hipMemcpyDeviceToHost) != hipSuccess)
+                err = fail(PA_EHIP, "learned order: inference failed");
+            feat.clear();
+        };
+        float f[kMlpFeatures];
+        for (uint32_t S = 1; S <= full && !err; ++S) {
+            if ((S & (S - 1)) == 0 || !considered(S)) continue;
+            const uint32_t low = S & (~S + 1), rest = S ^ low;
+            for (uint32_t sub = rest;; sub = (sub - 1) & rest) {
+                const uint32_t S1 = sub | low, S2 = S ^ S1;
+                if (S2 && allowed(S1, S2)) {
+                    ctx.compute(q[S1], q[S2], q[S], dens[S1], dens[S2], dens[S], f);
+                    feat.insert(feat.end(), f, f + kMlpFeatures);
+                    if ((int64_t)feat.size() >= chunk * kMlpFeatures) flush();
+                }
+                if (sub == 0) break;
+            }
+        }
+        flush();
+        (void)hipFree(dX);
+        (void)hipFree(dY);
+        if (err) return err;
+    }
+    // pass 2: dynamic program over the same enumeration; intermediates above
+    // kMaxLog2Bits are not considered (the root is the caller's output)
+    const double inf = std::numeric_limits<double>::infinity();
+    std::vector<double> best((size_t)full + 1, inf);
+    std::vector<uint32_t> split((size_t)full + 1, 0);
+    for (int i = 0; i < n; ++i) best[1u << i] = 0.0;
+    size_t ci = 0;
+    for (uint32_t S = 1; S <= full; ++S) {
+        if ((S & (S - 1)) == 0 || !considered(S)) continue;
+        const uint32_t low = S & (~S + 1), rest = S ^ low;
+        for (uint32_t sub = rest;; sub = (sub - 1) & rest) {
+            const uint32_t S1 = sub | low, S2 = S ^ S1;
+            if (S2 && allowed(S1, S2)) {
+                const double c = best[S1] + best[S2] + std::exp2((double)pred[ci++]);
+                if (c < best[S] && (S == full || lq[S] <= kMaxLog2Bits)) {
+                    best[S] = c;
+                    split[S] = S1;
+                }
+            }
+            if (sub == 0) break;
+        }
+    }
+    if (!(best[full] < inf)) return plan_exhaustive(si, t);   // every tree has a larger intermediate
+    std::vector<int> merges;
+    int next = n;
+    struct Rec {
+        static int go(uint32_t S, const std::vector<uint32_t> &split, std::vector<int> &merges, int &next) {
+            if ((S & (S - 1)) == 0) return __builtin_ctz(S);
+            const int a = go(split[S], split, merges, next);
+            const int b = go(S ^ split[S], split, merges, next);
+            merges.push_back(a);
+            merges.push_back(b);
+            return next++;
+        }
+    };
+    Rec::go(full, split, merges, next);
+    rc = tree_from_merges(si, merges, t);
+    if (rc == PA_OK) t.predicted_us = best[full];
+    return rc;
+}
+
+}  // namespace pa
+
+using namespace pa;
+
+extern "C" int32_t pa_model_n_params(void) { return kMlpParams; }
+extern "C" int32_t pa_model_n_features(void) { return kMlpFeatures; }
+
+extern "C" int pa_model_create(uint64_t seed, pa_model **out) {
+    if (!out) return fail(PA_EINVAL, "model_create: null pointer");
+    *out = nullptr;
+    pa_model *m = new pa_model();
+    int rc = model_alloc(m);
+    if (rc == PA_OK) {
+        const std::vector<float> p = init_params(seed);
+        rc = set_params(m, p.data());
+    }
+    if (rc) {
+        delete m;
+        return rc;
+    }
+    *out = m;
+    return PA_OK;
+}
+
+extern "C" void pa_model_destroy(pa_model *m) { delete m; }
+
+extern "C" int pa_model_get_params(const pa_model *m, float *host, int32_t n) {
+    if (!m || !host) return fail(PA_EINVAL, "model_get_params: null pointer");
+    if (n != kMlpParams) return fail(PA_EINVAL, "model_get_params: need " + std::to_string(kMlpParams) + " floats");
+    int rc = check_device(m);
+    if (rc) return rc;
+    HIP_TRY(hipMemcpy(host, m->P, sizeof(float) * kMlpParams, hipMemcpyDeviceToHost));
+    return PA_OK;
+}
+
+extern "C" int pa_model_set_params(pa_model *m, const float *host, int32_t n) {
+    if (!m || !host) return fail(PA_EINVAL, "model_set_params: null pointer");
+    if (n != kMlpParams) return fail(PA_EINVAL, "model_set_params: need " + std::to_string(kMlpParams) + " floats");
+    for (int i = 0; i < n; ++i)
+        if (!std::isfinite(host[i])) return fail(PA_EINVAL, "model_set_params: non-finite parameter");
+    int rc = check_device(m);
+    if (rc) return rc;
+    return set_params(m, host);
+}
+
+extern "C" int pa_model_forward(pa_model *m, const float *X, int64_t n, float *Y, void *stream) {
+    if (!m || (n > 0 && (!X || !Y))) return fail(PA_EINVAL, "model_forward: null pointer");
+    if (n < 0) return fail(PA_EINVAL, "model_forward: negative batch");
+    int rc = check_device(m);
+    if (rc) return rc;
+    HIP_TRY(mlp_forward(X, n, m->P, Y, nullptr, static_cast<hipStream_t>(stream)));
+    return PA_OK;
+}
+
+extern "C" int pa_model_gradient(pa_model *m, const float *X, const float *T, int64_t n, float *grad, float *loss,
+                                 void *stream) {
+    if (!m || !X || !T) return fail(PA_EINVAL, "model_gradient: null pointer");
+    if (n < 1) return fail(PA_EINVAL, "model_gradient: empty batch");
+    int rc = check_device(m);
+    if (!rc) rc = model_reserve(m, n);
+    if (rc) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIP_TRY(mlp_grad(X, T, n, m->P, m->Y, m->acts, m->dacts, m->dY, m->G, m->loss, s));
+    if (grad) HIP_TRY(hipMemcpyAsync(grad, m->G, sizeof(float) * kMlpParams, hipMemcpyDeviceToDevice, s));
+    if (loss) {
+        HIP_TRY(hipMemcpyAsync(loss, m->loss, sizeof(float), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    }
+    return PA_OK;
+}
+
+extern "C" int pa_model_train_step(pa_model *m, const float *X, const float *T, int64_t n, float lr, float *loss,
+                                   void *stream) {
+    if (!(lr > 0.0f) || !std::isfinite(lr)) return fail(PA_EINVAL, "model_train_step: learning rate must be > 0");
+    int rc = pa_model_gradient(m, X, T, n, nullptr, nullptr, stream);
+    if (rc) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    m->adam_step += 1;
+    HIP_TRY(mlp_adam(m->P, m->G, m->M, m->V, lr, 0.9f, 0.999f, 1e-8f, m->adam_step, s));
+    if (loss) {   // loss of the batch before this update
+        HIP_TRY(hipMemcpyAsync(loss, m->loss, sizeof(float), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    }
+    return PA_OK;
+}
+
+// File format: one line of JSON, a newline, then the parameters as
+// little-endian float32 in the flat layout.
+extern "C" int pa_model_save(const pa_model *m, const char *path) {
+    if (!m || !path) return fail(PA_EINVAL, "model_save: null pointer");
+    std::vector<float> p(kMlpParams);
+    int rc = pa_model_get_params(m, p.data(), kMlpParams);
+    if (rc) return rc;
+    FILE *f = std::fopen(path, "wb");
+    if (!f) return fail(PA_EINVAL, std::string("model_save: cannot open ") + path);
+    const std::string hdr = "{\"format\": \"pa-order-mlp\", \"version\": 1, \"features\": " +
+                            std::to_string(kMlpFeatures) + ", \"hidden\": " + std::to_string(kMlpHidden) +
+                            ", \"params\": " + std::to_string(kMlpParams) + ", \"adam_steps\": " +
+                            std::to_string(m->adam_step) + "}\n";
+    bool ok = std::fwrite(hdr.data(), 1, hdr.size(), f) == hdr.size();
+    ok = ok && std::fwrite(p.data(), sizeof(float), p.size(), f) == p.size();
+    ok = (std::fclose(f) == 0) && ok;
+    return ok ? PA_OK : fail(PA_EINVAL, std::string("model_save: write failed: ") + path);
+}
+
+extern "C" int pa_model_load(const char *path, pa_model **out) {
+    if (!path || !out) return fail(PA_EINVAL, "model_load: null pointer");
+    *out = nullptr;
+    FILE *f = std::fopen(path, "rb");
+    if (!f) return fail(PA_EINVAL, std::string("model_load: cannot open ") + path);
+    std::string hdr;
+    for (int c; (c = std::fgetc(f)) != EOF && c != '\n' && hdr.size() < 4096;) hdr.push_back((char)c);
+    const std::string want = "\"params\": " + std::to_string(kMlpParams);
+    std::vector<float> p(kMlpParams);
+    const bool ok = hdr.find("\"format\": \"pa-order-mlp\"") != std::string::npos &&
+                    hdr.find(want) != std::string::npos &&
+                    std::fread(p.data(), sizeof(float), p.size(), f) == p.size() && std::fgetc(f) == EOF;
+    std::fclose(f);
+    if (!ok) return fail(PA_EINVAL, std::string("model_load: not a model file of this shape: ") + path);
+    pa_model *m = nullptr;
+    int rc = pa_model_create(0, &m);
+    if (!rc) rc = pa_model_set_params(m, p.data(), kMlpParams);
+    if (rc) {
+        delete m;
+        return rc;
+    }
+    *out = m;
+    return PA_OK;
+}
+
+extern "C" int pa_step_features(const pa_system *sys, const int32_t *exposed, int32_t n_exposed, uint32_t s1,
+                                uint32_t s2, float *features) {
+    if (!features) return fail(PA_EINVAL, "step_features: null output");
+    SysInfo si;
+    int rc = build_sysinfo(sys, exposed, n_exposed, si);
+    if (rc) return rc;
+    const uint32_t all = si.n_rel == 32 ? 0xffffffffu : ((1u << si.n_rel) - 1u);
+    if (!s1 || !s2 || (s1 & s2) || ((s1 | s2) & ~all)) return fail(PA_EINVAL, "step_features: bad relation sets");
+    step_features(si, s1, s2, features);
+    return PA_OK;
+}
+
+extern "C" int32_t pa_plan_step_samples(pa_plan *P, float *features, float *log2_us, int32_t cap) {
+    if (!P) return fail(PA_EINVAL, "step_samples: null plan"), -1;
+    if (!P->per_op || P->op_events.empty() || !P->op_events_recorded)
+        return fail(PA_EINVAL, "step_samples: need a plan with per_op = 1 and timing = 2, executed"), -1;
+    if (hipEventSynchronize(P->op_events.back()) != hipSuccess) return fail(PA_EHIP, "step_samples: sync"), -1;
+    const int n = P->si.n_rel;
+    std::vector<double> ms(P->tree.nodes.size(), 0.0);
+    for (size_t oi = 0; oi < P->ops.size(); ++oi) {
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, P->op_events[2 + 2 * oi], P->op_events[3 + 2 * oi]) != hipSuccess)
+            return fail(PA_EHIP, "step_samples: event timing"), -1;
+        const int node = P->ops[oi].node;
+        if (node >= 0) ms[node] += t;
+    }
+    int32_t k = 0;
+    for (size_t id = n; id < P->tree.nodes.size(); ++id) {
+        const Node &nd = P->tree.nodes[id];
+        if (k < cap) {
+            if (features)
+                step_features(P->si, P->tree.nodes[nd.c0].leaves, P->tree.nodes[nd.c1].leaves,
+                              features + (size_t)k * kMlpFeatures);
+            if (log2_us) log2_us[k] = (float)std::log2(std::max(ms[id] * 1e3, 1e-3));
+        }
+        ++k;
+    }
+    return k;
+}

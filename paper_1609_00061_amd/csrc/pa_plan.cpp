@@ -1196,7 +1196,7 @@ extern "C" int64_t pa_plan_describe(const pa_system *sys, const int32_t *exposed
     } else {
         s << "{\"merges\":" << join(std::vector<int>(P->tree.merges.begin(), P->tree.merges.end()))
           << ",\"cost\":" << P->tree.cost << ",\"workspace_bytes\":" << P->ws_bytes << ",\"corners\":" << P->corners
-          << ",\"total_macs\":" << P->total_macs
+          << ",\"total_macs\":" << P->total_macs << ",\"predicted_us\":" << P->tree.predicted_us
           << ",\"plots\":[";
         for (size_t i = 0; i < P->plots.size(); ++i)
             s << (i ? "," : "") << "{\"rel\":" << P->plots[i].rel << ",\"buf\":" << P->plots[i].buf

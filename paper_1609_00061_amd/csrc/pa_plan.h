@@ -58,6 +58,7 @@ struct Tree {
     int root = -1;
     std::vector<int> merges;      // PA_ORDER_GIVEN format
     double cost = 0.0;            // sum of node costs (eqn naive_cost)
+    double predicted_us = 0.0;    // learned order: the model's predicted total step time
 };
 
 struct SysInfo {

@@ -224,11 +224,4 @@ int plan_exhaustive(const SysInfo &si, Tree &t) {
     return tree_from_merges(si, merges, t);
 }
 
-int plan_learned(const SysInfo &si, const pa_model *model, Tree &t) {
-    (void)si;
-    (void)t;
-    if (!model) return fail(PA_EINVAL, "opts: PA_ORDER_LEARNED needs a model");
-    return fail(PA_EUNSUPPORTED, "learned order: no model support in this build");
-}
-
 }  // namespace pa

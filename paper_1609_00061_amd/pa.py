@@ -21,6 +21,7 @@ OPKIND_BITS, OPKIND_STREAM_K, OPKIND_STREAM_W, OPKIND_GEMM, OPKIND_FILL, OPKIND_
     0, 1, 2, 10, 20, 30, 40
 PLOT_FP32_ESCALATE, PLOT_FP64 = 0, 1
 MAX_DIMS, MAX_RELATIONS = 12, 32
+MODEL_FEATURES = 16
 
 STATUS_NAMES = {0: "PA_OK", 1: "PA_EINVAL", 2: "PA_ENOMEM", 3: "PA_EHIP", 4: "PA_EUNSUPPORTED"}
 
@@ -123,6 +124,22 @@ def load(path: str = LIB_PATH):
     L.pa_batch_destroy.restype = None
     L.pa_solve_batch.argtypes = [ctypes.POINTER(System), ctypes.c_int32, ctypes.POINTER(ctypes.POINTER(ctypes.c_int32)),
                                  i32p, ctypes.POINTER(Opts), ctypes.POINTER(BitArray), ctypes.POINTER(ctypes.c_int64), vp]
+    fp = ctypes.POINTER(ctypes.c_float)
+    L.pa_model_n_params.restype = ctypes.c_int32
+    L.pa_model_n_features.restype = ctypes.c_int32
+    L.pa_model_create.argtypes = [ctypes.c_uint64, ctypes.POINTER(vp)]
+    L.pa_model_destroy.argtypes = [vp]
+    L.pa_model_destroy.restype = None
+    L.pa_model_get_params.argtypes = [vp, fp, ctypes.c_int32]
+    L.pa_model_set_params.argtypes = [vp, fp, ctypes.c_int32]
+    L.pa_model_forward.argtypes = [vp, vp, ctypes.c_int64, vp, vp]
+    L.pa_model_gradient.argtypes = [vp, vp, vp, ctypes.c_int64, vp, fp, vp]
+    L.pa_model_train_step.argtypes = [vp, vp, vp, ctypes.c_int64, ctypes.c_float, fp, vp]
+    L.pa_model_save.argtypes = [vp, ctypes.c_char_p]
+    L.pa_model_load.argtypes = [ctypes.c_char_p, ctypes.POINTER(vp)]
+    L.pa_step_features.argtypes = [ctypes.POINTER(System), i32p, ctypes.c_int32, ctypes.c_uint32, ctypes.c_uint32, fp]
+    L.pa_plan_step_samples.argtypes = [vp, fp, fp, ctypes.c_int32]
+    L.pa_plan_step_samples.restype = ctypes.c_int32
     _lib = L
     return L
 
@@ -393,6 +410,94 @@ class Batch:
         try:
             if getattr(self, "handle", None) and _lib is not None:
                 _lib.pa_batch_destroy(self.handle)
+                self.handle = None
+        except Exception:
+            pass
+
+
+def step_features(system, s1: int, s2: int, exposed=None) -> np.ndarray:
+    """Host-only: features of the step multiplying relation sets s1 and s2 (bit masks)."""
+    L = load()
+    keep = _Keep()
+    exposed = list(system.exposed if exposed is None else exposed)
+    s = _system(keep, system)
+    f = np.zeros(MODEL_FEATURES, dtype=np.float32)
+    _check(L.pa_step_features(ctypes.byref(s), keep.i32(exposed), len(exposed), s1, s2,
+                              f.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+    return f
+
+
+def plan_step_samples(plan: "Plan"):
+    """(features [k, F] float32, log2 microseconds [k]) of the last execute of a
+    plan created with per_op=True, timing=2."""
+    L = load()
+    cap = 64
+    X = np.zeros((cap, MODEL_FEATURES), dtype=np.float32)
+    T = np.zeros(cap, dtype=np.float32)
+    n = L.pa_plan_step_samples(plan.handle, X.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                               T.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), cap)
+    if n < 0:
+        _check(PA_EINVAL)
+    return X[:n].copy(), T[:n].copy()
+
+
+class Model:
+    """The learned step-time model (device-resident MLP)."""
+
+    def __init__(self, seed: int = 0, path: Optional[str] = None):
+        L = load()
+        h = ctypes.c_void_p()
+        if path is not None:
+            _check(L.pa_model_load(os.fsencode(path), ctypes.byref(h)))
+        else:
+            _check(L.pa_model_create(ctypes.c_uint64(seed), ctypes.byref(h)))
+        self.handle = h
+        self.n_params = int(L.pa_model_n_params())
+
+    def get_params(self) -> np.ndarray:
+        p = np.zeros(self.n_params, dtype=np.float32)
+        _check(load().pa_model_get_params(self.handle, p.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                          self.n_params))
+        return p
+
+    def set_params(self, p) -> None:
+        p = np.ascontiguousarray(np.asarray(p, dtype=np.float32))
+        _check(load().pa_model_set_params(self.handle, p.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), p.size))
+
+    def forward(self, X, stream=None):
+        """X: torch float32 [n, F] on the device -> torch float32 [n]."""
+        import torch
+        X = X.contiguous()
+        Y = torch.empty(X.shape[0], dtype=torch.float32, device=X.device)
+        _check(load().pa_model_forward(self.handle, ctypes.c_void_p(X.data_ptr()), X.shape[0],
+                                       ctypes.c_void_p(Y.data_ptr()), _stream_ptr(stream)))
+        return Y
+
+    def gradient(self, X, T, stream=None):
+        """(gradient torch float32 [n_params], loss) of the mean squared error."""
+        import torch
+        X, T = X.contiguous(), T.contiguous()
+        G = torch.empty(self.n_params, dtype=torch.float32, device=X.device)
+        loss = ctypes.c_float(0.0)
+        _check(load().pa_model_gradient(self.handle, ctypes.c_void_p(X.data_ptr()), ctypes.c_void_p(T.data_ptr()),
+                                        X.shape[0], ctypes.c_void_p(G.data_ptr()), ctypes.byref(loss),
+                                        _stream_ptr(stream)))
+        return G, float(loss.value)
+
+    def train_step(self, X, T, lr=1e-3, stream=None, want_loss=False):
+        loss = ctypes.c_float(0.0)
+        _check(load().pa_model_train_step(self.handle, ctypes.c_void_p(X.data_ptr()), ctypes.c_void_p(T.data_ptr()),
+                                          X.shape[0], ctypes.c_float(lr),
+                                          ctypes.byref(loss) if want_loss else None, _stream_ptr(stream)))
+        return float(loss.value) if want_loss else None
+
+    def save(self, path: str) -> None:
+        _check(load().pa_model_save(self.handle, os.fsencode(path)))
+
+    def __del__(self):
+        try:
+            if getattr(self, "handle", None) and _lib is not None:
+                _lib.pa_model_destroy(self.handle)
                 self.handle = None
         except Exception:
             pass
