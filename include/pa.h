@@ -145,6 +145,11 @@ typedef struct {
     const pa_model *model;    /* PA_ORDER_LEARNED: the cost model                   */
     void *workspace;          /* optional device workspace (NULL: library-owned)    */
     size_t workspace_bytes;
+    int32_t autotune;         /* 1: pa_plan_create / pa_batch_create take the executor
+                                 settings (single_launch, persist_wg, plot_strip,
+                                 contract_units) from the autotuner: cached per
+                                 workload structure and GPU architecture, tuned by
+                                 timing on the device (stream 0) on a cache miss */
 } pa_opts;
 
 typedef struct {
@@ -309,6 +314,26 @@ int pa_step_features(const pa_system *sys, const int32_t *exposed, int32_t n_exp
  * microseconds (the sum of the step's op launches, from HIP events).  Waits
  * for the events.  Returns the number of steps, or -1 (see pa_last_error). */
 int32_t pa_plan_step_samples(pa_plan *plan, float *features, float *log2_us, int32_t cap);
+
+/* ---------------------------------------------------------- autotuning
+ * Executor settings for a workload (one system: n_sys = 1), chosen by timing
+ * candidates on the device: first the executor (grouped launches, or one
+ * persistent launch with 256/512/1024/2048 workgroups), then the plot strip
+ * length (1/2/4/8 cells per thread), then the streaming tile (512..32768
+ * output bits), each from the best so far.  Every candidate is a batch built
+ * with opts (graph capture included if opts->graph), executed once untimed,
+ * then reps times between two events on `stream`.  Candidates that exceed
+ * the workspace cap are skipped.  best gets the fastest; tried (may be NULL)
+ * up to cap of the candidates in order, *n_tried their count.  The result is
+ * also cached for opts->autotune.  Allocates outputs and workspaces while
+ * tuning; synchronizes the stream. */
+typedef struct {
+    int32_t single_launch, persist_wg, plot_strip, contract_units;
+    double ms;                /* milliseconds per execution of the whole workload */
+} pa_tuning;
+int pa_autotune(const pa_system *systems, int32_t n_sys, const int32_t *const *exposed, const int32_t *n_exposed,
+                const pa_opts *opts, int32_t reps, pa_tuning *best, pa_tuning *tried, int32_t cap, int32_t *n_tried,
+                void *stream);
 
 /* pa_plan_create + pa_plan_execute + pa_plan_destroy. */
 int pa_solve_system(const pa_system *sys, const int32_t *exposed, int32_t n_exposed, const pa_opts *opts,

@@ -82,6 +82,10 @@ extern "C" int pa_batch_create(const pa_system *systems, int32_t n_sys, const in
     pa_opts o{};
     if (opts) o = *opts;
     if (o.plain || o.per_op) return fail(PA_EINVAL, "batch_create: batches run on the step executors (no plain/per_op)");
+    if (o.autotune) {
+        int rc = autotuned_opts(systems, n_sys, exposed, n_exposed, o);
+        if (rc) return rc;
+    }
     if (o.timing == 2) o.timing = 0;       // op events live on the merged plan, below
     std::unique_ptr<pa_batch> B(new pa_batch());
     size_t off = 0;

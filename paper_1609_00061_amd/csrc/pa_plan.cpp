@@ -1027,6 +1027,13 @@ extern "C" int pa_plan_create(const pa_system *sys, const int32_t *exposed, int3
     if (!plan) return fail(PA_EINVAL, "plan_create: null plan pointer");
     *plan = nullptr;
     std::unique_ptr<pa_plan> P(new pa_plan());
+    pa_opts tuned{};
+    if (opts && opts->autotune && !opts->plain && !opts->per_op && sys) {
+        tuned = *opts;
+        int rc = autotuned_opts(sys, 1, &exposed, &n_exposed, tuned);
+        if (rc) return rc;
+        opts = &tuned;
+    }
     int rc = build_plan(sys, exposed, n_exposed, opts, P.get());
     if (rc) return rc;
     if (opts && opts->workspace) {

@@ -59,7 +59,16 @@ class Opts(ctypes.Structure):
                 ("per_op", ctypes.c_int32), ("graph", ctypes.c_int32), ("single_launch", ctypes.c_int32),
                 ("persist_wg", ctypes.c_int32),
                 ("plot_strip", ctypes.c_int32), ("contract_units", ctypes.c_int32),
-                ("model", ctypes.c_void_p), ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t)]
+                ("model", ctypes.c_void_p), ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
+                ("autotune", ctypes.c_int32)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("single_launch", ctypes.c_int32), ("persist_wg", ctypes.c_int32), ("plot_strip", ctypes.c_int32),
+                ("contract_units", ctypes.c_int32), ("ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class Report(ctypes.Structure):
@@ -140,6 +149,9 @@ def load(path: str = LIB_PATH):
     L.pa_step_features.argtypes = [ctypes.POINTER(System), i32p, ctypes.c_int32, ctypes.c_uint32, ctypes.c_uint32, fp]
     L.pa_plan_step_samples.argtypes = [vp, fp, fp, ctypes.c_int32]
     L.pa_plan_step_samples.restype = ctypes.c_int32
+    L.pa_autotune.argtypes = [ctypes.POINTER(System), ctypes.c_int32, ctypes.POINTER(ctypes.POINTER(ctypes.c_int32)),
+                              i32p, ctypes.POINTER(Opts), ctypes.c_int32, ctypes.POINTER(Tuning),
+                              ctypes.POINTER(Tuning), ctypes.c_int32, i32p, vp]
     _lib = L
     return L
 
@@ -190,7 +202,8 @@ def _system(keep, system) -> System:
 
 def make_opts(order=ORDER_EXHAUSTIVE, precision=PLOT_FP32_ESCALATE, audit=False, timing=False, plain=False,
               given: Optional[Sequence[int]] = None, model=None, keep: Optional[_Keep] = None, per_op=False,
-              graph=False, single_launch=False, persist_wg=0, plot_strip=0, contract_units=0) -> Opts:
+              graph=False, single_launch=False, persist_wg=0, plot_strip=0, contract_units=0,
+              autotune=False) -> Opts:
     o = Opts()
     o.order_policy = order
     o.precision = precision
@@ -203,6 +216,7 @@ def make_opts(order=ORDER_EXHAUSTIVE, precision=PLOT_FP32_ESCALATE, audit=False,
     o.persist_wg = int(persist_wg)
     o.plot_strip = int(plot_strip)
     o.contract_units = int(contract_units)
+    o.autotune = int(autotune)
     if given is not None:
         assert keep is not None
         o.n_given = len(given) // 2
@@ -501,6 +515,27 @@ class Model:
                 self.handle = None
         except Exception:
             pass
+
+
+def autotune(systems, reps=3, stream=None, **opts_kw):
+    """Time the executor candidates for a workload (list of systems); returns
+    (best dict, [tried dicts])."""
+    L = load()
+    keep = _Keep()
+    systems = list(systems)
+    arr = (System * len(systems))(*[_system(keep, s) for s in systems])
+    exps = [keep.i32(list(s.exposed)) for s in systems]
+    exp_ptrs = (ctypes.POINTER(ctypes.c_int32) * len(exps))(*[ctypes.cast(e, ctypes.POINTER(ctypes.c_int32)) for e in exps])
+    n_exp = keep.i32([len(s.exposed) for s in systems])
+    keep.items += [arr, exp_ptrs]
+    opts = make_opts(keep=keep, **opts_kw)
+    best = Tuning()
+    cap = 32
+    tried = (Tuning * cap)()
+    n = ctypes.c_int32(0)
+    _check(L.pa_autotune(arr, len(systems), exp_ptrs, n_exp, ctypes.byref(opts), reps, ctypes.byref(best), tried,
+                         cap, ctypes.cast(ctypes.byref(n), ctypes.POINTER(ctypes.c_int32)), _stream_ptr(stream)))
+    return best.as_dict(), [tried[i].as_dict() for i in range(min(n.value, cap))]
 
 
 def solve_system(system, exposed=None, **kw):
