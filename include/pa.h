@@ -226,6 +226,18 @@ enum { PA_OPKIND_BITS = 0, PA_OPKIND_STREAM_K = 1, PA_OPKIND_STREAM_W = 2, PA_OP
        PA_OPKIND_FILL = 20, PA_OPKIND_PLOT = 30, PA_OPKIND_PERSIST = 40 };
 int32_t pa_plan_op_times(pa_plan *plan, double *ms, int32_t *kind, double *macs, int32_t cap);
 
+/* Kernel duration of every grouped launch of a plan on the default
+ * (level-grouped) executor, after at least one pa_plan_execute: for each
+ * group in order, reps back-to-back launches of that group on `stream`
+ * between two HIP events; ms[i] = elapsed / reps (so it includes the
+ * dispatch gap between consecutive launches, not the event overhead of a
+ * single launch).  Every group is idempotent given its inputs, so the
+ * plan's output is unchanged; the plot flag counters accumulate.  kind[i]
+ * and macs[i] as for pa_plan_op_times.  Synchronizes.  Returns the number of
+ * groups, or -1 (see pa_last_error). */
+int32_t pa_plan_time_groups(pa_plan *plan, int32_t reps, double *ms, int32_t *kind, double *macs, int32_t cap,
+                            void *stream);
+
 /* ---------------------------------------------------------- batches
  * Many independent systems solved together: each is planned on its own, all
  * share one workspace, and their steps are merged into one table sorted by
@@ -246,6 +258,9 @@ size_t pa_batch_workspace_bytes(const pa_batch *batch);
 /* As pa_plan_op_times, for a batch created with opts->timing == 2: one entry
  * per grouped launch (kind and summed macs of its steps). */
 int32_t pa_batch_op_times(pa_batch *batch, double *ms, int32_t *kind, double *macs, int32_t cap);
+/* As pa_plan_time_groups, for the batch's merged step table. */
+int32_t pa_batch_time_groups(pa_batch *batch, int32_t reps, double *ms, int32_t *kind, double *macs, int32_t cap,
+                             void *stream);
 void pa_batch_destroy(pa_batch *batch);
 /* pa_batch_create + pa_batch_execute + pa_batch_destroy (synchronizes). */
 int pa_solve_batch(const pa_system *systems, int32_t n_sys, const int32_t *const *exposed, const int32_t *n_exposed,

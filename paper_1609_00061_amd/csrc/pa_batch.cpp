@@ -225,6 +225,12 @@ extern "C" int32_t pa_batch_op_times(pa_batch *B, double *ms, int32_t *kind, dou
     return pa_plan_op_times(&B->master, ms, kind, macs, cap);
 }
 
+extern "C" int32_t pa_batch_time_groups(pa_batch *B, int32_t reps, double *ms, int32_t *kind, double *macs,
+                                        int32_t cap, void *stream) {
+    if (!B) return fail(PA_EINVAL, "time_groups: null batch"), -1;
+    return time_groups(&B->master, reps, ms, kind, macs, cap, static_cast<hipStream_t>(stream));
+}
+
 extern "C" void pa_batch_destroy(pa_batch *B) { delete B; }
 
 extern "C" int pa_solve_batch(const pa_system *systems, int32_t n_sys, const int32_t *const *exposed,

@@ -1105,6 +1105,50 @@ extern "C" int32_t pa_plan_op_times(pa_plan *P, double *ms, int32_t *kind, doubl
     return n;
 }
 
+namespace pa {
+int time_groups(pa_plan *P, int32_t reps, double *ms, int32_t *kind, double *macs, int32_t cap, hipStream_t s) {
+    if (P->per_op || P->single_launch || P->groups.empty() || P->last_outs.empty())
+        return fail(PA_EINVAL, "time_groups: need an executed plan on the grouped executor"), -1;
+    if (reps < 1) return fail(PA_EINVAL, "time_groups: reps must be >= 1"), -1;
+    char *base = static_cast<char *>(P->ws.ptr);
+    const PStep *d_steps = reinterpret_cast<const PStep *>(base + P->steps_off);
+    PlotCounters *cnt = reinterpret_cast<PlotCounters *>(base + P->counters_off);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return fail(PA_EHIP, "time_groups: event creation failed"), -1;
+    int rc = PA_OK;
+    const int32_t n = (int32_t)P->groups.size();
+    for (int32_t gi = 0; gi < n && !rc; ++gi) {
+        const auto &g = P->groups[gi];
+        if (hipEventRecord(e0, s) != hipSuccess) rc = fail(PA_EHIP, "time_groups: event record failed");
+        for (int r = 0; r < reps && !rc; ++r)
+            if (launch_group(g.kind, g.mode, d_steps, g.first, g.count, g.t0, g.t1, cnt, s) != hipSuccess)
+                rc = fail(PA_EHIP, "time_groups: launch failed");
+        float t = 0.f;
+        if (!rc && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                    hipEventElapsedTime(&t, e0, e1) != hipSuccess))
+            rc = fail(PA_EHIP, "time_groups: event timing failed");
+        if (!rc && gi < cap) {
+            if (ms) ms[gi] = (double)t / reps;
+            if (kind) kind[gi] = g.kind == kStepPlot ? PA_OPKIND_PLOT
+                                 : g.kind == kStepGemm ? PA_OPKIND_GEMM : g.kind == kStepFill ? PA_OPKIND_FILL : g.mode;
+            double mc = 0.0;
+            for (int j = g.first; j < g.first + g.count; ++j) mc += P->step_macs[j];
+            if (macs) macs[gi] = mc;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return rc ? -1 : n;
+}
+}  // namespace pa
+
+extern "C" int32_t pa_plan_time_groups(pa_plan *P, int32_t reps, double *ms, int32_t *kind, double *macs, int32_t cap,
+                                       void *stream) {
+    if (!P) return fail(PA_EINVAL, "time_groups: null plan"), -1;
+    return time_groups(P, reps, ms, kind, macs, cap, static_cast<hipStream_t>(stream));
+}
+
 extern "C" size_t pa_plan_workspace_bytes(const pa_plan *plan) { return plan ? plan->ws_bytes : 0; }
 
 extern "C" void pa_plan_destroy(pa_plan *plan) { delete plan; }

@@ -116,6 +116,7 @@ int build_plan(const pa_system *sys, const int32_t *exposed, int32_t n_exposed, 
 int upload_plan(pa_plan *P);
 int exec_steps(pa_plan *P, const std::vector<void *> &outs, hipStream_t s, int *launches);
 int plan_workspace_cap(size_t *cap);
+int time_groups(pa_plan *P, int32_t reps, double *ms, int32_t *kind, double *macs, int32_t cap, hipStream_t s);
 int autotuned_opts(const pa_system *systems, int32_t n_sys, const int32_t *const *exposed, const int32_t *n_exposed,
                    pa_opts &o);
 void make_groups(pa_plan *P);

@@ -149,6 +149,10 @@ def load(path: str = LIB_PATH):
     L.pa_step_features.argtypes = [ctypes.POINTER(System), i32p, ctypes.c_int32, ctypes.c_uint32, ctypes.c_uint32, fp]
     L.pa_plan_step_samples.argtypes = [vp, fp, fp, ctypes.c_int32]
     L.pa_plan_step_samples.restype = ctypes.c_int32
+    for fn in (L.pa_plan_time_groups, L.pa_batch_time_groups):
+        fn.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32),
+                       ctypes.POINTER(ctypes.c_double), ctypes.c_int32, vp]
+        fn.restype = ctypes.c_int32
     L.pa_autotune.argtypes = [ctypes.POINTER(System), ctypes.c_int32, ctypes.POINTER(ctypes.POINTER(ctypes.c_int32)),
                               i32p, ctypes.POINTER(Opts), ctypes.c_int32, ctypes.POINTER(Tuning),
                               ctypes.POINTER(Tuning), ctypes.c_int32, i32p, vp]
@@ -222,7 +226,8 @@ def make_opts(order=ORDER_EXHAUSTIVE, precision=PLOT_FP32_ESCALATE, audit=False,
         o.n_given = len(given) // 2
         o.given = keep.i32(given)
     if model is not None:
-        o.model = ctypes.c_void_p(model.handle if hasattr(model, "handle") else model)
+        h = model.handle if hasattr(model, "handle") else model
+        o.model = h.value if isinstance(h, ctypes.c_void_p) else h
     return o
 
 
@@ -319,6 +324,17 @@ def describe_plan(system, exposed=None, order=ORDER_EXHAUSTIVE, precision=PLOT_F
     return json.loads(buf.value.decode())
 
 
+def _time_groups(fn, handle, reps, stream):
+    cap = 4096
+    ms = (ctypes.c_double * cap)()
+    kd = (ctypes.c_int32 * cap)()
+    mc = (ctypes.c_double * cap)()
+    n = fn(handle, reps, ms, kd, mc, cap, _stream_ptr(stream))
+    if n < 0:
+        _check(PA_EINVAL)
+    return [(int(kd[i]), float(ms[i]), float(mc[i])) for i in range(min(n, cap))]
+
+
 class Plan:
     """A planned solve: pa_plan_create once, execute many times."""
 
@@ -360,6 +376,11 @@ class Plan:
         if n < 0:
             _check(PA_EINVAL)
         return [(int(kd[i]), float(ms[i]), float(mc[i])) for i in range(min(n, cap))]
+
+    def time_groups(self, reps=20, stream=None):
+        """[(kind, ms per launch, macs)] of every grouped launch, each timed
+        over `reps` back-to-back launches (plan executed at least once)."""
+        return _time_groups(load().pa_plan_time_groups, self.handle, reps, stream)
 
     def __del__(self):
         try:
@@ -419,6 +440,9 @@ class Batch:
         if n < 0:
             _check(PA_EINVAL)
         return [(int(kd[i]), float(ms[i]), float(mc[i])) for i in range(min(n, cap))]
+
+    def time_groups(self, reps=20, stream=None):
+        return _time_groups(load().pa_batch_time_groups, self.handle, reps, stream)
 
     def __del__(self):
         try:
