@@ -1,17 +1,20 @@
 #!/usr/bin/env python3
 """Benchmark of the pixel-array hot path on one MI355X.
 
-Workload: the chain system -- 8 binary cubic relations f_i(x_i, x_{i+1}) = 0
-with N(0,1) coefficients, box [-3,3]^9 at 1024 cells per axis, x_1 and x_9
-exposed, 7 latent variables (synthetic, seeded).  One step = one whole solve
-from device-resident coefficient and axis tables to the device output bits:
-plotting of all 8 relations (FP32 with FP64 escalation) and the 7 Boolean
-1024^3 contractions on int8 MFMA.
+Workload (the JSON line's `value`): the chain system -- 8 binary cubic
+relations f_i(x_i, x_{i+1}) = 0 with N(0,1) coefficients, box [-3,3]^9 at 1024
+cells per axis, x_1 and x_9 exposed, 7 latent variables (synthetic, seeded).
+One step = one whole solve from device-resident coefficient and axis tables
+to the device output bits: plotting of all 8 relations (FP32 with FP64
+escalation) and the 7 Boolean 1024^3 contractions on int8 MFMA, replayed as
+one hipGraph of level-grouped launches with autotuned tiles.
 
-Prints one JSON line: solves/s of the planned path, the plain GPU path beside
-it, contraction TOP/s, the roofline of the dominant kernel (the MFMA
-contraction, per-launch duration from HIP events on the execution stream),
-and the CPU oracle timed on a bounded sample of the same workload.
+Beside it: the plain GPU path on the same system, the single persistent
+launch, the batched workload (512 chains of 2-6 relations at 64..2048 cells
+per axis in one graph replay vs one plain solve per system), per-kernel
+durations and the roofline of the dominant kernel (HIP events around
+back-to-back launches of each grouped kernel on the execution stream), and
+the CPU oracle timed on a bounded sample of the chain workload.
 """
 import argparse
 import json
@@ -23,6 +26,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 INT8_DENSE_PEAK_TOPS = 5000.0      # MI355X dense int8 MFMA, 5.0 POP/s
+FP32_VECTOR_PEAK_TFLOPS = 157.3
 HBM_PEAK_GBS = 8000.0
 
 
@@ -38,25 +42,111 @@ def _time_plan(plan, out, steps, warmup, stream=None):
     return time.perf_counter() - t0
 
 
-def _op_profile(system, steps, **plan_kw):
-    """Average per-launch durations by kernel kind, from HIP events recorded
-    around every op on the execution stream."""
+def _step_percentiles(plan, out, stream, n):
+    """Per-solve durations from an event pair around each graph replay."""
+    import numpy as np
+    import torch
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
+    for e0, e1 in evs:
+        e0.record(stream)
+        plan.execute(out, stream=stream)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    ms = np.array([e0.elapsed_time(e1) for e0, e1 in evs])
+    return {"p10": float(np.percentile(ms, 10)), "p50": float(np.percentile(ms, 50)),
+            "p90": float(np.percentile(ms, 90))}
+
+
+def _plot_flops(system):
+    """Algorithmic plotting work: (r+1)^n corners per relation x 4d flop (d FMA
+    for the value and d for its error bound)."""
+    tot = 0.0
+    for rel in system.relations:
+        corners = 1
+        for v in rel.vars:
+            corners *= system.axes[v][2] + 1
+        tot += corners * 4.0 * rel.degree
+    return tot
+
+
+def _kernel_table(plan, stream, system, reps):
+    """Per grouped launch: kind, ms per launch (back-to-back repetitions
+    between two events), algorithmic work; and a roofline entry per kind."""
     from paper_1609_00061_amd import pa
-    plan = pa.Plan(system, timing=2, **plan_kw)
-    out = pa.empty_bits(plan.dims)
-    for _ in range(3):
-        plan.execute(out)
-        plan.op_times()
-    acc = {}
-    for _ in range(steps):
-        plan.execute(out)
-        for kind, ms, macs in plan.op_times():
-            a = acc.setdefault(kind, [0.0, 0, 0.0])
-            a[0] += ms
-            a[1] += 1
-            a[2] += macs
-    return {k: {"avg_ms": v[0] / v[1], "launches_per_step": v[1] / steps, "macs_per_launch": v[2] / v[1]}
-            for k, v in acc.items()}
+    groups = plan.time_groups(reps=reps, stream=stream)
+    by = {}
+    for kind, ms, macs in groups:
+        a = by.setdefault(kind, {"ms": 0.0, "launches": 0, "macs": 0.0})
+        a["ms"] += ms
+        a["launches"] += 1
+        a["macs"] += macs
+    roof = {}
+    g = by.get(pa.OPKIND_GEMM)
+    if g:
+        ops = 2.0 * g["macs"] / g["launches"]
+        avg = g["ms"] / g["launches"]
+        ach = ops / (avg * 1e-3) / 1e12
+        roof["gemm"] = {"kernel": "k_group<1> (MFMA Boolean contraction tiles of one tree level)", "bound": "mfma",
+                        "achieved": ach, "peak": INT8_DENSE_PEAK_TOPS, "unit": "TOP/s",
+                        "frac": ach / INT8_DENSE_PEAK_TOPS, "traffic": None, "avg_launch_ms": avg,
+                        "ops_per_launch": ops, "launches_per_step": g["launches"],
+                        "ms_per_step": g["ms"]}
+    p = by.get(pa.OPKIND_PLOT)
+    if p:
+        fl = _plot_flops(system) / p["launches"]
+        avg = p["ms"] / p["launches"]
+        ach = fl / (avg * 1e-3) / 1e12
+        roof["plot"] = {"kernel": "k_group<0> (corner plotting of all relations)", "bound": "alu",
+                        "achieved": ach, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                        "frac": ach / FP32_VECTOR_PEAK_TFLOPS, "traffic": None, "avg_launch_ms": avg,
+                        "flop_per_launch": fl, "launches_per_step": p["launches"], "ms_per_step": p["ms"]}
+    per_kind = {str(k): {"ms_per_step": v["ms"], "launches_per_step": v["launches"]} for k, v in by.items()}
+    return roof, per_kind, groups
+
+
+def _batched(stream, K, W):
+    """512 chains of uneven resolution: one graph replay of the batch (level-
+    grouped launches, autotuned tiles) vs the plain path solving each system."""
+    import torch
+    from paper_1609_00061_amd import inputs, pa
+    systems = inputs.config4()
+    t0 = time.perf_counter()
+    b = pa.Batch(systems, graph=True, autotune=True)
+    create_s = time.perf_counter() - t0
+    outs = b.alloc_outputs()
+    for _ in range(W):
+        b.execute(outs, stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(K):
+        b.execute(outs, stream=stream)
+    torch.cuda.synchronize()
+    bdt = (time.perf_counter() - t0) / K
+    plans = [pa.Plan(s, order=pa.ORDER_GREEDY, plain=True) for s in systems]
+    pouts = [pa.empty_bits(p.dims) for p in plans]
+    for p, o in zip(plans, pouts):
+        p.execute(o)
+    torch.cuda.synchronize()
+    reps = max(1, K // 20)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        for p, o in zip(plans, pouts):
+            p.execute(o)
+    torch.cuda.synchronize()
+    pdt = (time.perf_counter() - t0) / reps
+    same = all(bool(torch.equal(a, c)) for a, c in zip(outs, pouts))
+    groups = b.time_groups(reps=5, stream=stream)
+    kinds = {}
+    for kind, ms, _ in groups:
+        kinds[str(kind)] = kinds.get(str(kind), 0.0) + ms
+    return {"workload": "512 independent chains of 2-6 binary cubic relations, N(0,1) coefficients, [-3,3], "
+                        "per-axis resolution log-uniform in [64, 2048]",
+            "value": len(systems) / bdt, "unit": "solves/s", "ms_per_batch": 1e3 * bdt,
+            "executor": "one hipGraph replay of level-grouped launches over all systems, autotuned tiles",
+            "batch_create_s": create_s,
+            "plain_gpu": {"value": len(systems) / pdt, "unit": "solves/s", "ms_per_batch": 1e3 * pdt,
+                          "path": "one plain plan per system, greedy order, one launch per plot and step"},
+            "speedup_vs_plain": pdt / bdt, "same_bits_as_plain": same, "group_kernel_ms": kinds}
 
 
 def _cpu_baseline(system, budget_s, gpu_bits):
@@ -92,13 +182,13 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
               f"(independent systems would shard round-robin across GPUs without communication)", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
     from paper_1609_00061_amd import inputs, pa
 
@@ -107,11 +197,14 @@ def main():
     K, W = args.steps, args.warmup
 
     stream = torch.cuda.Stream()
-    plan = pa.Plan(system, order=pa.ORDER_EXHAUSTIVE, precision=pa.PLOT_FP32_ESCALATE, graph=True)
+    t0 = time.perf_counter()
+    plan = pa.Plan(system, order=pa.ORDER_EXHAUSTIVE, precision=pa.PLOT_FP32_ESCALATE, graph=True, autotune=True)
+    plan_s = time.perf_counter() - t0
     out = pa.empty_bits(plan.dims)
     dt = _time_plan(plan, out, K, W, stream)
     _, rep, _ = plan.execute(out, stream=stream, report=True)
     gpu_bits = pa.unpack_bits(out.cpu().numpy(), plan.dims)
+    pct = _step_percentiles(plan, out, stream, min(K, 200))
 
     result = {
         "metric": "pixel-array solves/sec + bool-contraction TOPS vs plain GPU path, bit-exact",
@@ -130,22 +223,37 @@ def main():
                                "[-3,3]^9 at 1024 cells/axis, x1 and x9 exposed, 7 latent",
                    "plotting": "fp32 + fp64 escalation", "contraction": "int8 MFMA, int32 accumulation, count>0",
                    "order": "exhaustive (balanced tree on cost ties)",
-                   "executor": "one grouped launch per tree level and kernel kind, hipGraph replay",
+                   "executor": "one grouped launch per tree level and kernel kind, hipGraph replay, autotuned tiles",
                    "global_batch": 1},
+        "step_ms_events": pct,
+        "plan_and_tune_s": plan_s,
         "nnz_out": rep["nnz_out"],
         "escalated_corners": rep["corners_flagged"],
         "corners": rep["corners"],
     }
+
+    # per-kernel durations and the roofline of the dominant kernel
+    roof, per_kind, _ = _kernel_table(plan, stream, system, reps=20)
+    dom = max(roof.values(), key=lambda r: r["ms_per_step"]) if roof else None
+    if dom:
+        result["roofline"] = {k: dom[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic")}
+        result["roofline"]["kernel"] = dom["kernel"]
+        result["roofline"]["avg_launch_ms"] = dom["avg_launch_ms"]
+    result["roofline_by_kernel"] = roof
+    result["group_kernel_ms"] = per_kind
+    g = roof.get("gemm")
+    if g:
+        result["contraction_tops"] = g["achieved"]
 
     if not args.no_plain:
         plain = pa.Plan(system, order=pa.ORDER_GREEDY, plain=True)
         pout = pa.empty_bits(plain.dims)
         pdt = _time_plan(plain, pout, K, W)
         torch.cuda.synchronize()
-        same = bool(torch.equal(pout, out))
         result["plain_gpu"] = {"value": K / pdt, "unit": "solves/s", "ms_per_step": 1e3 * pdt / K,
-                               "path": "greedy order, one plotting launch per relation, no split K",
-                               "same_bits": same}
+                               "path": "greedy order, one plotting launch per relation, one launch per step, "
+                                       "no split K, no graph",
+                               "same_bits": bool(torch.equal(pout, out))}
         result["speedup_vs_plain"] = (K / dt) / (K / pdt)
 
     # one persistent launch per solve (tiles wait on dependency counters)
@@ -155,32 +263,9 @@ def main():
     torch.cuda.synchronize()
     result["single_launch"] = {"value": K / sdt, "unit": "solves/s", "ms_per_step": 1e3 * sdt / K,
                                "same_bits": bool(torch.equal(sout, out))}
-    # dominant kernel of the timed path: per-group launch durations (HIP events)
-    prof = _op_profile(system, max(10, min(K, 100)), order=pa.ORDER_EXHAUSTIVE)
-    result["group_kernel_ms"] = {str(k): v["avg_ms"] * v["launches_per_step"] for k, v in prof.items()}
-    g = prof.get(pa.OPKIND_GEMM)
-    if g:
-        ops_per_launch = 2.0 * g["macs_per_launch"]                   # AND + OR per Boolean MAC
-        achieved = ops_per_launch / (g["avg_ms"] * 1e-3) / 1e12
-        result["roofline"] = {"kernel": "k_group<gemm> (k_gemm_mfma tiles)", "bound": "mfma", "achieved": achieved,
-                              "peak": INT8_DENSE_PEAK_TOPS, "unit": "TOP/s", "frac": achieved / INT8_DENSE_PEAK_TOPS,
-                              "traffic": None, "avg_launch_ms": g["avg_ms"],
-                              "ops_per_launch": ops_per_launch, "launches_per_step": g["launches_per_step"]}
-        contraction_ms = sum(v["avg_ms"] * v["launches_per_step"] for k, v in prof.items()
-                             if k not in (pa.OPKIND_PLOT,))
-        total_ops = 2.0 * sum(v["macs_per_launch"] * v["launches_per_step"] for k, v in prof.items()
-                              if k not in (pa.OPKIND_PLOT, pa.OPKIND_FILL))
-        result["contraction_tops"] = total_ops / (contraction_ms * 1e-3) / 1e12
-    # the stand-alone MFMA kernel, one launch per step (per-op path)
-    prof2 = _op_profile(system, max(10, min(K, 100)), order=pa.ORDER_EXHAUSTIVE, per_op=True)
-    g2 = prof2.get(pa.OPKIND_GEMM)
-    if g2:
-        ops2 = 2.0 * g2["macs_per_launch"]
-        ach2 = ops2 / (g2["avg_ms"] * 1e-3) / 1e12
-        result["gemm_kernel"] = {"kernel": "k_gemm_mfma", "achieved": ach2, "unit": "TOP/s",
-                                 "frac": ach2 / INT8_DENSE_PEAK_TOPS, "avg_launch_ms": g2["avg_ms"],
-                                 "ops_per_launch": ops2}
-        result["per_op_kernel_ms"] = {str(k): v["avg_ms"] * v["launches_per_step"] for k, v in prof2.items()}
+
+    if not args.no_batched:
+        result["batched"] = _batched(stream, max(5, K // 10), 3)
 
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = _cpu_baseline(system, args.cpu_budget, gpu_bits)

@@ -12,7 +12,10 @@ constexpr int kMaxA = PA_MAX_ARITY;
 constexpr int kDense = (kMaxD + 1) * (kMaxD + 1) * (kMaxD + 1);
 constexpr int kMaxDim = PA_MAX_DIMS;
 constexpr int kLineFloats = kMaxD + 2;          // a_0..a_d, E per corner line
-constexpr int kMaxTileLines = 640;              // LDS line table capacity of one plot tile
+constexpr int kMaxTileLines = 160;              // LDS line table capacity of one plot tile
+// LDS of a plot tile: the line table, then the storage-order coefficient table (doubles)
+constexpr int kPlotLineWords = (kMaxTileLines * kLineFloats + 1) / 2 * 2;
+constexpr int kPlotLdsWords = kPlotLineWords + 2 * kDense;
 
 // One relation to plot.  The relation's declared variables x_0..x_{n-1} are
 // stored on storage axes in the order perm: storage axis s holds declared

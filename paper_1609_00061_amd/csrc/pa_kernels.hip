@@ -14,6 +14,19 @@
 namespace pa {
 
 // ------------------------------------------------------------------ helpers
+// Pointers read from step tables are generic to the compiler, which would
+// access them with FLAT instructions (counted on both the vector-memory and
+// the LDS counters, so an LDS wait also waits for every load in flight).
+// Every array the kernels touch is in device global memory: accesses go
+// through address-space-1 pointers (global_load / global_store).
+#define PA_G __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ PA_G T *gp(T *p) {
+    return (PA_G T *)p;
+}
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
 // Blocks for `total` threads, capped (the kernels loop over the rest).
 static dim3 grid_for(int64_t total) {
     int64_t blocks = (total + 255) / 256;
@@ -25,7 +38,7 @@ static dim3 grid_for(int64_t total) {
 // Canonical FP64 value of a relation at a point given in DECLARED variable
 // order: nested Horner, last declared variable outermost, fma at every step.
 // c is the dense table c[e0 + (d+1)*(e1 + (d+1)*e2)].
-__device__ double canon_eval(const double *__restrict__ c, int n, int d, const double *x) {
+__device__ double canon_eval(const PA_G double *__restrict__ c, int n, int d, const double *x) {
     const int D1 = d + 1;
     if (n == 1) {
         double p = c[d];
@@ -45,7 +58,7 @@ __device__ double canon_eval(const double *__restrict__ c, int n, int d, const d
     // n == 3: A_i(x0, x1) = sum_k B_ik(x0) x1^k, B_ik(x0) = sum_j c_jki x0^j
     auto Bik = [&](int i, int k) {
         const int top = d - i - k;
-        const double *row = c + D1 * (k + D1 * i);
+        const PA_G double *row = c + D1 * (k + D1 * i);
         double b = row[top];
         for (int j = top - 1; j >= 0; --j) b = fma(b, x[0], row[j]);
         return b;
@@ -61,11 +74,96 @@ __device__ double canon_eval(const double *__restrict__ c, int n, int d, const d
     return p;
 }
 
-// ------------------------------------------------------------ plot: lines
-// Coefficients of the relation restricted to one corner line (fixed corner
-// indices li[s] on the non-packed storage axes), as a polynomial in the
-// packed variable, rounded to FP32, and the FP32 error bound E of evaluating
-// them by Horner at any corner of the line.
+struct PlotCount {
+    unsigned long long flagged = 0, dis = 0, dis_unf = 0;
+};
+
+// ------------------------------------------------------------ plot: tiles
+// A tile (256 threads) covers tw words of the packed axis x tb strips of s
+// cell rows along the walk axis (storage axis n-2) x ta cells of the fixed
+// axis (n == 3).  A thread owns one 32-cell word of one strip: it evaluates
+// the 33 corners of the word on every corner line bounding its strip (FP32,
+// coordinates held in registers), so a corner line is evaluated once per
+// strip.  The tile first stages the coefficient table, permuted to storage
+// order, in LDS, and builds the FP32 restriction and bound of each of its
+// corner lines there (FP64, one line per thread); the threads' coordinate
+// loads are issued before that so their latency overlaps it.
+
+// Fields of a relation a tile uses, held in registers (the record itself is
+// in global memory, which the tile's output stores could alias).
+struct PlotView {
+    int n, d, mode, audit;
+    int perm0, perm1, perm2;   // declared variable of storage axis 0, 1, 2
+    int res0, res1;            // resolutions of storage axes 0 and 1
+    int rwalk, rp;             // walk axis (storage n-2; 1 if n == 1) and packed axis
+    int64_t row_words;
+    const PA_G double *coef;
+    const PA_G double *ax0, *ax1;   // FP64 coordinates of storage axes 0 and 1
+    const PA_G double *axp;         // FP64 coordinates of the packed axis
+    const PA_G float *axfp;         // FP32 coordinates of the packed axis
+    PA_G uint32_t *out;
+    double vmax;
+};
+
+__device__ __forceinline__ PlotView plot_view(const PlotRel &R) {
+    PlotView v;
+    v.n = R.n;
+    v.d = R.d;
+    v.mode = R.mode;
+    v.audit = R.audit;
+    v.perm0 = R.perm[0];
+    v.perm1 = R.perm[1];
+    v.perm2 = R.perm[2];
+    v.res0 = R.res[0];
+    v.res1 = R.res[1];
+    const int n = v.n;
+    v.rp = n == 1 ? R.res[0] : (n == 2 ? R.res[1] : R.res[2]);
+    v.rwalk = n == 1 ? 1 : (n == 2 ? R.res[0] : R.res[1]);
+    v.row_words = R.row_words;
+    v.coef = gp(R.coef);
+    v.ax0 = gp(R.ax[0]);
+    v.ax1 = gp(R.ax[1]);
+    v.axp = gp(n == 1 ? R.ax[0] : (n == 2 ? R.ax[1] : R.ax[2]));
+    v.axfp = gp(n == 1 ? R.axf[0] : (n == 2 ? R.axf[1] : R.axf[2]));
+    v.out = gp(R.out);
+    v.vmax = R.vmax;
+    return v;
+}
+
+// Declared-order coordinates from storage-axis coordinates (no dynamically
+// indexed private arrays).
+__device__ __forceinline__ void decl_point(const PlotView &V, double s0, double s1, double s2, double *xd) {
+#pragma unroll
+    for (int v = 0; v < 3; ++v) {
+        double t = 0.0;
+        if (V.perm0 == v) t = s0;
+        if (V.n > 1 && V.perm1 == v) t = s1;
+        if (V.n > 2 && V.perm2 == v) t = s2;
+        xd[v] = t;
+    }
+}
+
+// Stage the dense coefficient table in LDS in storage order:
+// cst[s0 + D1*(s1 + D1*s2)] = coefficient with exponent s_j on storage axis j.
+__device__ __forceinline__ void stage_coefs(const PlotView &V, double *cst) {
+    const int D1 = V.d + 1;
+    const int tid = threadIdx.x;
+    const int total = V.n == 1 ? D1 : (V.n == 2 ? D1 * D1 : D1 * D1 * D1);
+    if (tid < total) {
+        const int s0 = tid % D1, s1 = (tid / D1) % D1, s2 = tid / (D1 * D1);
+        // declared exponent of variable v = storage exponent of the axis holding v
+        const int t1 = V.n > 1 ? s1 : 0, t2 = V.n > 2 ? s2 : 0;
+        const int e0 = (V.perm0 == 0 ? s0 : 0) + (V.n > 1 && V.perm1 == 0 ? t1 : 0) + (V.n > 2 && V.perm2 == 0 ? t2 : 0);
+        const int e1 = (V.perm0 == 1 ? s0 : 0) + (V.n > 1 && V.perm1 == 1 ? t1 : 0) + (V.n > 2 && V.perm2 == 1 ? t2 : 0);
+        const int e2 = (V.perm0 == 2 ? s0 : 0) + (V.n > 1 && V.perm1 == 2 ? t1 : 0) + (V.n > 2 && V.perm2 == 2 ? t2 : 0);
+        cst[tid] = V.coef[e0 + D1 * (e1 + D1 * e2)];
+    }
+}
+
+// Coefficients of the relation restricted to one corner line (storage
+// coordinates y0, y1 on the non-packed axes), as a polynomial in the packed
+// variable, rounded to FP32, and the FP32 error bound E of evaluating them by
+// Horner at any corner of the line.
 //
 // Bound.  Let v be a corner coordinate on the packed axis, v~ = RN32(v),
 // a~_t = RN32(a^_t) with a^_t the FP64 sum below, and p^ the FP32 Horner
@@ -78,222 +176,269 @@ __device__ double canon_eval(const double *__restrict__ c, int n, int d, const d
 // partial sum, s_t = sum of |terms| feeding a_t.  All FP64 errors (of a^_t,
 // of S, and of the canonical FP64 value) are below 2^-40 * S; underflow of
 // FP32 intermediates or of flushed denormals is below 2^-100 (1 + S) V^d.
-// A corner is escalated unless E < |p^| <= FLT_MAX; otherwise
-// |f_exact| > E - gamma S >= |f64 - f_exact|, so sign(p^) = sign(f64) != 0.
-__device__ void line_coefs(const PlotRel &R, const int *li, float *dst) {
-    const int n = R.n, d = R.d, D1 = d + 1;
-    const int pk = R.perm[n - 1];                 // declared index of the packed variable
-    double xd[kMaxA] = {0.0, 0.0, 0.0};
-    for (int s = 0; s < n - 1; ++s) xd[R.perm[s]] = R.ax[s][li[s]];
+// A corner is escalated unless |p^| > E (E = +inf when S > 2^126, where
+// FP32 could overflow); otherwise |f_exact| > E - gamma S >= |f64 - f_exact|,
+// so sign(p^) = sign(f64) != 0.
+__device__ void line_coefs(const PlotView &V, const double *cst, double y0, double y1, float *dst) {
+    const int n = V.n, d = V.d, D1 = d + 1;
     double a[kMaxD + 1], sab[kMaxD + 1];
-    for (int t = 0; t <= kMaxD; ++t) { a[t] = 0.0; sab[t] = 0.0; }
-    const int e2max = (n > 2) ? d : 0;
-    for (int e2 = 0; e2 <= e2max; ++e2) {
-        const int e1max = (n > 1) ? d - e2 : 0;
-        for (int e1 = 0; e1 <= e1max; ++e1) {
-            for (int e0 = 0; e0 <= d - e1 - e2; ++e0) {
-                const double c = R.coef[e0 + D1 * (e1 + D1 * e2)];
-                const int e[3] = {e0, e1, e2};
-                double term = c;
-                for (int v = 0; v < n; ++v) {
-                    if (v == pk) continue;
-                    for (int q = 0; q < e[v]; ++q) term *= xd[v];
+#pragma unroll
+    for (int t = 0; t <= kMaxD; ++t) {
+        double at = 0.0, st = 0.0;
+        if (t <= d) {
+            if (n == 1) {
+                at = cst[t];
+                st = fabs(at);
+            } else if (n == 2) {
+                double p = 1.0;
+#pragma unroll
+                for (int e0 = 0; e0 <= kMaxD; ++e0) {
+                    if (e0 + t <= d) {
+                        const double term = cst[e0 + D1 * t] * p;
+                        at += term;
+                        st += fabs(term);
+                    }
+                    p *= y0;
                 }
-                a[e[pk]] += term;
-                sab[e[pk]] += fabs(term);
+            } else {
+                double p1 = 1.0;
+#pragma unroll
+                for (int e1 = 0; e1 <= kMaxD; ++e1) {
+                    double p = p1;
+#pragma unroll
+                    for (int e0 = 0; e0 <= kMaxD; ++e0) {
+                        if (e0 + e1 + t <= d) {
+                            const double term = cst[e0 + D1 * (e1 + D1 * t)] * p;
+                            at += term;
+                            st += fabs(term);
+                        }
+                        p *= y0;
+                    }
+                    p1 *= y1;
+                }
             }
         }
+        a[t] = at;
+        sab[t] = st;
     }
-    const double V = fmax(1.0, R.vmax);
+    const double Vm = fmax(1.0, V.vmax);
     double S = 0.0, Vp = 1.0;
-    for (int t = 0; t <= d; ++t) { S += sab[t] * Vp; Vp *= V; }
+#pragma unroll
+    for (int t = 0; t <= kMaxD; ++t) {
+        if (t <= d) {
+            S += sab[t] * Vp;
+            Vp *= Vm;
+        }
+    }
     const double u = 0x1p-24;
     const double K = 2.0 * d + 1.0;
     const double gam = K * u / (1.0 - K * u);
     const double E = (gam + 0x1p-40) * S * (1.0 + 0x1p-30) + 0x1p-100 * (1.0 + S) * Vp;
     float Ef = (float)E;
     if ((double)Ef < E) Ef = nextafterf(Ef, INFINITY);
+    // every Horner partial sum is below 2S: with S <= 2^126 nothing overflows
+    // FP32; otherwise no corner of the line is certain
+    if (!(S <= 0x1p126)) Ef = INFINITY;
+#pragma unroll
     for (int t = 0; t <= kMaxD; ++t) dst[t] = (t <= d) ? (float)a[t] : 0.0f;
     dst[kLineFloats - 1] = Ef;
 }
 
-struct PlotCount {
-    unsigned long long flagged = 0, dis = 0, dis_unf = 0;
-};
-
 // FP32 pass over the corners k0..k0+kmax of one corner line (coordinates in
-// registers): LE/GE bits where the FP32 sign is certain, and a mask FL of the
-// corners that must be decided in FP64.  Coefficients above the degree are
-// zero, and fma(0, x, a) = a exactly, so a fixed 4-step Horner gives the same
-// value as a degree-d Horner.
+// registers), NF Horner steps (NF >= degree; coefficients above the degree
+// are zero and fma(0, x, a) = a exactly).  A corner's FP32 sign is certain
+// iff E - |f| < 0: min(., +0) sends a NaN to +0, and E is +inf when the
+// line's magnitude bound allows FP32 overflow, so a certain f is finite and
+// nonzero.  The sign bits and the certainty bits are shifted into words with
+// one alignbit each (corners taken from 31 down to 0).  Out: LE/GE where the
+// sign is certain, FL the corners FP64 decides.
+template <int NF>
 __device__ __forceinline__ void line_fp32(const float *ln, const float *xv, int kmax, uint64_t &LE, uint64_t &GE,
                                           uint64_t &FL) {
-    float ca[kMaxD + 1];
+    float ca[NF + 1];
 #pragma unroll
-    for (int t = 0; t <= kMaxD; ++t) ca[t] = ln[t];
+    for (int t = 0; t <= NF; ++t) ca[t] = ln[t];
     const float E = ln[kLineFloats - 1];
-    LE = 0;
-    GE = 0;
-    FL = 0;
+    auto value = [&](float x) {
+        float f = ca[NF];
 #pragma unroll
-    for (int kk = 0; kk < 33; ++kk) {
-        const float x = xv[kk];
-        float f = ca[kMaxD];
+        for (int t = NF - 1; t >= 0; --t) f = fmaf(f, x, ca[t]);
+        return f;
+    };
+    const float f32 = value(xv[32]);
+    const uint32_t sg32 = __float_as_uint(f32) >> 31, ok32 = __float_as_uint(fminf(E - fabsf(f32), 0.0f)) >> 31;
+    uint32_t sg = 0, ok = 0;
 #pragma unroll
-        for (int t = kMaxD - 1; t >= 0; --t) f = fmaf(f, x, ca[t]);
-        const float af = fabsf(f);
-        const bool ok = (af > E) && (af <= FLT_MAX);
-        const bool valid = kk <= kmax;
-        LE |= (uint64_t)(valid && ok && f < 0.0f) << kk;
-        GE |= (uint64_t)(valid && ok && f > 0.0f) << kk;
-        FL |= (uint64_t)(valid && !ok) << kk;
+    for (int kk = 31; kk >= 0; --kk) {
+        const float f = value(xv[kk]);
+        sg = __builtin_amdgcn_alignbit(sg, __float_as_uint(f), 31);
+        ok = __builtin_amdgcn_alignbit(ok, __float_as_uint(fminf(E - fabsf(f), 0.0f)), 31);
     }
+    const uint64_t valid = (kmax >= 63) ? ~0ull : ((2ull << kmax) - 1ull);
+    const uint64_t okm = ((uint64_t)ok | ((uint64_t)ok32 << 32)) & valid;
+    const uint64_t sgm = (uint64_t)sg | ((uint64_t)sg32 << 32);
+    LE = okm & sgm;
+    GE = okm & ~sgm;
+    FL = valid & ~okm;
 }
 
-// LE/GE bits of the corners k0..k0+kmax of one corner line; `own` says
-// whether this thread counts the line's corners (each corner is counted once).
-__device__ __forceinline__ void eval_line(const PlotRel &R, const float *ln, const float *xv, const int *li, int k0,
-                                          int kmax, bool own, uint64_t &LE, uint64_t &GE, PlotCount &cnt) {
-    const int n = R.n, d = R.d;
-    const int pk = R.perm[n - 1];
-    const int rp = R.res[n - 1];
+// LE/GE bits of the corners k0..k0+kmax of the corner line with storage
+// indices ia (fixed axis, n == 3) and ib (walk axis) on the non-packed axes; `own` says whether this thread
+// counts the line's corners (each corner is counted once).
+__device__ __forceinline__ void eval_line(const PlotView &V, const float *ln, const float *xv, int64_t ia, int64_t ib,
+                                          int k0, int kmax, bool own, uint64_t &LE, uint64_t &GE, PlotCount &cnt) {
+    const int n = V.n, rp = V.rp;
     const uint64_t valid = (kmax >= 63) ? ~0ull : ((2ull << kmax) - 1ull);
     const uint64_t owned = own ? (((1ull << kmax) - 1ull) | ((k0 + kmax == rp) ? (1ull << kmax) : 0ull)) : 0ull;
-    double xdec[kMaxA] = {0.0, 0.0, 0.0};
-    for (int s = 0; s < n - 1; ++s) xdec[R.perm[s]] = R.ax[s][li[s]];
-    const double *axp = R.ax[n - 1] + k0;
-    if (R.mode == PA_PLOT_FP32_ESCALATE) {
-        uint64_t FL;
-        line_fp32(ln, xv, kmax, LE, GE, FL);
+    const PA_G double *axp = V.axp + k0;
+    uint64_t FL = valid, todo;
+    if (V.mode == PA_PLOT_FP32_ESCALATE) {
+        if (V.d <= 3) line_fp32<3>(ln, xv, kmax, LE, GE, FL);
+        else line_fp32<kMaxD>(ln, xv, kmax, LE, GE, FL);
         cnt.flagged += __popcll(FL & owned);
-        // FP64 decides the escalated corners; in audit mode every corner's
-        // FP32 sign is also compared with its FP64 sign
-        uint64_t todo = R.audit ? valid : FL;
-        const float *xsf = R.axf[n - 1] + k0;
-        while (todo) {
-            const int kk = __ffsll((long long)todo) - 1;
-            todo &= todo - 1;
-            xdec[pk] = axp[kk];
-            const double f64 = canon_eval(R.coef, n, d, xdec);
-            const uint64_t bit = 1ull << kk;
-            const bool flagged = (FL & bit) != 0;
-            if (flagged) {
-                LE |= (uint64_t)(f64 <= 0.0) << kk;
-                GE |= (uint64_t)(f64 >= 0.0) << kk;
-            }
-            if (R.audit) {
-                // FP32 value of this corner, recomputed as in line_fp32
-                const float x = xsf[kk];
-                float f = ln[kMaxD];
-                for (int t = kMaxD - 1; t >= 0; --t) f = fmaf(f, x, ln[t]);
-                const int s32 = (f > 0.0f) - (f < 0.0f);
-                const int s64 = (f64 > 0.0) - (f64 < 0.0);
-                const bool dis = ((s32 != s64) || (f != f) || (f64 != f64)) && (owned & bit);
-                cnt.dis += dis;
-                cnt.dis_unf += dis && !flagged;
-            }
-        }
+        todo = V.audit ? valid : FL;
     } else {
         LE = 0;
         GE = 0;
-        for (int kk = 0; kk <= kmax; ++kk) {
-            xdec[pk] = axp[kk];
-            const double f64 = canon_eval(R.coef, n, d, xdec);
+        todo = valid;
+    }
+    // FP64 decides the escalated corners (every corner in FP64 mode); in
+    // audit mode every corner's FP32 sign is also compared with its FP64 sign
+    double y0 = 0.0, y1 = 0.0;
+    if (todo) {
+        if (n == 2) y0 = V.ax0[ib];
+        if (n == 3) {
+            y0 = V.ax0[ia];
+            y1 = V.ax1[ib];
+        }
+    }
+    while (todo) {
+        const int kk = __ffsll((long long)todo) - 1;
+        todo &= todo - 1;
+        double xd[3];
+        const double xk = axp[kk];
+        if (n == 1) decl_point(V, xk, 0.0, 0.0, xd);
+        else if (n == 2) decl_point(V, y0, xk, 0.0, xd);
+        else decl_point(V, y0, y1, xk, xd);
+        const double f64 = canon_eval(V.coef, n, V.d, xd);
+        const uint64_t bit = 1ull << kk;
+        const bool flagged = (FL & bit) != 0;
+        if (flagged) {
             LE |= (uint64_t)(f64 <= 0.0) << kk;
             GE |= (uint64_t)(f64 >= 0.0) << kk;
+        }
+        if (V.mode == PA_PLOT_FP32_ESCALATE && V.audit) {
+            // FP32 value of this corner, recomputed as in line_fp32 (same
+            // RN32 coordinate, from the table)
+            const float x = V.axfp[k0 + kk];
+            float f = ln[kMaxD];
+#pragma unroll
+            for (int t = kMaxD - 1; t >= 0; --t) f = fmaf(f, x, ln[t]);
+            const int s32 = (f > 0.0f) - (f < 0.0f);
+            const int s64 = (f64 > 0.0) - (f64 < 0.0);
+            const bool dis = ((s32 != s64) || (f != f) || (f64 != f64)) && (owned & bit);
+            cnt.dis += dis;
+            cnt.dis_unf += dis && !flagged;
         }
     }
 }
 
-// One plot tile (256 threads).  Cell (.., c, j) on the walk axis is set iff
-// its 2^n corners include f <= 0 and f >= 0 (closed cells; a NaN corner
-// counts as neither): with le(L) = LE | LE >> 1 per corner line L, the cell
-// word of walk cell c is (le(c) | le(c+1)) & (ge(c) | ge(c+1)), each term ORed
-// over the pair of lines on the fixed axis when n == 3.
-__device__ void plot_tile(const PlotRel &R, int64_t tile, float *lines, PlotCount &cnt) {
-    const int n = R.n;
+// One plot tile.  lines: kMaxTileLines * kLineFloats floats of LDS; cst:
+// kDense doubles of LDS.
+__device__ void plot_tile(const PlotRel &R, int64_t tile, float *lines, double *cst, PlotCount &cnt) {
+    const PlotView V = plot_view(R);
+    const int n = V.n;
     const int tid = threadIdx.x;
-    int64_t t = tile;
-    const int64_t t_w = t % R.tiles_w;
-    t /= R.tiles_w;
-    const int64_t t_walk = t % R.tiles_walk;
-    const int64_t t_fixed = t / R.tiles_walk;
-    const int wax = n - 2;                          // walk axis (-1 when n == 1)
-    const int rwalk = (n >= 2) ? R.res[wax] : 1;
-    const int span = R.tb * R.s;
+    const int tw_n = R.tw, ta = R.ta, tb = R.tb, s = R.s;
+    // tile counts are below 2^31 (checked on the host): 32-bit decomposition
+    const uint32_t tiles_w = (uint32_t)R.tiles_w, tiles_walk = (uint32_t)R.tiles_walk;
+    uint32_t t = (uint32_t)tile;
+    const int64_t t_w = t % tiles_w;
+    t /= tiles_w;
+    const int64_t t_walk = t % tiles_walk;
+    const int64_t t_fixed = t / tiles_walk;
+    const int rwalk = V.rwalk;
+    const int rp = V.rp;
+    const int span = tb * s;
     const int64_t b0 = t_walk * span;
-    const int64_t a0 = t_fixed * R.ta;
+    const int64_t a0 = t_fixed * ta;
     const int nwl = (n >= 2) ? span + 1 : 1;
-    const int nfl = (n == 3) ? R.ta + 1 : 1;
-    if (R.mode == PA_PLOT_FP32_ESCALATE) {
-        for (int l = tid; l < nwl * nfl; l += blockDim.x) {
-            const int lf = l / nwl, lw = l % nwl;
-            int li[kMaxA] = {0, 0, 0};
-            bool valid = true;
-            if (n >= 2) {
-                li[wax] = (int)(b0 + lw);
-                valid &= li[wax] <= rwalk;
-            }
-            if (n == 3) {
-                li[0] = (int)(a0 + lf);
-                valid &= li[0] <= R.res[0];
-            }
-            if (valid) line_coefs(R, li, lines + l * kLineFloats);
-        }
-    }
-    __syncthreads();
-    const int tw = tid % R.tw, slot = tid / R.tw;
-    const int fa = (n == 3) ? slot % R.ta : 0;
-    const int strip = (n == 3) ? slot / R.ta : slot;
-    const int64_t w = t_w * R.tw + tw;
-    if (strip >= R.tb || (n == 1 && slot != 0) || w >= R.row_words) return;
-    const int64_t cs = b0 + (int64_t)strip * R.s;
-    if (n >= 2 && cs >= rwalk) return;
-    const int64_t ce = (n >= 2) ? min((int64_t)rwalk, cs + R.s) : 0;
+    const int nfl = (n == 3) ? ta + 1 : 1;
+    // this thread's word and strip
+    const int twi = tid % tw_n, slot = tid / tw_n;
+    const int fa = (n == 3) ? slot % ta : 0;
+    const int strip = (n == 3) ? slot / ta : slot;
+    const int64_t w = t_w * tw_n + twi;
+    const int64_t cs = b0 + (int64_t)strip * s;
     const int64_t cf = a0 + fa;
-    if (n == 3 && cf >= R.res[0]) return;
-    const int rp = R.res[n - 1];
+    bool active = strip < tb && !(n == 1 && slot != 0) && w < V.row_words;
+    if (n >= 2) active = active && cs < rwalk;
+    if (n == 3) active = active && cf < V.res0;
     const bool pad = w * 32 >= rp;
     const int k0 = (int)(w * 32);
     const int kmax = pad ? 0 : min(32, rp - k0);
-    const uint32_t vmask = pad ? 0u : (kmax == 32 ? 0xffffffffu : ((1u << kmax) - 1u));
-    const int64_t row_base = (n == 3) ? cf * R.res[1] : 0;
-    // the 33 corner coordinates of this word, loaded once for all lines
+    // the 33 corner coordinates of this word, requested before the line
+    // tables are built
     float xv[33];
-    {
-        const float *xs = R.axf[n - 1] + k0;
 #pragma unroll
-        for (int kk = 0; kk < 33; ++kk) xv[kk] = (!pad && kk <= kmax) ? xs[kk] : 0.0f;
+    for (int kk = 0; kk < 33; ++kk) {
+        // load from a clamped index (no branch per load), then mask
+        const int64_t k = (active && !pad) ? min((int64_t)k0 + kk, (int64_t)rp) : 0;
+        const float x = V.axfp[k];
+        xv[kk] = (active && !pad && kk <= kmax) ? x : 0.0f;
     }
+    if (V.mode == PA_PLOT_FP32_ESCALATE) {
+        stage_coefs(V, cst);
+        __syncthreads();
+        for (int l = tid; l < nwl * nfl; l += blockDim.x) {
+            const int lf = l / nwl, lw = l % nwl;
+            bool valid = true;
+            double y0 = 0.0, y1 = 0.0;
+            if (n == 2) {
+                const int64_t ib = b0 + lw;
+                valid = ib <= rwalk;
+                if (valid) y0 = V.ax0[ib];
+            } else if (n == 3) {
+                const int64_t ia = a0 + lf, ib = b0 + lw;
+                valid = ia <= V.res0 && ib <= rwalk;
+                if (valid) {
+                    y0 = V.ax0[ia];
+                    y1 = V.ax1[ib];
+                }
+            }
+            if (valid) line_coefs(V, cst, y0, y1, lines + l * kLineFloats);
+        }
+    }
+    __syncthreads();
+    if (!active) return;
+    const uint32_t vmask = pad ? 0u : (kmax == 32 ? 0xffffffffu : ((1u << kmax) - 1u));
+    const int64_t ce = (n >= 2) ? min((int64_t)rwalk, cs + s) : 0;
+    const int64_t row_base = (n == 3) ? cf * V.res1 : 0;
     uint32_t prevL = 0, prevG = 0;
     for (int64_t c = cs; c <= ce; ++c) {
         uint32_t lc = 0, gc = 0;
         if (!pad) {
             for (int df = 0; df < (n == 3 ? 2 : 1); ++df) {
-                int li[kMaxA] = {0, 0, 0};
                 bool own = true;
                 int lf = 0;
-                if (n >= 2) {
-                    li[wax] = (int)c;
-                    own &= (c > cs) || (cs == 0);
-                }
-                if (n == 3) {
-                    li[0] = (int)(cf + df);
+                if (n == 2) {
+                    own = (c > cs) || (cs == 0);
+                } else if (n == 3) {
+                    own = ((c > cs) || (cs == 0)) && ((df == 0) || (cf + 1 == V.res0));
                     lf = fa + df;
-                    own &= (df == 0) || (li[0] == R.res[0]);
                 }
                 const float *ln = lines + (lf * nwl + (int)(c - b0)) * kLineFloats;
                 uint64_t LE, GE;
-                eval_line(R, ln, xv, li, k0, kmax, own, LE, GE, cnt);
+                eval_line(V, ln, xv, cf + df, c, k0, kmax, own, LE, GE, cnt);
                 lc |= (uint32_t)((LE | (LE >> 1)) & 0xffffffffull);
                 gc |= (uint32_t)((GE | (GE >> 1)) & 0xffffffffull);
             }
         }
         if (n == 1) {
-            R.out[w] = lc & gc & vmask;
+            V.out[w] = lc & gc & vmask;
             break;
         }
-        if (c > cs) R.out[(row_base + c - 1) * R.row_words + w] = (prevL | lc) & (prevG | gc) & vmask;
+        if (c > cs) V.out[(row_base + c - 1) * V.row_words + w] = (prevL | lc) & (prevG | gc) & vmask;
         prevL = lc;
         prevG = gc;
     }
@@ -317,11 +462,12 @@ __device__ __forceinline__ int find_rel(const PlotRel *rels, int nrel, int64_t t
 
 __global__ __launch_bounds__(256) void k_plot(const PlotRel *__restrict__ rels, int nrel, int64_t total_tiles,
                                               PlotCounters *__restrict__ counters) {
-    __shared__ float lines[kMaxTileLines * kLineFloats];
+    __shared__ __attribute__((aligned(16))) uint32_t lds[kPlotLdsWords];
     PlotCount cnt;
     for (int64_t tile = blockIdx.x; tile < total_tiles; tile += gridDim.x) {
         const PlotRel &R = rels[find_rel(rels, nrel, tile)];
-        plot_tile(R, tile - R.tile_base, lines, cnt);
+        plot_tile(R, tile - R.tile_base, reinterpret_cast<float *>(lds),
+                  reinterpret_cast<double *>(lds + kPlotLineWords), cnt);
         __syncthreads();
     }
     flush_counts(cnt, counters);
@@ -372,8 +518,8 @@ __device__ unsigned bits_unit(const ContractArgs &a, int64_t row, int64_t bit) {
     for (;;) {
         const int64_t pa = (a.a_pk_k >= 0) ? kidx[a.a_pk_k] : p.pa;
         const int64_t pb = (a.b_pk_k >= 0) ? kidx[a.b_pk_k] : p.pb;
-        const unsigned ba = (a.A[p.baseA + offA + (pa >> 5)] >> (pa & 31)) & 1u;
-        const unsigned bb = a.B ? ((a.B[p.baseB + offB + (pb >> 5)] >> (pb & 31)) & 1u) : 1u;
+        const unsigned ba = (gp(a.A)[p.baseA + offA + (pa >> 5)] >> (pa & 31)) & 1u;
+        const unsigned bb = a.B ? ((gp(a.B)[p.baseB + offB + (pb >> 5)] >> (pb & 31)) & 1u) : 1u;
         if (ba & bb) return 1u;
         int j = a.nk - 1;
         for (; j >= 0; --j) {
@@ -398,13 +544,13 @@ __device__ uint32_t streamk_unit(const ContractArgs &a, int64_t row, int64_t bit
     const int64_t rw = a.a_row_words;
     uint32_t acc = 0;
     for (int64_t j = 0; j < a.nktab; ++j) {
-        const uint32_t *pa = a.A + p.baseA + a.ktab[2 * j];
+        const PA_G uint32_t *pa = gp(a.A) + p.baseA + gp(a.ktab)[2 * j];
         if (a.B) {
-            const uint32_t *pb = a.B + p.baseB + a.ktab[2 * j + 1];
+            const PA_G uint32_t *pb = gp(a.B) + p.baseB + gp(a.ktab)[2 * j + 1];
             if (VEC4) {
                 for (int64_t w = 0; w < rw; w += 4) {
-                    const uint4 x = *reinterpret_cast<const uint4 *>(pa + w);
-                    const uint4 y = *reinterpret_cast<const uint4 *>(pb + w);
+                    const u32x4 x = *reinterpret_cast<const PA_G u32x4 *>(pa + w);
+                    const u32x4 y = *reinterpret_cast<const PA_G u32x4 *>(pb + w);
                     acc |= (x.x & y.x) | (x.y & y.y) | (x.z & y.z) | (x.w & y.w);
                 }
             } else {
@@ -413,7 +559,7 @@ __device__ uint32_t streamk_unit(const ContractArgs &a, int64_t row, int64_t bit
         } else {
             if (VEC4) {
                 for (int64_t w = 0; w < rw; w += 4) {
-                    const uint4 x = *reinterpret_cast<const uint4 *>(pa + w);
+                    const u32x4 x = *reinterpret_cast<const PA_G u32x4 *>(pa + w);
                     acc |= x.x | x.y | x.z | x.w;
                 }
             } else {
@@ -431,8 +577,8 @@ __device__ uint32_t streamw_word(const ContractArgs &a, int64_t row, int64_t wc)
     const OutPos p = out_pos(a, row, 0);
     uint32_t acc = 0;
     for (int64_t j = 0; j < a.nktab; ++j) {
-        const uint32_t x = a.A[p.baseA + wc + a.ktab[2 * j]];
-        acc |= a.B ? (x & a.B[p.baseB + wc + a.ktab[2 * j + 1]]) : x;
+        const uint32_t x = gp(a.A)[p.baseA + wc + gp(a.ktab)[2 * j]];
+        acc |= a.B ? (x & gp(a.B)[p.baseB + wc + gp(a.ktab)[2 * j + 1]]) : x;
     }
     return acc;
 }
@@ -444,7 +590,7 @@ __device__ void contract_range(const ContractArgs &a, int64_t u0, int64_t u1) {
     if (MODE == kModeStreamW) {
         for (int64_t g = u0 + threadIdx.x; g < u1; g += blockDim.x) {
             const int64_t row = g / a.c_row_words, wc = g % a.c_row_words;
-            a.C[row * a.c_row_words + wc] = streamw_word(a, row, wc);
+            gp(a.C)[row * a.c_row_words + wc] = streamw_word(a, row, wc);
         }
         return;
     }
@@ -465,9 +611,9 @@ __device__ void contract_range(const ContractArgs &a, int64_t u0, int64_t u1) {
         const unsigned long long bits = __ballot(acc != 0);
         if ((threadIdx.x & 63) == 0 && gid < total && gid < u1) {
             if (a.nout == 0) {
-                a.C[0] = (uint32_t)(bits & 1ull);
+                gp(a.C)[0] = (uint32_t)(bits & 1ull);
             } else {
-                uint32_t *dst = a.C + row * a.c_row_words + bit / 32;
+                PA_G uint32_t *dst = gp(a.C) + row * a.c_row_words + bit / 32;
                 dst[0] = (uint32_t)bits;
                 dst[1] = (uint32_t)(bits >> 32);
             }
@@ -510,16 +656,19 @@ constexpr int kChunk = 8;      // K words staged per iteration (256 Boolean k)
 constexpr int kPitch = 12;     // LDS row pitch in words: 16-byte reads of 8 rows hit distinct banks
 constexpr int kGemmLdsWords = 4 * kTile * kPitch;   // A and B, double-buffered
 
-__device__ __forceinline__ uint4 load_row4(const uint32_t *__restrict__ p, int64_t kw, int64_t kend, bool ok,
+__device__ __forceinline__ uint4 load_row4(const PA_G uint32_t *__restrict__ p, int64_t kw, int64_t kend, bool ok,
                                            bool vec4) {
     uint4 v = make_uint4(0u, 0u, 0u, 0u);
     if (!ok) return v;
     if (vec4) {
-        if (kw + 3 < kend) return *reinterpret_cast<const uint4 *>(p + kw);
+        if (kw + 3 < kend) {
+            const u32x4 t = *reinterpret_cast<const PA_G u32x4 *>(p + kw);
+            return make_uint4(t.x, t.y, t.z, t.w);
+        }
     }
     // rows are an even number of words: pairs are 8-byte aligned
-    if (kw + 1 < kend) { const uint2 t = *reinterpret_cast<const uint2 *>(p + kw); v.x = t.x; v.y = t.y; }
-    if (kw + 3 < kend) { const uint2 t = *reinterpret_cast<const uint2 *>(p + kw + 2); v.z = t.x; v.w = t.y; }
+    if (kw + 1 < kend) { const u32x2 t = *reinterpret_cast<const PA_G u32x2 *>(p + kw); v.x = t.x; v.y = t.y; }
+    if (kw + 3 < kend) { const u32x2 t = *reinterpret_cast<const PA_G u32x2 *>(p + kw + 2); v.z = t.x; v.w = t.y; }
     return v;
 }
 
@@ -552,11 +701,11 @@ __device__ void gemm_tile(const GemmArgs &g, int64_t b, int64_t tm, int64_t tn, 
     const int lrow = tid >> 1, lw = (tid & 1) * 4;
     const int64_t am = m0 + lrow;
     const bool a_ok = am < g.M;
-    const uint32_t *aptr = g.A + b * g.sA_b + (a_ok ? am : 0) * g.Kw;
+    const PA_G uint32_t *aptr = gp(g.A) + b * g.sA_b + (a_ok ? am : 0) * g.Kw;
     const int64_t bn = n0 + lrow;
     const int64_t bno = bn / Wc, bj = bn % Wc;
     const bool b_ok = (bno < g.No) && (bj < g.rn);
-    const uint32_t *bptr = g.B + b * g.sB_b + (b_ok ? (bno * g.rn + bj) : 0) * g.Kw;
+    const PA_G uint32_t *bptr = gp(g.B) + b * g.sB_b + (b_ok ? (bno * g.rn + bj) : 0) * g.Kw;
 
     uint32_t msk[4];
     for (int j = 0; j < 4; ++j) msk[j] = 0x01010101u << (4 * h + j);
@@ -639,9 +788,9 @@ __device__ void gemm_tile(const GemmArgs &g, int64_t b, int64_t tm, int64_t tn, 
                 const int64_t n = n0 + wn * 64 + j * 32;
                 const int64_t no = n / Wc, wc = (n % Wc) / 32;
                 if (m < g.M && no < g.No) {
-                    uint32_t *dst = g.C + b * g.sC_b + (m * g.No + no) * g.rwc + wc;
+                    PA_G uint32_t *dst = gp(g.C) + b * g.sC_b + (m * g.No + no) * g.rwc + wc;
                     if (g.ksplit > 1) {
-                        if (mask) atomicOr(dst, mask);
+                        if (mask) __hip_atomic_fetch_or(dst, mask, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     } else {
                         *dst = mask;
                     }
@@ -728,7 +877,8 @@ __device__ __forceinline__ int find_step(const PStep *steps, int first, int coun
 __device__ __forceinline__ void run_tile(const PStep &st, int64_t tile, uint32_t *lds, PlotCount &cnt) {
     switch (st.kind) {
         case kStepPlot:
-            plot_tile(st.plot, tile, reinterpret_cast<float *>(lds), cnt);
+            plot_tile(st.plot, tile, reinterpret_cast<float *>(lds), reinterpret_cast<double *>(lds + kPlotLineWords),
+                      cnt);
             break;
         case kStepGemm: {
             const GemmArgs g = st.gemm;
@@ -745,7 +895,7 @@ __device__ __forceinline__ void run_tile(const PStep &st, int64_t tile, uint32_t
         }
         default: {
             const int64_t u0 = tile * st.per_tile, u1 = min(st.units, u0 + st.per_tile);
-            for (int64_t i = u0 + threadIdx.x; i < u1; i += blockDim.x) st.fill_ptr[i] = 0u;
+            for (int64_t i = u0 + threadIdx.x; i < u1; i += blockDim.x) gp(st.fill_ptr)[i] = 0u;
             break;
         }
     }
@@ -756,13 +906,14 @@ template <int KIND>
 __global__ __launch_bounds__(256) void k_group(const PStep *__restrict__ steps, int first, int count, int64_t t0,
                                                int64_t t1, PlotCounters *counters) {
     constexpr int kind = KIND % 10, mode = KIND / 10;
-    constexpr int kWords = kind == kStepGemm ? kGemmLdsWords : (kind == kStepPlot ? kMaxTileLines * kLineFloats : 1);
+    constexpr int kWords = kind == kStepGemm ? kGemmLdsWords : (kind == kStepPlot ? kPlotLdsWords : 1);
     __shared__ __attribute__((aligned(16))) uint32_t lds[kWords];
     PlotCount cnt;
     for (int64_t item = t0 + blockIdx.x; item < t1; item += gridDim.x) {
         const PStep &st = steps[find_step(steps, first, count, item)];
         if (kind == kStepPlot) {
-            plot_tile(st.plot, item - st.tile_base, reinterpret_cast<float *>(lds), cnt);
+            plot_tile(st.plot, item - st.tile_base, reinterpret_cast<float *>(lds),
+                      reinterpret_cast<double *>(lds + kPlotLineWords), cnt);
         } else if (kind == kStepGemm) {
             const GemmArgs g = st.gemm;
             int64_t b, tm, tn;
@@ -774,7 +925,7 @@ __global__ __launch_bounds__(256) void k_group(const PStep *__restrict__ steps, 
             contract_range<mode>(st.ca, u0, min(st.units, u0 + st.per_tile));
         } else {
             const int64_t u0 = (item - st.tile_base) * st.per_tile, u1 = min(st.units, u0 + st.per_tile);
-            for (int64_t i = u0 + threadIdx.x; i < u1; i += blockDim.x) st.fill_ptr[i] = 0u;
+            for (int64_t i = u0 + threadIdx.x; i < u1; i += blockDim.x) gp(st.fill_ptr)[i] = 0u;
         }
         __syncthreads();
     }
@@ -817,9 +968,8 @@ constexpr long long kSpinLimit = 1ll << 26;
 __global__ __launch_bounds__(256) void k_persist(const PStep *__restrict__ steps, int nsteps, int64_t n_items,
                                                  PersistState *state, unsigned int *done,
                                                  PlotCounters *counters) {
-    __shared__ __attribute__((aligned(16))) uint32_t lds[kGemmLdsWords > kMaxTileLines * kLineFloats
-                                                             ? kGemmLdsWords
-                                                             : kMaxTileLines * kLineFloats];
+    __shared__ __attribute__((aligned(16))) uint32_t lds[kGemmLdsWords > kPlotLdsWords ? kGemmLdsWords
+                                                                                       : kPlotLdsWords];
     __shared__ long long s_item;
     __shared__ int s_ok;
     PlotCount cnt;

@@ -663,6 +663,7 @@ int build_plan(const pa_system *sys, const int32_t *exposed, int32_t n_exposed, 
         R.vmax = vmax * (1.0 + 0x1p-50) + 0x1p-1000;
         R.out = reinterpret_cast<uint32_t *>((size_t)P->buf_off[it.buf]);
         plot_tiling(R, P->plot_strip);
+        if (R.n_tiles >= ((int64_t)1 << 31)) return fail(PA_EUNSUPPORTED, "relation too large to plot in one array");
         P->plotrel_host.push_back(R);
     }
     int64_t tb = 0;
