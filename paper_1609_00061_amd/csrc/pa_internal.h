@@ -48,6 +48,30 @@ struct PlotCounters {
     unsigned long long pad;
 };
 
+// Division by a value fixed at plan time, for 0 <= n < 2^31 and
+// 1 <= d < 2^31: q = floor(n * m / 2^(31 + s)) with s = ceil(log2 d) and
+// m = ceil(2^(31+s) / d) < 2^32 (Granlund and Montgomery, "Division by
+// invariant integers using multiplication", 1994).  The error term
+// n (m d - 2^(31+s)) / (d 2^(31+s)) is below 2^-s <= 1/d, so the floor is
+// exact.
+struct FastDiv {
+    uint32_t d, m, s;
+};
+
+inline FastDiv make_fastdiv(uint64_t d) {
+    FastDiv f;
+    f.d = (uint32_t)d;
+    uint32_t s = 0;
+    while ((1ull << s) < d) ++s;
+    f.s = s;
+    f.m = (uint32_t)(((1ull << (31 + s)) + d - 1) / d);
+    return f;
+}
+
+__host__ __device__ inline uint32_t fdiv(uint32_t n, const FastDiv &f) {
+    return (uint32_t)(((uint64_t)n * f.m) >> (31 + f.s));
+}
+
 // General strided bitwise contraction C(out) = OR_k A AND B.  Each variable of
 // the output or of the latent set has, per operand, either a word stride
 // (non-packed axis of that operand, 0 if absent) or is that operand's packed
@@ -70,6 +94,10 @@ struct ContractArgs {
     // packed latent axis (mode K), precomputed on the host
     const int64_t *ktab;
     int64_t nktab;
+    // divisions by out_dim[i], by the output row length in bits and in
+    // words (output rows and row offsets are below 2^31, checked on the host)
+    FastDiv fd_dim[kMaxDim];
+    FastDiv fd_rowbits, fd_rowwords;
 };
 
 // Dense Boolean GEMM in canonical layout:
@@ -84,6 +112,9 @@ struct GemmArgs {
     int64_t tiles_m, tiles_n; // 128-row and 128-column tiles (N in padded coordinates)
     int64_t kchunk;           // words per K split (multiple of 8)
     int ksplit;               // >1: partial results OR-ed with atomics into zeroed C
+    // divisions of the tile index (below 2^31) and of N coordinates by the
+    // padded C row length in bits (below 2^31), checked on the host
+    FastDiv fd_ksplit, fd_tiles_n, fd_tiles_m, fd_wc;
 };
 
 enum ContractMode { kModeBits = 0, kModeStreamK = 1, kModeStreamW = 2 };

@@ -497,10 +497,12 @@ __device__ __forceinline__ OutPos out_pos(const ContractArgs &a, int64_t row, in
         if (a.a_pk_out == last) p.pa = bit;
         if (a.b_pk_out == last) p.pb = bit;
     }
-    int64_t rem = row;
+    // output rows are below 2^31 (checked on the host)
+    uint32_t rem = (uint32_t)row;
     for (int i = a.nout - 2; i >= 0; --i) {
-        const int64_t ci = rem % a.out_dim[i];
-        rem /= a.out_dim[i];
+        const uint32_t q = fdiv(rem, a.fd_dim[i]);
+        const int64_t ci = rem - q * (uint32_t)a.out_dim[i];
+        rem = q;
         p.baseA += ci * a.a_str[i];
         p.baseB += ci * a.b_str[i];
         if (a.a_pk_out == i) p.pa = ci;
@@ -587,10 +589,16 @@ __device__ uint32_t streamw_word(const ContractArgs &a, int64_t row, int64_t wc)
 // the bit-out modes (u0, u1 multiples of 64 or the end), words for mode W.
 template <int MODE>
 __device__ void contract_range(const ContractArgs &a, int64_t u0, int64_t u1) {
+    // the row of the block's first unit by one (uniform) division per step,
+    // each thread's offset from it by a 32-bit fast division
     if (MODE == kModeStreamW) {
-        for (int64_t g = u0 + threadIdx.x; g < u1; g += blockDim.x) {
-            const int64_t row = g / a.c_row_words, wc = g % a.c_row_words;
-            gp(a.C)[row * a.c_row_words + wc] = streamw_word(a, row, wc);
+        const int64_t crw = a.c_row_words;
+        for (int64_t g0 = u0; g0 < u1; g0 += blockDim.x) {
+            const int64_t row0 = g0 / crw;
+            const uint32_t off = (uint32_t)(g0 - row0 * crw) + threadIdx.x;
+            const uint32_t q = fdiv(off, a.fd_rowwords);
+            const int64_t row = row0 + q, wc = off - q * (uint32_t)crw;
+            if (g0 + threadIdx.x < u1) gp(a.C)[row * crw + wc] = streamw_word(a, row, wc);
         }
         return;
     }
@@ -599,7 +607,10 @@ __device__ void contract_range(const ContractArgs &a, int64_t u0, int64_t u1) {
     const bool vec4 = (a.a_row_words % 4) == 0;
     for (int64_t g0 = u0; g0 < u1; g0 += blockDim.x) {
         const int64_t gid = g0 + threadIdx.x;
-        const int64_t row = gid / rowbits, bit = gid % rowbits;
+        const int64_t row0 = g0 / rowbits;
+        const uint32_t off = (uint32_t)(g0 - row0 * rowbits) + threadIdx.x;
+        const uint32_t q = fdiv(off, a.fd_rowbits);
+        const int64_t row = row0 + q, bit = off - q * (uint32_t)rowbits;
         bool valid;
         if (a.nout == 0) valid = (gid == 0);
         else valid = (gid < u1) && (row < a.n_out_rows) && (bit < a.out_dim[a.nout - 1]);
@@ -685,111 +696,73 @@ __device__ __forceinline__ v4i spread(uint32_t x, const uint32_t *m) {
     return r;
 }
 
-// One 128x128 output tile (batch b, tile row tm, tile column tn, K split ks)
-// of the canonical Boolean GEMM.  lds holds kGemmLdsWords words.
-__device__ void gemm_tile(const GemmArgs &g, int64_t b, int64_t tm, int64_t tn, int ks, uint32_t *lds) {
-    uint32_t *sA0 = lds, *sA1 = lds + kTile * kPitch, *sB0 = lds + 2 * kTile * kPitch, *sB1 = lds + 3 * kTile * kPitch;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = wave >> 1, wn = wave & 1;
-    const int h = lane >> 5, l32 = lane & 31;
-    const int64_t m0 = tm * kTile, n0 = tn * kTile;
-    const int64_t Wc = g.rwc * 32;
-    const int64_t kw0 = (int64_t)ks * g.kchunk;
-    const int64_t kw1 = min(g.Kw, kw0 + g.kchunk);
-    const bool vec4 = (g.Kw % 4) == 0;
+// One tile of a Boolean GEMM as the loaders and the epilogue see it.
+// Loader thread tid stages row (tid >> 1), words (tid & 1) * 4 .. + 3 of each
+// K chunk, for A and for B.
+struct GemmTileRef {
+    const PA_G uint32_t *a, *b;   // this thread's A and B rows
+    PA_G uint32_t *c;             // C of the tile's batch
+    int64_t kw0, kw1;             // K range (words)
+    int64_t m0, n0, M, No, rwc;
+    FastDiv fd_wc;                // division by the padded C row length in bits
+    bool a_ok, b_ok, vec4, atomic;
+};
 
-    const int lrow = tid >> 1, lw = (tid & 1) * 4;
-    const int64_t am = m0 + lrow;
-    const bool a_ok = am < g.M;
-    const PA_G uint32_t *aptr = gp(g.A) + b * g.sA_b + (a_ok ? am : 0) * g.Kw;
-    const int64_t bn = n0 + lrow;
-    const int64_t bno = bn / Wc, bj = bn % Wc;
-    const bool b_ok = (bno < g.No) && (bj < g.rn);
-    const PA_G uint32_t *bptr = gp(g.B) + b * g.sB_b + (b_ok ? (bno * g.rn + bj) : 0) * g.Kw;
+__device__ __forceinline__ GemmTileRef gemm_locate(const GemmArgs &g, int64_t t64) {
+    GemmTileRef r;
+    // tile index and N coordinates are below 2^31 (checked on the host)
+    const uint32_t t = (uint32_t)t64;
+    const uint32_t q1 = fdiv(t, g.fd_ksplit);
+    const int ks = (int)(t - q1 * (uint32_t)g.ksplit);
+    const uint32_t q2 = fdiv(q1, g.fd_tiles_n);
+    const int64_t tn = q1 - q2 * (uint32_t)g.tiles_n;
+    const uint32_t q3 = fdiv(q2, g.fd_tiles_m);
+    const int64_t tm = q2 - q3 * (uint32_t)g.tiles_m;
+    const int64_t b = q3;
+    const int lrow = threadIdx.x >> 1;
+    r.m0 = tm * kTile;
+    r.n0 = tn * kTile;
+    r.kw0 = (int64_t)ks * g.kchunk;
+    r.kw1 = min(g.Kw, r.kw0 + g.kchunk);
+    r.vec4 = (g.Kw % 4) == 0;
+    const int64_t am = r.m0 + lrow;
+    r.a_ok = am < g.M;
+    r.a = gp(g.A) + b * g.sA_b + (r.a_ok ? am : 0) * g.Kw;
+    const uint32_t Wc = (uint32_t)(g.rwc * 32);
+    const uint32_t bn = (uint32_t)(r.n0 + lrow);
+    const uint32_t bno = fdiv(bn, g.fd_wc), bj = bn - bno * Wc;
+    r.b_ok = (bno < g.No) && (bj < g.rn);
+    r.b = gp(g.B) + b * g.sB_b + (r.b_ok ? (bno * g.rn + bj) : 0) * g.Kw;
+    r.c = gp(g.C) + b * g.sC_b;
+    r.M = g.M;
+    r.No = g.No;
+    r.rwc = g.rwc;
+    r.fd_wc = g.fd_wc;
+    r.atomic = g.ksplit > 1;
+    return r;
+}
 
-    uint32_t msk[4];
-    for (int j = 0; j < 4; ++j) msk[j] = 0x01010101u << (4 * h + j);
-
-    v16i acc[2][2];
-    for (int i = 0; i < 2; ++i)
-        for (int j = 0; j < 2; ++j)
-            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0;
-
-    int cur = 0;
-    if (kw0 < kw1) {
-        const uint4 ra = load_row4(aptr, kw0 + lw, kw1, a_ok, vec4);
-        const uint4 rb = load_row4(bptr, kw0 + lw, kw1, b_ok, vec4);
-        *reinterpret_cast<uint4 *>(&sA0[lrow * kPitch + lw]) = ra;
-        *reinterpret_cast<uint4 *>(&sB0[lrow * kPitch + lw]) = rb;
-    }
-    __syncthreads();
-    for (int64_t kc = kw0; kc < kw1; kc += kChunk) {
-        const bool more = kc + kChunk < kw1;
-        uint4 na = make_uint4(0u, 0u, 0u, 0u), nb = make_uint4(0u, 0u, 0u, 0u);
-        if (more) {
-            na = load_row4(aptr, kc + kChunk + lw, kw1, a_ok, vec4);
-            nb = load_row4(bptr, kc + kChunk + lw, kw1, b_ok, vec4);
-        }
-        const uint32_t *sA = cur ? sA1 : sA0;
-        const uint32_t *sB = cur ? sB1 : sB0;
-#pragma unroll
-        for (int q4 = 0; q4 < kChunk; q4 += 4) {
-            uint4 a4[2], b4[2];
-#pragma unroll
-            for (int i = 0; i < 2; ++i)
-                a4[i] = *reinterpret_cast<const uint4 *>(&sA[(wm * 64 + i * 32 + l32) * kPitch + q4]);
-#pragma unroll
-            for (int j = 0; j < 2; ++j)
-                b4[j] = *reinterpret_cast<const uint4 *>(&sB[(wn * 64 + j * 32 + l32) * kPitch + q4]);
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                v4i opa[2], opb[2];
-#pragma unroll
-                for (int i = 0; i < 2; ++i) {
-                    const uint32_t x = q == 0 ? a4[i].x : q == 1 ? a4[i].y : q == 2 ? a4[i].z : a4[i].w;
-                    opa[i] = spread(x, msk);
-                }
-#pragma unroll
-                for (int j = 0; j < 2; ++j) {
-                    const uint32_t y = q == 0 ? b4[j].x : q == 1 ? b4[j].y : q == 2 ? b4[j].z : b4[j].w;
-                    opb[j] = spread(y, msk);
-                }
-                // MFMA rows index n (from B), columns index m (from A): each lane
-                // then holds one column m, i.e. bits of one output row.
-#pragma unroll
-                for (int i = 0; i < 2; ++i)
-#pragma unroll
-                    for (int j = 0; j < 2; ++j)
-                        acc[i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(opb[j], opa[i], acc[i][j], 0, 0, 0);
-            }
-        }
-        if (more) {
-            uint32_t *dA = cur ? sA0 : sA1;
-            uint32_t *dB = cur ? sB0 : sB1;
-            *reinterpret_cast<uint4 *>(&dA[lrow * kPitch + lw]) = na;
-            *reinterpret_cast<uint4 *>(&dB[lrow * kPitch + lw]) = nb;
-        }
-        __syncthreads();
-        cur ^= 1;
-    }
-    // Epilogue: accumulator register r of a 32x32 block holds MFMA row
-    // 8*(r/4) + 4*h + r%4 (our n) at MFMA column l32 (our m).
+// Writes one tile's packed output words: accumulator register r of a 32x32
+// block holds MFMA row 8*(r/4) + 4*h + r%4 (our n) at MFMA column l32 (our m).
+__device__ __forceinline__ void gemm_epilogue(const GemmTileRef &T, v16i (&acc)[2][2]) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wm = wave >> 1, wn = wave & 1, h = lane >> 5, l32 = lane & 31;
+    const uint32_t Wc = (uint32_t)(T.rwc * 32);
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
             uint32_t mask = 0;
 #pragma unroll
-            for (int r = 0; r < 16; ++r)
-                mask |= (acc[i][j][r] > 0 ? 1u : 0u) << (8 * (r >> 2) + 4 * h + (r & 3));
+            for (int r = 0; r < 16; ++r) mask |= (acc[i][j][r] > 0 ? 1u : 0u) << (8 * (r >> 2) + 4 * h + (r & 3));
             mask |= __shfl_xor(mask, 32);
             if (h == 0) {
-                const int64_t m = m0 + wm * 64 + i * 32 + l32;
-                const int64_t n = n0 + wn * 64 + j * 32;
-                const int64_t no = n / Wc, wc = (n % Wc) / 32;
-                if (m < g.M && no < g.No) {
-                    PA_G uint32_t *dst = gp(g.C) + b * g.sC_b + (m * g.No + no) * g.rwc + wc;
-                    if (g.ksplit > 1) {
+                const int64_t m = T.m0 + wm * 64 + i * 32 + l32;
+                const uint32_t n = (uint32_t)(T.n0 + wn * 64 + j * 32);
+                const uint32_t no = fdiv(n, T.fd_wc), wc = (n - no * Wc) / 32;
+                if (m < T.M && no < T.No) {
+                    PA_G uint32_t *dst = T.c + (m * T.No + no) * T.rwc + wc;
+                    if (T.atomic) {
                         if (mask) __hip_atomic_fetch_or(dst, mask, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     } else {
                         *dst = mask;
@@ -800,33 +773,138 @@ __device__ void gemm_tile(const GemmArgs &g, int64_t b, int64_t tm, int64_t tn, 
     }
 }
 
-__device__ __forceinline__ void gemm_decode(const GemmArgs &g, int64_t t, int64_t &b, int64_t &tm, int64_t &tn,
-                                            int &ks) {
-    ks = (int)(t % g.ksplit);
-    t /= g.ksplit;
-    tn = t % g.tiles_n;
-    t /= g.tiles_n;
-    tm = t % g.tiles_m;
-    b = t / g.tiles_m;
+// MFMAs of one staged K chunk (kChunk words of A and B in LDS).
+__device__ __forceinline__ void gemm_chunk(const uint32_t *sA, const uint32_t *sB, const uint32_t *msk,
+                                           v16i (&acc)[2][2]) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wm = wave >> 1, wn = wave & 1, l32 = lane & 31;
+    // one 4-word step at a time keeps the spread operands of a single step live
+#pragma unroll 1
+    for (int q4 = 0; q4 < kChunk; q4 += 4) {
+        uint4 a4[2], b4[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+            a4[i] = *reinterpret_cast<const uint4 *>(&sA[(wm * 64 + i * 32 + l32) * kPitch + q4]);
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+            b4[j] = *reinterpret_cast<const uint4 *>(&sB[(wn * 64 + j * 32 + l32) * kPitch + q4]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            v4i opa[2], opb[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const uint32_t x = q == 0 ? a4[i].x : q == 1 ? a4[i].y : q == 2 ? a4[i].z : a4[i].w;
+                opa[i] = spread(x, msk);
+            }
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const uint32_t y = q == 0 ? b4[j].x : q == 1 ? b4[j].y : q == 2 ? b4[j].z : b4[j].w;
+                opb[j] = spread(y, msk);
+            }
+            // MFMA rows index n (from B), columns index m (from A): each lane
+            // then holds one column m, i.e. bits of one output row.
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(opb[j], opa[i], acc[i][j], 0, 0, 0);
+        }
+    }
 }
 
-__global__ __launch_bounds__(256) void k_gemm_mfma(GemmArgs g) {
+// 128x128 output tiles of the canonical Boolean GEMM, one after another,
+// software-pipelined across tile boundaries: the next K chunk -- of the same
+// tile, or the first chunk of the next tile -- is loaded into registers while
+// the current one is multiplied, and staged in the other LDS buffer.
+// next(T) yields the workgroup's next tile (returns false when done).  lds
+// holds kGemmLdsWords words.
+template <class Next>
+__device__ void gemm_tiles(Next next, uint32_t *lds) {
+    uint32_t *sA[2] = {lds, lds + kTile * kPitch};
+    uint32_t *sB[2] = {lds + 2 * kTile * kPitch, lds + 3 * kTile * kPitch};
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int h = lane >> 5;
+    const int lrow = tid >> 1, lw = (tid & 1) * 4;
+    uint32_t msk[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) msk[j] = 0x01010101u << (4 * h + j);
+    GemmTileRef T;
+    if (!next(T)) return;
+    int64_t kc = T.kw0;
+    uint4 ra = load_row4(T.a, kc + lw, T.kw1, T.a_ok, T.vec4);
+    uint4 rb = load_row4(T.b, kc + lw, T.kw1, T.b_ok, T.vec4);
+    v16i acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0;
+    int cur = 0;
+    for (;;) {
+        *reinterpret_cast<uint4 *>(&sA[cur][lrow * kPitch + lw]) = ra;
+        *reinterpret_cast<uint4 *>(&sB[cur][lrow * kPitch + lw]) = rb;
+        __syncthreads();
+        // next chunk: of this tile, else the first chunk of the next tile
+        const bool last = kc + kChunk >= T.kw1;
+        GemmTileRef N = T;
+        bool more = true;
+        int64_t kn = kc + kChunk;
+        if (last) {
+            more = next(N);
+            kn = N.kw0;
+        }
+        if (more) {
+            ra = load_row4(N.a, kn + lw, N.kw1, N.a_ok, N.vec4);
+            rb = load_row4(N.b, kn + lw, N.kw1, N.b_ok, N.vec4);
+        }
+        gemm_chunk(sA[cur], sB[cur], msk, acc);
+        if (last) {
+            gemm_epilogue(T, acc);
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) acc[i][j][r] = 0;
+        }
+        if (!more) break;
+        T = N;
+        kc = kn;
+        cur ^= 1;
+    }
+}
+
+__global__ __launch_bounds__(256, 3) void k_gemm_mfma(GemmArgs g) {
     __shared__ __attribute__((aligned(16))) uint32_t lds[kGemmLdsWords];
     const int64_t ntiles = g.nbatch * g.tiles_m * g.tiles_n * g.ksplit;
-    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        int64_t b, tm, tn;
-        int ks;
-        gemm_decode(g, t, b, tm, tn, ks);
-        gemm_tile(g, b, tm, tn, ks, lds);
-        __syncthreads();
+    int64_t t = blockIdx.x;
+    auto next = [&](GemmTileRef &T) {
+        if (t >= ntiles) return false;
+        T = gemm_locate(g, t);
+        t += gridDim.x;
+        return true;
+    };
+    gemm_tiles(next, lds);
+}
+
+// Workgroups of a persistent tile loop: every CU's worth, capped by the tiles.
+static int64_t gemm_grid(int64_t ntiles) {
+    static int cached = 0;
+    if (!cached) {
+        int dev = 0, cus = 256, per_cu = 1;
+        if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_gemm_mfma, 256, 0) != hipSuccess || per_cu < 1)
+            per_cu = 1;
+        cached = cus * per_cu;
     }
+    return ntiles < cached ? ntiles : cached;
 }
 
 hipError_t launch_gemm(const GemmArgs &g, hipStream_t s) {
     if (g.nbatch == 0 || g.M == 0 || g.No == 0) return hipSuccess;
     const int64_t nt = g.nbatch * g.tiles_m * g.tiles_n * g.ksplit;
-    const int64_t blocks = nt < (1 << 20) ? nt : (1 << 20);
-    hipLaunchKernelGGL(k_gemm_mfma, dim3((unsigned)blocks), dim3(256), 0, s, g);
+    hipLaunchKernelGGL(k_gemm_mfma, dim3((unsigned)gemm_grid(nt)), dim3(256), 0, s, g);
     return hipGetLastError();
 }
 
@@ -881,11 +959,14 @@ __device__ __forceinline__ void run_tile(const PStep &st, int64_t tile, uint32_t
                       cnt);
             break;
         case kStepGemm: {
-            const GemmArgs g = st.gemm;
-            int64_t b, tm, tn;
-            int ks;
-            gemm_decode(g, tile, b, tm, tn, ks);
-            gemm_tile(g, b, tm, tn, ks, lds);
+            bool once = true;
+            auto next = [&](GemmTileRef &T) {
+                if (!once) return false;
+                T = gemm_locate(st.gemm, tile);
+                once = false;
+                return true;
+            };
+            gemm_tiles(next, lds);
             break;
         }
         case kStepContract: {
@@ -903,23 +984,30 @@ __device__ __forceinline__ void run_tile(const PStep &st, int64_t tile, uint32_t
 
 // KIND: a StepKind; for contractions the mode is fixed too (kind 2 + 10 * mode).
 template <int KIND>
-__global__ __launch_bounds__(256) void k_group(const PStep *__restrict__ steps, int first, int count, int64_t t0,
+__global__ __launch_bounds__(256, KIND == kStepGemm ? 3 : 1) void k_group(const PStep *__restrict__ steps, int first, int count, int64_t t0,
                                                int64_t t1, PlotCounters *counters) {
     constexpr int kind = KIND % 10, mode = KIND / 10;
     constexpr int kWords = kind == kStepGemm ? kGemmLdsWords : (kind == kStepPlot ? kPlotLdsWords : 1);
     __shared__ __attribute__((aligned(16))) uint32_t lds[kWords];
+    if (kind == kStepGemm) {
+        // persistent tile loop with cross-tile prefetch
+        int64_t item = t0 + blockIdx.x;
+        auto next = [&](GemmTileRef &T) {
+            if (item >= t1) return false;
+            const PStep &st = steps[find_step(steps, first, count, item)];
+            T = gemm_locate(st.gemm, item - st.tile_base);
+            item += gridDim.x;
+            return true;
+        };
+        gemm_tiles(next, lds);
+        return;
+    }
     PlotCount cnt;
     for (int64_t item = t0 + blockIdx.x; item < t1; item += gridDim.x) {
         const PStep &st = steps[find_step(steps, first, count, item)];
         if (kind == kStepPlot) {
             plot_tile(st.plot, item - st.tile_base, reinterpret_cast<float *>(lds),
                       reinterpret_cast<double *>(lds + kPlotLineWords), cnt);
-        } else if (kind == kStepGemm) {
-            const GemmArgs g = st.gemm;
-            int64_t b, tm, tn;
-            int ks;
-            gemm_decode(g, item - st.tile_base, b, tm, tn, ks);
-            gemm_tile(g, b, tm, tn, ks, lds);
         } else if (kind == kStepContract) {
             const int64_t u0 = (item - st.tile_base) * st.per_tile;
             contract_range<mode>(st.ca, u0, min(st.units, u0 + st.per_tile));
@@ -936,7 +1024,7 @@ hipError_t launch_group(int kind, int mode, const PStep *d_steps, int first, int
                         PlotCounters *counters, hipStream_t s) {
     if (t1 <= t0) return hipSuccess;
     const int64_t nt = t1 - t0;
-    const dim3 grid((unsigned)(nt < (1 << 20) ? nt : (1 << 20)));
+    const dim3 grid((unsigned)(kind == kStepGemm ? gemm_grid(nt) : (nt < (1 << 20) ? nt : (1 << 20))));
 #define PA_GROUP(K) hipLaunchKernelGGL(k_group<K>, grid, dim3(256), 0, s, d_steps, first, count, t0, t1, counters)
     switch (kind) {
         case kStepPlot: PA_GROUP(kStepPlot); break;

@@ -330,6 +330,10 @@ struct Builder {
         ksplit = (g.Kw + chunk - 1) / chunk;
         g.kchunk = chunk;
         g.ksplit = (int)std::max<int64_t>(1, ksplit);
+        g.fd_ksplit = make_fastdiv((uint64_t)g.ksplit);
+        g.fd_tiles_n = make_fastdiv((uint64_t)std::max<int64_t>(1, g.tiles_n));
+        g.fd_tiles_m = make_fastdiv((uint64_t)std::max<int64_t>(1, g.tiles_m));
+        g.fd_wc = make_fastdiv((uint64_t)(g.rwc * 32));
         if (g.ksplit > 1) {
             Op f;
             f.kind = OP_FILL;
@@ -474,6 +478,9 @@ static void finish_contract(Op &op, bool has_b) {
         }
     }
     a.nktab = (int64_t)op.ktab.size() / 2;
+    for (int i = 0; i < a.nout; ++i) a.fd_dim[i] = make_fastdiv((uint64_t)std::max<int64_t>(1, a.out_dim[i]));
+    a.fd_rowbits = make_fastdiv((uint64_t)std::max<int64_t>(1, a.c_row_words * 32));
+    a.fd_rowwords = make_fastdiv((uint64_t)std::max<int64_t>(1, a.c_row_words));
 }
 
 static std::string join(const std::vector<int> &v) {
@@ -692,6 +699,12 @@ static int check_contract_bounds(const ContractArgs &a, int64_t a_words, int64_t
     const int64_t mc = (a.nout == 0) ? 0 : a.n_out_rows * a.c_row_words - 1;
     if (ma >= a_words || (has_b && mb >= b_words) || mc >= c_words || ma < 0 || mb < 0)
         return fail(PA_EINVAL, "internal: contraction would index outside its buffers");
+    // the kernels divide output rows and row offsets in 32 bits
+    const int64_t lim = (int64_t)1 << 31;
+    if (a.n_out_rows >= lim || a.c_row_words * 32 + 1024 >= lim)
+        return fail(PA_EUNSUPPORTED, "contraction output has too many rows for one array");
+    for (int i = 0; i < a.nout; ++i)
+        if (a.out_dim[i] >= lim) return fail(PA_EUNSUPPORTED, "contraction output dimension too large");
     return PA_OK;
 }
 
@@ -701,6 +714,10 @@ static int check_gemm_bounds(const GemmArgs &g, int64_t a_words, int64_t b_words
         g.rwc != row_words_of(g.rn) || ma > a_words || mb > b_words || mc > c_words || g.kchunk % 8 ||
         g.kchunk > 16384 || (int64_t)g.ksplit * g.kchunk < g.Kw)
         return fail(PA_EINVAL, "internal: GEMM would index outside its buffers");
+    // the kernels decode tile indices and N coordinates in 32 bits
+    const int64_t lim = (int64_t)1 << 31;
+    if (g.nbatch * g.tiles_m * g.tiles_n * g.ksplit >= lim || g.tiles_n * 128 + 128 >= lim)
+        return fail(PA_EUNSUPPORTED, "GEMM too large for one launch");
     return PA_OK;
 }
 
@@ -777,8 +794,17 @@ static int build_steps(pa_plan *P) {
             s.ca.B = buf_ptr(P, op.b, nullptr);
             s.ca.C = buf_ptr(P, op.c, nullptr);
             s.units = contract_units_of(op.ca, op.mode);
-            s.per_tile = (op.mode == kModeStreamW) ? std::max<int64_t>(256, P->contract_units / 32)
-                                                   : std::max<int64_t>(256, (P->contract_units + 255) / 256 * 256);
+            {
+                // units per tile: contract_units, fewer when each unit reads
+                // many words (a tile then holds about contract_units * 64 reads)
+                const int64_t cap = (op.mode == kModeStreamW) ? std::max<int64_t>(256, P->contract_units / 32)
+                                                              : std::max<int64_t>(256, P->contract_units);
+                int64_t work = 1;
+                if (op.mode == kModeStreamK) work = std::max<int64_t>(1, op.ca.nktab * op.ca.a_row_words);
+                else if (op.mode == kModeStreamW) work = std::max<int64_t>(1, op.ca.nktab);
+                const int64_t want = std::max<int64_t>(1, (int64_t)P->contract_units * 64 / work);
+                s.per_tile = std::max<int64_t>(256, std::min<int64_t>(cap, want) / 256 * 256);
+            }
             s.n_tiles = (s.units + s.per_tile - 1) / s.per_tile;
             dep(op.a);
             dep(op.b);
