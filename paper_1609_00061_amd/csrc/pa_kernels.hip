@@ -696,6 +696,49 @@ __device__ __forceinline__ v4i spread(uint32_t x, const uint32_t *m) {
     return r;
 }
 
+// Bit word of one 32x32 accumulator block for this lane: bit
+// 8*(r/4) + r%4 set iff count r > 0 (counts are >= 0), as one v_min_u32 and
+// one v_lshl_or_b32 per count (written out: the compiler would turn min(x,1)
+// into a compare and a select).
+__device__ __forceinline__ uint32_t block_bits(const v16i &a) {
+    uint32_t m, t;
+    asm(
+        "v_min_u32 %0, 1, %2\n"
+        "v_min_u32 %1, 1, %3\n"
+        "v_lshl_or_b32 %0, %1, 1, %0\n"
+        "v_min_u32 %1, 1, %4\n"
+        "v_lshl_or_b32 %0, %1, 2, %0\n"
+        "v_min_u32 %1, 1, %5\n"
+        "v_lshl_or_b32 %0, %1, 3, %0\n"
+        "v_min_u32 %1, 1, %6\n"
+        "v_lshl_or_b32 %0, %1, 8, %0\n"
+        "v_min_u32 %1, 1, %7\n"
+        "v_lshl_or_b32 %0, %1, 9, %0\n"
+        "v_min_u32 %1, 1, %8\n"
+        "v_lshl_or_b32 %0, %1, 10, %0\n"
+        "v_min_u32 %1, 1, %9\n"
+        "v_lshl_or_b32 %0, %1, 11, %0\n"
+        "v_min_u32 %1, 1, %10\n"
+        "v_lshl_or_b32 %0, %1, 16, %0\n"
+        "v_min_u32 %1, 1, %11\n"
+        "v_lshl_or_b32 %0, %1, 17, %0\n"
+        "v_min_u32 %1, 1, %12\n"
+        "v_lshl_or_b32 %0, %1, 18, %0\n"
+        "v_min_u32 %1, 1, %13\n"
+        "v_lshl_or_b32 %0, %1, 19, %0\n"
+        "v_min_u32 %1, 1, %14\n"
+        "v_lshl_or_b32 %0, %1, 24, %0\n"
+        "v_min_u32 %1, 1, %15\n"
+        "v_lshl_or_b32 %0, %1, 25, %0\n"
+        "v_min_u32 %1, 1, %16\n"
+        "v_lshl_or_b32 %0, %1, 26, %0\n"
+        "v_min_u32 %1, 1, %17\n"
+        "v_lshl_or_b32 %0, %1, 27, %0\n"
+        : "=&v"(m), "=&v"(t)
+        : "v"(a[0]), "v"(a[1]), "v"(a[2]), "v"(a[3]), "v"(a[4]), "v"(a[5]), "v"(a[6]), "v"(a[7]), "v"(a[8]), "v"(a[9]), "v"(a[10]), "v"(a[11]), "v"(a[12]), "v"(a[13]), "v"(a[14]), "v"(a[15]));
+    return m;
+}
+
 // One tile of a Boolean GEMM as the loaders and the epilogue see it.
 // Loader thread tid stages row (tid >> 1), words (tid & 1) * 4 .. + 3 of each
 // K chunk, for A and for B.
@@ -748,14 +791,15 @@ __device__ __forceinline__ void gemm_epilogue(const GemmTileRef &T, v16i (&acc)[
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm = wave >> 1, wn = wave & 1, h = lane >> 5, l32 = lane & 31;
     const uint32_t Wc = (uint32_t)(T.rwc * 32);
+    const int xor32 = (lane ^ 32) << 2;     // ds_bpermute byte address of the other lane half
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
-            uint32_t mask = 0;
-#pragma unroll
-            for (int r = 0; r < 16; ++r) mask |= (acc[i][j][r] > 0 ? 1u : 0u) << (8 * (r >> 2) + 4 * h + (r & 3));
-            mask |= __shfl_xor(mask, 32);
+            // counts are >= 0: min(count, 1) is the bit; positions without the
+            // lane-half term are constants, the half shifts the whole word
+            uint32_t mask = block_bits(acc[i][j]) << (4 * h);
+            mask |= (uint32_t)__builtin_amdgcn_ds_bpermute(xor32, (int)mask);
             if (h == 0) {
                 const int64_t m = T.m0 + wm * 64 + i * 32 + l32;
                 const uint32_t n = (uint32_t)(T.n0 + wn * 64 + j * 32);
@@ -773,9 +817,11 @@ __device__ __forceinline__ void gemm_epilogue(const GemmTileRef &T, v16i (&acc)[
     }
 }
 
-// MFMAs of one staged K chunk (kChunk words of A and B in LDS).
+// MFMAs of one staged K chunk (kChunk words of A and B in LDS); with
+// `fresh` the first MFMA of each block starts from zero (a new tile).
 __device__ __forceinline__ void gemm_chunk(const uint32_t *sA, const uint32_t *sB, const uint32_t *msk,
-                                           v16i (&acc)[2][2]) {
+                                           v16i (&acc)[2][2], bool fresh) {
+    const v16i zero = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm = wave >> 1, wn = wave & 1, l32 = lane & 31;
     // one 4-word step at a time keeps the spread operands of a single step live
@@ -803,21 +849,35 @@ __device__ __forceinline__ void gemm_chunk(const uint32_t *sA, const uint32_t *s
             }
             // MFMA rows index n (from B), columns index m (from A): each lane
             // then holds one column m, i.e. bits of one output row.
+            if (q == 0 && q4 == 0 && fresh) {
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
+                for (int i = 0; i < 2; ++i)
 #pragma unroll
-                for (int j = 0; j < 2; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(opb[j], opa[i], acc[i][j], 0, 0, 0);
+                    for (int j = 0; j < 2; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(opb[j], opa[i], zero, 0, 0, 0);
+            } else {
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(opb[j], opa[i], acc[i][j], 0, 0, 0);
+            }
         }
     }
 }
 
-// 128x128 output tiles of the canonical Boolean GEMM, one after another,
-// software-pipelined across tile boundaries: the next K chunk -- of the same
-// tile, or the first chunk of the next tile -- is loaded into registers while
-// the current one is multiplied, and staged in the other LDS buffer.
-// next(T) yields the workgroup's next tile (returns false when done).  lds
-// holds kGemmLdsWords words.
+// One K chunk of one tile in the workgroup's sequence.
+struct GemmChunk {
+    GemmTileRef T;
+    int64_t kc;
+    bool valid;
+};
+
+// 128x128 output tiles of the canonical Boolean GEMM, one after another, as
+// a sequence of K chunks software-pipelined two deep: while chunk i is
+// multiplied from LDS, chunk i+1 is already in registers and chunk i+2 is
+// being loaded, across tile boundaries.  next(T) yields the workgroup's next
+// tile (false when done).  lds holds kGemmLdsWords words.
 template <class Next>
 __device__ void gemm_tiles(Next next, uint32_t *lds) {
     uint32_t *sA[2] = {lds, lds + kTile * kPitch};
@@ -828,50 +888,49 @@ __device__ void gemm_tiles(Next next, uint32_t *lds) {
     uint32_t msk[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) msk[j] = 0x01010101u << (4 * h + j);
-    GemmTileRef T;
-    if (!next(T)) return;
-    int64_t kc = T.kw0;
-    uint4 ra = load_row4(T.a, kc + lw, T.kw1, T.a_ok, T.vec4);
-    uint4 rb = load_row4(T.b, kc + lw, T.kw1, T.b_ok, T.vec4);
+    auto advance = [&](const GemmChunk &c) {
+        GemmChunk n = c;
+        if (!c.valid) return n;
+        n.kc = c.kc + kChunk;
+        if (n.kc >= c.T.kw1) {
+            n.valid = next(n.T);
+            n.kc = n.T.kw0;
+        }
+        return n;
+    };
+    auto load = [&](const GemmChunk &c, uint4 &ra, uint4 &rb) {
+        if (c.valid) {
+            ra = load_row4(c.T.a, c.kc + lw, c.T.kw1, c.T.a_ok, c.T.vec4);
+            rb = load_row4(c.T.b, c.kc + lw, c.T.kw1, c.T.b_ok, c.T.vec4);
+        }
+    };
+    GemmChunk c0;
+    c0.valid = next(c0.T);
+    if (!c0.valid) return;
+    c0.kc = c0.T.kw0;
+    uint4 ra0 = make_uint4(0u, 0u, 0u, 0u), rb0 = ra0, ra1 = ra0, rb1 = ra0;
+    load(c0, ra0, rb0);
+    GemmChunk c1 = advance(c0);
+    load(c1, ra1, rb1);
     v16i acc[2][2];
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-#pragma unroll
-            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0;
-    int cur = 0;
-    for (;;) {
-        *reinterpret_cast<uint4 *>(&sA[cur][lrow * kPitch + lw]) = ra;
-        *reinterpret_cast<uint4 *>(&sB[cur][lrow * kPitch + lw]) = rb;
+    // one pipeline step: stage chunk c0 (in ra/rb) into LDS buffer `buf`,
+    // start loading chunk c0+2 into ra/rb, multiply, finish a tile
+    auto step = [&](uint4 &ra, uint4 &rb, int buf) {
+        *reinterpret_cast<uint4 *>(&sA[buf][lrow * kPitch + lw]) = ra;
+        *reinterpret_cast<uint4 *>(&sB[buf][lrow * kPitch + lw]) = rb;
         __syncthreads();
-        // next chunk: of this tile, else the first chunk of the next tile
-        const bool last = kc + kChunk >= T.kw1;
-        GemmTileRef N = T;
-        bool more = true;
-        int64_t kn = kc + kChunk;
-        if (last) {
-            more = next(N);
-            kn = N.kw0;
-        }
-        if (more) {
-            ra = load_row4(N.a, kn + lw, N.kw1, N.a_ok, N.vec4);
-            rb = load_row4(N.b, kn + lw, N.kw1, N.b_ok, N.vec4);
-        }
-        gemm_chunk(sA[cur], sB[cur], msk, acc);
-        if (last) {
-            gemm_epilogue(T, acc);
-#pragma unroll
-            for (int i = 0; i < 2; ++i)
-#pragma unroll
-                for (int j = 0; j < 2; ++j)
-#pragma unroll
-                    for (int r = 0; r < 16; ++r) acc[i][j][r] = 0;
-        }
-        if (!more) break;
-        T = N;
-        kc = kn;
-        cur ^= 1;
+        const GemmChunk c2 = advance(c1);
+        load(c2, ra, rb);
+        const bool fresh = c0.kc == c0.T.kw0;
+        gemm_chunk(sA[buf], sB[buf], msk, acc, fresh);
+        if (c0.kc + kChunk >= c0.T.kw1) gemm_epilogue(c0.T, acc);
+        c0 = c1;
+        c1 = c2;
+        return c0.valid;
+    };
+    for (;;) {
+        if (!step(ra0, rb0, 0)) break;
+        if (!step(ra1, rb1, 1)) break;
     }
 }
 
