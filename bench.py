@@ -11,10 +11,12 @@ one hipGraph of level-grouped launches with autotuned tiles.
 
 Beside it: the plain GPU path on the same system, the single persistent
 launch, the batched workload (512 chains of 2-6 relations at 64..2048 cells
-per axis in one graph replay vs one plain solve per system), per-kernel
-durations and the roofline of the dominant kernel (HIP events around
-back-to-back launches of each grouped kernel on the execution stream), and
-the CPU oracle timed on a bounded sample of the chain workload.
+per axis in one graph replay vs one plain solve per system), the learned
+contraction order on random relation hypergraphs (model trained on the GPU
+from the library's own timings; every policy timed; learned order batched vs
+plain), per-kernel durations and the roofline of the dominant kernel (HIP
+events around back-to-back launches of each grouped kernel on the execution
+stream), and the CPU oracle timed on a bounded sample of the chain workload.
 """
 import argparse
 import json
@@ -149,6 +151,75 @@ def _batched(stream, K, W):
             "speedup_vs_plain": pdt / bdt, "same_bits_as_plain": same, "group_kernel_ms": kinds}
 
 
+def _learned(stream, n_train=32, n_eval=48, res=128):
+    """Random relation hypergraphs (8-14 variables, arity 2-3, 2-4 exposed,
+    128 cells/axis): the step-time model trained on the GPU from the
+    library's own timings on training graphs, then every policy timed on
+    disjoint evaluation graphs (one graph replay per solve), and the learned
+    order batched into one replay vs one plain solve per system."""
+    import torch
+    from paper_1609_00061_amd import inputs, learn, pa
+    t0 = time.perf_counter()
+    model, X, T = learn.train_order_model(inputs.config5(n_graphs=n_train, index=1000, res=res), rounds=2)
+    train_s = time.perf_counter() - t0
+    import numpy as np
+    pred = model.forward(torch.from_numpy(X).cuda()).cpu().numpy()
+    r2 = float(1.0 - np.mean((pred - T) ** 2) / np.var(T))
+    evals = inputs.config5(n_graphs=n_eval, index=0, res=res)
+    pol = learn.time_policies(evals, model, steps=3, stream=stream)
+    out = {"workload": f"{n_eval} random relation hypergraphs (8-14 variables, arity 2-3, 2-4 exposed, "
+                       f"{res} cells/axis, [-3,3]); model trained on {n_train} disjoint graphs",
+           "train_s": train_s, "train_samples": int(len(T)), "fit_r2": r2,
+           "same_bits_all_policies": pol["same_bits"], "systems": pol["systems"],
+           "skipped_enomem": pol["skipped_enomem"]}
+    for p in ("greedy", "exhaustive", "learned"):
+        out[p] = {"total_ms": pol[p]["total_ms"], "plan_ms_mean": pol[p]["plan_ms_mean"]}
+    out["learned_vs_exhaustive"] = pol["exhaustive"]["total_ms"] / pol["learned"]["total_ms"]
+    out["learned_vs_greedy"] = pol["greedy"]["total_ms"] / pol["learned"]["total_ms"]
+    # learned order + batched graph replay vs the plain path, on the systems
+    # every policy could plan
+    # (systems whose greedy plan exceeds the workspace, or whose naive cost
+    # is beyond 1e12 and would take seconds per plain solve, are left out)
+    ok = []
+    for s in evals:
+        d = pa.describe_plan(s, order=pa.ORDER_GREEDY, plain=True)
+        if "error" not in d and d["cost"] <= 1e12:
+            ok.append(s)
+    out["batched_systems_excluded"] = len(evals) - len(ok)
+    try:
+        b = pa.Batch(ok, order=pa.ORDER_LEARNED, model=model, graph=True, autotune=True)
+        outs = b.alloc_outputs()
+        b.execute(outs, stream=stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            b.execute(outs, stream=stream)
+        torch.cuda.synchronize()
+        bdt = (time.perf_counter() - t0) / 3
+        plain_ms = []
+        for s in ok:
+            try:
+                p = pa.Plan(s, order=pa.ORDER_GREEDY, plain=True)
+            except pa.PaError:       # workspace cap
+                plain_ms = None
+                break
+            o = pa.empty_bits(p.dims)
+            p.execute(o)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            p.execute(o)
+            torch.cuda.synchronize()
+            plain_ms.append(1e3 * (time.perf_counter() - t1))
+        out["learned_batched"] = {"value": len(ok) / bdt, "unit": "solves/s", "systems": len(ok)}
+        if plain_ms:
+            out["plain_gpu"] = {"value": len(ok) / (1e-3 * sum(plain_ms)), "unit": "solves/s",
+                                "path": "greedy order, one launch per plot and step, per system"}
+            out["speedup_vs_plain"] = out["learned_batched"]["value"] / out["plain_gpu"]["value"]
+    except pa.PaError as e:
+        out["learned_batched"] = {"error": str(e)}
+    return out
+
+
 def _cpu_baseline(system, budget_s, gpu_bits):
     """The oracle (plain C, pthreads for plotting) solving the same instance:
     corner plots of every relation, then the chain multiplied pairwise."""
@@ -183,6 +254,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -266,6 +338,9 @@ def main():
 
     if not args.no_batched:
         result["batched"] = _batched(stream, max(5, K // 10), 3)
+
+    if not args.no_learned:
+        result["learned_order"] = _learned(stream)
 
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = _cpu_baseline(system, args.cpu_budget, gpu_bits)

@@ -274,8 +274,10 @@ int pa_solve_batch(const pa_system *systems, int32_t n_sys, const int32_t *const
  * predicts log2 of a step's duration in microseconds from features of its
  * index groups; PA_ORDER_LEARNED runs a dynamic program over connected sets
  * of relations (all sets if the relation graph is disconnected; greedy above
- * 16 relations) minimizing the sum of predicted step times, with one batched
- * forward pass on the device per 2^18 candidate steps.  Training data come
+ * 16 relations) minimizing the sum of predicted step times plus a cost per
+ * tree level, with one batched forward pass on the device per 2^18
+ * candidate steps; a tree whose naive cost exceeds 4x the exhaustive
+ * optimum is replaced by that optimum.  Training data come
  * from the library's own timings (pa_plan_step_samples); forward, backward
  * and the Adam update run in the library's kernels.
  *
@@ -296,6 +298,10 @@ void pa_model_destroy(pa_model *model);
  * wrong n or a non-finite value. */
 int pa_model_get_params(const pa_model *model, float *host_params, int32_t n);
 int pa_model_set_params(pa_model *model, const float *host_params, int32_t n);
+/* Cost in microseconds that PA_ORDER_LEARNED charges per tree level (the
+ * grouped executor launches each level separately); default 6.  EINVAL if
+ * negative or not finite. */
+int pa_model_set_level_cost(pa_model *model, double us);
 /* Y[i] = prediction for features X[i][F], i < n (device pointers; n >= 0). */
 int pa_model_forward(pa_model *model, const float *X, int64_t n, float *Y, void *stream);
 /* Gradient of the mean squared error (1/n) sum (y_i - T_i)^2 with respect

@@ -94,6 +94,10 @@ struct ContractArgs {
     // packed latent axis (mode K), precomputed on the host
     const int64_t *ktab;
     int64_t nktab;
+    // stream mode W: an operand without the output's packed variable
+    // contributes one bit per output row (its packed variable is an output
+    // variable), broadcast over the word
+    int a_bcast, b_bcast;
     // divisions by out_dim[i], by the output row length in bits and in
     // words (output rows and row offsets are below 2^31, checked on the host)
     FastDiv fd_dim[kMaxDim];

@@ -572,15 +572,23 @@ __device__ uint32_t streamk_unit(const ContractArgs &a, int64_t row, int64_t bit
     return acc;
 }
 
-// Stream mode W: A, B and C share the packed variable (an output variable);
-// whole words are ANDed and ORed over the latent entries (host table).
+// Stream mode W: C's packed variable is the packed variable of every operand
+// that has it; whole words are ANDed and ORed over the latent entries (host
+// table); an operand without it contributes its bit at this output row,
+// broadcast over the word.
 __device__ uint32_t streamw_word(const ContractArgs &a, int64_t row, int64_t wc) {
     if (wc * 32 >= a.out_dim[a.nout - 1]) return 0u;
     const OutPos p = out_pos(a, row, 0);
     uint32_t acc = 0;
     for (int64_t j = 0; j < a.nktab; ++j) {
-        const uint32_t x = gp(a.A)[p.baseA + wc + gp(a.ktab)[2 * j]];
-        acc |= a.B ? (x & gp(a.B)[p.baseB + wc + gp(a.ktab)[2 * j + 1]]) : x;
+        uint32_t x;
+        if (a.a_bcast) x = ((gp(a.A)[p.baseA + gp(a.ktab)[2 * j] + (p.pa >> 5)] >> (p.pa & 31)) & 1u) ? ~0u : 0u;
+        else x = gp(a.A)[p.baseA + wc + gp(a.ktab)[2 * j]];
+        if (a.B) {
+            if (a.b_bcast) x &= ((gp(a.B)[p.baseB + gp(a.ktab)[2 * j + 1] + (p.pb >> 5)] >> (p.pb & 31)) & 1u) ? ~0u : 0u;
+            else x &= gp(a.B)[p.baseB + wc + gp(a.ktab)[2 * j + 1]];
+        }
+        acc |= x;
     }
     return acc;
 }

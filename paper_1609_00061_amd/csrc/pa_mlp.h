@@ -30,6 +30,7 @@ struct pa_model {
     int device = 0;
     float *P = nullptr, *M = nullptr, *V = nullptr, *G = nullptr, *loss = nullptr;
     int adam_step = 0;
+    double level_us = 6.0;   // launch cost of one tree level charged by the learned order
     // per-batch scratch, grown on demand
     int64_t cap = 0;
     float *Y = nullptr, *acts = nullptr, *dacts = nullptr, *dY = nullptr;

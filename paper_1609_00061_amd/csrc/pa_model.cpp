@@ -40,6 +40,9 @@ namespace pa {
 constexpr double kLogScale = 1.0 / 8.0;
 // Largest intermediate the learned order may create: 2^33 bits (1 GiB).
 constexpr double kMaxLog2Bits = 33.0;
+// A learned tree may cost at most this factor times the optimal naive cost.
+constexpr double kJudgeFactor = 4.0;
+
 
 static double log2_cost(uint64_t m, const std::vector<double> &lr) {
     double s = 0.0;
@@ -179,9 +182,10 @@ static int set_params(pa_model *m, const float *host) {
 }
 
 // ------------------------------------------------------------------ planner
-// Least predicted total time over binary cluster trees whose every node
-// multiplies two connected clusters (no Kronecker products) when the
-// relation graph is connected, else over all trees.  Candidate steps are
+// Least predicted total time (step times plus a per-level launch cost) over
+// binary cluster trees whose every node multiplies two connected clusters
+// (no Kronecker products) when the relation graph is connected, else over
+// all trees.  Candidate steps are
 // scored in chunks by one batched forward pass each.
 int plan_learned(const SysInfo &si, const pa_model *model, Tree &t) {
     if (!model) return fail(PA_EINVAL, "opts: PA_ORDER_LEARNED needs a model");
@@ -264,45 +268,81 @@ int plan_learned(const SysInfo &si, const pa_model *model, Tree &t) {
         (void)hipFree(dY);
         if (err) return err;
     }
-    // pass 2: dynamic program over the same enumeration; intermediates above
-    // kMaxLog2Bits are not considered (the root is the caller's output)
+    // pass 2: dynamic program over the same enumeration, per tree height h
+    // (levels of pairwise steps): best[S][h] = least predicted step time of a
+    // tree over S no taller than h.  The executor launches each level
+    // separately, so the tree chosen minimizes best[full][h] + h * level_us.
+    // Intermediates above kMaxLog2Bits are not considered (the root is the
+    // caller's output).
     const double inf = std::numeric_limits<double>::infinity();
-    std::vector<double> best((size_t)full + 1, inf);
-    std::vector<uint32_t> split((size_t)full + 1, 0);
-    for (int i = 0; i < n; ++i) best[1u << i] = 0.0;
+    const int H = n;   // heights 0..n-1
+    std::vector<double> best(((size_t)full + 1) * H, inf);
+    std::vector<uint32_t> split(((size_t)full + 1) * H, 0);
+    auto at = [&](uint32_t S, int h) { return (size_t)S * H + h; };
+    for (int i = 0; i < n; ++i)
+        for (int h = 0; h < H; ++h) best[at(1u << i, h)] = 0.0;
     size_t ci = 0;
     for (uint32_t S = 1; S <= full; ++S) {
         if ((S & (S - 1)) == 0 || !considered(S)) continue;
+        const bool fits = S == full || lq[S] <= kMaxLog2Bits;
         const uint32_t low = S & (~S + 1), rest = S ^ low;
         for (uint32_t sub = rest;; sub = (sub - 1) & rest) {
             const uint32_t S1 = sub | low, S2 = S ^ S1;
             if (S2 && allowed(S1, S2)) {
-                const double c = best[S1] + best[S2] + std::exp2((double)pred[ci++]);
-                if (c < best[S] && (S == full || lq[S] <= kMaxLog2Bits)) {
-                    best[S] = c;
-                    split[S] = S1;
+                const double step = std::exp2((double)pred[ci++]);
+                if (fits) {
+                    for (int h = 1; h < H; ++h) {
+                        const double c = best[at(S1, h - 1)] + best[at(S2, h - 1)] + step;
+                        if (c < best[at(S, h)]) {
+                            best[at(S, h)] = c;
+                            split[at(S, h)] = S1;
+                        }
+                    }
                 }
             }
             if (sub == 0) break;
         }
     }
-    if (!(best[full] < inf)) return plan_exhaustive(si, t);   // every tree has a larger intermediate
+    int hbest = -1;
+    double obj = inf;
+    for (int h = 1; h < H; ++h) {
+        const double o = best[at(full, h)] + h * model->level_us;
+        if (best[at(full, h)] < inf && o < obj) {
+            obj = o;
+            hbest = h;
+        }
+    }
+    if (hbest < 0) return plan_exhaustive(si, t);   // every tree has a larger intermediate
     std::vector<int> merges;
     int next = n;
     struct Rec {
-        static int go(uint32_t S, const std::vector<uint32_t> &split, std::vector<int> &merges, int &next) {
+        static int go(uint32_t S, int h, int H, const std::vector<uint32_t> &split, std::vector<int> &merges,
+                      int &next) {
             if ((S & (S - 1)) == 0) return __builtin_ctz(S);
-            const int a = go(split[S], split, merges, next);
-            const int b = go(S ^ split[S], split, merges, next);
+            const uint32_t S1 = split[(size_t)S * H + h];
+            const int a = go(S1, h - 1, H, split, merges, next);
+            const int b = go(S ^ S1, h - 1, H, split, merges, next);
             merges.push_back(a);
             merges.push_back(b);
             return next++;
         }
     };
-    Rec::go(full, split, merges, next);
+    Rec::go(full, hbest, H, split, merges, next);
     rc = tree_from_merges(si, merges, t);
-    if (rc == PA_OK) t.predicted_us = best[full];
-    return rc;
+    if (rc) return rc;
+    t.predicted_us = best[at(full, hbest)];
+    // the exhaustive search judges the choice: a tree whose naive cost exceeds
+    // the optimum by more than kJudgeFactor is outside what the model was
+    // trained to rank, and the optimum is taken instead
+    Tree ex;
+    rc = plan_exhaustive(si, ex);
+    if (rc) return rc;
+    if (t.cost > kJudgeFactor * ex.cost) {
+        ex.predicted_us = t.predicted_us;
+        ex.learned_fallback = true;
+        t = ex;
+    }
+    return PA_OK;
 }
 
 }  // namespace pa
@@ -348,6 +388,13 @@ extern "C" int pa_model_set_params(pa_model *m, const float *host, int32_t n) {
     int rc = check_device(m);
     if (rc) return rc;
     return set_params(m, host);
+}
+
+extern "C" int pa_model_set_level_cost(pa_model *m, double us) {
+    if (!m) return fail(PA_EINVAL, "model_set_level_cost: null model");
+    if (!(us >= 0.0) || !std::isfinite(us)) return fail(PA_EINVAL, "model_set_level_cost: need a finite cost >= 0");
+    m->level_us = us;
+    return PA_OK;
 }
 
 extern "C" int pa_model_forward(pa_model *m, const float *X, int64_t n, float *Y, void *stream) {

@@ -255,13 +255,14 @@ struct Builder {
             }
         }
         if (bestc.kind < 0) {
+            // no latent variable: every child variable is an output variable.
+            // Word streaming with the children holding the output's packed
+            // axis packed along it (a child without it contributes a bit)
             Constraint c0, c1;
-            int kind = 2;   // bit level unless both share the output's packed axis
-            if (cp >= 0 && ((qx >> cp) & 1) && ((qy >> cp) & 1)) {
-                c0 = Constraint::pk(cp, -1);
-                c1 = Constraint::pk(cp, -1);
-                kind = 1;
-            }
+            int kind = 2;
+            if (cp >= 0 && ((qx >> cp) & 1)) c0 = Constraint::pk(cp, -1);
+            if (cp >= 0 && ((qy >> cp) & 1)) c1 = Constraint::pk(cp, -1);
+            if (cp >= 0 && (((qx | qy) >> cp) & 1)) kind = 1;
             bestc.kind = 1;
             bestc.oc = oc;
             bestc.cx = c0;
@@ -445,7 +446,20 @@ static void finish_contract(Op &op, bool has_b) {
     a.b_row_words = has_b ? lb.rw : 0;
     // A 0-dim operand has no packed axis: its bit is bit 0 of word 0.
     const bool k_ok = a.a_pk_k >= 0 && (!has_b || a.b_pk_k == a.a_pk_k) && a.a_pk_out < 0 && (!has_b || a.b_pk_out < 0);
-    const bool w_ok = a.nout >= 1 && a.a_pk_out == a.nout - 1 && (!has_b || a.b_pk_out == a.nout - 1) && !la.vars.empty();
+    // mode W: every operand holding the output's packed variable is packed
+    // along it; an operand without it must be packed along an output variable
+    // (it then contributes one bit per output row)
+    bool w_ok = a.nout >= 1 && !la.vars.empty();
+    if (w_ok) {
+        const int last = a.nout - 1, cvar = lc.vars[last];
+        if (la.has(cvar)) w_ok = a.a_pk_out == last;
+        else w_ok = (a.a_bcast = a.a_pk_out >= 0);
+        if (w_ok && has_b) {
+            if (lb.has(cvar)) w_ok = a.b_pk_out == last;
+            else w_ok = (a.b_bcast = a.b_pk_out >= 0);
+        }
+    }
+    if (!w_ok) a.a_bcast = a.b_bcast = 0;
     if (k_ok) op.mode = kModeStreamK;
     else if (w_ok) op.mode = kModeStreamW;
     else op.mode = kModeBits;
@@ -1275,6 +1289,7 @@ extern "C" int64_t pa_plan_describe(const pa_system *sys, const int32_t *exposed
         s << "{\"merges\":" << join(std::vector<int>(P->tree.merges.begin(), P->tree.merges.end()))
           << ",\"cost\":" << P->tree.cost << ",\"workspace_bytes\":" << P->ws_bytes << ",\"corners\":" << P->corners
           << ",\"total_macs\":" << P->total_macs << ",\"predicted_us\":" << P->tree.predicted_us
+          << ",\"learned_fallback\":" << (P->tree.learned_fallback ? "true" : "false")
           << ",\"plots\":[";
         for (size_t i = 0; i < P->plots.size(); ++i)
             s << (i ? "," : "") << "{\"rel\":" << P->plots[i].rel << ",\"buf\":" << P->plots[i].buf

@@ -59,6 +59,7 @@ struct Tree {
     std::vector<int> merges;      // PA_ORDER_GIVEN format
     double cost = 0.0;            // sum of node costs (eqn naive_cost)
     double predicted_us = 0.0;    // learned order: the model's predicted total step time
+    bool learned_fallback = false;  // learned order: the exhaustive optimum replaced the model's tree
 };
 
 struct SysInfo {

@@ -52,16 +52,20 @@ def _feasible(system, merges, max_out_log2=33.0) -> bool:
 
 
 def collect_samples(systems: Sequence, n_random: int = 3, reps: int = 3, seed: int = 1, stream=None,
-                    log=None):
+                    log=None, model=None, base_policies: bool = True):
     """(X [k, F] float32, T [k] float32 log2 microseconds) from timed plans.
-    Each tree is executed `reps` times after one warm-up; a step's sample is
-    its fastest repetition."""
+    Trees: greedy and exhaustive (base_policies), n_random random connected
+    merge orders, and the learned order of `model` when given.  Each tree is
+    executed `reps` times after one warm-up; a step's sample is its fastest
+    repetition."""
     rng = inputs.SplitMix64(seed)
     Xs, Ts = [], []
     for si, s in enumerate(systems):
         if len(s.relations) < 2:
             continue
-        trees = [dict(order=pa.ORDER_GREEDY), dict(order=pa.ORDER_EXHAUSTIVE)]
+        trees = [dict(order=pa.ORDER_GREEDY), dict(order=pa.ORDER_EXHAUSTIVE)] if base_policies else []
+        if model is not None:
+            trees.append(dict(order=pa.ORDER_LEARNED, model=model))
         for _ in range(n_random):
             m = random_connected_merges(s, rng)
             if _feasible(s, m):
@@ -115,6 +119,24 @@ def train(model: "pa.Model", X: np.ndarray, T: np.ndarray, steps: int = 3000, lr
             log(f"train: step {step + 1} loss {loss:.4f}")
     _, loss = model.gradient(Xd, Td)
     return loss
+
+
+def train_order_model(systems: Sequence, rounds: int = 2, n_random: int = 3, reps: int = 2, steps: int = 3000,
+                      seed: int = 1, stream=None, log=None):
+    """Fit the step-time model on the training systems' own timings, then
+    (rounds > 1) add the steps of the trees the model itself picks on those
+    systems and refit, so its training data covers the region it searches.
+    Returns (model, X, T)."""
+    X, T = collect_samples(systems, n_random=n_random, reps=reps, seed=seed, stream=stream, log=log)
+    model = pa.Model(seed=seed)
+    train(model, X, T, steps=steps, log=log)
+    for r in range(1, rounds):
+        Xl, Tl = collect_samples(systems, n_random=0, reps=reps, seed=seed + r, stream=stream, log=log, model=model,
+                                 base_policies=False)
+        X, T = np.concatenate([X, Xl]), np.concatenate([T, Tl])
+        model = pa.Model(seed=seed + r)
+        train(model, X, T, steps=steps, log=log)
+    return model, X, T
 
 
 def time_policies(systems: Sequence, model, policies=("greedy", "exhaustive", "learned"), steps: int = 10,

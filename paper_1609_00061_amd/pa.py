@@ -142,6 +142,7 @@ def load(path: str = LIB_PATH):
     L.pa_model_get_params.argtypes = [vp, fp, ctypes.c_int32]
     L.pa_model_set_params.argtypes = [vp, fp, ctypes.c_int32]
     L.pa_model_forward.argtypes = [vp, vp, ctypes.c_int64, vp, vp]
+    L.pa_model_set_level_cost.argtypes = [vp, ctypes.c_double]
     L.pa_model_gradient.argtypes = [vp, vp, vp, ctypes.c_int64, vp, fp, vp]
     L.pa_model_train_step.argtypes = [vp, vp, vp, ctypes.c_int64, ctypes.c_float, fp, vp]
     L.pa_model_save.argtypes = [vp, ctypes.c_char_p]
@@ -501,6 +502,9 @@ class Model:
     def set_params(self, p) -> None:
         p = np.ascontiguousarray(np.asarray(p, dtype=np.float32))
         _check(load().pa_model_set_params(self.handle, p.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), p.size))
+
+    def set_level_cost(self, us: float) -> None:
+        _check(load().pa_model_set_level_cost(self.handle, float(us)))
 
     def forward(self, X, stream=None):
         """X: torch float32 [n, F] on the device -> torch float32 [n]."""

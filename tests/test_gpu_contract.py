@@ -37,6 +37,10 @@ PATTERNS = [
     ((0, 1), (2, 3), (0, 1, 2, 3)),      # Kronecker
     ((0, 1), (1, 2), ()),                # 0-dim output
     ((0, 1, 2), (1,), (0,)),             # private latent 2 in A
+    ((0, 1), (0, 2), (0, 1, 2)),         # batched outer product: A broadcast over C's packed axis
+    ((0, 2), (0, 1), (0, 1, 2)),         # the same with B broadcast
+    ((1,), (0, 2), (0, 1, 2)),           # one-axis A broadcast
+    ((0, 1, 3), (0, 2), (0, 2, 1)),      # A packed along a latent variable: bit-level fallback
 ]
 
 SIZES = [

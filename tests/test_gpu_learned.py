@@ -1,0 +1,36 @@
+"""What the trained step-time model gains: trained on the GPU (library
+kernels) from the library's own step timings on one set of random relation
+hypergraphs, its order is compared with the exhaustive naive-cost order on a
+disjoint set, by measured solve time, with identical output bits."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1609_00061_amd import inputs, learn, pa
+from gpu_util import note, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+def test_learned_order_beats_exhaustive_order():
+    import torch
+    train = inputs.config5(n_graphs=24, index=1000, res=64)
+    evals = inputs.config5(n_graphs=16, index=0, res=64)
+    note("learned: training on", len(train), "graphs")
+    model, X, T = learn.train_order_model(train, rounds=2, steps=2000)
+    # the fit explains most of the variance of the measured log2 step times
+    Xd = torch.from_numpy(X).cuda()
+    pred = model.forward(Xd).cpu().numpy()
+    r2 = 1.0 - np.mean((pred - T) ** 2) / np.var(T)
+    assert r2 > 0.8, r2
+    note("learned: evaluating", len(evals), "graphs")
+    res = learn.time_policies(evals, model, policies=("exhaustive", "learned"), steps=3)
+    assert res["same_bits"]
+    assert res["systems"] >= 12
+    assert res["learned"]["total_ms"] < res["exhaustive"]["total_ms"], res
+    # and the learned order's bits are the oracle's
+    for s in evals[:3]:
+        ref = oracle.solve([a[2] for a in s.axes], [r.vars for r in s.relations],
+                           [oracle.plot(r, s.axes)[0] for r in s.relations], s.exposed)
+        out, dims, _ = pa.solve_system(s, order=pa.ORDER_LEARNED, model=model)
+        assert np.array_equal(to_host(out, dims), ref)

@@ -125,6 +125,7 @@ def _naive_cost_model():
     w3 = np.zeros(ref.H); w3[0] = 8.0
     m = pa.Model()
     m.set_params(ref.pack(W1, np.zeros(ref.H), W2, np.zeros(ref.H), w3, 0.0).astype(np.float32))
+    m.set_level_cost(0.0)
     return m
 
 
