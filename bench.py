@@ -32,6 +32,11 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3
 HBM_PEAK_GBS = 8000.0
 
 
+def _progress(msg):
+    """A progress line on stderr (the JSON result is the only stdout line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def _time_plan(plan, out, steps, warmup, stream=None):
     import torch
     for _ in range(warmup):
@@ -160,12 +165,14 @@ def _learned(stream, n_train=32, n_eval=48, res=128):
     import torch
     from paper_1609_00061_amd import inputs, learn, pa
     t0 = time.perf_counter()
-    model, X, T = learn.train_order_model(inputs.config5(n_graphs=n_train, index=1000, res=res), rounds=2)
+    model, X, T = learn.train_order_model(inputs.config5(n_graphs=n_train, index=1000, res=res), rounds=2,
+                                         log=_progress)
     train_s = time.perf_counter() - t0
     import numpy as np
     pred = model.forward(torch.from_numpy(X).cuda()).cpu().numpy()
     r2 = float(1.0 - np.mean((pred - T) ** 2) / np.var(T))
     evals = inputs.config5(n_graphs=n_eval, index=0, res=res)
+    _progress(f"trained in {train_s:.1f} s on {len(T)} samples; timing policies")
     pol = learn.time_policies(evals, model, steps=3, stream=stream)
     out = {"workload": f"{n_eval} random relation hypergraphs (8-14 variables, arity 2-3, 2-4 exposed, "
                        f"{res} cells/axis, [-3,3]); model trained on {n_train} disjoint graphs",
@@ -269,6 +276,7 @@ def main():
     K, W = args.steps, args.warmup
 
     stream = torch.cuda.Stream()
+    _progress("planning and autotuning the chain workload")
     t0 = time.perf_counter()
     plan = pa.Plan(system, order=pa.ORDER_EXHAUSTIVE, precision=pa.PLOT_FP32_ESCALATE, graph=True, autotune=True)
     plan_s = time.perf_counter() - t0
@@ -304,6 +312,7 @@ def main():
         "corners": rep["corners"],
     }
 
+    _progress(f"timed {K} solves: {1e3 * dt / K:.4f} ms each")
     # per-kernel durations and the roofline of the dominant kernel
     roof, per_kind, _ = _kernel_table(plan, stream, system, reps=20)
     dom = max(roof.values(), key=lambda r: r["ms_per_step"]) if roof else None
@@ -318,6 +327,7 @@ def main():
         result["contraction_tops"] = g["achieved"]
 
     if not args.no_plain:
+        _progress("plain path")
         plain = pa.Plan(system, order=pa.ORDER_GREEDY, plain=True)
         pout = pa.empty_bits(plain.dims)
         pdt = _time_plan(plain, pout, K, W)
@@ -329,6 +339,7 @@ def main():
         result["speedup_vs_plain"] = (K / dt) / (K / pdt)
 
     # one persistent launch per solve (tiles wait on dependency counters)
+    _progress("single-launch executor")
     splan = pa.Plan(system, order=pa.ORDER_EXHAUSTIVE, graph=True, single_launch=True)
     sout = pa.empty_bits(splan.dims)
     sdt = _time_plan(splan, sout, K, W, stream)
@@ -337,12 +348,15 @@ def main():
                                "same_bits": bool(torch.equal(sout, out))}
 
     if not args.no_batched:
+        _progress("batched workload")
         result["batched"] = _batched(stream, max(5, K // 10), 3)
 
     if not args.no_learned:
+        _progress("learned order")
         result["learned_order"] = _learned(stream)
 
     if not args.no_cpu_baseline:
+        _progress("cpu baseline (oracle)")
         result["cpu_baseline"] = _cpu_baseline(system, args.cpu_budget, gpu_bits)
         result["bit_exact_vs_oracle"] = result["cpu_baseline"]["bit_exact_vs_gpu"]
 

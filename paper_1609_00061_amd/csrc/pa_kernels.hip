@@ -1009,7 +1009,8 @@ hipError_t launch_popcount(const uint32_t *p, int64_t n, unsigned long long *out
 // ------------------------------------------------- grouped executors
 // Steps of one kind on one level of the cluster tree (possibly from many
 // systems), contiguous in the step table, run by one launch; tiles are
-// numbered by the steps' tile_base prefix.
+// numbered by the steps' tile_base prefix.  A plotting launch also runs the
+// fill steps of its level.
 __device__ __forceinline__ int find_step(const PStep *steps, int first, int count, int64_t item) {
     int lo = first, hi = first + count - 1;
     while (lo < hi) {
@@ -1072,7 +1073,7 @@ __global__ __launch_bounds__(256, KIND == kStepGemm ? 3 : 1) void k_group(const 
     PlotCount cnt;
     for (int64_t item = t0 + blockIdx.x; item < t1; item += gridDim.x) {
         const PStep &st = steps[find_step(steps, first, count, item)];
-        if (kind == kStepPlot) {
+        if (kind == kStepPlot && st.kind == kStepPlot) {
             plot_tile(st.plot, item - st.tile_base, reinterpret_cast<float *>(lds),
                       reinterpret_cast<double *>(lds + kPlotLineWords), cnt);
         } else if (kind == kStepContract) {

@@ -859,13 +859,15 @@ static int build_steps(pa_plan *P) {
 }
 
 // Groups: maximal runs of steps with the same (level, kind, mode), in the
-// sorted step table.
+// sorted step table; fills (which depend on nothing) join the plotting group
+// of their level, so zeroing split-K outputs costs no launch of its own.
 void make_groups(pa_plan *P) {
     P->groups.clear();
     for (size_t i = 0; i < P->steps_host.size(); ++i) {
         const PStep &x = P->steps_host[i];
-        const bool same = i > 0 && P->step_level[i] == P->step_level[i - 1] && x.kind == P->steps_host[i - 1].kind &&
-                          x.mode == P->steps_host[i - 1].mode;
+        const bool same_level = i > 0 && P->step_level[i] == P->step_level[i - 1];
+        const bool same = same_level && ((x.kind == P->steps_host[i - 1].kind && x.mode == P->steps_host[i - 1].mode) ||
+                                         (x.kind == kStepFill && P->groups.back().kind == kStepPlot));
         if (same) {
             P->groups.back().count += 1;
             P->groups.back().t1 = x.tile_base + x.n_tiles;

@@ -52,12 +52,14 @@ def _feasible(system, merges, max_out_log2=33.0) -> bool:
 
 
 def collect_samples(systems: Sequence, n_random: int = 3, reps: int = 3, seed: int = 1, stream=None,
-                    log=None, model=None, base_policies: bool = True):
+                    log=None, model=None, base_policies: bool = True, max_cost_ratio: float = 16.0):
     """(X [k, F] float32, T [k] float32 log2 microseconds) from timed plans.
     Trees: greedy and exhaustive (base_policies), n_random random connected
-    merge orders, and the learned order of `model` when given.  Each tree is
-    executed `reps` times after one warm-up; a step's sample is its fastest
-    repetition."""
+    merge orders, and the learned order of `model` when given; a tree whose
+    naive cost exceeds max_cost_ratio times the optimum is not timed (the
+    learned order never keeps such a tree, and one such solve can take
+    seconds).  Each tree is executed `reps` times after one warm-up; a step's
+    sample is its fastest repetition."""
     rng = inputs.SplitMix64(seed)
     Xs, Ts = [], []
     for si, s in enumerate(systems):
@@ -70,7 +72,14 @@ def collect_samples(systems: Sequence, n_random: int = 3, reps: int = 3, seed: i
             m = random_connected_merges(s, rng)
             if _feasible(s, m):
                 trees.append(dict(order=pa.ORDER_GIVEN, given=m))
+        best_cost = pa.describe_plan(s, order=pa.ORDER_EXHAUSTIVE).get("cost")
+        kept = []
         for kw in trees:
+            d = pa.describe_plan(s, **kw)
+            if "error" in d or (best_cost and d["cost"] > max_cost_ratio * best_cost):
+                continue
+            kept.append(kw)
+        for kw in kept:
             try:
                 plan = pa.Plan(s, per_op=True, timing=2, **kw)
             except pa.PaError as e:          # a tree whose intermediates exceed the workspace cap
@@ -87,7 +96,7 @@ def collect_samples(systems: Sequence, n_random: int = 3, reps: int = 3, seed: i
             Xs.append(X)
             Ts.append(best)
             del plan
-        if log and (si + 1) % 16 == 0:
+        if log:
             log(f"samples: {si + 1}/{len(systems)} systems, {sum(len(t) for t in Ts)} steps")
     return np.concatenate(Xs).astype(np.float32), np.concatenate(Ts).astype(np.float32)
 

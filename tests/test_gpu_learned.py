@@ -17,7 +17,7 @@ def test_learned_order_beats_exhaustive_order():
     train = inputs.config5(n_graphs=24, index=1000, res=64)
     evals = inputs.config5(n_graphs=16, index=0, res=64)
     note("learned: training on", len(train), "graphs")
-    model, X, T = learn.train_order_model(train, rounds=2, steps=2000)
+    model, X, T = learn.train_order_model(train, rounds=2, steps=2000, log=note)
     # the fit explains most of the variance of the measured log2 step times
     Xd = torch.from_numpy(X).cuda()
     pred = model.forward(Xd).cpu().numpy()
