@@ -150,6 +150,10 @@ typedef struct {
                                  contract_units) from the autotuner: cached per
                                  workload structure and GPU architecture, tuned by
                                  timing on the device (stream 0) on a cache miss */
+    int32_t gemm_split;       /* MFMA contractions: a contraction with fewer 128x128
+                                 output tiles than this splits its K range into
+                                 partial products OR-ed into a zeroed output
+                                 (exact); 1: never split; 0: default (512)       */
 } pa_opts;
 
 typedef struct {
@@ -341,7 +345,8 @@ int32_t pa_plan_step_samples(pa_plan *plan, float *features, float *log2_us, int
  * candidates on the device: first the executor (grouped launches, or one
  * persistent launch with 256/512/1024/2048 workgroups), then the plot strip
  * length (1/2/4/8 cells per thread), then the streaming tile (512..32768
- * output bits), each from the best so far.  Every candidate is a batch built
+ * output bits), then the MFMA K-split target (1, 256, 512, 1024, 2048 work
+ * items), each from the best so far.  Every candidate is a batch built
  * with opts (graph capture included if opts->graph), executed once untimed,
  * then reps times between two events on `stream`.  Candidates that exceed
  * the workspace cap are skipped.  best gets the fastest; tried (may be NULL)
@@ -349,7 +354,7 @@ int32_t pa_plan_step_samples(pa_plan *plan, float *features, float *log2_us, int
  * also cached for opts->autotune.  Allocates outputs and workspaces while
  * tuning; synchronizes the stream. */
 typedef struct {
-    int32_t single_launch, persist_wg, plot_strip, contract_units;
+    int32_t single_launch, persist_wg, plot_strip, contract_units, gemm_split;
     double ms;                /* milliseconds per execution of the whole workload */
 } pa_tuning;
 int pa_autotune(const pa_system *systems, int32_t n_sys, const int32_t *const *exposed, const int32_t *n_exposed,

@@ -151,6 +151,9 @@ extern "C" int pa_batch_create(const pa_system *systems, int32_t n_sys, const in
     }
     rc = merge_steps(B.get());
     if (rc) return rc;
+    HIP_TRY(hipMemset(base + M.counters_off, 0, sizeof(PlotCounters)));
+    HIP_TRY(hipMemset(base + M.state_off, 0, sizeof(PersistState)));
+    HIP_TRY(hipMemset(base + M.done_off, 0, sizeof(unsigned) * std::max<size_t>(1, nsteps)));
     if (opts && opts->timing == 2) {
         M.op_events.resize(M.single_launch ? 2 : std::max<size_t>(2, 2 * M.groups.size()));
         for (auto &e : M.op_events) HIP_TRY(hipEventCreate(&e));
@@ -175,6 +178,10 @@ extern "C" int pa_batch_execute(pa_batch *B, pa_bitarray *outs, pa_report *rep, 
     hipStream_t s = static_cast<hipStream_t>(stream);
     int launches = 0;
     M.timing_active = false;
+    char *mbase = static_cast<char *>(M.ws.ptr);
+    PlotCounters cnt0;
+    std::memset(&cnt0, 0, sizeof(cnt0));
+    if (rep) HIP_TRY(hipMemcpyAsync(&cnt0, mbase + M.counters_off, sizeof(cnt0), hipMemcpyDeviceToHost, s));
     int rc = exec_steps(&M, o, s, &launches);
     if (rc) return rc;
     if (rep || nnz) {
@@ -199,9 +206,9 @@ extern "C" int pa_batch_execute(pa_batch *B, pa_bitarray *outs, pa_report *rep, 
         if (rep) {
             std::memset(rep, 0, sizeof(*rep));
             rep->corners = M.corners;
-            rep->corners_flagged = (int64_t)cnt.flagged;
-            rep->corners_disagree = (int64_t)cnt.disagree;
-            rep->corners_disagree_unflagged = (int64_t)cnt.disagree_unflagged;
+            rep->corners_flagged = (int64_t)(cnt.flagged - cnt0.flagged);
+            rep->corners_disagree = (int64_t)(cnt.disagree - cnt0.disagree);
+            rep->corners_disagree_unflagged = (int64_t)(cnt.disagree_unflagged - cnt0.disagree_unflagged);
             rep->nnz_out = total;
             rep->n_launches = launches;
             int steps = 0;

@@ -13,9 +13,12 @@ constexpr int kDense = (kMaxD + 1) * (kMaxD + 1) * (kMaxD + 1);
 constexpr int kMaxDim = PA_MAX_DIMS;
 constexpr int kLineFloats = kMaxD + 2;          // a_0..a_d, E per corner line
 constexpr int kMaxTileLines = 160;              // LDS line table capacity of one plot tile
-// LDS of a plot tile: the line table, then the storage-order coefficient table (doubles)
+// LDS of a plot tile: the line table (floats), then as doubles the
+// storage-order and the declared-order coefficient tables and the FP64
+// coordinates (two per line) of the tile's corner lines
 constexpr int kPlotLineWords = (kMaxTileLines * kLineFloats + 1) / 2 * 2;
-constexpr int kPlotLdsWords = kPlotLineWords + 2 * kDense;
+constexpr int kPlotLdsWords = kPlotLineWords + 2 * (2 * kDense + 2 * kMaxTileLines);
+static_assert(kMaxTileLines <= 256, "one corner line per thread of a 256-thread plot tile");
 
 // One relation to plot.  The relation's declared variables x_0..x_{n-1} are
 // stored on storage axes in the order perm: storage axis s holds declared
@@ -154,8 +157,7 @@ hipError_t launch_fill(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
 hipError_t launch_popcount(const uint32_t *p, int64_t n, unsigned long long *out, hipStream_t s);
 hipError_t launch_persist(const PStep *d_steps, int nsteps, int64_t n_items, PersistState *state,
                           unsigned int *done, PlotCounters *counters, int n_workgroups, hipStream_t s);
-hipError_t launch_persist_reset(PersistState *state, unsigned int *done, int nsteps, PlotCounters *counters,
-                                hipStream_t s);
+hipError_t launch_persist_reset(PersistState *state, unsigned int *done, int nsteps, hipStream_t s);
 hipError_t launch_group(int kind, int mode, const PStep *d_steps, int first, int count, int64_t t0, int64_t t1,
                         PlotCounters *counters, hipStream_t s);
 int persist_default_workgroups();

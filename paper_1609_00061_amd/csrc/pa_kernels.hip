@@ -37,8 +37,8 @@ static dim3 grid_for(int64_t total) {
 
 // Canonical FP64 value of a relation at a point given in DECLARED variable
 // order: nested Horner, last declared variable outermost, fma at every step.
-// c is the dense table c[e0 + (d+1)*(e1 + (d+1)*e2)].
-__device__ double canon_eval(const PA_G double *__restrict__ c, int n, int d, const double *x) {
+// c is the dense table c[e0 + (d+1)*(e1 + (d+1)*e2)] (its LDS copy).
+__device__ double canon_eval(const double *__restrict__ c, int n, int d, const double *x) {
     const int D1 = d + 1;
     if (n == 1) {
         double p = c[d];
@@ -58,7 +58,7 @@ __device__ double canon_eval(const PA_G double *__restrict__ c, int n, int d, co
     // n == 3: A_i(x0, x1) = sum_k B_ik(x0) x1^k, B_ik(x0) = sum_j c_jki x0^j
     auto Bik = [&](int i, int k) {
         const int top = d - i - k;
-        const PA_G double *row = c + D1 * (k + D1 * i);
+        const double *row = c + D1 * (k + D1 * i);
         double b = row[top];
         for (int j = top - 1; j >= 0; --j) b = fma(b, x[0], row[j]);
         return b;
@@ -143,9 +143,10 @@ __device__ __forceinline__ void decl_point(const PlotView &V, double s0, double 
     }
 }
 
-// Stage the dense coefficient table in LDS in storage order:
-// cst[s0 + D1*(s1 + D1*s2)] = coefficient with exponent s_j on storage axis j.
-__device__ __forceinline__ void stage_coefs(const PlotView &V, double *cst) {
+// Stage the dense coefficient table in LDS in storage order,
+// cst[s0 + D1*(s1 + D1*s2)] = coefficient with exponent s_j on storage axis j,
+// and as it is (declared order) in cdl, for the canonical FP64 value.
+__device__ __forceinline__ void stage_coefs(const PlotView &V, double *cst, double *cdl) {
     const int D1 = V.d + 1;
     const int tid = threadIdx.x;
     const int total = V.n == 1 ? D1 : (V.n == 2 ? D1 * D1 : D1 * D1 * D1);
@@ -157,6 +158,7 @@ __device__ __forceinline__ void stage_coefs(const PlotView &V, double *cst) {
         const int e1 = (V.perm0 == 1 ? s0 : 0) + (V.n > 1 && V.perm1 == 1 ? t1 : 0) + (V.n > 2 && V.perm2 == 1 ? t2 : 0);
         const int e2 = (V.perm0 == 2 ? s0 : 0) + (V.n > 1 && V.perm1 == 2 ? t1 : 0) + (V.n > 2 && V.perm2 == 2 ? t2 : 0);
         cst[tid] = V.coef[e0 + D1 * (e1 + D1 * e2)];
+        cdl[tid] = V.coef[tid];
     }
 }
 
@@ -282,11 +284,14 @@ __device__ __forceinline__ void line_fp32(const float *ln, const float *xv, int 
     FL = valid & ~okm;
 }
 
-// LE/GE bits of the corners k0..k0+kmax of the corner line with storage
-// indices ia (fixed axis, n == 3) and ib (walk axis) on the non-packed axes; `own` says whether this thread
-// counts the line's corners (each corner is counted once).
-__device__ __forceinline__ void eval_line(const PlotView &V, const float *ln, const float *xv, int64_t ia, int64_t ib,
-                                          int k0, int kmax, bool own, uint64_t &LE, uint64_t &GE, PlotCount &cnt) {
+// LE/GE bits of the corners k0..k0+kmax of one corner line: ln its FP32
+// restriction and bound, ly its FP64 coordinates on the non-packed storage
+// axes (walk axis first for n == 2; fixed, walk for n == 3), cdl the
+// declared-order coefficient table (all three in LDS); `own` says whether
+// this thread counts the line's corners (each corner is counted once).
+__device__ __forceinline__ void eval_line(const PlotView &V, const float *ln, const float *xv, const double *ly,
+                                          const double *cdl, int k0, int kmax, bool own, uint64_t &LE, uint64_t &GE,
+                                          PlotCount &cnt) {
     const int n = V.n, rp = V.rp;
     const uint64_t valid = (kmax >= 63) ? ~0ull : ((2ull << kmax) - 1ull);
     const uint64_t owned = own ? (((1ull << kmax) - 1ull) | ((k0 + kmax == rp) ? (1ull << kmax) : 0ull)) : 0ull;
@@ -304,14 +309,7 @@ __device__ __forceinline__ void eval_line(const PlotView &V, const float *ln, co
     }
     // FP64 decides the escalated corners (every corner in FP64 mode); in
     // audit mode every corner's FP32 sign is also compared with its FP64 sign
-    double y0 = 0.0, y1 = 0.0;
-    if (todo) {
-        if (n == 2) y0 = V.ax0[ib];
-        if (n == 3) {
-            y0 = V.ax0[ia];
-            y1 = V.ax1[ib];
-        }
-    }
+    const double y0 = ly[0], y1 = ly[1];
     while (todo) {
         const int kk = __ffsll((long long)todo) - 1;
         todo &= todo - 1;
@@ -320,7 +318,7 @@ __device__ __forceinline__ void eval_line(const PlotView &V, const float *ln, co
         if (n == 1) decl_point(V, xk, 0.0, 0.0, xd);
         else if (n == 2) decl_point(V, y0, xk, 0.0, xd);
         else decl_point(V, y0, y1, xk, xd);
-        const double f64 = canon_eval(V.coef, n, V.d, xd);
+        const double f64 = canon_eval(cdl, n, V.d, xd);
         const uint64_t bit = 1ull << kk;
         const bool flagged = (FL & bit) != 0;
         if (flagged) {
@@ -387,28 +385,35 @@ __device__ void plot_tile(const PlotRel &R, int64_t tile, float *lines, double *
         const float x = V.axfp[k];
         xv[kk] = (active && !pad && kk <= kmax) ? x : 0.0f;
     }
-    if (V.mode == PA_PLOT_FP32_ESCALATE) {
-        stage_coefs(V, cst);
-        __syncthreads();
-        for (int l = tid; l < nwl * nfl; l += blockDim.x) {
-            const int lf = l / nwl, lw = l % nwl;
-            bool valid = true;
-            double y0 = 0.0, y1 = 0.0;
-            if (n == 2) {
-                const int64_t ib = b0 + lw;
-                valid = ib <= rwalk;
-                if (valid) y0 = V.ax0[ib];
-            } else if (n == 3) {
-                const int64_t ia = a0 + lf, ib = b0 + lw;
-                valid = ia <= V.res0 && ib <= rwalk;
-                if (valid) {
-                    y0 = V.ax0[ia];
-                    y1 = V.ax1[ib];
-                }
+    // this thread's corner line (one per thread: lines <= kMaxTileLines <=
+    // 256), its coordinates also requested before the staging
+    double *cdl = cst + kDense, *ly = cdl + kDense;
+    const int nlines = nwl * nfl;
+    bool lvalid = false;
+    double y0 = 0.0, y1 = 0.0;
+    if (tid < nlines) {
+        const int lf = tid / nwl, lw = tid % nwl;
+        lvalid = true;
+        if (n == 2) {
+            const int64_t ib = b0 + lw;
+            lvalid = ib <= rwalk;
+            if (lvalid) y0 = V.ax0[ib];
+        } else if (n == 3) {
+            const int64_t ia = a0 + lf, ib = b0 + lw;
+            lvalid = ia <= V.res0 && ib <= rwalk;
+            if (lvalid) {
+                y0 = V.ax0[ia];
+                y1 = V.ax1[ib];
             }
-            if (valid) line_coefs(V, cst, y0, y1, lines + l * kLineFloats);
         }
     }
+    stage_coefs(V, cst, cdl);
+    if (tid < nlines) {
+        ly[2 * tid] = y0;
+        ly[2 * tid + 1] = y1;
+    }
+    __syncthreads();
+    if (V.mode == PA_PLOT_FP32_ESCALATE && lvalid) line_coefs(V, cst, y0, y1, lines + tid * kLineFloats);
     __syncthreads();
     if (!active) return;
     const uint32_t vmask = pad ? 0u : (kmax == 32 ? 0xffffffffu : ((1u << kmax) - 1u));
@@ -427,9 +432,9 @@ __device__ void plot_tile(const PlotRel &R, int64_t tile, float *lines, double *
                     own = ((c > cs) || (cs == 0)) && ((df == 0) || (cf + 1 == V.res0));
                     lf = fa + df;
                 }
-                const float *ln = lines + (lf * nwl + (int)(c - b0)) * kLineFloats;
+                const int li = lf * nwl + (int)(c - b0);
                 uint64_t LE, GE;
-                eval_line(V, ln, xv, cf + df, c, k0, kmax, own, LE, GE, cnt);
+                eval_line(V, lines + li * kLineFloats, xv, ly + 2 * li, cdl, k0, kmax, own, LE, GE, cnt);
                 lc |= (uint32_t)((LE | (LE >> 1)) & 0xffffffffull);
                 gc |= (uint32_t)((GE | (GE >> 1)) & 0xffffffffull);
             }
@@ -1011,7 +1016,16 @@ hipError_t launch_popcount(const uint32_t *p, int64_t n, unsigned long long *out
 // systems), contiguous in the step table, run by one launch; tiles are
 // numbered by the steps' tile_base prefix.  A plotting launch also runs the
 // fill steps of its level.
+// The step holding tile `item`: the last of steps[first..first+count) whose
+// tile_base is <= item.  With a full wave and at most 64 steps, every lane
+// reads one tile_base at once and the answer is the population count of the
+// ballot (tile bases ascend); otherwise a binary search.
 __device__ __forceinline__ int find_step(const PStep *steps, int first, int count, int64_t item) {
+    if (count <= 64 && __builtin_amdgcn_read_exec() == ~0ull) {
+        const int lane = __lane_id();
+        const int64_t tb = lane < count ? gp(steps)[first + lane].tile_base : INT64_MAX;
+        return first + (int)__popcll(__ballot(tb <= item)) - 1;
+    }
     int lo = first, hi = first + count - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
@@ -1168,23 +1182,16 @@ __global__ __launch_bounds__(256) void k_persist(const PStep *__restrict__ steps
     flush_counts(cnt, counters);
 }
 
-__global__ void k_persist_reset(PersistState *state, unsigned int *done, int nsteps, PlotCounters *counters) {
+__global__ void k_persist_reset(PersistState *state, unsigned int *done, int nsteps) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nsteps; i += gridDim.x * blockDim.x) done[i] = 0u;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         state->queue = 0ull;
         state->abort = 0u;
-        if (counters) {
-            counters->flagged = 0ull;
-            counters->disagree = 0ull;
-            counters->disagree_unflagged = 0ull;
-        }
     }
 }
 
-hipError_t launch_persist_reset(PersistState *state, unsigned int *done, int nsteps, PlotCounters *counters,
-                                hipStream_t s) {
-    hipLaunchKernelGGL(k_persist_reset, grid_for(nsteps > 0 ? nsteps : 1), dim3(256), 0, s, state, done, nsteps,
-                       counters);
+hipError_t launch_persist_reset(PersistState *state, unsigned int *done, int nsteps, hipStream_t s) {
+    hipLaunchKernelGGL(k_persist_reset, grid_for(nsteps > 0 ? nsteps : 1), dim3(256), 0, s, state, done, nsteps);
     return hipGetLastError();
 }
 

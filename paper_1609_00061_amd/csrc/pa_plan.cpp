@@ -319,12 +319,14 @@ struct Builder {
         g.sC_b = g.M * g.No * g.rwc;
         g.tiles_m = (g.M + 127) / 128;
         g.tiles_n = (g.No * g.rwc * 32 + 127) / 128;
-        // K split: enough workgroups to fill 256 CUs twice; partial results
-        // are OR-ed (exact in the Boolean semiring); also bounds the int32
-        // accumulator (at most 87380 per K word).
+        // K split: about gemm_split work items (512: 256 CUs twice); partial
+        // results are OR-ed (exact in the Boolean semiring); also bounds the
+        // int32 accumulator (at most 87380 per K word).
         int64_t tiles = g.nbatch * g.tiles_m * g.tiles_n;
         int64_t ksplit = 1;
-        if (!P->plain && tiles < 512) ksplit = std::max<int64_t>(1, std::min<int64_t>((512 + tiles - 1) / tiles, (g.Kw + 7) / 8));
+        const int64_t target = P->gemm_split;
+        if (!P->plain && tiles < target)
+            ksplit = std::max<int64_t>(1, std::min<int64_t>((target + tiles - 1) / tiles, (g.Kw + 7) / 8));
         ksplit = std::max<int64_t>(ksplit, (g.Kw + 16383) / 16384);
         int64_t chunk = (g.Kw + ksplit - 1) / ksplit;
         chunk = (chunk + 7) / 8 * 8;
@@ -581,9 +583,10 @@ int build_plan(const pa_system *sys, const int32_t *exposed, int32_t n_exposed, 
     P->persist_wg = o.persist_wg;
     P->plot_strip = o.plot_strip > 0 ? o.plot_strip : 4;
     P->contract_units = o.contract_units > 0 ? o.contract_units : 2048;
+    P->gemm_split = o.gemm_split > 0 ? o.gemm_split : 512;
     if (o.precision != PA_PLOT_FP32_ESCALATE && o.precision != PA_PLOT_FP64)
         return fail(PA_EINVAL, "opts: unknown precision");
-    if (o.persist_wg < 0 || o.plot_strip < 0 || o.contract_units < 0)
+    if (o.persist_wg < 0 || o.plot_strip < 0 || o.contract_units < 0 || o.gemm_split < 0)
         return fail(PA_EINVAL, "opts: negative tuning parameter");
     switch (o.order_policy) {
         case PA_ORDER_GREEDY: rc = plan_greedy(P->si, P->tree); break;
@@ -914,6 +917,10 @@ int upload_plan(pa_plan *P) {
                               hipMemcpyHostToDevice));
     int rc = build_steps(P);
     if (rc) return rc;
+    // counters and executor state start at zero (plot counters only grow)
+    HIP_TRY(hipMemset(base + P->counters_off, 0, sizeof(PlotCounters)));
+    HIP_TRY(hipMemset(base + P->state_off, 0, sizeof(PersistState)));
+    HIP_TRY(hipMemset(base + P->done_off, 0, sizeof(unsigned) * std::max<size_t>(1, P->steps_host.size())));
     P->uploaded = true;
     return PA_OK;
 }
@@ -990,7 +997,9 @@ static int run_persist(pa_plan *P, hipStream_t s, int *launches, hipEvent_t befo
     const int nsteps = (int)P->steps_host.size();
     int64_t wg = P->persist_wg > 0 ? P->persist_wg : persist_default_workgroups();
     wg = std::max<int64_t>(1, std::min<int64_t>(wg, P->n_items));
-    HIP_TRY(launch_persist_reset(state, done, nsteps, cnt, s));
+    // the plot counters only ever grow (a report takes the difference of
+    // two reads), so the grouped executor needs no reset launch
+    if (P->single_launch) HIP_TRY(launch_persist_reset(state, done, nsteps, s));
     if (before) HIP_TRY(hipEventRecord(before, s));
     const PStep *d_steps = reinterpret_cast<const PStep *>(base + P->steps_off);
     if (P->single_launch) {
@@ -1207,11 +1216,12 @@ extern "C" int pa_plan_execute(pa_plan *P, pa_bitarray *out, pa_report *rep, voi
     const bool timing = P->timing && rep;
     if (timing)
         for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
+    PlotCounters cnt0;
+    std::memset(&cnt0, 0, sizeof(cnt0));
+    if (rep) HIP_TRY(hipMemcpyAsync(&cnt0, base + P->counters_off, sizeof(cnt0), hipMemcpyDeviceToHost, s));
     if (timing) HIP_TRY(hipEventRecord(ev[0], s));
     if (!P->op_events.empty() && P->per_op) HIP_TRY(hipEventRecord(P->op_events[0], s));
     if (P->per_op) {
-        HIP_TRY(launch_fill(reinterpret_cast<uint32_t *>(base + P->counters_off), sizeof(PlotCounters) / 4, 0u, s));
-        ++launches;
         rc = run_plots(P, s, &launches);
         if (rc) return rc;
         if (!P->op_events.empty()) HIP_TRY(hipEventRecord(P->op_events[1], s));
@@ -1240,9 +1250,9 @@ extern "C" int pa_plan_execute(pa_plan *P, pa_bitarray *out, pa_report *rep, voi
         HIP_TRY(hipStreamSynchronize(s));
         if (!P->per_op && pst.abort) return fail(PA_EHIP, "persistent executor gave up a dependency wait");
         rep->corners = P->corners;
-        rep->corners_flagged = (int64_t)cnt.flagged;
-        rep->corners_disagree = (int64_t)cnt.disagree;
-        rep->corners_disagree_unflagged = (int64_t)cnt.disagree_unflagged;
+        rep->corners_flagged = (int64_t)(cnt.flagged - cnt0.flagged);
+        rep->corners_disagree = (int64_t)(cnt.disagree - cnt0.disagree);
+        rep->corners_disagree_unflagged = (int64_t)(cnt.disagree_unflagged - cnt0.disagree_unflagged);
         rep->nnz_out = (int64_t)nnz;
         rep->n_launches = launches;
         int steps = 0;

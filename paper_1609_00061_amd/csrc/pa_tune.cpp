@@ -1,6 +1,7 @@
 // Autotuner for the step executors: picks the executor (level-grouped
 // launches or one persistent launch, and its workgroup count), the plot
-// strip length and the streaming-contraction tile size for a workload by
+// strip length, the streaming-contraction tile size and the MFMA K-split
+// target for a workload by
 // timing candidates on the device.  Coordinate descent from the defaults;
 // results are cached per structural signature of the workload and GPU
 // architecture for the life of the process.
@@ -63,6 +64,7 @@ static void apply(pa_opts &o, const pa_tuning &t) {
     o.persist_wg = t.persist_wg;
     o.plot_strip = t.plot_strip;
     o.contract_units = t.contract_units;
+    o.gemm_split = t.gemm_split;
 }
 
 // Milliseconds per execution of a batch built with `o`, after one untimed
@@ -144,6 +146,7 @@ int autotune(const pa_system *systems, int32_t n_sys, const int32_t *const *expo
     pa_tuning cur{};
     cur.plot_strip = base.plot_strip > 0 ? base.plot_strip : 4;
     cur.contract_units = base.contract_units > 0 ? base.contract_units : 2048;
+    cur.gemm_split = base.gemm_split > 0 ? base.gemm_split : 512;
     if (!rc) rc = trial(cur);
     for (int wg : cus_wg) {
         if (rc) break;
@@ -165,6 +168,13 @@ int autotune(const pa_system *systems, int32_t n_sys, const int32_t *const *expo
         if (rc || best.ms < 0.0 || u == best.contract_units) continue;
         pa_tuning t = best;
         t.contract_units = u;
+        rc = trial(t);
+    }
+    const int splits[] = {1, 256, 512, 1024, 2048};
+    for (int sp : splits) {
+        if (rc || best.ms < 0.0 || sp == best.gemm_split) continue;
+        pa_tuning t = best;
+        t.gemm_split = sp;
         rc = trial(t);
     }
     for (void *p : bufs) (void)hipFree(p);

@@ -52,13 +52,13 @@ def _feasible(system, merges, max_out_log2=33.0) -> bool:
 
 
 def collect_samples(systems: Sequence, n_random: int = 3, reps: int = 3, seed: int = 1, stream=None,
-                    log=None, model=None, base_policies: bool = True, max_cost_ratio: float = 16.0):
+                    log=None, model=None, base_policies: bool = True, max_cost_ratio: float = 128.0):
     """(X [k, F] float32, T [k] float32 log2 microseconds) from timed plans.
     Trees: greedy and exhaustive (base_policies), n_random random connected
     merge orders, and the learned order of `model` when given; a tree whose
-    naive cost exceeds max_cost_ratio times the optimum is not timed (the
-    learned order never keeps such a tree, and one such solve can take
-    seconds).  Each tree is executed `reps` times after one warm-up; a step's
+    naive cost exceeds max_cost_ratio times the optimum is not timed (one
+    such solve can take seconds; slow trees within the ratio stay, so the
+    model sees the slow regime it must avoid).  Each tree is executed `reps` times after one warm-up; a step's
     sample is its fastest repetition."""
     rng = inputs.SplitMix64(seed)
     Xs, Ts = [], []

@@ -143,6 +143,21 @@ def test_validation_errors():
     s = inputs.config1()
     s.relations[0] = inputs.Relation((0, 0), 2, s.relations[0].coef)
     assert _bad(s) == pa.PA_EINVAL                      # repeated variable in a relation
+    for k in ("persist_wg", "plot_strip", "contract_units", "gemm_split"):
+        assert _bad(c1, **{k: -1}) == pa.PA_EINVAL      # negative tuning parameter
+
+
+def test_gemm_split_target_sets_the_k_split():
+    """A 1024^3 contraction has 64 output tiles: the default target (512 work
+    items) splits K in 4 (256-bit chunks), a target of 1 never splits."""
+    s = inputs.config2(res=1024)
+    gemms = lambda d: [o for o in d["ops"] if o["op"] == "gemm_mfma"]
+    assert {o["ksplit"] for o in gemms(pa.describe_plan(s))} == {4}
+    assert {o["ksplit"] for o in gemms(pa.describe_plan(s, gemm_split=1))} == {1}
+    assert {o["ksplit"] for o in gemms(pa.describe_plan(s, gemm_split=128))} == {2}
+    fills = lambda d: [o for o in d["ops"] if o["op"] == "fill"]
+    assert len(fills(pa.describe_plan(s))) == 7
+    assert len(fills(pa.describe_plan(s, gemm_split=1))) == 0
 
 
 def test_plan_create_rejects_before_touching_the_device():
