@@ -173,7 +173,7 @@ def _learned(stream, n_train=32, n_eval=48, res=128):
     r2 = float(1.0 - np.mean((pred - T) ** 2) / np.var(T))
     evals = inputs.config5(n_graphs=n_eval, index=0, res=res)
     _progress(f"trained in {train_s:.1f} s on {len(T)} samples; timing policies")
-    pol = learn.time_policies(evals, model, steps=3, stream=stream)
+    pol = learn.time_policies(evals, model, steps=3, stream=stream, log=_progress)
     out = {"workload": f"{n_eval} random relation hypergraphs (8-14 variables, arity 2-3, 2-4 exposed, "
                        f"{res} cells/axis, [-3,3]); model trained on {n_train} disjoint graphs",
            "train_s": train_s, "train_samples": int(len(T)), "fit_r2": r2,

@@ -331,13 +331,21 @@ int plan_learned(const SysInfo &si, const pa_model *model, Tree &t) {
     rc = tree_from_merges(si, merges, t);
     if (rc) return rc;
     t.predicted_us = best[at(full, hbest)];
-    // the exhaustive search judges the choice: a tree whose naive cost exceeds
-    // the optimum by more than kJudgeFactor is outside what the model was
-    // trained to rank, and the optimum is taken instead
+    // the exhaustive search judges the choice: a tree whose naive cost, or
+    // whose intermediate volume (cells written by its steps, each read once
+    // more: the data it moves), exceeds the optimum's by more than
+    // kJudgeFactor is outside what the model was trained to rank, and the
+    // optimum is taken instead
     Tree ex;
     rc = plan_exhaustive(si, ex);
     if (rc) return rc;
-    if (t.cost > kJudgeFactor * ex.cost) {
+    auto volume = [&](const Tree &tr) {
+        double v = 0.0;
+        for (const Node &nd : tr.nodes)
+            if (nd.leaf < 0) v += mask_cost(nd.q, si);
+        return v;
+    };
+    if (t.cost > kJudgeFactor * ex.cost || volume(t) > kJudgeFactor * volume(ex)) {
         ex.predicted_us = t.predicted_us;
         ex.learned_fallback = true;
         t = ex;

@@ -149,7 +149,7 @@ def train_order_model(systems: Sequence, rounds: int = 2, n_random: int = 3, rep
 
 
 def time_policies(systems: Sequence, model, policies=("greedy", "exhaustive", "learned"), steps: int = 10,
-                  warmup: int = 2, stream=None, check_bits: bool = True) -> Dict[str, dict]:
+                  warmup: int = 2, stream=None, check_bits: bool = True, log=None) -> Dict[str, dict]:
     """Measured solve time of every system under each ordering policy (the
     default grouped executor replayed as a hipGraph), plan times, and whether
     all policies produced identical bits."""
@@ -190,6 +190,8 @@ def time_policies(systems: Sequence, model, policies=("greedy", "exhaustive", "l
         if check_bits:
             first = outs[policies[0]]
             same = same and all(bool(torch.equal(first, outs[p])) for p in policies[1:])
+        if log:
+            log(f"timed {s.name}: " + ", ".join(f"{p} {res[p]['ms'][-1]:.3f} ms" for p in policies))
     summary = {p: {"total_ms": float(np.sum(v["ms"])), "per_system_ms": v["ms"],
                    "plan_ms_mean": float(np.mean(v["plan_ms"]))} for p, v in res.items()}
     summary["same_bits"] = same

@@ -24,7 +24,7 @@ def test_learned_order_beats_exhaustive_order():
     r2 = 1.0 - np.mean((pred - T) ** 2) / np.var(T)
     assert r2 > 0.8, r2
     note("learned: evaluating", len(evals), "graphs")
-    res = learn.time_policies(evals, model, policies=("exhaustive", "learned"), steps=3)
+    res = learn.time_policies(evals, model, policies=("exhaustive", "learned"), steps=3, log=note)
     assert res["same_bits"]
     assert res["systems"] >= 12
     assert res["learned"]["total_ms"] < res["exhaustive"]["total_ms"], res
