@@ -376,15 +376,12 @@ __device__ void plot_tile(const PlotRel &R, int64_t tile, float *lines, double *
     const int k0 = (int)(w * 32);
     const int kmax = pad ? 0 : min(32, rp - k0);
     // the 33 corner coordinates of this word, requested before the line
-    // tables are built
+    // tables are built (the FP32 table has 32 entries past the last corner,
+    // so one base serves every word; corners past kmax are masked later)
     float xv[33];
+    const PA_G float *xp = V.axfp + ((active && !pad) ? k0 : 0);
 #pragma unroll
-    for (int kk = 0; kk < 33; ++kk) {
-        // load from a clamped index (no branch per load), then mask
-        const int64_t k = (active && !pad) ? min((int64_t)k0 + kk, (int64_t)rp) : 0;
-        const float x = V.axfp[k];
-        xv[kk] = (active && !pad && kk <= kmax) ? x : 0.0f;
-    }
+    for (int kk = 0; kk < 33; ++kk) xv[kk] = xp[kk];
     // this thread's corner line (one per thread: lines <= kMaxTileLines <=
     // 256), its coordinates also requested before the staging
     double *cdl = cst + kDense, *ly = cdl + kDense;

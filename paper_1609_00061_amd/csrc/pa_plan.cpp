@@ -636,6 +636,9 @@ int build_plan(const pa_system *sys, const int32_t *exposed, int32_t n_exposed, 
         std::vector<double> x;
         std::vector<float> xf;
         axis_table(sys->axes[v].lo, sys->axes[v].hi, sys->axes[v].res, x, xf);
+        // 32 more FP32 entries (copies of the last corner): a plot thread
+        // reads the 33 corners of its word from one base without clamping
+        xf.resize(xf.size() + 32, xf.back());
         ax_at[v] = put(x.data(), x.size() * sizeof(double));
         axf_at[v] = put(xf.data(), xf.size() * sizeof(float));
     }
