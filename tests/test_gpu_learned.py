@@ -28,8 +28,11 @@ def test_learned_order_beats_exhaustive_order():
     assert res["same_bits"]
     assert res["systems"] >= 12
     assert res["learned"]["total_ms"] < res["exhaustive"]["total_ms"], res
-    # and the learned order's bits are the oracle's
-    for s in evals[:3]:
+    # and the learned order's bits are the oracle's (on the three graphs of
+    # smallest naive cost: the CPU oracle takes minutes beyond ~1e9 MACs)
+    small = sorted(evals, key=lambda s: pa.describe_plan(s)["cost"])[:3]
+    for s in small:
+        note("learned: oracle check", s.name)
         ref = oracle.solve([a[2] for a in s.axes], [r.vars for r in s.relations],
                            [oracle.plot(r, s.axes)[0] for r in s.relations], s.exposed)
         out, dims, _ = pa.solve_system(s, order=pa.ORDER_LEARNED, model=model)
