@@ -289,6 +289,9 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--tuning", type=str, default="",
+                    help="JSON executor settings to use instead of autotuning (e.g. for counter runs, whose "
+                         "serialization distorts timings)")
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
                     help="after the run, copy a buffer of this size 3 times (scales HBM byte counters)")
     args = ap.parse_args()
@@ -307,7 +310,12 @@ def main():
     stream = torch.cuda.Stream()
     _progress("planning and autotuning the chain workload")
     t0 = time.perf_counter()
-    plan = pa.Plan(system, order=pa.ORDER_EXHAUSTIVE, precision=pa.PLOT_FP32_ESCALATE, graph=True, autotune=True)
+    if args.tuning:
+        tuning = {k: int(v) for k, v in json.loads(args.tuning).items()}
+    else:
+        tuning, _ = pa.autotune([system], reps=5, stream=stream, order=pa.ORDER_EXHAUSTIVE, graph=True)
+        tuning = {k: int(v) for k, v in tuning.items() if k != "ms"}
+    plan = pa.Plan(system, order=pa.ORDER_EXHAUSTIVE, precision=pa.PLOT_FP32_ESCALATE, graph=True, **tuning)
     plan_s = time.perf_counter() - t0
     out = pa.empty_bits(plan.dims)
     dt = _time_plan(plan, out, K, W, stream)
@@ -332,10 +340,13 @@ def main():
                                "[-3,3]^9 at 1024 cells/axis, x1 and x9 exposed, 7 latent",
                    "plotting": "fp32 + fp64 escalation", "contraction": "int8 MFMA, int32 accumulation, count>0",
                    "order": "exhaustive (balanced tree on cost ties)",
-                   "executor": "one grouped launch per tree level and kernel kind, hipGraph replay, autotuned tiles",
+                   "executor": ("one persistent launch per solve, hipGraph replay" if tuning.get("single_launch")
+                                else "one grouped launch per tree level and kernel kind, hipGraph replay") +
+                               (", tiles " + ("given" if args.tuning else "autotuned")),
                    "global_batch": 1},
         "step_ms_events": pct,
         "plan_and_tune_s": plan_s,
+        "tuning": tuning,
         "nnz_out": rep["nnz_out"],
         "escalated_corners": rep["corners_flagged"],
         "corners": rep["corners"],
@@ -343,7 +354,12 @@ def main():
 
     _progress(f"timed {K} solves: {1e3 * dt / K:.4f} ms each")
     # per-kernel durations and the roofline of the dominant kernel
-    roof, per_kind, _ = _kernel_table(plan, stream, system, reps=20)
+    kplan = plan
+    if tuning.get("single_launch"):
+        # per-launch durations need the grouped executor (same tiles)
+        kplan = pa.Plan(system, order=pa.ORDER_EXHAUSTIVE, graph=True, **dict(tuning, single_launch=0))
+        kplan.execute(pa.empty_bits(kplan.dims), stream=stream)
+    roof, per_kind, _ = _kernel_table(kplan, stream, system, reps=20)
     dom = max(roof.values(), key=lambda r: r["ms_per_step"]) if roof else None
     if dom:
         result["roofline"] = {k: dom[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic")}

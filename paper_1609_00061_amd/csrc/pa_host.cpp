@@ -108,17 +108,9 @@ std::vector<double> dense_coef(const pa_relation &r) {
 }
 
 // Pixel boundaries x_k = lo + k * ((hi - lo) / r), k = 0..r (eqn Pixel_def,
-// 0-based corners), in FP64 without contraction, plus RN-to-FP32 copies.
-void axis_table(double lo, double hi, int r, std::vector<double> &x, std::vector<float> &xf) {
-    x.resize((size_t)r + 1);
-    xf.resize((size_t)r + 1);
-    const double delta = (hi - lo) / (double)r;
-    for (int k = 0; k <= r; ++k) {
-        volatile double t = (double)k * delta;
-        x[k] = lo + t;
-        xf[k] = (float)x[k];
-    }
-}
+// 0-based corners): the kernels form k * step and then lo + that in FP64,
+// each rounded (no contraction), and take the nearest float for FP32.
+double axis_step(double lo, double hi, int r) { return (hi - lo) / (double)r; }
 
 // -------------------------------------------------------------- validation
 int validate_relation(const pa_relation &r, const pa_axis *axes_of_vars, int n_vars_total, const char *who) {

@@ -34,10 +34,13 @@ struct PlotRel {
     int perm[kMaxA];
     int res[kMaxA];            // resolution per storage axis
     int64_t row_words;
-    const double *coef;        // dense table c[e0 + (d+1)*(e1 + (d+1)*e2)], declared exponents
-    const double *ax[kMaxA];   // FP64 pixel boundaries per storage axis (res+1 entries)
-    const float *axf[kMaxA];   // RN-to-FP32 copies
+    // corner k of storage axis s is lo[s] + k * step[s] in FP64 (a product
+    // and a sum, each rounded), its FP32 copy the nearest float to that
+    double lo[kMaxA], step[kMaxA];
     double vmax;               // upper bound of |x| on the packed storage axis
+    double ebound;             // (gamma_{2d+1} + 2^-40)(1 + 2^-30): the FP32 line bound's factor of S
+    double vpow[kMaxD + 2];    // max(1, vmax)^t, t = 0..d+1
+    double coef[kDense];       // dense table c[e0 + (d+1)*(e1 + (d+1)*e2)], declared exponents
     uint32_t *out;
     int tw, ta, tb, s;
     int64_t tiles_w, tiles_walk, tiles_fixed, n_tiles;

@@ -84,10 +84,12 @@ struct PlotCount {
 // axis (n == 3).  A thread owns one 32-cell word of one strip: it evaluates
 // the 33 corners of the word on every corner line bounding its strip (FP32,
 // coordinates held in registers), so a corner line is evaluated once per
-// strip.  The tile first stages the coefficient table, permuted to storage
-// order, in LDS, and builds the FP32 restriction and bound of each of its
-// corner lines there (FP64, one line per thread); the threads' coordinate
-// loads are issued before that so their latency overlaps it.
+// strip.  The tile first stages the coefficient table (carried by the plot
+// record) in LDS, in storage order and as declared, with the FP64
+// coordinates of its corner lines, and builds the FP32 restriction and bound
+// of each corner line there (FP64, one line per thread).  Corner coordinates
+// are formed from the axis origin and step, not loaded: the record is the
+// only memory a tile reads.
 
 // Fields of a relation a tile uses, held in registers (the record itself is
 // in global memory, which the tile's output stores could alias).
@@ -97,13 +99,20 @@ struct PlotView {
     int res0, res1;            // resolutions of storage axes 0 and 1
     int rwalk, rp;             // walk axis (storage n-2; 1 if n == 1) and packed axis
     int64_t row_words;
-    const PA_G double *coef;
-    const PA_G double *ax0, *ax1;   // FP64 coordinates of storage axes 0 and 1
-    const PA_G double *axp;         // FP64 coordinates of the packed axis
-    const PA_G float *axfp;         // FP32 coordinates of the packed axis
+    const PA_G double *coef;        // the record's dense coefficient table
+    double lo0, st0, lo1, st1;      // corners of storage axes 0 and 1: lo + k * st
+    double lop, stp;                // corners of the packed axis
+    double ebound;                  // factor of S in the FP32 line bound
+    const PA_G double *vpow;        // max(1, vmax)^t
     PA_G uint32_t *out;
-    double vmax;
 };
+
+// FP64 corner coordinate lo + k * st: the product, then the sum, each
+// rounded (the build does not contract them into an fma), as on the host.
+__device__ __forceinline__ double corner_coord(double lo, double st, int64_t k) {
+    const double t = (double)k * st;
+    return lo + t;
+}
 
 __device__ __forceinline__ PlotView plot_view(const PlotRel &R) {
     PlotView v;
@@ -120,13 +129,16 @@ __device__ __forceinline__ PlotView plot_view(const PlotRel &R) {
     v.rp = n == 1 ? R.res[0] : (n == 2 ? R.res[1] : R.res[2]);
     v.rwalk = n == 1 ? 1 : (n == 2 ? R.res[0] : R.res[1]);
     v.row_words = R.row_words;
-    v.coef = gp(R.coef);
-    v.ax0 = gp(R.ax[0]);
-    v.ax1 = gp(R.ax[1]);
-    v.axp = gp(n == 1 ? R.ax[0] : (n == 2 ? R.ax[1] : R.ax[2]));
-    v.axfp = gp(n == 1 ? R.axf[0] : (n == 2 ? R.axf[1] : R.axf[2]));
+    v.coef = gp(&R.coef[0]);
+    v.lo0 = R.lo[0];
+    v.st0 = R.step[0];
+    v.lo1 = R.lo[1];
+    v.st1 = R.step[1];
+    v.lop = n == 1 ? R.lo[0] : (n == 2 ? R.lo[1] : R.lo[2]);
+    v.stp = n == 1 ? R.step[0] : (n == 2 ? R.step[1] : R.step[2]);
+    v.ebound = R.ebound;
+    v.vpow = gp(&R.vpow[0]);
     v.out = gp(R.out);
-    v.vmax = R.vmax;
     return v;
 }
 
@@ -183,77 +195,71 @@ __device__ __forceinline__ void stage_coefs(const PlotView &V, double *cst, doub
 // so sign(p^) = sign(f64) != 0.
 __device__ void line_coefs(const PlotView &V, const double *cst, double y0, double y1, float *dst) {
     const int n = V.n, d = V.d, D1 = d + 1;
-    double a[kMaxD + 1], sab[kMaxD + 1];
+    const double ay0 = fabs(y0), ay1 = fabs(y1);
+    // a_t and s_t as Horner polynomials in y0 (and y1): s_t uses |c| and
+    // |y|, whose products are the |terms|; the d + 1 chains are independent
+    double S = 0.0;
 #pragma unroll
     for (int t = 0; t <= kMaxD; ++t) {
         double at = 0.0, st = 0.0;
         if (t <= d) {
+            const int top = d - t;     // a_t has degree d - t in the other variables
             if (n == 1) {
                 at = cst[t];
                 st = fabs(at);
             } else if (n == 2) {
-                double p = 1.0;
+                at = cst[top + D1 * t];
+                st = fabs(at);
 #pragma unroll
-                for (int e0 = 0; e0 <= kMaxD; ++e0) {
-                    if (e0 + t <= d) {
-                        const double term = cst[e0 + D1 * t] * p;
-                        at += term;
-                        st += fabs(term);
+                for (int e0 = kMaxD - 1; e0 >= 0; --e0) {
+                    if (e0 < top) {
+                        const double c = cst[e0 + D1 * t];
+                        at = fma(at, y0, c);
+                        st = fma(st, ay0, fabs(c));
                     }
-                    p *= y0;
                 }
             } else {
-                double p1 = 1.0;
+                // sum over e1 (Horner in y1) of B_e1(y0) (Horner in y0)
 #pragma unroll
-                for (int e1 = 0; e1 <= kMaxD; ++e1) {
-                    double p = p1;
+                for (int e1 = kMaxD; e1 >= 0; --e1) {
+                    if (e1 <= top) {
+                        const int tb = top - e1;
+                        double b = cst[tb + D1 * (e1 + D1 * t)], sb = fabs(b);
 #pragma unroll
-                    for (int e0 = 0; e0 <= kMaxD; ++e0) {
-                        if (e0 + e1 + t <= d) {
-                            const double term = cst[e0 + D1 * (e1 + D1 * t)] * p;
-                            at += term;
-                            st += fabs(term);
+                        for (int e0 = kMaxD - 1; e0 >= 0; --e0) {
+                            if (e0 < tb) {
+                                const double c = cst[e0 + D1 * (e1 + D1 * t)];
+                                b = fma(b, y0, c);
+                                sb = fma(sb, ay0, fabs(c));
+                            }
                         }
-                        p *= y0;
+                        at = (e1 == top) ? b : fma(at, y1, b);
+                        st = (e1 == top) ? sb : fma(st, ay1, sb);
                     }
-                    p1 *= y1;
                 }
             }
+            S = fma(st, V.vpow[t], S);
         }
-        a[t] = at;
-        sab[t] = st;
+        dst[t] = (t <= d) ? (float)at : 0.0f;
     }
-    const double Vm = fmax(1.0, V.vmax);
-    double S = 0.0, Vp = 1.0;
-#pragma unroll
-    for (int t = 0; t <= kMaxD; ++t) {
-        if (t <= d) {
-            S += sab[t] * Vp;
-            Vp *= Vm;
-        }
-    }
-    const double u = 0x1p-24;
-    const double K = 2.0 * d + 1.0;
-    const double gam = K * u / (1.0 - K * u);
-    const double E = (gam + 0x1p-40) * S * (1.0 + 0x1p-30) + 0x1p-100 * (1.0 + S) * Vp;
+    const double E = V.ebound * S + 0x1p-100 * (1.0 + S) * V.vpow[d + 1];
     float Ef = (float)E;
     if ((double)Ef < E) Ef = nextafterf(Ef, INFINITY);
     // every Horner partial sum is below 2S: with S <= 2^126 nothing overflows
     // FP32; otherwise no corner of the line is certain
     if (!(S <= 0x1p126)) Ef = INFINITY;
-#pragma unroll
-    for (int t = 0; t <= kMaxD; ++t) dst[t] = (t <= d) ? (float)a[t] : 0.0f;
     dst[kLineFloats - 1] = Ef;
 }
 
 // FP32 pass over the corners k0..k0+kmax of one corner line (coordinates in
 // registers), NF Horner steps (NF >= degree; coefficients above the degree
-// are zero and fma(0, x, a) = a exactly).  A corner's FP32 sign is certain
-// iff E - |f| < 0: min(., +0) sends a NaN to +0, and E is +inf when the
-// line's magnitude bound allows FP32 overflow, so a certain f is finite and
-// nonzero.  The sign bits and the certainty bits are shifted into words with
-// one alignbit each (corners taken from 31 down to 0).  Out: LE/GE where the
-// sign is certain, FL the corners FP64 decides.
+// are zero and fma(0, x, a) = a exactly).  E is +inf when the line's
+// magnitude bound allows FP32 overflow: then FP64 decides every corner.
+// Otherwise every f is finite (its partial sums stay below 2S <= 2^127) and
+// a corner's FP32 sign is certain iff E - |f| < 0 (f then nonzero).  The
+// sign bits and the certainty bits are shifted into words with one alignbit
+// each (corners taken from 31 down to 0).  Out: LE/GE where the sign is
+// certain, FL the corners FP64 decides.
 template <int NF>
 __device__ __forceinline__ void line_fp32(const float *ln, const float *xv, int kmax, uint64_t &LE, uint64_t &GE,
                                           uint64_t &FL) {
@@ -261,6 +267,13 @@ __device__ __forceinline__ void line_fp32(const float *ln, const float *xv, int 
 #pragma unroll
     for (int t = 0; t <= NF; ++t) ca[t] = ln[t];
     const float E = ln[kLineFloats - 1];
+    const uint64_t valid = (kmax >= 63) ? ~0ull : ((2ull << kmax) - 1ull);
+    if (!(E < INFINITY)) {
+        LE = 0;
+        GE = 0;
+        FL = valid;
+        return;
+    }
     auto value = [&](float x) {
         float f = ca[NF];
 #pragma unroll
@@ -268,15 +281,14 @@ __device__ __forceinline__ void line_fp32(const float *ln, const float *xv, int 
         return f;
     };
     const float f32 = value(xv[32]);
-    const uint32_t sg32 = __float_as_uint(f32) >> 31, ok32 = __float_as_uint(fminf(E - fabsf(f32), 0.0f)) >> 31;
+    const uint32_t sg32 = __float_as_uint(f32) >> 31, ok32 = __float_as_uint(E - fabsf(f32)) >> 31;
     uint32_t sg = 0, ok = 0;
 #pragma unroll
     for (int kk = 31; kk >= 0; --kk) {
         const float f = value(xv[kk]);
         sg = __builtin_amdgcn_alignbit(sg, __float_as_uint(f), 31);
-        ok = __builtin_amdgcn_alignbit(ok, __float_as_uint(fminf(E - fabsf(f), 0.0f)), 31);
+        ok = __builtin_amdgcn_alignbit(ok, __float_as_uint(E - fabsf(f)), 31);
     }
-    const uint64_t valid = (kmax >= 63) ? ~0ull : ((2ull << kmax) - 1ull);
     const uint64_t okm = ((uint64_t)ok | ((uint64_t)ok32 << 32)) & valid;
     const uint64_t sgm = (uint64_t)sg | ((uint64_t)sg32 << 32);
     LE = okm & sgm;
@@ -295,7 +307,6 @@ __device__ __forceinline__ void eval_line(const PlotView &V, const float *ln, co
     const int n = V.n, rp = V.rp;
     const uint64_t valid = (kmax >= 63) ? ~0ull : ((2ull << kmax) - 1ull);
     const uint64_t owned = own ? (((1ull << kmax) - 1ull) | ((k0 + kmax == rp) ? (1ull << kmax) : 0ull)) : 0ull;
-    const PA_G double *axp = V.axp + k0;
     uint64_t FL = valid, todo;
     if (V.mode == PA_PLOT_FP32_ESCALATE) {
         if (V.d <= 3) line_fp32<3>(ln, xv, kmax, LE, GE, FL);
@@ -314,7 +325,7 @@ __device__ __forceinline__ void eval_line(const PlotView &V, const float *ln, co
         const int kk = __ffsll((long long)todo) - 1;
         todo &= todo - 1;
         double xd[3];
-        const double xk = axp[kk];
+        const double xk = corner_coord(V.lop, V.stp, k0 + kk);
         if (n == 1) decl_point(V, xk, 0.0, 0.0, xd);
         else if (n == 2) decl_point(V, y0, xk, 0.0, xd);
         else decl_point(V, y0, y1, xk, xd);
@@ -327,8 +338,8 @@ __device__ __forceinline__ void eval_line(const PlotView &V, const float *ln, co
         }
         if (V.mode == PA_PLOT_FP32_ESCALATE && V.audit) {
             // FP32 value of this corner, recomputed as in line_fp32 (same
-            // RN32 coordinate, from the table)
-            const float x = V.axfp[k0 + kk];
+            // RN32 coordinate)
+            const float x = (float)xk;
             float f = ln[kMaxD];
 #pragma unroll
             for (int t = kMaxD - 1; t >= 0; --t) f = fmaf(f, x, ln[t]);
@@ -375,15 +386,14 @@ __device__ void plot_tile(const PlotRel &R, int64_t tile, float *lines, double *
     const bool pad = w * 32 >= rp;
     const int k0 = (int)(w * 32);
     const int kmax = pad ? 0 : min(32, rp - k0);
-    // the 33 corner coordinates of this word, requested before the line
-    // tables are built (the FP32 table has 32 entries past the last corner,
-    // so one base serves every word; corners past kmax are masked later)
+    // the 33 corner coordinates of this word (corners past kmax are masked
+    // later), formed in FP64 and rounded to FP32
     float xv[33];
-    const PA_G float *xp = V.axfp + ((active && !pad) ? k0 : 0);
+    const int kb = (active && !pad) ? k0 : 0;
 #pragma unroll
-    for (int kk = 0; kk < 33; ++kk) xv[kk] = xp[kk];
+    for (int kk = 0; kk < 33; ++kk) xv[kk] = (float)corner_coord(V.lop, V.stp, kb + kk);
     // this thread's corner line (one per thread: lines <= kMaxTileLines <=
-    // 256), its coordinates also requested before the staging
+    // 256) and its FP64 coordinates
     double *cdl = cst + kDense, *ly = cdl + kDense;
     const int nlines = nwl * nfl;
     bool lvalid = false;
@@ -394,13 +404,13 @@ __device__ void plot_tile(const PlotRel &R, int64_t tile, float *lines, double *
         if (n == 2) {
             const int64_t ib = b0 + lw;
             lvalid = ib <= rwalk;
-            if (lvalid) y0 = V.ax0[ib];
+            if (lvalid) y0 = corner_coord(V.lo0, V.st0, ib);
         } else if (n == 3) {
             const int64_t ia = a0 + lf, ib = b0 + lw;
             lvalid = ia <= V.res0 && ib <= rwalk;
             if (lvalid) {
-                y0 = V.ax0[ia];
-                y1 = V.ax1[ib];
+                y0 = corner_coord(V.lo0, V.st0, ia);
+                y1 = corner_coord(V.lo1, V.st1, ib);
             }
         }
     }

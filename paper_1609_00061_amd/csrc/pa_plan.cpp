@@ -626,22 +626,7 @@ int build_plan(const pa_system *sys, const int32_t *exposed, int32_t n_exposed, 
         std::memcpy(T.data() + at, p, n);
         return at;
     };
-    std::vector<size_t> coef_at(sys->n_rel), ax_at(sys->n_vars), axf_at(sys->n_vars);
-    for (int r = 0; r < sys->n_rel; ++r) {
-        std::vector<double> c = dense_coef(sys->rel[r]);
-        c.resize(kDense, 0.0);
-        coef_at[r] = put(c.data(), c.size() * sizeof(double));
-    }
-    for (int v = 0; v < sys->n_vars; ++v) {
-        std::vector<double> x;
-        std::vector<float> xf;
-        axis_table(sys->axes[v].lo, sys->axes[v].hi, sys->axes[v].res, x, xf);
-        // 32 more FP32 entries (copies of the last corner): a plot thread
-        // reads the 33 corners of its word from one base without clamping
-        xf.resize(xf.size() + 32, xf.back());
-        ax_at[v] = put(x.data(), x.size() * sizeof(double));
-        axf_at[v] = put(xf.data(), xf.size() * sizeof(float));
-    }
+    (void)put;   // plot records carry their coefficients and axes by value
     const size_t nsteps = P->plots.size() + P->ops.size();
     P->tables_off = take(T.size());
     P->plotrel_off = take(sizeof(PlotRel) * std::max<size_t>(1, P->plots.size()));
@@ -675,19 +660,33 @@ int build_plan(const pa_system *sys, const int32_t *exposed, int32_t n_exposed, 
         R.mode = P->precision;
         R.audit = P->audit;
         R.row_words = it.layout.rw;
-        R.coef = reinterpret_cast<const double *>(coef_at[it.rel]);
+        {
+            std::vector<double> c = dense_coef(rel);
+            std::copy(c.begin(), c.end(), R.coef);
+        }
         double vmax = 0.0;
         for (int s = 0; s < R.n; ++s) {
             const int dv = it.storage[s];
             const int var = rel.vars[dv];
             R.perm[s] = dv;
             R.res[s] = sys->axes[var].res;
-            R.ax[s] = reinterpret_cast<const double *>(ax_at[var]);
-            R.axf[s] = reinterpret_cast<const float *>(axf_at[var]);
+            R.lo[s] = sys->axes[var].lo;
+            R.step[s] = axis_step(sys->axes[var].lo, sys->axes[var].hi, sys->axes[var].res);
             if (s == R.n - 1) vmax = std::max(std::fabs(sys->axes[var].lo), std::fabs(sys->axes[var].hi));
         }
         // |x_k| <= max(|lo|, |hi|) up to the two roundings of x_k
         R.vmax = vmax * (1.0 + 0x1p-50) + 0x1p-1000;
+        {
+            const double u = 0x1p-24, K = 2.0 * R.d + 1.0;
+            const double gam = K * u / (1.0 - K * u);
+            R.ebound = (gam + 0x1p-40) * (1.0 + 0x1p-30);
+            const double Vm = std::max(1.0, R.vmax);
+            double p = 1.0;
+            for (int t = 0; t <= R.d + 1; ++t) {
+                R.vpow[t] = p;
+                p *= Vm;
+            }
+        }
         R.out = reinterpret_cast<uint32_t *>((size_t)P->buf_off[it.buf]);
         plot_tiling(R, P->plot_strip);
         if (R.n_tiles >= ((int64_t)1 << 31)) return fail(PA_EUNSUPPORTED, "relation too large to plot in one array");
@@ -897,15 +896,10 @@ int upload_plan(pa_plan *P) {
     char *base = static_cast<char *>(P->ws.ptr);
     std::vector<PlotRel> rels = P->plotrel_host;
     auto fix = [&](const void *off) { return (void *)(base + P->tables_off + (size_t)off); };
-    for (auto &R : rels) {
-        R.coef = (const double *)fix(R.coef);
-        for (int s = 0; s < R.n; ++s) {
-            R.ax[s] = (const double *)fix(R.ax[s]);
-            R.axf[s] = (const float *)fix(R.axf[s]);
-        }
-        R.out = (uint32_t *)(base + (size_t)R.out);
-    }
-    HIP_TRY(hipMemcpy(base + P->tables_off, P->tables_host.data(), P->tables_host.size(), hipMemcpyHostToDevice));
+    (void)fix;
+    for (auto &R : rels) R.out = (uint32_t *)(base + (size_t)R.out);
+    if (!P->tables_host.empty())
+        HIP_TRY(hipMemcpy(base + P->tables_off, P->tables_host.data(), P->tables_host.size(), hipMemcpyHostToDevice));
     P->plotrel1_dev = rels;
     for (auto &R : P->plotrel1_dev) R.tile_base = 0;
     if (!rels.empty()) {

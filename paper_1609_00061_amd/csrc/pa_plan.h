@@ -30,7 +30,7 @@ Layout make_layout(const std::vector<int> &vars, const std::vector<int64_t> &res
 std::vector<std::array<int, 3>> graded_lex(int n, int d);
 int64_t n_monomials(int n, int d);
 std::vector<double> dense_coef(const pa_relation &r);
-void axis_table(double lo, double hi, int r, std::vector<double> &x, std::vector<float> &xf);
+double axis_step(double lo, double hi, int r);   // corner k: lo + k * step (two roundings)
 int validate_relation(const pa_relation &r, const pa_axis *axes_of_vars, int n_vars_total, const char *who);
 int check_bitarray(const pa_bitarray *a, const std::vector<int64_t> &dims, const char *who);
 

@@ -102,3 +102,32 @@ def test_full_size_relations(which):
         assert np.array_equal(got, ref), rel.vars
         flagged += rep["corners_flagged"]
     note(which, "flagged corners", flagged)
+
+
+EXTREMES = [
+    ("huge", 1e36, [(-3.0, 3.0, 40), (-3.0, 3.0, 70)]),         # S > 2^126: every corner escalated
+    ("tiny", 1e-30, [(-3.0, 3.0, 40), (-3.0, 3.0, 70)]),        # values near the 2^-100 underflow term
+    ("wide", 1.0, [(-1e9, 1e9, 65), (-2e8, 3e9, 66)]),          # |x|^3 ~ 1e27
+    ("mixed", 1.0, [(-3.0, 3.0, 50), (-3.0, 3.0, 50)]),         # one coefficient 1e37, the rest N(0,1)
+]
+
+
+@pytest.mark.parametrize("case", range(len(EXTREMES)))
+def test_extreme_magnitudes(case):
+    """The FP32 bound at its edges: coefficients so large that FP32 could
+    overflow (the line bound is +inf and FP64 decides every corner), values
+    down at the underflow term, wide axes; bit-exact in both precisions and
+    no unflagged FP32/FP64 sign disagreement."""
+    name, scale, axes = EXTREMES[case]
+    rel = random_relation(9100 + case, 2)
+    rel.coef[:] = np.asarray(rel.coef) * scale
+    if name == "mixed":
+        rel.coef[4] = 1e37
+    ref, _ = oracle.plot(rel, axes)
+    for precision in MODES:
+        got, rep = _plot(rel, axes, precision, audit=(precision == pa.PLOT_FP32_ESCALATE))
+        assert np.array_equal(got, ref), (name, precision)
+        if precision == pa.PLOT_FP32_ESCALATE:
+            assert rep["corners_disagree_unflagged"] == 0
+            if name == "huge":
+                assert rep["corners_flagged"] == rep["corners"]
