@@ -150,10 +150,12 @@ typedef struct {
                                  contract_units) from the autotuner: cached per
                                  workload structure and GPU architecture, tuned by
                                  timing on the device (stream 0) on a cache miss */
-    int32_t gemm_split;       /* MFMA contractions: a contraction with fewer 128x128
-                                 output tiles than this splits its K range into
-                                 partial products OR-ed into a zeroed output
-                                 (exact); 1: never split; 0: default (512)       */
+    int32_t gemm_split;       /* MFMA contractions: those of one tree level (one
+                                 grouped launch) split their K range until the
+                                 launch holds about this many work items (128x128
+                                 tiles x parts); partial products are OR-ed into a
+                                 zeroed output (exact); 1: never split; 0: default
+                                 (512)                                            */
 } pa_opts;
 
 typedef struct {

@@ -142,6 +142,8 @@ struct Choice {
     double cost = 0.0;
 };
 
+static void set_ksplit(GemmArgs &g, int64_t want);
+
 struct Builder {
     pa_plan *P;
     const pa_system *sys;
@@ -319,32 +321,12 @@ struct Builder {
         g.sC_b = g.M * g.No * g.rwc;
         g.tiles_m = (g.M + 127) / 128;
         g.tiles_n = (g.No * g.rwc * 32 + 127) / 128;
-        // K split: about gemm_split work items (512: 256 CUs twice); partial
-        // results are OR-ed (exact in the Boolean semiring); also bounds the
-        // int32 accumulator (at most 87380 per K word).
-        int64_t tiles = g.nbatch * g.tiles_m * g.tiles_n;
-        int64_t ksplit = 1;
-        const int64_t target = P->gemm_split;
-        if (!P->plain && tiles < target)
-            ksplit = std::max<int64_t>(1, std::min<int64_t>((target + tiles - 1) / tiles, (g.Kw + 7) / 8));
-        ksplit = std::max<int64_t>(ksplit, (g.Kw + 16383) / 16384);
-        int64_t chunk = (g.Kw + ksplit - 1) / ksplit;
-        chunk = (chunk + 7) / 8 * 8;
-        ksplit = (g.Kw + chunk - 1) / chunk;
-        g.kchunk = chunk;
-        g.ksplit = (int)std::max<int64_t>(1, ksplit);
-        g.fd_ksplit = make_fastdiv((uint64_t)g.ksplit);
+        // the K split (and the fill it needs) is set by split_gemms once
+        // every step of the tree is known
+        set_ksplit(g, 1);
         g.fd_tiles_n = make_fastdiv((uint64_t)std::max<int64_t>(1, g.tiles_n));
         g.fd_tiles_m = make_fastdiv((uint64_t)std::max<int64_t>(1, g.tiles_m));
         g.fd_wc = make_fastdiv((uint64_t)(g.rwc * 32));
-        if (g.ksplit > 1) {
-            Op f;
-            f.kind = OP_FILL;
-            f.c = c;
-            f.fill_words = lc.words;
-            f.node = node;
-            P->ops.push_back(f);
-        }
         P->ops.push_back(op);
     }
 
@@ -528,6 +510,61 @@ std::string Op::describe() const {
 // --------------------------------------------------------------- planning
 // Plot tiles: tw words along the packed axis; the rest of the 256 threads
 // spread over ta cells of the fixed axis (n == 3) x tb strips of s walk cells.
+// K split of an MFMA contraction: about `want` parts of whole 256-bit
+// chunks, and enough parts that none has more than 16384 K words (a count
+// gains at most 87380 per K word, so the int32 accumulator stays below 2^31).
+static void set_ksplit(GemmArgs &g, int64_t want) {
+    int64_t ksplit = std::max<int64_t>(1, std::min<int64_t>(want, (g.Kw + 7) / 8));
+    ksplit = std::max<int64_t>(ksplit, (g.Kw + 16383) / 16384);
+    int64_t chunk = (g.Kw + ksplit - 1) / ksplit;
+    chunk = (chunk + 7) / 8 * 8;
+    ksplit = (g.Kw + chunk - 1) / chunk;
+    g.kchunk = chunk;
+    g.ksplit = (int)std::max<int64_t>(1, ksplit);
+    g.fd_ksplit = make_fastdiv((uint64_t)g.ksplit);
+}
+
+// Level-aware K split: the MFMA contractions that run in one grouped launch
+// (one level of the tree) split their K range until the launch holds about
+// gemm_split work items (tiles x parts; 512: 256 CUs twice); partial
+// products are OR-ed into a zeroed output (exact in the Boolean semiring),
+// so every split contraction gets a fill step before it.
+static void split_gemms(pa_plan *P) {
+    std::map<int, int> level_of_buf;
+    for (const auto &pl : P->plots) level_of_buf[pl.buf] = 0;
+    std::vector<int> level(P->ops.size(), 0);
+    std::map<int, int64_t> tiles_at;
+    for (size_t i = 0; i < P->ops.size(); ++i) {
+        const Op &op = P->ops[i];
+        int lv = 0;
+        for (int b : {op.a, op.b}) {
+            auto it = level_of_buf.find(b);
+            if (it != level_of_buf.end()) lv = std::max(lv, it->second + 1);
+        }
+        level[i] = lv;
+        level_of_buf[op.c] = lv;
+        if (op.kind == OP_GEMM) tiles_at[lv] += op.ga.nbatch * op.ga.tiles_m * op.ga.tiles_n;
+    }
+    std::vector<Op> ops;
+    for (size_t i = 0; i < P->ops.size(); ++i) {
+        Op op = P->ops[i];
+        if (op.kind == OP_GEMM) {
+            const int64_t tiles = tiles_at[level[i]], target = P->gemm_split;
+            set_ksplit(op.ga, (!P->plain && tiles < target) ? (target + tiles - 1) / tiles : 1);
+            if (op.ga.ksplit > 1) {
+                Op f;
+                f.kind = OP_FILL;
+                f.c = op.c;
+                f.fill_words = op.lc.words;
+                f.node = op.node;
+                ops.push_back(f);
+            }
+        }
+        ops.push_back(op);
+    }
+    P->ops.swap(ops);
+}
+
 static void plot_tiling(PlotRel &R, int strip) {
     const int n = R.n;
     R.tw = (int)std::min<int64_t>(32, R.row_words);
@@ -608,6 +645,7 @@ int build_plan(const pa_system *sys, const int32_t *exposed, int32_t n_exposed, 
         return g_err.empty() ? fail(PA_EINVAL, "internal: root not written to output") : PA_EINVAL;
     for (auto &op : P->ops)
         if (op.kind == OP_CONTRACT) finish_contract(op, op.b >= 0 || op.b == kBufOutput);
+    split_gemms(P);
     P->total_macs = 0.0;
     for (const auto &op : P->ops)
         if (op.kind != OP_FILL) P->total_macs += op.macs;
@@ -1444,6 +1482,8 @@ extern "C" int pa_contract(const pa_bitarray *A, const int32_t *a_vars, const pa
             tmp.si.n_vars = PA_MAX_VARS;
             Builder Bd{&tmp, nullptr};
             Bd.emit_gemm(0, la, 1, lb, kBufOutput, lc, nb, nm, -1);
+            tmp.gemm_split = opts && opts->gemm_split > 0 ? opts->gemm_split : 512;
+            split_gemms(&tmp);
             for (auto &op : tmp.ops) {
                 if (op.kind == OP_FILL) {
                     HIP_TRY(launch_fill(static_cast<uint32_t *>(C->data), op.fill_words, 0u, s));

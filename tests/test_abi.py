@@ -148,15 +148,20 @@ def test_validation_errors():
 
 
 def test_gemm_split_target_sets_the_k_split():
-    """A 1024^3 contraction has 64 output tiles: the default target (512 work
-    items) splits K in 4 (256-bit chunks), a target of 1 never splits."""
+    """The chain's balanced tree runs 4, 2 and 1 contractions of 1024^3 (64
+    output tiles each) per level.  The default target (512 work items per
+    grouped launch) splits K in 2 on the first level (256 tiles), in 4 on
+    the second (128) and in 4 on the third (64 tiles; 4 parts of 256 bits is
+    the most a 1024-bit K allows); a target of 1 never splits; every split
+    contraction gets one fill."""
     s = inputs.config2(res=1024)
-    gemms = lambda d: [o for o in d["ops"] if o["op"] == "gemm_mfma"]
-    assert {o["ksplit"] for o in gemms(pa.describe_plan(s))} == {4}
-    assert {o["ksplit"] for o in gemms(pa.describe_plan(s, gemm_split=1))} == {1}
-    assert {o["ksplit"] for o in gemms(pa.describe_plan(s, gemm_split=128))} == {2}
+    ks = lambda d: [o["ksplit"] for o in d["ops"] if o["op"] == "gemm_mfma"]
+    assert ks(pa.describe_plan(s)) == [2, 2, 4, 2, 2, 4, 4]
+    assert ks(pa.describe_plan(s, gemm_split=1)) == [1] * 7
+    assert ks(pa.describe_plan(s, gemm_split=128)) == [1, 1, 1, 1, 1, 1, 2]
     fills = lambda d: [o for o in d["ops"] if o["op"] == "fill"]
     assert len(fills(pa.describe_plan(s))) == 7
+    assert len(fills(pa.describe_plan(s, gemm_split=128))) == 1
     assert len(fills(pa.describe_plan(s, gemm_split=1))) == 0
 
 
