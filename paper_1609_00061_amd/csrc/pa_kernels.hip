@@ -155,13 +155,19 @@ __device__ __forceinline__ void decl_point(const PlotView &V, double s0, double 
     }
 }
 
-// Stage the dense coefficient table in LDS in storage order,
-// cst[s0 + D1*(s1 + D1*s2)] = coefficient with exponent s_j on storage axis j,
-// and as it is (declared order) in cdl, for the canonical FP64 value.
-__device__ __forceinline__ void stage_coefs(const PlotView &V, double *cst, double *cdl) {
+// The dense coefficient table for LDS: thread tid < D1^n reads entry tid in
+// storage order, cst[s0 + D1*(s1 + D1*s2)] = coefficient with exponent s_j
+// on storage axis j, and entry tid as it is (declared order), for the
+// canonical FP64 value.  Loaded first, stored after other work.
+struct CoefPair {
+    double st, dl;
+};
+
+__device__ __forceinline__ CoefPair load_coefs(const PlotView &V) {
     const int D1 = V.d + 1;
     const int tid = threadIdx.x;
     const int total = V.n == 1 ? D1 : (V.n == 2 ? D1 * D1 : D1 * D1 * D1);
+    CoefPair c{0.0, 0.0};
     if (tid < total) {
         const int s0 = tid % D1, s1 = (tid / D1) % D1, s2 = tid / (D1 * D1);
         // declared exponent of variable v = storage exponent of the axis holding v
@@ -169,8 +175,18 @@ __device__ __forceinline__ void stage_coefs(const PlotView &V, double *cst, doub
         const int e0 = (V.perm0 == 0 ? s0 : 0) + (V.n > 1 && V.perm1 == 0 ? t1 : 0) + (V.n > 2 && V.perm2 == 0 ? t2 : 0);
         const int e1 = (V.perm0 == 1 ? s0 : 0) + (V.n > 1 && V.perm1 == 1 ? t1 : 0) + (V.n > 2 && V.perm2 == 1 ? t2 : 0);
         const int e2 = (V.perm0 == 2 ? s0 : 0) + (V.n > 1 && V.perm1 == 2 ? t1 : 0) + (V.n > 2 && V.perm2 == 2 ? t2 : 0);
-        cst[tid] = V.coef[e0 + D1 * (e1 + D1 * e2)];
-        cdl[tid] = V.coef[tid];
+        c.st = V.coef[e0 + D1 * (e1 + D1 * e2)];
+        c.dl = V.coef[tid];
+    }
+    return c;
+}
+
+__device__ __forceinline__ void store_coefs(const PlotView &V, const CoefPair &c, double *cst, double *cdl) {
+    const int D1 = V.d + 1;
+    const int total = V.n == 1 ? D1 : (V.n == 2 ? D1 * D1 : D1 * D1 * D1);
+    if ((int)threadIdx.x < total) {
+        cst[threadIdx.x] = c.st;
+        cdl[threadIdx.x] = c.dl;
     }
 }
 
@@ -356,6 +372,8 @@ __device__ __forceinline__ void eval_line(const PlotView &V, const float *ln, co
 // kDense doubles of LDS.
 __device__ void plot_tile(const PlotRel &R, int64_t tile, float *lines, double *cst, PlotCount &cnt) {
     const PlotView V = plot_view(R);
+    // the only loads of the tile (coefficients), issued first
+    const CoefPair coefs = load_coefs(V);
     const int n = V.n;
     const int tid = threadIdx.x;
     const int tw_n = R.tw, ta = R.ta, tb = R.tb, s = R.s;
@@ -414,7 +432,7 @@ __device__ void plot_tile(const PlotRel &R, int64_t tile, float *lines, double *
             }
         }
     }
-    stage_coefs(V, cst, cdl);
+    store_coefs(V, coefs, cst, cdl);
     if (tid < nlines) {
         ly[2 * tid] = y0;
         ly[2 * tid + 1] = y1;
