@@ -347,8 +347,8 @@ int32_t pa_plan_step_samples(pa_plan *plan, float *features, float *log2_us, int
  * candidates on the device: first the executor (grouped launches, or one
  * persistent launch with 256/512/1024/2048 workgroups), then the plot strip
  * length (1/2/4/8 cells per thread), then the streaming tile (512..32768
- * output bits), then the MFMA K-split target (1, 256, 512, 1024, 2048 work
- * items), each from the best so far.  Every candidate is a batch built
+ * output bits), then the MFMA K-split target (1, 64, 128, 256, 512, 1024,
+ * 2048 work items), each from the best so far.  Every candidate is a batch built
  * with opts (graph capture included if opts->graph), executed once untimed,
  * then reps times between two events on `stream`.  Candidates that exceed
  * the workspace cap are skipped.  best gets the fastest; tried (may be NULL)

@@ -299,11 +299,23 @@ __device__ __forceinline__ void line_fp32(const float *ln, const float *xv, int 
     const float f32 = value(xv[32]);
     const uint32_t sg32 = __float_as_uint(f32) >> 31, ok32 = __float_as_uint(E - fabsf(f32)) >> 31;
     uint32_t sg = 0, ok = 0;
+    // four corners at a time, their Horner steps interleaved: one wave per
+    // SIMD is common here, and a single dependent chain would leave the
+    // VALU waiting on each result
 #pragma unroll
-    for (int kk = 31; kk >= 0; --kk) {
-        const float f = value(xv[kk]);
-        sg = __builtin_amdgcn_alignbit(sg, __float_as_uint(f), 31);
-        ok = __builtin_amdgcn_alignbit(ok, __float_as_uint(E - fabsf(f)), 31);
+    for (int kk = 31; kk >= 0; kk -= 4) {
+        float f[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) f[i] = ca[NF];
+#pragma unroll
+        for (int t = NF - 1; t >= 0; --t)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) f[i] = fmaf(f[i], xv[kk - i], ca[t]);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            sg = __builtin_amdgcn_alignbit(sg, __float_as_uint(f[i]), 31);
+            ok = __builtin_amdgcn_alignbit(ok, __float_as_uint(E - fabsf(f[i])), 31);
+        }
     }
     const uint64_t okm = ((uint64_t)ok | ((uint64_t)ok32 << 32)) & valid;
     const uint64_t sgm = (uint64_t)sg | ((uint64_t)sg32 << 32);

@@ -170,7 +170,7 @@ int autotune(const pa_system *systems, int32_t n_sys, const int32_t *const *expo
         t.contract_units = u;
         rc = trial(t);
     }
-    const int splits[] = {1, 256, 512, 1024, 2048};
+    const int splits[] = {1, 64, 128, 256, 512, 1024, 2048};
     for (int sp : splits) {
         if (rc || best.ms < 0.0 || sp == best.gemm_split) continue;
         pa_tuning t = best;
