@@ -138,6 +138,47 @@ def _kernel_table(plan, stream, system, reps):
     return roof, per_kind, groups
 
 
+def _ternary(stream, steps=10):
+    """The ternary workload (4 trivariate cubics over 6 variables at 256
+    cells/axis, 2 exposed): solves/s, and per kernel kind the grouped
+    launch's rate against its roofline -- the MFMA contractions (two
+    65536 x 65536 x 256-bit Boolean GEMMs, 512 MiB outputs) and the word-
+    streaming contraction that reads both 512 MiB intermediates once."""
+    from paper_1609_00061_amd import inputs, pa
+    s = inputs.config3()
+    tuning, _ = pa.autotune([s], reps=3, stream=stream, order=pa.ORDER_EXHAUSTIVE, graph=True)
+    tuning = {k: int(v) for k, v in tuning.items() if k != "ms"}
+    plan = pa.Plan(s, order=pa.ORDER_EXHAUSTIVE, graph=True, **tuning)
+    out = pa.empty_bits(plan.dims)
+    dt = _time_plan(plan, out, steps, 2, stream)
+    d = pa.describe_plan(s, order=pa.ORDER_EXHAUSTIVE, **tuning)
+    words = [b["words"] for b in d["buffers"]]
+    stream_bytes = sum(4.0 * (words[o["a"]] + (words[o["b"]] if o["b"] >= 0 else 0))
+                       for o in d["ops"] if o["op"] in ("stream_k", "stream_w"))
+    kplan = plan
+    if tuning.get("single_launch"):
+        kplan = pa.Plan(s, order=pa.ORDER_EXHAUSTIVE, graph=True, **dict(tuning, single_launch=0))
+        kplan.execute(pa.empty_bits(kplan.dims), stream=stream)
+    groups = kplan.time_groups(reps=3, stream=stream)
+    res = {"workload": "4 random trivariate cubics over 6 variables, N(0,1) coefficients, [-3,3]^6 at 256 "
+                       "cells/axis, 2 exposed", "value": steps / dt, "unit": "solves/s", "ms_per_solve": 1e3 * dt / steps,
+           "tuning": tuning}
+    gm = [(ms, macs) for kind, ms, macs in groups if kind == pa.OPKIND_GEMM]
+    if gm:
+        ops = sum(2.0 * m for _, m in gm) / len(gm)
+        avg = sum(ms for ms, _ in gm) / len(gm)
+        ach = ops / (avg * 1e-3) / 1e12
+        res["contraction_mfma"] = {"bound": "mfma", "achieved": ach, "peak": INT8_DENSE_PEAK_TOPS, "unit": "TOP/s",
+                                   "frac": ach / INT8_DENSE_PEAK_TOPS, "avg_launch_ms": avg, "launches": len(gm),
+                                   "ops_per_launch": ops}
+    st = [ms for kind, ms, _ in groups if kind in (pa.OPKIND_STREAM_K, pa.OPKIND_STREAM_W)]
+    if st and stream_bytes:
+        gbs = stream_bytes / (sum(st) * 1e-3) / 1e9
+        res["contraction_stream"] = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                     "frac": gbs / HBM_PEAK_GBS, "ms": sum(st), "operand_bytes": stream_bytes}
+    return res
+
+
 def _batched(stream, K, W):
     """512 chains of uneven resolution: one graph replay of the batch (level-
     grouped launches, autotuned tiles) vs the plain path solving each system."""
@@ -288,6 +329,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-ternary", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--tuning", type=str, default="",
                     help="JSON executor settings to use instead of autotuning (e.g. for counter runs, whose "
@@ -391,6 +433,10 @@ def main():
     torch.cuda.synchronize()
     result["single_launch"] = {"value": K / sdt, "unit": "solves/s", "ms_per_step": 1e3 * sdt / K,
                                "same_bits": bool(torch.equal(sout, out))}
+
+    if not args.no_ternary:
+        _progress("ternary workload")
+        result["ternary"] = _ternary(stream)
 
     if not args.no_batched:
         _progress("batched workload")
