@@ -241,16 +241,18 @@ def _learned(stream, n_train=32, n_eval=48, res=128):
     r2 = float(1.0 - np.mean((pred - T) ** 2) / np.var(T))
     evals = inputs.config5(n_graphs=n_eval, index=0, res=res)
     _progress(f"trained in {train_s:.1f} s on {len(T)} samples; timing policies")
-    pol = learn.time_policies(evals, model, steps=3, stream=stream, log=_progress)
+    pol = learn.time_policies(evals, model, policies=("greedy", "exhaustive", "learned", "learned_verified"),
+                              steps=3, stream=stream, log=_progress)
     out = {"workload": f"{n_eval} random relation hypergraphs (8-14 variables, arity 2-3, 2-4 exposed, "
                        f"{res} cells/axis, [-3,3]); model trained on {n_train} disjoint graphs",
            "train_s": train_s, "train_samples": int(len(T)), "fit_r2": r2,
            "same_bits_all_policies": pol["same_bits"], "systems": pol["systems"],
            "skipped_enomem": pol["skipped_enomem"]}
-    for p in ("greedy", "exhaustive", "learned"):
+    for p in ("greedy", "exhaustive", "learned", "learned_verified"):
         out[p] = {"total_ms": pol[p]["total_ms"], "plan_ms_mean": pol[p]["plan_ms_mean"]}
     out["learned_vs_exhaustive"] = pol["exhaustive"]["total_ms"] / pol["learned"]["total_ms"]
     out["learned_vs_greedy"] = pol["greedy"]["total_ms"] / pol["learned"]["total_ms"]
+    out["learned_verified_vs_exhaustive"] = pol["exhaustive"]["total_ms"] / pol["learned_verified"]["total_ms"]
     # learned order + batched graph replay vs the plain path, on the systems
     # every policy could plan
     # (systems whose greedy plan exceeds the workspace, or whose naive cost

@@ -156,6 +156,14 @@ typedef struct {
                                  tiles x parts); partial products are OR-ed into a
                                  zeroed output (exact); 1: never split; 0: default
                                  (512)                                            */
+    int32_t gemm_path;        /* MFMA contractions: 1 = K chunks staged in LDS by the
+                                 workgroup; 2 = each wave loads its own rows straight
+                                 into registers (no LDS, no barriers); 0: default */
+    int32_t verify_order;     /* PA_ORDER_LEARNED, pa_plan_create: 1 = when the model's
+                                 tree differs from the exhaustive one, build both,
+                                 time each on the device (one untimed and two timed
+                                 executions on stream 0, temporary outputs) and keep
+                                 the faster; the exhaustive search stays the judge */
 } pa_opts;
 
 typedef struct {
@@ -348,7 +356,8 @@ int32_t pa_plan_step_samples(pa_plan *plan, float *features, float *log2_us, int
  * persistent launch with 256/512/1024/2048 workgroups), then the plot strip
  * length (1/2/4/8 cells per thread), then the streaming tile (512..32768
  * output bits), then the MFMA K-split target (1, 64, 128, 256, 512, 1024,
- * 2048 work items), each from the best so far.  Every candidate is a batch built
+ * 2048 work items), then the MFMA operand path (LDS-staged or direct), each
+ * from the best so far.  Every candidate is a batch built
  * with opts (graph capture included if opts->graph), executed once untimed,
  * then reps times between two events on `stream`.  Candidates that exceed
  * the workspace cap are skipped.  best gets the fastest; tried (may be NULL)
@@ -356,7 +365,7 @@ int32_t pa_plan_step_samples(pa_plan *plan, float *features, float *log2_us, int
  * also cached for opts->autotune.  Allocates outputs and workspaces while
  * tuning; synchronizes the stream. */
 typedef struct {
-    int32_t single_launch, persist_wg, plot_strip, contract_units, gemm_split;
+    int32_t single_launch, persist_wg, plot_strip, contract_units, gemm_split, gemm_path;
     double ms;                /* milliseconds per execution of the whole workload */
 } pa_tuning;
 int pa_autotune(const pa_system *systems, int32_t n_sys, const int32_t *const *exposed, const int32_t *n_exposed,

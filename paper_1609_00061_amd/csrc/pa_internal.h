@@ -122,6 +122,7 @@ struct GemmArgs {
     int64_t tiles_m, tiles_n; // 128-row and 128-column tiles (N in padded coordinates)
     int64_t kchunk;           // words per K split (multiple of 8)
     int ksplit;               // >1: partial results OR-ed with atomics into zeroed C
+    int direct;               // 1: waves load K chunks straight into registers (no LDS)
     // divisions of the tile index (below 2^31) and of N coordinates by the
     // padded C row length in bits (below 2^31), checked on the host
     FastDiv fd_ksplit, fd_tiles_n, fd_tiles_m, fd_wc;

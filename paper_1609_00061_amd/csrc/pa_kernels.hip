@@ -799,6 +799,8 @@ struct GemmTileRef {
     int64_t m0, n0, M, No, rwc;
     FastDiv fd_wc;                // division by the padded C row length in bits
     bool a_ok, b_ok, vec4, atomic;
+    const PA_G uint32_t *abase, *bbase;   // A and B of the tile's batch
+    int64_t Kw, rn;
 };
 
 __device__ __forceinline__ GemmTileRef gemm_locate(const GemmArgs &g, int64_t t64) {
@@ -827,6 +829,10 @@ __device__ __forceinline__ GemmTileRef gemm_locate(const GemmArgs &g, int64_t t6
     r.b_ok = (bno < g.No) && (bj < g.rn);
     r.b = gp(g.B) + b * g.sB_b + (r.b_ok ? (bno * g.rn + bj) : 0) * g.Kw;
     r.c = gp(g.C) + b * g.sC_b;
+    r.abase = gp(g.A) + b * g.sA_b;
+    r.bbase = gp(g.B) + b * g.sB_b;
+    r.Kw = g.Kw;
+    r.rn = g.rn;
     r.M = g.M;
     r.No = g.No;
     r.rwc = g.rwc;
@@ -984,8 +990,127 @@ __device__ void gemm_tiles(Next next, uint32_t *lds) {
     }
 }
 
-__global__ __launch_bounds__(256, 3) void k_gemm_mfma(GemmArgs g) {
-    __shared__ __attribute__((aligned(16))) uint32_t lds[kGemmLdsWords];
+// ---- direct path: no LDS, no barriers.  Each wave loads the two A rows
+// and two B rows its lanes multiply (lanes l and l + 32 read the same
+// words) straight into registers, one K chunk ahead, and runs its 64 x 64
+// quadrant of the tile on its own.
+struct GemmRows {
+    const PA_G uint32_t *a[2], *b[2];
+    bool a_ok[2], b_ok[2];
+};
+
+__device__ __forceinline__ GemmRows gemm_rows(const GemmTileRef &T) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wm = wave >> 1, wn = wave & 1, l32 = lane & 31;
+    const uint32_t Wc = (uint32_t)(T.rwc * 32);
+    GemmRows R;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const int64_t am = T.m0 + wm * 64 + i * 32 + l32;
+        R.a_ok[i] = am < T.M;
+        R.a[i] = T.abase + (R.a_ok[i] ? am : 0) * T.Kw;
+        const uint32_t bn = (uint32_t)(T.n0 + wn * 64 + i * 32 + l32);
+        const uint32_t bno = fdiv(bn, T.fd_wc), bj = bn - bno * Wc;
+        R.b_ok[i] = (bno < T.No) && (bj < T.rn);
+        R.b[i] = T.bbase + (R.b_ok[i] ? (bno * T.rn + bj) : 0) * T.Kw;
+    }
+    return R;
+}
+
+struct GemmChunkD {
+    GemmTileRef T;
+    GemmRows R;
+    int64_t kc;
+    bool valid;
+};
+
+// MFMAs of one K chunk held in registers: a4[i][h4] = words 4*h4 .. 4*h4+3
+// of this lane's A row i (b4 likewise for B).
+__device__ __forceinline__ void gemm_chunk_regs(const uint4 (&a4)[2][2], const uint4 (&b4)[2][2],
+                                                const uint32_t *msk, v16i (&acc)[2][2], bool fresh) {
+    const v16i zero = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int q = 0; q < kChunk; ++q) {
+        v4i opa[2], opb[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const uint4 &w = a4[i][q >> 2];
+            const uint32_t x = (q & 3) == 0 ? w.x : (q & 3) == 1 ? w.y : (q & 3) == 2 ? w.z : w.w;
+            opa[i] = spread(x, msk);
+            const uint4 &v = b4[i][q >> 2];
+            const uint32_t y = (q & 3) == 0 ? v.x : (q & 3) == 1 ? v.y : (q & 3) == 2 ? v.z : v.w;
+            opb[i] = spread(y, msk);
+        }
+        if (q == 0 && fresh) {
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(opb[j], opa[i], zero, 0, 0, 0);
+        } else {
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(opb[j], opa[i], acc[i][j], 0, 0, 0);
+        }
+    }
+}
+
+template <class Next>
+__device__ void gemm_tiles_direct(Next next) {
+    const int h = (threadIdx.x & 63) >> 5;
+    uint32_t msk[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) msk[j] = 0x01010101u << (4 * h + j);
+    auto advance = [&](const GemmChunkD &c) {
+        GemmChunkD n = c;
+        if (!c.valid) return n;
+        n.kc = c.kc + kChunk;
+        if (n.kc >= c.T.kw1) {
+            n.valid = next(n.T);
+            if (n.valid) {
+                n.R = gemm_rows(n.T);
+                n.kc = n.T.kw0;
+            }
+        }
+        return n;
+    };
+    auto load = [&](const GemmChunkD &c, uint4 (&a4)[2][2], uint4 (&b4)[2][2]) {
+        if (!c.valid) return;
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int h4 = 0; h4 < 2; ++h4) {
+                a4[i][h4] = load_row4(c.R.a[i], c.kc + 4 * h4, c.T.kw1, c.R.a_ok[i], c.T.vec4);
+                b4[i][h4] = load_row4(c.R.b[i], c.kc + 4 * h4, c.T.kw1, c.R.b_ok[i], c.T.vec4);
+            }
+    };
+    GemmChunkD c0;
+    c0.valid = next(c0.T);
+    if (!c0.valid) return;
+    c0.R = gemm_rows(c0.T);
+    c0.kc = c0.T.kw0;
+    uint4 A0[2][2], B0[2][2], A1[2][2], B1[2][2];
+    load(c0, A0, B0);
+    v16i acc[2][2];
+    // chunk c0 is in (Ac, Bc); load the next chunk into (An, Bn), multiply
+    auto step = [&](uint4 (&Ac)[2][2], uint4 (&Bc)[2][2], uint4 (&An)[2][2], uint4 (&Bn)[2][2]) {
+        const GemmChunkD c1 = advance(c0);
+        load(c1, An, Bn);
+        gemm_chunk_regs(Ac, Bc, msk, acc, c0.kc == c0.T.kw0);
+        if (c0.kc + kChunk >= c0.T.kw1) gemm_epilogue(c0.T, acc);
+        c0 = c1;
+        return c0.valid;
+    };
+    for (;;) {
+        if (!step(A0, B0, A1, B1)) break;
+        if (!step(A1, B1, A0, B0)) break;
+    }
+}
+
+template <bool DIRECT>
+__global__ __launch_bounds__(256, DIRECT ? 2 : 3) void k_gemm_mfma(GemmArgs g) {
+    __shared__ __attribute__((aligned(16))) uint32_t lds[DIRECT ? 1 : kGemmLdsWords];
     const int64_t ntiles = g.nbatch * g.tiles_m * g.tiles_n * g.ksplit;
     int64_t t = blockIdx.x;
     auto next = [&](GemmTileRef &T) {
@@ -994,26 +1119,29 @@ __global__ __launch_bounds__(256, 3) void k_gemm_mfma(GemmArgs g) {
         t += gridDim.x;
         return true;
     };
-    gemm_tiles(next, lds);
+    if (DIRECT) gemm_tiles_direct(next);
+    else gemm_tiles(next, lds);
 }
 
 // Workgroups of a persistent tile loop: every CU's worth, capped by the tiles.
-static int64_t gemm_grid(int64_t ntiles) {
-    static int cached = 0;
-    if (!cached) {
+static int64_t gemm_grid(int64_t ntiles, bool direct) {
+    static int cached[2] = {0, 0};
+    if (!cached[direct]) {
         int dev = 0, cus = 256, per_cu = 1;
         if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_gemm_mfma, 256, 0) != hipSuccess || per_cu < 1)
-            per_cu = 1;
-        cached = cus * per_cu;
+        const hipError_t e = direct ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_gemm_mfma<true>, 256, 0)
+                                    : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_gemm_mfma<false>, 256, 0);
+        if (e != hipSuccess || per_cu < 1) per_cu = 1;
+        cached[direct] = cus * per_cu;
     }
-    return ntiles < cached ? ntiles : cached;
+    return ntiles < cached[direct] ? ntiles : cached[direct];
 }
 
 hipError_t launch_gemm(const GemmArgs &g, hipStream_t s) {
     if (g.nbatch == 0 || g.M == 0 || g.No == 0) return hipSuccess;
     const int64_t nt = g.nbatch * g.tiles_m * g.tiles_n * g.ksplit;
-    hipLaunchKernelGGL(k_gemm_mfma, dim3((unsigned)gemm_grid(nt)), dim3(256), 0, s, g);
+    if (g.direct) hipLaunchKernelGGL(k_gemm_mfma<true>, dim3((unsigned)gemm_grid(nt, true)), dim3(256), 0, s, g);
+    else hipLaunchKernelGGL(k_gemm_mfma<false>, dim3((unsigned)gemm_grid(nt, false)), dim3(256), 0, s, g);
     return hipGetLastError();
 }
 
@@ -1085,7 +1213,8 @@ __device__ __forceinline__ void run_tile(const PStep &st, int64_t tile, uint32_t
                 once = false;
                 return true;
             };
-            gemm_tiles(next, lds);
+            if (st.gemm.direct) gemm_tiles_direct(next);
+            else gemm_tiles(next, lds);
             break;
         }
         case kStepContract: {
@@ -1103,10 +1232,12 @@ __device__ __forceinline__ void run_tile(const PStep &st, int64_t tile, uint32_t
 
 // KIND: a StepKind; for contractions the mode is fixed too (kind 2 + 10 * mode).
 template <int KIND>
-__global__ __launch_bounds__(256, KIND == kStepGemm ? 3 : 1) void k_group(const PStep *__restrict__ steps, int first, int count, int64_t t0,
+__global__ __launch_bounds__(256, KIND == kStepGemm ? 3 : (KIND == kStepGemm + 10 ? 2 : 1)) void k_group(const PStep *__restrict__ steps, int first, int count, int64_t t0,
                                                int64_t t1, PlotCounters *counters) {
     constexpr int kind = KIND % 10, mode = KIND / 10;
-    constexpr int kWords = kind == kStepGemm ? kGemmLdsWords : (kind == kStepPlot ? kPlotLdsWords : 1);
+    // MFMA contractions: mode 0 stages K chunks in LDS, mode 1 loads them
+    // straight into each wave's registers
+    constexpr int kWords = kind == kStepGemm ? (mode == 0 ? kGemmLdsWords : 1) : (kind == kStepPlot ? kPlotLdsWords : 1);
     __shared__ __attribute__((aligned(16))) uint32_t lds[kWords];
     if (kind == kStepGemm) {
         // persistent tile loop with cross-tile prefetch
@@ -1118,7 +1249,8 @@ __global__ __launch_bounds__(256, KIND == kStepGemm ? 3 : 1) void k_group(const 
             item += gridDim.x;
             return true;
         };
-        gemm_tiles(next, lds);
+        if (mode == 1) gemm_tiles_direct(next);
+        else gemm_tiles(next, lds);
         return;
     }
     PlotCount cnt;
@@ -1143,11 +1275,14 @@ hipError_t launch_group(int kind, int mode, const PStep *d_steps, int first, int
                         PlotCounters *counters, hipStream_t s) {
     if (t1 <= t0) return hipSuccess;
     const int64_t nt = t1 - t0;
-    const dim3 grid((unsigned)(kind == kStepGemm ? gemm_grid(nt) : (nt < (1 << 20) ? nt : (1 << 20))));
+    const dim3 grid((unsigned)(kind == kStepGemm ? gemm_grid(nt, mode == 1) : (nt < (1 << 20) ? nt : (1 << 20))));
 #define PA_GROUP(K) hipLaunchKernelGGL(k_group<K>, grid, dim3(256), 0, s, d_steps, first, count, t0, t1, counters)
     switch (kind) {
         case kStepPlot: PA_GROUP(kStepPlot); break;
-        case kStepGemm: PA_GROUP(kStepGemm); break;
+        case kStepGemm:
+            if (mode == 1) PA_GROUP(kStepGemm + 10);
+            else PA_GROUP(kStepGemm);
+            break;
         case kStepContract:
             if (mode == kModeStreamK) PA_GROUP(kStepContract + 10 * kModeStreamK);
             else if (mode == kModeStreamW) PA_GROUP(kStepContract + 10 * kModeStreamW);

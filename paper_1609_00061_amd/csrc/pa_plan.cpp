@@ -324,6 +324,7 @@ struct Builder {
         // the K split (and the fill it needs) is set by split_gemms once
         // every step of the tree is known
         set_ksplit(g, 1);
+        g.direct = P->gemm_direct;
         g.fd_tiles_n = make_fastdiv((uint64_t)std::max<int64_t>(1, g.tiles_n));
         g.fd_tiles_m = make_fastdiv((uint64_t)std::max<int64_t>(1, g.tiles_m));
         g.fd_wc = make_fastdiv((uint64_t)(g.rwc * 32));
@@ -502,7 +503,7 @@ std::string Op::describe() const {
       << ",\"c_vars\":" << join(lc.vars) << ",\"macs\":" << macs;
     if (kind == OP_GEMM)
         s << ",\"batch\":" << ga.nbatch << ",\"M\":" << ga.M << ",\"No\":" << ga.No << ",\"rn\":" << ga.rn
-          << ",\"Kw\":" << ga.Kw << ",\"ksplit\":" << ga.ksplit;
+          << ",\"Kw\":" << ga.Kw << ",\"ksplit\":" << ga.ksplit << ",\"direct\":" << ga.direct;
     s << "}";
     return s.str();
 }
@@ -621,9 +622,11 @@ int build_plan(const pa_system *sys, const int32_t *exposed, int32_t n_exposed, 
     P->plot_strip = o.plot_strip > 0 ? o.plot_strip : 4;
     P->contract_units = o.contract_units > 0 ? o.contract_units : 2048;
     P->gemm_split = o.gemm_split > 0 ? o.gemm_split : 512;
+    P->gemm_direct = o.gemm_path == 2 ? 1 : 0;
     if (o.precision != PA_PLOT_FP32_ESCALATE && o.precision != PA_PLOT_FP64)
         return fail(PA_EINVAL, "opts: unknown precision");
-    if (o.persist_wg < 0 || o.plot_strip < 0 || o.contract_units < 0 || o.gemm_split < 0)
+    if (o.persist_wg < 0 || o.plot_strip < 0 || o.contract_units < 0 || o.gemm_split < 0 || o.gemm_path < 0 ||
+        o.gemm_path > 2)
         return fail(PA_EINVAL, "opts: negative tuning parameter");
     switch (o.order_policy) {
         case PA_ORDER_GREEDY: rc = plan_greedy(P->si, P->tree); break;
@@ -827,6 +830,7 @@ static int build_steps(pa_plan *P) {
             int rc = check_gemm_bounds(op.ga, op.la.words, op.lb.words, op.lc.words);
             if (rc) return rc;
             s.kind = kStepGemm;
+            s.mode = op.ga.direct;      // grouped launches: one instantiation per operand path
             s.gemm = op.ga;
             s.gemm.A = buf_ptr(P, op.a, nullptr);
             s.gemm.B = buf_ptr(P, op.b, nullptr);
@@ -1109,6 +1113,67 @@ int plan_workspace_cap(size_t *cap) {
 // ====================================================================== ABI
 using namespace pa;
 
+// Milliseconds per execution of a plan built with `o` (one untimed and
+// `reps` timed executions on stream 0 into a temporary output).
+static int time_plan_once(const pa_system *sys, const int32_t *exposed, int32_t n_exposed, const pa_opts &o,
+                          int reps, double *ms, std::vector<int> *merges) {
+    pa_plan *p = nullptr;
+    int rc = pa_plan_create(sys, exposed, n_exposed, &o, &p);
+    if (rc) return rc;
+    std::unique_ptr<pa_plan> hold(p);
+    if (merges) *merges = p->tree.merges;
+    pa_bitarray out;
+    std::memset(&out, 0, sizeof(out));
+    out.ndim = (int32_t)p->out_layout.dims.size();
+    for (int i = 0; i < out.ndim; ++i) out.dims[i] = (int32_t)p->out_layout.dims[i];
+    out.row_words = p->out_layout.rw;
+    void *buf = nullptr;
+    if (hipMalloc(&buf, sizeof(uint32_t) * (size_t)std::max<int64_t>(1, p->out_layout.words)) != hipSuccess)
+        return fail(PA_ENOMEM, "verify_order: output allocation failed");
+    out.data = buf;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    rc = pa_plan_execute(p, &out, nullptr, nullptr);
+    if (!rc && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+        rc = fail(PA_EHIP, "verify_order: event creation failed");
+    if (!rc && hipEventRecord(e0, nullptr) != hipSuccess) rc = fail(PA_EHIP, "verify_order: event record failed");
+    for (int i = 0; i < reps && !rc; ++i) rc = pa_plan_execute(p, &out, nullptr, nullptr);
+    float t = 0.f;
+    if (!rc && (hipEventRecord(e1, nullptr) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&t, e0, e1) != hipSuccess))
+        rc = fail(PA_EHIP, "verify_order: event timing failed");
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(buf);
+    if (!rc) *ms = (double)t / reps;
+    return rc;
+}
+
+// The exhaustive search judges a learned tree by measurement: both trees are
+// planned and timed, the faster order is returned in *choice.
+static int verify_learned_order(const pa_system *sys, const int32_t *exposed, int32_t n_exposed, const pa_opts &o,
+                                int *choice) {
+    pa_opts lo = o, eo = o;
+    lo.verify_order = 0;
+    lo.timing = 0;
+    lo.autotune = 0;
+    lo.workspace = nullptr;
+    lo.workspace_bytes = 0;
+    eo = lo;
+    eo.order_policy = PA_ORDER_EXHAUSTIVE;
+    double tl = 0.0, te = 0.0;
+    std::vector<int> ml, me;
+    int rc = time_plan_once(sys, exposed, n_exposed, eo, 2, &te, &me);
+    if (rc) return rc;
+    rc = time_plan_once(sys, exposed, n_exposed, lo, 2, &tl, &ml);
+    if (rc == PA_ENOMEM) {               // the learned tree does not fit: the exhaustive one does
+        *choice = PA_ORDER_EXHAUSTIVE;
+        return PA_OK;
+    }
+    if (rc) return rc;
+    *choice = (ml == me || tl <= te) ? PA_ORDER_LEARNED : PA_ORDER_EXHAUSTIVE;
+    return PA_OK;
+}
+
 extern "C" int pa_plan_create(const pa_system *sys, const int32_t *exposed, int32_t n_exposed, const pa_opts *opts,
                               pa_plan **plan) {
     if (!plan) return fail(PA_EINVAL, "plan_create: null plan pointer");
@@ -1121,8 +1186,21 @@ extern "C" int pa_plan_create(const pa_system *sys, const int32_t *exposed, int3
         if (rc) return rc;
         opts = &tuned;
     }
+    bool verified_fallback = false;
+    if (opts && opts->order_policy == PA_ORDER_LEARNED && opts->verify_order && !opts->plain && !opts->per_op && sys) {
+        int choice = PA_ORDER_LEARNED;
+        int rc = verify_learned_order(sys, exposed, n_exposed, *opts, &choice);
+        if (rc) return rc;
+        if (choice != PA_ORDER_LEARNED) {
+            if (opts != &tuned) tuned = *opts;
+            tuned.order_policy = choice;
+            opts = &tuned;
+            verified_fallback = true;
+        }
+    }
     int rc = build_plan(sys, exposed, n_exposed, opts, P.get());
     if (rc) return rc;
+    if (verified_fallback) P->tree.learned_fallback = true;
     if (opts && opts->workspace) {
         if (opts->workspace_bytes < P->ws_bytes)
             return fail(PA_ENOMEM, "workspace too small: need " + std::to_string(P->ws_bytes) + " bytes");
@@ -1483,6 +1561,7 @@ extern "C" int pa_contract(const pa_bitarray *A, const int32_t *a_vars, const pa
             Builder Bd{&tmp, nullptr};
             Bd.emit_gemm(0, la, 1, lb, kBufOutput, lc, nb, nm, -1);
             tmp.gemm_split = opts && opts->gemm_split > 0 ? opts->gemm_split : 512;
+            tmp.gemm_direct = opts && opts->gemm_path == 2 ? 1 : 0;
             split_gemms(&tmp);
             for (auto &op : tmp.ops) {
                 if (op.kind == OP_FILL) {

@@ -1,7 +1,7 @@
 // Autotuner for the step executors: picks the executor (level-grouped
 // launches or one persistent launch, and its workgroup count), the plot
-// strip length, the streaming-contraction tile size and the MFMA K-split
-// target for a workload by
+// strip length, the streaming-contraction tile size, the MFMA K-split
+// target and the MFMA operand path for a workload by
 // timing candidates on the device.  Coordinate descent from the defaults;
 // results are cached per structural signature of the workload and GPU
 // architecture for the life of the process.
@@ -65,6 +65,7 @@ static void apply(pa_opts &o, const pa_tuning &t) {
     o.plot_strip = t.plot_strip;
     o.contract_units = t.contract_units;
     o.gemm_split = t.gemm_split;
+    o.gemm_path = t.gemm_path;
 }
 
 // Milliseconds per execution of a batch built with `o`, after one untimed
@@ -147,6 +148,7 @@ int autotune(const pa_system *systems, int32_t n_sys, const int32_t *const *expo
     cur.plot_strip = base.plot_strip > 0 ? base.plot_strip : 4;
     cur.contract_units = base.contract_units > 0 ? base.contract_units : 2048;
     cur.gemm_split = base.gemm_split > 0 ? base.gemm_split : 512;
+    cur.gemm_path = base.gemm_path > 0 ? base.gemm_path : 1;
     if (!rc) rc = trial(cur);
     for (int wg : cus_wg) {
         if (rc) break;
@@ -175,6 +177,12 @@ int autotune(const pa_system *systems, int32_t n_sys, const int32_t *const *expo
         if (rc || best.ms < 0.0 || sp == best.gemm_split) continue;
         pa_tuning t = best;
         t.gemm_split = sp;
+        rc = trial(t);
+    }
+    for (int path : {1, 2}) {
+        if (rc || best.ms < 0.0 || path == best.gemm_path) continue;
+        pa_tuning t = best;
+        t.gemm_path = path;
         rc = trial(t);
     }
     for (void *p : bufs) (void)hipFree(p);

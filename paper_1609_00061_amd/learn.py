@@ -152,9 +152,11 @@ def time_policies(systems: Sequence, model, policies=("greedy", "exhaustive", "l
                   warmup: int = 2, stream=None, check_bits: bool = True, log=None) -> Dict[str, dict]:
     """Measured solve time of every system under each ordering policy (the
     default grouped executor replayed as a hipGraph), plan times, and whether
-    all policies produced identical bits."""
+    all policies produced identical bits.  "learned_verified" is the learned
+    order with the exhaustive tree as a measured judge (verify_order)."""
     import torch
-    order = {"greedy": pa.ORDER_GREEDY, "exhaustive": pa.ORDER_EXHAUSTIVE, "learned": pa.ORDER_LEARNED}
+    order = {"greedy": pa.ORDER_GREEDY, "exhaustive": pa.ORDER_EXHAUSTIVE, "learned": pa.ORDER_LEARNED,
+             "learned_verified": pa.ORDER_LEARNED}
     stream = stream or torch.cuda.Stream()
     res = {p: {"ms": [], "plan_ms": []} for p in policies}
     same = True
@@ -165,7 +167,8 @@ def time_policies(systems: Sequence, model, policies=("greedy", "exhaustive", "l
         try:
             for p in policies:
                 t0 = time.perf_counter()
-                plans[p] = pa.Plan(s, order=order[p], model=model if p == "learned" else None, graph=True)
+                plans[p] = pa.Plan(s, order=order[p], model=model if p.startswith("learned") else None, graph=True,
+                                   verify_order=(p == "learned_verified"))
                 res[p]["plan_ms"].append(1e3 * (time.perf_counter() - t0))
         except pa.PaError as e:              # some policy's tree does not fit the workspace cap
             if e.code != pa.PA_ENOMEM:

@@ -60,12 +60,14 @@ class Opts(ctypes.Structure):
                 ("persist_wg", ctypes.c_int32),
                 ("plot_strip", ctypes.c_int32), ("contract_units", ctypes.c_int32),
                 ("model", ctypes.c_void_p), ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
-                ("autotune", ctypes.c_int32), ("gemm_split", ctypes.c_int32)]
+                ("autotune", ctypes.c_int32), ("gemm_split", ctypes.c_int32), ("gemm_path", ctypes.c_int32),
+                ("verify_order", ctypes.c_int32)]
 
 
 class Tuning(ctypes.Structure):
     _fields_ = [("single_launch", ctypes.c_int32), ("persist_wg", ctypes.c_int32), ("plot_strip", ctypes.c_int32),
-                ("contract_units", ctypes.c_int32), ("gemm_split", ctypes.c_int32), ("ms", ctypes.c_double)]
+                ("contract_units", ctypes.c_int32), ("gemm_split", ctypes.c_int32), ("gemm_path", ctypes.c_int32),
+                ("ms", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -208,7 +210,7 @@ def _system(keep, system) -> System:
 def make_opts(order=ORDER_EXHAUSTIVE, precision=PLOT_FP32_ESCALATE, audit=False, timing=False, plain=False,
               given: Optional[Sequence[int]] = None, model=None, keep: Optional[_Keep] = None, per_op=False,
               graph=False, single_launch=False, persist_wg=0, plot_strip=0, contract_units=0,
-              autotune=False, gemm_split=0) -> Opts:
+              autotune=False, gemm_split=0, gemm_path=0, verify_order=False) -> Opts:
     o = Opts()
     o.order_policy = order
     o.precision = precision
@@ -223,6 +225,8 @@ def make_opts(order=ORDER_EXHAUSTIVE, precision=PLOT_FP32_ESCALATE, audit=False,
     o.contract_units = int(contract_units)
     o.autotune = int(autotune)
     o.gemm_split = int(gemm_split)
+    o.gemm_path = int(gemm_path)
+    o.verify_order = int(verify_order)
     if given is not None:
         assert keep is not None
         o.n_given = len(given) // 2
