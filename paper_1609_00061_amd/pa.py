@@ -302,14 +302,14 @@ def plot_relation(rel, axes_of_vars, precision=PLOT_FP32_ESCALATE, audit=False, 
     return out, dims, (rep.as_dict() if report else None)
 
 
-def contract(A, a_dims, a_vars, B, b_dims, b_vars, out_vars, out_dims, stream=None, plain=False):
+def contract(A, a_dims, a_vars, B, b_dims, b_vars, out_vars, out_dims, stream=None, plain=False, **exec_opts):
     """C(out_vars) = OR over the other variables of A AND B (B may be None)."""
     L = load()
     keep = _Keep()
     C = empty_bits(out_dims)
     ba, bc = bitarray(A, a_dims), bitarray(C, out_dims)
     bb = bitarray(B, b_dims) if B is not None else None
-    opts = make_opts(plain=plain)
+    opts = make_opts(plain=plain, **exec_opts)
     _check(L.pa_contract(ctypes.byref(ba), keep.i32(a_vars), ctypes.byref(bb) if bb is not None else None,
                          keep.i32(b_vars if B is not None else []), keep.i32(out_vars), len(out_vars),
                          ctypes.byref(bc), ctypes.byref(opts), _stream_ptr(stream)))

@@ -63,27 +63,31 @@ def test_projection_without_b():
     _run((0, 1, 2), (), (0,), res, 0.02, 56, b_none=True)
 
 
+@pytest.mark.parametrize("path", [1, 2])
 @pytest.mark.parametrize("M,N,K", [(64, 64, 64), (128, 128, 256), (100, 130, 70), (1024, 1024, 1024),
                                    (33, 1000, 5000), (300, 65, 129), (257, 7, 3000)])
-def test_mfma_gemm_sizes(M, N, K):
-    """Dense canonical layout A[m][k], B[n][k] -> C[m][n] on int8 MFMA: all
+def test_mfma_gemm_sizes(M, N, K, path):
+    """Dense canonical layout A[m][k], B[n][k] -> C[m][n] on int8 MFMA, with
+    K chunks staged in LDS (path 1) or loaded by each wave (path 2): all
     tile residues, ragged K tails, split K; against integer matmul > 0."""
     A = inputs.random_bool_array((M, K), 2.0 / K, 91 + M)
     B = inputs.random_bool_array((N, K), 2.0 / K, 92 + N)
-    note("gemm", M, N, K)
-    C = pa.contract(to_device(A), [M, K], (0, 1), to_device(B), [N, K], (2, 1), (0, 2), [M, N])
+    note("gemm", M, N, K, "path", path)
+    C = pa.contract(to_device(A), [M, K], (0, 1), to_device(B), [N, K], (2, 1), (0, 2), [M, N], gemm_path=path)
     got = to_host(C, [M, N])
     ref = (A.astype(np.int64) @ B.astype(np.int64).T) > 0
     assert np.array_equal(got.astype(bool), ref)
 
 
-def test_mfma_gemm_dense_and_batched():
+@pytest.mark.parametrize("path", [1, 2])
+def test_mfma_gemm_dense_and_batched(path):
     """Dense inputs (every count large) and a batch index."""
     nb, M, N, K = 3, 200, 150, 600
     A = inputs.random_bool_array((nb, M, K), 0.5, 5)
     B = inputs.random_bool_array((nb, N, K), 0.01, 6)
-    note("gemm batched", nb, M, N, K)
-    C = pa.contract(to_device(A), [nb, M, K], (0, 1, 2), to_device(B), [nb, N, K], (0, 3, 2), (0, 1, 3), [nb, M, N])
+    note("gemm batched", nb, M, N, K, "path", path)
+    C = pa.contract(to_device(A), [nb, M, K], (0, 1, 2), to_device(B), [nb, N, K], (0, 3, 2), (0, 1, 3), [nb, M, N],
+                    gemm_path=path)
     got = to_host(C, [nb, M, N])
     ref = np.einsum("bmk,bnk->bmn", A.astype(np.int64), B.astype(np.int64)) > 0
     assert np.array_equal(got.astype(bool), ref)

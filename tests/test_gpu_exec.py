@@ -53,7 +53,9 @@ def test_executors_agree(si, mode):
                                     dict(single_launch=True, persist_wg=64, plot_strip=3, contract_units=256),
                                     dict(plot_strip=8, contract_units=8192), dict(plot_strip=1, contract_units=256),
                                     dict(gemm_split=1), dict(gemm_split=2048, plot_strip=2),
-                                    dict(single_launch=True, gemm_split=1024)])
+                                    dict(single_launch=True, gemm_split=1024), dict(gemm_path=2),
+                                    dict(gemm_path=2, gemm_split=1), dict(single_launch=True, gemm_path=2),
+                                    dict(gemm_path=2, graph=True, gemm_split=64)])
 def test_persistent_tuning_parameters(params):
     for s in SYSTEMS[:4]:
         ref = _oracle_solve(s)
