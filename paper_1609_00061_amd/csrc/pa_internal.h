@@ -82,6 +82,8 @@ __host__ __device__ inline uint32_t fdiv(uint32_t n, const FastDiv &f) {
 // the output or of the latent set has, per operand, either a word stride
 // (non-packed axis of that operand, 0 if absent) or is that operand's packed
 // axis (then it indexes bits).  B == nullptr means B is all ones.
+enum ContractMode { kModeBits = 0, kModeStreamK = 1, kModeStreamW = 2 };
+
 struct ContractArgs {
     const uint32_t *A, *B;
     uint32_t *C;
@@ -108,7 +110,23 @@ struct ContractArgs {
     // words (output rows and row offsets are below 2^31, checked on the host)
     FastDiv fd_dim[kMaxDim];
     FastDiv fd_rowbits, fd_rowwords;
+    // stream mode K: a wave's 64 output bits are tq consecutive output rows
+    // x 64/tq consecutive bits (tq = 1, 2, 4, 8), so that both operands are
+    // read in long runs when one is contiguous along the packed output
+    // variable and the other along the last row variable; fd_segs divides a
+    // block index by the row's 64/tq-bit segments
+    int tq;
+    FastDiv fd_segs;
 };
+
+// Work units of a contraction: output bits (rows padded to whole groups of
+// tq in stream mode K), or output words in stream mode W.
+inline int64_t contract_units(const ContractArgs &a, int mode) {
+    if (mode == kModeStreamW) return a.n_out_rows * a.c_row_words;
+    if (a.nout == 0) return 64;
+    const int64_t tq = a.tq > 1 ? a.tq : 1;
+    return (a.n_out_rows + tq - 1) / tq * tq * a.c_row_words * 32;
+}
 
 // Dense Boolean GEMM in canonical layout:
 //   A[b][m][k], B[b][n][k] with the k vector contiguous (Kw words, bits),
@@ -128,7 +146,6 @@ struct GemmArgs {
     FastDiv fd_ksplit, fd_tiles_n, fd_tiles_m, fd_wc;
 };
 
-enum ContractMode { kModeBits = 0, kModeStreamK = 1, kModeStreamW = 2 };
 
 // One step of the persistent executor: a plot, a GEMM, a contraction or a
 // fill, cut into tiles.  Steps are listed so that every step's producers come

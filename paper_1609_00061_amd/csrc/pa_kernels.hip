@@ -655,6 +655,33 @@ __device__ void contract_range(const ContractArgs &a, int64_t u0, int64_t u1) {
     const int64_t rowbits = a.c_row_words * 32;
     const int64_t total = (a.nout == 0) ? 64 : a.n_out_rows * rowbits;
     const bool vec4 = (a.a_row_words % 4) == 0;
+    if (MODE == kModeStreamK && a.tq > 1) {
+        // a wave's 64 units are tq rows x tp bits (blocks of 64 units; u0 is
+        // a multiple of 64, block indices are below 2^31: host checks); the
+        // first lane of each row stores its tp bits (tp >= 8: whole bytes,
+        // disjoint from every other wave's)
+        const int tq = a.tq, tp = 64 / tq;
+        const int lane = threadIdx.x & 63;
+        const int i = lane / tp, j = lane - i * tp;
+        for (int64_t g0 = u0; g0 < u1; g0 += blockDim.x) {
+            const int64_t gid = g0 + threadIdx.x;
+            const uint32_t blk = (uint32_t)(gid >> 6);
+            const uint32_t grp = fdiv(blk, a.fd_segs), seg = blk - grp * a.fd_segs.d;
+            const int64_t row = (int64_t)grp * tq + i, bit = (int64_t)seg * tp + j;
+            const bool in_row = gid < u1 && row < a.n_out_rows;
+            uint32_t acc = 0;
+            if (in_row && bit < a.out_dim[a.nout - 1])
+                acc = vec4 ? streamk_unit<true>(a, row, bit) : streamk_unit<false>(a, row, bit);
+            const unsigned long long bits = __ballot(acc != 0) >> (i * tp);
+            if (j == 0 && in_row) {
+                PA_G uint8_t *dst = reinterpret_cast<PA_G uint8_t *>(gp(a.C) + row * a.c_row_words) + bit / 8;
+                if (tp == 32) *reinterpret_cast<PA_G uint32_t *>(dst) = (uint32_t)bits;
+                else if (tp == 16) *reinterpret_cast<PA_G uint16_t *>(dst) = (uint16_t)bits;
+                else *dst = (uint8_t)bits;
+            }
+        }
+        return;
+    }
     for (int64_t g0 = u0; g0 < u1; g0 += blockDim.x) {
         const int64_t gid = g0 + threadIdx.x;
         const int64_t row0 = g0 / rowbits;
@@ -694,10 +721,7 @@ __global__ __launch_bounds__(256) void k_contract(ContractArgs a, int64_t total)
         contract_range<MODE>(a, g0, min(total, g0 + (int64_t)blockDim.x));
 }
 
-static int64_t contract_units(const ContractArgs &a, int mode) {
-    if (mode == kModeStreamW) return a.n_out_rows * a.c_row_words;
-    return (a.nout == 0) ? 64 : a.n_out_rows * a.c_row_words * 32;
-}
+
 
 hipError_t launch_contract(const ContractArgs &a, int mode, hipStream_t s) {
     const int64_t total = contract_units(a, mode);

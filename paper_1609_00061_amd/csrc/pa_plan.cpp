@@ -480,6 +480,36 @@ static void finish_contract(Op &op, bool has_b) {
     for (int i = 0; i < a.nout; ++i) a.fd_dim[i] = make_fastdiv((uint64_t)std::max<int64_t>(1, a.out_dim[i]));
     a.fd_rowbits = make_fastdiv((uint64_t)std::max<int64_t>(1, a.c_row_words * 32));
     a.fd_rowwords = make_fastdiv((uint64_t)std::max<int64_t>(1, a.c_row_words));
+    // stream mode K: the row x bit shape of a wave's 64 outputs that touches
+    // the fewest 128-byte lines with its first 16-byte loads of A and B
+    a.tq = 1;
+    if (op.mode == kModeStreamK && a.nout >= 2) {
+        auto lines = [&](int tq) {
+            const int tp = 64 / tq;
+            std::vector<int64_t> la, lb;
+            for (int i = 0; i < tq; ++i)
+                for (int j = 0; j < tp; ++j) {
+                    la.push_back(4 * (i * a.a_str[a.nout - 2] + j * a.a_str[a.nout - 1]) / 128);
+                    if (has_b) lb.push_back(4 * (i * a.b_str[a.nout - 2] + j * a.b_str[a.nout - 1]) / 128);
+                }
+            std::sort(la.begin(), la.end());
+            std::sort(lb.begin(), lb.end());
+            return (int64_t)(std::unique(la.begin(), la.end()) - la.begin()) +
+                   (int64_t)(std::unique(lb.begin(), lb.end()) - lb.begin());
+        };
+        const int64_t rowbits = a.c_row_words * 32;
+        int64_t best = lines(1);
+        for (int tq : {2, 4, 8}) {
+            const int64_t blocks = (a.n_out_rows + tq - 1) / tq * rowbits / (64 / tq);
+            if (blocks >= ((int64_t)1 << 31)) continue;
+            const int64_t l = lines(tq);
+            if (l < best) {
+                best = l;
+                a.tq = tq;
+            }
+        }
+    }
+    a.fd_segs = make_fastdiv((uint64_t)std::max<int64_t>(1, a.c_row_words * 32 / (64 / a.tq)));
 }
 
 static std::string join(const std::vector<int> &v) {
@@ -504,6 +534,8 @@ std::string Op::describe() const {
     if (kind == OP_GEMM)
         s << ",\"batch\":" << ga.nbatch << ",\"M\":" << ga.M << ",\"No\":" << ga.No << ",\"rn\":" << ga.rn
           << ",\"Kw\":" << ga.Kw << ",\"ksplit\":" << ga.ksplit << ",\"direct\":" << ga.direct;
+    else if (mode == kModeStreamK)
+        s << ",\"tq\":" << ca.tq;
     s << "}";
     return s.str();
 }
@@ -594,10 +626,7 @@ static void plot_tiling(PlotRel &R, int strip) {
     R.n_tiles = R.tiles_w * R.tiles_walk * R.tiles_fixed;
 }
 
-static int64_t contract_units_of(const ContractArgs &a, int mode) {
-    if (mode == kModeStreamW) return a.n_out_rows * a.c_row_words;
-    return (a.nout == 0) ? 64 : a.n_out_rows * a.c_row_words * 32;
-}
+static int64_t contract_units_of(const ContractArgs &a, int mode) { return contract_units(a, mode); }
 
 int build_plan(const pa_system *sys, const int32_t *exposed, int32_t n_exposed, const pa_opts *opts, pa_plan *P) {
     auto t0 = std::chrono::steady_clock::now();

@@ -41,6 +41,9 @@ PATTERNS = [
     ((0, 2), (0, 1), (0, 1, 2)),         # the same with B broadcast
     ((1,), (0, 2), (0, 1, 2)),           # one-axis A broadcast
     ((0, 1, 3), (0, 2), (0, 2, 1)),      # A packed along a latent variable: bit-level fallback
+    ((3, 1, 0, 2), (0, 1, 3, 2), (0, 3)),  # stream over a shared packed latent, A contiguous along the row
+                                           # variable and B along the packed one: rows x bits wave tiles
+    ((1, 3, 0, 2), (1, 0, 3, 2), (0, 3)),  # the same with the other latent outermost
 ]
 
 SIZES = [

@@ -97,6 +97,18 @@ def test_c2_reduced_resolution_exact():
     assert np.array_equal(got, ref)
 
 
+@pytest.mark.parametrize("res", [16, 40])
+def test_c3_reduced_resolution_exact(res):
+    """The ternary system where its word-streaming steps run with 2 x 32 and
+    8 x 8 row-by-bit wave tiles."""
+    s = inputs.config3(res=res)
+    tqs = [o.get("tq") for o in pa.describe_plan(s)["ops"] if o["op"] == "stream_k"]
+    assert max(tqs) == (2 if res == 16 else 8)
+    ref = oracle.solve([a[2] for a in s.axes], [r.vars for r in s.relations], _oracle_plots(s), s.exposed)
+    got, rep = _solve(s)
+    assert np.array_equal(got, ref)
+
+
 def test_c2_full_size_exact():
     """Chain of 8 at 1024 per axis: the oracle multiplies the chain pairwise
     (Sec. 3.5 clustering, left to right)."""
