@@ -579,13 +579,63 @@ __device__ unsigned bits_unit(const ContractArgs &a, int64_t row, int64_t bit) {
     }
 }
 
+// The latent-entry table is read-only while a kernel runs and indexed
+// uniformly: read through the constant address space (scalar loads).
+#define PA_K __attribute__((address_space(4)))
+
+// Stream mode K with RW (4, 8 or 16) words per row of the shared packed
+// latent axis and both operands: four latent entries at a time, all their
+// loads issued before any is used.
+template <int RW>
+__device__ __forceinline__ uint32_t streamk_rows(const ContractArgs &a, const OutPos &p) {
+    const PA_K int64_t *kt = (const PA_K int64_t *)a.ktab;
+    const PA_G uint32_t *A = gp(a.A) + p.baseA, *B = gp(a.B) + p.baseB;
+    constexpr int V = RW / 4;
+    uint32_t acc = 0;
+    int64_t j = 0;
+    for (; j + 4 <= a.nktab; j += 4) {
+        u32x4 x[4][V], y[4][V];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const PA_G uint32_t *pa = A + kt[2 * (j + e)], *pb = B + kt[2 * (j + e) + 1];
+#pragma unroll
+            for (int w = 0; w < V; ++w) {
+                x[e][w] = *reinterpret_cast<const PA_G u32x4 *>(pa + 4 * w);
+                y[e][w] = *reinterpret_cast<const PA_G u32x4 *>(pb + 4 * w);
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+            for (int w = 0; w < V; ++w) {
+                const u32x4 t = x[e][w] & y[e][w];
+                acc |= t.x | t.y | t.z | t.w;
+            }
+    }
+    for (; j < a.nktab; ++j) {
+        const PA_G uint32_t *pa = A + kt[2 * j], *pb = B + kt[2 * j + 1];
+#pragma unroll
+        for (int w = 0; w < V; ++w) {
+            const u32x4 t = *reinterpret_cast<const PA_G u32x4 *>(pa + 4 * w) &
+                            *reinterpret_cast<const PA_G u32x4 *>(pb + 4 * w);
+            acc |= t.x | t.y | t.z | t.w;
+        }
+    }
+    return acc;
+}
+
 // Stream mode K: A and B are both bit-packed along the same latent variable;
 // whole rows of it are ANDed (16 bytes at a time when rows allow) for every
 // entry of the other latent variables (offsets from the host table).
 template <bool VEC4>
-__device__ uint32_t streamk_unit(const ContractArgs &a, int64_t row, int64_t bit) {
+__device__ __forceinline__ uint32_t streamk_unit(const ContractArgs &a, int64_t row, int64_t bit) {
     const OutPos p = out_pos(a, row, bit);
     const int64_t rw = a.a_row_words;
+    if (VEC4 && a.B) {
+        if (rw == 4) return streamk_rows<4>(a, p);
+        if (rw == 8) return streamk_rows<8>(a, p);
+        if (rw == 16) return streamk_rows<16>(a, p);
+    }
     uint32_t acc = 0;
     for (int64_t j = 0; j < a.nktab; ++j) {
         const PA_G uint32_t *pa = gp(a.A) + p.baseA + gp(a.ktab)[2 * j];
@@ -618,7 +668,7 @@ __device__ uint32_t streamk_unit(const ContractArgs &a, int64_t row, int64_t bit
 // that has it; whole words are ANDed and ORed over the latent entries (host
 // table); an operand without it contributes its bit at this output row,
 // broadcast over the word.
-__device__ uint32_t streamw_word(const ContractArgs &a, int64_t row, int64_t wc) {
+__device__ __forceinline__ uint32_t streamw_word(const ContractArgs &a, int64_t row, int64_t wc) {
     if (wc * 32 >= a.out_dim[a.nout - 1]) return 0u;
     const OutPos p = out_pos(a, row, 0);
     uint32_t acc = 0;
@@ -637,8 +687,10 @@ __device__ uint32_t streamw_word(const ContractArgs &a, int64_t row, int64_t wc)
 
 // Units [u0, u1) of a contraction by one 256-thread block: output bits for
 // the bit-out modes (u0, u1 multiples of 64 or the end), words for mode W.
+// Inlined, so that the step's fields (the latent-entry table above all)
+// stay uniform: scalar loads, not a per-lane round trip per entry.
 template <int MODE>
-__device__ void contract_range(const ContractArgs &a, int64_t u0, int64_t u1) {
+__device__ __forceinline__ void contract_range(const ContractArgs &a, int64_t u0, int64_t u1) {
     // the row of the block's first unit by one (uniform) division per step,
     // each thread's offset from it by a 32-bit fast division
     if (MODE == kModeStreamW) {

@@ -94,3 +94,14 @@ def test_mfma_gemm_dense_and_batched(path):
     got = to_host(C, [nb, M, N])
     ref = np.einsum("bmk,bnk->bmn", A.astype(np.int64), B.astype(np.int64)) > 0
     assert np.array_equal(got.astype(bool), ref)
+
+
+@pytest.mark.parametrize("kdim", [100, 200, 400, 1000])
+@pytest.mark.parametrize("latent", [3, 8, 13])
+def test_stream_over_shared_packed_latent(kdim, latent):
+    """Word streaming over a packed latent axis of 4, 8, 16 and 32 words
+    per row (the 4/8/16-word rows take the four-entries-at-a-time path),
+    with latent-entry counts that are and are not multiples of four, and
+    rows-by-bits wave tiles."""
+    res = {0: 40, 1: latent, 2: kdim, 3: 70}
+    _run((3, 1, 0, 2), (0, 1, 3, 2), (0, 3), res, 0.02, 700 + kdim + latent)
