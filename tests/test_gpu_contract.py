@@ -104,4 +104,5 @@ def test_stream_over_shared_packed_latent(kdim, latent):
     with latent-entry counts that are and are not multiples of four, and
     rows-by-bits wave tiles."""
     res = {0: 40, 1: latent, 2: kdim, 3: 70}
-    _run((3, 1, 0, 2), (0, 1, 3, 2), (0, 3), res, 0.02, 700 + kdim + latent)
+    # about one matching latent entry per output bit: half the outputs set
+    _run((3, 1, 0, 2), (0, 1, 3, 2), (0, 3), res, 1.0 / np.sqrt(kdim * latent), 700 + kdim + latent)
