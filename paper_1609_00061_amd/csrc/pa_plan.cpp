@@ -805,7 +805,8 @@ static int check_gemm_bounds(const GemmArgs &g, int64_t a_words, int64_t b_words
         return fail(PA_EINVAL, "internal: GEMM would index outside its buffers");
     // the kernels decode tile indices and N coordinates in 32 bits
     const int64_t lim = (int64_t)1 << 31;
-    if (g.nbatch * g.tiles_m * g.tiles_n * g.ksplit >= lim || g.tiles_n * 128 + 128 >= lim)
+    if (g.nbatch * g.tiles_m * g.tiles_n * g.ksplit >= lim || g.tiles_n * 128 + 128 >= lim || g.M + 128 >= lim ||
+        g.Kw >= lim)
         return fail(PA_EUNSUPPORTED, "GEMM too large for one launch");
     return PA_OK;
 }
