@@ -864,95 +864,80 @@ __device__ __forceinline__ uint32_t block_bits(const v16i &a) {
 // Loader thread tid stages row (tid >> 1), words (tid & 1) * 4 .. + 3 of each
 // K chunk, for A and for B.
 struct GemmTileRef {
-    const GemmArgs *g;            // the tile's contraction (read-only while the kernel runs)
-    const PA_G uint32_t *a, *b;   // this thread's A and B rows (LDS-staged path)
-    int64_t bt;                   // batch
-    int32_t m0, n0;               // tile origin (below 2^31: host checks)
-    int32_t kw0, kw1;             // K range (words)
-    bool a_ok, b_ok;
+    const PA_G uint32_t *a, *b;   // this thread's A and B rows
+    PA_G uint32_t *c;             // C of the tile's batch
+    int64_t kw0, kw1;             // K range (words)
+    int64_t m0, n0, M, No, rwc;
+    FastDiv fd_wc;                // division by the padded C row length in bits
+    bool a_ok, b_ok, vec4, atomic;
+    const PA_G uint32_t *abase, *bbase;   // A and B of the tile's batch
+    int64_t Kw, rn;
 };
-
-// Row of B (n index within the batch, or -1 past the end) of padded output
-// column n: n = (no, j) with Wc = 32 rwc columns per no.
-__device__ __forceinline__ int64_t gemm_brow(const GemmArgs &g, uint32_t n) {
-    const uint32_t Wc = (uint32_t)(g.rwc * 32);
-    const uint32_t no = fdiv(n, g.fd_wc), j = n - no * Wc;
-    return (no < g.No && j < g.rn) ? (int64_t)no * g.rn + j : -1;
-}
 
 __device__ __forceinline__ GemmTileRef gemm_locate(const GemmArgs &g, int64_t t64) {
     GemmTileRef r;
-    r.g = &g;
     // tile index and N coordinates are below 2^31 (checked on the host)
     const uint32_t t = (uint32_t)t64;
     const uint32_t q1 = fdiv(t, g.fd_ksplit);
     const int ks = (int)(t - q1 * (uint32_t)g.ksplit);
     const uint32_t q2 = fdiv(q1, g.fd_tiles_n);
-    const uint32_t tn = q1 - q2 * (uint32_t)g.tiles_n;
+    const int64_t tn = q1 - q2 * (uint32_t)g.tiles_n;
     const uint32_t q3 = fdiv(q2, g.fd_tiles_m);
-    const uint32_t tm = q2 - q3 * (uint32_t)g.tiles_m;
-    r.bt = q3;
-    r.m0 = (int32_t)(tm * kTile);
-    r.n0 = (int32_t)(tn * kTile);
-    r.kw0 = (int32_t)(ks * g.kchunk);
-    r.kw1 = (int32_t)min(g.Kw, (int64_t)r.kw0 + g.kchunk);
-    // loader row of this thread
+    const int64_t tm = q2 - q3 * (uint32_t)g.tiles_m;
+    const int64_t b = q3;
     const int lrow = threadIdx.x >> 1;
-    const int32_t am = r.m0 + lrow;
+    r.m0 = tm * kTile;
+    r.n0 = tn * kTile;
+    r.kw0 = (int64_t)ks * g.kchunk;
+    r.kw1 = min(g.Kw, r.kw0 + g.kchunk);
+    r.vec4 = (g.Kw % 4) == 0;
+    const int64_t am = r.m0 + lrow;
     r.a_ok = am < g.M;
-    r.a = gp(g.A) + r.bt * g.sA_b + (int64_t)(r.a_ok ? am : 0) * g.Kw;
-    int64_t brow;
-    if ((g.rwc & 3) == 0) {
-        // 128-column tiles never cross an output row: one division per tile
-        const uint32_t Wc = (uint32_t)(g.rwc * 32);
-        const uint32_t no = fdiv((uint32_t)r.n0, g.fd_wc), j = (uint32_t)r.n0 - no * Wc + lrow;
-        brow = (no < g.No && j < g.rn) ? (int64_t)no * g.rn + j : -1;
-    } else {
-        brow = gemm_brow(g, (uint32_t)(r.n0 + lrow));
-    }
-    r.b_ok = brow >= 0;
-    r.b = gp(g.B) + r.bt * g.sB_b + (r.b_ok ? brow : 0) * g.Kw;
+    r.a = gp(g.A) + b * g.sA_b + (r.a_ok ? am : 0) * g.Kw;
+    const uint32_t Wc = (uint32_t)(g.rwc * 32);
+    const uint32_t bn = (uint32_t)(r.n0 + lrow);
+    const uint32_t bno = fdiv(bn, g.fd_wc), bj = bn - bno * Wc;
+    r.b_ok = (bno < g.No) && (bj < g.rn);
+    r.b = gp(g.B) + b * g.sB_b + (r.b_ok ? (bno * g.rn + bj) : 0) * g.Kw;
+    r.c = gp(g.C) + b * g.sC_b;
+    r.abase = gp(g.A) + b * g.sA_b;
+    r.bbase = gp(g.B) + b * g.sB_b;
+    r.Kw = g.Kw;
+    r.rn = g.rn;
+    r.M = g.M;
+    r.No = g.No;
+    r.rwc = g.rwc;
+    r.fd_wc = g.fd_wc;
+    r.atomic = g.ksplit > 1;
     return r;
 }
 
 // Writes one tile's packed output words: accumulator register r of a 32x32
 // block holds MFMA row 8*(r/4) + 4*h + r%4 (our n) at MFMA column l32 (our m).
 __device__ __forceinline__ void gemm_epilogue(const GemmTileRef &T, v16i (&acc)[2][2]) {
-    const GemmArgs &g = *T.g;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm = wave >> 1, wn = wave & 1, h = lane >> 5, l32 = lane & 31;
-    const uint32_t Wc = (uint32_t)(g.rwc * 32);
-    PA_G uint32_t *c = gp(g.C) + T.bt * g.sC_b;
-    const bool atomic = g.ksplit > 1;
+    const uint32_t Wc = (uint32_t)(T.rwc * 32);
     const int xor32 = (lane ^ 32) << 2;     // ds_bpermute byte address of the other lane half
-    // the two column words of the wave's quadrant (uniform), and this lane's
-    // two output rows as pointers to their starts
-    int64_t colw[2];
-    bool col_ok[2];
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-        const uint32_t n = (uint32_t)(T.n0 + wn * 64 + j * 32);
-        const uint32_t no = fdiv(n, g.fd_wc);
-        colw[j] = (int64_t)no * g.rwc + (n - no * Wc) / 32;
-        col_ok[j] = no < g.No;
-    }
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
-        const int64_t m = T.m0 + wm * 64 + i * 32 + l32;
-        const bool row_ok = h == 0 && m < g.M;
-        PA_G uint32_t *row = c + m * (g.No * g.rwc);
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
             // counts are >= 0: min(count, 1) is the bit; positions without the
             // lane-half term are constants, the half shifts the whole word
             uint32_t mask = block_bits(acc[i][j]) << (4 * h);
             mask |= (uint32_t)__builtin_amdgcn_ds_bpermute(xor32, (int)mask);
-            if (row_ok && col_ok[j]) {
-                PA_G uint32_t *dst = row + colw[j];
-                if (atomic) {
-                    if (mask) __hip_atomic_fetch_or(dst, mask, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                } else {
-                    *dst = mask;
+            if (h == 0) {
+                const int64_t m = T.m0 + wm * 64 + i * 32 + l32;
+                const uint32_t n = (uint32_t)(T.n0 + wn * 64 + j * 32);
+                const uint32_t no = fdiv(n, T.fd_wc), wc = (n - no * Wc) / 32;
+                if (m < T.M && no < T.No) {
+                    PA_G uint32_t *dst = T.c + (m * T.No + no) * T.rwc + wc;
+                    if (T.atomic) {
+                        if (mask) __hip_atomic_fetch_or(dst, mask, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    } else {
+                        *dst = mask;
+                    }
                 }
             }
         }
@@ -1042,9 +1027,8 @@ __device__ void gemm_tiles(Next next, uint32_t *lds) {
     };
     auto load = [&](const GemmChunk &c, uint4 &ra, uint4 &rb) {
         if (c.valid) {
-            const bool vec4 = (c.T.g->Kw & 3) == 0;
-            ra = load_row4(c.T.a, c.kc + lw, c.T.kw1, c.T.a_ok, vec4);
-            rb = load_row4(c.T.b, c.kc + lw, c.T.kw1, c.T.b_ok, vec4);
+            ra = load_row4(c.T.a, c.kc + lw, c.T.kw1, c.T.a_ok, c.T.vec4);
+            rb = load_row4(c.T.b, c.kc + lw, c.T.kw1, c.T.b_ok, c.T.vec4);
         }
     };
     GemmChunk c0;
@@ -1089,17 +1073,17 @@ struct GemmRows {
 __device__ __forceinline__ GemmRows gemm_rows(const GemmTileRef &T) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm = wave >> 1, wn = wave & 1, l32 = lane & 31;
-    const GemmArgs &g = *T.g;
-    const PA_G uint32_t *abase = gp(g.A) + T.bt * g.sA_b, *bbase = gp(g.B) + T.bt * g.sB_b;
+    const uint32_t Wc = (uint32_t)(T.rwc * 32);
     GemmRows R;
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
         const int64_t am = T.m0 + wm * 64 + i * 32 + l32;
-        R.a_ok[i] = am < g.M;
-        R.a[i] = abase + (R.a_ok[i] ? am : 0) * g.Kw;
-        const int64_t brow = gemm_brow(g, (uint32_t)(T.n0 + wn * 64 + i * 32 + l32));
-        R.b_ok[i] = brow >= 0;
-        R.b[i] = bbase + (R.b_ok[i] ? brow : 0) * g.Kw;
+        R.a_ok[i] = am < T.M;
+        R.a[i] = T.abase + (R.a_ok[i] ? am : 0) * T.Kw;
+        const uint32_t bn = (uint32_t)(T.n0 + wn * 64 + i * 32 + l32);
+        const uint32_t bno = fdiv(bn, T.fd_wc), bj = bn - bno * Wc;
+        R.b_ok[i] = (bno < T.No) && (bj < T.rn);
+        R.b[i] = T.bbase + (R.b_ok[i] ? (bno * T.rn + bj) : 0) * T.Kw;
     }
     return R;
 }
@@ -1168,8 +1152,8 @@ __device__ void gemm_tiles_direct(Next next) {
         for (int i = 0; i < 2; ++i)
 #pragma unroll
             for (int h4 = 0; h4 < 2; ++h4) {
-                a4[i][h4] = load_row4(c.R.a[i], c.kc + 4 * h4, c.T.kw1, c.R.a_ok[i], (c.T.g->Kw & 3) == 0);
-                b4[i][h4] = load_row4(c.R.b[i], c.kc + 4 * h4, c.T.kw1, c.R.b_ok[i], (c.T.g->Kw & 3) == 0);
+                a4[i][h4] = load_row4(c.R.a[i], c.kc + 4 * h4, c.T.kw1, c.R.a_ok[i], c.T.vec4);
+                b4[i][h4] = load_row4(c.R.b[i], c.kc + 4 * h4, c.T.kw1, c.R.b_ok[i], c.T.vec4);
             }
     };
     GemmChunkD c0;
