@@ -866,12 +866,12 @@ __device__ __forceinline__ uint32_t block_bits(const v16i &a) {
 struct GemmTileRef {
     const PA_G uint32_t *a, *b;   // this thread's A and B rows
     PA_G uint32_t *c;             // C of the tile's batch
-    int64_t kw0, kw1;             // K range (words)
-    int64_t m0, n0, M, No, rwc;
-    FastDiv fd_wc;                // division by the padded C row length in bits
-    bool a_ok, b_ok, vec4, atomic;
     const PA_G uint32_t *abase, *bbase;   // A and B of the tile's batch
-    int64_t Kw, rn;
+    FastDiv fd_wc;                // division by the padded C row length in bits
+    // 32-bit sizes and coordinates (below 2^31: host checks), which halves
+    // the scalar registers three tiles in flight hold
+    int32_t kw0, kw1, m0, n0, M, No, rwc, Kw, rn;
+    bool a_ok, b_ok, vec4, atomic;
 };
 
 __device__ __forceinline__ GemmTileRef gemm_locate(const GemmArgs &g, int64_t t64) {
@@ -886,12 +886,12 @@ __device__ __forceinline__ GemmTileRef gemm_locate(const GemmArgs &g, int64_t t6
     const int64_t tm = q2 - q3 * (uint32_t)g.tiles_m;
     const int64_t b = q3;
     const int lrow = threadIdx.x >> 1;
-    r.m0 = tm * kTile;
-    r.n0 = tn * kTile;
-    r.kw0 = (int64_t)ks * g.kchunk;
-    r.kw1 = min(g.Kw, r.kw0 + g.kchunk);
+    r.m0 = (int32_t)(tm * kTile);
+    r.n0 = (int32_t)(tn * kTile);
+    r.kw0 = (int32_t)(ks * g.kchunk);
+    r.kw1 = (int32_t)min(g.Kw, (int64_t)r.kw0 + g.kchunk);
     r.vec4 = (g.Kw % 4) == 0;
-    const int64_t am = r.m0 + lrow;
+    const int64_t am = (int64_t)r.m0 + lrow;
     r.a_ok = am < g.M;
     r.a = gp(g.A) + b * g.sA_b + (r.a_ok ? am : 0) * g.Kw;
     const uint32_t Wc = (uint32_t)(g.rwc * 32);
@@ -902,11 +902,11 @@ __device__ __forceinline__ GemmTileRef gemm_locate(const GemmArgs &g, int64_t t6
     r.c = gp(g.C) + b * g.sC_b;
     r.abase = gp(g.A) + b * g.sA_b;
     r.bbase = gp(g.B) + b * g.sB_b;
-    r.Kw = g.Kw;
-    r.rn = g.rn;
-    r.M = g.M;
-    r.No = g.No;
-    r.rwc = g.rwc;
+    r.Kw = (int32_t)g.Kw;
+    r.rn = (int32_t)g.rn;
+    r.M = (int32_t)g.M;
+    r.No = (int32_t)g.No;
+    r.rwc = (int32_t)g.rwc;
     r.fd_wc = g.fd_wc;
     r.atomic = g.ksplit > 1;
     return r;
@@ -996,7 +996,7 @@ __device__ __forceinline__ void gemm_chunk(const uint32_t *sA, const uint32_t *s
 // One K chunk of one tile in the workgroup's sequence.
 struct GemmChunk {
     GemmTileRef T;
-    int64_t kc;
+    int32_t kc;
     bool valid;
 };
 
@@ -1091,7 +1091,7 @@ __device__ __forceinline__ GemmRows gemm_rows(const GemmTileRef &T) {
 struct GemmChunkD {
     GemmTileRef T;
     GemmRows R;
-    int64_t kc;
+    int32_t kc;
     bool valid;
 };
 
