@@ -276,17 +276,22 @@ __device__ void line_coefs(const PlotView &V, const double *cst, double y0, doub
 // sign bits and the certainty bits are shifted into words with one alignbit
 // each (corners taken from 31 down to 0).  Out: LE/GE where the sign is
 // certain, FL the corners FP64 decides.
+// Bits of the 33 corners of a word (corner kk at bit kk of lo, corner 32 in
+// hi): 32-bit operations on the common path.
+struct Corners {
+    uint32_t lo, hi;
+};
+
 template <int NF>
-__device__ __forceinline__ void line_fp32(const float *ln, const float *xv, int kmax, uint64_t &LE, uint64_t &GE,
-                                          uint64_t &FL) {
+__device__ __forceinline__ void line_fp32(const float *ln, const float *xv, const Corners &valid, Corners &LE,
+                                          Corners &GE, Corners &FL) {
     float ca[NF + 1];
 #pragma unroll
     for (int t = 0; t <= NF; ++t) ca[t] = ln[t];
     const float E = ln[kLineFloats - 1];
-    const uint64_t valid = (kmax >= 63) ? ~0ull : ((2ull << kmax) - 1ull);
     if (!(E < INFINITY)) {
-        LE = 0;
-        GE = 0;
+        LE = {0u, 0u};
+        GE = {0u, 0u};
         FL = valid;
         return;
     }
@@ -297,7 +302,7 @@ __device__ __forceinline__ void line_fp32(const float *ln, const float *xv, int 
         return f;
     };
     const float f32 = value(xv[32]);
-    const uint32_t sg32 = __float_as_uint(f32) >> 31, ok32 = __float_as_uint(E - fabsf(f32)) >> 31;
+    const uint32_t sg32 = __float_as_uint(f32) >> 31, ok32 = (__float_as_uint(E - fabsf(f32)) >> 31) & valid.hi;
     uint32_t sg = 0, ok = 0;
     // four corners at a time, their Horner steps interleaved: one wave per
     // SIMD is common here, and a single dependent chain would leave the
@@ -317,11 +322,10 @@ __device__ __forceinline__ void line_fp32(const float *ln, const float *xv, int 
             ok = __builtin_amdgcn_alignbit(ok, __float_as_uint(E - fabsf(f[i])), 31);
         }
     }
-    const uint64_t okm = ((uint64_t)ok | ((uint64_t)ok32 << 32)) & valid;
-    const uint64_t sgm = (uint64_t)sg | ((uint64_t)sg32 << 32);
-    LE = okm & sgm;
-    GE = okm & ~sgm;
-    FL = valid & ~okm;
+    ok &= valid.lo;
+    LE = {ok & sg, ok32 & sg32};
+    GE = {ok & ~sg, ok32 & ~sg32};
+    FL = {valid.lo & ~ok, valid.hi & ~ok32};
 }
 
 // LE/GE bits of the corners k0..k0+kmax of one corner line: ln its FP32
@@ -330,39 +334,49 @@ __device__ __forceinline__ void line_fp32(const float *ln, const float *xv, int 
 // declared-order coefficient table (all three in LDS); `own` says whether
 // this thread counts the line's corners (each corner is counted once).
 __device__ __forceinline__ void eval_line(const PlotView &V, const float *ln, const float *xv, const double *ly,
-                                          const double *cdl, int k0, int kmax, bool own, uint64_t &LE, uint64_t &GE,
+                                          const double *cdl, int k0, int kmax, bool own, Corners &LE, Corners &GE,
                                           PlotCount &cnt) {
     const int n = V.n, rp = V.rp;
-    const uint64_t valid = (kmax >= 63) ? ~0ull : ((2ull << kmax) - 1ull);
-    const uint64_t owned = own ? (((1ull << kmax) - 1ull) | ((k0 + kmax == rp) ? (1ull << kmax) : 0ull)) : 0ull;
-    uint64_t FL = valid, todo;
+    // kmax <= 32 corners past k0 belong to this word
+    const Corners valid = {kmax >= 31 ? ~0u : ((2u << kmax) - 1u), kmax >= 32 ? 1u : 0u};
+    Corners FL = valid, todo;
     if (V.mode == PA_PLOT_FP32_ESCALATE) {
-        if (V.d <= 3) line_fp32<3>(ln, xv, kmax, LE, GE, FL);
-        else line_fp32<kMaxD>(ln, xv, kmax, LE, GE, FL);
-        cnt.flagged += __popcll(FL & owned);
+        if (V.d <= 3) line_fp32<3>(ln, xv, valid, LE, GE, FL);
+        else line_fp32<kMaxD>(ln, xv, valid, LE, GE, FL);
         todo = V.audit ? valid : FL;
     } else {
-        LE = 0;
-        GE = 0;
+        LE = {0u, 0u};
+        GE = {0u, 0u};
         todo = valid;
     }
+    if ((todo.lo | todo.hi) == 0u) return;       // the common case: every corner certain in FP32
+    const bool last = k0 + kmax == rp;
+    const Corners owned = {own ? (kmax >= 32 ? ~0u : ((1u << kmax) - 1u) | (last ? (1u << kmax) : 0u)) : 0u,
+                           (own && last && kmax == 32) ? 1u : 0u};
+    if (V.mode == PA_PLOT_FP32_ESCALATE) cnt.flagged += __popc(FL.lo & owned.lo) + (FL.hi & owned.hi);
     // FP64 decides the escalated corners (every corner in FP64 mode); in
     // audit mode every corner's FP32 sign is also compared with its FP64 sign
     const double y0 = ly[0], y1 = ly[1];
-    while (todo) {
-        const int kk = __ffsll((long long)todo) - 1;
-        todo &= todo - 1;
+    uint64_t rest = (uint64_t)todo.lo | ((uint64_t)todo.hi << 32);
+    while (rest) {
+        const int kk = __ffsll((long long)rest) - 1;
+        rest &= rest - 1;
         double xd[3];
         const double xk = corner_coord(V.lop, V.stp, k0 + kk);
         if (n == 1) decl_point(V, xk, 0.0, 0.0, xd);
         else if (n == 2) decl_point(V, y0, xk, 0.0, xd);
         else decl_point(V, y0, y1, xk, xd);
         const double f64 = canon_eval(cdl, n, V.d, xd);
-        const uint64_t bit = 1ull << kk;
-        const bool flagged = (FL & bit) != 0;
+        const bool hi = kk == 32;
+        const uint32_t bit = hi ? 1u : (1u << kk);
+        const bool flagged = ((hi ? FL.hi : FL.lo) & bit) != 0;
         if (flagged) {
-            LE |= (uint64_t)(f64 <= 0.0) << kk;
-            GE |= (uint64_t)(f64 >= 0.0) << kk;
+            if (f64 <= 0.0) {
+                if (hi) LE.hi |= 1u; else LE.lo |= bit;
+            }
+            if (f64 >= 0.0) {
+                if (hi) GE.hi |= 1u; else GE.lo |= bit;
+            }
         }
         if (V.mode == PA_PLOT_FP32_ESCALATE && V.audit) {
             // FP32 value of this corner, recomputed as in line_fp32 (same
@@ -373,7 +387,8 @@ __device__ __forceinline__ void eval_line(const PlotView &V, const float *ln, co
             for (int t = kMaxD - 1; t >= 0; --t) f = fmaf(f, x, ln[t]);
             const int s32 = (f > 0.0f) - (f < 0.0f);
             const int s64 = (f64 > 0.0) - (f64 < 0.0);
-            const bool dis = ((s32 != s64) || (f != f) || (f64 != f64)) && (owned & bit);
+            const bool is_owned = ((hi ? owned.hi : owned.lo) & bit) != 0;
+            const bool dis = ((s32 != s64) || (f != f) || (f64 != f64)) && is_owned;
             cnt.dis += dis;
             cnt.dis_unf += dis && !flagged;
         }
@@ -470,10 +485,11 @@ __device__ void plot_tile(const PlotRel &R, int64_t tile, float *lines, double *
                     lf = fa + df;
                 }
                 const int li = lf * nwl + (int)(c - b0);
-                uint64_t LE, GE;
+                Corners LE, GE;
                 eval_line(V, lines + li * kLineFloats, xv, ly + 2 * li, cdl, k0, kmax, own, LE, GE, cnt);
-                lc |= (uint32_t)((LE | (LE >> 1)) & 0xffffffffull);
-                gc |= (uint32_t)((GE | (GE >> 1)) & 0xffffffffull);
+                // cell i holds corners i and i + 1
+                lc |= LE.lo | __builtin_amdgcn_alignbit(LE.hi, LE.lo, 1);
+                gc |= GE.lo | __builtin_amdgcn_alignbit(GE.hi, GE.lo, 1);
             }
         }
         if (n == 1) {
