@@ -152,13 +152,15 @@ typedef struct {
                                  timing on the device (stream 0) on a cache miss */
     int32_t gemm_split;       /* MFMA contractions: those of one tree level (one
                                  grouped launch) split their K range until the
-                                 launch holds about this many work items (128x128
+                                 launch holds about this many work items (output
                                  tiles x parts); partial products are OR-ed into a
                                  zeroed output (exact); 1: never split; 0: default
                                  (512)                                            */
     int32_t gemm_path;        /* MFMA contractions: 1 = K chunks staged in LDS by the
-                                 workgroup; 2 = each wave loads its own rows straight
-                                 into registers (no LDS, no barriers); 0: default */
+                                 workgroup, 128x128 output tiles; 2 = each wave loads
+                                 its own rows straight into registers (no LDS, no
+                                 barriers); 3 = staged in LDS, 256x128 output tiles
+                                 (4x2 MFMA blocks per wave); 0: default (1)       */
     int32_t verify_order;     /* PA_ORDER_LEARNED, pa_plan_create: 1 = when the model's
                                  tree differs from the exhaustive one, build both,
                                  time each on the device (one untimed and two timed
@@ -356,7 +358,8 @@ int32_t pa_plan_step_samples(pa_plan *plan, float *features, float *log2_us, int
  * persistent launch with 256/512/1024/2048 workgroups), then the plot strip
  * length (1/2/4/8 cells per thread), then the streaming tile (512..32768
  * output bits), then the MFMA K-split target (1, 64, 128, 256, 512, 1024,
- * 2048 work items), then the MFMA operand path (LDS-staged or direct), each
+ * 2048 work items), then the MFMA operand path (LDS-staged 128x128 or
+ * 256x128 tiles, or direct), each
  * from the best so far.  Every candidate is a batch built
  * with opts (graph capture included if opts->graph), executed once untimed,
  * then reps times between two events on `stream`.  Candidates that exceed

@@ -140,7 +140,9 @@ struct GemmArgs {
     int64_t tiles_m, tiles_n; // 128-row and 128-column tiles (N in padded coordinates)
     int64_t kchunk;           // words per K split (multiple of 8)
     int ksplit;               // >1: partial results OR-ed with atomics into zeroed C
-    int direct;               // 1: waves load K chunks straight into registers (no LDS)
+    int path;                 // operand path: 0 = K chunks staged in LDS, 128 x 128 tiles;
+                              // 1 = waves load K chunks straight into registers (no LDS);
+                              // 2 = staged in LDS, 256 x 128 tiles (tiles_m counts 256 rows)
     // divisions of the tile index (below 2^31) and of N coordinates by the
     // padded C row length in bits (below 2^31), checked on the host
     FastDiv fd_ksplit, fd_tiles_n, fd_tiles_m, fd_wc;

@@ -804,10 +804,15 @@ hipError_t launch_contract(const ContractArgs &a, int mode, hipStream_t s) {
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 
-constexpr int kTile = 128;     // 128 x 128 output tile per workgroup (4 waves of 64 x 64)
+constexpr int kTile = 128;     // output tile columns (and rows of the 128 x 128 tile): 4 waves of 64 x 64
 constexpr int kChunk = 8;      // K words staged per iteration (256 Boolean k)
 constexpr int kPitch = 12;     // LDS row pitch in words: 16-byte reads of 8 rows hit distinct banks
-constexpr int kGemmLdsWords = 4 * kTile * kPitch;   // A and B, double-buffered
+// LDS words of the staged paths: A (64 WI rows) and B (128 rows), double-buffered;
+// WI = 32-row blocks per wave (2: 128 x 128 tiles, 4: 256 x 128 tiles)
+template <int WI>
+constexpr int gemm_lds_words() { return 2 * (64 * WI + kTile) * kPitch; }
+constexpr int kGemmLdsWords = gemm_lds_words<2>();
+constexpr int kGemmLdsWordsWide = gemm_lds_words<4>();
 
 __device__ __forceinline__ uint4 load_row4(const PA_G uint32_t *__restrict__ p, int64_t kw, int64_t kend, bool ok,
                                            bool vec4) {
@@ -838,14 +843,22 @@ __device__ __forceinline__ v4i spread(uint32_t x, const uint32_t *m) {
     return r;
 }
 
-// Bit word of one 32x32 accumulator block for this lane: bit
-// 8*(r/4) + r%4 set iff count r > 0 (counts are >= 0).  Registers r and
-// r + 8 land 16 bits apart, so each pair is packed into one dword with
-// 16-bit saturation, both halves are clamped to 1 with one packed 16-bit
-// min, and the dword is shifted into place: 23 instructions for 16 counts
-// (written out: the compiler would turn min(x,1) into compares and selects).
-__device__ __forceinline__ uint32_t block_bits(const v16i &a) {
-    const uint32_t one2 = 0x00010001u;
+// B rows are presented to the MFMA permuted within each 32-row block: MFMA
+// row rho = 8a + 4h + b (accumulator register 4a + b of lane half h, in the
+// 32 x 32 output layout) multiplies B row 16h + 4a + b.  Then register r of
+// lane half h holds output column 16h + r, and each lane owns 16 consecutive
+// output bits.
+__device__ __forceinline__ int brow_of_mfma_row(int rho) { return ((rho >> 2) & 1) * 16 + (rho >> 3) * 4 + (rho & 3); }
+__device__ __forceinline__ int mfma_row_of_brow(int n) { return ((n >> 2) & 3) * 8 + (n >> 4) * 4 + (n & 3); }
+
+// The 16 output bits of one 32x32 accumulator block for this lane: bit r set
+// iff count r > 0 (counts are >= 0).  Registers r and r + 8 are packed into
+// one dword with 16-bit saturation, both halves clamped to 1 with one packed
+// 16-bit min and shifted into place (bits r and 16 + r), then byte 2 moves
+// next to byte 0: 24 instructions for 16 counts (written out: the compiler
+// would turn min(x, 1) into compares and selects).
+__device__ __forceinline__ uint32_t block_bits16(const v16i &a) {
+    const uint32_t one2 = 0x00010001u, sel = 0x0c0c0200u;
     uint32_t m, t;
     asm("v_cvt_pk_u16_u32 %0, %2, %10\n"
         "v_pk_min_u16 %0, %0, %18\n"
@@ -860,19 +873,20 @@ __device__ __forceinline__ uint32_t block_bits(const v16i &a) {
         "v_lshl_or_b32 %0, %1, 3, %0\n"
         "v_cvt_pk_u16_u32 %1, %6, %14\n"
         "v_pk_min_u16 %1, %1, %18\n"
-        "v_lshl_or_b32 %0, %1, 8, %0\n"
+        "v_lshl_or_b32 %0, %1, 4, %0\n"
         "v_cvt_pk_u16_u32 %1, %7, %15\n"
         "v_pk_min_u16 %1, %1, %18\n"
-        "v_lshl_or_b32 %0, %1, 9, %0\n"
+        "v_lshl_or_b32 %0, %1, 5, %0\n"
         "v_cvt_pk_u16_u32 %1, %8, %16\n"
         "v_pk_min_u16 %1, %1, %18\n"
-        "v_lshl_or_b32 %0, %1, 10, %0\n"
+        "v_lshl_or_b32 %0, %1, 6, %0\n"
         "v_cvt_pk_u16_u32 %1, %9, %17\n"
         "v_pk_min_u16 %1, %1, %18\n"
-        "v_lshl_or_b32 %0, %1, 11, %0\n"
+        "v_lshl_or_b32 %0, %1, 7, %0\n"
+        "v_perm_b32 %0, %0, %0, %19\n"
         : "=&v"(m), "=&v"(t)
         : "v"(a[0]), "v"(a[1]), "v"(a[2]), "v"(a[3]), "v"(a[4]), "v"(a[5]), "v"(a[6]), "v"(a[7]), "v"(a[8]), "v"(a[9]),
-          "v"(a[10]), "v"(a[11]), "v"(a[12]), "v"(a[13]), "v"(a[14]), "v"(a[15]), "v"(one2));
+          "v"(a[10]), "v"(a[11]), "v"(a[12]), "v"(a[13]), "v"(a[14]), "v"(a[15]), "v"(one2), "v"(sel));
     return m;
 }
 
@@ -890,6 +904,21 @@ struct GemmTileRef {
     bool a_ok, b_ok, vec4, atomic;
 };
 
+// B row of output column n0 + off (n0 a tile origin, off < 128) in the padded
+// column space of C, where column n = no * Wc + j is B row no * rn + j if
+// no < No and j < rn (else padding: ok = false, row 0).  q0 and r0 are the
+// quotient and remainder of n0 by Wc (tile-uniform); Wc >= 64, so adding off
+// wraps at most twice and no per-lane division is needed.
+__device__ __forceinline__ uint32_t b_row_of(uint32_t q0, uint32_t r0, uint32_t off, uint32_t Wc, uint32_t rn,
+                                             uint32_t No, bool &ok) {
+    uint32_t x = r0 + off, q = q0;
+    if (x >= Wc) { x -= Wc; ++q; }
+    if (x >= Wc) { x -= Wc; ++q; }
+    ok = q < No && x < rn;
+    return ok ? q * rn + x : 0u;
+}
+
+template <int WI>
 __device__ __forceinline__ GemmTileRef gemm_locate(const GemmArgs &g, int64_t t64) {
     GemmTileRef r;
     // tile index and N coordinates are below 2^31 (checked on the host)
@@ -902,7 +931,7 @@ __device__ __forceinline__ GemmTileRef gemm_locate(const GemmArgs &g, int64_t t6
     const int64_t tm = q2 - q3 * (uint32_t)g.tiles_m;
     const int64_t b = q3;
     const int lrow = threadIdx.x >> 1;
-    r.m0 = (int32_t)(tm * kTile);
+    r.m0 = (int32_t)(tm * 64 * WI);
     r.n0 = (int32_t)(tn * kTile);
     r.kw0 = (int32_t)(ks * g.kchunk);
     r.kw1 = (int32_t)min(g.Kw, (int64_t)r.kw0 + g.kchunk);
@@ -911,10 +940,9 @@ __device__ __forceinline__ GemmTileRef gemm_locate(const GemmArgs &g, int64_t t6
     r.a_ok = am < g.M;
     r.a = gp(g.A) + b * g.sA_b + (r.a_ok ? am : 0) * g.Kw;
     const uint32_t Wc = (uint32_t)(g.rwc * 32);
-    const uint32_t bn = (uint32_t)(r.n0 + lrow);
-    const uint32_t bno = fdiv(bn, g.fd_wc), bj = bn - bno * Wc;
-    r.b_ok = (bno < g.No) && (bj < g.rn);
-    r.b = gp(g.B) + b * g.sB_b + (r.b_ok ? (bno * g.rn + bj) : 0) * g.Kw;
+    const uint32_t q0 = fdiv((uint32_t)r.n0, g.fd_wc);
+    const uint32_t brow = b_row_of(q0, (uint32_t)r.n0 - q0 * Wc, (uint32_t)lrow, Wc, (uint32_t)g.rn, (uint32_t)g.No, r.b_ok);
+    r.b = gp(g.B) + b * g.sB_b + (int64_t)brow * g.Kw;
     r.c = gp(g.C) + b * g.sC_b;
     r.abase = gp(g.A) + b * g.sA_b;
     r.bbase = gp(g.B) + b * g.sB_b;
@@ -928,60 +956,68 @@ __device__ __forceinline__ GemmTileRef gemm_locate(const GemmArgs &g, int64_t t6
     return r;
 }
 
-// Writes one tile's packed output words: accumulator register r of a 32x32
-// block holds MFMA row 8*(r/4) + 4*h + r%4 (our n) at MFMA column l32 (our m).
-__device__ __forceinline__ void gemm_epilogue(const GemmTileRef &T, v16i (&acc)[2][2]) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int wm = wave >> 1, wn = wave & 1, h = lane >> 5, l32 = lane & 31;
+// Writes one tile's packed output (a wave's WI x 2 blocks of 32 x 32): lane
+// (h, l32) of block (i, j) holds columns 16h .. 16h + 15 of the block's row
+// l32.  Row addresses are formed once per tile; the block offsets are
+// uniform.  Without a K split every lane stores its 16 bits; with one, the two
+// halves of each word are merged and OR-ed into the (zeroed) output.
+template <int WI>
+__device__ __forceinline__ void gemm_epilogue(const GemmTileRef &T, v16i (&acc)[WI][2]) {
+    const int lane = threadIdx.x & 63, h = lane >> 5, l32 = lane & 31;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int wm = wave >> 1, wn = wave & 1;
     const uint32_t Wc = (uint32_t)(T.rwc * 32);
-    const int xor32 = (lane ^ 32) << 2;     // ds_bpermute byte address of the other lane half
+    const int64_t rs = (int64_t)T.No * T.rwc;                 // words per output row
+    const int32_t mw = T.m0 + wm * (32 * WI);                 // the wave's first row
+    PA_G uint32_t *crow = T.c + (int64_t)(mw + l32) * rs;     // this lane's row in block i = 0
+    const int xor32 = (lane ^ 32) << 2;                       // ds_bpermute address of the other half
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
+    for (int j = 0; j < 2; ++j) {
+        const uint32_t n = (uint32_t)(T.n0 + wn * 64 + j * 32);
+        const uint32_t no = fdiv(n, T.fd_wc);
+        if (no >= (uint32_t)T.No) continue;
+        const int64_t col = (int64_t)no * T.rwc + (n - no * Wc) / 32;
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            // counts are >= 0: min(count, 1) is the bit; positions without the
-            // lane-half term are constants, the half shifts the whole word
-            uint32_t mask = block_bits(acc[i][j]) << (4 * h);
-            mask |= (uint32_t)__builtin_amdgcn_ds_bpermute(xor32, (int)mask);
-            if (h == 0) {
-                const int64_t m = T.m0 + wm * 64 + i * 32 + l32;
-                const uint32_t n = (uint32_t)(T.n0 + wn * 64 + j * 32);
-                const uint32_t no = fdiv(n, T.fd_wc), wc = (n - no * Wc) / 32;
-                if (m < T.M && no < T.No) {
-                    PA_G uint32_t *dst = T.c + (m * T.No + no) * T.rwc + wc;
-                    if (T.atomic) {
-                        if (mask) __hip_atomic_fetch_or(dst, mask, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    } else {
-                        *dst = mask;
-                    }
-                }
+        for (int i = 0; i < WI; ++i) {
+            const uint32_t v = block_bits16(acc[i][j]);
+            const bool row_ok = mw + i * 32 + l32 < T.M;
+            PA_G uint32_t *dst = crow + (int64_t)(i * 32) * rs + col;
+            if (T.atomic) {
+                const uint32_t w = v << (16 * h);
+                const uint32_t word = w | (uint32_t)__builtin_amdgcn_ds_bpermute(xor32, (int)w);
+                if (h == 0 && row_ok && word)
+                    __hip_atomic_fetch_or(dst, word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            } else if (row_ok) {
+                reinterpret_cast<PA_G uint16_t *>(dst)[h] = (uint16_t)v;
             }
         }
     }
 }
 
-// MFMAs of one staged K chunk (kChunk words of A and B in LDS); with
-// `fresh` the first MFMA of each block starts from zero (a new tile).
+// MFMAs of one staged K chunk (kChunk words of A and B in LDS) for a wave's
+// WI x 2 blocks; with `fresh` the first MFMA of each block starts from zero
+// (a new tile).
+template <int WI>
 __device__ __forceinline__ void gemm_chunk(const uint32_t *sA, const uint32_t *sB, const uint32_t *msk,
-                                           v16i (&acc)[2][2], bool fresh) {
+                                           v16i (&acc)[WI][2], bool fresh) {
     const v16i zero = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm = wave >> 1, wn = wave & 1, l32 = lane & 31;
     // one 4-word step at a time keeps the spread operands of a single step live
 #pragma unroll 1
     for (int q4 = 0; q4 < kChunk; q4 += 4) {
-        uint4 a4[2], b4[2];
+        uint4 a4[WI], b4[2];
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
-            a4[i] = *reinterpret_cast<const uint4 *>(&sA[(wm * 64 + i * 32 + l32) * kPitch + q4]);
+        for (int i = 0; i < WI; ++i)
+            a4[i] = *reinterpret_cast<const uint4 *>(&sA[(wm * (32 * WI) + i * 32 + l32) * kPitch + q4]);
 #pragma unroll
         for (int j = 0; j < 2; ++j)
             b4[j] = *reinterpret_cast<const uint4 *>(&sB[(wn * 64 + j * 32 + l32) * kPitch + q4]);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            v4i opa[2], opb[2];
+            v4i opa[WI], opb[2];
 #pragma unroll
-            for (int i = 0; i < 2; ++i) {
+            for (int i = 0; i < WI; ++i) {
                 const uint32_t x = q == 0 ? a4[i].x : q == 1 ? a4[i].y : q == 2 ? a4[i].z : a4[i].w;
                 opa[i] = spread(x, msk);
             }
@@ -994,13 +1030,13 @@ __device__ __forceinline__ void gemm_chunk(const uint32_t *sA, const uint32_t *s
             // then holds one column m, i.e. bits of one output row.
             if (q == 0 && q4 == 0 && fresh) {
 #pragma unroll
-                for (int i = 0; i < 2; ++i)
+                for (int i = 0; i < WI; ++i)
 #pragma unroll
                     for (int j = 0; j < 2; ++j)
                         acc[i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(opb[j], opa[i], zero, 0, 0, 0);
             } else {
 #pragma unroll
-                for (int i = 0; i < 2; ++i)
+                for (int i = 0; i < WI; ++i)
 #pragma unroll
                     for (int j = 0; j < 2; ++j)
                         acc[i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(opb[j], opa[i], acc[i][j], 0, 0, 0);
@@ -1016,18 +1052,27 @@ struct GemmChunk {
     bool valid;
 };
 
-// 128x128 output tiles of the canonical Boolean GEMM, one after another, as
-// a sequence of K chunks software-pipelined two deep: while chunk i is
+// (64 WI) x 128 output tiles of the canonical Boolean GEMM, one after another,
+// as a sequence of K chunks software-pipelined two deep: while chunk i is
 // multiplied from LDS, chunk i+1 is already in registers and chunk i+2 is
 // being loaded, across tile boundaries.  next(T) yields the workgroup's next
-// tile (false when done).  lds holds kGemmLdsWords words.
-template <class Next>
+// tile (false when done).  lds holds gemm_lds_words<WI>() words.  Loader
+// thread tid stages A rows (tid >> 1) + 128 r (r < WI / 2) and B row
+// (tid >> 1), words (tid & 1) * 4 .. + 3 of each chunk.
+template <int WI>
+struct GemmStage {
+    uint4 a[WI / 2], b;
+};
+
+template <int WI, class Next>
 __device__ void gemm_tiles(Next next, uint32_t *lds) {
-    uint32_t *sA[2] = {lds, lds + kTile * kPitch};
-    uint32_t *sB[2] = {lds + 2 * kTile * kPitch, lds + 3 * kTile * kPitch};
+    constexpr int TM = 64 * WI;
+    uint32_t *sA[2] = {lds, lds + TM * kPitch};
+    uint32_t *sB[2] = {lds + 2 * TM * kPitch, lds + 2 * TM * kPitch + kTile * kPitch};
     const int tid = threadIdx.x, lane = tid & 63;
     const int h = lane >> 5;
     const int lrow = tid >> 1, lw = (tid & 1) * 4;
+    const int brow = (lrow & ~31) | mfma_row_of_brow(lrow & 31);   // LDS row of this thread's B row
     uint32_t msk[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) msk[j] = 0x01010101u << (4 * h + j);
@@ -1041,39 +1086,50 @@ __device__ void gemm_tiles(Next next, uint32_t *lds) {
         }
         return n;
     };
-    auto load = [&](const GemmChunk &c, uint4 &ra, uint4 &rb) {
+    auto load = [&](const GemmChunk &c, GemmStage<WI> &r) {
         if (c.valid) {
-            ra = load_row4(c.T.a, c.kc + lw, c.T.kw1, c.T.a_ok, c.T.vec4);
-            rb = load_row4(c.T.b, c.kc + lw, c.T.kw1, c.T.b_ok, c.T.vec4);
+            r.a[0] = load_row4(c.T.a, c.kc + lw, c.T.kw1, c.T.a_ok, c.T.vec4);
+#pragma unroll
+            for (int q = 1; q < WI / 2; ++q) {
+                // row lrow + 128 q exists only if row lrow does (T.a is then its row)
+                const bool ok = c.T.m0 + lrow + 128 * q < c.T.M;
+                r.a[q] = load_row4(c.T.a + (int64_t)(128 * q) * c.T.Kw, c.kc + lw, c.T.kw1, ok, c.T.vec4);
+            }
+            r.b = load_row4(c.T.b, c.kc + lw, c.T.kw1, c.T.b_ok, c.T.vec4);
         }
     };
     GemmChunk c0;
     c0.valid = next(c0.T);
     if (!c0.valid) return;
     c0.kc = c0.T.kw0;
-    uint4 ra0 = make_uint4(0u, 0u, 0u, 0u), rb0 = ra0, ra1 = ra0, rb1 = ra0;
-    load(c0, ra0, rb0);
+    GemmStage<WI> r0, r1;
+#pragma unroll
+    for (int q = 0; q < WI / 2; ++q) r0.a[q] = r1.a[q] = make_uint4(0u, 0u, 0u, 0u);
+    r0.b = r1.b = make_uint4(0u, 0u, 0u, 0u);
+    load(c0, r0);
     GemmChunk c1 = advance(c0);
-    load(c1, ra1, rb1);
-    v16i acc[2][2];
-    // one pipeline step: stage chunk c0 (in ra/rb) into LDS buffer `buf`,
-    // start loading chunk c0+2 into ra/rb, multiply, finish a tile
-    auto step = [&](uint4 &ra, uint4 &rb, int buf) {
-        *reinterpret_cast<uint4 *>(&sA[buf][lrow * kPitch + lw]) = ra;
-        *reinterpret_cast<uint4 *>(&sB[buf][lrow * kPitch + lw]) = rb;
+    load(c1, r1);
+    v16i acc[WI][2];
+    // one pipeline step: stage chunk c0 (in r) into LDS buffer `buf`, start
+    // loading chunk c0+2 into r, multiply, finish a tile
+    auto step = [&](GemmStage<WI> &r, int buf) {
+#pragma unroll
+        for (int q = 0; q < WI / 2; ++q)
+            *reinterpret_cast<uint4 *>(&sA[buf][(lrow + 128 * q) * kPitch + lw]) = r.a[q];
+        *reinterpret_cast<uint4 *>(&sB[buf][brow * kPitch + lw]) = r.b;
         __syncthreads();
         const GemmChunk c2 = advance(c1);
-        load(c2, ra, rb);
+        load(c2, r);
         const bool fresh = c0.kc == c0.T.kw0;
-        gemm_chunk(sA[buf], sB[buf], msk, acc, fresh);
-        if (c0.kc + kChunk >= c0.T.kw1) gemm_epilogue(c0.T, acc);
+        gemm_chunk<WI>(sA[buf], sB[buf], msk, acc, fresh);
+        if (c0.kc + kChunk >= c0.T.kw1) gemm_epilogue<WI>(c0.T, acc);
         c0 = c1;
         c1 = c2;
         return c0.valid;
     };
     for (;;) {
-        if (!step(ra0, rb0, 0)) break;
-        if (!step(ra1, rb1, 1)) break;
+        if (!step(r0, 0)) break;
+        if (!step(r1, 1)) break;
     }
 }
 
@@ -1090,16 +1146,16 @@ __device__ __forceinline__ GemmRows gemm_rows(const GemmTileRef &T) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm = wave >> 1, wn = wave & 1, l32 = lane & 31;
     const uint32_t Wc = (uint32_t)(T.rwc * 32);
+    const uint32_t q0 = fdiv((uint32_t)T.n0, T.fd_wc), r0 = (uint32_t)T.n0 - q0 * Wc;
     GemmRows R;
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
         const int64_t am = T.m0 + wm * 64 + i * 32 + l32;
         R.a_ok[i] = am < T.M;
         R.a[i] = T.abase + (R.a_ok[i] ? am : 0) * T.Kw;
-        const uint32_t bn = (uint32_t)(T.n0 + wn * 64 + i * 32 + l32);
-        const uint32_t bno = fdiv(bn, T.fd_wc), bj = bn - bno * Wc;
-        R.b_ok[i] = (bno < T.No) && (bj < T.rn);
-        R.b[i] = T.bbase + (R.b_ok[i] ? (bno * T.rn + bj) : 0) * T.Kw;
+        const uint32_t off = (uint32_t)(wn * 64 + i * 32 + brow_of_mfma_row(l32));
+        const uint32_t brow = b_row_of(q0, r0, off, Wc, (uint32_t)T.rn, (uint32_t)T.No, R.b_ok[i]);
+        R.b[i] = T.bbase + (int64_t)brow * T.Kw;
     }
     return R;
 }
@@ -1185,7 +1241,7 @@ __device__ void gemm_tiles_direct(Next next) {
         const GemmChunkD c1 = advance(c0);
         load(c1, An, Bn);
         gemm_chunk_regs(Ac, Bc, msk, acc, c0.kc == c0.T.kw0);
-        if (c0.kc + kChunk >= c0.T.kw1) gemm_epilogue(c0.T, acc);
+        if (c0.kc + kChunk >= c0.T.kw1) gemm_epilogue<2>(c0.T, acc);
         c0 = c1;
         return c0.valid;
     };
@@ -1195,40 +1251,75 @@ __device__ void gemm_tiles_direct(Next next) {
     }
 }
 
-template <bool DIRECT>
-__global__ __launch_bounds__(256, DIRECT ? 2 : 3) void k_gemm_mfma(GemmArgs g) {
-    __shared__ __attribute__((aligned(16))) uint32_t lds[DIRECT ? 1 : kGemmLdsWords];
-    const int64_t ntiles = g.nbatch * g.tiles_m * g.tiles_n * g.ksplit;
-    int64_t t = blockIdx.x;
-    auto next = [&](GemmTileRef &T) {
-        if (t >= ntiles) return false;
-        T = gemm_locate(g, t);
-        t += gridDim.x;
-        return true;
-    };
-    if (DIRECT) gemm_tiles_direct(next);
-    else gemm_tiles(next, lds);
+// Operand paths of the MFMA contraction (GemmArgs::path): 0 stages 128 x 128
+// tiles in LDS, 1 loads straight into registers, 2 stages 256 x 128 tiles
+// (4 x 2 blocks per wave: fewer operand spreads per MFMA, two waves per SIMD).
+constexpr int gemm_occupancy(int path) { return path == 0 ? 3 : 2; }
+constexpr int gemm_lds_of(int path) { return path == 0 ? kGemmLdsWords : path == 2 ? kGemmLdsWordsWide : 1; }
+
+// Tiles of the canonical GEMM on operand path PATH; next(T) yields the tiles.
+template <int PATH, class Next>
+__device__ __forceinline__ void gemm_run(Next next, uint32_t *lds) {
+    if constexpr (PATH == 1) gemm_tiles_direct(next);
+    else gemm_tiles<PATH == 2 ? 4 : 2>(next, lds);
 }
 
-// Workgroups of a persistent tile loop: every CU's worth, capped by the tiles.
-static int64_t gemm_grid(int64_t ntiles, bool direct) {
-    static int cached[2] = {0, 0};
-    if (!cached[direct]) {
+// XCD-aware order of a launch's n tiles.  Workgroups are dispatched to the
+// 8 XCDs round-robin, so with a grid that is a multiple of 8, slot t of the
+// persistent loop (workgroup t % grid) runs on XCD t % 8.  Slot t takes tile
+// (t % 8) * per + t / 8 with per = ceil(n / 8): each XCD runs one contiguous
+// eighth of the tiles, so tiles that write the same output lines (adjacent
+// column tiles) and read the same operand rows meet in one L2 instead of
+// being spread over all eight.  A bijection of [0, 8 per); tiles >= n are
+// skipped.
+__device__ __forceinline__ int64_t xcd_tile(int64_t t, int64_t per) { return (t & 7) * per + (t >> 3); }
+
+template <int PATH>
+__global__ __launch_bounds__(256, gemm_occupancy(PATH)) void k_gemm_mfma(GemmArgs g) {
+    __shared__ __attribute__((aligned(16))) uint32_t lds[gemm_lds_of(PATH)];
+    const int64_t ntiles = g.nbatch * g.tiles_m * g.tiles_n * g.ksplit;
+    const int64_t per = (ntiles + 7) >> 3;
+    int64_t t = blockIdx.x;
+    auto next = [&](GemmTileRef &T) {
+        for (; t < 8 * per; t += gridDim.x) {
+            const int64_t tile = xcd_tile(t, per);
+            if (tile < ntiles) {
+                T = gemm_locate<PATH == 2 ? 4 : 2>(g, tile);
+                t += gridDim.x;
+                return true;
+            }
+        }
+        return false;
+    };
+    gemm_run<PATH>(next, lds);
+}
+
+// Workgroups of a persistent tile loop: every CU's worth (a multiple of 8),
+// capped by the tiles rounded up to a multiple of 8.
+static int64_t gemm_grid(int64_t ntiles, int path) {
+    static int cached[3] = {0, 0, 0};
+    if (!cached[path]) {
         int dev = 0, cus = 256, per_cu = 1;
         if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        const hipError_t e = direct ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_gemm_mfma<true>, 256, 0)
-                                    : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_gemm_mfma<false>, 256, 0);
+        const hipError_t e =
+            path == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_gemm_mfma<1>, 256, 0)
+            : path == 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_gemm_mfma<2>, 256, 0)
+                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_gemm_mfma<0>, 256, 0);
         if (e != hipSuccess || per_cu < 1) per_cu = 1;
-        cached[direct] = cus * per_cu;
+        cached[path] = (cus * per_cu + 7) / 8 * 8;
     }
-    return ntiles < cached[direct] ? ntiles : cached[direct];
+    const int64_t want = (ntiles + 7) / 8 * 8;
+    return want < cached[path] ? want : cached[path];
 }
 
 hipError_t launch_gemm(const GemmArgs &g, hipStream_t s) {
     if (g.nbatch == 0 || g.M == 0 || g.No == 0) return hipSuccess;
+    if (g.path < 0 || g.path > 2) return hipErrorInvalidValue;
     const int64_t nt = g.nbatch * g.tiles_m * g.tiles_n * g.ksplit;
-    if (g.direct) hipLaunchKernelGGL(k_gemm_mfma<true>, dim3((unsigned)gemm_grid(nt, true)), dim3(256), 0, s, g);
-    else hipLaunchKernelGGL(k_gemm_mfma<false>, dim3((unsigned)gemm_grid(nt, false)), dim3(256), 0, s, g);
+    const dim3 grid((unsigned)gemm_grid(nt, g.path));
+    if (g.path == 1) hipLaunchKernelGGL(k_gemm_mfma<1>, grid, dim3(256), 0, s, g);
+    else if (g.path == 2) hipLaunchKernelGGL(k_gemm_mfma<2>, grid, dim3(256), 0, s, g);
+    else hipLaunchKernelGGL(k_gemm_mfma<0>, grid, dim3(256), 0, s, g);
     return hipGetLastError();
 }
 
@@ -1294,14 +1385,16 @@ __device__ __forceinline__ void run_tile(const PStep &st, int64_t tile, uint32_t
             break;
         case kStepGemm: {
             bool once = true;
+            // the persistent executor runs 128 x 128 tiles only (operand
+            // paths 0 and 1; plans for it never use path 2)
             auto next = [&](GemmTileRef &T) {
                 if (!once) return false;
-                T = gemm_locate(st.gemm, tile);
+                T = gemm_locate<2>(st.gemm, tile);
                 once = false;
                 return true;
             };
-            if (st.gemm.direct) gemm_tiles_direct(next);
-            else gemm_tiles(next, lds);
+            if (st.gemm.path == 1) gemm_run<1>(next, lds);
+            else gemm_run<0>(next, lds);
             break;
         }
         case kStepContract: {
@@ -1319,25 +1412,29 @@ __device__ __forceinline__ void run_tile(const PStep &st, int64_t tile, uint32_t
 
 // KIND: a StepKind; for contractions the mode is fixed too (kind 2 + 10 * mode).
 template <int KIND>
-__global__ __launch_bounds__(256, KIND == kStepGemm ? 3 : (KIND == kStepGemm + 10 ? 2 : 1)) void k_group(const PStep *__restrict__ steps, int first, int count, int64_t t0,
-                                               int64_t t1, PlotCounters *counters) {
+__global__ __launch_bounds__(256, KIND % 10 == kStepGemm ? gemm_occupancy(KIND / 10) : 1) void k_group(
+    const PStep *__restrict__ steps, int first, int count, int64_t t0, int64_t t1, PlotCounters *counters) {
     constexpr int kind = KIND % 10, mode = KIND / 10;
-    // MFMA contractions: mode 0 stages K chunks in LDS, mode 1 loads them
-    // straight into each wave's registers
-    constexpr int kWords = kind == kStepGemm ? (mode == 0 ? kGemmLdsWords : 1) : (kind == kStepPlot ? kPlotLdsWords : 1);
+    // MFMA contractions: the mode is the operand path
+    constexpr int kWords = kind == kStepGemm ? gemm_lds_of(mode) : (kind == kStepPlot ? kPlotLdsWords : 1);
     __shared__ __attribute__((aligned(16))) uint32_t lds[kWords];
     if (kind == kStepGemm) {
-        // persistent tile loop with cross-tile prefetch
-        int64_t item = t0 + blockIdx.x;
+        // persistent tile loop with cross-tile prefetch, tiles in XCD-aware order
+        const int64_t per = (t1 - t0 + 7) >> 3;
+        int64_t t = blockIdx.x;
         auto next = [&](GemmTileRef &T) {
-            if (item >= t1) return false;
-            const PStep &st = steps[find_step(steps, first, count, item)];
-            T = gemm_locate(st.gemm, item - st.tile_base);
-            item += gridDim.x;
-            return true;
+            for (; t < 8 * per; t += gridDim.x) {
+                const int64_t item = t0 + xcd_tile(t, per);
+                if (item < t1) {
+                    const PStep &st = steps[find_step(steps, first, count, item)];
+                    T = gemm_locate<mode == 2 ? 4 : 2>(st.gemm, item - st.tile_base);
+                    t += gridDim.x;
+                    return true;
+                }
+            }
+            return false;
         };
-        if (mode == 1) gemm_tiles_direct(next);
-        else gemm_tiles(next, lds);
+        gemm_run<mode>(next, lds);
         return;
     }
     PlotCount cnt;
@@ -1362,12 +1459,14 @@ hipError_t launch_group(int kind, int mode, const PStep *d_steps, int first, int
                         PlotCounters *counters, hipStream_t s) {
     if (t1 <= t0) return hipSuccess;
     const int64_t nt = t1 - t0;
-    const dim3 grid((unsigned)(kind == kStepGemm ? gemm_grid(nt, mode == 1) : (nt < (1 << 20) ? nt : (1 << 20))));
+    if (kind == kStepGemm && (mode < 0 || mode > 2)) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)(kind == kStepGemm ? gemm_grid(nt, mode) : (nt < (1 << 20) ? nt : (1 << 20))));
 #define PA_GROUP(K) hipLaunchKernelGGL(k_group<K>, grid, dim3(256), 0, s, d_steps, first, count, t0, t1, counters)
     switch (kind) {
         case kStepPlot: PA_GROUP(kStepPlot); break;
         case kStepGemm:
             if (mode == 1) PA_GROUP(kStepGemm + 10);
+            else if (mode == 2) PA_GROUP(kStepGemm + 20);
             else PA_GROUP(kStepGemm);
             break;
         case kStepContract:

@@ -319,12 +319,13 @@ struct Builder {
         g.sA_b = g.M * g.Kw;
         g.sB_b = g.No * g.rn * g.Kw;
         g.sC_b = g.M * g.No * g.rwc;
-        g.tiles_m = (g.M + 127) / 128;
+        g.path = P->gemm_path;
+        const int64_t tm = g.path == 2 ? 256 : 128;   // tile rows of the operand path
+        g.tiles_m = (g.M + tm - 1) / tm;
         g.tiles_n = (g.No * g.rwc * 32 + 127) / 128;
         // the K split (and the fill it needs) is set by split_gemms once
         // every step of the tree is known
         set_ksplit(g, 1);
-        g.direct = P->gemm_direct;
         g.fd_tiles_n = make_fastdiv((uint64_t)std::max<int64_t>(1, g.tiles_n));
         g.fd_tiles_m = make_fastdiv((uint64_t)std::max<int64_t>(1, g.tiles_m));
         g.fd_wc = make_fastdiv((uint64_t)(g.rwc * 32));
@@ -533,7 +534,7 @@ std::string Op::describe() const {
       << ",\"c_vars\":" << join(lc.vars) << ",\"macs\":" << macs;
     if (kind == OP_GEMM)
         s << ",\"batch\":" << ga.nbatch << ",\"M\":" << ga.M << ",\"No\":" << ga.No << ",\"rn\":" << ga.rn
-          << ",\"Kw\":" << ga.Kw << ",\"ksplit\":" << ga.ksplit << ",\"direct\":" << ga.direct;
+          << ",\"Kw\":" << ga.Kw << ",\"ksplit\":" << ga.ksplit << ",\"path\":" << ga.path;
     else if (mode == kModeStreamK)
         s << ",\"tq\":" << ca.tq;
     s << "}";
@@ -543,6 +544,11 @@ std::string Op::describe() const {
 // --------------------------------------------------------------- planning
 // Plot tiles: tw words along the packed axis; the rest of the 256 threads
 // spread over ta cells of the fixed axis (n == 3) x tb strips of s walk cells.
+// Operand path of the MFMA kernels for the pa_opts value: 1 (and 0, the
+// default) stages 128 x 128 tiles in LDS, 2 loads straight into registers,
+// 3 stages 256 x 128 tiles.
+static int gemm_path_of(int opt) { return opt == 2 ? 1 : opt == 3 ? 2 : 0; }
+
 // K split of an MFMA contraction: about `want` parts of whole 256-bit
 // chunks, and enough parts that none has more than 16384 K words (a count
 // gains at most 87380 per K word, so the int32 accumulator stays below 2^31).
@@ -651,11 +657,11 @@ int build_plan(const pa_system *sys, const int32_t *exposed, int32_t n_exposed, 
     P->plot_strip = o.plot_strip > 0 ? o.plot_strip : 4;
     P->contract_units = o.contract_units > 0 ? o.contract_units : 2048;
     P->gemm_split = o.gemm_split > 0 ? o.gemm_split : 512;
-    P->gemm_direct = o.gemm_path == 2 ? 1 : 0;
+    P->gemm_path = gemm_path_of(o.gemm_path);
     if (o.precision != PA_PLOT_FP32_ESCALATE && o.precision != PA_PLOT_FP64)
         return fail(PA_EINVAL, "opts: unknown precision");
     if (o.persist_wg < 0 || o.plot_strip < 0 || o.contract_units < 0 || o.gemm_split < 0 || o.gemm_path < 0 ||
-        o.gemm_path > 2)
+        o.gemm_path > 3)
         return fail(PA_EINVAL, "opts: negative tuning parameter");
     switch (o.order_policy) {
         case PA_ORDER_GREEDY: rc = plan_greedy(P->si, P->tree); break;
@@ -805,7 +811,7 @@ static int check_gemm_bounds(const GemmArgs &g, int64_t a_words, int64_t b_words
         return fail(PA_EINVAL, "internal: GEMM would index outside its buffers");
     // the kernels decode tile indices and N coordinates in 32 bits
     const int64_t lim = (int64_t)1 << 31;
-    if (g.nbatch * g.tiles_m * g.tiles_n * g.ksplit >= lim || g.tiles_n * 128 + 128 >= lim || g.M + 128 >= lim ||
+    if (g.nbatch * g.tiles_m * g.tiles_n * g.ksplit >= lim || g.tiles_n * 128 + 128 >= lim || g.M + 256 >= lim ||
         g.Kw >= lim)
         return fail(PA_EUNSUPPORTED, "GEMM too large for one launch");
     return PA_OK;
@@ -860,7 +866,7 @@ static int build_steps(pa_plan *P) {
             int rc = check_gemm_bounds(op.ga, op.la.words, op.lb.words, op.lc.words);
             if (rc) return rc;
             s.kind = kStepGemm;
-            s.mode = op.ga.direct;      // grouped launches: one instantiation per operand path
+            s.mode = op.ga.path;        // grouped launches: one instantiation per operand path
             s.gemm = op.ga;
             s.gemm.A = buf_ptr(P, op.a, nullptr);
             s.gemm.B = buf_ptr(P, op.b, nullptr);
@@ -1589,9 +1595,9 @@ extern "C" int pa_contract(const pa_bitarray *A, const int32_t *a_vars, const pa
             tmp.si.res = res;
             tmp.si.n_vars = PA_MAX_VARS;
             Builder Bd{&tmp, nullptr};
+            tmp.gemm_path = gemm_path_of(opts ? opts->gemm_path : 0);
             Bd.emit_gemm(0, la, 1, lb, kBufOutput, lc, nb, nm, -1);
             tmp.gemm_split = opts && opts->gemm_split > 0 ? opts->gemm_split : 512;
-            tmp.gemm_direct = opts && opts->gemm_path == 2 ? 1 : 0;
             split_gemms(&tmp);
             for (auto &op : tmp.ops) {
                 if (op.kind == OP_FILL) {

@@ -140,7 +140,7 @@ struct pa_plan {
     std::vector<std::pair<int, int>> step_out_refs;   // (step, output index): steps writing a caller's output
     std::vector<int> step_level;              // per sorted step
     int64_t n_items = 0;
-    int per_op = 0, graph = 0, single_launch = 0, persist_wg = 0, plot_strip = 0, contract_units = 0, gemm_split = 512, gemm_direct = 0;
+    int per_op = 0, graph = 0, single_launch = 0, persist_wg = 0, plot_strip = 0, contract_units = 0, gemm_split = 512, gemm_path = 0;
     struct Group {
         int kind, mode, first, count;
         int64_t t0, t1;

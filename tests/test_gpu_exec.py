@@ -55,7 +55,8 @@ def test_executors_agree(si, mode):
                                     dict(gemm_split=1), dict(gemm_split=2048, plot_strip=2),
                                     dict(single_launch=True, gemm_split=1024), dict(gemm_path=2),
                                     dict(gemm_path=2, gemm_split=1), dict(single_launch=True, gemm_path=2),
-                                    dict(gemm_path=2, graph=True, gemm_split=64)])
+                                    dict(gemm_path=2, graph=True, gemm_split=64), dict(gemm_path=3),
+                                    dict(gemm_path=3, gemm_split=1), dict(single_launch=True, gemm_path=3)])
 def test_persistent_tuning_parameters(params):
     for s in SYSTEMS[:4]:
         ref = _oracle_solve(s)

@@ -121,7 +121,7 @@ def test_c2_full_size_exact():
     assert np.array_equal(got, ref)
     got2, _ = _solve(s, plain=True, order=pa.ORDER_GREEDY)
     assert np.array_equal(got2, ref)
-    for kw in (dict(gemm_path=2), dict(gemm_path=2, gemm_split=1), dict(gemm_split=128)):
+    for kw in (dict(gemm_path=2), dict(gemm_path=2, gemm_split=1), dict(gemm_split=128), dict(gemm_path=3)):
         got3, _ = _solve(s, **kw)
         assert np.array_equal(got3, ref), kw
 
@@ -142,6 +142,7 @@ def test_c3_full_size_sampled():
     ref = oracle.solve_entries(res, [r.vars for r in s.relations], plots, s.exposed, ent)
     assert np.array_equal(got[tuple(ent.T)], ref)
     note("c3 nnz", int(got.sum()), "flagged", rep["corners_flagged"])
-    # the other MFMA operand path gives the same array
-    got2, _ = _solve(s, gemm_path=2)
-    assert np.array_equal(got2, got)
+    # the other MFMA operand paths give the same array
+    for path in (2, 3):
+        got2, _ = _solve(s, gemm_path=path)
+        assert np.array_equal(got2, got), path
