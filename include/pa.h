@@ -160,7 +160,10 @@ typedef struct {
                                  workgroup, 128x128 output tiles; 2 = each wave loads
                                  its own rows straight into registers (no LDS, no
                                  barriers); 3 = staged in LDS, 256x128 output tiles
-                                 (4x2 MFMA blocks per wave); 0: default (1)       */
+                                 (4x2 MFMA blocks per wave); 0: default (3 for
+                                 contractions of at least 8192 128x128 tiles, else
+                                 1).  A single persistent launch (single_launch)
+                                 uses 1 in place of 3 and of the default        */
     int32_t verify_order;     /* PA_ORDER_LEARNED, pa_plan_create: 1 = when the model's
                                  tree differs from the exhaustive one, build both,
                                  time each on the device (one untimed and two timed

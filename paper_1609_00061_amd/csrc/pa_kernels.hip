@@ -272,9 +272,11 @@ __device__ void line_coefs(const PlotView &V, const double *cst, double y0, doub
 // are zero and fma(0, x, a) = a exactly).  E is +inf when the line's
 // magnitude bound allows FP32 overflow: then FP64 decides every corner.
 // Otherwise every f is finite (its partial sums stay below 2S <= 2^127) and
-// a corner's FP32 sign is certain iff E - |f| < 0 (f then nonzero).  The
-// sign bits and the certainty bits are shifted into words with one alignbit
-// each (corners taken from 31 down to 0).  Out: LE/GE where the sign is
+// a corner's FP32 sign is certain iff |f| > E (f then nonzero).  The sign
+// bits are shifted into a word with one alignbit each (corners taken from 31
+// down to 0); certainty is first tested for the whole line with the minimum
+// of |f| (two corners per min3), and only a line with some |f| <= E repeats
+// the pass to find its uncertain corners.  Out: LE/GE where the sign is
 // certain, FL the corners FP64 decides.
 // Bits of the 33 corners of a word (corner kk at bit kk of lo, corner 32 in
 // hi): 32-bit operations on the common path.
@@ -302,11 +304,10 @@ __device__ __forceinline__ void line_fp32(const float *ln, const float *xv, cons
         return f;
     };
     const float f32 = value(xv[32]);
-    const uint32_t sg32 = __float_as_uint(f32) >> 31, ok32 = (__float_as_uint(E - fabsf(f32)) >> 31) & valid.hi;
-    uint32_t sg = 0, ok = 0;
-    // four corners at a time, their Horner steps interleaved: one wave per
-    // SIMD is common here, and a single dependent chain would leave the
-    // VALU waiting on each result
+    const uint32_t sg32 = __float_as_uint(f32) >> 31;
+    uint32_t sg = 0;
+    float amin = fabsf(f32);
+    // four corners at a time, their Horner steps interleaved
 #pragma unroll
     for (int kk = 31; kk >= 0; kk -= 4) {
         float f[4];
@@ -317,12 +318,20 @@ __device__ __forceinline__ void line_fp32(const float *ln, const float *xv, cons
 #pragma unroll
             for (int i = 0; i < 4; ++i) f[i] = fmaf(f[i], xv[kk - i], ca[t]);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            sg = __builtin_amdgcn_alignbit(sg, __float_as_uint(f[i]), 31);
-            ok = __builtin_amdgcn_alignbit(ok, __float_as_uint(E - fabsf(f[i])), 31);
-        }
+        for (int i = 0; i < 4; ++i) sg = __builtin_amdgcn_alignbit(sg, __float_as_uint(f[i]), 31);
+        amin = fminf(fminf(amin, fabsf(f[0])), fabsf(f[1]));
+        amin = fminf(fminf(amin, fabsf(f[2])), fabsf(f[3]));
+    }
+    uint32_t ok = ~0u, ok32 = 1u;
+    if (!(amin > E)) {
+        // some corner within the bound: the exact certainty bits
+        ok = 0u;
+#pragma unroll
+        for (int kk = 31; kk >= 0; --kk) ok = __builtin_amdgcn_alignbit(ok, __float_as_uint(E - fabsf(value(xv[kk]))), 31);
+        ok32 = __float_as_uint(E - fabsf(f32)) >> 31;
     }
     ok &= valid.lo;
+    ok32 &= valid.hi;
     LE = {ok & sg, ok32 & sg32};
     GE = {ok & ~sg, ok32 & ~sg32};
     FL = {valid.lo & ~ok, valid.hi & ~ok32};
@@ -395,9 +404,136 @@ __device__ __forceinline__ void eval_line(const PlotView &V, const float *ln, co
     }
 }
 
+// Bivariate plot tile: 4 words x 64 s cell rows.  Wave v takes word
+// 4 t_w + v of every row; lane l takes cell rows b0 + l s .. b0 + l s + s - 1
+// and evaluates the corner lines on top of them (s lines).  The line below
+// its last row is the next lane's first line (shuffled down); for lane 63 it
+// is the tile's last line, which the wave evaluates one corner per lane and
+// collects with ballots.  So every corner line is evaluated once per word
+// (plus the tile's last line, also evaluated by the next tile).  The 33
+// corner coordinates of the word are the same for the whole wave: lane k
+// forms corner k and the wave reads them into scalar registers.
+__device__ void plot_tile2(const PlotRel &R, int64_t tile, float *lines, double *cst, PlotCount &cnt) {
+    const PlotView V = plot_view(R);
+    const CoefPair coefs = load_coefs(V);
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int s = R.s, span = 64 * s;
+    // tile counts are below 2^31 (checked on the host)
+    const uint32_t tiles_w = (uint32_t)R.tiles_w, t = (uint32_t)tile;
+    const int64_t t_w = t % tiles_w, t_walk = t / tiles_w;
+    const int rwalk = V.rwalk, rp = V.rp;
+    const int64_t b0 = t_walk * span;
+    const int64_t w = t_w * 4 + wave;
+    const bool wave_on = w < V.row_words, pad = w * 32 >= rp;
+    const int k0 = (int)(w * 32);
+    const int kmax = (pad || !wave_on) ? 0 : min(32, rp - k0);
+    // lane k < 33: corner k0 + k of the word (FP64, then the nearest float)
+    const int kk_lane = lane < 33 ? lane : 32;
+    const double x64 = corner_coord(V.lop, V.stp, (int64_t)k0 + kk_lane);
+    const float xk = (float)x64;
+    // the tile's corner lines: thread i <= span takes line b0 + i
+    double *cdl = cst + kDense, *ly = cdl + kDense;
+    const int nlines = span + 1;
+    bool lvalid = false;
+    double y0 = 0.0;
+    if (tid < nlines) {
+        lvalid = b0 + tid <= rwalk;
+        if (lvalid) y0 = corner_coord(V.lo0, V.st0, b0 + tid);
+    }
+    store_coefs(V, coefs, cst, cdl);
+    if (tid < nlines) {
+        ly[2 * tid] = y0;
+        ly[2 * tid + 1] = 0.0;
+    }
+    __syncthreads();
+    if (V.mode == PA_PLOT_FP32_ESCALATE && lvalid) line_coefs(V, cst, y0, 0.0, lines + tid * kLineFloats);
+    __syncthreads();
+    if (!wave_on) return;
+    float xv[33];
+#pragma unroll
+    for (int k = 0; k < 33; ++k) xv[k] = __uint_as_float(__builtin_amdgcn_readlane(__float_as_uint(xk), k));
+    // cell masks (cell i: corners i and i + 1) of this lane's own lines
+    uint32_t lcq[2] = {0u, 0u}, gcq[2] = {0u, 0u};
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int L = lane * s + q;
+        if (q < s && !pad && b0 + L <= rwalk) {
+            Corners LE, GE;
+            eval_line(V, lines + L * kLineFloats, xv, ly + 2 * L, cdl, k0, kmax, true, LE, GE, cnt);
+            lcq[q] = LE.lo | __builtin_amdgcn_alignbit(LE.hi, LE.lo, 1);
+            gcq[q] = GE.lo | __builtin_amdgcn_alignbit(GE.hi, GE.lo, 1);
+        }
+    }
+    // the line below this lane's last row
+    uint32_t lcb = (uint32_t)__shfl_down((int)lcq[0], 1), gcb = (uint32_t)__shfl_down((int)gcq[0], 1);
+    if (!pad && b0 + span <= rwalk) {
+        // the tile's last line, one corner per lane (lanes 0..kmax)
+        const bool valid = lane <= kmax;
+        const bool owned_line = b0 + span == rwalk;    // no later tile evaluates it
+        const bool last_word = k0 + kmax == rp;
+        const bool owned = owned_line && (lane < kmax || (lane == kmax && last_word));
+        bool lb = false, gb = false, fl = valid;
+        float f = 0.0f;
+        if (V.mode == PA_PLOT_FP32_ESCALATE) {
+            const float *le = lines + span * kLineFloats;
+            const float E = le[kLineFloats - 1];
+            f = le[kMaxD];
+#pragma unroll
+            for (int tt = kMaxD - 1; tt >= 0; --tt) f = fmaf(f, xk, le[tt]);
+            if (E < INFINITY) {
+                const bool ok = fabsf(f) > E;
+                fl = valid && !ok;
+                lb = valid && ok && f < 0.0f;
+                gb = valid && ok && f > 0.0f;
+            }
+        }
+        const bool todo = (V.mode != PA_PLOT_FP32_ESCALATE || V.audit) ? valid : fl;
+        if (V.mode == PA_PLOT_FP32_ESCALATE && owned_line) {
+            const uint64_t m = __ballot(fl && owned);
+            if (lane == 0) cnt.flagged += __popcll(m);
+        }
+        if (__ballot(todo)) {
+            if (todo) {
+                double xd[3];
+                decl_point(V, ly[2 * span], x64, 0.0, xd);
+                const double f64 = canon_eval(cdl, 2, V.d, xd);
+                if (fl) {
+                    lb = f64 <= 0.0;
+                    gb = f64 >= 0.0;
+                }
+                if (V.mode == PA_PLOT_FP32_ESCALATE && V.audit && owned) {
+                    const int s32 = (f > 0.0f) - (f < 0.0f), s64 = (f64 > 0.0) - (f64 < 0.0);
+                    const bool dis = (s32 != s64) || (f != f) || (f64 != f64);
+                    cnt.dis += dis;
+                    cnt.dis_unf += dis && !fl;
+                }
+            }
+        }
+        const uint64_t lm = __ballot(lb), gm = __ballot(gb);
+        if (lane == 63) {
+            lcb = (uint32_t)(lm | (lm >> 1));
+            gcb = (uint32_t)(gm | (gm >> 1));
+        }
+    }
+    const uint32_t vmask = pad ? 0u : (kmax == 32 ? 0xffffffffu : ((1u << kmax) - 1u));
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int64_t row = b0 + lane * s + q;
+        if (q < s && row < rwalk) {
+            const uint32_t lbot = (q + 1 < s) ? lcq[1] : lcb, gbot = (q + 1 < s) ? gcq[1] : gcb;
+            V.out[row * V.row_words + w] = (lcq[q] | lbot) & (gcq[q] | gbot) & vmask;
+        }
+    }
+}
+
 // One plot tile.  lines: kMaxTileLines * kLineFloats floats of LDS; cst:
 // kDense doubles of LDS.
 __device__ void plot_tile(const PlotRel &R, int64_t tile, float *lines, double *cst, PlotCount &cnt) {
+    if (R.n == 2) {
+        plot_tile2(R, tile, lines, cst, cnt);
+        return;
+    }
     const PlotView V = plot_view(R);
     // the only loads of the tile (coefficients), issued first
     const CoefPair coefs = load_coefs(V);

@@ -144,6 +144,15 @@ struct Choice {
 
 static void set_ksplit(GemmArgs &g, int64_t want);
 
+// Default operand path of one MFMA contraction: 256 x 128 tiles (fewer
+// operand spreads and tile set-ups per MFMA) once the output has at least
+// 8192 tiles of 128 x 128, where the extra tiles in flight cost nothing;
+// 128 x 128 tiles below that, where parallelism matters more.
+static int auto_gemm_path(const GemmArgs &g) {
+    const int64_t tiles = g.nbatch * ((g.M + 127) / 128) * ((g.No * g.rwc * 32 + 127) / 128);
+    return tiles >= 8192 ? 2 : 0;
+}
+
 struct Builder {
     pa_plan *P;
     const pa_system *sys;
@@ -319,7 +328,7 @@ struct Builder {
         g.sA_b = g.M * g.Kw;
         g.sB_b = g.No * g.rn * g.Kw;
         g.sC_b = g.M * g.No * g.rwc;
-        g.path = P->gemm_path;
+        g.path = P->gemm_path >= 0 ? P->gemm_path : auto_gemm_path(g);
         const int64_t tm = g.path == 2 ? 256 : 128;   // tile rows of the operand path
         g.tiles_m = (g.M + tm - 1) / tm;
         g.tiles_n = (g.No * g.rwc * 32 + 127) / 128;
@@ -544,10 +553,10 @@ std::string Op::describe() const {
 // --------------------------------------------------------------- planning
 // Plot tiles: tw words along the packed axis; the rest of the 256 threads
 // spread over ta cells of the fixed axis (n == 3) x tb strips of s walk cells.
-// Operand path of the MFMA kernels for the pa_opts value: 1 (and 0, the
-// default) stages 128 x 128 tiles in LDS, 2 loads straight into registers,
-// 3 stages 256 x 128 tiles.
-static int gemm_path_of(int opt) { return opt == 2 ? 1 : opt == 3 ? 2 : 0; }
+// Operand path of the MFMA kernels for the pa_opts value: 1 stages 128 x 128
+// tiles in LDS, 2 loads straight into registers, 3 stages 256 x 128 tiles;
+// 0 (the default) is -1 here: chosen per contraction by auto_gemm_path.
+static int gemm_path_of(int opt) { return opt == 0 ? -1 : opt == 2 ? 1 : opt == 3 ? 2 : 0; }
 
 // K split of an MFMA contraction: about `want` parts of whole 256-bit
 // chunks, and enough parts that none has more than 16384 K words (a count
@@ -606,6 +615,18 @@ static void split_gemms(pa_plan *P) {
 
 static void plot_tiling(PlotRel &R, int strip) {
     const int n = R.n;
+    if (n == 2) {
+        // 4 words (one per wave) x 64 strips (one per lane) of s <= 2 rows
+        R.tw = 4;
+        R.ta = 1;
+        R.tb = 64;
+        R.s = strip <= 1 ? 1 : 2;
+        R.tiles_w = (R.row_words + 3) / 4;
+        R.tiles_walk = (R.res[0] + 64 * R.s - 1) / (64 * R.s);
+        R.tiles_fixed = 1;
+        R.n_tiles = R.tiles_w * R.tiles_walk;
+        return;
+    }
     R.tw = (int)std::min<int64_t>(32, R.row_words);
     const int ts = 256 / R.tw;
     R.s = std::max(1, strip);
@@ -658,6 +679,8 @@ int build_plan(const pa_system *sys, const int32_t *exposed, int32_t n_exposed, 
     P->contract_units = o.contract_units > 0 ? o.contract_units : 2048;
     P->gemm_split = o.gemm_split > 0 ? o.gemm_split : 512;
     P->gemm_path = gemm_path_of(o.gemm_path);
+    // the single persistent launch runs 128 x 128 tiles only
+    if (P->single_launch && P->gemm_path != 1) P->gemm_path = 0;
     if (o.precision != PA_PLOT_FP32_ESCALATE && o.precision != PA_PLOT_FP64)
         return fail(PA_EINVAL, "opts: unknown precision");
     if (o.persist_wg < 0 || o.plot_strip < 0 || o.contract_units < 0 || o.gemm_split < 0 || o.gemm_path < 0 ||
@@ -1078,6 +1101,9 @@ static int run_persist(pa_plan *P, hipStream_t s, int *launches, hipEvent_t befo
     if (before) HIP_TRY(hipEventRecord(before, s));
     const PStep *d_steps = reinterpret_cast<const PStep *>(base + P->steps_off);
     if (P->single_launch) {
+        for (const PStep &st : P->steps_host)
+            if (st.kind == kStepGemm && st.gemm.path == 2)
+                return fail(PA_EINVAL, "internal: 256-row MFMA tiles in a single persistent launch");
         HIP_TRY(launch_persist(d_steps, nsteps, P->n_items, state, done, cnt, (int)wg, s));
         *launches += 2;
     } else {

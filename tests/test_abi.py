@@ -165,6 +165,24 @@ def test_gemm_split_target_sets_the_k_split():
     assert len(fills(pa.describe_plan(s, gemm_split=1))) == 0
 
 
+def test_mfma_operand_path_choice():
+    """Default operand path: 256 x 128 tiles (path 2 in the plan) for the
+    ternary system's two 65536^2 x 256 contractions (262144 tiles of
+    128 x 128 each), 128 x 128 tiles (path 0) for the chain's 1024^3 ones;
+    gemm_path 1/2/3 force paths 0/1/2; a single persistent launch never
+    uses 256-row tiles; out-of-range values are refused."""
+    paths = lambda d: [o["path"] for o in d["ops"] if o["op"] == "gemm_mfma"]
+    c2, c3 = inputs.config2(res=1024), inputs.config3()
+    assert set(paths(pa.describe_plan(c3))) == {2}
+    assert set(paths(pa.describe_plan(c2))) == {0}
+    for opt, path in ((1, 0), (2, 1), (3, 2)):
+        assert set(paths(pa.describe_plan(c2, gemm_path=opt))) == {path}
+    assert set(paths(pa.describe_plan(c3, single_launch=True))) == {0}
+    assert set(paths(pa.describe_plan(c3, single_launch=True, gemm_path=3))) == {0}
+    assert set(paths(pa.describe_plan(c3, single_launch=True, gemm_path=2))) == {1}
+    assert _bad(inputs.config1(), gemm_path=4) == pa.PA_EINVAL
+
+
 def test_plan_create_rejects_before_touching_the_device():
     s = inputs.config1()
     s.axes = [(-2.0, 2.0, 1)] + s.axes[1:]

@@ -65,6 +65,18 @@ def test_persistent_tuning_parameters(params):
         assert np.array_equal(to_host(out, dims), ref)
 
 
+@pytest.mark.parametrize("kw", [dict(gemm_path=3), dict(single_launch=True, gemm_path=3), dict(gemm_path=3, gemm_split=1)])
+def test_256_row_tiles_cover_every_row(kw):
+    """A chain at 200 per axis (200-row contractions: one partial 256-row
+    tile, two 128-row tiles in the single persistent launch, which keeps
+    128 x 128 tiles)."""
+    s = inputs.config2(res=200)
+    ref = _oracle_solve(s)
+    note("wide tiles", s.name, kw)
+    out, dims, rep = pa.solve_system(s, **kw)
+    assert np.array_equal(to_host(out, dims), ref)
+
+
 @pytest.mark.parametrize("single", [False, True])
 def test_graph_replays_with_eager_work_between(single):
     """Each replay of the captured launch is checked against the oracle, with
