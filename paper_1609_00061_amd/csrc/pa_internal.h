@@ -14,10 +14,10 @@ constexpr int kMaxDim = PA_MAX_DIMS;
 constexpr int kLineFloats = kMaxD + 2;          // a_0..a_d, E per corner line
 constexpr int kMaxTileLines = 160;              // LDS line table capacity of one plot tile
 // LDS of a plot tile: the line table (floats), then as doubles the
-// storage-order and the declared-order coefficient tables and the FP64
-// coordinates (two per line) of the tile's corner lines
+// declared-order coefficient table and the FP64 coordinates (two per line)
+// of the tile's corner lines
 constexpr int kPlotLineWords = (kMaxTileLines * kLineFloats + 1) / 2 * 2;
-constexpr int kPlotLdsWords = kPlotLineWords + 2 * (2 * kDense + 2 * kMaxTileLines);
+constexpr int kPlotLdsWords = kPlotLineWords + 2 * (kDense + 2 * kMaxTileLines);
 static_assert(kMaxTileLines <= 256, "one corner line per thread of a 256-thread plot tile");
 
 // One relation to plot.  The relation's declared variables x_0..x_{n-1} are

@@ -84,12 +84,12 @@ struct PlotCount {
 // axis (n == 3).  A thread owns one 32-cell word of one strip: it evaluates
 // the 33 corners of the word on every corner line bounding its strip (FP32,
 // coordinates held in registers), so a corner line is evaluated once per
-// strip.  The tile first stages the coefficient table (carried by the plot
-// record) in LDS, in storage order and as declared, with the FP64
-// coordinates of its corner lines, and builds the FP32 restriction and bound
-// of each corner line there (FP64, one line per thread).  Corner coordinates
-// are formed from the axis origin and step, not loaded: the record is the
-// only memory a tile reads.
+// strip.  (Bivariate relations use the lane-strip tiles of plot_tile2.)
+// The tile first stages the coefficient table (carried by the plot record,
+// declared order) in LDS with the FP64 coordinates of its corner lines, and
+// builds the FP32 restriction and bound of each corner line there (FP64, one
+// line per thread).  Corner coordinates are formed from the axis origin and
+// step, not loaded: the record is the only memory a tile reads.
 
 // Fields of a relation a tile uses, held in registers (the record itself is
 // in global memory, which the tile's output stores could alias).
@@ -155,39 +155,27 @@ __device__ __forceinline__ void decl_point(const PlotView &V, double s0, double 
     }
 }
 
-// The dense coefficient table for LDS: thread tid < D1^n reads entry tid in
-// storage order, cst[s0 + D1*(s1 + D1*s2)] = coefficient with exponent s_j
-// on storage axis j, and entry tid as it is (declared order), for the
-// canonical FP64 value.  Loaded first, stored after other work.
-struct CoefPair {
-    double st, dl;
-};
-
-__device__ __forceinline__ CoefPair load_coefs(const PlotView &V) {
-    const int D1 = V.d + 1;
-    const int tid = threadIdx.x;
-    const int total = V.n == 1 ? D1 : (V.n == 2 ? D1 * D1 : D1 * D1 * D1);
-    CoefPair c{0.0, 0.0};
-    if (tid < total) {
-        const int s0 = tid % D1, s1 = (tid / D1) % D1, s2 = tid / (D1 * D1);
-        // declared exponent of variable v = storage exponent of the axis holding v
-        const int t1 = V.n > 1 ? s1 : 0, t2 = V.n > 2 ? s2 : 0;
-        const int e0 = (V.perm0 == 0 ? s0 : 0) + (V.n > 1 && V.perm1 == 0 ? t1 : 0) + (V.n > 2 && V.perm2 == 0 ? t2 : 0);
-        const int e1 = (V.perm0 == 1 ? s0 : 0) + (V.n > 1 && V.perm1 == 1 ? t1 : 0) + (V.n > 2 && V.perm2 == 1 ? t2 : 0);
-        const int e2 = (V.perm0 == 2 ? s0 : 0) + (V.n > 1 && V.perm1 == 2 ? t1 : 0) + (V.n > 2 && V.perm2 == 2 ? t2 : 0);
-        c.st = V.coef[e0 + D1 * (e1 + D1 * e2)];
-        c.dl = V.coef[tid];
-    }
-    return c;
+// The dense coefficient table (declared order) for LDS: thread tid < kDense
+// loads entry tid, with no dependence on the record's other fields, so the
+// load is issued at once.  Loaded first, stored after other work.
+__device__ __forceinline__ double load_coefs(const PlotView &V) {
+    return (int)threadIdx.x < kDense ? V.coef[threadIdx.x] : 0.0;
 }
 
-__device__ __forceinline__ void store_coefs(const PlotView &V, const CoefPair &c, double *cst, double *cdl) {
+__device__ __forceinline__ void store_coefs(double c, double *cdl) {
+    if ((int)threadIdx.x < kDense) cdl[threadIdx.x] = c;
+}
+
+// Strides of the storage exponents in the declared-order table: exponent e
+// on storage axis j moves the index by e * D1^perm[j].
+struct CoefStrides {
+    int m0, m1, m2;
+};
+
+__device__ __forceinline__ CoefStrides coef_strides(const PlotView &V) {
     const int D1 = V.d + 1;
-    const int total = V.n == 1 ? D1 : (V.n == 2 ? D1 * D1 : D1 * D1 * D1);
-    if ((int)threadIdx.x < total) {
-        cst[threadIdx.x] = c.st;
-        cdl[threadIdx.x] = c.dl;
-    }
+    auto st = [&](int v) { return v == 0 ? 1 : (v == 1 ? D1 : D1 * D1); };
+    return {st(V.perm0), st(V.perm1), st(V.perm2)};
 }
 
 // Coefficients of the relation restricted to one corner line (storage
@@ -209,8 +197,11 @@ __device__ __forceinline__ void store_coefs(const PlotView &V, const CoefPair &c
 // A corner is escalated unless |p^| > E (E = +inf when S > 2^126, where
 // FP32 could overflow); otherwise |f_exact| > E - gamma S >= |f64 - f_exact|,
 // so sign(p^) = sign(f64) != 0.
-__device__ void line_coefs(const PlotView &V, const double *cst, double y0, double y1, float *dst) {
-    const int n = V.n, d = V.d, D1 = d + 1;
+__device__ void line_coefs(const PlotView &V, const double *cdl, double y0, double y1, float *dst) {
+    const int n = V.n, d = V.d;
+    const CoefStrides M = coef_strides(V);
+    // storage-order entry (e0, e1, e2) of the declared-order table
+    auto cst = [&](int e0, int e1, int e2) { return cdl[e0 * M.m0 + e1 * M.m1 + e2 * M.m2]; };
     const double ay0 = fabs(y0), ay1 = fabs(y1);
     // a_t and s_t as Horner polynomials in y0 (and y1): s_t uses |c| and
     // |y|, whose products are the |terms|; the d + 1 chains are independent
@@ -221,15 +212,15 @@ __device__ void line_coefs(const PlotView &V, const double *cst, double y0, doub
         if (t <= d) {
             const int top = d - t;     // a_t has degree d - t in the other variables
             if (n == 1) {
-                at = cst[t];
+                at = cst(t, 0, 0);
                 st = fabs(at);
             } else if (n == 2) {
-                at = cst[top + D1 * t];
+                at = cst(top, t, 0);
                 st = fabs(at);
 #pragma unroll
                 for (int e0 = kMaxD - 1; e0 >= 0; --e0) {
                     if (e0 < top) {
-                        const double c = cst[e0 + D1 * t];
+                        const double c = cst(e0, t, 0);
                         at = fma(at, y0, c);
                         st = fma(st, ay0, fabs(c));
                     }
@@ -240,11 +231,11 @@ __device__ void line_coefs(const PlotView &V, const double *cst, double y0, doub
                 for (int e1 = kMaxD; e1 >= 0; --e1) {
                     if (e1 <= top) {
                         const int tb = top - e1;
-                        double b = cst[tb + D1 * (e1 + D1 * t)], sb = fabs(b);
+                        double b = cst(tb, e1, t), sb = fabs(b);
 #pragma unroll
                         for (int e0 = kMaxD - 1; e0 >= 0; --e0) {
                             if (e0 < tb) {
-                                const double c = cst[e0 + D1 * (e1 + D1 * t)];
+                                const double c = cst(e0, e1, t);
                                 b = fma(b, y0, c);
                                 sb = fma(sb, ay0, fabs(c));
                             }
@@ -413,9 +404,9 @@ __device__ __forceinline__ void eval_line(const PlotView &V, const float *ln, co
 // (plus the tile's last line, also evaluated by the next tile).  The 33
 // corner coordinates of the word are the same for the whole wave: lane k
 // forms corner k and the wave reads them into scalar registers.
-__device__ void plot_tile2(const PlotRel &R, int64_t tile, float *lines, double *cst, PlotCount &cnt) {
+__device__ void plot_tile2(const PlotRel &R, int64_t tile, float *lines, double *tabs, PlotCount &cnt) {
     const PlotView V = plot_view(R);
-    const CoefPair coefs = load_coefs(V);
+    const double coefs = load_coefs(V);
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int s = R.s, span = 64 * s;
@@ -433,7 +424,7 @@ __device__ void plot_tile2(const PlotRel &R, int64_t tile, float *lines, double 
     const double x64 = corner_coord(V.lop, V.stp, (int64_t)k0 + kk_lane);
     const float xk = (float)x64;
     // the tile's corner lines: thread i <= span takes line b0 + i
-    double *cdl = cst + kDense, *ly = cdl + kDense;
+    double *cdl = tabs, *ly = tabs + kDense;
     const int nlines = span + 1;
     bool lvalid = false;
     double y0 = 0.0;
@@ -441,13 +432,13 @@ __device__ void plot_tile2(const PlotRel &R, int64_t tile, float *lines, double 
         lvalid = b0 + tid <= rwalk;
         if (lvalid) y0 = corner_coord(V.lo0, V.st0, b0 + tid);
     }
-    store_coefs(V, coefs, cst, cdl);
+    store_coefs(coefs, cdl);
     if (tid < nlines) {
         ly[2 * tid] = y0;
         ly[2 * tid + 1] = 0.0;
     }
     __syncthreads();
-    if (V.mode == PA_PLOT_FP32_ESCALATE && lvalid) line_coefs(V, cst, y0, 0.0, lines + tid * kLineFloats);
+    if (V.mode == PA_PLOT_FP32_ESCALATE && lvalid) line_coefs(V, cdl, y0, 0.0, lines + tid * kLineFloats);
     __syncthreads();
     if (!wave_on) return;
     float xv[33];
@@ -527,16 +518,17 @@ __device__ void plot_tile2(const PlotRel &R, int64_t tile, float *lines, double 
     }
 }
 
-// One plot tile.  lines: kMaxTileLines * kLineFloats floats of LDS; cst:
-// kDense doubles of LDS.
-__device__ void plot_tile(const PlotRel &R, int64_t tile, float *lines, double *cst, PlotCount &cnt) {
+// One plot tile.  lines: kMaxTileLines * kLineFloats floats of LDS; tabs:
+// the declared-order coefficient table (kDense doubles of LDS), then the FP64
+// coordinates of the tile's corner lines (two per line).
+__device__ void plot_tile(const PlotRel &R, int64_t tile, float *lines, double *tabs, PlotCount &cnt) {
     if (R.n == 2) {
-        plot_tile2(R, tile, lines, cst, cnt);
+        plot_tile2(R, tile, lines, tabs, cnt);
         return;
     }
     const PlotView V = plot_view(R);
     // the only loads of the tile (coefficients), issued first
-    const CoefPair coefs = load_coefs(V);
+    const double coefs = load_coefs(V);
     const int n = V.n;
     const int tid = threadIdx.x;
     const int tw_n = R.tw, ta = R.ta, tb = R.tb, s = R.s;
@@ -575,7 +567,7 @@ __device__ void plot_tile(const PlotRel &R, int64_t tile, float *lines, double *
     for (int kk = 0; kk < 33; ++kk) xv[kk] = (float)corner_coord(V.lop, V.stp, kb + kk);
     // this thread's corner line (one per thread: lines <= kMaxTileLines <=
     // 256) and its FP64 coordinates
-    double *cdl = cst + kDense, *ly = cdl + kDense;
+    double *cdl = tabs, *ly = tabs + kDense;
     const int nlines = nwl * nfl;
     bool lvalid = false;
     double y0 = 0.0, y1 = 0.0;
@@ -595,13 +587,13 @@ __device__ void plot_tile(const PlotRel &R, int64_t tile, float *lines, double *
             }
         }
     }
-    store_coefs(V, coefs, cst, cdl);
+    store_coefs(coefs, cdl);
     if (tid < nlines) {
         ly[2 * tid] = y0;
         ly[2 * tid + 1] = y1;
     }
     __syncthreads();
-    if (V.mode == PA_PLOT_FP32_ESCALATE && lvalid) line_coefs(V, cst, y0, y1, lines + tid * kLineFloats);
+    if (V.mode == PA_PLOT_FP32_ESCALATE && lvalid) line_coefs(V, cdl, y0, y1, lines + tid * kLineFloats);
     __syncthreads();
     if (!active) return;
     const uint32_t vmask = pad ? 0u : (kmax == 32 ? 0xffffffffu : ((1u << kmax) - 1u));
