@@ -169,6 +169,19 @@ typedef struct {
                                  time each on the device (one untimed and two timed
                                  executions on stream 0, temporary outputs) and keep
                                  the faster; the exhaustive search stays the judge */
+    int32_t sparse_pass;      /* MFMA contractions whose B operand is a plotted
+                                 relation: 1 = always, 0 (default) = when the
+                                 contraction has at least 2^32 MACs, -1 = never,
+                                 get a sparse pass: the relation is also plotted
+                                 with its output variables packed, a count step
+                                 adds up the set bits of A, and if A has at most
+                                 sparse_max_density set bits per 1024 the pass
+                                 computes each output row as the OR of the rows of
+                                 that plot selected by the set bits of the A row
+                                 (and the MFMA kernel exits at once); otherwise the
+                                 MFMA kernel runs (and the pass exits).  Not used by
+                                 the plain path or a single persistent launch.   */
+    int32_t sparse_max_density; /* 0..1024 set bits per 1024 bits of A (0: 64)     */
 } pa_opts;
 
 typedef struct {
@@ -242,7 +255,7 @@ void pa_plan_destroy(pa_plan *plan);
  * eqn naive_cost; 0 for plots and fills).  Waits for the events.  Returns
  * the number of ops, or -1 if the plan does not record op timings. */
 enum { PA_OPKIND_BITS = 0, PA_OPKIND_STREAM_K = 1, PA_OPKIND_STREAM_W = 2, PA_OPKIND_GEMM = 10,
-       PA_OPKIND_FILL = 20, PA_OPKIND_PLOT = 30, PA_OPKIND_PERSIST = 40 };
+       PA_OPKIND_FILL = 20, PA_OPKIND_GATHER = 25, PA_OPKIND_COUNT = 26, PA_OPKIND_PLOT = 30, PA_OPKIND_PERSIST = 40 };
 int32_t pa_plan_op_times(pa_plan *plan, double *ms, int32_t *kind, double *macs, int32_t cap);
 
 /* Kernel duration of every grouped launch of a plan on the default

@@ -140,6 +140,8 @@ struct GemmArgs {
     int64_t tiles_m, tiles_n; // 128-row and 128-column tiles (N in padded coordinates)
     int64_t kchunk;           // words per K split (multiple of 8)
     int ksplit;               // >1: partial results OR-ed with atomics into zeroed C
+    const uint32_t *dense;    // non-null: the tiles run only if *dense != 0, written by the
+                              // contraction's sparse pass when A is too dense for it
     int path;                 // operand path: 0 = K chunks staged in LDS, 128 x 128 tiles;
                               // 1 = waves load K chunks straight into registers (no LDS);
                               // 2 = staged in LDS, 256 x 128 tiles (tiles_m counts 256 rows)
@@ -149,19 +151,50 @@ struct GemmArgs {
 };
 
 
-// One step of the persistent executor: a plot, a GEMM, a contraction or a
-// fill, cut into tiles.  Steps are listed so that every step's producers come
-// earlier; a tile starts once all tiles of the step's producers are done.
-enum StepKind { kStepPlot = 0, kStepGemm = 1, kStepContract = 2, kStepFill = 3 };
+// Sparse pass of a canonical Boolean GEMM (a row gather): output row r =
+// (b, m) is the OR, over the set bits k of A row r, of row k of Bt[b], which
+// holds B with the n variables packed (the layout of an output row).  Bit
+// `bit` of A word w = ko * rwk + wp is k = ko * rkp + 32 wp + bit (ko indexes
+// the latent variables before the packed one, rkp is the packed one's
+// resolution, rwk its row words).  A count step first writes the set bits
+// of A as nparts partial sums (one per wave of its tiles: re-running it
+// changes nothing); the pass runs iff their total is at most max_total (A
+// sparse enough that reading one Bt row per set bit costs less than the
+// MFMA kernel, which runs in the other case: every wave of the pass writes
+// the decision to *dense).  A wave handles 2048 words of one output row.
+struct GatherArgs {
+    const uint32_t *A, *Bt;
+    uint32_t *C;
+    uint32_t *parts, *dense;
+    int64_t nparts;
+    int64_t rows;             // nbatch * M
+    int64_t M, Kw, rwk, rkp, Nw;
+    int64_t sBt_b;            // Bt words per batch entry
+    int64_t chunks;           // 2048-word chunks per output row
+    int64_t max_total;        // the pass runs iff the set bits of A are at most this
+    FastDiv fd_chunks, fd_M;  // divisions of wave-tile indices (below 2^31, host check)
+};
+
+constexpr int64_t kCountTileWords = 65536;   // A words per tile of a count step (4 partial sums)
+
+// Wave-tiles of a sparse pass (2048 words of one output row each).
+__host__ __device__ inline int64_t gather_wave_tiles(const GatherArgs &g) { return g.rows * g.chunks; }
+
+// One step of the persistent executor: a plot, a GEMM, a contraction, a
+// fill or a sparse pass, cut into tiles.  Steps are listed so that every
+// step's producers come earlier; a tile starts once all tiles of the step's
+// producers are done.
+enum StepKind { kStepPlot = 0, kStepGemm = 1, kStepContract = 2, kStepFill = 3, kStepGather = 4, kStepCount = 5 };
 
 struct PStep {
     int kind, mode;
-    int ndep, dep[3];
+    int ndep, dep[4];
     int64_t n_tiles, tile_base;
     int64_t units, per_tile;        // contract: output bits/words; fill: words
     PlotRel plot;
     GemmArgs gemm;
     ContractArgs ca;
+    GatherArgs gather;              // sparse pass: tiles of 4 wave-tiles; count: of kCountTileWords words
     uint32_t *fill_ptr;
 };
 
@@ -176,13 +209,17 @@ hipError_t launch_plot(const PlotRel *d_rels, int nrel, int64_t total_tiles, Plo
                        hipStream_t s);
 hipError_t launch_contract(const ContractArgs &a, int mode, hipStream_t s);
 hipError_t launch_gemm(const GemmArgs &g, hipStream_t s);
+hipError_t launch_gather(const GatherArgs &g, hipStream_t s);
+hipError_t launch_count(const GatherArgs &g, hipStream_t s);
 hipError_t launch_fill(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
 hipError_t launch_popcount(const uint32_t *p, int64_t n, unsigned long long *out, hipStream_t s);
 hipError_t launch_persist(const PStep *d_steps, int nsteps, int64_t n_items, PersistState *state,
                           unsigned int *done, PlotCounters *counters, int n_workgroups, hipStream_t s);
 hipError_t launch_persist_reset(PersistState *state, unsigned int *done, int nsteps, hipStream_t s);
+// Steps first..first+count-1 (tiles t0..t1-1) of one kind; flags: some of the
+// MFMA contractions among them have a sparse pass (and may be skipped).
 hipError_t launch_group(int kind, int mode, const PStep *d_steps, int first, int count, int64_t t0, int64_t t1,
-                        PlotCounters *counters, hipStream_t s);
+                        int flags, PlotCounters *counters, hipStream_t s);
 int persist_default_workgroups();
 
 }  // namespace pa

@@ -928,6 +928,16 @@ hipError_t launch_contract(const ContractArgs &a, int mode, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Whether the sparse pass of a contraction runs: the count step's partial
+// sums add up to at most max_total set bits of A (else the MFMA kernel
+// computes the contraction).  Called by whole waves (a wave reduction).
+__device__ __forceinline__ bool sparse_ran(const uint32_t *parts, int64_t nparts, int64_t max_total) {
+    unsigned long long c = 0;
+    for (int64_t i = __lane_id(); i < nparts; i += 64) c += gp(parts)[i];
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
+    return c <= (unsigned long long)max_total;
+}
+
 // ------------------------------------------------------- MFMA contraction
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
@@ -1405,6 +1415,8 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t t, int64_t per) { return (t 
 template <int PATH>
 __global__ __launch_bounds__(256, gemm_occupancy(PATH)) void k_gemm_mfma(GemmArgs g) {
     __shared__ __attribute__((aligned(16))) uint32_t lds[gemm_lds_of(PATH)];
+    // when the sparse pass ran (A sparse enough) there is nothing to do
+    if (g.dense && __hip_atomic_load(gp(g.dense), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u) return;
     const int64_t ntiles = g.nbatch * g.tiles_m * g.tiles_n * g.ksplit;
     const int64_t per = (ntiles + 7) >> 3;
     int64_t t = blockIdx.x;
@@ -1448,6 +1460,139 @@ hipError_t launch_gemm(const GemmArgs &g, hipStream_t s) {
     if (g.path == 1) hipLaunchKernelGGL(k_gemm_mfma<1>, grid, dim3(256), 0, s, g);
     else if (g.path == 2) hipLaunchKernelGGL(k_gemm_mfma<2>, grid, dim3(256), 0, s, g);
     else hipLaunchKernelGGL(k_gemm_mfma<0>, grid, dim3(256), 0, s, g);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------- sparse pass
+// Four words of a row of n words starting at word c (c and n even: pairs are
+// 8-byte aligned; with vec4 the row and c are 16-byte aligned).
+__device__ __forceinline__ uint4 load_words4(const PA_G uint32_t *p, int64_t c, int64_t n, bool vec4) {
+    uint4 v = make_uint4(0u, 0u, 0u, 0u);
+    if (c + 3 < n) {
+        if (vec4) {
+            const u32x4 t = *reinterpret_cast<const PA_G u32x4 *>(p + c);
+            v = make_uint4(t.x, t.y, t.z, t.w);
+        } else {
+            const u32x2 t0 = *reinterpret_cast<const PA_G u32x2 *>(p + c);
+            const u32x2 t1 = *reinterpret_cast<const PA_G u32x2 *>(p + c + 2);
+            v = make_uint4(t0.x, t0.y, t1.x, t1.y);
+        }
+    } else if (c < n) {
+        const u32x2 t0 = *reinterpret_cast<const PA_G u32x2 *>(p + c);
+        v.x = t0.x;
+        v.y = t0.y;
+    }
+    return v;
+}
+
+__device__ __forceinline__ void store_words4(PA_G uint32_t *p, int64_t c, int64_t n, bool vec4, uint4 v) {
+    if (c + 3 < n) {
+        if (vec4) {
+            *reinterpret_cast<PA_G u32x4 *>(p + c) = u32x4{v.x, v.y, v.z, v.w};
+        } else {
+            *reinterpret_cast<PA_G u32x2 *>(p + c) = u32x2{v.x, v.y};
+            *reinterpret_cast<PA_G u32x2 *>(p + c + 2) = u32x2{v.z, v.w};
+        }
+    } else if (c < n) {
+        *reinterpret_cast<PA_G u32x2 *>(p + c) = u32x2{v.x, v.y};
+    }
+}
+
+// Count step, tile t: the set bits of A words [t K, (t + 1) K) (K =
+// kCountTileWords), one partial sum per wave stored at parts[4 t + wave].
+__device__ void count_tile(const GatherArgs &g, int64_t t) {
+    const int64_t u0 = t * kCountTileWords, u1 = min(g.rows * g.Kw, u0 + kCountTileWords);
+    uint32_t c = 0;
+    const PA_G uint32_t *a = gp(g.A);
+    for (int64_t i = u0 + threadIdx.x; i < u1; i += blockDim.x) c += __popc(a[i]);
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_down(c, off);
+    if ((threadIdx.x & 63) == 0) gp(g.parts)[4 * t + (threadIdx.x >> 6)] = c;
+}
+
+// One wave-tile of the sparse pass: words ch * 2048 .. + 2047 of output row
+// `row`; lane l holds words 4l + 256 j (j < 8).  The A row is read by the
+// whole wave (uniform), its set bits walked in order, and for each the
+// matching 2048 words of Bt OR-ed in (eight independent 16-byte loads per
+// lane).
+__device__ void gather_wave(const GatherArgs &g, int64_t wt) {
+    const int lane = threadIdx.x & 63;
+    const uint32_t row = fdiv((uint32_t)wt, g.fd_chunks);
+    const uint32_t ch = (uint32_t)wt - row * (uint32_t)g.chunks;
+    const uint32_t b = fdiv(row, g.fd_M);
+    const PA_G uint32_t *arow = gp(g.A) + (int64_t)row * g.Kw;
+    const int64_t n = g.Nw;
+    const bool vec4 = (n & 3) == 0;
+    const int64_t c0 = (int64_t)ch * 2048 + 4 * lane;
+    uint4 acc[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc[j] = make_uint4(0u, 0u, 0u, 0u);
+    const PA_G uint32_t *bt = gp(g.Bt) + (int64_t)b * g.sBt_b;
+    PA_G uint32_t *crow = gp(g.C) + (int64_t)row * n;
+    const int64_t kouters = g.Kw / g.rwk;
+    int64_t w = 0;
+    for (int64_t ko = 0; ko < kouters; ++ko) {
+        for (int64_t wp = 0; wp < g.rwk; ++wp, ++w) {
+            uint32_t bits = arow[w];
+            while (bits) {
+                const int bit = __ffs((int)bits) - 1;
+                bits &= bits - 1;
+                if (32 * wp + bit >= g.rkp) break;     // padding bits (zero in every array) end the word
+                const PA_G uint32_t *src = bt + (ko * g.rkp + 32 * wp + bit) * n;
+                uint4 v[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) v[j] = load_words4(src, c0 + 256 * j, n, vec4);
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    acc[j].x |= v[j].x;
+                    acc[j].y |= v[j].y;
+                    acc[j].z |= v[j].z;
+                    acc[j].w |= v[j].w;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) store_words4(crow, c0 + 256 * j, n, vec4, acc[j]);
+}
+
+// Stand-alone sparse pass: workgroups of four wave-tiles, grid-stride.
+// The decision of a wave of the sparse pass; the wave of wave-tile 0 also
+// writes it for the MFMA kernel of the contraction (one store: thousands of
+// stores to one word would serialize at the memory side).
+__device__ __forceinline__ bool gather_decide(const GatherArgs &g, int64_t wt) {
+    const bool run = sparse_ran(g.parts, g.nparts, g.max_total);
+    if (wt == 0 && __lane_id() == 0) gp(g.dense)[0] = run ? 0u : 1u;
+    return run;
+}
+
+__global__ __launch_bounds__(256) void k_gather(GatherArgs g, int64_t ntiles) {
+    const int wave0 = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    if (!gather_decide(g, blockIdx.x * 4 + wave0)) return;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int64_t nw = gather_wave_tiles(g);
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int64_t wt = t * 4 + wave;
+        if (wt < nw) gather_wave(g, wt);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_count(GatherArgs g, int64_t ntiles) {
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) count_tile(g, t);
+}
+
+hipError_t launch_count(const GatherArgs &g, hipStream_t s) {
+    const int64_t nt = (g.rows * g.Kw + kCountTileWords - 1) / kCountTileWords;
+    if (nt <= 0) return hipSuccess;
+    const int64_t blocks = nt < (1 << 20) ? nt : (1 << 20);
+    hipLaunchKernelGGL(k_count, dim3((unsigned)blocks), dim3(256), 0, s, g, nt);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather(const GatherArgs &g, hipStream_t s) {
+    const int64_t nt = (gather_wave_tiles(g) + 3) / 4;
+    if (nt <= 0) return hipSuccess;
+    const int64_t blocks = nt < (1 << 20) ? nt : (1 << 20);
+    hipLaunchKernelGGL(k_gather, dim3((unsigned)blocks), dim3(256), 0, s, g, nt);
     return hipGetLastError();
 }
 
@@ -1541,12 +1686,25 @@ __device__ __forceinline__ void run_tile(const PStep &st, int64_t tile, uint32_t
 // KIND: a StepKind; for contractions the mode is fixed too (kind 2 + 10 * mode).
 template <int KIND>
 __global__ __launch_bounds__(256, KIND % 10 == kStepGemm ? gemm_occupancy(KIND / 10) : 1) void k_group(
-    const PStep *__restrict__ steps, int first, int count, int64_t t0, int64_t t1, PlotCounters *counters) {
+    const PStep *__restrict__ steps, int first, int count, int64_t t0, int64_t t1, int flags,
+    PlotCounters *counters) {
     constexpr int kind = KIND % 10, mode = KIND / 10;
     // MFMA contractions: the mode is the operand path
     constexpr int kWords = kind == kStepGemm ? gemm_lds_of(mode) : (kind == kStepPlot ? kPlotLdsWords : 1);
     __shared__ __attribute__((aligned(16))) uint32_t lds[kWords];
     if (kind == kStepGemm) {
+        // with `flags`, a contraction whose sparse pass handled every row is
+        // skipped: lane i reads the flag of step first + i (at most 64 steps;
+        // with more, every contraction runs: it writes the same bits)
+        uint64_t active = ~0ull;
+        if (flags && count <= 64) {
+            const int lane = __lane_id();
+            const uint32_t *dn = lane < count ? steps[first + lane].gemm.dense : nullptr;
+            const bool on =
+                lane < count && (!dn || __hip_atomic_load(gp(dn), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u);
+            active = __ballot(on);
+            if (active == 0) return;
+        }
         // persistent tile loop with cross-tile prefetch, tiles in XCD-aware order
         const int64_t per = (t1 - t0 + 7) >> 3;
         int64_t t = blockIdx.x;
@@ -1554,7 +1712,9 @@ __global__ __launch_bounds__(256, KIND % 10 == kStepGemm ? gemm_occupancy(KIND /
             for (; t < 8 * per; t += gridDim.x) {
                 const int64_t item = t0 + xcd_tile(t, per);
                 if (item < t1) {
-                    const PStep &st = steps[find_step(steps, first, count, item)];
+                    const int si = find_step(steps, first, count, item);
+                    if (!((active >> ((si - first) & 63)) & 1)) continue;
+                    const PStep &st = steps[si];
                     T = gemm_locate<mode == 2 ? 4 : 2>(st.gemm, item - st.tile_base);
                     t += gridDim.x;
                     return true;
@@ -1574,6 +1734,12 @@ __global__ __launch_bounds__(256, KIND % 10 == kStepGemm ? gemm_occupancy(KIND /
         } else if (kind == kStepContract) {
             const int64_t u0 = (item - st.tile_base) * st.per_tile;
             contract_range<mode>(st.ca, u0, min(st.units, u0 + st.per_tile));
+        } else if (kind == kStepGather) {
+            const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+            const int64_t wt = (item - st.tile_base) * 4 + wave;
+            if (wt < gather_wave_tiles(st.gather) && gather_decide(st.gather, wt)) gather_wave(st.gather, wt);
+        } else if (kind == kStepCount) {
+            count_tile(st.gather, item - st.tile_base);
         } else {
             const int64_t u0 = (item - st.tile_base) * st.per_tile, u1 = min(st.units, u0 + st.per_tile);
             for (int64_t i = u0 + threadIdx.x; i < u1; i += blockDim.x) gp(st.fill_ptr)[i] = 0u;
@@ -1584,12 +1750,12 @@ __global__ __launch_bounds__(256, KIND % 10 == kStepGemm ? gemm_occupancy(KIND /
 }
 
 hipError_t launch_group(int kind, int mode, const PStep *d_steps, int first, int count, int64_t t0, int64_t t1,
-                        PlotCounters *counters, hipStream_t s) {
+                        int flags, PlotCounters *counters, hipStream_t s) {
     if (t1 <= t0) return hipSuccess;
     const int64_t nt = t1 - t0;
     if (kind == kStepGemm && (mode < 0 || mode > 2)) return hipErrorInvalidValue;
     const dim3 grid((unsigned)(kind == kStepGemm ? gemm_grid(nt, mode) : (nt < (1 << 20) ? nt : (1 << 20))));
-#define PA_GROUP(K) hipLaunchKernelGGL(k_group<K>, grid, dim3(256), 0, s, d_steps, first, count, t0, t1, counters)
+#define PA_GROUP(K) hipLaunchKernelGGL(k_group<K>, grid, dim3(256), 0, s, d_steps, first, count, t0, t1, flags, counters)
     switch (kind) {
         case kStepPlot: PA_GROUP(kStepPlot); break;
         case kStepGemm:
@@ -1602,6 +1768,8 @@ hipError_t launch_group(int kind, int mode, const PStep *d_steps, int first, int
             else if (mode == kModeStreamW) PA_GROUP(kStepContract + 10 * kModeStreamW);
             else PA_GROUP(kStepContract + 10 * kModeBits);
             break;
+        case kStepGather: PA_GROUP(kStepGather); break;
+        case kStepCount: PA_GROUP(kStepCount); break;
         default: PA_GROUP(kStepFill); break;
     }
 #undef PA_GROUP

@@ -341,6 +341,79 @@ struct Builder {
         P->ops.push_back(op);
     }
 
+    // An MFMA contraction with a sparse pass, when B is a plotted relation and
+    // the pass is enabled for the contraction's size: the relation is plotted
+    // a second time as Bt = [batch vars, latent vars in A's order, output n
+    // vars in C's order] (rows of Bt have C's row layout); a two-word counter
+    // is zeroed, a count step adds up the set bits of A, and then either the
+    // pass (at most sparse_max_density set bits per 1024 bits of A) or the
+    // MFMA kernel computes the output; the other exits at once.
+    void emit_gemm_with_pass(int a, const Layout &la, int b, const Layout &lb, int bnode, int c, const Layout &lc,
+                             int nb, int nm, int node) {
+        const Node &bn = P->tree.nodes[bnode];
+        const bool b_plot = bn.leaf >= 0 && !(P->si.rel_vars[bn.leaf] & ~bn.q);
+        const double macs = mask_cost(list_mask(la.vars) | list_mask(lb.vars), P->si);
+        const bool use = b_plot && P->sparse_pass >= 0 && (P->sparse_pass == 1 || macs >= 4294967296.0);
+        if (!use) {
+            emit_gemm(a, la, b, lb, c, lc, nb, nm, node);
+            return;
+        }
+        std::vector<int> order(lc.vars.begin(), lc.vars.begin() + nb);
+        order.insert(order.end(), la.vars.begin() + nb + nm, la.vars.end());
+        order.insert(order.end(), lc.vars.begin() + nb + nm, lc.vars.end());
+        const int bt = plot_leaf(bn.leaf, order);
+        GatherArgs ga{};
+        int64_t nbatch = 1, M = 1, kout = 1, kall = 1, nout = 1;
+        for (int i = 0; i < nb; ++i) nbatch *= lc.dims[i];
+        for (int i = nb; i < nb + nm; ++i) M *= lc.dims[i];
+        for (size_t i = nb + nm; i < la.vars.size(); ++i) {
+            kall *= la.dims[i];
+            if (i + 1 < la.vars.size()) kout *= la.dims[i];
+        }
+        for (size_t i = nb + nm; i + 1 < lc.vars.size(); ++i) nout *= lc.dims[i];
+        ga.rows = nbatch * M;
+        ga.M = M;
+        ga.rwk = la.rw;
+        ga.Kw = kout * la.rw;
+        ga.rkp = la.dims.back();
+        ga.Nw = nout * lc.rw;
+        ga.sBt_b = kall * ga.Nw;
+        ga.chunks = (ga.Nw + 2047) / 2048;
+        // bits of A (rows x latent entries) times the density threshold
+        ga.max_total = (int64_t)std::floor((double)ga.rows * (double)kall * P->sparse_max_density / 1024.0);
+        ga.fd_chunks = make_fastdiv((uint64_t)std::max<int64_t>(1, ga.chunks));
+        ga.fd_M = make_fastdiv((uint64_t)std::max<int64_t>(1, M));
+        // the count's partial sums: four per tile of kCountTileWords words of A
+        ga.nparts = 4 * ((ga.rows * ga.Kw + kCountTileWords - 1) / kCountTileWords);
+        Layout cl;            // the partial sums, then the decision word
+        cl.rw = (ga.nparts + 2) / 2 * 2;
+        cl.words = cl.rw;
+        const int flag = new_buf(cl);
+        Op k;
+        k.kind = OP_COUNT;
+        k.a = a;
+        k.flag = flag;
+        k.la = la;
+        k.node = node;
+        k.gg = ga;
+        P->ops.push_back(k);
+        Op g;
+        g.kind = OP_GATHER;
+        g.a = a;
+        g.b = bt;
+        g.c = c;
+        g.flag = flag;
+        g.la = la;
+        g.lb = P->buf_layout[bt];
+        g.lc = lc;
+        g.node = node;
+        g.gg = ga;
+        P->ops.push_back(g);
+        emit_gemm(a, la, b, lb, c, lc, nb, nm, node);
+        P->ops.back().flag = flag;
+
+    }
+
     int plot_leaf(int r, const std::vector<int> &order) {
         const auto &decl = P->si.rel_list[r];
         PlotItem it;
@@ -397,8 +470,8 @@ struct Builder {
         Layout lc = lay(ch.oc);
         const int dst = (out_buf == -1) ? new_buf(lc) : out_buf;
         if (ch.kind == 0) {
-            if (ch.roleB) emit_gemm(bx, lx, by, ly, dst, lc, ch.nb, ch.nm, id);
-            else emit_gemm(by, ly, bx, lx, dst, lc, ch.nb, ch.nm, id);
+            if (ch.roleB) emit_gemm_with_pass(bx, lx, by, ly, nd.c1, dst, lc, ch.nb, ch.nm, id);
+            else emit_gemm_with_pass(by, ly, bx, lx, nd.c0, dst, lc, ch.nb, ch.nm, id);
         } else {
             emit_contract(bx, lx, by, &ly, dst, lc, id);
         }
@@ -538,12 +611,23 @@ std::string Op::describe() const {
         s << "{\"op\":\"fill\",\"buf\":" << c << ",\"words\":" << fill_words << "}";
         return s.str();
     }
+    if (kind == OP_COUNT) {
+        s << "{\"op\":\"sparse_count\",\"a\":" << a << ",\"flag\":" << flag << ",\"words\":" << gg.rows * gg.Kw << "}";
+        return s.str();
+    }
+    if (kind == OP_GATHER) {
+        s << "{\"op\":\"sparse_pass\",\"a\":" << a << ",\"bt\":" << b << ",\"c\":" << c << ",\"flag\":" << flag
+          << ",\"a_vars\":" << join(la.vars) << ",\"bt_vars\":" << join(lb.vars) << ",\"c_vars\":" << join(lc.vars)
+          << ",\"rows\":" << gg.rows << ",\"Kw\":" << gg.Kw << ",\"Nw\":" << gg.Nw
+          << ",\"max_total\":" << gg.max_total << "}";
+        return s.str();
+    }
     s << "{\"op\":\"" << (kind == OP_GEMM ? "gemm_mfma" : names[mode]) << "\",\"a\":" << a << ",\"b\":" << b
       << ",\"c\":" << c << ",\"a_vars\":" << join(la.vars) << ",\"b_vars\":" << join(lb.vars)
       << ",\"c_vars\":" << join(lc.vars) << ",\"macs\":" << macs;
     if (kind == OP_GEMM)
         s << ",\"batch\":" << ga.nbatch << ",\"M\":" << ga.M << ",\"No\":" << ga.No << ",\"rn\":" << ga.rn
-          << ",\"Kw\":" << ga.Kw << ",\"ksplit\":" << ga.ksplit << ",\"path\":" << ga.path;
+          << ",\"Kw\":" << ga.Kw << ",\"ksplit\":" << ga.ksplit << ",\"path\":" << ga.path << ",\"flag\":" << flag;
     else if (mode == kModeStreamK)
         s << ",\"tq\":" << ca.tq;
     s << "}";
@@ -585,12 +669,15 @@ static void split_gemms(pa_plan *P) {
     for (size_t i = 0; i < P->ops.size(); ++i) {
         const Op &op = P->ops[i];
         int lv = 0;
-        for (int b : {op.a, op.b}) {
+        // the steps of a sparse pass and its MFMA contraction read the counter
+        for (int b : {op.a, op.b, op.kind == OP_FILL ? -1 : op.flag}) {
+            if (b < 0 && b != kBufOutput) continue;
             auto it = level_of_buf.find(b);
             if (it != level_of_buf.end()) lv = std::max(lv, it->second + 1);
         }
         level[i] = lv;
-        level_of_buf[op.c] = lv;
+        if (op.c >= 0 || op.c == kBufOutput) level_of_buf[op.c] = lv;
+        if ((op.kind == OP_COUNT || op.kind == OP_GATHER) && op.flag >= 0) level_of_buf[op.flag] = lv;
         if (op.kind == OP_GEMM) tiles_at[lv] += op.ga.nbatch * op.ga.tiles_m * op.ga.tiles_n;
     }
     std::vector<Op> ops;
@@ -605,7 +692,12 @@ static void split_gemms(pa_plan *P) {
                 f.c = op.c;
                 f.fill_words = op.lc.words;
                 f.node = op.node;
-                ops.push_back(f);
+                // the sparse pass writing the same output (just before) runs
+                // after the zeroing
+                if (op.flag >= 0 && !ops.empty() && ops.back().kind == OP_GATHER && ops.back().c == op.c)
+                    ops.insert(ops.end() - 1, f);
+                else
+                    ops.push_back(f);
             }
         }
         ops.push_back(op);
@@ -681,6 +773,11 @@ int build_plan(const pa_system *sys, const int32_t *exposed, int32_t n_exposed, 
     P->gemm_path = gemm_path_of(o.gemm_path);
     // the single persistent launch runs 128 x 128 tiles only
     if (P->single_launch && P->gemm_path != 1) P->gemm_path = 0;
+    // the sparse pass: not in the plain path nor in a single persistent launch
+    P->sparse_pass = (P->plain || P->single_launch) ? -1 : o.sparse_pass;
+    P->sparse_max_density = o.sparse_max_density > 0 ? o.sparse_max_density : 64;
+    if (o.sparse_pass < -1 || o.sparse_pass > 1 || o.sparse_max_density < 0 || o.sparse_max_density > 1024)
+        return fail(PA_EINVAL, "opts: sparse_pass must be -1, 0 or 1 and sparse_max_density 0..1024");
     if (o.precision != PA_PLOT_FP32_ESCALATE && o.precision != PA_PLOT_FP64)
         return fail(PA_EINVAL, "opts: unknown precision");
     if (o.persist_wg < 0 || o.plot_strip < 0 || o.contract_units < 0 || o.gemm_split < 0 || o.gemm_path < 0 ||
@@ -840,6 +937,26 @@ static int check_gemm_bounds(const GemmArgs &g, int64_t a_words, int64_t b_words
     return PA_OK;
 }
 
+// Buffer sizes of a count step (bt_words, c_words < 0) or a sparse pass.
+static int check_gather_bounds(const GatherArgs &g, int64_t a_words, int64_t bt_words, int64_t c_words) {
+    const bool pass = bt_words >= 0;
+    if (g.rows < 1 || g.M < 1 || g.rwk < 2 || g.Kw % g.rwk || g.rkp < 1 || g.rkp > 32 * g.rwk || g.Nw < 2 ||
+        g.Nw % 2 || g.rows * g.Kw > a_words || (pass && g.rows * g.Nw > c_words) ||
+        (pass && (g.rows / g.M) * g.sBt_b > bt_words) || g.sBt_b != (g.Kw / g.rwk) * g.rkp * g.Nw)
+        return fail(PA_EINVAL, "internal: sparse pass would index outside its buffers");
+    // wave-tile indices and rows are divided in 32 bits
+    if (g.rows * g.chunks >= ((int64_t)1 << 31)) return fail(PA_EUNSUPPORTED, "sparse pass too large for one launch");
+    return PA_OK;
+}
+
+// Partial sums in the count buffer `buf` of a sparse pass (the decision word
+// follows them).
+static int64_t sparse_nparts_of(const pa_plan *P, int buf) {
+    for (const Op &op : P->ops)
+        if (op.kind == OP_COUNT && op.flag == buf) return op.gg.nparts;
+    return 0;
+}
+
 static uint32_t *buf_ptr(pa_plan *P, int id, void *out) {
     if (id == kBufOutput) return static_cast<uint32_t *>(out);
     if (id < 0) return nullptr;
@@ -885,6 +1002,27 @@ static int build_steps(pa_plan *P) {
             s.n_tiles = (s.units + s.per_tile - 1) / s.per_tile;
             fill_for_next = (int)st.size();
             if (op.c == kBufOutput) out_refs.push_back((int)st.size());
+        } else if (op.kind == OP_COUNT || op.kind == OP_GATHER) {
+            const bool pass = op.kind == OP_GATHER;
+            int rc = check_gather_bounds(op.gg, op.la.words, pass ? op.lb.words : -1, pass ? op.lc.words : -1);
+            if (rc) return rc;
+            s.kind = pass ? kStepGather : kStepCount;
+            s.gather = op.gg;
+            s.gather.A = buf_ptr(P, op.a, nullptr);
+            s.gather.Bt = pass ? buf_ptr(P, op.b, nullptr) : nullptr;
+            s.gather.C = pass ? buf_ptr(P, op.c, nullptr) : nullptr;
+            s.gather.parts = buf_ptr(P, op.flag, nullptr);
+            s.gather.dense = s.gather.parts + op.gg.nparts;
+            s.n_tiles = pass ? (gather_wave_tiles(op.gg) + 3) / 4
+                             : (op.gg.rows * op.gg.Kw + kCountTileWords - 1) / kCountTileWords;
+            dep(op.a);
+            if (pass) {
+                dep(op.flag);       // the count
+                dep(op.b);
+                dep(op.c);          // the zeroing of a split contraction's output
+                if (op.c == kBufOutput) out_refs.push_back((int)st.size());
+            }
+            producer[op.flag] = (int)st.size();
         } else if (op.kind == OP_GEMM) {
             int rc = check_gemm_bounds(op.ga, op.la.words, op.lb.words, op.lc.words);
             if (rc) return rc;
@@ -894,9 +1032,11 @@ static int build_steps(pa_plan *P) {
             s.gemm.A = buf_ptr(P, op.a, nullptr);
             s.gemm.B = buf_ptr(P, op.b, nullptr);
             s.gemm.C = buf_ptr(P, op.c, nullptr);
+            s.gemm.dense = op.flag >= 0 ? buf_ptr(P, op.flag, nullptr) + sparse_nparts_of(P, op.flag) : nullptr;
             s.n_tiles = op.ga.nbatch * op.ga.tiles_m * op.ga.tiles_n * op.ga.ksplit;
             dep(op.a);
             dep(op.b);
+            if (op.flag >= 0) dep(op.flag);
             if (op.ga.ksplit > 1 && fill_for_next >= 0) {
                 s.dep[s.ndep++] = fill_for_next;
                 lv = std::max(lv, level[fill_for_next] + 1);
@@ -930,7 +1070,7 @@ static int build_steps(pa_plan *P) {
             dep(op.b);
             if (op.c == kBufOutput) out_refs.push_back((int)st.size());
         }
-        if (op.kind != OP_FILL) producer[op.c] = (int)st.size();
+        if (op.c >= 0 || op.c == kBufOutput) producer[op.c] = (int)st.size();   // fills too: a sparse pass waits for its zeroing
         st.push_back(s);
         level.push_back(lv);
     }
@@ -974,11 +1114,13 @@ void make_groups(pa_plan *P) {
         const bool same_level = i > 0 && P->step_level[i] == P->step_level[i - 1];
         const bool same = same_level && ((x.kind == P->steps_host[i - 1].kind && x.mode == P->steps_host[i - 1].mode) ||
                                          (x.kind == kStepFill && P->groups.back().kind == kStepPlot));
+        const int flags = x.kind == kStepGemm && x.gemm.dense != nullptr;
         if (same) {
             P->groups.back().count += 1;
             P->groups.back().t1 = x.tile_base + x.n_tiles;
+            P->groups.back().flags |= flags;
         } else {
-            P->groups.push_back({x.kind, x.mode, (int)i, 1, x.tile_base, x.tile_base + x.n_tiles});
+            P->groups.push_back({x.kind, x.mode, (int)i, 1, x.tile_base, x.tile_base + x.n_tiles, flags});
         }
     }
 }
@@ -989,6 +1131,7 @@ static void patch_outputs(pa_plan *P, const std::vector<void *> &outs) {
         uint32_t *o = static_cast<uint32_t *>(outs[ref.second]);
         if (s.kind == kStepGemm) s.gemm.C = o;
         else if (s.kind == kStepContract) s.ca.C = o;
+        else if (s.kind == kStepGather) s.gather.C = o;
         else if (s.kind == kStepFill) s.fill_ptr = o;
     }
 }
@@ -1047,7 +1190,20 @@ static int run_ops(pa_plan *P, void *out, hipStream_t s, int *launches) {
             g.A = buf_ptr(P, op0.a, out);
             g.B = buf_ptr(P, op0.b, out);
             g.C = buf_ptr(P, op0.c, out);
+            g.dense = op0.flag >= 0 ? buf_ptr(P, op0.flag, out) + sparse_nparts_of(P, op0.flag) : nullptr;
             HIP_TRY(launch_gemm(g, s));
+            ++*launches;
+        } else if (op0.kind == OP_COUNT || op0.kind == OP_GATHER) {
+            const bool pass = op0.kind == OP_GATHER;
+            GatherArgs g = op0.gg;
+            int rc = check_gather_bounds(g, op0.la.words, pass ? op0.lb.words : -1, pass ? op0.lc.words : -1);
+            if (rc) return rc;
+            g.A = buf_ptr(P, op0.a, out);
+            g.Bt = pass ? buf_ptr(P, op0.b, out) : nullptr;
+            g.C = pass ? buf_ptr(P, op0.c, out) : nullptr;
+            g.parts = buf_ptr(P, op0.flag, out);
+            g.dense = g.parts + g.nparts;
+            HIP_TRY(pass ? launch_gather(g, s) : launch_count(g, s));
             ++*launches;
         } else {
             ContractArgs a = op0.ca;
@@ -1102,8 +1258,9 @@ static int run_persist(pa_plan *P, hipStream_t s, int *launches, hipEvent_t befo
     const PStep *d_steps = reinterpret_cast<const PStep *>(base + P->steps_off);
     if (P->single_launch) {
         for (const PStep &st : P->steps_host)
-            if (st.kind == kStepGemm && st.gemm.path == 2)
-                return fail(PA_EINVAL, "internal: 256-row MFMA tiles in a single persistent launch");
+            if ((st.kind == kStepGemm && (st.gemm.path == 2 || st.gemm.dense)) || st.kind == kStepGather ||
+                st.kind == kStepCount)
+                return fail(PA_EINVAL, "internal: 256-row MFMA tiles or a sparse pass in a single persistent launch");
         HIP_TRY(launch_persist(d_steps, nsteps, P->n_items, state, done, cnt, (int)wg, s));
         *launches += 2;
     } else {
@@ -1111,7 +1268,7 @@ static int run_persist(pa_plan *P, hipStream_t s, int *launches, hipEvent_t befo
         for (size_t gi = 0; gi < P->groups.size(); ++gi) {
             const auto &g = P->groups[gi];
             if (ev && gi > 0) HIP_TRY(hipEventRecord(P->op_events[2 * gi], s));
-            HIP_TRY(launch_group(g.kind, g.mode, d_steps, g.first, g.count, g.t0, g.t1, cnt, s));
+            HIP_TRY(launch_group(g.kind, g.mode, d_steps, g.first, g.count, g.t0, g.t1, g.flags, cnt, s));
             if (ev) HIP_TRY(hipEventRecord(P->op_events[2 * gi + 1], s));
             ++*launches;
         }
@@ -1316,13 +1473,21 @@ extern "C" int32_t pa_plan_op_times(pa_plan *P, double *ms, int32_t *kind, doubl
             mc = 0.0;
             if (i > 0) {
                 const Op &op = P->ops[i - 1];
-                k = op.kind == OP_GEMM ? PA_OPKIND_GEMM : op.kind == OP_FILL ? PA_OPKIND_FILL : op.mode;
-                mc = op.kind == OP_FILL ? 0.0 : op.macs;
+                k = op.kind == OP_GEMM     ? PA_OPKIND_GEMM
+                    : op.kind == OP_FILL   ? PA_OPKIND_FILL
+                    : op.kind == OP_GATHER ? PA_OPKIND_GATHER
+                    : op.kind == OP_COUNT  ? PA_OPKIND_COUNT
+                                           : op.mode;
+                mc = (op.kind == OP_FILL || op.kind == OP_GATHER || op.kind == OP_COUNT) ? 0.0 : op.macs;
             }
         } else if (groups) {
             const auto &g = P->groups[i];
-            k = g.kind == kStepPlot ? PA_OPKIND_PLOT
-                                    : g.kind == kStepGemm ? PA_OPKIND_GEMM : g.kind == kStepFill ? PA_OPKIND_FILL : g.mode;
+            k = g.kind == kStepPlot     ? PA_OPKIND_PLOT
+                : g.kind == kStepGemm   ? PA_OPKIND_GEMM
+                : g.kind == kStepFill   ? PA_OPKIND_FILL
+                : g.kind == kStepGather ? PA_OPKIND_GATHER
+                : g.kind == kStepCount  ? PA_OPKIND_COUNT
+                                        : g.mode;
             mc = 0.0;
             for (int j = g.first; j < g.first + g.count; ++j) mc += P->step_macs[j];
         }
@@ -1349,7 +1514,7 @@ int time_groups(pa_plan *P, int32_t reps, double *ms, int32_t *kind, double *mac
         const auto &g = P->groups[gi];
         if (hipEventRecord(e0, s) != hipSuccess) rc = fail(PA_EHIP, "time_groups: event record failed");
         for (int r = 0; r < reps && !rc; ++r)
-            if (launch_group(g.kind, g.mode, d_steps, g.first, g.count, g.t0, g.t1, cnt, s) != hipSuccess)
+            if (launch_group(g.kind, g.mode, d_steps, g.first, g.count, g.t0, g.t1, g.flags, cnt, s) != hipSuccess)
                 rc = fail(PA_EHIP, "time_groups: launch failed");
         float t = 0.f;
         if (!rc && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
@@ -1357,8 +1522,13 @@ int time_groups(pa_plan *P, int32_t reps, double *ms, int32_t *kind, double *mac
             rc = fail(PA_EHIP, "time_groups: event timing failed");
         if (!rc && gi < cap) {
             if (ms) ms[gi] = (double)t / reps;
-            if (kind) kind[gi] = g.kind == kStepPlot ? PA_OPKIND_PLOT
-                                 : g.kind == kStepGemm ? PA_OPKIND_GEMM : g.kind == kStepFill ? PA_OPKIND_FILL : g.mode;
+            if (kind)
+                kind[gi] = g.kind == kStepPlot     ? PA_OPKIND_PLOT
+                           : g.kind == kStepGemm   ? PA_OPKIND_GEMM
+                           : g.kind == kStepFill   ? PA_OPKIND_FILL
+                           : g.kind == kStepGather ? PA_OPKIND_GATHER
+                           : g.kind == kStepCount  ? PA_OPKIND_COUNT
+                                                   : g.mode;
             double mc = 0.0;
             for (int j = g.first; j < g.first + g.count; ++j) mc += P->step_macs[j];
             if (macs) macs[gi] = mc;
@@ -1432,7 +1602,7 @@ extern "C" int pa_plan_execute(pa_plan *P, pa_bitarray *out, pa_report *rep, voi
         rep->n_launches = launches;
         int steps = 0;
         for (const auto &op : P->ops)
-            if (op.kind != OP_FILL && op.b != -1) ++steps;
+            if (op.kind != OP_FILL && op.kind != OP_GATHER && op.kind != OP_COUNT && op.b != -1) ++steps;
         rep->n_steps = steps;
         rep->cost_macs = P->tree.cost;
         for (size_t i = 0; i < P->tree.merges.size() && i < 2 * PA_MAX_RELATIONS; ++i) rep->merges[i] = P->tree.merges[i];

@@ -80,7 +80,7 @@ int plan_exhaustive(const SysInfo &si, Tree &t);
 int plan_learned(const SysInfo &si, const pa_model *model, Tree &t);
 
 // ---------------------------------------------------------------- op list
-enum OpKind { OP_CONTRACT = 0, OP_GEMM = 1, OP_FILL = 2 };
+enum OpKind { OP_CONTRACT = 0, OP_GEMM = 1, OP_FILL = 2, OP_GATHER = 3, OP_COUNT = 4 };
 
 constexpr int kBufOutput = -2;
 
@@ -88,6 +88,9 @@ struct Op {
     OpKind kind = OP_CONTRACT;
     int mode = kModeBits;         // contract mode
     int a = -1, b = -1, c = -1;   // buffer ids (kBufOutput = caller's output)
+    int flag = -1;                // sparse pass (OP_COUNT, OP_GATHER: b is the Bt plot) and its
+                                  // MFMA contraction: the two-word buffer of A's set-bit count
+    GatherArgs gg{};              // OP_COUNT, OP_GATHER (pointers patched at execution)
     Layout la, lb, lc;
     std::vector<int> kvars;
     ContractArgs ca{};            // pointers patched at execution
@@ -141,9 +144,11 @@ struct pa_plan {
     std::vector<int> step_level;              // per sorted step
     int64_t n_items = 0;
     int per_op = 0, graph = 0, single_launch = 0, persist_wg = 0, plot_strip = 0, contract_units = 0, gemm_split = 512, gemm_path = 0;
+    int sparse_pass = 0, sparse_max_density = 64;
     struct Group {
         int kind, mode, first, count;
         int64_t t0, t1;
+        int flags;         // MFMA steps of the group that follow a sparse pass
     };
     std::vector<Group> groups;                // level-synchronous executor
     std::vector<double> step_macs;            // per sorted step (0 for plots and fills)

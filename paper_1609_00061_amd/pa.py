@@ -17,8 +17,8 @@ LIB_PATH = os.path.join(_HERE, "libpa.so")
 
 PA_OK, PA_EINVAL, PA_ENOMEM, PA_EHIP, PA_EUNSUPPORTED = 0, 1, 2, 3, 4
 ORDER_GREEDY, ORDER_EXHAUSTIVE, ORDER_LEARNED, ORDER_GIVEN = 0, 1, 2, 3
-OPKIND_BITS, OPKIND_STREAM_K, OPKIND_STREAM_W, OPKIND_GEMM, OPKIND_FILL, OPKIND_PLOT, OPKIND_PERSIST = \
-    0, 1, 2, 10, 20, 30, 40
+OPKIND_BITS, OPKIND_STREAM_K, OPKIND_STREAM_W, OPKIND_GEMM, OPKIND_FILL = 0, 1, 2, 10, 20
+OPKIND_GATHER, OPKIND_COUNT, OPKIND_PLOT, OPKIND_PERSIST = 25, 26, 30, 40
 PLOT_FP32_ESCALATE, PLOT_FP64 = 0, 1
 MAX_DIMS, MAX_RELATIONS = 12, 32
 MODEL_FEATURES = 16
@@ -61,7 +61,8 @@ class Opts(ctypes.Structure):
                 ("plot_strip", ctypes.c_int32), ("contract_units", ctypes.c_int32),
                 ("model", ctypes.c_void_p), ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
                 ("autotune", ctypes.c_int32), ("gemm_split", ctypes.c_int32), ("gemm_path", ctypes.c_int32),
-                ("verify_order", ctypes.c_int32)]
+                ("verify_order", ctypes.c_int32), ("sparse_pass", ctypes.c_int32),
+                ("sparse_max_density", ctypes.c_int32)]
 
 
 class Tuning(ctypes.Structure):
@@ -210,7 +211,8 @@ def _system(keep, system) -> System:
 def make_opts(order=ORDER_EXHAUSTIVE, precision=PLOT_FP32_ESCALATE, audit=False, timing=False, plain=False,
               given: Optional[Sequence[int]] = None, model=None, keep: Optional[_Keep] = None, per_op=False,
               graph=False, single_launch=False, persist_wg=0, plot_strip=0, contract_units=0,
-              autotune=False, gemm_split=0, gemm_path=0, verify_order=False) -> Opts:
+              autotune=False, gemm_split=0, gemm_path=0, verify_order=False, sparse_pass=0,
+              sparse_max_density=0) -> Opts:
     o = Opts()
     o.order_policy = order
     o.precision = precision
@@ -227,6 +229,8 @@ def make_opts(order=ORDER_EXHAUSTIVE, precision=PLOT_FP32_ESCALATE, audit=False,
     o.gemm_split = int(gemm_split)
     o.gemm_path = int(gemm_path)
     o.verify_order = int(verify_order)
+    o.sparse_pass = int(sparse_pass)
+    o.sparse_max_density = int(sparse_max_density)
     if given is not None:
         assert keep is not None
         o.n_given = len(given) // 2

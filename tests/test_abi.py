@@ -58,12 +58,46 @@ def test_plans_put_dense_steps_on_mfma():
     c2 = pa.describe_plan(inputs.config2())
     assert _kernels(c2) == ["gemm_mfma"] * 7
     c3 = pa.describe_plan(inputs.config3())
-    assert _kernels(c3) == ["gemm_mfma", "gemm_mfma", "stream_k"]
-    # both r^5 steps (65536 x 65536 x 256) on MFMA, the r^4 step streamed
+    assert _kernels(c3) == ["sparse_count", "sparse_pass", "gemm_mfma"] * 2 + ["stream_k"]
+    assert _kernels(pa.describe_plan(inputs.config3(), sparse_pass=-1)) == ["gemm_mfma", "gemm_mfma", "stream_k"]
+    # both r^5 steps (65536 x 65536 x 256) on MFMA after a sparse pass each,
+    # the r^4 step streamed
     g = [o for o in c3["ops"] if o["op"] == "gemm_mfma"]
     assert all(o["macs"] == 256 ** 5 and o["Kw"] == 8 for o in g)
     assert [o["macs"] for o in c3["ops"] if o["op"] == "stream_k"] == [256 ** 4]
     assert c3["cost"] == 2 * 256 ** 5 + 256 ** 4
+
+
+def test_sparse_pass_plan():
+    """The ternary system's r^5 contractions (2^40 MACs) get a sparse pass:
+    B's relation is plotted a second time with the output variables packed
+    (256 rows of k x 65536 output bits), a count step reads A (65536 rows of
+    8 words), the pass writes output rows of 2048 words when A has at most
+    64 set bits per 1024 (default), and each MFMA contraction reads the same
+    counter; the chain's 2^30-MAC contractions get none unless asked; the
+    plain path and a single persistent launch never use it."""
+    d = pa.describe_plan(inputs.config3())
+    cn = [o for o in d["ops"] if o["op"] == "sparse_count"]
+    sp = [o for o in d["ops"] if o["op"] == "sparse_pass"]
+    gm = [o for o in d["ops"] if o["op"] == "gemm_mfma"]
+    assert len(sp) == 2 and len(cn) == 2 and len(d["plots"]) == 6
+    for k, s, g in zip(cn, sp, gm):
+        assert s["rows"] == 65536 and s["Kw"] == 8 and s["Nw"] == 2048
+        assert s["max_total"] == 65536 * 256 * 64 // 1024
+        assert k["words"] == 65536 * 8 and k["a"] == s["a"] == g["a"]
+        assert k["flag"] == s["flag"] == g["flag"] >= 0 and s["c"] == g["c"]
+        bt = [p for p in d["plots"] if p["buf"] == s["bt"]][0]
+        assert bt["vars"] == s["bt_vars"] and len(bt["vars"]) == 3
+    assert all(o["flag"] == -1 for o in pa.describe_plan(inputs.config2())["ops"] if o["op"] == "gemm_mfma")
+    c2 = pa.describe_plan(inputs.config2(), sparse_pass=1, sparse_max_density=5)
+    sp2 = [o for o in c2["ops"] if o["op"] == "sparse_pass"]
+    assert len(sp2) == 4                                    # level 1: B is a plot
+    assert all(o["max_total"] == 1024 * 1024 * 5 // 1024 for o in sp2)
+    for kw in (dict(plain=True), dict(single_launch=True), dict(sparse_pass=-1)):
+        assert not [o for o in pa.describe_plan(inputs.config3(), **kw)["ops"] if o["op"].startswith("sparse")], kw
+    assert _bad(inputs.config1(), sparse_pass=2) == pa.PA_EINVAL
+    assert _bad(inputs.config1(), sparse_max_density=-1) == pa.PA_EINVAL
+    assert _bad(inputs.config1(), sparse_max_density=1025) == pa.PA_EINVAL
 
 
 def test_exhaustive_prefers_parallel_trees_on_ties():

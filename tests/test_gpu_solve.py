@@ -74,6 +74,37 @@ def test_random_hypergraphs_all_policies(seed):
         assert e.value.code == pa.PA_ENOMEM
 
 
+@pytest.mark.parametrize("seed", range(6))
+def test_sparse_pass_on_random_hypergraphs(seed):
+    """Every MFMA contraction whose B is a plot gets a sparse pass (batch
+    variables, several latent and output variables in any layout); with a
+    density threshold of 1/1024 the MFMA kernel computes them instead, with
+    1024/1024 the pass always does: always the oracle's bits."""
+    s = _random_small_system(4300 + seed)
+    res = [a[2] for a in s.axes]
+    ref = oracle.solve(res, [r.vars for r in s.relations], _oracle_plots(s), s.exposed)
+    n_pass = len([o for o in pa.describe_plan(s, sparse_pass=1)["ops"] if o["op"] == "sparse_pass"])
+    note("sparse passes", n_pass)
+    for kw in (dict(sparse_pass=1), dict(sparse_pass=1, sparse_max_density=1),
+               dict(sparse_pass=1, sparse_max_density=1024), dict(sparse_pass=1, gemm_split=2048, sparse_max_density=1),
+               dict(sparse_pass=1, order=pa.ORDER_GREEDY, gemm_path=3), dict(sparse_pass=1, per_op=True),
+               dict(sparse_pass=1, per_op=True, sparse_max_density=1)):
+        got, _ = _solve(s, **kw)
+        assert np.array_equal(got, ref), kw
+
+
+def test_sparse_pass_chain_and_ternary():
+    """The chain (pass on the first level) and the ternary system at reduced
+    resolution, with the pass or the MFMA kernel computing the contractions."""
+    for s in (inputs.config2(res=128), inputs.config3(res=24)):
+        res = [a[2] for a in s.axes]
+        ref = oracle.solve(res, [r.vars for r in s.relations], _oracle_plots(s), s.exposed)
+        for kw in (dict(sparse_pass=1), dict(sparse_pass=1, sparse_max_density=1024),
+                   dict(sparse_pass=1, sparse_max_density=1), dict(sparse_pass=1, graph=True)):
+            got, _ = _solve(s, **kw)
+            assert np.array_equal(got, ref), (s.name, kw)
+
+
 def test_huge_intermediate_with_grid_stride():
     """A Kronecker-heavy order whose intermediate has more than 2^32 bits:
     every contraction kernel loops over its output (grid-stride), so the
@@ -142,7 +173,8 @@ def test_c3_full_size_sampled():
     ref = oracle.solve_entries(res, [r.vars for r in s.relations], plots, s.exposed, ent)
     assert np.array_equal(got[tuple(ent.T)], ref)
     note("c3 nnz", int(got.sum()), "flagged", rep["corners_flagged"])
-    # the other MFMA operand paths give the same array
-    for path in (2, 3):
-        got2, _ = _solve(s, gemm_path=path)
-        assert np.array_equal(got2, got), path
+    # the sparse pass (default here) and the MFMA operand paths alone give the same array
+    assert [o["op"] for o in pa.describe_plan(s)["ops"]].count("sparse_pass") == 2
+    for kw in (dict(sparse_pass=-1), dict(sparse_pass=-1, gemm_path=2), dict(sparse_max_density=1)):
+        got2, _ = _solve(s, **kw)
+        assert np.array_equal(got2, got), kw
