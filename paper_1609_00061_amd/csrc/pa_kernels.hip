@@ -1485,16 +1485,19 @@ __device__ __forceinline__ uint4 load_words4(const PA_G uint32_t *p, int64_t c, 
     return v;
 }
 
+// Stores of output words that no later kernel of the launch reads:
+// non-temporal, so the streamed output does not evict the rows the pass
+// keeps re-reading from L2.
 __device__ __forceinline__ void store_words4(PA_G uint32_t *p, int64_t c, int64_t n, bool vec4, uint4 v) {
     if (c + 3 < n) {
         if (vec4) {
-            *reinterpret_cast<PA_G u32x4 *>(p + c) = u32x4{v.x, v.y, v.z, v.w};
+            __builtin_nontemporal_store(u32x4{v.x, v.y, v.z, v.w}, reinterpret_cast<PA_G u32x4 *>(p + c));
         } else {
-            *reinterpret_cast<PA_G u32x2 *>(p + c) = u32x2{v.x, v.y};
-            *reinterpret_cast<PA_G u32x2 *>(p + c + 2) = u32x2{v.z, v.w};
+            __builtin_nontemporal_store(u32x2{v.x, v.y}, reinterpret_cast<PA_G u32x2 *>(p + c));
+            __builtin_nontemporal_store(u32x2{v.z, v.w}, reinterpret_cast<PA_G u32x2 *>(p + c + 2));
         }
     } else if (c < n) {
-        *reinterpret_cast<PA_G u32x2 *>(p + c) = u32x2{v.x, v.y};
+        __builtin_nontemporal_store(u32x2{v.x, v.y}, reinterpret_cast<PA_G u32x2 *>(p + c));
     }
 }
 
@@ -1532,11 +1535,13 @@ __device__ void gather_wave(const GatherArgs &g, int64_t wt) {
     int64_t w = 0;
     for (int64_t ko = 0; ko < kouters; ++ko) {
         for (int64_t wp = 0; wp < g.rwk; ++wp, ++w) {
-            uint32_t bits = arow[w];
+            // padding bits are zero in every array; masked anyway, as they
+            // would index past Bt
+            const int64_t lim = g.rkp - 32 * wp;
+            uint32_t bits = arow[w] & (lim <= 0 ? 0u : lim >= 32 ? ~0u : ((1u << lim) - 1u));
             while (bits) {
                 const int bit = __ffs((int)bits) - 1;
                 bits &= bits - 1;
-                if (32 * wp + bit >= g.rkp) break;     // padding bits (zero in every array) end the word
                 const PA_G uint32_t *src = bt + (ko * g.rkp + 32 * wp + bit) * n;
                 uint4 v[8];
 #pragma unroll
@@ -1725,6 +1730,18 @@ __global__ __launch_bounds__(256, KIND % 10 == kStepGemm ? gemm_occupancy(KIND /
         gemm_run<mode>(next, lds);
         return;
     }
+    if (kind == kStepGather) {
+        // persistent waves over the launch's wave-tiles (no barriers)
+        const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+        const int64_t slots = (t1 - t0) * 4, stride = (int64_t)gridDim.x * 4;
+        for (int64_t gi = (int64_t)blockIdx.x * 4 + wave; gi < slots; gi += stride) {
+            const int64_t item = t0 + (gi >> 2);
+            const PStep &st = steps[find_step(steps, first, count, item)];
+            const int64_t wt = (item - st.tile_base) * 4 + (gi & 3);
+            if (wt < gather_wave_tiles(st.gather) && gather_decide(st.gather, wt)) gather_wave(st.gather, wt);
+        }
+        return;
+    }
     PlotCount cnt;
     for (int64_t item = t0 + blockIdx.x; item < t1; item += gridDim.x) {
         const PStep &st = steps[find_step(steps, first, count, item)];
@@ -1734,10 +1751,6 @@ __global__ __launch_bounds__(256, KIND % 10 == kStepGemm ? gemm_occupancy(KIND /
         } else if (kind == kStepContract) {
             const int64_t u0 = (item - st.tile_base) * st.per_tile;
             contract_range<mode>(st.ca, u0, min(st.units, u0 + st.per_tile));
-        } else if (kind == kStepGather) {
-            const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-            const int64_t wt = (item - st.tile_base) * 4 + wave;
-            if (wt < gather_wave_tiles(st.gather) && gather_decide(st.gather, wt)) gather_wave(st.gather, wt);
         } else if (kind == kStepCount) {
             count_tile(st.gather, item - st.tile_base);
         } else {
@@ -1749,12 +1762,26 @@ __global__ __launch_bounds__(256, KIND % 10 == kStepGemm ? gemm_occupancy(KIND /
     if (kind == kStepPlot) flush_counts(cnt, counters);
 }
 
+// Workgroups of the persistent sparse-pass loop: every CU's worth.
+static int64_t gather_grid() {
+    static int cached = 0;
+    if (!cached) {
+        int dev = 0, cus = 256, per_cu = 1;
+        if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_group<kStepGather>, 256, 0) != hipSuccess || per_cu < 1)
+            per_cu = 1;
+        cached = cus * per_cu;
+    }
+    return cached;
+}
+
 hipError_t launch_group(int kind, int mode, const PStep *d_steps, int first, int count, int64_t t0, int64_t t1,
                         int flags, PlotCounters *counters, hipStream_t s) {
     if (t1 <= t0) return hipSuccess;
     const int64_t nt = t1 - t0;
     if (kind == kStepGemm && (mode < 0 || mode > 2)) return hipErrorInvalidValue;
-    const dim3 grid((unsigned)(kind == kStepGemm ? gemm_grid(nt, mode) : (nt < (1 << 20) ? nt : (1 << 20))));
+    const int64_t cap = kind == kStepGather ? gather_grid() : ((int64_t)1 << 20);
+    const dim3 grid((unsigned)(kind == kStepGemm ? gemm_grid(nt, mode) : (nt < cap ? nt : cap)));
 #define PA_GROUP(K) hipLaunchKernelGGL(k_group<K>, grid, dim3(256), 0, s, d_steps, first, count, t0, t1, flags, counters)
     switch (kind) {
         case kStepPlot: PA_GROUP(kStepPlot); break;
