@@ -138,7 +138,7 @@ def _kernel_table(plan, stream, system, reps):
     return roof, per_kind, groups
 
 
-def _ternary(stream, steps=10):
+def _ternary(stream, steps=10, tuning=None):
     """The ternary workload (4 trivariate cubics over 6 variables at 256
     cells/axis, 2 exposed): solves/s, and per kernel kind the grouped
     launch's rate against its roofline.  Its two 65536 x 65536 x 256-bit
@@ -150,7 +150,8 @@ def _ternary(stream, steps=10):
     The word-streaming contraction reads both 512 MiB intermediates once."""
     from paper_1609_00061_amd import inputs, pa
     s = inputs.config3()
-    tuning, _ = pa.autotune([s], reps=3, stream=stream, order=pa.ORDER_EXHAUSTIVE, graph=True)
+    if tuning is None:
+        tuning, _ = pa.autotune([s], reps=3, stream=stream, order=pa.ORDER_EXHAUSTIVE, graph=True)
     tuning = {k: int(v) for k, v in tuning.items() if k != "ms"}
     plan = pa.Plan(s, order=pa.ORDER_EXHAUSTIVE, graph=True, **tuning)
     out = pa.empty_bits(plan.dims)
@@ -357,6 +358,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-ternary", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--ternary-only", action="store_true",
+                    help="run only the ternary workload (--steps solves) and print its JSON line (for profiling)")
     ap.add_argument("--tuning", type=str, default="",
                     help="JSON executor settings to use instead of autotuning (e.g. for counter runs, whose "
                          "serialization distorts timings)")
@@ -376,6 +379,11 @@ def main():
     K, W = args.steps, args.warmup
 
     stream = torch.cuda.Stream()
+    if args.ternary_only:
+        _progress("ternary workload")
+        given = {k: int(v) for k, v in json.loads(args.tuning).items()} if args.tuning else None
+        print(json.dumps(_ternary(stream, steps=K, tuning=given)), flush=True)
+        return
     _progress("planning and autotuning the chain workload")
     t0 = time.perf_counter()
     if args.tuning:
