@@ -105,6 +105,23 @@ def test_sparse_pass_chain_and_ternary():
             assert np.array_equal(got, ref), (s.name, kw)
 
 
+def test_sparse_pass_long_output_rows():
+    """Output rows of 41 x 94 words (more than one 2048-word wave-tile per
+    row, a row length that is not a multiple of 4 words): R1(a, k) and
+    R2(k, b, c) with b at 41 and c at 3000 cells, k latent."""
+    rng = inputs.SplitMix64(4400)
+    s = inputs.System([(-3.0, 3.0, 40), (-3.0, 3.0, 40), (-3.0, 3.0, 41), (-3.0, 3.0, 3000)],
+                      [inputs.random_relation(rng, (0, 1)), inputs.random_relation(rng, (1, 2, 3))], (0, 2, 3),
+                      name="long_rows")
+    sp = [o for o in pa.describe_plan(s, sparse_pass=1)["ops"] if o["op"] == "sparse_pass"]
+    assert sp and sp[0]["Nw"] > 2048 and sp[0]["Nw"] % 4 == 2
+    res = [a[2] for a in s.axes]
+    ref = oracle.solve(res, [r.vars for r in s.relations], _oracle_plots(s), s.exposed)
+    for kw in (dict(sparse_pass=1), dict(sparse_pass=1, per_op=True), dict(sparse_pass=-1)):
+        got, _ = _solve(s, **kw)
+        assert np.array_equal(got, ref), kw
+
+
 def test_huge_intermediate_with_grid_stride():
     """A Kronecker-heavy order whose intermediate has more than 2^32 bits:
     every contraction kernel loops over its output (grid-stride), so the
