@@ -170,17 +170,21 @@ typedef struct {
                                  executions on stream 0, temporary outputs) and keep
                                  the faster; the exhaustive search stays the judge */
     int32_t sparse_pass;      /* MFMA contractions whose B operand is a plotted
-                                 relation: 1 = always, 0 (default) = when the
-                                 contraction has at least 2^32 MACs, -1 = never,
-                                 get a sparse pass: the relation is also plotted
-                                 with its output variables packed, a count step
-                                 adds up the set bits of A, and if A has at most
+                                 relation get a sparse pass: the relation is also
+                                 plotted with its output variables packed, and each
+                                 output row is computed as the OR of the rows of
+                                 that plot selected by the set bits of the A row.
+                                 0 (default): contractions of at least 2^32 MACs
+                                 get the pass with an MFMA fallback (a count step
+                                 adds up the set bits of A; with at most
                                  sparse_max_density set bits per 1024 the pass
-                                 computes each output row as the OR of the rows of
-                                 that plot selected by the set bits of the A row
-                                 (and the MFMA kernel exits at once); otherwise the
-                                 MFMA kernel runs (and the pass exits).  Not used by
-                                 the plain path or a single persistent launch.   */
+                                 computes the output and the MFMA kernel exits at
+                                 once, otherwise the reverse).  1 = the pass with
+                                 the fallback for every such contraction, 2 = the
+                                 pass alone (no count, no MFMA kernel; B's first
+                                 plot is dropped when nothing else reads it) for
+                                 every such contraction, -1 = never.  Not used by
+                                 the plain path or a single persistent launch.    */
     int32_t sparse_max_density; /* 0..1024 set bits per 1024 bits of A (0: 64)     */
 } pa_opts;
 

@@ -216,7 +216,7 @@ extern "C" int pa_batch_execute(pa_batch *B, pa_bitarray *outs, pa_report *rep, 
             for (auto &P : B->subs) {
                 cost += P->tree.cost;
                 for (const auto &op : P->ops)
-                    if (op.kind != OP_FILL && op.kind != OP_GATHER && op.kind != OP_COUNT && op.b != -1) ++steps;
+                    if (op.kind != OP_FILL && op.kind != OP_COUNT && !(op.kind == OP_GATHER && op.flag >= 0) && op.b != -1) ++steps;
             }
             rep->n_steps = steps;
             rep->cost_macs = cost;

@@ -175,7 +175,7 @@ struct GatherArgs {
     FastDiv fd_chunks, fd_M;  // divisions of wave-tile indices (below 2^31, host check)
 };
 
-constexpr int64_t kCountTileWords = 65536;   // A words per tile of a count step (4 partial sums)
+constexpr int64_t kCountTileWords = 8192;    // A words per tile of a count step (4 partial sums)
 
 // Wave-tiles of a sparse pass (2048 words of one output row each).
 __host__ __device__ inline int64_t gather_wave_tiles(const GatherArgs &g) { return g.rows * g.chunks; }

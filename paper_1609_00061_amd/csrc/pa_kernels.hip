@@ -932,6 +932,7 @@ hipError_t launch_contract(const ContractArgs &a, int mode, hipStream_t s) {
 // sums add up to at most max_total set bits of A (else the MFMA kernel
 // computes the contraction).  Called by whole waves (a wave reduction).
 __device__ __forceinline__ bool sparse_ran(const uint32_t *parts, int64_t nparts, int64_t max_total) {
+    if (!parts) return true;      // a pass without a count always runs
     unsigned long long c = 0;
     for (int64_t i = __lane_id(); i < nparts; i += 64) c += gp(parts)[i];
     for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
@@ -1503,56 +1504,128 @@ __device__ __forceinline__ void store_words4(PA_G uint32_t *p, int64_t c, int64_
 
 // Count step, tile t: the set bits of A words [t K, (t + 1) K) (K =
 // kCountTileWords), one partial sum per wave stored at parts[4 t + wave].
+// A full tile of 16-byte aligned words is read with eight independent
+// 16-byte loads per lane.
 __device__ void count_tile(const GatherArgs &g, int64_t t) {
+    static_assert(kCountTileWords == 8 * 4 * 256, "count tile: eight 16-byte loads per lane of 256");
     const int64_t u0 = t * kCountTileWords, u1 = min(g.rows * g.Kw, u0 + kCountTileWords);
     uint32_t c = 0;
     const PA_G uint32_t *a = gp(g.A);
-    for (int64_t i = u0 + threadIdx.x; i < u1; i += blockDim.x) c += __popc(a[i]);
+    if (u1 - u0 == kCountTileWords && ((uintptr_t)(a + u0) & 15u) == 0) {
+        const PA_G u32x4 *a4 = reinterpret_cast<const PA_G u32x4 *>(a + u0);
+        u32x4 v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = a4[threadIdx.x + 256 * j];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) c += __popc(v[j].x) + __popc(v[j].y) + __popc(v[j].z) + __popc(v[j].w);
+    } else {
+        for (int64_t i = u0 + threadIdx.x; i < u1; i += blockDim.x) c += __popc(a[i]);
+    }
     for (int off = 32; off > 0; off >>= 1) c += __shfl_down(c, off);
     if ((threadIdx.x & 63) == 0) gp(g.parts)[4 * t + (threadIdx.x >> 6)] = c;
 }
 
+// The set bits of one A row, in order, as row indices of Bt (latent entry
+// ko * rkp + 32 wp + bit of A word w = ko * rwk + wp): the row's words are
+// read 64 at a time, one per lane, so their loads overlap; a ballot finds
+// the nonzero words and readlane hands each to the whole wave.  Padding
+// bits are zero in every array; they are masked anyway, as they would
+// index past Bt.  Every member but aw and base is uniform.
+struct RowBits {
+    const PA_G uint32_t *arow;
+    uint32_t Kw, rwk, rkp;
+    uint32_t aw, base;      // this lane's word and the Bt row of its bit 0
+    uint64_t nz;            // lanes whose nonzero word is not taken yet
+    uint32_t cur, cbase;    // the word being walked and its Bt row of bit 0
+
+    __device__ __forceinline__ void load(uint32_t w0) {
+        const uint32_t w = w0 + (threadIdx.x & 63);
+        aw = 0u;
+        base = 0u;
+        if (w < Kw) {
+            const uint32_t ko = w / rwk, wp = w - ko * rwk;
+            const int32_t lim = (int32_t)rkp - 32 * (int32_t)wp;
+            aw = arow[w] & (lim <= 0 ? 0u : lim >= 32 ? ~0u : ((1u << lim) - 1u));
+            base = ko * rkp + 32u * wp;
+        }
+        nz = __ballot(aw != 0u);
+        cur = 0u;
+    }
+    __device__ __forceinline__ bool more() const { return cur != 0u || nz != 0u; }
+    // the next set bit's Bt row, or -1 when the 64 words hold no more
+    __device__ __forceinline__ int64_t next() {
+        if (cur == 0u) {
+            if (nz == 0u) return -1;
+            const int l = __builtin_ctzll(nz);
+            nz &= nz - 1u;
+            cur = (uint32_t)__builtin_amdgcn_readlane((int)aw, l);
+            cbase = (uint32_t)__builtin_amdgcn_readlane((int)base, l);
+        }
+        const uint32_t bit = (uint32_t)__builtin_ctz(cur);
+        cur &= cur - 1u;
+        return (int64_t)(cbase + bit);
+    }
+};
+
 // One wave-tile of the sparse pass: words ch * 2048 .. + 2047 of output row
-// `row`; lane l holds words 4l + 256 j (j < 8).  The A row is read by the
-// whole wave (uniform), its set bits walked in order, and for each the
-// matching 2048 words of Bt OR-ed in (eight independent 16-byte loads per
-// lane).
+// `row`; lane l holds words 4l + 256 j (j < 8), and for each set bit of the
+// A row the matching 2048 words of Bt are OR-ed in (eight independent
+// 16-byte loads per lane).  A row of at most 256 words is one wave-tile
+// with one position per lane, and four set bits are taken at a time so that
+// four Bt rows' loads are in flight together.
 __device__ void gather_wave(const GatherArgs &g, int64_t wt) {
     const int lane = threadIdx.x & 63;
     const uint32_t row = fdiv((uint32_t)wt, g.fd_chunks);
     const uint32_t ch = (uint32_t)wt - row * (uint32_t)g.chunks;
     const uint32_t b = fdiv(row, g.fd_M);
-    const PA_G uint32_t *arow = gp(g.A) + (int64_t)row * g.Kw;
     const int64_t n = g.Nw;
     const bool vec4 = (n & 3) == 0;
+    const PA_G uint32_t *bt = gp(g.Bt) + (int64_t)b * g.sBt_b;
+    PA_G uint32_t *crow = gp(g.C) + (int64_t)row * n;
+    RowBits rb;
+    rb.arow = gp(g.A) + (int64_t)row * g.Kw;
+    rb.Kw = (uint32_t)g.Kw;
+    rb.rwk = (uint32_t)g.rwk;
+    rb.rkp = (uint32_t)g.rkp;
+    if (n <= 256) {
+        const int64_t c = 4 * lane;
+        uint4 acc = make_uint4(0u, 0u, 0u, 0u);
+        for (uint32_t w0 = 0; w0 < rb.Kw; w0 += 64) {
+            rb.load(w0);
+            while (rb.more()) {
+                int64_t k[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) k[q] = rb.next();
+                uint4 v[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    v[q] = k[q] >= 0 ? load_words4(bt + k[q] * n, c, n, vec4) : make_uint4(0u, 0u, 0u, 0u);
+                acc.x |= (v[0].x | v[1].x) | (v[2].x | v[3].x);
+                acc.y |= (v[0].y | v[1].y) | (v[2].y | v[3].y);
+                acc.z |= (v[0].z | v[1].z) | (v[2].z | v[3].z);
+                acc.w |= (v[0].w | v[1].w) | (v[2].w | v[3].w);
+            }
+        }
+        store_words4(crow, c, n, vec4, acc);
+        return;
+    }
     const int64_t c0 = (int64_t)ch * 2048 + 4 * lane;
     uint4 acc[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) acc[j] = make_uint4(0u, 0u, 0u, 0u);
-    const PA_G uint32_t *bt = gp(g.Bt) + (int64_t)b * g.sBt_b;
-    PA_G uint32_t *crow = gp(g.C) + (int64_t)row * n;
-    const int64_t kouters = g.Kw / g.rwk;
-    int64_t w = 0;
-    for (int64_t ko = 0; ko < kouters; ++ko) {
-        for (int64_t wp = 0; wp < g.rwk; ++wp, ++w) {
-            // padding bits are zero in every array; masked anyway, as they
-            // would index past Bt
-            const int64_t lim = g.rkp - 32 * wp;
-            uint32_t bits = arow[w] & (lim <= 0 ? 0u : lim >= 32 ? ~0u : ((1u << lim) - 1u));
-            while (bits) {
-                const int bit = __ffs((int)bits) - 1;
-                bits &= bits - 1;
-                const PA_G uint32_t *src = bt + (ko * g.rkp + 32 * wp + bit) * n;
-                uint4 v[8];
+    for (uint32_t w0 = 0; w0 < rb.Kw; w0 += 64) {
+        rb.load(w0);
+        while (rb.more()) {
+            const PA_G uint32_t *src = bt + rb.next() * n;
+            uint4 v[8];
 #pragma unroll
-                for (int j = 0; j < 8; ++j) v[j] = load_words4(src, c0 + 256 * j, n, vec4);
+            for (int j = 0; j < 8; ++j) v[j] = load_words4(src, c0 + 256 * j, n, vec4);
 #pragma unroll
-                for (int j = 0; j < 8; ++j) {
-                    acc[j].x |= v[j].x;
-                    acc[j].y |= v[j].y;
-                    acc[j].z |= v[j].z;
-                    acc[j].w |= v[j].w;
-                }
+            for (int j = 0; j < 8; ++j) {
+                acc[j].x |= v[j].x;
+                acc[j].y |= v[j].y;
+                acc[j].z |= v[j].z;
+                acc[j].w |= v[j].w;
             }
         }
     }
@@ -1566,7 +1639,7 @@ __device__ void gather_wave(const GatherArgs &g, int64_t wt) {
 // stores to one word would serialize at the memory side).
 __device__ __forceinline__ bool gather_decide(const GatherArgs &g, int64_t wt) {
     const bool run = sparse_ran(g.parts, g.nparts, g.max_total);
-    if (wt == 0 && __lane_id() == 0) gp(g.dense)[0] = run ? 0u : 1u;
+    if (g.dense && wt == 0 && __lane_id() == 0) gp(g.dense)[0] = run ? 0u : 1u;
     return run;
 }
 

@@ -341,20 +341,26 @@ struct Builder {
         P->ops.push_back(op);
     }
 
-    // An MFMA contraction with a sparse pass, when B is a plotted relation and
-    // the pass is enabled for the contraction's size: the relation is plotted
-    // a second time as Bt = [batch vars, latent vars in A's order, output n
-    // vars in C's order] (rows of Bt have C's row layout); a two-word counter
-    // is zeroed, a count step adds up the set bits of A, and then either the
-    // pass (at most sparse_max_density set bits per 1024 bits of A) or the
-    // MFMA kernel computes the output; the other exits at once.
+    // An MFMA contraction with a sparse pass, when B is a plotted relation: the
+    // relation is plotted a second time as Bt = [batch vars, latent vars in
+    // A's order, output n vars in C's order] (rows of Bt have C's row layout).
+    // With a fallback (at least 2^32 MACs, or sparse_pass = 1) a count step
+    // adds up the set bits of A and then either the pass (at most
+    // sparse_max_density set bits per 1024 bits of A) or the MFMA kernel
+    // computes the output; the other exits at once.  With sparse_pass = 2
+    // the pass alone computes it (no count, and B's first plot is dropped
+    // when nothing else reads it): for callers who know A is sparse.
     void emit_gemm_with_pass(int a, const Layout &la, int b, const Layout &lb, int bnode, int c, const Layout &lc,
                              int nb, int nm, int node) {
         const Node &bn = P->tree.nodes[bnode];
         const bool b_plot = bn.leaf >= 0 && !(P->si.rel_vars[bn.leaf] & ~bn.q);
         const double macs = mask_cost(list_mask(la.vars) | list_mask(lb.vars), P->si);
-        const bool use = b_plot && P->sparse_pass >= 0 && (P->sparse_pass == 1 || macs >= 4294967296.0);
-        if (!use) {
+        int mode = 0;         // 0: MFMA only, 1: pass with MFMA fallback, 2: pass only
+        if (b_plot && P->sparse_pass >= 0) {
+            if (P->sparse_pass >= 1) mode = P->sparse_pass;
+            else if (macs >= 4294967296.0) mode = 1;
+        }
+        if (mode == 0) {
             emit_gemm(a, la, b, lb, c, lc, nb, nm, node);
             return;
         }
@@ -383,6 +389,22 @@ struct Builder {
         ga.max_total = (int64_t)std::floor((double)ga.rows * (double)kall * P->sparse_max_density / 1024.0);
         ga.fd_chunks = make_fastdiv((uint64_t)std::max<int64_t>(1, ga.chunks));
         ga.fd_M = make_fastdiv((uint64_t)std::max<int64_t>(1, M));
+        if (mode == 2) {
+            Op g;
+            g.kind = OP_GATHER;
+            g.a = a;
+            g.b = bt;
+            g.c = c;
+            g.la = la;
+            g.lb = P->buf_layout[bt];
+            g.lc = lc;
+            g.node = node;
+            g.macs = macs;
+            g.gg = ga;
+            g.gg.max_total = -1;      // no decision: the pass always runs
+            P->ops.push_back(g);
+            return;
+        }
         // the count's partial sums: four per tile of kCountTileWords words of A
         ga.nparts = 4 * ((ga.rows * ga.Kw + kCountTileWords - 1) / kCountTileWords);
         Layout cl;            // the partial sums, then the decision word
@@ -776,8 +798,8 @@ int build_plan(const pa_system *sys, const int32_t *exposed, int32_t n_exposed, 
     // the sparse pass: not in the plain path nor in a single persistent launch
     P->sparse_pass = (P->plain || P->single_launch) ? -1 : o.sparse_pass;
     P->sparse_max_density = o.sparse_max_density > 0 ? o.sparse_max_density : 64;
-    if (o.sparse_pass < -1 || o.sparse_pass > 1 || o.sparse_max_density < 0 || o.sparse_max_density > 1024)
-        return fail(PA_EINVAL, "opts: sparse_pass must be -1, 0 or 1 and sparse_max_density 0..1024");
+    if (o.sparse_pass < -1 || o.sparse_pass > 2 || o.sparse_max_density < 0 || o.sparse_max_density > 1024)
+        return fail(PA_EINVAL, "opts: sparse_pass must be -1..2 and sparse_max_density 0..1024");
     if (o.precision != PA_PLOT_FP32_ESCALATE && o.precision != PA_PLOT_FP64)
         return fail(PA_EINVAL, "opts: unknown precision");
     if (o.persist_wg < 0 || o.plot_strip < 0 || o.contract_units < 0 || o.gemm_split < 0 || o.gemm_path < 0 ||
@@ -804,6 +826,23 @@ int build_plan(const pa_system *sys, const int32_t *exposed, int32_t n_exposed, 
     for (auto &op : P->ops)
         if (op.kind == OP_CONTRACT) finish_contract(op, op.b >= 0 || op.b == kBufOutput);
     split_gemms(P);
+    // a plot that no step reads (the first plot of B in a contraction left to
+    // the sparse pass alone) is dropped, and its buffer takes no space
+    {
+        std::vector<char> read(P->buf_layout.size(), 0);
+        for (const auto &op : P->ops)
+            for (int id : {op.a, op.b, op.c, op.flag})
+                if (id >= 0) read[id] = 1;
+        std::vector<PlotItem> kept;
+        for (const auto &it : P->plots) {
+            if (it.buf >= 0 && !read[it.buf]) {
+                P->buf_words[it.buf] = 0;
+                continue;
+            }
+            kept.push_back(it);
+        }
+        P->plots.swap(kept);
+    }
     P->total_macs = 0.0;
     for (const auto &op : P->ops)
         if (op.kind != OP_FILL) P->total_macs += op.macs;
@@ -944,8 +983,10 @@ static int check_gather_bounds(const GatherArgs &g, int64_t a_words, int64_t bt_
         g.Nw % 2 || g.rows * g.Kw > a_words || (pass && g.rows * g.Nw > c_words) ||
         (pass && (g.rows / g.M) * g.sBt_b > bt_words) || g.sBt_b != (g.Kw / g.rwk) * g.rkp * g.Nw)
         return fail(PA_EINVAL, "internal: sparse pass would index outside its buffers");
-    // wave-tile indices and rows are divided in 32 bits
-    if (g.rows * g.chunks >= ((int64_t)1 << 31)) return fail(PA_EUNSUPPORTED, "sparse pass too large for one launch");
+    // wave-tile indices, rows, A word indices and Bt row indices are 32-bit
+    if (g.rows * g.chunks >= ((int64_t)1 << 31) || g.Kw >= ((int64_t)1 << 31) ||
+        (g.Kw / g.rwk) * g.rkp >= ((int64_t)1 << 31))
+        return fail(PA_EUNSUPPORTED, "sparse pass too large for one launch");
     return PA_OK;
 }
 
@@ -1011,8 +1052,8 @@ static int build_steps(pa_plan *P) {
             s.gather.A = buf_ptr(P, op.a, nullptr);
             s.gather.Bt = pass ? buf_ptr(P, op.b, nullptr) : nullptr;
             s.gather.C = pass ? buf_ptr(P, op.c, nullptr) : nullptr;
-            s.gather.parts = buf_ptr(P, op.flag, nullptr);
-            s.gather.dense = s.gather.parts + op.gg.nparts;
+            s.gather.parts = op.flag >= 0 ? buf_ptr(P, op.flag, nullptr) : nullptr;
+            s.gather.dense = op.flag >= 0 ? s.gather.parts + op.gg.nparts : nullptr;
             s.n_tiles = pass ? (gather_wave_tiles(op.gg) + 3) / 4
                              : (op.gg.rows * op.gg.Kw + kCountTileWords - 1) / kCountTileWords;
             dep(op.a);
@@ -1022,7 +1063,7 @@ static int build_steps(pa_plan *P) {
                 dep(op.c);          // the zeroing of a split contraction's output
                 if (op.c == kBufOutput) out_refs.push_back((int)st.size());
             }
-            producer[op.flag] = (int)st.size();
+            if (op.flag >= 0) producer[op.flag] = (int)st.size();
         } else if (op.kind == OP_GEMM) {
             int rc = check_gemm_bounds(op.ga, op.la.words, op.lb.words, op.lc.words);
             if (rc) return rc;
@@ -1201,8 +1242,8 @@ static int run_ops(pa_plan *P, void *out, hipStream_t s, int *launches) {
             g.A = buf_ptr(P, op0.a, out);
             g.Bt = pass ? buf_ptr(P, op0.b, out) : nullptr;
             g.C = pass ? buf_ptr(P, op0.c, out) : nullptr;
-            g.parts = buf_ptr(P, op0.flag, out);
-            g.dense = g.parts + g.nparts;
+            g.parts = op0.flag >= 0 ? buf_ptr(P, op0.flag, out) : nullptr;
+            g.dense = op0.flag >= 0 ? g.parts + g.nparts : nullptr;
             HIP_TRY(pass ? launch_gather(g, s) : launch_count(g, s));
             ++*launches;
         } else {
@@ -1478,7 +1519,7 @@ extern "C" int32_t pa_plan_op_times(pa_plan *P, double *ms, int32_t *kind, doubl
                     : op.kind == OP_GATHER ? PA_OPKIND_GATHER
                     : op.kind == OP_COUNT  ? PA_OPKIND_COUNT
                                            : op.mode;
-                mc = (op.kind == OP_FILL || op.kind == OP_GATHER || op.kind == OP_COUNT) ? 0.0 : op.macs;
+                mc = (op.kind == OP_FILL || op.kind == OP_COUNT) ? 0.0 : op.macs;
             }
         } else if (groups) {
             const auto &g = P->groups[i];
@@ -1602,7 +1643,7 @@ extern "C" int pa_plan_execute(pa_plan *P, pa_bitarray *out, pa_report *rep, voi
         rep->n_launches = launches;
         int steps = 0;
         for (const auto &op : P->ops)
-            if (op.kind != OP_FILL && op.kind != OP_GATHER && op.kind != OP_COUNT && op.b != -1) ++steps;
+            if (op.kind != OP_FILL && op.kind != OP_COUNT && !(op.kind == OP_GATHER && op.flag >= 0) && op.b != -1) ++steps;
         rep->n_steps = steps;
         rep->cost_macs = P->tree.cost;
         for (size_t i = 0; i < P->tree.merges.size() && i < 2 * PA_MAX_RELATIONS; ++i) rep->merges[i] = P->tree.merges[i];

@@ -57,6 +57,10 @@ def test_plans_put_dense_steps_on_mfma():
     assert _kernels(c1) == ["gemm_mfma"]
     c2 = pa.describe_plan(inputs.config2())
     assert _kernels(c2) == ["gemm_mfma"] * 7
+    # the sparse pass alone: the circle pair, and the chain's four first-level steps
+    assert _kernels(pa.describe_plan(inputs.config1(), sparse_pass=2)) == ["sparse_pass"]
+    c2p = pa.describe_plan(inputs.config2(), sparse_pass=2)
+    assert sorted(_kernels(c2p)) == ["gemm_mfma"] * 3 + ["sparse_pass"] * 4
     c3 = pa.describe_plan(inputs.config3())
     assert _kernels(c3) == ["sparse_count", "sparse_pass", "gemm_mfma"] * 2 + ["stream_k"]
     assert _kernels(pa.describe_plan(inputs.config3(), sparse_pass=-1)) == ["gemm_mfma", "gemm_mfma", "stream_k"]
@@ -88,14 +92,33 @@ def test_sparse_pass_plan():
         assert k["flag"] == s["flag"] == g["flag"] >= 0 and s["c"] == g["c"]
         bt = [p for p in d["plots"] if p["buf"] == s["bt"]][0]
         assert bt["vars"] == s["bt_vars"] and len(bt["vars"]) == 3
+    # the chain (2^30-MAC steps): no pass by default; with sparse_pass = 2 the
+    # four first-level contractions (B a plot) get the pass alone, with no
+    # count step and no decision, and the other levels no pass
     assert all(o["flag"] == -1 for o in pa.describe_plan(inputs.config2())["ops"] if o["op"] == "gemm_mfma")
+    c2 = pa.describe_plan(inputs.config2(), sparse_pass=2)
+    assert all(o["flag"] == -1 for o in c2["ops"] if o["op"] == "gemm_mfma")
+    sp = [o for o in c2["ops"] if o["op"] == "sparse_pass"]
+    assert len(sp) == 4 and all(o["flag"] == -1 and o["max_total"] == -1 for o in sp)
+    assert not [o for o in c2["ops"] if o["op"] == "sparse_count"]
+    # each of them reads the second plot of B only, so B's first plot is
+    # dropped: eight plots, as without the pass (twelve with the fallback)
+    assert len(c2["plots"]) == 8 and {p["buf"] for p in c2["plots"]} >= {o["bt"] for o in sp}
+    assert len(pa.describe_plan(inputs.config2())["plots"]) == 8
+    assert len(pa.describe_plan(inputs.config2(), sparse_pass=1)["plots"]) == 12
     c2 = pa.describe_plan(inputs.config2(), sparse_pass=1, sparse_max_density=5)
     sp2 = [o for o in c2["ops"] if o["op"] == "sparse_pass"]
     assert len(sp2) == 4                                    # level 1: B is a plot
-    assert all(o["max_total"] == 1024 * 1024 * 5 // 1024 for o in sp2)
+    assert all(o["max_total"] == 1024 * 1024 * 5 // 1024 and o["flag"] >= 0 for o in sp2)
+    assert len([o for o in c2["ops"] if o["op"] == "sparse_count"]) == 4
+    # sparse_pass = 2 on the ternary system: the pass alone for both r^5 steps
+    c3 = pa.describe_plan(inputs.config3(), sparse_pass=2)
+    assert _kernels(c3) == ["sparse_pass"] * 2 + ["stream_k"]
     for kw in (dict(plain=True), dict(single_launch=True), dict(sparse_pass=-1)):
-        assert not [o for o in pa.describe_plan(inputs.config3(), **kw)["ops"] if o["op"].startswith("sparse")], kw
-    assert _bad(inputs.config1(), sparse_pass=2) == pa.PA_EINVAL
+        for s in (inputs.config2(), inputs.config3()):
+            assert not [o for o in pa.describe_plan(s, **kw)["ops"] if o["op"].startswith("sparse")], kw
+    assert _bad(inputs.config1(), sparse_pass=3) == pa.PA_EINVAL
+    assert _bad(inputs.config1(), sparse_pass=-2) == pa.PA_EINVAL
     assert _bad(inputs.config1(), sparse_max_density=-1) == pa.PA_EINVAL
     assert _bad(inputs.config1(), sparse_max_density=1025) == pa.PA_EINVAL
 
@@ -187,16 +210,19 @@ def test_gemm_split_target_sets_the_k_split():
     grouped launch) splits K in 2 on the first level (256 tiles), in 4 on
     the second (128) and in 4 on the third (64 tiles; 4 parts of 256 bits is
     the most a 1024-bit K allows); a target of 1 never splits; every split
-    contraction gets one fill."""
+    contraction gets one fill.  With the first level on the sparse pass
+    alone the other two levels keep their splits."""
     s = inputs.config2(res=1024)
     ks = lambda d: [o["ksplit"] for o in d["ops"] if o["op"] == "gemm_mfma"]
     assert ks(pa.describe_plan(s)) == [2, 2, 4, 2, 2, 4, 4]
     assert ks(pa.describe_plan(s, gemm_split=1)) == [1] * 7
     assert ks(pa.describe_plan(s, gemm_split=128)) == [1, 1, 1, 1, 1, 1, 2]
+    assert ks(pa.describe_plan(s, sparse_pass=2)) == [4, 4, 4]
     fills = lambda d: [o for o in d["ops"] if o["op"] == "fill"]
     assert len(fills(pa.describe_plan(s))) == 7
     assert len(fills(pa.describe_plan(s, gemm_split=128))) == 1
     assert len(fills(pa.describe_plan(s, gemm_split=1))) == 0
+    assert len(fills(pa.describe_plan(s, sparse_pass=2))) == 3
 
 
 def test_mfma_operand_path_choice():

@@ -22,7 +22,7 @@ def _small_chains(n=24):
 
 MODES = [dict(), dict(graph=True), dict(single_launch=True), dict(single_launch=True, graph=True),
          dict(order=pa.ORDER_GREEDY, plot_strip=2, contract_units=512), dict(graph=True, sparse_pass=1),
-         dict(sparse_pass=1, sparse_max_density=1)]
+         dict(sparse_pass=1, sparse_max_density=1), dict(sparse_pass=2, graph=True), dict(sparse_pass=-1)]
 
 
 @pytest.mark.parametrize("mode", range(len(MODES)))

@@ -79,7 +79,8 @@ def test_sparse_pass_on_random_hypergraphs(seed):
     """Every MFMA contraction whose B is a plot gets a sparse pass (batch
     variables, several latent and output variables in any layout); with a
     density threshold of 1/1024 the MFMA kernel computes them instead, with
-    1024/1024 the pass always does: always the oracle's bits."""
+    1024/1024 the pass always does, and with sparse_pass = 2 the pass alone
+    (no count, no MFMA kernel): always the oracle's bits."""
     s = _random_small_system(4300 + seed)
     res = [a[2] for a in s.axes]
     ref = oracle.solve(res, [r.vars for r in s.relations], _oracle_plots(s), s.exposed)
@@ -88,7 +89,8 @@ def test_sparse_pass_on_random_hypergraphs(seed):
     for kw in (dict(sparse_pass=1), dict(sparse_pass=1, sparse_max_density=1),
                dict(sparse_pass=1, sparse_max_density=1024), dict(sparse_pass=1, gemm_split=2048, sparse_max_density=1),
                dict(sparse_pass=1, order=pa.ORDER_GREEDY, gemm_path=3), dict(sparse_pass=1, per_op=True),
-               dict(sparse_pass=1, per_op=True, sparse_max_density=1)):
+               dict(sparse_pass=1, per_op=True, sparse_max_density=1), dict(sparse_pass=2),
+               dict(sparse_pass=2, per_op=True), dict(sparse_pass=2, graph=True, gemm_split=2048)):
         got, _ = _solve(s, **kw)
         assert np.array_equal(got, ref), kw
 
@@ -100,7 +102,8 @@ def test_sparse_pass_chain_and_ternary():
         res = [a[2] for a in s.axes]
         ref = oracle.solve(res, [r.vars for r in s.relations], _oracle_plots(s), s.exposed)
         for kw in (dict(sparse_pass=1), dict(sparse_pass=1, sparse_max_density=1024),
-                   dict(sparse_pass=1, sparse_max_density=1), dict(sparse_pass=1, graph=True)):
+                   dict(sparse_pass=1, sparse_max_density=1), dict(sparse_pass=1, graph=True),
+                   dict(sparse_pass=2), dict(sparse_pass=2, graph=True), dict()):
             got, _ = _solve(s, **kw)
             assert np.array_equal(got, ref), (s.name, kw)
 
@@ -117,7 +120,7 @@ def test_sparse_pass_long_output_rows():
     assert sp and sp[0]["Nw"] > 2048 and sp[0]["Nw"] % 4 == 2
     res = [a[2] for a in s.axes]
     ref = oracle.solve(res, [r.vars for r in s.relations], _oracle_plots(s), s.exposed)
-    for kw in (dict(sparse_pass=1), dict(sparse_pass=1, per_op=True), dict(sparse_pass=-1)):
+    for kw in (dict(sparse_pass=1), dict(sparse_pass=1, per_op=True), dict(sparse_pass=-1), dict(sparse_pass=2)):
         got, _ = _solve(s, **kw)
         assert np.array_equal(got, ref), kw
 
@@ -192,6 +195,7 @@ def test_c3_full_size_sampled():
     note("c3 nnz", int(got.sum()), "flagged", rep["corners_flagged"])
     # the sparse pass (default here) and the MFMA operand paths alone give the same array
     assert [o["op"] for o in pa.describe_plan(s)["ops"]].count("sparse_pass") == 2
-    for kw in (dict(sparse_pass=-1), dict(sparse_pass=-1, gemm_path=2), dict(sparse_max_density=1)):
+    for kw in (dict(sparse_pass=-1), dict(sparse_pass=-1, gemm_path=2), dict(sparse_max_density=1),
+               dict(sparse_pass=2)):
         got2, _ = _solve(s, **kw)
         assert np.array_equal(got2, got), kw
