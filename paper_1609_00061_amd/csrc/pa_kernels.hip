@@ -1538,7 +1538,9 @@ struct RowBits {
     uint64_t nz;            // lanes whose nonzero word is not taken yet
     uint32_t cur, cbase;    // the word being walked and its Bt row of bit 0
 
-    __device__ __forceinline__ void load(uint32_t w0) {
+    // issue() starts the lane loads of words w0 .. w0 + 63; finish() waits
+    // for them (the ballot is their first use)
+    __device__ __forceinline__ void issue(uint32_t w0) {
         const uint32_t w = w0 + (threadIdx.x & 63);
         aw = 0u;
         base = 0u;
@@ -1548,8 +1550,14 @@ struct RowBits {
             aw = arow[w] & (lim <= 0 ? 0u : lim >= 32 ? ~0u : ((1u << lim) - 1u));
             base = ko * rkp + 32u * wp;
         }
+    }
+    __device__ __forceinline__ void finish() {
         nz = __ballot(aw != 0u);
         cur = 0u;
+    }
+    __device__ __forceinline__ void load(uint32_t w0) {
+        issue(w0);
+        finish();
     }
     __device__ __forceinline__ bool more() const { return cur != 0u || nz != 0u; }
     // the next set bit's Bt row, or -1 when the 64 words hold no more
@@ -1567,13 +1575,27 @@ struct RowBits {
     }
 };
 
+// The A row of wave-tile wt with its first 64 words' loads issued, so that
+// a wave can start them a tile ahead.
+__device__ __forceinline__ RowBits gather_row_issue(const GatherArgs &g, int64_t wt) {
+    const uint32_t row = fdiv((uint32_t)wt, g.fd_chunks);
+    RowBits rb;
+    rb.arow = gp(g.A) + (int64_t)row * g.Kw;
+    rb.Kw = (uint32_t)g.Kw;
+    rb.rwk = (uint32_t)g.rwk;
+    rb.rkp = (uint32_t)g.rkp;
+    rb.issue(0u);
+    return rb;
+}
+
 // One wave-tile of the sparse pass: words ch * 2048 .. + 2047 of output row
 // `row`; lane l holds words 4l + 256 j (j < 8), and for each set bit of the
 // A row the matching 2048 words of Bt are OR-ed in (eight independent
 // 16-byte loads per lane).  A row of at most 256 words is one wave-tile
 // with one position per lane, and four set bits are taken at a time so that
-// four Bt rows' loads are in flight together.
-__device__ void gather_wave(const GatherArgs &g, int64_t wt) {
+// four Bt rows' loads are in flight together.  rb comes from
+// gather_row_issue(g, wt).
+__device__ void gather_wave(const GatherArgs &g, int64_t wt, RowBits rb) {
     const int lane = threadIdx.x & 63;
     const uint32_t row = fdiv((uint32_t)wt, g.fd_chunks);
     const uint32_t ch = (uint32_t)wt - row * (uint32_t)g.chunks;
@@ -1582,16 +1604,12 @@ __device__ void gather_wave(const GatherArgs &g, int64_t wt) {
     const bool vec4 = (n & 3) == 0;
     const PA_G uint32_t *bt = gp(g.Bt) + (int64_t)b * g.sBt_b;
     PA_G uint32_t *crow = gp(g.C) + (int64_t)row * n;
-    RowBits rb;
-    rb.arow = gp(g.A) + (int64_t)row * g.Kw;
-    rb.Kw = (uint32_t)g.Kw;
-    rb.rwk = (uint32_t)g.rwk;
-    rb.rkp = (uint32_t)g.rkp;
     if (n <= 256) {
         const int64_t c = 4 * lane;
         uint4 acc = make_uint4(0u, 0u, 0u, 0u);
         for (uint32_t w0 = 0; w0 < rb.Kw; w0 += 64) {
-            rb.load(w0);
+            if (w0) rb.issue(w0);
+            rb.finish();
             while (rb.more()) {
                 int64_t k[4];
 #pragma unroll
@@ -1614,7 +1632,8 @@ __device__ void gather_wave(const GatherArgs &g, int64_t wt) {
 #pragma unroll
     for (int j = 0; j < 8; ++j) acc[j] = make_uint4(0u, 0u, 0u, 0u);
     for (uint32_t w0 = 0; w0 < rb.Kw; w0 += 64) {
-        rb.load(w0);
+        if (w0) rb.issue(w0);
+        rb.finish();
         while (rb.more()) {
             const PA_G uint32_t *src = bt + rb.next() * n;
             uint4 v[8];
@@ -1650,7 +1669,7 @@ __global__ __launch_bounds__(256) void k_gather(GatherArgs g, int64_t ntiles) {
     const int64_t nw = gather_wave_tiles(g);
     for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const int64_t wt = t * 4 + wave;
-        if (wt < nw) gather_wave(g, wt);
+        if (wt < nw) gather_wave(g, wt, gather_row_issue(g, wt));
     }
 }
 
@@ -1804,14 +1823,42 @@ __global__ __launch_bounds__(256, KIND % 10 == kStepGemm ? gemm_occupancy(KIND /
         return;
     }
     if (kind == kStepGather) {
-        // persistent waves over the launch's wave-tiles (no barriers)
+        // persistent waves over the launch's wave-tiles (no barriers); a
+        // wave decides once per step (its first tile of a step is the one
+        // with the lowest index, so the wave holding tile 0 writes the
+        // decision word) and starts the loads of its next tile's A row
+        // before working on the current one
         const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
         const int64_t slots = (t1 - t0) * 4, stride = (int64_t)gridDim.x * 4;
-        for (int64_t gi = (int64_t)blockIdx.x * 4 + wave; gi < slots; gi += stride) {
-            const int64_t item = t0 + (gi >> 2);
-            const PStep &st = steps[find_step(steps, first, count, item)];
-            const int64_t wt = (item - st.tile_base) * 4 + (gi & 3);
-            if (wt < gather_wave_tiles(st.gather) && gather_decide(st.gather, wt)) gather_wave(st.gather, wt);
+        int si = -1;
+        int64_t wt = 0;
+        // the first slot at or after gi holding a wave-tile (slots if none)
+        auto seek = [&](int64_t gi) {
+            for (; gi < slots; gi += stride) {
+                const int64_t item = t0 + (gi >> 2);
+                si = find_step(steps, first, count, item);
+                wt = (item - steps[si].tile_base) * 4 + (gi & 3);
+                if (wt < gather_wave_tiles(steps[si].gather)) break;
+            }
+            return gi;
+        };
+        int64_t gi = seek((int64_t)blockIdx.x * 4 + wave);
+        RowBits rb;
+        if (gi < slots) rb = gather_row_issue(steps[si].gather, wt);
+        int decided = -1;
+        bool run = false;
+        while (gi < slots) {
+            const int cs = si;
+            const int64_t cwt = wt;
+            const RowBits cur = rb;
+            gi = seek(gi + stride);
+            if (gi < slots) rb = gather_row_issue(steps[si].gather, wt);
+            const GatherArgs &g = steps[cs].gather;
+            if (cs != decided) {
+                decided = cs;
+                run = gather_decide(g, cwt);
+            }
+            if (run) gather_wave(g, cwt, cur);
         }
         return;
     }
