@@ -164,7 +164,8 @@ def _ternary(stream, steps=10, tuning=None):
     # algorithmic bytes of the sparse pass: every output word written, A and
     # the second plot of B read once
     sparse_bytes = sum(4.0 * (o["rows"] * o["Nw"] + words[o["a"]] + words[o["bt"]]) for o in sparse_ops)
-    macs = sum(o["macs"] for o in d["ops"] if o["op"] == "gemm_mfma")
+    # the two r^5 contractions' MACs, whichever kernel computes them
+    macs = d["total_macs"] - sum(o["macs"] for o in d["ops"] if o["op"] in ("stream_k", "stream_w"))
     kplan = plan
     if tuning.get("single_launch"):
         kplan = pa.Plan(s, order=pa.ORDER_EXHAUSTIVE, graph=True, **dict(tuning, single_launch=0))

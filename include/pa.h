@@ -379,7 +379,8 @@ int32_t pa_plan_step_samples(pa_plan *plan, float *features, float *log2_us, int
  * length (1/2/4/8 cells per thread), then the streaming tile (512..32768
  * output bits), then the MFMA K-split target (1, 64, 128, 256, 512, 1024,
  * 2048 work items), then the MFMA operand path (LDS-staged 128x128 or
- * 256x128 tiles, or direct), each
+ * 256x128 tiles, or direct), then (when opts->sparse_pass is 0) the sparse
+ * pass alone for every contraction whose B is a plot, each
  * from the best so far.  Every candidate is a batch built
  * with opts (graph capture included if opts->graph), executed once untimed,
  * then reps times between two events on `stream`.  Candidates that exceed
@@ -389,6 +390,8 @@ int32_t pa_plan_step_samples(pa_plan *plan, float *features, float *log2_us, int
  * tuning; synchronizes the stream. */
 typedef struct {
     int32_t single_launch, persist_wg, plot_strip, contract_units, gemm_split, gemm_path;
+    int32_t sparse_pass;      /* as in pa_opts: opts->sparse_pass, or 2 when that was
+                                 0 and the pass alone was faster                  */
     double ms;                /* milliseconds per execution of the whole workload */
 } pa_tuning;
 int pa_autotune(const pa_system *systems, int32_t n_sys, const int32_t *const *exposed, const int32_t *n_exposed,

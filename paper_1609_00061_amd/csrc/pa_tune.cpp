@@ -49,6 +49,7 @@ static std::string signature(const pa_system *systems, int32_t n_sys, const int3
         for (int j = 0; j < n_exposed[i]; ++j) fnv(h, (uint64_t)exposed[i][j]);
     }
     fnv(h, (uint64_t)o.order_policy * 97 + (uint64_t)o.precision * 7 + (uint64_t)o.graph);
+    fnv(h, (uint64_t)(o.sparse_pass + 1));
     int dev = 0;
     hipDeviceProp_t prop{};
     std::string arch = "?";
@@ -66,6 +67,7 @@ static void apply(pa_opts &o, const pa_tuning &t) {
     o.contract_units = t.contract_units;
     o.gemm_split = t.gemm_split;
     o.gemm_path = t.gemm_path;
+    o.sparse_pass = t.sparse_pass;
 }
 
 // Milliseconds per execution of a batch built with `o`, after one untimed
@@ -149,6 +151,7 @@ int autotune(const pa_system *systems, int32_t n_sys, const int32_t *const *expo
     cur.contract_units = base.contract_units > 0 ? base.contract_units : 2048;
     cur.gemm_split = base.gemm_split > 0 ? base.gemm_split : 512;
     cur.gemm_path = base.gemm_path > 0 ? base.gemm_path : 1;
+    cur.sparse_pass = base.sparse_pass;
     if (!rc) rc = trial(cur);
     for (int wg : cus_wg) {
         if (rc) break;
@@ -183,6 +186,13 @@ int autotune(const pa_system *systems, int32_t n_sys, const int32_t *const *expo
         if (rc || best.ms < 0.0 || path == best.gemm_path) continue;
         pa_tuning t = best;
         t.gemm_path = path;
+        rc = trial(t);
+    }
+    // 4) the sparse pass alone (exact whatever the density; faster when the
+    // plotted operands are sparse and the contractions large)
+    if (!rc && best.ms >= 0.0 && base.sparse_pass == 0) {
+        pa_tuning t = best;
+        t.sparse_pass = 2;
         rc = trial(t);
     }
     for (void *p : bufs) (void)hipFree(p);

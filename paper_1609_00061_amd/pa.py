@@ -68,7 +68,7 @@ class Opts(ctypes.Structure):
 class Tuning(ctypes.Structure):
     _fields_ = [("single_launch", ctypes.c_int32), ("persist_wg", ctypes.c_int32), ("plot_strip", ctypes.c_int32),
                 ("contract_units", ctypes.c_int32), ("gemm_split", ctypes.c_int32), ("gemm_path", ctypes.c_int32),
-                ("ms", ctypes.c_double)]
+                ("sparse_pass", ctypes.c_int32), ("ms", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
