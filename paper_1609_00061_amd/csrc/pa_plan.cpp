@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <utility>
 #include <chrono>
 #include <cmath>
 #include <cstdlib>
@@ -586,16 +587,19 @@ static void finish_contract(Op &op, bool has_b) {
     a.fd_rowbits = make_fastdiv((uint64_t)std::max<int64_t>(1, a.c_row_words * 32));
     a.fd_rowwords = make_fastdiv((uint64_t)std::max<int64_t>(1, a.c_row_words));
     // stream mode K: the row x bit shape of a wave's 64 outputs that touches
-    // the fewest 128-byte lines with its first 16-byte loads of A and B
+    // the fewest 128-byte lines with its first 16-byte loads of A and B; on a
+    // tie, the fewest 256-byte segments (longer runs: the ternary system's
+    // final step reads 8 runs of 256 bytes from each operand with 8 x 8 tiles
+    // instead of 16 x 128 and 4 x 512 with 4 x 16, 13% faster measured)
     a.tq = 1;
     if (op.mode == kModeStreamK && a.nout >= 2) {
-        auto lines = [&](int tq) {
+        auto lines = [&](int tq, int64_t bytes) {
             const int tp = 64 / tq;
             std::vector<int64_t> la, lb;
             for (int i = 0; i < tq; ++i)
                 for (int j = 0; j < tp; ++j) {
-                    la.push_back(4 * (i * a.a_str[a.nout - 2] + j * a.a_str[a.nout - 1]) / 128);
-                    if (has_b) lb.push_back(4 * (i * a.b_str[a.nout - 2] + j * a.b_str[a.nout - 1]) / 128);
+                    la.push_back(4 * (i * a.a_str[a.nout - 2] + j * a.a_str[a.nout - 1]) / bytes);
+                    if (has_b) lb.push_back(4 * (i * a.b_str[a.nout - 2] + j * a.b_str[a.nout - 1]) / bytes);
                 }
             std::sort(la.begin(), la.end());
             std::sort(lb.begin(), lb.end());
@@ -603,11 +607,11 @@ static void finish_contract(Op &op, bool has_b) {
                    (int64_t)(std::unique(lb.begin(), lb.end()) - lb.begin());
         };
         const int64_t rowbits = a.c_row_words * 32;
-        int64_t best = lines(1);
+        std::pair<int64_t, int64_t> best{lines(1, 128), lines(1, 256)};
         for (int tq : {2, 4, 8}) {
             const int64_t blocks = (a.n_out_rows + tq - 1) / tq * rowbits / (64 / tq);
             if (blocks >= ((int64_t)1 << 31)) continue;
-            const int64_t l = lines(tq);
+            const std::pair<int64_t, int64_t> l{lines(tq, 128), lines(tq, 256)};
             if (l < best) {
                 best = l;
                 a.tq = tq;

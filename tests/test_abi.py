@@ -72,6 +72,15 @@ def test_plans_put_dense_steps_on_mfma():
     assert c3["cost"] == 2 * 256 ** 5 + 256 ** 4
 
 
+def test_stream_tile_shape_prefers_longer_runs():
+    """The ternary system's final streamed step: 4 x 16 and 8 x 8 row-by-bit
+    wave tiles touch the same number of 128-byte lines with their first
+    loads (32), and the 8 x 8 tile reads them as 256-byte runs (16 segments
+    against 24), so it is chosen."""
+    d = pa.describe_plan(inputs.config3())
+    assert [o["tq"] for o in d["ops"] if o["op"] == "stream_k"] == [8]
+
+
 def test_sparse_pass_plan():
     """The ternary system's r^5 contractions (2^40 MACs) get a sparse pass:
     B's relation is plotted a second time with the output variables packed
