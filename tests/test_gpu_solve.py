@@ -125,6 +125,27 @@ def test_sparse_pass_long_output_rows():
         assert np.array_equal(got, ref), kw
 
 
+@pytest.mark.parametrize("case", ["short_rows", "long_rows"])
+def test_sparse_pass_two_latent_variables(case):
+    """A rows of more than 64 words (two latent variables packed into K: 128
+    and 80 words), so the pass reads each A row in several batches of 64
+    words; output rows of 2 words (one position per lane) and of 282 words
+    (more than 256: eight words per lane)."""
+    rng = inputs.SplitMix64(4500 if case == "short_rows" else 4501)
+    res = (48, 64, 64, 40) if case == "short_rows" else (40, 40, 40, 9000)
+    s = inputs.System([(-3.0, 3.0, r) for r in res],
+                      [inputs.random_relation(rng, (0, 1, 2)), inputs.random_relation(rng, (1, 2, 3))], (0, 3),
+                      name="two_latent_" + case)
+    sp = [o for o in pa.describe_plan(s, sparse_pass=2)["ops"] if o["op"] == "sparse_pass"]
+    assert len(sp) == 1 and sp[0]["Kw"] > 64 and (sp[0]["Nw"] <= 256) == (case == "short_rows")
+    ref = oracle.solve(list(res), [r.vars for r in s.relations], _oracle_plots(s), s.exposed)
+    note(case, "Kw", sp[0]["Kw"], "Nw", sp[0]["Nw"], "nnz", int(ref.sum()))
+    for kw in (dict(sparse_pass=2), dict(sparse_pass=2, per_op=True), dict(sparse_pass=1, sparse_max_density=1024),
+               dict(sparse_pass=1, sparse_max_density=1), dict(sparse_pass=-1)):
+        got, _ = _solve(s, **kw)
+        assert np.array_equal(got, ref), kw
+
+
 def test_huge_intermediate_with_grid_stride():
     """A Kronecker-heavy order whose intermediate has more than 2^32 bits:
     every contraction kernel loops over its output (grid-stride), so the
