@@ -58,7 +58,7 @@ def lib():
                                ctypes.POINTER(ctypes.c_longlong), ctypes.c_int]
         L.orc_plot.restype = ctypes.c_int
         L.orc_contract.argtypes = [ucp, ctypes.c_int, ip, ucp, ctypes.c_int, ip,
-                                   ctypes.c_int, ip, ip, ucp]
+                                   ctypes.c_int, ip, ip, ucp, ctypes.c_int]
         L.orc_contract.restype = ctypes.c_int
         L.orc_solve_entries.argtypes = [ctypes.c_int, ip, ctypes.c_int, ip, ip,
                                         ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ip,
@@ -135,9 +135,10 @@ def plot(rel, axes, nthreads: int = DEFAULT_THREADS) -> Tuple[np.ndarray, int]:
 
 # ------------------------------------------------------------ multiplication
 def contract(A: np.ndarray, a_vars: Sequence[int], B: np.ndarray, b_vars: Sequence[int],
-             out_vars: Sequence[int], var_res: Dict[int, int]) -> np.ndarray:
+             out_vars: Sequence[int], var_res: Dict[int, int], nthreads: int = DEFAULT_THREADS) -> np.ndarray:
     """C(out_vars) = OR over entries of vars(A) u vars(B) of A AND B (eqn GAM,
-    two inner packs)."""
+    two inner packs).  The entries of A are split over `nthreads` threads; the
+    result does not depend on the split (OR is idempotent)."""
     nv = max(list(a_vars) + list(b_vars) + list(out_vars) + [0]) + 1
     res = _i32([var_res.get(v, 1) for v in range(nv)])
     A = np.asarray(A, dtype=np.uint8, order="C")
@@ -147,7 +148,7 @@ def contract(A: np.ndarray, a_vars: Sequence[int], B: np.ndarray, b_vars: Sequen
     C = np.empty(tuple(var_res[v] for v in out_vars), dtype=np.uint8)
     av, bv, cv = _i32(a_vars), _i32(b_vars), _i32(out_vars)
     rc = lib().orc_contract(A.ctypes.data, len(a_vars), _ip(av), B.ctypes.data, len(b_vars), _ip(bv),
-                            len(out_vars), _ip(cv), _ip(res), C.ctypes.data)
+                            len(out_vars), _ip(cv), _ip(res), C.ctypes.data, int(nthreads))
     if rc:
         raise ValueError(f"orc_contract failed ({rc})")
     return C
@@ -203,13 +204,14 @@ def alg1_literal(var_res: Sequence[int], rel_vars: Sequence[Sequence[int]],
 
 def solve_pairwise(var_res: Dict[int, int], rel_vars: Sequence[Sequence[int]],
                    arrays: Sequence[np.ndarray], exposed: Sequence[int],
-                   merges: Sequence[Tuple[int, int]]) -> np.ndarray:
+                   merges: Sequence[Tuple[int, int]], nthreads: int = DEFAULT_THREADS, log=None) -> np.ndarray:
     """Execute a binary clustering (Sec. 3.5): factors are numbered 0..n-1 for
     the relations, and each merge (i, j) creates factor n, n+1, ... as the GAM of
     factors i and j whose output keeps every variable that is exposed or occurs
     in a factor not yet merged (the intermediate pack Q_C).  Variables private
     to a single relation are projected out first.  The last factor is permuted
-    to the exposed order."""
+    to the exposed order.  Each merge's operands are released once it is done;
+    `log`, if given, is called with a line per merge."""
     factors: Dict[int, Tuple[np.ndarray, Tuple[int, ...]]] = {}
     alive = set()
     for i, (A, vs) in enumerate(zip(arrays, rel_vars)):
@@ -225,7 +227,10 @@ def solve_pairwise(var_res: Dict[int, int], rel_vars: Sequence[Sequence[int]],
         for k in alive:
             others |= set(factors[k][1])
         keep = tuple(v for v in dict.fromkeys(vi + vj) if v in others)
-        C = contract(Ai, vi, Aj, vj, keep, var_res)
+        C = contract(Ai, vi, Aj, vj, keep, var_res, nthreads)
+        del factors[i], factors[j], Ai, Aj
+        if log is not None:
+            log(f"oracle merge ({i}, {j}) -> factor {nxt} over {keep}")
         factors[nxt] = (C, keep)
         alive.add(nxt)
         nxt += 1
@@ -235,7 +240,7 @@ def solve_pairwise(var_res: Dict[int, int], rel_vars: Sequence[Sequence[int]],
     if set(vs) != set(exposed):
         # project out anything left that is not exposed
         C2 = np.ones(tuple(var_res[v] for v in ()), dtype=np.uint8)
-        C = contract(C, vs, C2, (), tuple(v for v in vs if v in exposed), var_res)
+        C = contract(C, vs, C2, (), tuple(v for v in vs if v in exposed), var_res, nthreads)
         vs = tuple(v for v in vs if v in exposed)
     perm = [vs.index(v) for v in exposed]
     return np.ascontiguousarray(np.transpose(C, perm)) if len(perm) else C

@@ -223,40 +223,134 @@ int orc_plot(int n, int d, const double *coef, const double *lo, const double *h
 /* C(out_vars) = OR over all entries of vars(A) u vars(B) projecting to the
  * output entry of A(a_vars) AND B(b_vars): generalized array multiplication of
  * a two-pack cluster (Alg. "Generalized array multiplication" restricted to
- * two inner packs).  Loops over the entries of A; for every set entry, loops
- * over the variables that only B has.  var_res[v] = resolution of variable v.
- * Output vars must be a subset of vars(A) u vars(B) and distinct. */
+ * two inner packs).  var_res[v] = resolution of variable v.  Output vars must
+ * be a subset of vars(A) u vars(B) and distinct.
+ *
+ * Written as the i-k-j loop of a Boolean matrix product: the shared
+ * variables play k, the variables only A has i, those only B has j.  For
+ * every set entry of A (i, k) the loop visits the set entries of B with the
+ * same k and sets C at the output entry their union projects to.  To find
+ * those B entries the set entries of B are first listed as (k, j) pairs
+ * sorted by k; a B without variables of its own is read directly.
+ *
+ * The entries of A are split into contiguous ranges, one per thread.  Each
+ * output byte is only ever set to 1 (the OR of the semiring), so the threads
+ * write with relaxed atomic stores and the result does not depend on how the
+ * range is split or on the thread count. */
+typedef struct { long k, j; } kj_pair;
+
+static int kj_cmp(const void *x, const void *y) {
+    const kj_pair *p = (const kj_pair *)x, *q = (const kj_pair *)y;
+    if (p->k != q->k) return p->k < q->k ? -1 : 1;
+    return (p->j > q->j) - (p->j < q->j);
+}
+
+typedef struct {
+    const unsigned char *A, *B;
+    unsigned char *C;
+    int na, nb, nc, nbx, nsh;
+    const int *a_vars, *b_vars, *c_vars, *var_res;
+    int bx[ORC_MAXDIM], sh[ORC_MAXDIM];   /* variables only in B; variables in both */
+    const kj_pair *pairs;                 /* set entries of B sorted by k (nbx > 0) */
+    long npairs;
+    long begin, end;
+} contract_job;
+
+static void *contract_worker(void *arg) {
+    contract_job *j = (contract_job *)arg;
+    int val[ORC_MAXV];
+    for (long ea = j->begin; ea < j->end; ++ea) {
+        if (!j->A[ea]) continue;
+        long rem = ea;
+        for (int i = j->na - 1; i >= 0; --i) {
+            val[j->a_vars[i]] = (int)(rem % j->var_res[j->a_vars[i]]);
+            rem /= j->var_res[j->a_vars[i]];
+        }
+        if (j->nbx == 0) {               /* every variable of B is bound by A */
+            long ib = 0;
+            for (int i = 0; i < j->nb; ++i) ib = ib * j->var_res[j->b_vars[i]] + val[j->b_vars[i]];
+            if (!j->B[ib]) continue;
+            long ic = 0;
+            for (int i = 0; i < j->nc; ++i) ic = ic * j->var_res[j->c_vars[i]] + val[j->c_vars[i]];
+            __atomic_store_n(&j->C[ic], (unsigned char)1, __ATOMIC_RELAXED);
+            continue;
+        }
+        long k = 0;
+        for (int i = 0; i < j->nsh; ++i) k = k * j->var_res[j->sh[i]] + val[j->sh[i]];
+        long lo = 0, hi = j->npairs;     /* first pair with key >= k */
+        while (lo < hi) {
+            long mid = lo + (hi - lo) / 2;
+            if (j->pairs[mid].k < k) lo = mid + 1; else hi = mid;
+        }
+        for (long p = lo; p < j->npairs && j->pairs[p].k == k; ++p) {
+            long r2 = j->pairs[p].j;
+            for (int i = j->nbx - 1; i >= 0; --i) {
+                val[j->bx[i]] = (int)(r2 % j->var_res[j->bx[i]]);
+                r2 /= j->var_res[j->bx[i]];
+            }
+            long ic = 0;
+            for (int i = 0; i < j->nc; ++i) ic = ic * j->var_res[j->c_vars[i]] + val[j->c_vars[i]];
+            __atomic_store_n(&j->C[ic], (unsigned char)1, __ATOMIC_RELAXED);
+        }
+    }
+    return NULL;
+}
+
 int orc_contract(const unsigned char *A, int na, const int *a_vars,
                  const unsigned char *B, int nb, const int *b_vars,
-                 int nc, const int *c_vars, const int *var_res, unsigned char *C) {
+                 int nc, const int *c_vars, const int *var_res, unsigned char *C, int nthreads) {
     int in_a[ORC_MAXV] = {0}, in_b[ORC_MAXV] = {0};
     for (int i = 0; i < na; ++i) { if (a_vars[i] < 0 || a_vars[i] >= ORC_MAXV || in_a[a_vars[i]]) return -1; in_a[a_vars[i]] = 1; }
     for (int i = 0; i < nb; ++i) { if (b_vars[i] < 0 || b_vars[i] >= ORC_MAXV || in_b[b_vars[i]]) return -1; in_b[b_vars[i]] = 1; }
     for (int i = 0; i < nc; ++i) if (c_vars[i] < 0 || c_vars[i] >= ORC_MAXV || !(in_a[c_vars[i]] || in_b[c_vars[i]])) return -1;
     if (na > ORC_MAXDIM || nb > ORC_MAXDIM || nc > ORC_MAXDIM) return -1;
-    int bx[ORC_MAXDIM], nbx = 0;              /* variables only in B */
-    for (int i = 0; i < nb; ++i) if (!in_a[b_vars[i]]) bx[nbx++] = b_vars[i];
-    long sizeA = 1, sizeBX = 1, sizeC = 1;
+    contract_job base;
+    memset(&base, 0, sizeof(base));
+    base.A = A; base.B = B; base.C = C;
+    base.na = na; base.nb = nb; base.nc = nc;
+    base.a_vars = a_vars; base.b_vars = b_vars; base.c_vars = c_vars; base.var_res = var_res;
+    for (int i = 0; i < nb; ++i) {
+        if (in_a[b_vars[i]]) base.sh[base.nsh++] = b_vars[i];
+        else base.bx[base.nbx++] = b_vars[i];
+    }
+    long sizeA = 1, sizeB = 1, sizeC = 1;
     for (int i = 0; i < na; ++i) sizeA *= var_res[a_vars[i]];
-    for (int i = 0; i < nbx; ++i) sizeBX *= var_res[bx[i]];
+    for (int i = 0; i < nb; ++i) sizeB *= var_res[b_vars[i]];
     for (int i = 0; i < nc; ++i) sizeC *= var_res[c_vars[i]];
     memset(C, 0, (size_t)sizeC);
-    int val[ORC_MAXV];
-    for (long ea = 0; ea < sizeA; ++ea) {
-        if (!A[ea]) continue;
-        long rem = ea;
-        for (int i = na - 1; i >= 0; --i) { val[a_vars[i]] = (int)(rem % var_res[a_vars[i]]); rem /= var_res[a_vars[i]]; }
-        for (long eb = 0; eb < sizeBX; ++eb) {
-            long r2 = eb;
-            for (int i = nbx - 1; i >= 0; --i) { val[bx[i]] = (int)(r2 % var_res[bx[i]]); r2 /= var_res[bx[i]]; }
-            long ib = 0;
-            for (int i = 0; i < nb; ++i) ib = ib * var_res[b_vars[i]] + val[b_vars[i]];
-            if (!B[ib]) continue;
-            long ic = 0;
-            for (int i = 0; i < nc; ++i) ic = ic * var_res[c_vars[i]] + val[c_vars[i]];
-            C[ic] = 1;
+    kj_pair *pairs = NULL;
+    if (base.nbx > 0) {
+        long n = 0;
+        for (long eb = 0; eb < sizeB; ++eb) n += (B[eb] != 0);
+        pairs = (kj_pair *)malloc(sizeof(kj_pair) * (size_t)(n > 0 ? n : 1));
+        if (!pairs) return -2;
+        int val[ORC_MAXV];
+        long t = 0;
+        for (long eb = 0; eb < sizeB; ++eb) {
+            if (!B[eb]) continue;
+            long rem = eb;
+            for (int i = nb - 1; i >= 0; --i) { val[b_vars[i]] = (int)(rem % var_res[b_vars[i]]); rem /= var_res[b_vars[i]]; }
+            long k = 0, j = 0;
+            for (int i = 0; i < base.nsh; ++i) k = k * var_res[base.sh[i]] + val[base.sh[i]];
+            for (int i = 0; i < base.nbx; ++i) j = j * var_res[base.bx[i]] + val[base.bx[i]];
+            pairs[t].k = k; pairs[t].j = j; ++t;
         }
+        qsort(pairs, (size_t)n, sizeof(kj_pair), kj_cmp);
+        base.pairs = pairs;
+        base.npairs = n;
     }
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > 64) nthreads = 64;
+    pthread_t th[64];
+    contract_job jobs[64];
+    for (int t = 0; t < nthreads; ++t) {
+        jobs[t] = base;
+        jobs[t].begin = sizeA * t / nthreads;
+        jobs[t].end = sizeA * (t + 1) / nthreads;
+        pthread_create(&th[t], NULL, contract_worker, &jobs[t]);
+    }
+    for (int t = 0; t < nthreads; ++t) pthread_join(th[t], NULL);
+    free(pairs);
     return 0;
 }
 

@@ -211,3 +211,88 @@ def all_binary_trees(items: Sequence[int]):
             for lt in all_binary_trees(left):
                 for rt in all_binary_trees(right):
                     yield (lt, rt)
+
+
+# ------------------------------------------------- bounded tree for the oracle
+def bounded_merges(packs: Sequence[Tuple[int, ...]], exposed: Sequence[int], res: Dict[int, int],
+                   max_out: int = 4, max_scope: int = 6):
+    """A binary cluster tree (Sec. 3.5) for executing a diagram on the oracle
+    with byte arrays: among trees whose every merge joins two clusters that
+    share a link (the whole diagram being connected), whose intermediate packs
+    Q_C (Def. "efficient_factorization") have at most max_out links and whose
+    merges range over at most max_scope links, the one of least naive cost
+    (eqn naive_cost, the product of the resolutions of the links a merge ranges
+    over; a leaf enters a merge with its own Q).  Returns the merges in the
+    format of oracle.solve_pairwise, or None when no such tree exists."""
+    n = len(packs)
+    ex = set(exposed)
+
+    def q_of(block):
+        return frozenset(q_pack(block, packs, ex))
+
+    def links_of(block):
+        return set(v for i in block for v in packs[i])
+
+    def shares(b1, b2):
+        return bool(links_of(b1) & links_of(b2))
+
+    def connected(block):
+        block = sorted(block)
+        seen = {block[0]}
+        frontier = [block[0]]
+        while frontier:
+            i = frontier.pop()
+            for j in block:
+                if j not in seen and set(packs[i]) & set(packs[j]):
+                    seen.add(j)
+                    frontier.append(j)
+        return len(seen) == len(block)
+
+    @lru_cache(maxsize=None)
+    def best(S: FrozenSet[int]):
+        """(cost, tree) of the cheapest admissible tree over S, or None."""
+        if len(S) == 1:
+            return 0, next(iter(S))
+        if len(q_of(S)) > max_out:
+            return None
+        items = sorted(S)
+        first, rest = items[0], items[1:]
+        out = None
+        for k in range(0, len(rest)):
+            for comb in itertools.combinations(rest, k):
+                L = frozenset((first,) + comb)
+                R = S - L
+                if not connected(L) or not connected(R) or not shares(L, R):
+                    continue
+                span = q_of(L) | q_of(R)
+                if len(span) > max_scope:
+                    continue
+                bl, br = best(L), best(R)
+                if bl is None or br is None:
+                    continue
+                c = bl[0] + br[0]
+                node = 1
+                for v in span:
+                    node *= res[v]
+                c += node
+                if out is None or c < out[0]:
+                    out = (c, (bl[1], br[1]))
+        return out
+
+    full = frozenset(range(n))
+    got = best(full)
+    if got is None:
+        return None
+    merges: List[Tuple[int, int]] = []
+    counter = [n]
+
+    def emit(t):
+        if isinstance(t, int):
+            return t
+        a, b = emit(t[0]), emit(t[1])
+        merges.append((a, b))
+        counter[0] += 1
+        return counter[0] - 1
+
+    emit(got[1])
+    return merges
