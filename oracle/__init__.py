@@ -8,6 +8,9 @@ own module and holds none of the method's arithmetic.
 
 Contents (each function cites the paper passage it follows):
   axis, eval_poly, corner_values, plot   -- Sec. 3.2 plotting (C, pa_oracle.c)
+  plot_ineq                              -- corner plot of f <= 0 / f < 0 (C)
+  centers, plot_center                   -- Def. sample_in_center (C)
+  plot_relation                          -- dispatch on rule and target
   contract                               -- Sec. 3.3 GAM of a two-pack cluster (C)
   solve_entries, solve                   -- eqn GAM for a whole diagram with
                                             short-circuit AND/OR (C)
@@ -57,6 +60,13 @@ def lib():
         L.orc_plot.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, dp, ip, ucp,
                                ctypes.POINTER(ctypes.c_longlong), ctypes.c_int]
         L.orc_plot.restype = ctypes.c_int
+        L.orc_plot_ineq.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, dp, ip, ctypes.c_int, ucp, ctypes.c_int]
+        L.orc_plot_ineq.restype = ctypes.c_int
+        L.orc_centers.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_int, dp]
+        L.orc_centers.restype = ctypes.c_int
+        L.orc_plot_center.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, dp, ip, ctypes.c_double, ctypes.c_int,
+                                      ucp, ctypes.c_int]
+        L.orc_plot_center.restype = ctypes.c_int
         L.orc_contract.argtypes = [ucp, ctypes.c_int, ip, ucp, ctypes.c_int, ip,
                                    ctypes.c_int, ip, ip, ucp, ctypes.c_int]
         L.orc_contract.restype = ctypes.c_int
@@ -131,6 +141,53 @@ def plot(rel, axes, nthreads: int = DEFAULT_THREADS) -> Tuple[np.ndarray, int]:
     if rc:
         raise ValueError(f"orc_plot failed ({rc})")
     return out, int(nz.value)
+
+
+def plot_ineq(rel, axes, target: int, nthreads: int = DEFAULT_THREADS) -> np.ndarray:
+    """Corner plot of f <= 0 (target 1) or f < 0 (target 2) (Sec. 3.2): a cell is
+    set iff one of its corners satisfies the inequality."""
+    lo, hi, res = _rel_axes(rel, axes)
+    out = np.empty(tuple(int(r) for r in res), dtype=np.uint8)
+    c = np.ascontiguousarray(rel.coef, dtype=np.float64)
+    if lib().orc_plot_ineq(len(rel.vars), rel.degree, _dp(c), _dp(lo), _dp(hi), _ip(res), int(target),
+                           out.ctypes.data, nthreads):
+        raise ValueError("orc_plot_ineq failed")
+    return out
+
+
+def centers(lo: float, hi: float, r: int) -> np.ndarray:
+    """Pixel centres lo + (k + 1/2) * ((hi - lo) / r), k = 0..r-1 (eqn Pixel_def)."""
+    x = np.empty(r, dtype=np.float64)
+    if lib().orc_centers(float(lo), float(hi), int(r), _dp(x)):
+        raise ValueError("bad axis")
+    return x
+
+
+def plot_center(rel, axes, eps: float, target: int = 0, nthreads: int = DEFAULT_THREADS) -> np.ndarray:
+    """epsilon-tolerance sample-in-center plot (Def. sample_in_center): a cell
+    is set iff the distance of f(centre) to the target set is at most eps
+    (target 0: |f| <= eps; 1: f <= eps; 2: f < eps)."""
+    lo, hi, res = _rel_axes(rel, axes)
+    out = np.empty(tuple(int(r) for r in res), dtype=np.uint8)
+    c = np.ascontiguousarray(rel.coef, dtype=np.float64)
+    if lib().orc_plot_center(len(rel.vars), rel.degree, _dp(c), _dp(lo), _dp(hi), _ip(res), float(eps),
+                             int(target), out.ctypes.data, nthreads):
+        raise ValueError("orc_plot_center failed")
+    return out
+
+
+def plot_relation(rel, axes, rule: str = "corner", eps: float = 0.0, nthreads: int = DEFAULT_THREADS) -> np.ndarray:
+    """The plot of a relation under a plotting rule: "corner" (sign change at
+    the cell corners for f = 0, a satisfying corner for f <= 0 / f < 0) or
+    "center" (the epsilon-tolerance sample-in-center plot).  The relation's
+    `target` (0: f = 0, 1: f <= 0, 2: f < 0; 0 if absent) selects the target
+    subset."""
+    target = int(getattr(rel, "target", 0))
+    if rule == "center":
+        return plot_center(rel, axes, eps, target, nthreads)
+    if target == 0:
+        return plot(rel, axes, nthreads)[0]
+    return plot_ineq(rel, axes, target, nthreads)
 
 
 # ------------------------------------------------------------ multiplication

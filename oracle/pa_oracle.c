@@ -219,6 +219,119 @@ int orc_plot(int n, int d, const double *coef, const double *lo, const double *h
     return 0;
 }
 
+/* Corner plot of an inequality (Sec. 3.2: relations f <= 0 and f < 0, the
+ * target subsets (-inf, 0] and (-inf, 0) of Def. "functionally_defined"),
+ * by the same corner sampling as orc_plot: a cell (closed) is set iff one of
+ * its 2^n corners satisfies the inequality, target 1: f <= 0, target 2:
+ * f < 0 (a NaN corner satisfies neither).  Such a corner is a point of the
+ * closed cell in the relation.  out: one byte per cell, as orc_plot. */
+int orc_plot_ineq(int n, int d, const double *coef, const double *lo, const double *hi,
+                  const int *res, int target, unsigned char *out, int nthreads) {
+    if (target != 1 && target != 2) return -1;
+    long nc = 1, ncell = 1;
+    for (int a = 0; a < n; ++a) { nc *= res[a] + 1; ncell *= res[a]; }
+    double *vals = (double *)malloc(sizeof(double) * nc);
+    if (!vals) return -2;
+    if (orc_corner_values(n, d, coef, lo, hi, res, vals, nthreads)) { free(vals); return -1; }
+    for (long cell = 0; cell < ncell; ++cell) {
+        long rem = cell;
+        int idx[ORC_MAXN];
+        for (int a = n - 1; a >= 0; --a) { idx[a] = (int)(rem % res[a]); rem /= res[a]; }
+        int hit = 0;
+        for (int corner = 0; corner < (1 << n); ++corner) {
+            long off = 0;
+            for (int a = 0; a < n; ++a) off = off * (res[a] + 1) + idx[a] + ((corner >> a) & 1);
+            double f = vals[off];
+            if (target == 1 ? (f <= 0.0) : (f < 0.0)) hit = 1;
+        }
+        out[cell] = (unsigned char)hit;
+    }
+    free(vals);
+    return 0;
+}
+
+/* Centre of pixel k of one axis: lo + (k + 1/2) * ((hi - lo) / r), k = 0..r-1
+ * (eqn Pixel_def, 0-based; the sample code's centre form in App. A); the
+ * step, the product and the sum are each rounded once. */
+int orc_centers(double lo, double hi, int r, double *c) {
+    if (r < 1 || !(lo <= hi)) return -1;
+    double delta = (hi - lo) / (double)r;
+    for (int k = 0; k < r; ++k) {
+        double t = ((double)k + 0.5) * delta;
+        c[k] = lo + t;
+    }
+    return 0;
+}
+
+/* epsilon-tolerance sample-in-center plot (Def. sample_in_center): cell e is
+ * set iff the {c_e}-error of the relation achieves eps, i.e. the distance
+ * from f(c_e) to the target subset S is at most eps (Def. plot_error:
+ * "achieves u" means some distance in [0, u]).  Target 0, S = {0}: |f| <= eps;
+ * target 1, S = (-inf, 0]: f <= eps; target 2, S = (-inf, 0): the distances
+ * to S form the open ray (f, inf) when f >= 0, so f < eps.  A NaN value
+ * achieves nothing.  f(c_e) is the canonical FP64 value (orc_eval's Horner)
+ * at the FP64 centre.  out: one byte per cell, row-major over (r_0..r_{n-1}). */
+typedef struct {
+    const poly_t *p;
+    const double *const *cx;
+    const int *res;
+    double eps;
+    int target;
+    unsigned char *out;
+    long begin, end;
+} center_job;
+
+static void *center_worker(void *arg) {
+    center_job *j = (center_job *)arg;
+    int n = j->p->n;
+    for (long cell = j->begin; cell < j->end; ++cell) {
+        long rem = cell;
+        double x[ORC_MAXN];
+        for (int a = n - 1; a >= 0; --a) {
+            long k = rem % j->res[a];
+            rem /= j->res[a];
+            x[a] = j->cx[a][k];
+        }
+        int e[ORC_MAXN] = {0};
+        double f = horner(j->p, n, j->p->d, e, x);
+        int on;
+        if (j->target == 0) on = fabs(f) <= j->eps;
+        else if (j->target == 1) on = f <= j->eps;
+        else on = f < j->eps;
+        j->out[cell] = (unsigned char)on;
+    }
+    return NULL;
+}
+
+int orc_plot_center(int n, int d, const double *coef, const double *lo, const double *hi, const int *res,
+                    double eps, int target, unsigned char *out, int nthreads) {
+    if (target < 0 || target > 2 || !(eps >= 0.0)) return -1;
+    poly_t *p = (poly_t *)malloc(sizeof(poly_t));
+    if (!p || poly_init(p, n, d, coef)) { free(p); return -1; }
+    double *cx[ORC_MAXN];
+    long ncell = 1;
+    for (int a = 0; a < n; ++a) {
+        if (res[a] < 1) { free(p); return -1; }
+        cx[a] = (double *)malloc(sizeof(double) * res[a]);
+        if (orc_centers(lo[a], hi[a], res[a], cx[a])) { free(p); return -1; }
+        ncell *= res[a];
+    }
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > 64) nthreads = 64;
+    pthread_t th[64];
+    center_job jobs[64];
+    for (int t = 0; t < nthreads; ++t) {
+        jobs[t].p = p; jobs[t].cx = (const double *const *)cx; jobs[t].res = res;
+        jobs[t].eps = eps; jobs[t].target = target; jobs[t].out = out;
+        jobs[t].begin = ncell * t / nthreads; jobs[t].end = ncell * (t + 1) / nthreads;
+        pthread_create(&th[t], NULL, center_worker, &jobs[t]);
+    }
+    for (int t = 0; t < nthreads; ++t) pthread_join(th[t], NULL);
+    for (int a = 0; a < n; ++a) free(cx[a]);
+    free(p);
+    return 0;
+}
+
 /* ------------------------------------------------------ pairwise contraction */
 /* C(out_vars) = OR over all entries of vars(A) u vars(B) projecting to the
  * output entry of A(a_vars) AND B(b_vars): generalized array multiplication of

@@ -27,6 +27,9 @@ CASES = [
     ((0, 1, 2), (1,), (0,)),             # pre-reduce of 2, vector
     ((0,), (0,), (0,)),                  # elementwise AND
     ((0, 1), (1, 2), (1,)),              # kept shared index, both others latent
+    ((0, 1), (2, 1), (0, 2)),            # B's shared index after its own one
+    ((0, 1, 2), (3, 2, 1), (3, 0)),      # two shared indices in reverse order in B
+    ((2, 0), (3, 1, 0), (1, 3, 2)),      # B's own indices around the shared one
 ]
 
 
@@ -44,6 +47,19 @@ def test_pairwise_contract_matches_printed_algorithm(case):
         # both packs do not occur here.
         ref = oracle.alg1_literal(var_res, [a_vars, b_vars], [A, B], out_vars)
         assert np.array_equal(C, ref)
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_pairwise_contract_independent_of_threads(case):
+    """The contraction's entries of A are split over threads; the output does
+    not depend on the split."""
+    a_vars, b_vars, out_vars = case
+    res = {0: 7, 1: 5, 2: 6, 3: 4}
+    A = _rand([res[v] for v in a_vars], 0.3, 300)
+    B = _rand([res[v] for v in b_vars], 0.3, 301)
+    ref = oracle.contract(A, a_vars, B, b_vars, out_vars, res, nthreads=1)
+    for t in (2, 3, 7, 64):
+        assert np.array_equal(oracle.contract(A, a_vars, B, b_vars, out_vars, res, nthreads=t), ref), t
 
 
 def test_matmul_special_case():

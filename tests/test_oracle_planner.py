@@ -108,3 +108,96 @@ def test_binary_dp_matches_brute_force(seed):
     brute = min(P.tree_cost(t, packs, exposed, res=res)[0] for t in P.all_binary_trees(range(n)))
     assert best == brute
     assert P.tree_cost(tree, packs, exposed, res=res)[0] == best
+
+
+def _admissible(tree, packs, exposed, max_out, max_scope):
+    """Every merge of a binary tree joins two connected clusters sharing a
+    link, keeps at most max_out links and ranges over at most max_scope."""
+    def links(block):
+        return set(v for i in block for v in packs[i])
+
+    def connected(block):
+        block = list(block)
+        seen, todo = {block[0]}, [block[0]]
+        while todo:
+            i = todo.pop()
+            for j in block:
+                if j not in seen and set(packs[i]) & set(packs[j]):
+                    seen.add(j)
+                    todo.append(j)
+        return len(seen) == len(block)
+
+    def rec(t):
+        if isinstance(t, int):
+            return True
+        L, R = P.leaves(t[0]), P.leaves(t[1])
+        if not (connected(L) and connected(R) and links(L) & links(R)):
+            return False
+        if len(P.q_pack(L + R, packs, exposed)) > max_out:
+            return False
+        if len(P.q_pack(L, packs, exposed) | P.q_pack(R, packs, exposed)) > max_scope:
+            return False
+        return rec(t[0]) and rec(t[1])
+    return rec(tree)
+
+
+def _tree_of(merges, n):
+    f = {i: i for i in range(n)}
+    for t, (a, b) in enumerate(merges):
+        f[n + t] = (f[a], f[b])
+    return f[n + len(merges) - 1] if merges else 0
+
+
+def _bounded_cost(tree, packs, exposed, res):
+    if isinstance(tree, int):
+        return 0
+    L, R = P.leaves(tree[0]), P.leaves(tree[1])
+    node = 1
+    for v in P.q_pack(L, packs, exposed) | P.q_pack(R, packs, exposed):
+        node *= res[v]
+    return node + _bounded_cost(tree[0], packs, exposed, res) + _bounded_cost(tree[1], packs, exposed, res)
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_bounded_merges_brute_force(seed):
+    """The oracle's bounded tree is the cheapest admissible binary tree, found
+    by brute force over every binary tree; None iff there is none."""
+    rng = inputs.SplitMix64(900 + seed)
+    nv = rng.randint(4, 8)
+    n = rng.randint(2, 6)
+    packs = [tuple(rng.randint(0, nv - 1) for _ in range(rng.randint(2, 3))) for _ in range(n)]
+    packs = [tuple(dict.fromkeys(p)) for p in packs]
+    exposed = tuple(sorted(set(rng.randint(0, nv - 1) for _ in range(rng.randint(1, 3)))))
+    res = {v: rng.randint(2, 9) for v in range(nv)}
+    max_out, max_scope = rng.randint(2, 4), rng.randint(3, 5)
+    got = P.bounded_merges(packs, exposed, res, max_out=max_out, max_scope=max_scope)
+    trees = [t for t in P.all_binary_trees(range(n)) if _admissible(t, packs, exposed, max_out, max_scope)]
+    if not trees:
+        assert got is None
+        return
+    best = min(_bounded_cost(t, packs, exposed, res) for t in trees)
+    tree = _tree_of(got, n)
+    assert _admissible(tree, packs, exposed, max_out, max_scope)
+    assert _bounded_cost(tree, packs, exposed, res) == best
+
+
+def test_generator_scope_filter_agrees_with_oracle():
+    """The hypergraph generator's structural filter and the oracle's bounded
+    tree search (two separate implementations) agree on which diagrams admit
+    a tree within the caps."""
+    rng = inputs.SplitMix64(950)
+    checked = {True: 0, False: 0}
+    for _ in range(60):
+        nv = rng.randint(5, 9)
+        n = rng.randint(nv - 1, nv + 1)
+        packs = [tuple(dict.fromkeys(rng.randint(0, nv - 1) for _ in range(rng.randint(2, 3)))) for _ in range(n)]
+        if len(set(v for p in packs for v in p)) != nv:
+            continue
+        exposed = tuple(sorted(set(rng.randint(0, nv - 1) for _ in range(rng.randint(2, 4)))))
+        res = {v: 4 for v in range(nv)}
+        for max_out, max_scope in ((2, 3), (3, 4), (4, 6)):
+            a = inputs._fits_scope_caps(packs, exposed, max_out, max_scope)
+            b = P.bounded_merges(packs, exposed, res, max_out=max_out, max_scope=max_scope) is not None
+            assert a == b, (packs, exposed, max_out, max_scope)
+            checked[a] += 1
+    assert checked[True] > 10 and checked[False] > 10, checked
