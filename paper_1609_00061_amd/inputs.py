@@ -77,11 +77,15 @@ def n_monomials(arity: int, degree: int) -> int:
     return math.comb(arity + degree, degree)
 
 
+TARGET_EQ, TARGET_LE, TARGET_LT = 0, 1, 2     # f = 0, f <= 0, f < 0
+
+
 @dataclass
 class Relation:
     vars: Tuple[int, ...]          # distinct variable ids, declared order
     degree: int
     coef: np.ndarray               # float64, graded-lex order
+    target: int = TARGET_EQ        # target subset of f: {0}, (-inf, 0] or (-inf, 0)
 
     def __post_init__(self):
         self.vars = tuple(int(v) for v in self.vars)
@@ -110,6 +114,8 @@ class System:
         for rel in self.relations:
             h.update(np.array(rel.vars + (rel.degree,), dtype="<i8").tobytes())
             h.update(rel.coef.astype("<f8").tobytes())
+            if rel.target:
+                h.update(np.array([rel.target], dtype="<i8").tobytes())
         h.update(np.array(self.exposed, dtype="<i8").tobytes())
         return h.hexdigest()
 
@@ -167,9 +173,82 @@ def config4(n_systems: int = 512, index: int = 0, rmin: int = 64, rmax: int = 20
     return out
 
 
+def _fits_scope_caps(rel_vars: Sequence[Tuple[int, ...]], exposed: Sequence[int], max_out: int = 4,
+                     max_scope: int = 6) -> bool:
+    """Structural filter of the hypergraph workload (variable sets only; no
+    plotting, contraction or cost arithmetic): is there a binary merge tree of
+    the relations, each merge joining two connected clusters that share a
+    variable, in which every merge ranges over at most `max_scope` variables
+    and keeps at most `max_out`?  A cluster S keeps the variables of its
+    relations that are exposed or occur in a relation outside S; a merge of S1
+    and S2 ranges over the union of what they keep.  At 128 cells per axis
+    the caps are 128^4 bits (32 MiB) per intermediate and 128^6 pairs per
+    step."""
+    m = len(rel_vars)
+    rv = [sum(1 << v for v in vs) for vs in rel_vars]
+    ex = sum(1 << v for v in exposed)
+    full = (1 << m) - 1
+    var_of = [0] * (1 << m)                 # union of the variables of a relation set
+    for S in range(1, 1 << m):
+        low = S & -S
+        var_of[S] = var_of[S ^ low] | rv[low.bit_length() - 1]
+    adj = [0] * m
+    for i in range(m):
+        for j in range(m):
+            if i != j and rv[i] & rv[j]:
+                adj[i] |= 1 << j
+
+    def kept(S):
+        return var_of[S] & (var_of[full ^ S] | ex)
+
+    conn = {}
+
+    def connected(S):
+        c = conn.get(S)
+        if c is None:
+            seen = frontier = S & -S
+            while frontier:
+                nb, f = 0, frontier
+                while f:
+                    b = f & -f
+                    f ^= b
+                    nb |= adj[b.bit_length() - 1]
+                frontier = nb & S & ~seen
+                seen |= frontier
+            c = conn[S] = seen == S
+        return c
+
+    memo = {}
+
+    def ok(S):
+        r = memo.get(S)
+        if r is None:
+            r = S & (S - 1) == 0
+            if not r and bin(kept(S)).count("1") <= max_out:
+                low = S & -S
+                rest = S ^ low
+                sub = rest
+                while True:
+                    L = sub | low
+                    R = S ^ L
+                    if (R and connected(L) and connected(R) and var_of[L] & var_of[R]
+                            and bin(kept(L) | kept(R)).count("1") <= max_scope and ok(L) and ok(R)):
+                        r = True
+                        break
+                    if sub == 0:
+                        break
+                    sub = (sub - 1) & rest
+            memo[S] = r
+        return r
+
+    return ok(full)
+
+
 def random_hypergraph(rng: SplitMix64, res: int = 128, max_tries: int = 1000) -> System:
     """Random relation hypergraph: n in {8..14} variables, m = n-1+U{0,1,2}
-    relations of arity U{2,3}, connected, covering every variable; 2-4 exposed."""
+    relations of arity U{2,3}, connected, covering every variable; 2-4 exposed.
+    Drawn again until some merge tree keeps at most 4 variables per
+    intermediate and ranges over at most 6 per step (_fits_scope_caps)."""
     for _ in range(max_tries):
         n = rng.randint(8, 14)
         m = n - 1 + rng.randint(0, 2)
@@ -204,9 +283,11 @@ def random_hypergraph(rng: SplitMix64, res: int = 128, max_tries: int = 1000) ->
             v = rng.randint(0, n - 1)
             if v not in exposed:
                 exposed.append(v)
+        if not _fits_scope_caps(rel_vars, exposed):
+            continue
         rels = [random_relation(rng, vs) for vs in rel_vars]
         return System([(-3.0, 3.0, res)] * n, rels, tuple(exposed))
-    raise RuntimeError("no connected hypergraph drawn")
+    raise RuntimeError("no admissible hypergraph drawn")
 
 
 def config5(n_graphs: int = 256, index: int = 0, res: int = 128) -> List[System]:
