@@ -83,7 +83,12 @@ typedef struct {
     int32_t reserved;
 } pa_axis;
 
-/* A polynomial relation f(x_{vars[0]}, ..., x_{vars[arity-1]}) = 0.
+/* Target subset of a relation's defining function (Def.
+ * "functionally_defined": the relations f = 0, f <= 0 and f < 0). */
+enum { PA_TARGET_EQ = 0, PA_TARGET_LE = 1, PA_TARGET_LT = 2 };
+
+/* A polynomial relation f(x_{vars[0]}, ..., x_{vars[arity-1]}) in S, with S
+ * the target subset: {0}, (-inf, 0] or (-inf, 0).
  * coef has C(arity + degree, degree) entries in graded-lex order of the
  * monomials in the declared variable order: total degree ascending, then
  * lexicographically descending exponent tuples (for (x, y), degree 3:
@@ -93,6 +98,8 @@ typedef struct {
     int32_t degree;           /* 0..PA_MAX_DEGREE */
     const int32_t *vars;      /* host, arity entries, ids in [0, n_vars) */
     const double *coef;       /* host                                     */
+    int32_t target;           /* PA_TARGET_* (0: f = 0)                   */
+    int32_t reserved;         /* 0                                        */
 } pa_relation;
 
 /* Bit-packed Boolean array, layout above.  data is a device pointer. */
@@ -114,6 +121,21 @@ typedef struct {
 
 enum { PA_ORDER_GREEDY = 0, PA_ORDER_EXHAUSTIVE = 1, PA_ORDER_LEARNED = 2, PA_ORDER_GIVEN = 3 };
 enum { PA_PLOT_FP32_ESCALATE = 0, PA_PLOT_FP64 = 1 };
+/* Plotting rule (pa_opts.plot_rule).
+ * PA_RULE_CORNER: f is evaluated at the pixel corners; for f = 0 a pixel is
+ *   set iff one corner has f <= 0 and one has f >= 0, for f <= 0 (f < 0) iff
+ *   one corner has f <= 0 (f < 0).
+ * PA_RULE_CENTER: the epsilon-tolerance sample-in-center plot (Def.
+ *   "sample_in_center", Cor. "guarantees"): f is evaluated at the pixel
+ *   centre c_k = a + (k + 1/2) * delta (FP64, each operation rounded once) and
+ *   a pixel is set iff the distance from f(c) to the target subset is at most
+ *   eps = pa_opts.tolerance: |f(c)| <= eps, f(c) <= eps or f(c) < eps for the
+ *   three targets.  With eps a valid tolerance (Sec. 3.2: f moves by less
+ *   than eps within a pixel radius) the plot is eps-accurate, and so is the
+ *   solution (Thm "extended").
+ * Both rules decide with the canonical FP64 value (below); FP32 with
+ * escalation gives the same bits. */
+enum { PA_RULE_CORNER = 0, PA_RULE_CENTER = 1 };
 
 typedef struct pa_model pa_model;   /* learned contraction-order cost model */
 
@@ -186,6 +208,9 @@ typedef struct {
                                  every such contraction, -1 = never.  Not used by
                                  the plain path or a single persistent launch.    */
     int32_t sparse_max_density; /* 0..1024 set bits per 1024 bits of A (0: 64)     */
+    int32_t plot_rule;        /* PA_RULE_* (0: corners)                           */
+    int32_t reserved0;
+    double tolerance;         /* PA_RULE_CENTER: eps >= 0, finite                  */
 } pa_opts;
 
 typedef struct {
@@ -287,9 +312,11 @@ typedef struct pa_batch pa_batch;
 int pa_batch_create(const pa_system *systems, int32_t n_sys, const int32_t *const *exposed,
                     const int32_t *n_exposed, const pa_opts *opts, pa_batch **batch);
 /* outs[i]: system i's output (dims = its exposed resolutions).  report (the
- * batch totals) and nnz (set bits per system) may be NULL; when either is
- * given the call synchronizes the stream. */
-int pa_batch_execute(pa_batch *batch, pa_bitarray *outs, pa_report *report, int64_t *nnz, void *stream);
+ * batch totals) and reports (n_sys entries, system i's report in reports[i]:
+ * its corners, escalated and audit counts, set bits, steps, merges, naive
+ * cost and planning time; n_launches is the batch's) may be NULL; when either
+ * is given the call synchronizes the stream. */
+int pa_batch_execute(pa_batch *batch, pa_bitarray *outs, pa_report *report, pa_report *reports, void *stream);
 size_t pa_batch_workspace_bytes(const pa_batch *batch);
 /* As pa_plan_op_times, for a batch created with opts->timing == 2: one entry
  * per grouped launch (kind and summed macs of its steps). */
@@ -298,9 +325,16 @@ int32_t pa_batch_op_times(pa_batch *batch, double *ms, int32_t *kind, double *ma
 int32_t pa_batch_time_groups(pa_batch *batch, int32_t reps, double *ms, int32_t *kind, double *macs, int32_t cap,
                              void *stream);
 void pa_batch_destroy(pa_batch *batch);
-/* pa_batch_create + pa_batch_execute + pa_batch_destroy (synchronizes). */
+/* Solve n_sys independent systems: for each, the solution array on its
+ * exposed variables, i.e. the generalized array multiplication of its
+ * relation plots over its wiring diagram (Def. "wd", eqn GAM), evaluated as a
+ * cluster tree (Sec. 3.5).  pa_batch_create + pa_batch_execute +
+ * pa_batch_destroy: outs[i] as for pa_batch_execute (device, caller-owned,
+ * dims = system i's exposed resolutions); reports (host, n_sys entries) may
+ * be NULL.  Synchronizes the stream.  Errors as for pa_batch_create (failing
+ * system named in pa_last_error) and pa_batch_execute. */
 int pa_solve_batch(const pa_system *systems, int32_t n_sys, const int32_t *const *exposed, const int32_t *n_exposed,
-                   const pa_opts *opts, pa_bitarray *outs, int64_t *nnz, void *stream);
+                   const pa_opts *opts, pa_bitarray *outs, pa_report *reports, void *stream);
 
 /* ---------------------------------------------------------- learned order
  * The tree of pairwise steps only decides the work (Sec. 3.5), and the naive
@@ -398,9 +432,28 @@ int pa_autotune(const pa_system *systems, int32_t n_sys, const int32_t *const *e
                 const pa_opts *opts, int32_t reps, pa_tuning *best, pa_tuning *tried, int32_t cap, int32_t *n_tried,
                 void *stream);
 
-/* pa_plan_create + pa_plan_execute + pa_plan_destroy. */
+/* Solve one system: the solution array A' on the exposed variables (the
+ * outer pack), the generalized array multiplication of the relation plots
+ * over the system's wiring diagram (Def. "wd", eqn GAM) with every latent
+ * variable projected out, evaluated as a cluster tree (Sec. 3.5,
+ * Thm "associative": every tree gives the same bits).  pa_plan_create +
+ * pa_plan_execute + pa_plan_destroy.  out: device, caller-owned, dims = the
+ * exposed resolutions in the listed order; report (host) may be NULL.  The
+ * workspace is the library's unless opts->workspace is given (then at least
+ * pa_workspace_bytes).  Synchronizes the stream.  Errors as for
+ * pa_plan_create and pa_plan_execute. */
 int pa_solve_system(const pa_system *sys, const int32_t *exposed, int32_t n_exposed, const pa_opts *opts,
                     pa_bitarray *out, pa_report *report, void *stream);
+
+/* Device bytes of workspace that pa_plan_create / pa_solve_system need for
+ * this system and opts (intermediates, tables, executor state: 256-byte
+ * aligned), computed by planning on the host without creating a plan or
+ * allocating device memory (PA_ORDER_LEARNED runs the model's inference on its
+ * device).  opts->autotune and opts->verify_order are not applied: the figure
+ * is for the given executor settings and order policy (pass pa_autotune's
+ * settings to size an autotuned plan).  Returns 0 on invalid input (EINVAL /
+ * ENOMEM cases of pa_plan_create; message in pa_last_error). */
+size_t pa_workspace_bytes(const pa_system *sys, const int32_t *exposed, int32_t n_exposed, const pa_opts *opts);
 
 /* Number of set bits of a device bit array (padding is zero by contract). */
 int pa_popcount(const pa_bitarray *a, int64_t *count, void *stream);

@@ -103,7 +103,7 @@ extern "C" int pa_batch_create(const pa_system *systems, int32_t n_sys, const in
     pa_plan &M = B->master;
     M.per_op = 0;
     M.graph = o.graph;
-    M.single_launch = o.single_launch;
+    M.single_launch = o.single_launch && o.plot_rule != PA_RULE_CENTER;   // corner plots only (as for plans)
     M.persist_wg = o.persist_wg;
     M.timing = o.timing;
     size_t nsteps = 0;
@@ -116,7 +116,7 @@ extern "C" int pa_batch_create(const pa_system *systems, int32_t n_sys, const in
     M.steps_off = take(sizeof(PStep) * std::max<size_t>(1, nsteps));
     M.done_off = take(sizeof(unsigned) * std::max<size_t>(1, nsteps));
     M.state_off = take(sizeof(PersistState));
-    M.counters_off = take(sizeof(PlotCounters));
+    M.counters_off = take(sizeof(PlotCounters) * (size_t)n_sys);   // one block per system
     M.popcnt_off = take(sizeof(unsigned long long) * (size_t)n_sys);
     M.ws_bytes = off;
     int rc;
@@ -144,6 +144,7 @@ extern "C" int pa_batch_create(const pa_system *systems, int32_t n_sys, const in
         P.ws.ptr = base + B->sub_off[i];
         P.ws.cap = P.ws_bytes;
         P.ws.external = true;
+        P.counters_dev = reinterpret_cast<PlotCounters *>(base + M.counters_off) + i;
         rc = upload_plan(&P);
         if (rc) return rc;
         M.total_macs += P.total_macs;
@@ -151,7 +152,7 @@ extern "C" int pa_batch_create(const pa_system *systems, int32_t n_sys, const in
     }
     rc = merge_steps(B.get());
     if (rc) return rc;
-    HIP_TRY(hipMemset(base + M.counters_off, 0, sizeof(PlotCounters)));
+    HIP_TRY(hipMemset(base + M.counters_off, 0, sizeof(PlotCounters) * (size_t)n_sys));
     HIP_TRY(hipMemset(base + M.state_off, 0, sizeof(PersistState)));
     HIP_TRY(hipMemset(base + M.done_off, 0, sizeof(unsigned) * std::max<size_t>(1, nsteps)));
     if (opts && opts->timing == 2) {
@@ -162,7 +163,17 @@ extern "C" int pa_batch_create(const pa_system *systems, int32_t n_sys, const in
     return PA_OK;
 }
 
-extern "C" int pa_batch_execute(pa_batch *B, pa_bitarray *outs, pa_report *rep, int64_t *nnz, void *stream) {
+// Steps of a plan counted in a report: the pairwise contractions (not
+// projections of one operand, fills, count steps, or a sparse pass whose MFMA
+// contraction is counted).
+static int counted_steps(const pa_plan &P) {
+    int steps = 0;
+    for (const auto &op : P.ops)
+        if (op.kind != OP_FILL && op.kind != OP_COUNT && !(op.kind == OP_GATHER && op.flag >= 0) && op.b != -1) ++steps;
+    return steps;
+}
+
+extern "C" int pa_batch_execute(pa_batch *B, pa_bitarray *outs, pa_report *rep, pa_report *reports, void *stream) {
     if (!B || !outs) return fail(PA_EINVAL, "batch_execute: null argument");
     const size_t n = B->subs.size();
     std::vector<void *> o(n);
@@ -178,49 +189,52 @@ extern "C" int pa_batch_execute(pa_batch *B, pa_bitarray *outs, pa_report *rep, 
     hipStream_t s = static_cast<hipStream_t>(stream);
     int launches = 0;
     M.timing_active = false;
-    char *mbase = static_cast<char *>(M.ws.ptr);
-    PlotCounters cnt0;
-    std::memset(&cnt0, 0, sizeof(cnt0));
-    if (rep) HIP_TRY(hipMemcpyAsync(&cnt0, mbase + M.counters_off, sizeof(cnt0), hipMemcpyDeviceToHost, s));
+    char *base = static_cast<char *>(M.ws.ptr);
+    auto *cdev = reinterpret_cast<PlotCounters *>(base + M.counters_off);
+    std::vector<PlotCounters> cnt0(n), cnt(n);
+    if (rep || reports) HIP_TRY(hipMemcpyAsync(cnt0.data(), cdev, n * sizeof(PlotCounters), hipMemcpyDeviceToHost, s));
     int rc = exec_steps(&M, o, s, &launches);
     if (rc) return rc;
-    if (rep || nnz) {
-        char *base = static_cast<char *>(M.ws.ptr);
+    if (rep || reports) {
         auto *counts = reinterpret_cast<unsigned long long *>(base + M.popcnt_off);
         HIP_TRY(launch_fill(reinterpret_cast<uint32_t *>(counts), 2 * (int64_t)n, 0u, s));
         for (size_t i = 0; i < n; ++i)
             HIP_TRY(launch_popcount(static_cast<const uint32_t *>(o[i]), B->subs[i]->out_layout.words, counts + i, s));
         std::vector<unsigned long long> c(n);
-        PlotCounters cnt;
         PersistState pst;
         HIP_TRY(hipMemcpyAsync(c.data(), counts, n * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipMemcpyAsync(&cnt, base + M.counters_off, sizeof(cnt), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(cnt.data(), cdev, n * sizeof(PlotCounters), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipMemcpyAsync(&pst, base + M.state_off, sizeof(pst), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         if (pst.abort) return fail(PA_EHIP, "persistent executor gave up a dependency wait");
-        int64_t total = 0;
+        pa_report tot;
+        std::memset(&tot, 0, sizeof(tot));
         for (size_t i = 0; i < n; ++i) {
-            if (nnz) nnz[i] = (int64_t)c[i];
-            total += (int64_t)c[i];
+            const pa_plan &P = *B->subs[i];
+            pa_report r;
+            std::memset(&r, 0, sizeof(r));
+            r.corners = P.corners;
+            r.corners_flagged = (int64_t)(cnt[i].flagged - cnt0[i].flagged);
+            r.corners_disagree = (int64_t)(cnt[i].disagree - cnt0[i].disagree);
+            r.corners_disagree_unflagged = (int64_t)(cnt[i].disagree_unflagged - cnt0[i].disagree_unflagged);
+            r.nnz_out = (int64_t)c[i];
+            r.n_steps = counted_steps(P);
+            r.n_launches = launches;
+            for (size_t k = 0; k < P.tree.merges.size() && k < 2 * PA_MAX_RELATIONS; ++k) r.merges[k] = P.tree.merges[k];
+            r.cost_macs = P.tree.cost;
+            r.t_plan_ms = P.t_plan_ms;
+            if (reports) reports[i] = r;
+            tot.corners += r.corners;
+            tot.corners_flagged += r.corners_flagged;
+            tot.corners_disagree += r.corners_disagree;
+            tot.corners_disagree_unflagged += r.corners_disagree_unflagged;
+            tot.nnz_out += r.nnz_out;
+            tot.n_steps += r.n_steps;
+            tot.cost_macs += r.cost_macs;
+            tot.t_plan_ms += r.t_plan_ms;
         }
-        if (rep) {
-            std::memset(rep, 0, sizeof(*rep));
-            rep->corners = M.corners;
-            rep->corners_flagged = (int64_t)(cnt.flagged - cnt0.flagged);
-            rep->corners_disagree = (int64_t)(cnt.disagree - cnt0.disagree);
-            rep->corners_disagree_unflagged = (int64_t)(cnt.disagree_unflagged - cnt0.disagree_unflagged);
-            rep->nnz_out = total;
-            rep->n_launches = launches;
-            int steps = 0;
-            double cost = 0.0;
-            for (auto &P : B->subs) {
-                cost += P->tree.cost;
-                for (const auto &op : P->ops)
-                    if (op.kind != OP_FILL && op.kind != OP_COUNT && !(op.kind == OP_GATHER && op.flag >= 0) && op.b != -1) ++steps;
-            }
-            rep->n_steps = steps;
-            rep->cost_macs = cost;
-        }
+        tot.n_launches = launches;
+        if (rep) *rep = tot;
     }
     return PA_OK;
 }
@@ -241,12 +255,12 @@ extern "C" int32_t pa_batch_time_groups(pa_batch *B, int32_t reps, double *ms, i
 extern "C" void pa_batch_destroy(pa_batch *B) { delete B; }
 
 extern "C" int pa_solve_batch(const pa_system *systems, int32_t n_sys, const int32_t *const *exposed,
-                              const int32_t *n_exposed, const pa_opts *opts, pa_bitarray *outs, int64_t *nnz,
+                              const int32_t *n_exposed, const pa_opts *opts, pa_bitarray *outs, pa_report *reports,
                               void *stream) {
     pa_batch *B = nullptr;
     int rc = pa_batch_create(systems, n_sys, exposed, n_exposed, opts, &B);
     if (rc) return rc;
-    rc = pa_batch_execute(B, outs, nullptr, nnz, stream);
+    rc = pa_batch_execute(B, outs, nullptr, reports, stream);
     if (rc == PA_OK && hipStreamSynchronize(static_cast<hipStream_t>(stream)) != hipSuccess)
         rc = fail(PA_EHIP, "sync failed");
     pa_batch_destroy(B);

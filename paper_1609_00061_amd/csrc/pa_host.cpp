@@ -119,6 +119,8 @@ int validate_relation(const pa_relation &r, const pa_axis *axes_of_vars, int n_v
     if (r.degree < 0 || r.degree > PA_MAX_DEGREE)
         return fail(PA_EINVAL, std::string(who) + ": degree must be 0..4");
     if (!r.vars || !r.coef) return fail(PA_EINVAL, std::string(who) + ": null vars or coef");
+    if (r.target < PA_TARGET_EQ || r.target > PA_TARGET_LT)
+        return fail(PA_EINVAL, std::string(who) + ": target must be PA_TARGET_EQ, _LE or _LT");
     for (int i = 0; i < r.arity; ++i) {
         if (n_vars_total >= 0 && (r.vars[i] < 0 || r.vars[i] >= n_vars_total))
             return fail(PA_EINVAL, std::string(who) + ": variable id out of range");

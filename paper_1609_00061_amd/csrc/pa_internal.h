@@ -29,8 +29,20 @@ static_assert(kMaxTileLines <= 256, "one corner line per thread of a 256-thread 
 // walk axis, storage axis n-2).  A thread walks its strip, so each corner
 // line of the strip is evaluated once; the tile's line coefficients are built
 // cooperatively in LDS.
+struct PlotCounters {
+    unsigned long long flagged;
+    unsigned long long disagree;
+    unsigned long long disagree_unflagged;
+    unsigned long long pad;
+};
+
+enum PlotRule { kRuleCorner = 0, kRuleCenter = 1 };
+
 struct PlotRel {
     int n, d, mode, audit;
+    int rule;                  // kRuleCorner: corner sampling; kRuleCenter: sample in the pixel centre
+    int target;                // f = 0 (0), f <= 0 (1), f < 0 (2)
+    double eps;                // kRuleCenter: the tolerance
     int perm[kMaxA];
     int res[kMaxA];            // resolution per storage axis
     int64_t row_words;
@@ -42,17 +54,13 @@ struct PlotRel {
     double vpow[kMaxD + 2];    // max(1, vmax)^t, t = 0..d+1
     double coef[kDense];       // dense table c[e0 + (d+1)*(e1 + (d+1)*e2)], declared exponents
     uint32_t *out;
+    PlotCounters *counters;    // escalation counters of the relation's system (null: the launch's)
     int tw, ta, tb, s;
     int64_t tiles_w, tiles_walk, tiles_fixed, n_tiles;
     int64_t tile_base;         // prefix over relations of n_tiles (multi-relation launches)
 };
 
-struct PlotCounters {
-    unsigned long long flagged;
-    unsigned long long disagree;
-    unsigned long long disagree_unflagged;
-    unsigned long long pad;
-};
+
 
 // Division by a value fixed at plan time, for 0 <= n < 2^31 and
 // 1 <= d < 2^31: q = floor(n * m / 2^(31 + s)) with s = ceil(log2 d) and
@@ -205,7 +213,7 @@ struct PersistState {
 };
 
 // Kernel launchers (pa_kernels.hip).  All return hipError_t of the launch.
-hipError_t launch_plot(const PlotRel *d_rels, int nrel, int64_t total_tiles, PlotCounters *d_counters,
+hipError_t launch_plot(const PlotRel *d_rels, int nrel, int64_t total_tiles, bool center, PlotCounters *d_counters,
                        hipStream_t s);
 hipError_t launch_contract(const ContractArgs &a, int mode, hipStream_t s);
 hipError_t launch_gemm(const GemmArgs &g, hipStream_t s);
@@ -216,8 +224,9 @@ hipError_t launch_popcount(const uint32_t *p, int64_t n, unsigned long long *out
 hipError_t launch_persist(const PStep *d_steps, int nsteps, int64_t n_items, PersistState *state,
                           unsigned int *done, PlotCounters *counters, int n_workgroups, hipStream_t s);
 hipError_t launch_persist_reset(PersistState *state, unsigned int *done, int nsteps, hipStream_t s);
-// Steps first..first+count-1 (tiles t0..t1-1) of one kind; flags: some of the
-// MFMA contractions among them have a sparse pass (and may be skipped).
+// Steps first..first+count-1 (tiles t0..t1-1) of one kind and mode (plots:
+// mode 1 = centre rule); flags: some of the MFMA contractions among them have
+// a sparse pass (and may be skipped).
 hipError_t launch_group(int kind, int mode, const PStep *d_steps, int first, int count, int64_t t0, int64_t t1,
                         int flags, PlotCounters *counters, hipStream_t s);
 int persist_default_workgroups();

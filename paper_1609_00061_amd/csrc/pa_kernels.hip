@@ -95,6 +95,8 @@ struct PlotCount {
 // in global memory, which the tile's output stores could alias).
 struct PlotView {
     int n, d, mode, audit;
+    int target;                // f = 0 (0), f <= 0 (1), f < 0 (2)
+    double eps;                // centre rule: the tolerance
     int perm0, perm1, perm2;   // declared variable of storage axis 0, 1, 2
     int res0, res1;            // resolutions of storage axes 0 and 1
     int rwalk, rp;             // walk axis (storage n-2; 1 if n == 1) and packed axis
@@ -114,12 +116,21 @@ __device__ __forceinline__ double corner_coord(double lo, double st, int64_t k) 
     return lo + t;
 }
 
+// FP64 centre of pixel k: lo + (k + 1/2) * st, the product and the sum each
+// rounded, as on the host.
+__device__ __forceinline__ double center_coord(double lo, double st, int64_t k) {
+    const double t = ((double)k + 0.5) * st;
+    return lo + t;
+}
+
 __device__ __forceinline__ PlotView plot_view(const PlotRel &R) {
     PlotView v;
     v.n = R.n;
     v.d = R.d;
     v.mode = R.mode;
     v.audit = R.audit;
+    v.target = R.target;
+    v.eps = R.eps;
     v.perm0 = R.perm[0];
     v.perm1 = R.perm[1];
     v.perm2 = R.perm[2];
@@ -328,6 +339,17 @@ __device__ __forceinline__ void line_fp32(const float *ln, const float *xv, cons
     FL = {valid.lo & ~ok, valid.hi & ~ok32};
 }
 
+// Corner bits for the target of an inequality: a cell is set iff one of its
+// corners satisfies it, so the "some corner f >= 0" half of the sign-change
+// test becomes always true and the other half is f <= 0 (target 1) or f < 0
+// (target 2: f <= 0 and not f >= 0; a corner with a certain FP32 sign is
+// nonzero, an escalated one has its FP64 sign).
+__device__ __forceinline__ void apply_target(int target, Corners &LE, Corners &GE) {
+    if (target == 0) return;
+    if (target == 2) LE = {LE.lo & ~GE.lo, LE.hi & ~GE.hi};
+    GE = {~0u, ~0u};
+}
+
 // LE/GE bits of the corners k0..k0+kmax of one corner line: ln its FP32
 // restriction and bound, ly its FP64 coordinates on the non-packed storage
 // axes (walk axis first for n == 2; fixed, walk for n == 3), cdl the
@@ -452,6 +474,7 @@ __device__ void plot_tile2(const PlotRel &R, int64_t tile, float *lines, double 
         if (q < s && !pad && b0 + L <= rwalk) {
             Corners LE, GE;
             eval_line(V, lines + L * kLineFloats, xv, ly + 2 * L, cdl, k0, kmax, true, LE, GE, cnt);
+            apply_target(V.target, LE, GE);
             lcq[q] = LE.lo | __builtin_amdgcn_alignbit(LE.hi, LE.lo, 1);
             gcq[q] = GE.lo | __builtin_amdgcn_alignbit(GE.hi, GE.lo, 1);
         }
@@ -501,6 +524,8 @@ __device__ void plot_tile2(const PlotRel &R, int64_t tile, float *lines, double 
                 }
             }
         }
+        if (V.target == 2) lb = lb && !gb;
+        if (V.target != 0) gb = true;
         const uint64_t lm = __ballot(lb), gm = __ballot(gb);
         if (lane == 63) {
             lcb = (uint32_t)(lm | (lm >> 1));
@@ -515,6 +540,164 @@ __device__ void plot_tile2(const PlotRel &R, int64_t tile, float *lines, double 
             const uint32_t lbot = (q + 1 < s) ? lcq[1] : lcb, gbot = (q + 1 < s) ? gcq[1] : gcb;
             V.out[row * V.row_words + w] = (lcq[q] | lbot) & (gcq[q] | gbot) & vmask;
         }
+    }
+}
+
+// epsilon-tolerance sample-in-center plot (Def. sample_in_center): a cell
+// is set iff the distance from f at its centre to the target subset is at
+// most eps -- |f| <= eps for f = 0, f <= eps for f <= 0, f < eps for f < 0 --
+// with f the canonical FP64 value at the FP64 centre.  Tiles as plot_tile (tw
+// words x tb strips of s rows x ta cells of the fixed axis); a thread owns a
+// 32-cell word of a strip and evaluates the centre line of each of its rows
+// at the word's 32 centres.  The FP32 value p of a centre differs from the
+// FP64 one by at most E (the line bound of line_coefs), so with
+// lo = RD32(eps - E) and hi = RU32(eps + E) (each pushed outward past the
+// FP64 rounding of the difference) the decision is certain when the
+// distance d (|p| or p) has d < lo (set: d64 <= d + E < eps) or d > hi
+// (unset: d64 >= d - E > eps); the others, and every centre in FP64 mode,
+// are decided by the canonical FP64 value.
+__device__ __forceinline__ void center_thresholds(float E, double eps, float &lo, float &hi) {
+    if (!(E < INFINITY)) {
+        lo = -INFINITY;
+        hi = INFINITY;
+        return;
+    }
+    double t = eps - (double)E;
+    t -= fabs(t) * 0x1p-50;
+    lo = (float)t;
+    if ((double)lo > t) lo = nextafterf(lo, -INFINITY);
+    double u = eps + (double)E;
+    u += fabs(u) * 0x1p-50;
+    hi = (float)u;
+    if ((double)hi < u) hi = nextafterf(hi, INFINITY);
+}
+
+__device__ __forceinline__ bool center_on(int target, double f, double eps) {
+    return target == 0 ? fabs(f) <= eps : (target == 1 ? f <= eps : f < eps);
+}
+
+__device__ void center_tile(const PlotRel &R, int64_t tile, float *lines, double *tabs, PlotCount &cnt) {
+    const PlotView V = plot_view(R);
+    const double coefs = load_coefs(V);
+    const int n = V.n;
+    const int tid = threadIdx.x;
+    const int tw_n = R.tw, ta = R.ta, tb = R.tb, s = R.s;
+    const uint32_t tiles_w = (uint32_t)R.tiles_w, tiles_walk = (uint32_t)R.tiles_walk;
+    uint32_t t = (uint32_t)tile;
+    const int64_t t_w = t % tiles_w;
+    t /= tiles_w;
+    const int64_t t_walk = t % tiles_walk;
+    const int64_t t_fixed = t / tiles_walk;
+    const int rwalk = V.rwalk, rp = V.rp;
+    const int span = tb * s;
+    const int64_t b0 = t_walk * span;
+    const int64_t a0 = t_fixed * ta;
+    const int nwl = (n >= 2) ? span : 1;
+    const int nfl = (n == 3) ? ta : 1;
+    const int twi = tid % tw_n, slot = tid / tw_n;
+    const int fa = (n == 3) ? slot % ta : 0;
+    const int strip = (n == 3) ? slot / ta : slot;
+    const int64_t w = t_w * tw_n + twi;
+    const int64_t cs = b0 + (int64_t)strip * s;
+    const int64_t cf = a0 + fa;
+    bool active = strip < tb && !(n == 1 && slot != 0) && w < V.row_words;
+    if (n >= 2) active = active && cs < rwalk;
+    if (n == 3) active = active && cf < V.res0;
+    const bool pad = w * 32 >= rp;
+    const int k0 = (int)(w * 32);
+    const int kmax = pad ? 0 : min(32, rp - k0);
+    // the word's 32 centres (FP64, rounded to FP32)
+    float xv[32];
+    const int kb = (active && !pad) ? k0 : 0;
+#pragma unroll
+    for (int kk = 0; kk < 32; ++kk) xv[kk] = (float)center_coord(V.lop, V.stp, kb + kk);
+    // the tile's centre lines: thread i < nlines takes line (i / nwl, i % nwl)
+    double *cdl = tabs, *ly = tabs + kDense;
+    const int nlines = nwl * nfl;
+    bool lvalid = false;
+    double y0 = 0.0, y1 = 0.0;
+    if (tid < nlines) {
+        const int lf = tid / nwl, lw = tid % nwl;
+        lvalid = true;
+        if (n == 2) {
+            const int64_t ib = b0 + lw;
+            lvalid = ib < rwalk;
+            if (lvalid) y0 = center_coord(V.lo0, V.st0, ib);
+        } else if (n == 3) {
+            const int64_t ia = a0 + lf, ib = b0 + lw;
+            lvalid = ia < V.res0 && ib < rwalk;
+            if (lvalid) {
+                y0 = center_coord(V.lo0, V.st0, ia);
+                y1 = center_coord(V.lo1, V.st1, ib);
+            }
+        }
+    }
+    store_coefs(coefs, cdl);
+    if (tid < nlines) {
+        ly[2 * tid] = y0;
+        ly[2 * tid + 1] = y1;
+    }
+    __syncthreads();
+    if (V.mode == PA_PLOT_FP32_ESCALATE && lvalid) line_coefs(V, cdl, y0, y1, lines + tid * kLineFloats);
+    __syncthreads();
+    if (!active) return;
+    const uint32_t vmask = pad ? 0u : (kmax == 32 ? 0xffffffffu : ((1u << kmax) - 1u));
+    const int64_t ce = (n >= 2) ? min((int64_t)rwalk, cs + s) : cs + 1;
+    const int64_t row_base = (n == 3) ? cf * V.res1 : 0;
+    const int target = V.target;
+    const float eps32 = (float)V.eps;
+    for (int64_t c = cs; c < ce; ++c) {
+        if (pad) {                         // a row's padding word: zero
+            V.out[(row_base + c) * V.row_words + w] = 0u;
+            continue;
+        }
+        const int li = (n == 3 ? fa * nwl : 0) + (n >= 2 ? (int)(c - b0) : 0);
+        const float *ln = lines + li * kLineFloats;
+        uint32_t on = 0u, todo = vmask, fp32on = 0u;
+        if (V.mode == PA_PLOT_FP32_ESCALATE) {
+            float ca[kMaxD + 1];
+#pragma unroll
+            for (int tt = 0; tt <= kMaxD; ++tt) ca[tt] = ln[tt];
+            float lo, hi;
+            center_thresholds(ln[kLineFloats - 1], V.eps, lo, hi);
+            uint32_t sure_on = 0u, sure_off = 0u;
+#pragma unroll
+            for (int kk = 0; kk < 32; ++kk) {
+                float f = ca[kMaxD];
+#pragma unroll
+                for (int tt = kMaxD - 1; tt >= 0; --tt) f = fmaf(f, xv[kk], ca[tt]);
+                const float dist = target == 0 ? fabsf(f) : f;
+                sure_on |= (uint32_t)(dist < lo) << kk;
+                sure_off |= (uint32_t)(dist > hi) << kk;
+                if (V.audit) fp32on |= (uint32_t)(target == 2 ? dist < eps32 : dist <= eps32) << kk;
+            }
+            on = sure_on & vmask;
+            todo = vmask & ~(sure_on | sure_off);
+            cnt.flagged += __popc(todo);
+        }
+        const uint32_t flagged = todo;
+        if (V.audit && V.mode == PA_PLOT_FP32_ESCALATE) todo = vmask;
+        const double yy0 = ly[2 * li], yy1 = ly[2 * li + 1];
+        uint32_t rest = todo;
+        while (rest) {
+            const int kk = __ffs(rest) - 1;
+            rest &= rest - 1;
+            double xd[3];
+            const double xk = center_coord(V.lop, V.stp, k0 + kk);
+            if (n == 1) decl_point(V, xk, 0.0, 0.0, xd);
+            else if (n == 2) decl_point(V, yy0, xk, 0.0, xd);
+            else decl_point(V, yy0, yy1, xk, xd);
+            const double f64 = canon_eval(cdl, n, V.d, xd);
+            const bool on64 = center_on(target, f64, V.eps);
+            const uint32_t bit = 1u << kk;
+            if (flagged & bit) on |= on64 ? bit : 0u;
+            if (V.audit && V.mode == PA_PLOT_FP32_ESCALATE) {
+                const bool dis = ((fp32on & bit) != 0) != on64;
+                cnt.dis += dis;
+                cnt.dis_unf += dis && !(flagged & bit);
+            }
+        }
+        V.out[(row_base + c) * V.row_words + w] = on;
     }
 }
 
@@ -615,6 +798,7 @@ __device__ void plot_tile(const PlotRel &R, int64_t tile, float *lines, double *
                 const int li = lf * nwl + (int)(c - b0);
                 Corners LE, GE;
                 eval_line(V, lines + li * kLineFloats, xv, ly + 2 * li, cdl, k0, kmax, own, LE, GE, cnt);
+                apply_target(V.target, LE, GE);
                 // cell i holds corners i and i + 1
                 lc |= LE.lo | __builtin_amdgcn_alignbit(LE.hi, LE.lo, 1);
                 gc |= GE.lo | __builtin_amdgcn_alignbit(GE.hi, GE.lo, 1);
@@ -630,12 +814,40 @@ __device__ void plot_tile(const PlotRel &R, int64_t tile, float *lines, double *
     }
 }
 
+// A plot tile of the rule CENTER selects at compile time (corner tiles, or
+// the centre tiles of the sample-in-center plot), so that each kernel holds
+// the registers of one rule only.  Plots of one plan share its rule; the
+// single persistent launch runs corner tiles only (centre-rule plans use
+// the grouped executor).
+template <bool CENTER>
+__device__ __forceinline__ void plot_tile_rule(const PlotRel &R, int64_t tile, float *lines, double *tabs,
+                                               PlotCount &cnt) {
+    if (CENTER) center_tile(R, tile, lines, tabs, cnt);
+    else plot_tile(R, tile, lines, tabs, cnt);
+}
+
 __device__ __forceinline__ void flush_counts(const PlotCount &cnt, PlotCounters *counters) {
     if (!counters) return;
     if (cnt.flagged) atomicAdd(&counters->flagged, cnt.flagged);
     if (cnt.dis) atomicAdd(&counters->disagree, cnt.dis);
     if (cnt.dis_unf) atomicAdd(&counters->disagree_unflagged, cnt.dis_unf);
 }
+
+// A thread's escalation counts, kept until its tiles move to a relation with
+// other counters (a batch gives every system its own), then added there.
+struct CountSink {
+    PlotCount cnt;
+    PlotCounters *to = nullptr;
+    __device__ __forceinline__ void use(const PlotRel &R, PlotCounters *launch_counters) {
+        PlotCounters *p = R.counters ? R.counters : launch_counters;
+        if (p != to) {
+            flush_counts(cnt, to);
+            cnt = PlotCount();
+            to = p;
+        }
+    }
+    __device__ __forceinline__ void finish() { flush_counts(cnt, to); }
+};
 
 __device__ __forceinline__ int find_rel(const PlotRel *rels, int nrel, int64_t tile) {
     int lo = 0, hi = nrel - 1;
@@ -646,24 +858,31 @@ __device__ __forceinline__ int find_rel(const PlotRel *rels, int nrel, int64_t t
     return lo;
 }
 
+template <bool CENTER>
 __global__ __launch_bounds__(256) void k_plot(const PlotRel *__restrict__ rels, int nrel, int64_t total_tiles,
                                               PlotCounters *__restrict__ counters) {
     __shared__ __attribute__((aligned(16))) uint32_t lds[kPlotLdsWords];
-    PlotCount cnt;
+    CountSink sink;
     for (int64_t tile = blockIdx.x; tile < total_tiles; tile += gridDim.x) {
         const PlotRel &R = rels[find_rel(rels, nrel, tile)];
-        plot_tile(R, tile - R.tile_base, reinterpret_cast<float *>(lds),
-                  reinterpret_cast<double *>(lds + kPlotLineWords), cnt);
+        sink.use(R, counters);
+        plot_tile_rule<CENTER>(R, tile - R.tile_base, reinterpret_cast<float *>(lds),
+                  reinterpret_cast<double *>(lds + kPlotLineWords), sink.cnt);
         __syncthreads();
     }
-    flush_counts(cnt, counters);
+    sink.finish();
 }
 
-hipError_t launch_plot(const PlotRel *d_rels, int nrel, int64_t total_tiles, PlotCounters *d_counters,
+hipError_t launch_plot(const PlotRel *d_rels, int nrel, int64_t total_tiles, bool center, PlotCounters *d_counters,
                        hipStream_t s) {
     if (total_tiles <= 0) return hipSuccess;
     const int64_t blocks = total_tiles < (1 << 20) ? total_tiles : (1 << 20);
-    hipLaunchKernelGGL(k_plot, dim3((unsigned)blocks), dim3(256), 0, s, d_rels, nrel, total_tiles, d_counters);
+    if (center)
+        hipLaunchKernelGGL(k_plot<true>, dim3((unsigned)blocks), dim3(256), 0, s, d_rels, nrel, total_tiles,
+                           d_counters);
+    else
+        hipLaunchKernelGGL(k_plot<false>, dim3((unsigned)blocks), dim3(256), 0, s, d_rels, nrel, total_tiles,
+                           d_counters);
     return hipGetLastError();
 }
 
@@ -1862,12 +2081,13 @@ __global__ __launch_bounds__(256, KIND % 10 == kStepGemm ? gemm_occupancy(KIND /
         }
         return;
     }
-    PlotCount cnt;
+    CountSink sink;
     for (int64_t item = t0 + blockIdx.x; item < t1; item += gridDim.x) {
         const PStep &st = steps[find_step(steps, first, count, item)];
         if (kind == kStepPlot && st.kind == kStepPlot) {
-            plot_tile(st.plot, item - st.tile_base, reinterpret_cast<float *>(lds),
-                      reinterpret_cast<double *>(lds + kPlotLineWords), cnt);
+            sink.use(st.plot, counters);
+            plot_tile_rule<mode == 1>(st.plot, item - st.tile_base, reinterpret_cast<float *>(lds),
+                      reinterpret_cast<double *>(lds + kPlotLineWords), sink.cnt);
         } else if (kind == kStepContract) {
             const int64_t u0 = (item - st.tile_base) * st.per_tile;
             contract_range<mode>(st.ca, u0, min(st.units, u0 + st.per_tile));
@@ -1879,7 +2099,7 @@ __global__ __launch_bounds__(256, KIND % 10 == kStepGemm ? gemm_occupancy(KIND /
         }
         __syncthreads();
     }
-    if (kind == kStepPlot) flush_counts(cnt, counters);
+    if (kind == kStepPlot) sink.finish();
 }
 
 // Workgroups of the persistent sparse-pass loop: every CU's worth.
@@ -1904,7 +2124,10 @@ hipError_t launch_group(int kind, int mode, const PStep *d_steps, int first, int
     const dim3 grid((unsigned)(kind == kStepGemm ? gemm_grid(nt, mode) : (nt < cap ? nt : cap)));
 #define PA_GROUP(K) hipLaunchKernelGGL(k_group<K>, grid, dim3(256), 0, s, d_steps, first, count, t0, t1, flags, counters)
     switch (kind) {
-        case kStepPlot: PA_GROUP(kStepPlot); break;
+        case kStepPlot:
+            if (mode == 1) PA_GROUP(kStepPlot + 10);      // centre-rule plots
+            else PA_GROUP(kStepPlot);
+            break;
         case kStepGemm:
             if (mode == 1) PA_GROUP(kStepGemm + 10);
             else if (mode == 2) PA_GROUP(kStepGemm + 20);
@@ -1943,7 +2166,7 @@ __global__ __launch_bounds__(256) void k_persist(const PStep *__restrict__ steps
                                                                                        : kPlotLdsWords];
     __shared__ long long s_item;
     __shared__ int s_ok;
-    PlotCount cnt;
+    CountSink sink;
     for (;;) {
         if (threadIdx.x == 0)
             s_item = (long long)__hip_atomic_fetch_add(&state->queue, 1ull, __ATOMIC_RELAXED,
@@ -1975,12 +2198,13 @@ __global__ __launch_bounds__(256) void k_persist(const PStep *__restrict__ steps
         }
         __syncthreads();
         if (!s_ok) break;
-        run_tile(steps[si], tile, lds, cnt);
+        if (steps[si].kind == kStepPlot) sink.use(steps[si].plot, counters);
+        run_tile(steps[si], tile, lds, sink.cnt);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         __syncthreads();
         if (threadIdx.x == 0) __hip_atomic_fetch_add(&done[si], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     }
-    flush_counts(cnt, counters);
+    sink.finish();
 }
 
 __global__ void k_persist_reset(PersistState *state, unsigned int *done, int nsteps) {

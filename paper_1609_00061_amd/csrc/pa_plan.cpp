@@ -401,6 +401,7 @@ struct Builder {
             g.lc = lc;
             g.node = node;
             g.macs = macs;
+            g.dense_macs = macs;
             g.gg = ga;
             g.gg.max_total = -1;      // no decision: the pass always runs
             P->ops.push_back(g);
@@ -430,6 +431,7 @@ struct Builder {
         g.lb = P->buf_layout[bt];
         g.lc = lc;
         g.node = node;
+        g.dense_macs = macs;
         g.gg = ga;
         P->ops.push_back(g);
         emit_gemm(a, la, b, lb, c, lc, nb, nm, node);
@@ -645,7 +647,7 @@ std::string Op::describe() const {
         s << "{\"op\":\"sparse_pass\",\"a\":" << a << ",\"bt\":" << b << ",\"c\":" << c << ",\"flag\":" << flag
           << ",\"a_vars\":" << join(la.vars) << ",\"bt_vars\":" << join(lb.vars) << ",\"c_vars\":" << join(lc.vars)
           << ",\"rows\":" << gg.rows << ",\"Kw\":" << gg.Kw << ",\"Nw\":" << gg.Nw
-          << ",\"max_total\":" << gg.max_total << "}";
+          << ",\"max_total\":" << gg.max_total << ",\"dense_macs\":" << dense_macs << "}";
         return s.str();
     }
     s << "{\"op\":\"" << (kind == OP_GEMM ? "gemm_mfma" : names[mode]) << "\",\"a\":" << a << ",\"b\":" << b
@@ -786,12 +788,20 @@ int build_plan(const pa_system *sys, const int32_t *exposed, int32_t n_exposed, 
     pa_opts dflt{};
     const pa_opts &o = opts ? *opts : dflt;
     P->precision = o.precision;
+    P->plot_rule = o.plot_rule;
+    P->tolerance = o.tolerance;
+    if (o.plot_rule != PA_RULE_CORNER && o.plot_rule != PA_RULE_CENTER)
+        return fail(PA_EINVAL, "opts: unknown plot rule");
+    if (o.plot_rule == PA_RULE_CENTER && !(std::isfinite(o.tolerance) && o.tolerance >= 0.0))
+        return fail(PA_EINVAL, "opts: the centre rule needs a finite tolerance >= 0");
     P->audit = o.audit;
     P->timing = o.timing;
     P->plain = o.plain;
     P->per_op = o.per_op || o.plain;
     P->graph = o.graph && !P->per_op;
-    P->single_launch = o.single_launch && !P->per_op;
+    // the single persistent launch runs corner plots only: centre-rule plans
+    // use the grouped executor
+    P->single_launch = o.single_launch && !P->per_op && o.plot_rule != PA_RULE_CENTER;
     P->persist_wg = o.persist_wg;
     P->plot_strip = o.plot_strip > 0 ? o.plot_strip : 4;
     P->contract_units = o.contract_units > 0 ? o.contract_units : 2048;
@@ -875,10 +885,10 @@ int build_plan(const pa_system *sys, const int32_t *exposed, int32_t n_exposed, 
     P->steps_off = take(sizeof(PStep) * std::max<size_t>(1, nsteps));
     P->done_off = take(sizeof(unsigned) * std::max<size_t>(1, nsteps));
     P->state_off = take(sizeof(PersistState));
-    int64_t corners = 0;
+    int64_t corners = 0;     // points evaluated: corners, or centres under the centre rule
     for (const auto &it : P->plots) {
         int64_t cn = 1;
-        for (int64_t dm : it.layout.dims) cn *= dm + 1;
+        for (int64_t dm : it.layout.dims) cn *= dm + (P->plot_rule == PA_RULE_CENTER ? 0 : 1);
         corners += cn;
     }
     P->corners = corners;
@@ -898,6 +908,9 @@ int build_plan(const pa_system *sys, const int32_t *exposed, int32_t n_exposed, 
         R.d = rel.degree;
         R.mode = P->precision;
         R.audit = P->audit;
+        R.rule = P->plot_rule == PA_RULE_CENTER ? kRuleCenter : kRuleCorner;
+        R.target = rel.target;
+        R.eps = P->tolerance;
         R.row_words = it.layout.rw;
         {
             std::vector<double> c = dense_coef(rel);
@@ -1019,6 +1032,7 @@ static int build_steps(pa_plan *P) {
         PStep s;
         std::memset(&s, 0, sizeof(s));
         s.kind = kStepPlot;
+        s.mode = P->plotrel1_dev[i].rule == kRuleCenter ? 1 : 0;    // one kernel per plotting rule
         s.plot = P->plotrel1_dev[i];
         s.n_tiles = s.plot.n_tiles;
         producer[P->plots[i].buf] = (int)st.size();
@@ -1186,7 +1200,11 @@ int upload_plan(pa_plan *P) {
     std::vector<PlotRel> rels = P->plotrel_host;
     auto fix = [&](const void *off) { return (void *)(base + P->tables_off + (size_t)off); };
     (void)fix;
-    for (auto &R : rels) R.out = (uint32_t *)(base + (size_t)R.out);
+    PlotCounters *cdev = P->counters_dev ? P->counters_dev : reinterpret_cast<PlotCounters *>(base + P->counters_off);
+    for (auto &R : rels) {
+        R.out = (uint32_t *)(base + (size_t)R.out);
+        R.counters = cdev;
+    }
     if (!P->tables_host.empty())
         HIP_TRY(hipMemcpy(base + P->tables_off, P->tables_host.data(), P->tables_host.size(), hipMemcpyHostToDevice));
     P->plotrel1_dev = rels;
@@ -1274,12 +1292,12 @@ static int run_plots(pa_plan *P, hipStream_t s, int *launches) {
     const int nrel = (int)P->plotrel_host.size();
     if (nrel == 0) return PA_OK;
     if (!P->plain) {
-        HIP_TRY(launch_plot(d_rels, nrel, P->total_tiles, cnt, s));
+        HIP_TRY(launch_plot(d_rels, nrel, P->total_tiles, P->plot_rule == PA_RULE_CENTER, cnt, s));
         ++*launches;
     } else {
         const PlotRel *d_one = reinterpret_cast<const PlotRel *>(base + P->plotrel1_off);
         for (int i = 0; i < nrel; ++i) {
-            HIP_TRY(launch_plot(d_one + i, 1, P->plotrel_host[i].n_tiles, cnt, s));
+            HIP_TRY(launch_plot(d_one + i, 1, P->plotrel_host[i].n_tiles, P->plot_rule == PA_RULE_CENTER, cnt, s));
             ++*launches;
         }
     }
@@ -1304,8 +1322,9 @@ static int run_persist(pa_plan *P, hipStream_t s, int *launches, hipEvent_t befo
     if (P->single_launch) {
         for (const PStep &st : P->steps_host)
             if ((st.kind == kStepGemm && (st.gemm.path == 2 || st.gemm.dense)) || st.kind == kStepGather ||
-                st.kind == kStepCount)
-                return fail(PA_EINVAL, "internal: 256-row MFMA tiles or a sparse pass in a single persistent launch");
+                st.kind == kStepCount || (st.kind == kStepPlot && st.plot.rule != kRuleCorner))
+                return fail(PA_EINVAL,
+                            "internal: 256-row MFMA tiles, a sparse pass or a centre plot in a single persistent launch");
         HIP_TRY(launch_persist(d_steps, nsteps, P->n_items, state, done, cnt, (int)wg, s));
         *launches += 2;
     } else {
@@ -1326,13 +1345,24 @@ static int run_persist(pa_plan *P, hipStream_t s, int *launches, hipEvent_t befo
 // the callers' output pointers patched in, directly or as a hipGraph replay.
 int exec_steps(pa_plan *P, const std::vector<void *> &outs, hipStream_t s, int *launches) {
     int rc;
-    if (P->last_outs != outs) {
+    const bool use_graph = P->graph && s != nullptr && P->op_events.empty() && !P->timing_active;
+    const bool new_table = P->last_outs != outs;
+    const bool new_graph = use_graph && (!P->graph_exec || P->graph_outs != outs || P->graph_stream != s);
+    if ((new_table || new_graph) && P->has_run) {
+        // the step table (a synchronous copy) and the graph are rewritten
+        // below: earlier executions, on this stream or the one last used,
+        // must have finished reading them
+        HIP_TRY(hipStreamSynchronize(P->last_stream));
+        if (s != P->last_stream) HIP_TRY(hipStreamSynchronize(s));
+    }
+    if (new_table) {
         rc = upload_steps(P, outs);
         if (rc) return rc;
     }
-    const bool use_graph = P->graph && s != nullptr && P->op_events.empty() && !P->timing_active;
+    P->has_run = true;
+    P->last_stream = s;
     if (use_graph) {
-        if (!P->graph_exec || P->graph_outs != outs || P->graph_stream != s) {
+        if (new_graph) {
             if (P->graph_exec) (void)hipGraphExecDestroy(P->graph_exec);
             if (P->graph_h) (void)hipGraphDestroy(P->graph_h);
             P->graph_exec = nullptr;
@@ -1677,6 +1707,13 @@ extern "C" int pa_solve_system(const pa_system *sys, const int32_t *exposed, int
     }
     pa_plan_destroy(P);
     return rc;
+}
+
+extern "C" size_t pa_workspace_bytes(const pa_system *sys, const int32_t *exposed, int32_t n_exposed,
+                                     const pa_opts *opts) {
+    std::unique_ptr<pa_plan> P(new pa_plan());
+    if (build_plan(sys, exposed, n_exposed, opts, P.get()) != PA_OK) return 0;
+    return std::max<size_t>(P->ws_bytes, 256);
 }
 
 extern "C" int64_t pa_plan_describe(const pa_system *sys, const int32_t *exposed, int32_t n_exposed,

@@ -99,6 +99,8 @@ struct Op {
     GemmArgs ga{};
     int64_t fill_words = 0;
     double macs = 0.0;            // product of the step's link resolutions
+    double dense_macs = 0.0;      // sparse pass: the MACs of the contraction it computes (its
+                                  // dense equivalent; counted in macs only without a fallback)
     int node = -1;
     std::string describe() const;
 };
@@ -157,10 +159,16 @@ struct pa_plan {
     hipGraphExec_t graph_exec = nullptr;
     std::vector<void *> graph_outs;
     hipStream_t graph_stream = nullptr;
+    hipStream_t last_stream = nullptr;        // stream of the last execution (has_run)
+    bool has_run = false;
     double total_macs = 0.0;
     std::vector<unsigned char> tables_host;   // uploaded once
     pa::Workspace ws;
+    pa::PlotCounters *counters_dev = nullptr;   // set by a batch: the system's counters in the batch's
+                                                // table (else the plan's own, at counters_off)
     int precision = PA_PLOT_FP32_ESCALATE;
+    int plot_rule = PA_RULE_CORNER;
+    double tolerance = 0.0;
     int audit = 0, timing = 0, plain = 0;
     int device = 0;
     int64_t corners = 0, total_tiles = 0;

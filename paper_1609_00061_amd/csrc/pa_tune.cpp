@@ -30,8 +30,12 @@ static void fnv(uint64_t &h, uint64_t v) {
     }
 }
 
-// Structure only: resolutions, relation scopes and degrees, exposed lists and
-// the options that change the plan (coefficients do not change the work).
+// Resolutions, relation scopes and degrees, exposed lists and the options
+// that change the plan.  The coefficients decide the densities of the plots
+// and intermediates; every candidate but the sparse pass alone costs the
+// same at any density, so they enter the key only when the tuner is free to
+// pick the pass alone (opts->sparse_pass == 0): such a choice is reused only
+// for the same instance, whose operands it was timed on.
 static std::string signature(const pa_system *systems, int32_t n_sys, const int32_t *const *exposed,
                              const int32_t *n_exposed, const pa_opts &o) {
     uint64_t h = 0xcbf29ce484222325ull;
@@ -44,11 +48,37 @@ static std::string signature(const pa_system *systems, int32_t n_sys, const int3
         for (int r = 0; r < s.n_rel; ++r) {
             fnv(h, (uint64_t)s.rel[r].arity * 16 + (uint64_t)s.rel[r].degree);
             for (int j = 0; j < s.rel[r].arity; ++j) fnv(h, (uint64_t)s.rel[r].vars[j]);
+            if (o.sparse_pass == 0 && s.rel[r].coef && s.rel[r].arity >= 1 && s.rel[r].arity <= PA_MAX_ARITY &&
+                s.rel[r].degree >= 0 && s.rel[r].degree <= PA_MAX_DEGREE) {
+                const int64_t nc = n_monomials(s.rel[r].arity, s.rel[r].degree);
+                for (int64_t c = 0; c < nc; ++c) {
+                    uint64_t bits;
+                    std::memcpy(&bits, &s.rel[r].coef[c], sizeof(bits));
+                    fnv(h, bits);
+                }
+            }
+        }
+        if (o.sparse_pass == 0) {
+            for (int v = 0; v < s.n_vars; ++v) {
+                uint64_t lo, hi;
+                std::memcpy(&lo, &s.axes[v].lo, sizeof(lo));
+                std::memcpy(&hi, &s.axes[v].hi, sizeof(hi));
+                fnv(h, lo);
+                fnv(h, hi);
+            }
         }
         fnv(h, (uint64_t)n_exposed[i]);
         for (int j = 0; j < n_exposed[i]; ++j) fnv(h, (uint64_t)exposed[i][j]);
     }
     fnv(h, (uint64_t)o.order_policy * 97 + (uint64_t)o.precision * 7 + (uint64_t)o.graph);
+    {
+        uint64_t tol;
+        std::memcpy(&tol, &o.tolerance, sizeof(tol));
+        fnv(h, (uint64_t)o.plot_rule);
+        fnv(h, tol);
+        for (int32_t i = 0; i < n_sys; ++i)
+            for (int r = 0; r < systems[i].n_rel; ++r) fnv(h, (uint64_t)systems[i].rel[r].target);
+    }
     fnv(h, (uint64_t)(o.sparse_pass + 1));
     int dev = 0;
     hipDeviceProp_t prop{};

@@ -20,6 +20,8 @@ ORDER_GREEDY, ORDER_EXHAUSTIVE, ORDER_LEARNED, ORDER_GIVEN = 0, 1, 2, 3
 OPKIND_BITS, OPKIND_STREAM_K, OPKIND_STREAM_W, OPKIND_GEMM, OPKIND_FILL = 0, 1, 2, 10, 20
 OPKIND_GATHER, OPKIND_COUNT, OPKIND_PLOT, OPKIND_PERSIST = 25, 26, 30, 40
 PLOT_FP32_ESCALATE, PLOT_FP64 = 0, 1
+RULE_CORNER, RULE_CENTER = 0, 1
+TARGET_EQ, TARGET_LE, TARGET_LT = 0, 1, 2
 MAX_DIMS, MAX_RELATIONS = 12, 32
 MODEL_FEATURES = 16
 
@@ -39,7 +41,8 @@ class Axis(ctypes.Structure):
 
 class Relation(ctypes.Structure):
     _fields_ = [("arity", ctypes.c_int32), ("degree", ctypes.c_int32),
-                ("vars", ctypes.POINTER(ctypes.c_int32)), ("coef", ctypes.POINTER(ctypes.c_double))]
+                ("vars", ctypes.POINTER(ctypes.c_int32)), ("coef", ctypes.POINTER(ctypes.c_double)),
+                ("target", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class BitArray(ctypes.Structure):
@@ -62,7 +65,8 @@ class Opts(ctypes.Structure):
                 ("model", ctypes.c_void_p), ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
                 ("autotune", ctypes.c_int32), ("gemm_split", ctypes.c_int32), ("gemm_path", ctypes.c_int32),
                 ("verify_order", ctypes.c_int32), ("sparse_pass", ctypes.c_int32),
-                ("sparse_max_density", ctypes.c_int32)]
+                ("sparse_max_density", ctypes.c_int32), ("plot_rule", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("tolerance", ctypes.c_double)]
 
 
 class Tuning(ctypes.Structure):
@@ -125,8 +129,7 @@ def load(path: str = LIB_PATH):
     L.pa_plan_op_times.restype = ctypes.c_int32
     L.pa_batch_create.argtypes = [ctypes.POINTER(System), ctypes.c_int32, ctypes.POINTER(ctypes.POINTER(ctypes.c_int32)),
                                   i32p, ctypes.POINTER(Opts), ctypes.POINTER(vp)]
-    L.pa_batch_execute.argtypes = [vp, ctypes.POINTER(BitArray), ctypes.POINTER(Report),
-                                   ctypes.POINTER(ctypes.c_int64), vp]
+    L.pa_batch_execute.argtypes = [vp, ctypes.POINTER(BitArray), ctypes.POINTER(Report), ctypes.POINTER(Report), vp]
     L.pa_batch_workspace_bytes.argtypes = [vp]
     L.pa_batch_workspace_bytes.restype = ctypes.c_size_t
     L.pa_batch_op_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32),
@@ -135,7 +138,9 @@ def load(path: str = LIB_PATH):
     L.pa_batch_destroy.argtypes = [vp]
     L.pa_batch_destroy.restype = None
     L.pa_solve_batch.argtypes = [ctypes.POINTER(System), ctypes.c_int32, ctypes.POINTER(ctypes.POINTER(ctypes.c_int32)),
-                                 i32p, ctypes.POINTER(Opts), ctypes.POINTER(BitArray), ctypes.POINTER(ctypes.c_int64), vp]
+                                 i32p, ctypes.POINTER(Opts), ctypes.POINTER(BitArray), ctypes.POINTER(Report), vp]
+    L.pa_workspace_bytes.argtypes = [ctypes.POINTER(System), i32p, ctypes.c_int32, ctypes.POINTER(Opts)]
+    L.pa_workspace_bytes.restype = ctypes.c_size_t
     fp = ctypes.POINTER(ctypes.c_float)
     L.pa_model_n_params.restype = ctypes.c_int32
     L.pa_model_n_features.restype = ctypes.c_int32
@@ -198,7 +203,7 @@ class _Keep:
 
 def _relation(keep, rel, var_map=None) -> Relation:
     vs = list(rel.vars) if var_map is None else [var_map[v] for v in rel.vars]
-    return Relation(len(vs), int(rel.degree), keep.i32(vs), keep.f64(rel.coef))
+    return Relation(len(vs), int(rel.degree), keep.i32(vs), keep.f64(rel.coef), int(getattr(rel, "target", 0)), 0)
 
 
 def _system(keep, system) -> System:
@@ -212,7 +217,9 @@ def make_opts(order=ORDER_EXHAUSTIVE, precision=PLOT_FP32_ESCALATE, audit=False,
               given: Optional[Sequence[int]] = None, model=None, keep: Optional[_Keep] = None, per_op=False,
               graph=False, single_launch=False, persist_wg=0, plot_strip=0, contract_units=0,
               autotune=False, gemm_split=0, gemm_path=0, verify_order=False, sparse_pass=0,
-              sparse_max_density=0) -> Opts:
+              sparse_max_density=0, workspace=None, plot_rule=RULE_CORNER, tolerance=0.0) -> Opts:
+    """pa_opts from keyword arguments; `workspace` is a device tensor the
+    caller owns (its data pointer and byte size are passed)."""
     o = Opts()
     o.order_policy = order
     o.precision = precision
@@ -231,6 +238,11 @@ def make_opts(order=ORDER_EXHAUSTIVE, precision=PLOT_FP32_ESCALATE, audit=False,
     o.verify_order = int(verify_order)
     o.sparse_pass = int(sparse_pass)
     o.sparse_max_density = int(sparse_max_density)
+    o.plot_rule = int(plot_rule)
+    o.tolerance = float(tolerance)
+    if workspace is not None:
+        o.workspace = ctypes.c_void_p(workspace.data_ptr())
+        o.workspace_bytes = workspace.numel() * workspace.element_size()
     if given is not None:
         assert keep is not None
         o.n_given = len(given) // 2
@@ -428,17 +440,22 @@ class Batch:
     def alloc_outputs(self):
         return [empty_bits(d) for d in self.dims]
 
-    def execute(self, outs=None, stream=None, report=False):
-        """Returns (outs, report dict or None, nnz list or None)."""
+    def execute(self, outs=None, stream=None, report=False, per_system=False):
+        """Returns (outs, report dict or None, nnz list or None), plus the list
+        of per-system report dicts when per_system is set."""
         L = load()
         if outs is None:
             outs = self.alloc_outputs()
         bas = (BitArray * len(outs))(*[bitarray(t, d) for t, d in zip(outs, self.dims)])
         rep = Report() if report else None
-        nnz = (ctypes.c_int64 * len(outs))() if report else None
-        _check(L.pa_batch_execute(self.handle, bas, ctypes.byref(rep) if report else None, nnz,
+        reps = (Report * len(outs))() if (report or per_system) else None
+        _check(L.pa_batch_execute(self.handle, bas, ctypes.byref(rep) if report else None, reps,
                                   _stream_ptr(stream)))
-        return outs, (rep.as_dict() if report else None), (list(nnz) if report else None)
+        nnz = [int(r.nnz_out) for r in reps] if reps is not None else None
+        res = (outs, (rep.as_dict() if report else None), nnz if report else None)
+        if per_system:
+            res = res + ([_report_dict(r) for r in reps],)
+        return res
 
     def op_times(self):
         L = load()
@@ -575,11 +592,65 @@ def autotune(systems, reps=3, stream=None, **opts_kw):
     return best.as_dict(), [tried[i].as_dict() for i in range(min(n.value, cap))]
 
 
-def solve_system(system, exposed=None, **kw):
-    """Plan + execute; returns (device words, dims, report dict)."""
-    p = Plan(system, exposed, **kw)
-    out, rep, _ = p.execute(report=True)
-    return out, p.dims, rep
+def _report_dict(rep: Report) -> dict:
+    d = rep.as_dict()
+    d["merges"] = [int(x) for x in rep.merges[:2 * MAX_RELATIONS]]
+    return d
+
+
+def solve_system(system, exposed=None, order=ORDER_EXHAUSTIVE, precision=PLOT_FP32_ESCALATE, audit=False,
+                 timing=False, plain=False, given=None, model=None, stream=None, **exec_opts):
+    """pa_solve_system (plan, execute, destroy); returns (device words, dims,
+    report dict)."""
+    L = load()
+    keep = _Keep()
+    exposed = list(system.exposed if exposed is None else exposed)
+    dims = [int(system.axes[v][2]) for v in exposed]
+    s = _system(keep, system)
+    opts = make_opts(order=order, precision=precision, audit=audit, timing=timing, plain=plain, given=given,
+                     model=model, keep=keep, **exec_opts)
+    out = empty_bits(dims)
+    ba = bitarray(out, dims)
+    rep = Report()
+    _check(L.pa_solve_system(ctypes.byref(s), keep.i32(exposed), len(exposed), ctypes.byref(opts), ctypes.byref(ba),
+                             ctypes.byref(rep), _stream_ptr(stream)))
+    return out, dims, rep.as_dict()
+
+
+def solve_batch(systems, order=ORDER_EXHAUSTIVE, precision=PLOT_FP32_ESCALATE, audit=False, model=None, stream=None,
+                **exec_opts):
+    """pa_solve_batch (batch create, execute, destroy); returns (list of device
+    words, list of dims, list of per-system report dicts)."""
+    L = load()
+    keep = _Keep()
+    systems = list(systems)
+    dims = [[int(s.axes[v][2]) for v in s.exposed] for s in systems]
+    arr = (System * len(systems))(*[_system(keep, s) for s in systems])
+    exps = [keep.i32(list(s.exposed)) for s in systems]
+    exp_ptrs = (ctypes.POINTER(ctypes.c_int32) * len(exps))(*[ctypes.cast(e, ctypes.POINTER(ctypes.c_int32)) for e in exps])
+    n_exp = keep.i32([len(s.exposed) for s in systems])
+    keep.items += [arr, exp_ptrs]
+    opts = make_opts(order=order, precision=precision, audit=audit, model=model, keep=keep, **exec_opts)
+    outs = [empty_bits(d) for d in dims]
+    bas = (BitArray * len(outs))(*[bitarray(t, d) for t, d in zip(outs, dims)])
+    reps = (Report * len(outs))()
+    _check(L.pa_solve_batch(arr, len(systems), exp_ptrs, n_exp, ctypes.byref(opts), bas, reps, _stream_ptr(stream)))
+    return outs, dims, [_report_dict(r) for r in reps]
+
+
+def workspace_bytes(system, exposed=None, order=ORDER_EXHAUSTIVE, precision=PLOT_FP32_ESCALATE, given=None,
+                    model=None, **exec_opts) -> int:
+    """pa_workspace_bytes: device bytes a plan of this system needs (host
+    planning only, no allocation).  Raises PaError on invalid input."""
+    L = load()
+    keep = _Keep()
+    exposed = list(system.exposed if exposed is None else exposed)
+    s = _system(keep, system)
+    opts = make_opts(order=order, precision=precision, given=given, model=model, keep=keep, **exec_opts)
+    n = int(L.pa_workspace_bytes(ctypes.byref(s), keep.i32(exposed), len(exposed), ctypes.byref(opts)))
+    if n == 0:
+        raise PaError(PA_EINVAL, L.pa_last_error().decode())
+    return n
 
 
 def popcount(t, dims) -> int:

@@ -258,3 +258,18 @@ def test_plan_create_rejects_before_touching_the_device():
     with pytest.raises(pa.PaError) as e:
         pa.Plan(s)
     assert e.value.code == pa.PA_EINVAL
+
+
+def test_workspace_bytes_is_host_planning():
+    """pa_workspace_bytes sizes a plan on the host (no device here): the
+    figure equals the plan description's, and invalid systems give an error
+    instead of a size."""
+    for s in (inputs.config1(), inputs.config2(), inputs.config3()):
+        for kw in (dict(), dict(order=pa.ORDER_GREEDY, plain=True), dict(sparse_pass=2)):
+            assert pa.workspace_bytes(s, **kw) == max(256, pa.describe_plan(s, **kw)["workspace_bytes"])
+    with pytest.raises(pa.PaError):
+        pa.workspace_bytes(inputs.config1(), exposed=[0, 0])
+    s = inputs.config1()
+    s.axes = [(-2.0, 2.0, 1)] + s.axes[1:]
+    with pytest.raises(pa.PaError):
+        pa.workspace_bytes(s)

@@ -53,21 +53,27 @@ def test_random_hypergraph_batch():
         assert np.array_equal(to_host(o, d), ref), i
 
 
-def test_full_size_batch_sampled():
-    """The 512-chain workload (resolutions 64..2048) in one batch; every
-    eighth system checked exactly against the oracle's pairwise chain."""
+def test_full_size_batch_exact():
+    """The 512-chain workload (resolutions 64..2048) in one batch replayed as
+    one graph: every system's output compared entry by entry with the
+    oracle's pairwise chain, and its per-system report (set bits, corners,
+    escalations summing to the batch total)."""
     import torch
     systems = inputs.config4()
     note("batch c4", len(systems))
     b = pa.Batch(systems, graph=True)
-    outs, rep, nnz = b.execute(stream=torch.cuda.Stream(), report=True)
+    outs, rep, nnz, reps = b.execute(stream=torch.cuda.Stream(), report=True, per_system=True)
     torch.cuda.synchronize()
-    for i in range(0, len(systems), 64):
-        s = systems[i]
+    assert sum(r["corners_flagged"] for r in reps) == rep["corners_flagged"]
+    for i, s in enumerate(systems):
         plots = [oracle.plot(r, s.axes)[0] for r in s.relations]
         res = {v: s.axes[v][2] for v in range(len(s.axes))}
         n = len(s.relations)
         merges = [(0, 1)] + [(n + t, t + 2) for t in range(n - 2)]
         ref = oracle.solve_pairwise(res, [r.vars for r in s.relations], plots, s.exposed, merges)
         assert np.array_equal(to_host(outs[i], b.dims[i]), ref), s.name
-        assert nnz[i] == int(ref.sum())
+        assert nnz[i] == int(ref.sum()) == reps[i]["nnz_out"]
+        assert reps[i]["corners"] == sum((s.axes[r.vars[0]][2] + 1) * (s.axes[r.vars[1]][2] + 1)
+                                         for r in s.relations)
+        if i % 64 == 0:
+            note("batch c4: checked through system", i)

@@ -198,25 +198,25 @@ def test_c2_full_size_exact():
         assert np.array_equal(got3, ref), kw
 
 
-def test_c3_full_size_sampled():
-    """Four ternary relations at 256^3: sampled output entries evaluated one by
-    one by the oracle (eqn GAM with short-circuit), plus every set entry."""
+def test_c3_full_size_exact():
+    """Four ternary relations at 256^3, the whole 256 x 256 output compared
+    entry by entry with the oracle (plots, then the cluster tree
+    {{R1, R2}, {R3, R4}} multiplied pairwise), for the default plan (sparse
+    pass with MFMA fallback), the MFMA kernel alone on both operand paths,
+    the fallback taken (density threshold 1/1024), the pass alone, and the
+    plain path."""
     s = inputs.config3()
+    note("c3 full: oracle plots and pairwise solve")
     plots = _oracle_plots(s)
-    got, rep = _solve(s)
-    res = [a[2] for a in s.axes]
-    rng = inputs.SplitMix64(77)
-    ent = np.array([[rng.randint(0, 255), rng.randint(0, 255)] for _ in range(200)], dtype=np.int32)
-    on = np.argwhere(got == 1)
-    if len(on) > 300:
-        on = on[:: max(1, len(on) // 300)]
-    ent = np.concatenate([ent, on.astype(np.int32)]) if len(on) else ent
-    ref = oracle.solve_entries(res, [r.vars for r in s.relations], plots, s.exposed, ent)
-    assert np.array_equal(got[tuple(ent.T)], ref)
-    note("c3 nnz", int(got.sum()), "flagged", rep["corners_flagged"])
-    # the sparse pass (default here) and the MFMA operand paths alone give the same array
+    res = {v: s.axes[v][2] for v in range(len(s.axes))}
+    ref = oracle.solve_pairwise(res, [r.vars for r in s.relations], plots, s.exposed, [(0, 1), (2, 3), (4, 5)],
+                                log=note)
+    del plots
+    note("c3 full: oracle nnz", int(ref.sum()))
     assert [o["op"] for o in pa.describe_plan(s)["ops"]].count("sparse_pass") == 2
-    for kw in (dict(sparse_pass=-1), dict(sparse_pass=-1, gemm_path=2), dict(sparse_max_density=1),
-               dict(sparse_pass=2)):
-        got2, _ = _solve(s, **kw)
-        assert np.array_equal(got2, got), kw
+    for kw in (dict(), dict(sparse_pass=-1), dict(sparse_pass=-1, gemm_path=2), dict(sparse_max_density=1),
+               dict(sparse_pass=2), dict(plain=True, order=pa.ORDER_GREEDY)):
+        got, rep = _solve(s, **kw)
+        note("c3 full", kw, "nnz", int(got.sum()), "flagged", rep["corners_flagged"])
+        assert np.array_equal(got, ref), kw
+        assert rep["nnz_out"] == int(ref.sum())
