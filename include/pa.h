@@ -254,6 +254,18 @@ int pa_plot_relation(const pa_relation *rel, const pa_axis *axes_of_vars, const 
 int pa_contract(const pa_bitarray *A, const int32_t *a_vars, const pa_bitarray *B, const int32_t *b_vars,
                 const int32_t *out_vars, int32_t n_out, pa_bitarray *C, const pa_opts *opts, void *stream);
 
+/* pa_contract for callers that cannot allocate device memory (code under
+ * hipGraph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same arguments, layouts and results, and no hipMalloc, hipFree or other
+ * allocation.  Its one scratch buffer -- the latent-entry table of a streamed
+ * contraction -- is a static device array of the library (1 MiB per GPU, kept
+ * until the process ends), written by a kernel on `stream`; contractions with
+ * more than 65536 latent entries (outside the packed latent variable) are
+ * refused with PA_ENOMEM.  Every call on one GPU shares that GPU's array:
+ * calls that overlap on one GPU (other streams, other threads) race. */
+int pa_contract_noalloc(const pa_bitarray *A, const int32_t *a_vars, const pa_bitarray *B, const int32_t *b_vars,
+                        const int32_t *out_vars, int32_t n_out, pa_bitarray *C, const pa_opts *opts, void *stream);
+
 /* Plan a whole solve: choose the cluster tree (opts->order_policy), lay out
  * every intermediate, upload coefficient and axis tables and size the
  * workspace.  exposed lists the outer pack's variables in the output's axis

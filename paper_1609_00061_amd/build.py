@@ -8,7 +8,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpa.so")
 
-SOURCES = ["pa_kernels.hip", "pa_mlp.hip", "pa_host.cpp", "pa_planner.cpp", "pa_plan.cpp", "pa_batch.cpp",
+SOURCES = ["pa_kernels.hip", "pa_mlp.hip", "pa_noalloc.hip", "pa_host.cpp", "pa_planner.cpp", "pa_plan.cpp", "pa_batch.cpp",
            "pa_model.cpp", "pa_tune.cpp"]
 HEADERS = ["pa_internal.h", "pa_plan.h", "pa_mlp.h"]
 

@@ -216,6 +216,11 @@ struct PersistState {
 hipError_t launch_plot(const PlotRel *d_rels, int nrel, int64_t total_tiles, bool center, PlotCounters *d_counters,
                        hipStream_t s);
 hipError_t launch_contract(const ContractArgs &a, int mode, hipStream_t s);
+// The latent-entry table of a streamed contraction (the host's ordering:
+// entry e lists the A and B word offsets of the e-th latent index tuple, last
+// latent variable fastest, the packed one left out in mode K), written by a
+// kernel into tab (2 * n int64).
+hipError_t launch_ktab(const ContractArgs &a, int mode, int64_t *tab, int64_t n, hipStream_t s);
 hipError_t launch_gemm(const GemmArgs &g, hipStream_t s);
 hipError_t launch_gather(const GatherArgs &g, hipStream_t s);
 hipError_t launch_count(const GatherArgs &g, hipStream_t s);

@@ -1158,6 +1158,30 @@ __device__ __forceinline__ bool sparse_ran(const uint32_t *parts, int64_t nparts
     return c <= (unsigned long long)max_total;
 }
 
+// Latent-entry table on the device: entry e is the mixed-radix tuple of the
+// latent variables (last fastest; mode K skips the shared packed one, which
+// the kernel walks word by word) and its word offsets in A and B.
+__global__ void k_ktab(ContractArgs a, int mode, int64_t *tab, int64_t n) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        int64_t rem = e, oa = 0, ob = 0;
+        for (int j = a.nk - 1; j >= 0; --j) {
+            if (mode == kModeStreamK && j == a.a_pk_k) continue;
+            const int64_t idx = rem % a.k_dim[j];
+            rem /= a.k_dim[j];
+            oa += idx * a.ka_str[j];
+            ob += idx * a.kb_str[j];
+        }
+        tab[2 * e] = oa;
+        tab[2 * e + 1] = ob;
+    }
+}
+
+hipError_t launch_ktab(const ContractArgs &a, int mode, int64_t *tab, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ktab, grid_for(n), dim3(256), 0, s, a, mode, tab, n);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------- MFMA contraction
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));

@@ -1805,9 +1805,13 @@ extern "C" int pa_popcount(const pa_bitarray *a, int64_t *count, void *stream) {
 }
 
 // ---------------------------------------------------------- pa_contract
-extern "C" int pa_contract(const pa_bitarray *A, const int32_t *a_vars, const pa_bitarray *B, const int32_t *b_vars,
-                           const int32_t *out_vars, int32_t n_out, pa_bitarray *C, const pa_opts *opts, void *stream) {
-    (void)opts;
+// pa_contract, and (with `tab` a device buffer of tab_cap int64 entries)
+// its variant that allocates nothing: the latent-entry table of a streamed
+// contraction is then written into `tab` by a kernel on the stream instead of
+// being copied from the host into a stream-ordered allocation.
+int pa::contract_impl(const pa_bitarray *A, const int32_t *a_vars, const pa_bitarray *B, const int32_t *b_vars,
+                      const int32_t *out_vars, int32_t n_out, pa_bitarray *C, const pa_opts *opts, void *stream,
+                      int64_t *tab_dev, int64_t tab_cap) {
     if (!A || !C || (!a_vars && A->ndim > 0) || (n_out > 0 && !out_vars)) return fail(PA_EINVAL, "contract: null argument");
     if (A->ndim < 0 || A->ndim > PA_MAX_DIMS || n_out < 0 || n_out > PA_MAX_DIMS || (B && (B->ndim < 0 || B->ndim > PA_MAX_DIMS)))
         return fail(PA_EINVAL, "contract: rank out of range");
@@ -1904,6 +1908,17 @@ extern "C" int pa_contract(const pa_bitarray *A, const int32_t *a_vars, const pa
     op.ca.A = static_cast<const uint32_t *>(A->data);
     op.ca.B = B ? static_cast<const uint32_t *>(B->data) : nullptr;
     op.ca.C = static_cast<uint32_t *>(C->data);
+    if (tab_dev) {
+        if ((int64_t)op.ktab.size() > tab_cap)
+            return fail(PA_ENOMEM, "contract: latent-entry table of " + std::to_string(op.ktab.size() / 2) +
+                                       " entries exceeds the static buffer (" + std::to_string(tab_cap / 2) + ")");
+        if (!op.ktab.empty()) {
+            HIP_TRY(launch_ktab(op.ca, op.mode, tab_dev, op.ca.nktab, s));
+            op.ca.ktab = tab_dev;
+        }
+        HIP_TRY(launch_contract(op.ca, op.mode, s));
+        return PA_OK;
+    }
     void *tab = nullptr;
     if (!op.ktab.empty()) {
         // stream-ordered table: allocated, filled, used and freed on `s`
@@ -1920,4 +1935,9 @@ extern "C" int pa_contract(const pa_bitarray *A, const int32_t *a_vars, const pa
     }
     if (le != hipSuccess) return fail(PA_EHIP, std::string("contract launch: ") + hipGetErrorString(le));
     return PA_OK;
+}
+
+extern "C" int pa_contract(const pa_bitarray *A, const int32_t *a_vars, const pa_bitarray *B, const int32_t *b_vars,
+                           const int32_t *out_vars, int32_t n_out, pa_bitarray *C, const pa_opts *opts, void *stream) {
+    return contract_impl(A, a_vars, B, b_vars, out_vars, n_out, C, opts, stream, nullptr, 0);
 }

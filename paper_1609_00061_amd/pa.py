@@ -111,6 +111,7 @@ def load(path: str = LIB_PATH):
                                    ctypes.POINTER(BitArray), ctypes.POINTER(Report), vp]
     L.pa_contract.argtypes = [ctypes.POINTER(BitArray), i32p, ctypes.POINTER(BitArray), i32p, i32p, ctypes.c_int32,
                               ctypes.POINTER(BitArray), ctypes.POINTER(Opts), vp]
+    L.pa_contract_noalloc.argtypes = L.pa_contract.argtypes
     L.pa_plan_create.argtypes = [ctypes.POINTER(System), i32p, ctypes.c_int32, ctypes.POINTER(Opts),
                                  ctypes.POINTER(vp)]
     L.pa_plan_execute.argtypes = [vp, ctypes.POINTER(BitArray), ctypes.POINTER(Report), vp]
@@ -318,17 +319,21 @@ def plot_relation(rel, axes_of_vars, precision=PLOT_FP32_ESCALATE, audit=False, 
     return out, dims, (rep.as_dict() if report else None)
 
 
-def contract(A, a_dims, a_vars, B, b_dims, b_vars, out_vars, out_dims, stream=None, plain=False, **exec_opts):
-    """C(out_vars) = OR over the other variables of A AND B (B may be None)."""
+def contract(A, a_dims, a_vars, B, b_dims, b_vars, out_vars, out_dims, stream=None, plain=False, noalloc=False,
+             out=None, **exec_opts):
+    """C(out_vars) = OR over the other variables of A AND B (B may be None).
+    noalloc: call pa_contract_noalloc (no device allocation by the library);
+    out: the caller's output buffer (else a new one)."""
     L = load()
     keep = _Keep()
-    C = empty_bits(out_dims)
+    C = empty_bits(out_dims) if out is None else out
     ba, bc = bitarray(A, a_dims), bitarray(C, out_dims)
     bb = bitarray(B, b_dims) if B is not None else None
     opts = make_opts(plain=plain, **exec_opts)
-    _check(L.pa_contract(ctypes.byref(ba), keep.i32(a_vars), ctypes.byref(bb) if bb is not None else None,
-                         keep.i32(b_vars if B is not None else []), keep.i32(out_vars), len(out_vars),
-                         ctypes.byref(bc), ctypes.byref(opts), _stream_ptr(stream)))
+    fn = L.pa_contract_noalloc if noalloc else L.pa_contract
+    _check(fn(ctypes.byref(ba), keep.i32(a_vars), ctypes.byref(bb) if bb is not None else None,
+              keep.i32(b_vars if B is not None else []), keep.i32(out_vars), len(out_vars),
+              ctypes.byref(bc), ctypes.byref(opts), _stream_ptr(stream)))
     return C
 
 
