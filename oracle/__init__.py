@@ -12,6 +12,7 @@ Contents (each function cites the paper passage it follows):
   centers, plot_center                   -- Def. sample_in_center (C)
   plot_relation                          -- dispatch on rule and target
   contract                               -- Sec. 3.3 GAM of a two-pack cluster (C)
+  contract_count, alg1_literal_count     -- the same in the semiring N (counts)
   solve_entries, solve                   -- eqn GAM for a whole diagram with
                                             short-circuit AND/OR (C)
   alg1_literal                           -- Alg. "Generalized array
@@ -67,6 +68,8 @@ def lib():
         L.orc_plot_center.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, dp, ip, ctypes.c_double, ctypes.c_int,
                                       ucp, ctypes.c_int]
         L.orc_plot_center.restype = ctypes.c_int
+        L.orc_contract_count.argtypes = [ucp, ctypes.c_int, ip, ucp, ctypes.c_int, ip, ctypes.c_int, ip, ip, ucp]
+        L.orc_contract_count.restype = ctypes.c_int
         L.orc_contract.argtypes = [ucp, ctypes.c_int, ip, ucp, ctypes.c_int, ip,
                                    ctypes.c_int, ip, ip, ucp, ctypes.c_int]
         L.orc_contract.restype = ctypes.c_int
@@ -209,6 +212,40 @@ def contract(A: np.ndarray, a_vars: Sequence[int], B: np.ndarray, b_vars: Sequen
     if rc:
         raise ValueError(f"orc_contract failed ({rc})")
     return C
+
+
+def contract_count(A: np.ndarray, a_vars: Sequence[int], B: np.ndarray, b_vars: Sequence[int],
+                   out_vars: Sequence[int], var_res: Dict[int, int]) -> np.ndarray:
+    """C(out_vars) = sum over entries of vars(A) u vars(B) of A * B in the
+    semiring N (uint64, saturating): the count-semiring GAM of two packs."""
+    nv = max(list(a_vars) + list(b_vars) + list(out_vars) + [0]) + 1
+    res = _i32([var_res.get(v, 1) for v in range(nv)])
+    A = np.ascontiguousarray(A, dtype=np.uint64)
+    B = np.ascontiguousarray(B, dtype=np.uint64)
+    assert A.shape == tuple(var_res[v] for v in a_vars)
+    assert B.shape == tuple(var_res[v] for v in b_vars)
+    C = np.empty(tuple(var_res[v] for v in out_vars), dtype=np.uint64)
+    av, bv, cv = _i32(a_vars), _i32(b_vars), _i32(out_vars)
+    rc = lib().orc_contract_count(A.ctypes.data, len(a_vars), _ip(av), B.ctypes.data, len(b_vars), _ip(bv),
+                                  len(out_vars), _ip(cv), _ip(res), C.ctypes.data)
+    if rc:
+        raise ValueError(f"orc_contract_count failed ({rc})")
+    return C
+
+
+def alg1_literal_count(var_res: Sequence[int], rel_vars: Sequence[Sequence[int]],
+                       arrays: Sequence[np.ndarray], exposed: Sequence[int]) -> np.ndarray:
+    """Alg. "Generalized array multiplication" as printed, in the semiring N:
+    A'(Entr'(e)) += prod_i A_i(Entr^i(e)) over every link entry e.  Python
+    integers; tiny inputs."""
+    out = np.zeros(tuple(int(var_res[v]) for v in exposed), dtype=object)
+    for e in itertools.product(*[range(int(r)) for r in var_res]):
+        a_e = 1
+        for A, vs in zip(arrays, rel_vars):
+            a_e = a_e * int(A[tuple(e[v] for v in vs)])
+        ep = tuple(e[v] for v in exposed)
+        out[ep] = out[ep] + a_e
+    return out
 
 
 def solve_entries(var_res: Sequence[int], rel_vars: Sequence[Sequence[int]],

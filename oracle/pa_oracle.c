@@ -467,6 +467,50 @@ int orc_contract(const unsigned char *A, int na, const int *a_vars,
     return 0;
 }
 
+/* ------------------------------------- pairwise contraction, count semiring */
+/* Generalized array multiplication of a two-pack cluster in the semiring N of
+ * natural numbers (footnote on semirings in Sec. 2.2, Notation of Ch. 3: the
+ * same formula with + and * of N): C(e') = sum over the entries of
+ * vars(A) u vars(B) projecting to e' of A(e_A) * B(e_B).  Entries are uint64;
+ * sums and products saturate at UINT64_MAX.  Plain nested loops over every
+ * entry of A and, for each nonzero one, every entry of the variables only B
+ * has (no index structure: the inputs here are small).  Single-threaded. */
+static uint64_t sat_add(uint64_t a, uint64_t b) { return a > UINT64_MAX - b ? UINT64_MAX : a + b; }
+static uint64_t sat_mul(uint64_t a, uint64_t b) { return (a != 0 && b > UINT64_MAX / a) ? UINT64_MAX : a * b; }
+
+int orc_contract_count(const uint64_t *A, int na, const int *a_vars, const uint64_t *B, int nb, const int *b_vars,
+                       int nc, const int *c_vars, const int *var_res, uint64_t *C) {
+    int in_a[ORC_MAXV] = {0}, in_b[ORC_MAXV] = {0};
+    for (int i = 0; i < na; ++i) { if (a_vars[i] < 0 || a_vars[i] >= ORC_MAXV || in_a[a_vars[i]]) return -1; in_a[a_vars[i]] = 1; }
+    for (int i = 0; i < nb; ++i) { if (b_vars[i] < 0 || b_vars[i] >= ORC_MAXV || in_b[b_vars[i]]) return -1; in_b[b_vars[i]] = 1; }
+    for (int i = 0; i < nc; ++i) if (c_vars[i] < 0 || c_vars[i] >= ORC_MAXV || !(in_a[c_vars[i]] || in_b[c_vars[i]])) return -1;
+    if (na > ORC_MAXDIM || nb > ORC_MAXDIM || nc > ORC_MAXDIM) return -1;
+    int bx[ORC_MAXDIM], nbx = 0;
+    for (int i = 0; i < nb; ++i) if (!in_a[b_vars[i]]) bx[nbx++] = b_vars[i];
+    long sizeA = 1, sizeBX = 1, sizeC = 1;
+    for (int i = 0; i < na; ++i) sizeA *= var_res[a_vars[i]];
+    for (int i = 0; i < nbx; ++i) sizeBX *= var_res[bx[i]];
+    for (int i = 0; i < nc; ++i) sizeC *= var_res[c_vars[i]];
+    for (long i = 0; i < sizeC; ++i) C[i] = 0;
+    int val[ORC_MAXV];
+    for (long ea = 0; ea < sizeA; ++ea) {
+        if (!A[ea]) continue;
+        long rem = ea;
+        for (int i = na - 1; i >= 0; --i) { val[a_vars[i]] = (int)(rem % var_res[a_vars[i]]); rem /= var_res[a_vars[i]]; }
+        for (long eb = 0; eb < sizeBX; ++eb) {
+            long r2 = eb;
+            for (int i = nbx - 1; i >= 0; --i) { val[bx[i]] = (int)(r2 % var_res[bx[i]]); r2 /= var_res[bx[i]]; }
+            long ib = 0;
+            for (int i = 0; i < nb; ++i) ib = ib * var_res[b_vars[i]] + val[b_vars[i]];
+            if (!B[ib]) continue;
+            long ic = 0;
+            for (int i = 0; i < nc; ++i) ic = ic * var_res[c_vars[i]] + val[c_vars[i]];
+            C[ic] = sat_add(C[ic], sat_mul(A[ea], B[ib]));
+        }
+    }
+    return 0;
+}
+
 /* --------------------------------------------------- whole-diagram formula */
 /* eqn GAM for a whole wiring diagram with short-circuit evaluation: variables
  * are assigned one at a time (exposed ones first, in the order given, then the

@@ -172,3 +172,58 @@ def test_solve_entries_sampled_equals_full():
     ent = np.indices(full.shape).reshape(len(exposed), -1).T[::3]
     part = oracle.solve_entries(var_res, rel_vars, arrays, exposed, ent)
     assert np.array_equal(part, full[tuple(ent.T)])
+
+
+# ------------------------------------------------------------ count semiring
+@pytest.mark.parametrize("case", CASES)
+def test_count_contract_matches_printed_algorithm(case):
+    """The printed algorithm run in the semiring N (sum of products over every
+    link entry) equals the oracle's count contraction, on 0/1 inputs (plots)
+    and on small integer inputs (intermediate counts)."""
+    a_vars, b_vars, out_vars = case
+    res = {0: 3, 1: 4, 2: 2, 3: 3}
+    for seed in range(3):
+        A = _rand([res[v] for v in a_vars], 0.5, 400 + seed).astype(np.uint64)
+        B = _rand([res[v] for v in b_vars], 0.5, 500 + seed).astype(np.uint64)
+        if seed == 2:
+            A = A * np.uint64(3) + _rand(A.shape, 0.5, 600).astype(np.uint64)
+            B = B * np.uint64(5)
+        C = oracle.contract_count(A, a_vars, B, b_vars, out_vars, res)
+        nv = 1 + max(a_vars + b_vars)
+        ref = oracle.alg1_literal_count([res[v] for v in range(nv)], [a_vars, b_vars], [A, B], out_vars)
+        assert np.array_equal(C.astype(object), ref)
+
+
+def test_count_matmul_special_case():
+    """Thm after eqn GAM in N: M, N -> MN is integer matrix multiplication;
+    the Boolean result is its support (counts > 0)."""
+    res = {0: 37, 1: 29, 2: 41}
+    for seed in range(3):
+        M = _rand((37, 29), 0.2, 700 + seed)
+        N = _rand((29, 41), 0.2, 750 + seed)
+        C = oracle.contract_count(M, (0, 1), N, (1, 2), (0, 2), res)
+        ref = M.astype(np.int64) @ N.astype(np.int64)
+        assert np.array_equal(C.astype(np.int64), ref)
+        assert np.array_equal(C > 0, oracle.contract(M, (0, 1), N, (1, 2), (0, 2), res).astype(bool))
+
+
+def test_count_associativity_and_saturation():
+    """Associativity in N (Thm 'associative' holds in any semiring): both
+    bracketings of a chain of three give the same counts; sums and products
+    saturate at 2^64 - 1 instead of wrapping."""
+    res = {0: 6, 1: 7, 2: 5, 3: 8}
+    A = _rand((6, 7), 0.4, 800).astype(np.uint64) * np.uint64(2)
+    B = _rand((7, 5), 0.4, 801).astype(np.uint64) * np.uint64(3)
+    C = _rand((5, 8), 0.4, 802).astype(np.uint64)
+    left = oracle.contract_count(oracle.contract_count(A, (0, 1), B, (1, 2), (0, 2), res), (0, 2), C, (2, 3), (0, 3), res)
+    right = oracle.contract_count(A, (0, 1), oracle.contract_count(B, (1, 2), C, (2, 3), (1, 3), res), (1, 3), (0, 3), res)
+    assert np.array_equal(left, right)
+    assert np.array_equal(left.astype(np.int64),
+                          A.astype(np.int64) @ B.astype(np.int64) @ C.astype(np.int64))
+    big = np.full((1, 2), 2 ** 63, dtype=np.uint64)
+    one = np.ones((2, 1), dtype=np.uint64)
+    s = oracle.contract_count(big, (0, 1), one, (1, 2), (0, 2), {0: 1, 1: 2, 2: 1})
+    assert s[0, 0] == np.uint64(2 ** 64 - 1)
+    m = oracle.contract_count(np.full((1, 1), 2 ** 40, dtype=np.uint64), (0, 1), np.full((1, 1), 2 ** 40, dtype=np.uint64),
+                              (1, 2), (0, 2), {0: 1, 1: 1, 2: 1})
+    assert m[0, 0] == np.uint64(2 ** 64 - 1)
