@@ -220,8 +220,8 @@ def contract_count(A: np.ndarray, a_vars: Sequence[int], B: np.ndarray, b_vars: 
     semiring N (uint64, saturating): the count-semiring GAM of two packs."""
     nv = max(list(a_vars) + list(b_vars) + list(out_vars) + [0]) + 1
     res = _i32([var_res.get(v, 1) for v in range(nv)])
-    A = np.ascontiguousarray(A, dtype=np.uint64)
-    B = np.ascontiguousarray(B, dtype=np.uint64)
+    A = np.asarray(A, dtype=np.uint64, order="C")      # keeps a 0-dim array 0-dim
+    B = np.asarray(B, dtype=np.uint64, order="C")
     assert A.shape == tuple(var_res[v] for v in a_vars)
     assert B.shape == tuple(var_res[v] for v in b_vars)
     C = np.empty(tuple(var_res[v] for v in out_vars), dtype=np.uint64)
