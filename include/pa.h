@@ -266,6 +266,22 @@ int pa_contract(const pa_bitarray *A, const int32_t *a_vars, const pa_bitarray *
 int pa_contract_noalloc(const pa_bitarray *A, const int32_t *a_vars, const pa_bitarray *B, const int32_t *b_vars,
                         const int32_t *out_vars, int32_t n_out, pa_bitarray *C, const pa_opts *opts, void *stream);
 
+/* Generalized array multiplication of two Boolean packs in the semiring N of
+ * natural numbers (the semiring footnote of Sec. 2.2; Notation, Ch. 3: the
+ * method works over any semiring): C(out_vars) = the number of entries of the
+ * variables of A or B not in out_vars at which A and B are both set -- the
+ * density of solutions per pixel instead of their existence.  A, B, a_vars,
+ * b_vars, out_vars as for pa_contract (B may be NULL: C counts A's set
+ * entries over the other variables).  C: device, caller-owned, uint32 per
+ * entry, row-major over out_vars with no padding (one entry for n_out = 0).
+ * Counts are exact: EUNSUPPORTED when the latent variables have 2^31 or more
+ * entries.  Canonical layouts (A = [batch][m][k], B = [batch][n][k],
+ * C = [batch][m][n], as for the MFMA path of pa_contract) run on int8 MFMA
+ * with 0/1 operands and int32 accumulation; others visit every latent entry
+ * per output entry.  EINVAL as for pa_contract. */
+int pa_contract_count(const pa_bitarray *A, const int32_t *a_vars, const pa_bitarray *B, const int32_t *b_vars,
+                      const int32_t *out_vars, int32_t n_out, uint32_t *C, const pa_opts *opts, void *stream);
+
 /* Plan a whole solve: choose the cluster tree (opts->order_policy), lay out
  * every intermediate, upload coefficient and axis tables and size the
  * workspace.  exposed lists the outer pack's variables in the output's axis

@@ -222,6 +222,13 @@ hipError_t launch_contract(const ContractArgs &a, int mode, hipStream_t s);
 // kernel into tab (2 * n int64).
 hipError_t launch_ktab(const ContractArgs &a, int mode, int64_t *tab, int64_t n, hipStream_t s);
 hipError_t launch_gemm(const GemmArgs &g, hipStream_t s);
+// Count semiring: C[b][m][n] = number of k with A[b][m][k] and B[b][n][k]
+// (canonical layout, 128 x 128 tiles; C dense uint32 with element
+// ((b M + m) No + no) rn + j; with a K split the parts add into a zeroed C).
+hipError_t launch_gemm_count(const GemmArgs &g, hipStream_t s);
+// Count semiring, any layouts: C[e] (dense uint32, row-major over the output
+// variables) = number of latent entries where A and B are both set.
+hipError_t launch_count_bits(const ContractArgs &a, int64_t n_elems, hipStream_t s);
 hipError_t launch_gather(const GatherArgs &g, hipStream_t s);
 hipError_t launch_count(const GatherArgs &g, hipStream_t s);
 hipError_t launch_fill(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);

@@ -1707,6 +1707,147 @@ hipError_t launch_gemm(const GemmArgs &g, hipStream_t s) {
     return hipGetLastError();
 }
 
+// ------------------------------------------------------- count semiring
+// Spread one 32-bit word of Boolean k-entries into an int8 MFMA operand with
+// every weight 1: byte p of dword j is bit (8p + 4h + j) of x as 0 or 1
+// (h = lane half; the same positions as spread(), unscaled), so the int32
+// sum over k is the number of k where both operands are set.
+__device__ __forceinline__ v4i spread_count(uint32_t x, int h) {
+    v4i r;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) r[j] = (int)((x >> (4 * h + j)) & 0x01010101u);
+    return r;
+}
+
+// 128 x 128 output tiles of the canonical GEMM in the count semiring: each
+// workgroup stages K chunks of its A and B rows in LDS (B rows permuted as in
+// gemm_tiles, so a lane's 16 accumulators are 16 consecutive output
+// columns) and each wave accumulates its 2 x 2 blocks of 32 x 32 counts;
+// counts are stored as uint32 (added atomically with a K split).
+__global__ __launch_bounds__(256) void k_gemm_count(GemmArgs g) {
+    __shared__ __attribute__((aligned(16))) uint32_t lds[2 * kTile * kPitch];
+    uint32_t *sA = lds, *sB = lds + kTile * kPitch;
+    const int tid = threadIdx.x, lane = tid & 63, h = lane >> 5, l32 = lane & 31;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wm = wave >> 1, wn = wave & 1;
+    const int lrow = tid >> 1, lw = (tid & 1) * 4;
+    const int brow = (lrow & ~31) | mfma_row_of_brow(lrow & 31);
+    const v16i zero = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    const int64_t ntiles = g.nbatch * g.tiles_m * g.tiles_n * g.ksplit;
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const GemmTileRef T = gemm_locate<2>(g, t);
+        v16i acc[2][2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) acc[i][j] = zero;
+        for (int32_t kc = T.kw0; kc < T.kw1; kc += kChunk) {
+            const uint4 a = load_row4(T.a, kc + lw, T.kw1, T.a_ok, T.vec4);
+            const uint4 b = load_row4(T.b, kc + lw, T.kw1, T.b_ok, T.vec4);
+            __syncthreads();                       // the previous chunk is consumed
+            *reinterpret_cast<uint4 *>(&sA[lrow * kPitch + lw]) = a;
+            *reinterpret_cast<uint4 *>(&sB[brow * kPitch + lw]) = b;
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < kChunk; ++q) {
+                v4i opa[2], opb[2];
+#pragma unroll
+                for (int i = 0; i < 2; ++i) {
+                    opa[i] = spread_count(sA[(wm * 64 + i * 32 + l32) * kPitch + q], h);
+                    opb[i] = spread_count(sB[(wn * 64 + i * 32 + l32) * kPitch + q], h);
+                }
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(opb[j], opa[i], acc[i][j], 0, 0, 0);
+            }
+        }
+        // lane (h, l32) of block (i, j): row m0 + wm 64 + 32 i + l32, columns
+        // n .. n + 15 with n = n0 + wn 64 + 32 j + 16 h (padded column space:
+        // column n is output (no, jj) with n = no Wc + jj, valid if jj < rn)
+        const uint32_t Wc = (uint32_t)(T.rwc * 32);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const uint32_t nb = (uint32_t)(T.n0 + wn * 64 + j * 32);
+            const uint32_t no = fdiv(nb, T.fd_wc);
+            if (no >= (uint32_t)T.No) continue;
+            const int32_t jj0 = (int32_t)(nb - no * Wc) + 16 * h;
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const int32_t m = T.m0 + wm * 64 + i * 32 + l32;
+                if (m >= T.M) continue;
+                PA_G uint32_t *dst = T.c + ((int64_t)m * T.No + no) * T.rn;
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int32_t jj = jj0 + r;
+                    if (jj < T.rn) {
+                        const uint32_t v = (uint32_t)acc[i][j][r];
+                        if (T.atomic) {
+                            if (v) __hip_atomic_fetch_add(dst + jj, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        } else {
+                            dst[jj] = v;
+                        }
+                    }
+                }
+            }
+        }
+    }
+}
+
+hipError_t launch_gemm_count(const GemmArgs &g, hipStream_t s) {
+    if (g.nbatch == 0 || g.M == 0 || g.No == 0) return hipSuccess;
+    const int64_t nt = g.nbatch * g.tiles_m * g.tiles_n * g.ksplit;
+    const int64_t blocks = nt < (1 << 20) ? nt : (1 << 20);
+    hipLaunchKernelGGL(k_gemm_count, dim3((unsigned)blocks), dim3(256), 0, s, g);
+    return hipGetLastError();
+}
+
+// Count semiring, any layouts: the number of latent entries where A and B
+// are both set (every latent entry visited, as bits_unit does).
+__device__ uint32_t count_unit(const ContractArgs &a, int64_t row, int64_t bit) {
+    const OutPos p = out_pos(a, row, bit);
+    int kidx[kMaxDim];
+    for (int j = 0; j < a.nk; ++j) kidx[j] = 0;
+    int64_t offA = 0, offB = 0;
+    uint32_t count = 0;
+    for (;;) {
+        const int64_t pa = (a.a_pk_k >= 0) ? kidx[a.a_pk_k] : p.pa;
+        const int64_t pb = (a.b_pk_k >= 0) ? kidx[a.b_pk_k] : p.pb;
+        const unsigned ba = (gp(a.A)[p.baseA + offA + (pa >> 5)] >> (pa & 31)) & 1u;
+        const unsigned bb = a.B ? ((gp(a.B)[p.baseB + offB + (pb >> 5)] >> (pb & 31)) & 1u) : 1u;
+        count += ba & bb;
+        int j = a.nk - 1;
+        for (; j >= 0; --j) {
+            ++kidx[j];
+            offA += a.ka_str[j];
+            offB += a.kb_str[j];
+            if (kidx[j] < a.k_dim[j]) break;
+            offA -= a.ka_str[j] * a.k_dim[j];
+            offB -= a.kb_str[j] * a.k_dim[j];
+            kidx[j] = 0;
+        }
+        if (j < 0) return count;
+    }
+}
+
+// One thread per output element e = row * L + bit (L = the last output
+// variable's length; one element for a 0-dim output).
+__global__ __launch_bounds__(256) void k_count_bits(ContractArgs a, int64_t n_elems) {
+    const int64_t L = a.nout > 0 ? a.out_dim[a.nout - 1] : 1;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n_elems;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t row = e / L, bit = e - row * L;
+        gp(a.C)[e] = count_unit(a, row, bit);
+    }
+}
+
+hipError_t launch_count_bits(const ContractArgs &a, int64_t n_elems, hipStream_t s) {
+    if (n_elems <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_count_bits, grid_for(n_elems), dim3(256), 0, s, a, n_elems);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------- sparse pass
 // Four words of a row of n words starting at word c (c and n even: pairs are
 // 8-byte aligned; with vec4 the row and c are 16-byte aligned).

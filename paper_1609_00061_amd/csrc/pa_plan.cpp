@@ -1809,13 +1809,43 @@ extern "C" int pa_popcount(const pa_bitarray *a, int64_t *count, void *stream) {
 // its variant that allocates nothing: the latent-entry table of a streamed
 // contraction is then written into `tab` by a kernel on the stream instead of
 // being copied from the host into a stream-ordered allocation.
-int pa::contract_impl(const pa_bitarray *A, const int32_t *a_vars, const pa_bitarray *B, const int32_t *b_vars,
-                      const int32_t *out_vars, int32_t n_out, pa_bitarray *C, const pa_opts *opts, void *stream,
-                      int64_t *tab_dev, int64_t tab_cap) {
-    if (!A || !C || (!a_vars && A->ndim > 0) || (n_out > 0 && !out_vars)) return fail(PA_EINVAL, "contract: null argument");
+// Is a two-pack contraction in the MFMA kernel's canonical layout, A =
+// [batch][m][k], B = [batch][n][k], C = [batch][m][n] (k the shared latent
+// variables, contiguous, with the packed one last in both; batch variables
+// shared and kept)?  nb and nm: the counts of batch and m variables.
+static bool canonical_gemm(const ContractLayouts &cl, int &nb, int &nm) {
+    const std::vector<int> &av = cl.av, &bv = cl.bv, &ov = cl.ov;
+    const uint64_t outm = cl.outm;
+    const uint64_t ma = list_mask(av), mb = list_mask(bv);
+    const uint64_t bm = ma & mb & outm, km = ma & mb & ~outm, em = ma & ~mb, en = mb & ~ma;
+    nb = __builtin_popcountll(bm);
+    nm = __builtin_popcountll(em);
+    const int nn = __builtin_popcountll(en), nk = __builtin_popcountll(km);
+    bool canon = km && em && en && ((em | en) & ~outm) == 0 && (int)av.size() == nb + nm + nk &&
+                 (int)bv.size() == nb + nn + nk && (int)ov.size() == nb + nm + nn;
+    if (canon) {
+        auto seg = [](const std::vector<int> &l, int a, int n) { return std::vector<int>(l.begin() + a, l.begin() + a + n); };
+        canon = list_mask(seg(av, 0, nb)) == bm && seg(av, 0, nb) == seg(bv, 0, nb) && seg(av, 0, nb) == seg(ov, 0, nb) &&
+                list_mask(seg(av, nb, nm)) == em && seg(av, nb, nm) == seg(ov, nb, nm) &&
+                list_mask(seg(bv, nb, nn)) == en && seg(bv, nb, nn) == seg(ov, nb + nm, nn) &&
+                list_mask(seg(av, nb + nm, nk)) == km && seg(av, nb + nm, nk) == seg(bv, nb + nn, nk);
+    }
+    return canon;
+}
+
+// Validation and layouts of a two-pack contraction's arguments (shared by
+// the Boolean and the count entry points): variable lengths from A and B,
+// A's and B's layouts checked against their arrays, C's layout from out_vars.
+int pa::contract_layouts(const pa_bitarray *A, const int32_t *a_vars, const pa_bitarray *B, const int32_t *b_vars,
+                         const int32_t *out_vars, int32_t n_out, bool has_c, ContractLayouts &cl) {
+    std::vector<int64_t> &res = cl.res;
+    std::vector<int> &av = cl.av, &bv = cl.bv, &ov = cl.ov;
+    uint64_t &outm = cl.outm;
+    Layout &la = cl.la, &lb = cl.lb, &lc = cl.lc;
+    if (!A || !has_c || (!a_vars && A->ndim > 0) || (n_out > 0 && !out_vars)) return fail(PA_EINVAL, "contract: null argument");
     if (A->ndim < 0 || A->ndim > PA_MAX_DIMS || n_out < 0 || n_out > PA_MAX_DIMS || (B && (B->ndim < 0 || B->ndim > PA_MAX_DIMS)))
         return fail(PA_EINVAL, "contract: rank out of range");
-    std::vector<int64_t> res(PA_MAX_VARS, -1);
+    res.assign(PA_MAX_VARS, -1);
     auto note = [&](const pa_bitarray *X, const int32_t *vs) -> int {
         uint64_t seen = 0;
         for (int i = 0; i < X->ndim; ++i) {
@@ -1835,8 +1865,8 @@ int pa::contract_impl(const pa_bitarray *A, const int32_t *a_vars, const pa_bita
         rc = note(B, b_vars);
         if (rc) return rc;
     }
-    uint64_t outm = 0;
-    std::vector<int> ov;
+    outm = 0;
+    ov.clear();
     for (int i = 0; i < n_out; ++i) {
         const int v = out_vars[i];
         if (v < 0 || v >= PA_MAX_VARS || res[v] < 0) return fail(PA_EINVAL, "contract: output variable not in A or B");
@@ -1844,33 +1874,38 @@ int pa::contract_impl(const pa_bitarray *A, const int32_t *a_vars, const pa_bita
         outm |= 1ull << v;
         ov.push_back(v);
     }
-    std::vector<int> av(a_vars, a_vars + A->ndim), bv;
+    av.assign(a_vars, a_vars + A->ndim);
+    bv.clear();
     if (B) bv.assign(b_vars, b_vars + B->ndim);
-    Layout la = make_layout(av, res), lb = B ? make_layout(bv, res) : Layout(), lc = make_layout(ov, res);
+    la = make_layout(av, res);
+    lb = B ? make_layout(bv, res) : Layout();
+    lc = make_layout(ov, res);
     rc = check_bitarray(A, la.dims, "contract: A");
     if (rc) return rc;
     if (B) {
         rc = check_bitarray(B, lb.dims, "contract: B");
         if (rc) return rc;
     }
+    return PA_OK;
+}
+
+int pa::contract_impl(const pa_bitarray *A, const int32_t *a_vars, const pa_bitarray *B, const int32_t *b_vars,
+                      const int32_t *out_vars, int32_t n_out, pa_bitarray *C, const pa_opts *opts, void *stream,
+                      int64_t *tab_dev, int64_t tab_cap) {
+    ContractLayouts cl;
+    int rc = contract_layouts(A, a_vars, B, b_vars, out_vars, n_out, C != nullptr, cl);
+    if (rc) return rc;
+    std::vector<int64_t> &res = cl.res;
+    std::vector<int> &av = cl.av, &bv = cl.bv, &ov = cl.ov;
+    const uint64_t outm = cl.outm;
+    const Layout &la = cl.la, &lb = cl.lb, &lc = cl.lc;
     rc = check_bitarray(C, lc.dims, "contract: C");
     if (rc) return rc;
     hipStream_t s = static_cast<hipStream_t>(stream);
     // canonical GEMM layout: A = [b][m][k], B = [b][n][k], C = [b][m][n]
     if (B) {
-        const uint64_t ma = list_mask(av), mb = list_mask(bv);
-        const uint64_t bm = ma & mb & outm, km = ma & mb & ~outm, em = ma & ~mb, en = mb & ~ma;
-        const int nb = __builtin_popcountll(bm), nm = __builtin_popcountll(em), nn = __builtin_popcountll(en),
-                  nk = __builtin_popcountll(km);
-        bool canon = km && em && en && ((em | en) & ~outm) == 0 && (int)av.size() == nb + nm + nk &&
-                     (int)bv.size() == nb + nn + nk && (int)ov.size() == nb + nm + nn;
-        if (canon) {
-            auto seg = [](const std::vector<int> &l, int a, int n) { return std::vector<int>(l.begin() + a, l.begin() + a + n); };
-            canon = list_mask(seg(av, 0, nb)) == bm && seg(av, 0, nb) == seg(bv, 0, nb) && seg(av, 0, nb) == seg(ov, 0, nb) &&
-                    list_mask(seg(av, nb, nm)) == em && seg(av, nb, nm) == seg(ov, nb, nm) &&
-                    list_mask(seg(bv, nb, nn)) == en && seg(bv, nb, nn) == seg(ov, nb + nm, nn) &&
-                    list_mask(seg(av, nb + nm, nk)) == km && seg(av, nb + nm, nk) == seg(bv, nb + nn, nk);
-        }
+        int nb = 0, nm = 0;
+        const bool canon = canonical_gemm(cl, nb, nm);
         if (canon) {
             pa_plan tmp;
             tmp.plain = opts ? opts->plain : 0;
@@ -1940,4 +1975,65 @@ int pa::contract_impl(const pa_bitarray *A, const int32_t *a_vars, const pa_bita
 extern "C" int pa_contract(const pa_bitarray *A, const int32_t *a_vars, const pa_bitarray *B, const int32_t *b_vars,
                            const int32_t *out_vars, int32_t n_out, pa_bitarray *C, const pa_opts *opts, void *stream) {
     return contract_impl(A, a_vars, B, b_vars, out_vars, n_out, C, opts, stream, nullptr, 0);
+}
+
+// ------------------------------------------------------ count semiring
+extern "C" int pa_contract_count(const pa_bitarray *A, const int32_t *a_vars, const pa_bitarray *B,
+                                 const int32_t *b_vars, const int32_t *out_vars, int32_t n_out, uint32_t *C,
+                                 const pa_opts *opts, void *stream) {
+    ContractLayouts cl;
+    int rc = contract_layouts(A, a_vars, B, b_vars, out_vars, n_out, C != nullptr, cl);
+    if (rc) return rc;
+    const Layout &la = cl.la, &lb = cl.lb, &lc = cl.lc;
+    // latent entries: the largest count (int32 accumulation in the kernels)
+    double nlat = 1.0;
+    const uint64_t all = list_mask(cl.av) | (B ? list_mask(cl.bv) : 0);
+    for (int v : mask_list(all & ~cl.outm)) nlat *= (double)cl.res[v];
+    if (nlat >= 2147483648.0) return fail(PA_EUNSUPPORTED, "contract_count: more than 2^31 - 1 latent entries");
+    int64_t n_elems = 1;
+    for (int64_t d : lc.dims) n_elems *= d;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int nb = 0, nm = 0;
+    if (B && canonical_gemm(cl, nb, nm)) {
+        pa_plan tmp;
+        tmp.si.res = cl.res;
+        tmp.si.n_vars = PA_MAX_VARS;
+        tmp.gemm_path = 0;
+        Builder Bd{&tmp, nullptr};
+        Bd.emit_gemm(0, la, 1, lb, kBufOutput, lc, nb, nm, -1);
+        GemmArgs g = tmp.ops.back().ga;
+        rc = check_gemm_bounds(g, la.words, lb.words, lc.words);
+        if (rc) return rc;
+        // counts: C[b][m][n] dense, n = (no, j) with j < rn
+        g.sC_b = g.M * g.No * g.rn;
+        g.path = 0;
+        g.tiles_m = (g.M + 127) / 128;
+        g.fd_tiles_m = make_fastdiv((uint64_t)std::max<int64_t>(1, g.tiles_m));
+        // split K until the launch has about 512 work items (parts add into a
+        // zeroed output)
+        const int64_t tiles = g.nbatch * g.tiles_m * g.tiles_n;
+        set_ksplit(g, std::max<int64_t>(1, 512 / std::max<int64_t>(1, tiles)));
+        if (tiles * g.ksplit >= ((int64_t)1 << 31) || g.M * g.No * g.rn >= ((int64_t)1 << 40))
+            return fail(PA_EUNSUPPORTED, "contract_count: too many tiles");
+        g.A = static_cast<const uint32_t *>(A->data);
+        g.B = static_cast<const uint32_t *>(B->data);
+        g.C = C;
+        if (g.ksplit > 1) HIP_TRY(launch_fill(C, n_elems, 0u, s));
+        HIP_TRY(launch_gemm_count(g, s));
+        return PA_OK;
+    }
+    Op op;
+    op.la = la;
+    op.lb = lb;
+    op.lc = lc;
+    op.kvars = mask_list(all & ~cl.outm);
+    finish_contract(op, B != nullptr);
+    rc = check_contract_bounds(op.ca, la.words, B ? lb.words : 0, lc.words, B != nullptr);
+    if (rc) return rc;
+    op.ca.A = static_cast<const uint32_t *>(A->data);
+    op.ca.B = B ? static_cast<const uint32_t *>(B->data) : nullptr;
+    op.ca.C = C;
+    HIP_TRY(launch_count_bits(op.ca, n_elems, s));
+    (void)opts;
+    return PA_OK;
 }

@@ -126,6 +126,14 @@ int time_groups(pa_plan *P, int32_t reps, double *ms, int32_t *kind, double *mac
 int autotuned_opts(const pa_system *systems, int32_t n_sys, const int32_t *const *exposed, const int32_t *n_exposed,
                    pa_opts &o);
 void make_groups(pa_plan *P);
+struct ContractLayouts {
+    std::vector<int64_t> res;          // length per variable label (-1: unused)
+    std::vector<int> av, bv, ov;       // variables of A, B and the output
+    uint64_t outm = 0;                 // output variables as a mask
+    Layout la, lb, lc;
+};
+int contract_layouts(const pa_bitarray *A, const int32_t *a_vars, const pa_bitarray *B, const int32_t *b_vars,
+                     const int32_t *out_vars, int32_t n_out, bool has_c, ContractLayouts &cl);
 int contract_impl(const pa_bitarray *A, const int32_t *a_vars, const pa_bitarray *B, const int32_t *b_vars,
                   const int32_t *out_vars, int32_t n_out, pa_bitarray *C, const pa_opts *opts, void *stream,
                   int64_t *tab_dev, int64_t tab_cap);

@@ -112,6 +112,8 @@ def load(path: str = LIB_PATH):
     L.pa_contract.argtypes = [ctypes.POINTER(BitArray), i32p, ctypes.POINTER(BitArray), i32p, i32p, ctypes.c_int32,
                               ctypes.POINTER(BitArray), ctypes.POINTER(Opts), vp]
     L.pa_contract_noalloc.argtypes = L.pa_contract.argtypes
+    L.pa_contract_count.argtypes = [ctypes.POINTER(BitArray), i32p, ctypes.POINTER(BitArray), i32p, i32p,
+                                    ctypes.c_int32, vp, ctypes.POINTER(Opts), vp]
     L.pa_plan_create.argtypes = [ctypes.POINTER(System), i32p, ctypes.c_int32, ctypes.POINTER(Opts),
                                  ctypes.POINTER(vp)]
     L.pa_plan_execute.argtypes = [vp, ctypes.POINTER(BitArray), ctypes.POINTER(Report), vp]
@@ -334,6 +336,26 @@ def contract(A, a_dims, a_vars, B, b_dims, b_vars, out_vars, out_dims, stream=No
     _check(fn(ctypes.byref(ba), keep.i32(a_vars), ctypes.byref(bb) if bb is not None else None,
               keep.i32(b_vars if B is not None else []), keep.i32(out_vars), len(out_vars),
               ctypes.byref(bc), ctypes.byref(opts), _stream_ptr(stream)))
+    return C
+
+
+def contract_count(A, a_dims, a_vars, B, b_dims, b_vars, out_vars, out_dims, stream=None):
+    """Counts (count semiring): C(out_vars) = number of entries of the other
+    variables where A and B are both set (B may be None).  Returns a device
+    int32 tensor holding the uint32 counts, row-major over out_dims."""
+    import torch
+    L = load()
+    keep = _Keep()
+    n = 1
+    for d in out_dims:
+        n *= int(d)
+    C = torch.zeros(max(1, n), dtype=torch.int32, device="cuda")
+    ba = bitarray(A, a_dims)
+    bb = bitarray(B, b_dims) if B is not None else None
+    opts = make_opts()
+    _check(L.pa_contract_count(ctypes.byref(ba), keep.i32(a_vars), ctypes.byref(bb) if bb is not None else None,
+                               keep.i32(b_vars if B is not None else []), keep.i32(out_vars), len(out_vars),
+                               ctypes.c_void_p(C.data_ptr()), ctypes.byref(opts), _stream_ptr(stream)))
     return C
 
 

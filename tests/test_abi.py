@@ -273,3 +273,20 @@ def test_workspace_bytes_is_host_planning():
     s.axes = [(-2.0, 2.0, 1)] + s.axes[1:]
     with pytest.raises(pa.PaError):
         pa.workspace_bytes(s)
+
+
+def test_count_contraction_rejects_inexact_counts():
+    """pa_contract_count refuses latent variables with 2^31 or more entries
+    (its int32 accumulators would not be exact), before touching the device."""
+    import ctypes
+    L = pa.load()
+    a = pa.BitArray()
+    a.data = ctypes.c_void_p(0x1000)
+    a.ndim = 3
+    for i, d in enumerate((4, 65536, 65536)):
+        a.dims[i] = d
+    a.row_words = pa.row_words(65536)
+    av = (ctypes.c_int32 * 3)(0, 1, 2)
+    ov = (ctypes.c_int32 * 1)(0)
+    rc = L.pa_contract_count(ctypes.byref(a), av, None, None, ov, 1, ctypes.c_void_p(0x2000), None, None)
+    assert rc == pa.PA_EUNSUPPORTED
