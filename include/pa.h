@@ -209,7 +209,12 @@ typedef struct {
                                  the plain path or a single persistent launch.    */
     int32_t sparse_max_density; /* 0..1024 set bits per 1024 bits of A (0: 64)     */
     int32_t plot_rule;        /* PA_RULE_* (0: corners)                           */
-    int32_t reserved0;
+    int32_t measure_density;  /* 1: plan creation plots every relation once on the
+                                 device and counts its set cells; the learned
+                                 order's density features (and those of
+                                 pa_plan_step_samples) then start from these
+                                 measured plot densities instead of an
+                                 analytic estimate                               */
     double tolerance;         /* PA_RULE_CENTER: eps >= 0, finite                  */
 } pa_opts;
 
@@ -299,7 +304,8 @@ int pa_plan_execute(pa_plan *plan, pa_bitarray *out, pa_report *report, void *st
 size_t pa_plan_workspace_bytes(const pa_plan *plan);
 /* JSON description of the plan (steps, kernels, layouts, costs) into buf;
  * returns the length needed (excluding the NUL). Host-only except under
- * PA_ORDER_LEARNED, whose model inference runs on the model's device. */
+ * PA_ORDER_LEARNED, whose model inference runs on the model's device, and
+ * with opts->measure_density, whose plots run on the current device. */
 int64_t pa_plan_describe(const pa_system *sys, const int32_t *exposed, int32_t n_exposed, const pa_opts *opts,
                          char *buf, int64_t buf_len);
 void pa_plan_destroy(pa_plan *plan);
@@ -424,7 +430,13 @@ int pa_model_load(const char *path, pa_model **model);
  * the batch, M, N and shared latent groups, of the scope, output and
  * operands; the path flags (MFMA-eligible, streaming over a shared latent
  * variable, no shared latent variable); scope and output arity / 4; and
- * estimated log2 densities / 8 of both operands and the output.  Host-only. */
+ * estimated log2 densities / 8 of both operands and the output: analytic
+ * (n generic equations in V unknowns leave a set of dimension V - n; each
+ * dimension its projection lacks thins the array by about r/2), or, when the
+ * plan measured its plots (opts->measure_density), from the measured plot
+ * densities taken as independent: log2 d(S) = min(0, sum of the plots' log2
+ * densities + sum of log2 r over the cluster's variables outside its pack).
+ * Host-only (analytic densities). */
 int pa_step_features(const pa_system *sys, const int32_t *exposed, int32_t n_exposed, uint32_t s1, uint32_t s2,
                      float *features);
 /* Training samples from the last execute of a plan created with per_op = 1
@@ -477,7 +489,8 @@ int pa_solve_system(const pa_system *sys, const int32_t *exposed, int32_t n_expo
  * this system and opts (intermediates, tables, executor state: 256-byte
  * aligned), computed by planning on the host without creating a plan or
  * allocating device memory (PA_ORDER_LEARNED runs the model's inference on its
- * device).  opts->autotune and opts->verify_order are not applied: the figure
+ * device).  opts->autotune, opts->verify_order and opts->measure_density are
+ * not applied (the learned order then uses analytic densities): the figure
  * is for the given executor settings and order policy (pass pa_autotune's
  * settings to size an autotuned plan).  Returns 0 on invalid input (EINVAL /
  * ENOMEM cases of pa_plan_create; message in pa_last_error). */
@@ -485,6 +498,14 @@ size_t pa_workspace_bytes(const pa_system *sys, const int32_t *exposed, int32_t 
 
 /* Number of set bits of a device bit array (padding is zero by contract). */
 int pa_popcount(const pa_bitarray *a, int64_t *count, void *stream);
+
+/* Set bits per tile of a device bit array (its density map): the array's
+ * rows (every axis but the last) are cut into blocks of tile_rows rows and
+ * its row words into blocks of tile_words words; counts (device, caller-owned,
+ * uint32) receives ceil(rows / tile_rows) x ceil(row_words / tile_words)
+ * counts, row-major (block of rows outer).  A 0-dim array is one row of one
+ * word.  EINVAL: tile sizes < 1, or tile_rows * tile_words * 32 >= 2^32. */
+int pa_tile_popcount(const pa_bitarray *a, int32_t tile_rows, int32_t tile_words, uint32_t *counts, void *stream);
 
 /* Thread-local message describing the last error. */
 const char *pa_last_error(void);

@@ -6,7 +6,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
+#include <limits>
 #include <memory>
 #include <string>
 #include <tuple>
@@ -70,6 +72,102 @@ static int merge_steps(pa_batch *B) {
     return PA_OK;
 }
 
+int measure_leaf_densities(const pa_system *systems, int32_t n_sys, const pa_opts &o,
+                           std::vector<std::vector<double>> &ld) {
+    ld.assign(n_sys, {});
+    struct One {
+        std::vector<int32_t> vars;
+        std::vector<pa_axis> axes;
+        pa_relation rel;
+        std::vector<int64_t> dims;
+        int sys, r;
+    };
+    std::vector<One> ones;
+    for (int32_t i = 0; i < n_sys; ++i) {
+        const pa_system &S = systems[i];
+        if (!S.rel || !S.axes || S.n_rel < 1 || S.n_rel > PA_MAX_RELATIONS || S.n_vars < 1) continue;
+        bool ok = true;
+        for (int r = 0; r < S.n_rel && ok; ++r) {
+            const pa_relation &R = S.rel[r];
+            if (R.arity < 1 || R.arity > PA_MAX_ARITY || !R.vars) { ok = false; break; }
+            std::vector<pa_axis> ax;
+            for (int j = 0; j < R.arity; ++j) {
+                if (R.vars[j] < 0 || R.vars[j] >= S.n_vars) { ok = false; break; }
+                ax.push_back(S.axes[R.vars[j]]);
+            }
+            ok = ok && validate_relation(R, ax.data(), -1, "density probe") == PA_OK;
+        }
+        if (!ok) {
+            g_err.clear();
+            continue;
+        }
+        ld[i].assign(S.n_rel, 0.0);
+        for (int r = 0; r < S.n_rel; ++r) {
+            One one;
+            const pa_relation &R = S.rel[r];
+            one.sys = i;
+            one.r = r;
+            for (int j = 0; j < R.arity; ++j) {
+                one.vars.push_back(j);
+                one.axes.push_back(S.axes[R.vars[j]]);
+                one.dims.push_back(S.axes[R.vars[j]].res);
+            }
+            one.rel = R;
+            ones.push_back(std::move(one));
+        }
+    }
+    if (ones.empty()) return PA_OK;
+    // one single-relation system per plot, every variable exposed: the plot itself
+    const size_t n = ones.size();
+    std::vector<pa_system> subs(n);
+    std::vector<const int32_t *> exp(n);
+    std::vector<int32_t> n_exp(n);
+    std::vector<int64_t> off(n);
+    int64_t words = 0;
+    for (size_t k = 0; k < n; ++k) {
+        One &one = ones[k];
+        one.rel.vars = one.vars.data();
+        subs[k] = {one.rel.arity, one.axes.data(), 1, &one.rel};
+        exp[k] = one.vars.data();
+        n_exp[k] = one.rel.arity;
+        off[k] = words;
+        std::vector<int32_t> d32(one.dims.begin(), one.dims.end());
+        words += pa_array_words(one.rel.arity, d32.data());
+    }
+    pa_opts po{};
+    po.precision = o.precision;
+    po.plot_rule = o.plot_rule;
+    po.tolerance = o.tolerance;
+    pa_batch *B = nullptr;
+    int rc = pa_batch_create(subs.data(), (int32_t)n, exp.data(), n_exp.data(), &po, &B);
+    if (rc) return rc;
+    void *buf = nullptr;
+    if (hipMalloc(&buf, sizeof(uint32_t) * (size_t)std::max<int64_t>(1, words)) != hipSuccess) {
+        pa_batch_destroy(B);
+        return fail(PA_ENOMEM, "density probe: output allocation failed");
+    }
+    std::vector<pa_bitarray> outs(n);
+    for (size_t k = 0; k < n; ++k) {
+        std::memset(&outs[k], 0, sizeof(pa_bitarray));
+        outs[k].data = static_cast<uint32_t *>(buf) + off[k];
+        outs[k].ndim = ones[k].rel.arity;
+        for (int j = 0; j < outs[k].ndim; ++j) outs[k].dims[j] = (int32_t)ones[k].dims[j];
+        outs[k].row_words = pa_row_words(outs[k].dims[outs[k].ndim - 1]);
+    }
+    std::vector<pa_report> reps(n);
+    rc = pa_batch_execute(B, outs.data(), nullptr, reps.data(), nullptr);
+    pa_batch_destroy(B);
+    (void)hipFree(buf);
+    if (rc) return rc;
+    for (size_t k = 0; k < n; ++k) {
+        double cells = 1.0;
+        for (int64_t d : ones[k].dims) cells *= (double)d;
+        const double nnz = (double)reps[k].nnz_out;
+        ld[ones[k].sys][ones[k].r] = nnz > 0.0 ? std::log2(nnz / cells) : -std::numeric_limits<double>::infinity();
+    }
+    return PA_OK;
+}
+
 }  // namespace pa
 
 using namespace pa;
@@ -87,10 +185,16 @@ extern "C" int pa_batch_create(const pa_system *systems, int32_t n_sys, const in
         if (rc) return rc;
     }
     if (o.timing == 2) o.timing = 0;       // op events live on the merged plan, below
+    std::vector<std::vector<double>> dens;
+    if (o.measure_density) {
+        int rc = measure_leaf_densities(systems, n_sys, o, dens);
+        if (rc) return rc;
+    }
     std::unique_ptr<pa_batch> B(new pa_batch());
     size_t off = 0;
     for (int32_t i = 0; i < n_sys; ++i) {
         std::unique_ptr<pa_plan> P(new pa_plan());
+        if (o.measure_density) P->leaf_log2d = dens[i];
         int rc = build_plan(&systems[i], exposed[i], n_exposed[i], &o, P.get());
         if (rc) {
             g_err = "system " + std::to_string(i) + ": " + g_err;

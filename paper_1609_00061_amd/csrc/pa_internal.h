@@ -233,6 +233,8 @@ hipError_t launch_gather(const GatherArgs &g, hipStream_t s);
 hipError_t launch_count(const GatherArgs &g, hipStream_t s);
 hipError_t launch_fill(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
 hipError_t launch_popcount(const uint32_t *p, int64_t n, unsigned long long *out, hipStream_t s);
+hipError_t launch_tile_popcount(const uint32_t *p, int64_t rows, int64_t rw, int tile_rows, int tile_words,
+                                uint32_t *out, hipStream_t s);
 hipError_t launch_persist(const PStep *d_steps, int nsteps, int64_t n_items, PersistState *state,
                           unsigned int *done, PlotCounters *counters, int n_workgroups, hipStream_t s);
 hipError_t launch_persist_reset(PersistState *state, unsigned int *done, int nsteps, hipStream_t s);

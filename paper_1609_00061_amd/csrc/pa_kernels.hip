@@ -2100,6 +2100,40 @@ __global__ void k_popcount(const uint32_t *p, int64_t n, unsigned long long *out
     if (threadIdx.x == 0) atomicAdd(out, part[0] + part[1] + part[2] + part[3]);
 }
 
+// Set bits per tile (tile_rows rows x tile_words words of a rows x rw word
+// array): one workgroup per tile, grid-stride over tiles, a block reduction.
+__global__ __launch_bounds__(256) void k_tile_popcount(const uint32_t *p, int64_t rows, int64_t rw, int tile_rows,
+                                                       int tile_words, int64_t tiles_r, int64_t tiles_w,
+                                                       uint32_t *out) {
+    __shared__ uint32_t part[4];
+    const int64_t ntiles = tiles_r * tiles_w;
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int64_t tr = t / tiles_w, tw = t - tr * tiles_w;
+        const int64_t r0 = tr * tile_rows, w0 = tw * tile_words;
+        const int64_t nr = min((int64_t)tile_rows, rows - r0), nw = min((int64_t)tile_words, rw - w0);
+        uint32_t c = 0;
+        for (int64_t i = threadIdx.x; i < nr * nw; i += blockDim.x) {
+            const int64_t rr = i / nw, ww = i - rr * nw;
+            c += __popc(p[(r0 + rr) * rw + w0 + ww]);
+        }
+        for (int off = 32; off > 0; off >>= 1) c += __shfl_down(c, off);
+        if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = c;
+        __syncthreads();
+        if (threadIdx.x == 0) out[t] = part[0] + part[1] + part[2] + part[3];
+        __syncthreads();
+    }
+}
+
+hipError_t launch_tile_popcount(const uint32_t *p, int64_t rows, int64_t rw, int tile_rows, int tile_words,
+                                uint32_t *out, hipStream_t s) {
+    const int64_t tiles_r = (rows + tile_rows - 1) / tile_rows, tiles_w = (rw + tile_words - 1) / tile_words;
+    const int64_t nt = tiles_r * tiles_w;
+    if (nt <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tile_popcount, dim3((unsigned)(nt < (1 << 20) ? nt : (1 << 20))), dim3(256), 0, s, p, rows,
+                       rw, tile_rows, tile_words, tiles_r, tiles_w, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_popcount(const uint32_t *p, int64_t n, unsigned long long *out, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     int64_t blocks = (n + 255) / 256;

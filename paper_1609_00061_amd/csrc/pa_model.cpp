@@ -53,17 +53,31 @@ static double log2_cost(uint64_t m, const std::vector<double> &lr) {
     return s;
 }
 
-// Estimated log2 density of a cluster's array: n generic equations in V
-// unknowns leave a solution set of dimension V - n, whose projection onto
-// the pack Q has dimension min(|Q|, V - n); each missing dimension thins the
-// array by about one cell in r/2 along that axis.
-static double est_log2_density(int n_rel, int n_vars, uint64_t q, double lq) {
+// Estimated log2 density of a cluster's array over its pack q.
+// Analytic (no measurement): n generic equations in V unknowns leave a
+// solution set of dimension V - n, whose projection onto q has dimension
+// min(|q|, V - n); each missing dimension thins the array by about one cell
+// in r/2 along that axis.  Measured (opts->measure_density): the plots of the
+// cluster's relations taken as independent, so the joint array over the
+// cluster's variables has density prod d_r (d_r the measured density of
+// relation r's plot), and projecting out the variables outside q leaves
+// prod d_r * prod r_v witnesses per cell of q on average (capped at 1);
+// empty plots count as 2^-60.
+constexpr double kLog2DensityFloor = -60.0;
+
+static double est_log2_density(const SysInfo &si, uint32_t S, uint64_t vars, uint64_t q, const std::vector<double> &lr) {
     const int nq = __builtin_popcountll(q);
-    if (nq == 0) return 0.0;
-    const int dim = std::min(nq, std::max(0, n_vars - n_rel));
-    const int codim = nq - dim;
-    const double lr_mean = lq / nq;
-    return -codim * std::max(0.0, lr_mean - 1.0);
+    if (si.leaf_log2d.empty()) {
+        if (nq == 0) return 0.0;
+        const int dim = std::min(nq, std::max(0, __builtin_popcountll(vars) - __builtin_popcount(S)));
+        const int codim = nq - dim;
+        const double lr_mean = log2_cost(q, lr) / nq;
+        return -codim * std::max(0.0, lr_mean - 1.0);
+    }
+    double d = 0.0;
+    for (uint32_t t = S; t; t &= t - 1) d += std::max(kLog2DensityFloor, si.leaf_log2d[__builtin_ctz(t)]);
+    for (uint64_t m = vars & ~q; m; m &= m - 1) d += lr[__builtin_ctzll(m)];
+    return std::max(kLog2DensityFloor, std::min(0.0, d));
 }
 
 struct FeatureCtx {
@@ -107,9 +121,7 @@ static uint64_t vars_of(uint32_t S, const SysInfo &si) {
 void step_features(const SysInfo &si, uint32_t s1, uint32_t s2, float *f) {
     const FeatureCtx ctx(si);
     const uint64_t qx = q_of(s1, si), qy = q_of(s2, si), q = q_of(s1 | s2, si);
-    auto dens = [&](uint32_t S, uint64_t qq) {
-        return est_log2_density(popc32(S), __builtin_popcountll(vars_of(S, si)), qq, log2_cost(qq, ctx.lr));
-    };
+    auto dens = [&](uint32_t S, uint64_t qq) { return est_log2_density(si, S, vars_of(S, si), qq, ctx.lr); };
     ctx.compute(qx, qy, q, dens(s1, qx), dens(s2, qy), dens(s1 | s2, q), f);
 }
 
@@ -204,7 +216,7 @@ int plan_learned(const SysInfo &si, const pa_model *model, Tree &t) {
         vars[S] = vars[S ^ low] | si.rel_vars[__builtin_ctz(low)];
         q[S] = q_of(S, si);
         lq[S] = log2_cost(q[S], ctx.lr);
-        dens[S] = est_log2_density(popc32(S), __builtin_popcountll(vars[S]), q[S], lq[S]);
+        dens[S] = est_log2_density(si, S, vars[S], q[S], ctx.lr);
         // connected: grow from the lowest relation through shared variables
         uint32_t seen = low;
         uint64_t sv = si.rel_vars[__builtin_ctz(low)];

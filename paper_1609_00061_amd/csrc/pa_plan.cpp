@@ -779,6 +779,7 @@ int build_plan(const pa_system *sys, const int32_t *exposed, int32_t n_exposed, 
     auto t0 = std::chrono::steady_clock::now();
     int rc = build_sysinfo(sys, exposed, n_exposed, P->si);
     if (rc) return rc;
+    if ((int)P->leaf_log2d.size() == P->si.n_rel) P->si.leaf_log2d = P->leaf_log2d;
     for (int r = 0; r < sys->n_rel; ++r) {
         std::vector<pa_axis> ax;
         for (int i = 0; i < sys->rel[r].arity; ++i) ax.push_back(sys->axes[sys->rel[r].vars[i]]);
@@ -1492,6 +1493,12 @@ extern "C" int pa_plan_create(const pa_system *sys, const int32_t *exposed, int3
             verified_fallback = true;
         }
     }
+    if (opts && opts->measure_density && sys) {
+        std::vector<std::vector<double>> dens;
+        int rc = measure_leaf_densities(sys, 1, *opts, dens);
+        if (rc) return rc;
+        P->leaf_log2d = dens[0];
+    }
     int rc = build_plan(sys, exposed, n_exposed, opts, P.get());
     if (rc) return rc;
     if (verified_fallback) P->tree.learned_fallback = true;
@@ -1719,7 +1726,13 @@ extern "C" size_t pa_workspace_bytes(const pa_system *sys, const int32_t *expose
 extern "C" int64_t pa_plan_describe(const pa_system *sys, const int32_t *exposed, int32_t n_exposed,
                                     const pa_opts *opts, char *buf, int64_t buf_len) {
     std::unique_ptr<pa_plan> P(new pa_plan());
-    int rc = build_plan(sys, exposed, n_exposed, opts, P.get());
+    int rc = PA_OK;
+    if (opts && opts->measure_density && sys) {
+        std::vector<std::vector<double>> dens;
+        rc = measure_leaf_densities(sys, 1, *opts, dens);
+        if (rc == PA_OK) P->leaf_log2d = dens[0];
+    }
+    if (rc == PA_OK) rc = build_plan(sys, exposed, n_exposed, opts, P.get());
     std::ostringstream s;
     s.precision(17);
     if (rc) {
@@ -1729,6 +1742,14 @@ extern "C" int64_t pa_plan_describe(const pa_system *sys, const int32_t *exposed
           << ",\"cost\":" << P->tree.cost << ",\"workspace_bytes\":" << P->ws_bytes << ",\"corners\":" << P->corners
           << ",\"total_macs\":" << P->total_macs << ",\"predicted_us\":" << P->tree.predicted_us
           << ",\"learned_fallback\":" << (P->tree.learned_fallback ? "true" : "false")
+          << ",\"leaf_log2_density\":[";
+        for (size_t i = 0; i < P->si.leaf_log2d.size(); ++i) {
+            const double v = P->si.leaf_log2d[i];
+            s << (i ? "," : "");
+            if (std::isfinite(v)) s << v;
+            else s << "null";
+        }
+        s << "]"
           << ",\"plots\":[";
         for (size_t i = 0; i < P->plots.size(); ++i)
             s << (i ? "," : "") << "{\"rel\":" << P->plots[i].rel << ",\"buf\":" << P->plots[i].buf
@@ -1801,6 +1822,23 @@ extern "C" int pa_popcount(const pa_bitarray *a, int64_t *count, void *stream) {
     HIP_TRY(hipMemcpyAsync(&c, S.ws.ptr, sizeof(c), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     *count = (int64_t)c;
+    return PA_OK;
+}
+
+extern "C" int pa_tile_popcount(const pa_bitarray *a, int32_t tile_rows, int32_t tile_words, uint32_t *counts,
+                                void *stream) {
+    if (!a || !counts || !a->data || a->ndim < 0 || a->ndim > PA_MAX_DIMS) return fail(PA_EINVAL, "tile_popcount: bad args");
+    if (tile_rows < 1 || tile_words < 1 || (double)tile_rows * tile_words * 32.0 >= 4294967296.0)
+        return fail(PA_EINVAL, "tile_popcount: tile sizes must be >= 1 with fewer than 2^32 bits per tile");
+    int64_t rows = 1;
+    for (int i = 0; i + 1 < a->ndim; ++i) {
+        if (a->dims[i] < 1) return fail(PA_EINVAL, "tile_popcount: dims must be >= 1");
+        rows *= a->dims[i];
+    }
+    const int64_t rw = a->ndim == 0 ? 1 : pa_row_words(a->dims[a->ndim - 1]);
+    if (a->ndim > 0 && a->row_words != rw) return fail(PA_EINVAL, "tile_popcount: row_words must be 2*ceil(d/64)");
+    HIP_TRY(launch_tile_popcount(static_cast<const uint32_t *>(a->data), rows, rw, tile_rows, tile_words, counts,
+                                 static_cast<hipStream_t>(stream)));
     return PA_OK;
 }
 

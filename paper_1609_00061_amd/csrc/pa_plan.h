@@ -69,6 +69,9 @@ struct SysInfo {
     std::vector<std::vector<int>> rel_list;   // declared order per relation
     uint64_t exposed = 0;
     std::vector<int> exposed_list;
+    // measured log2 density of each relation's plot (set cells / cells;
+    // empty: not measured, the features then use an analytic estimate)
+    std::vector<double> leaf_log2d;
 };
 
 int build_sysinfo(const pa_system *sys, const int32_t *exposed, int32_t n_exposed, SysInfo &si);
@@ -122,6 +125,12 @@ int build_plan(const pa_system *sys, const int32_t *exposed, int32_t n_exposed, 
 int upload_plan(pa_plan *P);
 int exec_steps(pa_plan *P, const std::vector<void *> &outs, hipStream_t s, int *launches);
 int plan_workspace_cap(size_t *cap);
+// The log2 density of every relation's plot, per system, measured on the
+// current device (all relations of all systems plotted in one batch, their
+// set cells counted; synchronizes).  A system with an invalid relation gets
+// an empty list (planning reports the error).
+int measure_leaf_densities(const pa_system *systems, int32_t n_sys, const pa_opts &o,
+                           std::vector<std::vector<double>> &ld);
 int time_groups(pa_plan *P, int32_t reps, double *ms, int32_t *kind, double *macs, int32_t cap, hipStream_t s);
 int autotuned_opts(const pa_system *systems, int32_t n_sys, const int32_t *const *exposed, const int32_t *n_exposed,
                    pa_opts &o);
@@ -175,6 +184,7 @@ struct pa_plan {
     double total_macs = 0.0;
     std::vector<unsigned char> tables_host;   // uploaded once
     pa::Workspace ws;
+    std::vector<double> leaf_log2d;            // measured plot densities to plan with (opts->measure_density)
     pa::PlotCounters *counters_dev = nullptr;   // set by a batch: the system's counters in the batch's
                                                 // table (else the plan's own, at counters_off)
     int precision = PA_PLOT_FP32_ESCALATE;

@@ -75,6 +75,7 @@ static std::string signature(const pa_system *systems, int32_t n_sys, const int3
         uint64_t tol;
         std::memcpy(&tol, &o.tolerance, sizeof(tol));
         fnv(h, (uint64_t)o.plot_rule);
+        fnv(h, (uint64_t)o.measure_density);
         fnv(h, tol);
         for (int32_t i = 0; i < n_sys; ++i)
             for (int r = 0; r < systems[i].n_rel; ++r) fnv(h, (uint64_t)systems[i].rel[r].target);

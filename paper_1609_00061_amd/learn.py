@@ -52,14 +52,16 @@ def _feasible(system, merges, max_out_log2=33.0) -> bool:
 
 
 def collect_samples(systems: Sequence, n_random: int = 3, reps: int = 3, seed: int = 1, stream=None,
-                    log=None, model=None, base_policies: bool = True, max_cost_ratio: float = 128.0):
+                    log=None, model=None, base_policies: bool = True, max_cost_ratio: float = 128.0,
+                    measure_density: bool = False):
     """(X [k, F] float32, T [k] float32 log2 microseconds) from timed plans.
     Trees: greedy and exhaustive (base_policies), n_random random connected
     merge orders, and the learned order of `model` when given; a tree whose
     naive cost exceeds max_cost_ratio times the optimum is not timed (one
     such solve can take seconds; slow trees within the ratio stay, so the
     model sees the slow regime it must avoid).  Each tree is executed `reps` times after one warm-up; a step's
-    sample is its fastest repetition."""
+    sample is its fastest repetition.  With measure_density the plans measure their plots' densities and
+    the samples' density features start from them (as the learned order then does)."""
     rng = inputs.SplitMix64(seed)
     Xs, Ts = [], []
     for si, s in enumerate(systems):
@@ -74,6 +76,8 @@ def collect_samples(systems: Sequence, n_random: int = 3, reps: int = 3, seed: i
                 trees.append(dict(order=pa.ORDER_GIVEN, given=m))
         best_cost = pa.describe_plan(s, order=pa.ORDER_EXHAUSTIVE).get("cost")
         kept = []
+        if model is not None and measure_density:
+            trees[-1] = dict(trees[-1], measure_density=True)
         for kw in trees:
             d = pa.describe_plan(s, **kw)
             if "error" in d or (best_cost and d["cost"] > max_cost_ratio * best_cost):
@@ -81,7 +85,7 @@ def collect_samples(systems: Sequence, n_random: int = 3, reps: int = 3, seed: i
             kept.append(kw)
         for kw in kept:
             try:
-                plan = pa.Plan(s, per_op=True, timing=2, **kw)
+                plan = pa.Plan(s, per_op=True, timing=2, **dict(kw, measure_density=measure_density))
             except pa.PaError as e:          # a tree whose intermediates exceed the workspace cap
                 if e.code == pa.PA_ENOMEM:
                     continue
@@ -131,17 +135,18 @@ def train(model: "pa.Model", X: np.ndarray, T: np.ndarray, steps: int = 3000, lr
 
 
 def train_order_model(systems: Sequence, rounds: int = 2, n_random: int = 3, reps: int = 2, steps: int = 3000,
-                      seed: int = 1, stream=None, log=None):
+                      seed: int = 1, stream=None, log=None, measure_density: bool = False):
     """Fit the step-time model on the training systems' own timings, then
     (rounds > 1) add the steps of the trees the model itself picks on those
     systems and refit, so its training data covers the region it searches.
     Returns (model, X, T)."""
-    X, T = collect_samples(systems, n_random=n_random, reps=reps, seed=seed, stream=stream, log=log)
+    X, T = collect_samples(systems, n_random=n_random, reps=reps, seed=seed, stream=stream, log=log,
+                           measure_density=measure_density)
     model = pa.Model(seed=seed)
     train(model, X, T, steps=steps, log=log)
     for r in range(1, rounds):
         Xl, Tl = collect_samples(systems, n_random=0, reps=reps, seed=seed + r, stream=stream, log=log, model=model,
-                                 base_policies=False)
+                                 base_policies=False, measure_density=measure_density)
         X, T = np.concatenate([X, Xl]), np.concatenate([T, Tl])
         model = pa.Model(seed=seed + r)
         train(model, X, T, steps=steps, log=log)
@@ -149,7 +154,8 @@ def train_order_model(systems: Sequence, rounds: int = 2, n_random: int = 3, rep
 
 
 def time_policies(systems: Sequence, model, policies=("greedy", "exhaustive", "learned"), steps: int = 10,
-                  warmup: int = 2, stream=None, check_bits: bool = True, log=None) -> Dict[str, dict]:
+                  warmup: int = 2, stream=None, check_bits: bool = True, log=None,
+                  measure_density: bool = False) -> Dict[str, dict]:
     """Measured solve time of every system under each ordering policy (the
     default grouped executor replayed as a hipGraph), plan times, and whether
     all policies produced identical bits.  "learned_verified" is the learned
@@ -167,8 +173,9 @@ def time_policies(systems: Sequence, model, policies=("greedy", "exhaustive", "l
         try:
             for p in policies:
                 t0 = time.perf_counter()
-                plans[p] = pa.Plan(s, order=order[p], model=model if p.startswith("learned") else None, graph=True,
-                                   verify_order=(p == "learned_verified"))
+                learned = p.startswith("learned")
+                plans[p] = pa.Plan(s, order=order[p], model=model if learned else None, graph=True,
+                                   verify_order=(p == "learned_verified"), measure_density=measure_density and learned)
                 res[p]["plan_ms"].append(1e3 * (time.perf_counter() - t0))
         except pa.PaError as e:              # some policy's tree does not fit the workspace cap
             if e.code != pa.PA_ENOMEM:

@@ -65,8 +65,8 @@ class Opts(ctypes.Structure):
                 ("model", ctypes.c_void_p), ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
                 ("autotune", ctypes.c_int32), ("gemm_split", ctypes.c_int32), ("gemm_path", ctypes.c_int32),
                 ("verify_order", ctypes.c_int32), ("sparse_pass", ctypes.c_int32),
-                ("sparse_max_density", ctypes.c_int32), ("plot_rule", ctypes.c_int32), ("reserved0", ctypes.c_int32),
-                ("tolerance", ctypes.c_double)]
+                ("sparse_max_density", ctypes.c_int32), ("plot_rule", ctypes.c_int32),
+                ("measure_density", ctypes.c_int32), ("tolerance", ctypes.c_double)]
 
 
 class Tuning(ctypes.Structure):
@@ -94,12 +94,21 @@ _lib = None
 
 
 def load(path: str = LIB_PATH):
-    """Load libpa.so (built in-tree by paper_1609_00061_amd/build.py)."""
+    """Load libpa.so (built in-tree by paper_1609_00061_amd/build.py).  On a
+    machine with a GPU, PyTorch's device runtime is initialised first: device
+    memory and streams come from PyTorch, and its runtime does not start once
+    the library has initialised HIP in the process."""
     global _lib
     if _lib is not None:
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"libpa.so not built ({path}); run __graft_entry__.build() first")
+    try:
+        import torch
+        if torch.cuda.is_available():
+            torch.cuda.init()
+    except ImportError:
+        pass
     L = ctypes.CDLL(path)
     vp, i32p = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)
     L.pa_row_words.argtypes = [ctypes.c_int32]
@@ -127,6 +136,7 @@ def load(path: str = LIB_PATH):
     L.pa_solve_system.argtypes = [ctypes.POINTER(System), i32p, ctypes.c_int32, ctypes.POINTER(Opts),
                                   ctypes.POINTER(BitArray), ctypes.POINTER(Report), vp]
     L.pa_popcount.argtypes = [ctypes.POINTER(BitArray), ctypes.POINTER(ctypes.c_int64), vp]
+    L.pa_tile_popcount.argtypes = [ctypes.POINTER(BitArray), ctypes.c_int32, ctypes.c_int32, vp, vp]
     L.pa_plan_op_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32),
                                    ctypes.POINTER(ctypes.c_double), ctypes.c_int32]
     L.pa_plan_op_times.restype = ctypes.c_int32
@@ -220,7 +230,8 @@ def make_opts(order=ORDER_EXHAUSTIVE, precision=PLOT_FP32_ESCALATE, audit=False,
               given: Optional[Sequence[int]] = None, model=None, keep: Optional[_Keep] = None, per_op=False,
               graph=False, single_launch=False, persist_wg=0, plot_strip=0, contract_units=0,
               autotune=False, gemm_split=0, gemm_path=0, verify_order=False, sparse_pass=0,
-              sparse_max_density=0, workspace=None, plot_rule=RULE_CORNER, tolerance=0.0) -> Opts:
+              sparse_max_density=0, workspace=None, plot_rule=RULE_CORNER, tolerance=0.0,
+              measure_density=False) -> Opts:
     """pa_opts from keyword arguments; `workspace` is a device tensor the
     caller owns (its data pointer and byte size are passed)."""
     o = Opts()
@@ -243,6 +254,7 @@ def make_opts(order=ORDER_EXHAUSTIVE, precision=PLOT_FP32_ESCALATE, audit=False,
     o.sparse_max_density = int(sparse_max_density)
     o.plot_rule = int(plot_rule)
     o.tolerance = float(tolerance)
+    o.measure_density = int(measure_density)
     if workspace is not None:
         o.workspace = ctypes.c_void_p(workspace.data_ptr())
         o.workspace_bytes = workspace.numel() * workspace.element_size()
@@ -686,3 +698,19 @@ def popcount(t, dims) -> int:
     ba = bitarray(t, dims)
     _check(L.pa_popcount(ctypes.byref(ba), ctypes.byref(c), _stream_ptr()))
     return int(c.value)
+
+
+def tile_popcount(t, dims, tile_rows, tile_words, stream=None):
+    """Set bits per tile (density map) of a device bit array: a device int32
+    tensor of shape (row blocks, word blocks) holding uint32 counts."""
+    import torch
+    rows = 1
+    for d in dims[:-1]:
+        rows *= int(d)
+    rw = row_words(dims[-1]) if len(dims) else 1
+    tr, tw = -(-rows // tile_rows), -(-rw // tile_words)
+    out = torch.zeros(max(1, tr * tw), dtype=torch.int32, device="cuda")
+    ba = bitarray(t, dims)
+    _check(load().pa_tile_popcount(ctypes.byref(ba), int(tile_rows), int(tile_words), ctypes.c_void_p(out.data_ptr()),
+                                   _stream_ptr(stream)))
+    return out[: tr * tw].reshape(tr, tw)
