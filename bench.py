@@ -366,16 +366,18 @@ def _learned(stream, n_train=128, n_eval=256, res=128):
     from paper_1609_00061_amd import inputs, learn, pa
     t0 = time.perf_counter()
     model, X, T = learn.train_order_model(inputs.config5(n_graphs=n_train, index=1000, res=res), rounds=2,
-                                         n_random=4, steps=4000, log=_progress)
+                                         n_random=4, steps=4000, log=_progress, measure_density=True)
     train_s = time.perf_counter() - t0
     pred = model.forward(torch.from_numpy(X).cuda()).cpu().numpy()
     r2 = float(1.0 - np.mean((pred - T) ** 2) / np.var(T))
     evals = inputs.config5(n_graphs=n_eval, index=0, res=res)
     _progress(f"trained in {train_s:.1f} s on {len(T)} samples; timing policies on {len(evals)} graphs")
-    pol = learn.time_policies(evals, model, policies=("greedy", "exhaustive", "learned"), steps=3, stream=stream)
+    pol = learn.time_policies(evals, model, policies=("greedy", "exhaustive", "learned"), steps=3, stream=stream,
+                              measure_density=True)
     out = {"workload": f"{n_eval} random relation hypergraphs (8-14 variables, arity 2-3, 2-4 exposed, "
                        f"{res} cells/axis, [-3,3], at most 4 variables kept and 6 ranged over per merge of some "
-                       f"tree); model trained on {n_train} disjoint graphs",
+                       f"tree); model trained on {n_train} disjoint graphs; density features from the plot "
+                       f"densities each plan measures",
            "train_s": train_s, "train_samples": int(len(T)), "fit_r2": r2,
            "same_bits_all_policies": pol["same_bits"], "systems": pol["systems"],
            "skipped_enomem": pol["skipped_enomem"]}
@@ -399,7 +401,7 @@ def _learned(stream, n_train=128, n_eval=256, res=128):
             ok.append(s)
     out["vs_plain_graphs"] = len(ok)
     try:
-        b = pa.Batch(ok, order=pa.ORDER_LEARNED, model=model, graph=True, autotune=True)
+        b = pa.Batch(ok, order=pa.ORDER_LEARNED, model=model, graph=True, autotune=True, measure_density=True)
         outs = b.alloc_outputs()
         torch.cuda.synchronize()
         b.execute(outs, stream=stream)

@@ -1,6 +1,7 @@
 """The learned contraction order on the hypergraph workload at its stated
 size: a step-time model trained on the GPU (library kernels) from the
-library's own step timings on training graphs (a disjoint seed range), then
+library's own step timings on training graphs (a disjoint seed range), its
+density features starting from the plot densities each plan measures, then
 all 256 evaluation graphs (8-14 variables, arity 2-3, 2-4 exposed, 128 cells
 per axis) solved under the model's own order and the exhaustive naive-cost
 order, and under the greedy order where its tree needs at most 32 GiB and
@@ -30,7 +31,7 @@ def model():
     import torch
     train = inputs.config5(n_graphs=128, index=1000, res=128)
     note("learned: training on", len(train), "graphs at 128")
-    m, X, T = learn.train_order_model(train, rounds=2, n_random=4, steps=4000, log=note)
+    m, X, T = learn.train_order_model(train, rounds=2, n_random=4, steps=4000, log=note, measure_density=True)
     pred = m.forward(torch.from_numpy(X).cuda()).cpu().numpy()
     r2 = 1.0 - np.mean((pred - T) ** 2) / np.var(T)
     note("learned: fit r2", float(r2), "samples", len(T))
@@ -50,7 +51,8 @@ def test_learned_order_full_size(model):
     graphs = inputs.config5(n_graphs=len(golden), index=0, res=128)
     assert len(graphs) == 256
     stream = torch.cuda.Stream()
-    pols = {"exhaustive": dict(order=pa.ORDER_EXHAUSTIVE), "learned": dict(order=pa.ORDER_LEARNED, model=model),
+    pols = {"exhaustive": dict(order=pa.ORDER_EXHAUSTIVE),
+            "learned": dict(order=pa.ORDER_LEARNED, model=model, measure_density=True),
             "greedy": dict(order=pa.ORDER_GREEDY)}
     ms = {p: [] for p in pols}
     plan_ms = {p: [] for p in pols}
