@@ -182,10 +182,13 @@ typedef struct {
                                  workgroup, 128x128 output tiles; 2 = each wave loads
                                  its own rows straight into registers (no LDS, no
                                  barriers); 3 = staged in LDS, 256x128 output tiles
-                                 (4x2 MFMA blocks per wave); 0: default (3 for
+                                 (4x2 MFMA blocks per wave); 4 = 256x128 tiles with
+                                 the A operands kept in registers while consecutive
+                                 tiles share their rows (K of at most 256 bits, else
+                                 3); 0: default (4, or 3 when K is longer, for
                                  contractions of at least 8192 128x128 tiles, else
                                  1).  A single persistent launch (single_launch)
-                                 uses 1 in place of 3 and of the default        */
+                                 uses 1 in place of 3, 4 and of the default     */
     int32_t verify_order;     /* PA_ORDER_LEARNED, pa_plan_create: 1 = when the model's
                                  tree differs from the exhaustive one, build both,
                                  time each on the device (one untimed and two timed
@@ -453,7 +456,8 @@ int32_t pa_plan_step_samples(pa_plan *plan, float *features, float *log2_us, int
  * length (1/2/4/8 cells per thread), then the streaming tile (512..32768
  * output bits), then the MFMA K-split target (1, 64, 128, 256, 512, 1024,
  * 2048 work items), then the MFMA operand path (LDS-staged 128x128 or
- * 256x128 tiles, or direct), then (when opts->sparse_pass is 0) the sparse
+ * 256x128 tiles, direct, or resident A operands), then (when
+ * opts->sparse_pass is 0) the sparse
  * pass alone for every contraction whose B is a plot, each
  * from the best so far.  Every candidate is a batch built
  * with opts (graph capture included if opts->graph), executed once untimed,

@@ -1,7 +1,8 @@
 // gfx950 kernels of the pixel array method: corner plotting with FP32
 // evaluation and FP64 escalation, bitwise OR-of-AND contractions, a dense
-// Boolean contraction on int8 MFMA with int32 accumulation, and a persistent
-// work-queue executor that runs all of them as tiles of one launch.
+// Boolean contraction on fp4 MFMA with fp32 accumulation (the count semiring
+// on int8 MFMA with int32 accumulation), and a persistent work-queue
+// executor that runs all of them as tiles of one launch.
 //
 // Build flags (see build.py): -O3 --offload-arch=gfx950 -ffp-contract=off
 // (no implicit FMA: every fused multiply-add below is an explicit fma/fmaf).
@@ -1184,7 +1185,9 @@ hipError_t launch_ktab(const ContractArgs &a, int mode, int64_t *tab, int64_t n,
 
 // ------------------------------------------------------- MFMA contraction
 typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v8i __attribute__((ext_vector_type(8)));
 typedef int v16i __attribute__((ext_vector_type(16)));
+typedef float v16f __attribute__((ext_vector_type(16)));
 
 constexpr int kTile = 128;     // output tile columns (and rows of the 128 x 128 tile): 4 waves of 64 x 64
 constexpr int kChunk = 8;      // K words staged per iteration (256 Boolean k)
@@ -1212,17 +1215,31 @@ __device__ __forceinline__ uint4 load_row4(const PA_G uint32_t *__restrict__ p, 
     return v;
 }
 
-// Spread one 32-bit word of Boolean k-entries into an int8 MFMA operand:
-// byte p of dword j (j = 0..3) is bit (8p + 4h + j) of x times 2^(4h + j),
-// h = lane half.  A and B use the same map, so every product is 0 or a
-// positive 4^(4h+j) and an accumulated count is > 0 iff some k has both bits.
-__device__ __forceinline__ v4i spread(uint32_t x, const uint32_t *m) {
+// The Boolean contraction runs on the fp4 (e2m1) MFMA 32 x 32 x 64 with fp32
+// accumulation: lane half h supplies 32 of the 64 k of a step as one 32-bit
+// word of Boolean k-entries, spread into 4 dwords of 8 nibbles.  Nibble i of
+// dword j (j < 3) is bit 4i + j of x left in place (e2m1 codes 0001, 0010,
+// 0100: 0.5, 1, 2); dword 3 takes bit 4i + 3 moved down one place (code
+// 0100), the nibble's top bit being the sign.  A and B use the same map, so
+// every product is 0 or a positive 0.25, 1 or 4, and an fp32 sum of them is
+// > 0 iff some k has both bits (whatever the rounding: every term is >= 0).
+// The instruction reads 4 of the 8 operand dwords for fp4; the rest are
+// left undefined.
+__device__ __forceinline__ v4i spread_fp4(uint32_t x) {
     v4i r;
-    r[0] = (int)(x & m[0]);
-    r[1] = (int)(x & m[1]);
-    r[2] = (int)(x & m[2]);
-    r[3] = (int)(x & m[3]);
+    r[0] = (int)(x & 0x11111111u);
+    r[1] = (int)(x & 0x22222222u);
+    r[2] = (int)(x & 0x44444444u);
+    r[3] = (int)((x >> 1) & 0x44444444u);
     return r;
+}
+
+// acc + A^T B over one 64-k step (both operands fp4, block scales 2^0); the
+// operands are held as 4 dwords, widened to the builtin's 8 at the call
+__device__ __forceinline__ v16f mfma_fp4(const v4i &b, const v4i &a, const v16f &acc) {
+    const v8i b8 = __builtin_shufflevector(b, b, 0, 1, 2, 3, -1, -1, -1, -1);
+    const v8i a8 = __builtin_shufflevector(a, a, 0, 1, 2, 3, -1, -1, -1, -1);
+    return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(b8, a8, acc, 4, 4, 0, 127, 0, 127);
 }
 
 // B rows are presented to the MFMA permuted within each 32-row block: MFMA
@@ -1234,42 +1251,41 @@ __device__ __forceinline__ int brow_of_mfma_row(int rho) { return ((rho >> 2) & 
 __device__ __forceinline__ int mfma_row_of_brow(int n) { return ((n >> 2) & 3) * 8 + (n >> 4) * 4 + (n & 3); }
 
 // The 16 output bits of one 32x32 accumulator block for this lane: bit r set
-// iff count r > 0 (counts are >= 0).  Registers r and r + 8 are packed into
-// one dword with 16-bit saturation, both halves clamped to 1 with one packed
-// 16-bit min and shifted into place (bits r and 16 + r), then byte 2 moves
-// next to byte 0: 24 instructions for 16 counts (written out: the compiler
-// would turn min(x, 1) into compares and selects).
-__device__ __forceinline__ uint32_t block_bits16(const v16i &a) {
-    const uint32_t one2 = 0x00010001u, sel = 0x0c0c0200u;
-    uint32_t m, t;
-    asm("v_cvt_pk_u16_u32 %0, %2, %10\n"
-        "v_pk_min_u16 %0, %0, %18\n"
-        "v_cvt_pk_u16_u32 %1, %3, %11\n"
-        "v_pk_min_u16 %1, %1, %18\n"
-        "v_lshl_or_b32 %0, %1, 1, %0\n"
-        "v_cvt_pk_u16_u32 %1, %4, %12\n"
-        "v_pk_min_u16 %1, %1, %18\n"
-        "v_lshl_or_b32 %0, %1, 2, %0\n"
-        "v_cvt_pk_u16_u32 %1, %5, %13\n"
-        "v_pk_min_u16 %1, %1, %18\n"
-        "v_lshl_or_b32 %0, %1, 3, %0\n"
-        "v_cvt_pk_u16_u32 %1, %6, %14\n"
-        "v_pk_min_u16 %1, %1, %18\n"
-        "v_lshl_or_b32 %0, %1, 4, %0\n"
-        "v_cvt_pk_u16_u32 %1, %7, %15\n"
-        "v_pk_min_u16 %1, %1, %18\n"
-        "v_lshl_or_b32 %0, %1, 5, %0\n"
-        "v_cvt_pk_u16_u32 %1, %8, %16\n"
-        "v_pk_min_u16 %1, %1, %18\n"
-        "v_lshl_or_b32 %0, %1, 6, %0\n"
-        "v_cvt_pk_u16_u32 %1, %9, %17\n"
-        "v_pk_min_u16 %1, %1, %18\n"
-        "v_lshl_or_b32 %0, %1, 7, %0\n"
-        "v_perm_b32 %0, %0, %0, %19\n"
-        : "=&v"(m), "=&v"(t)
-        : "v"(a[0]), "v"(a[1]), "v"(a[2]), "v"(a[3]), "v"(a[4]), "v"(a[5]), "v"(a[6]), "v"(a[7]), "v"(a[8]), "v"(a[9]),
-          "v"(a[10]), "v"(a[11]), "v"(a[12]), "v"(a[13]), "v"(a[14]), "v"(a[15]), "v"(one2), "v"(sel));
-    return m;
+// iff sum r > 0.  The sums are fp32 >= 0, so as unsigned integers a positive
+// one is >= 0x3e800000 (0.25) and saturates to 0xffff in a 16-bit pack:
+// registers r and r + 8 are packed into dword d_r (0 or 0xffff in each
+// half).  Bit-field inserts then merge them as a tree: d_0 and d_1 on
+// alternate bits (d_0 on the even ones), likewise d_2, d_3 (bits 2 and 3
+// are then d_2 and d_3), ...; those pairs on alternate bit pairs; the two
+// quads on alternate nibbles.  Bits r and 16 + r end up as d_r, and byte 2
+// moves next to byte 0: 16 instructions for 16 sums, with 3 masks.  The
+// packs and the byte move are builtins, so that the compiler sees every
+// read of an MFMA result (the hardware does not wait for one: the compiler
+// inserts the wait states) and every write that a later cross-lane move
+// reads; only the inserts, which the compiler would otherwise rewrite into
+// ANDs and ORs, are written out.
+__device__ __forceinline__ uint32_t pack_u16_sat(float lo, float hi) {
+    return __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pk_u16(__float_as_uint(lo), __float_as_uint(hi)));
+}
+
+__device__ __forceinline__ uint32_t block_bits16(const v16f &a) {
+    uint32_t d[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) d[r] = pack_u16_sat(a[r], a[r + 8]);
+    // VOP3 takes no literal: the masks come in SGPRs
+    const uint32_t m1 = 0x55555555u, m2 = 0x33333333u, m4 = 0x0f0f0f0fu;
+    uint32_t m, t, u;
+    asm("v_bfi_b32 %0, %11, %3, %4\n"
+        "v_bfi_b32 %1, %11, %5, %6\n"
+        "v_bfi_b32 %0, %12, %0, %1\n"
+        "v_bfi_b32 %1, %11, %7, %8\n"
+        "v_bfi_b32 %2, %11, %9, %10\n"
+        "v_bfi_b32 %1, %12, %1, %2\n"
+        "v_bfi_b32 %0, %13, %0, %1\n"
+        : "=&v"(m), "=&v"(t), "=&v"(u)
+        : "v"(d[0]), "v"(d[1]), "v"(d[2]), "v"(d[3]), "v"(d[4]), "v"(d[5]), "v"(d[6]), "v"(d[7]), "s"(m1), "s"(m2),
+          "s"(m4));
+    return __builtin_amdgcn_perm(m, m, 0x0c0c0200u);
 }
 
 // One tile of a Boolean GEMM as the loaders and the epilogue see it.
@@ -1344,7 +1360,7 @@ __device__ __forceinline__ GemmTileRef gemm_locate(const GemmArgs &g, int64_t t6
 // uniform.  Without a K split every lane stores its 16 bits; with one, the two
 // halves of each word are merged and OR-ed into the (zeroed) output.
 template <int WI>
-__device__ __forceinline__ void gemm_epilogue(const GemmTileRef &T, v16i (&acc)[WI][2]) {
+__device__ __forceinline__ void gemm_epilogue(const GemmTileRef &T, v16f (&acc)[WI][2]) {
     const int lane = threadIdx.x & 63, h = lane >> 5, l32 = lane & 31;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int wm = wave >> 1, wn = wave & 1;
@@ -1378,52 +1394,45 @@ __device__ __forceinline__ void gemm_epilogue(const GemmTileRef &T, v16i (&acc)[
 
 // MFMAs of one staged K chunk (kChunk words of A and B in LDS) for a wave's
 // WI x 2 blocks; with `fresh` the first MFMA of each block starts from zero
-// (a new tile).
+// (a new tile).  Lane half h reads words 4h .. 4h + 3 of its rows; step q
+// multiplies words q and 4 + q (halves 0 and 1).
 template <int WI>
-__device__ __forceinline__ void gemm_chunk(const uint32_t *sA, const uint32_t *sB, const uint32_t *msk,
-                                           v16i (&acc)[WI][2], bool fresh) {
-    const v16i zero = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+__device__ __forceinline__ void gemm_chunk(const uint32_t *sA, const uint32_t *sB, v16f (&acc)[WI][2], bool fresh) {
+    const v16f zero = {};
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int wm = wave >> 1, wn = wave & 1, l32 = lane & 31;
-    // one 4-word step at a time keeps the spread operands of a single step live
-#pragma unroll 1
-    for (int q4 = 0; q4 < kChunk; q4 += 4) {
-        uint4 a4[WI], b4[2];
+    const int wm = wave >> 1, wn = wave & 1, l32 = lane & 31, h4 = (lane >> 5) * 4;
+    uint4 a4[WI], b4[2];
+#pragma unroll
+    for (int i = 0; i < WI; ++i)
+        a4[i] = *reinterpret_cast<const uint4 *>(&sA[(wm * (32 * WI) + i * 32 + l32) * kPitch + h4]);
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+        b4[j] = *reinterpret_cast<const uint4 *>(&sB[(wn * 64 + j * 32 + l32) * kPitch + h4]);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        v4i opa[WI], opb[2];
 #pragma unroll
         for (int i = 0; i < WI; ++i)
-            a4[i] = *reinterpret_cast<const uint4 *>(&sA[(wm * (32 * WI) + i * 32 + l32) * kPitch + q4]);
+            opa[i] = spread_fp4(q == 0 ? a4[i].x : q == 1 ? a4[i].y : q == 2 ? a4[i].z : a4[i].w);
 #pragma unroll
         for (int j = 0; j < 2; ++j)
-            b4[j] = *reinterpret_cast<const uint4 *>(&sB[(wn * 64 + j * 32 + l32) * kPitch + q4]);
+            opb[j] = spread_fp4(q == 0 ? b4[j].x : q == 1 ? b4[j].y : q == 2 ? b4[j].z : b4[j].w);
+        // MFMA rows index n (from B), columns index m (from A): each lane
+        // then holds one column m, i.e. bits of one output row.
+        if (q == 0 && fresh) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            v4i opa[WI], opb[2];
+            for (int i = 0; i < WI; ++i)
 #pragma unroll
-            for (int i = 0; i < WI; ++i) {
-                const uint32_t x = q == 0 ? a4[i].x : q == 1 ? a4[i].y : q == 2 ? a4[i].z : a4[i].w;
-                opa[i] = spread(x, msk);
-            }
+                for (int j = 0; j < 2; ++j) acc[i][j] = mfma_fp4(opb[j], opa[i], zero);
+        } else {
 #pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                const uint32_t y = q == 0 ? b4[j].x : q == 1 ? b4[j].y : q == 2 ? b4[j].z : b4[j].w;
-                opb[j] = spread(y, msk);
-            }
-            // MFMA rows index n (from B), columns index m (from A): each lane
-            // then holds one column m, i.e. bits of one output row.
-            if (q == 0 && q4 == 0 && fresh) {
+            for (int i = 0; i < WI; ++i)
 #pragma unroll
-                for (int i = 0; i < WI; ++i)
-#pragma unroll
-                    for (int j = 0; j < 2; ++j)
-                        acc[i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(opb[j], opa[i], zero, 0, 0, 0);
-            } else {
-#pragma unroll
-                for (int i = 0; i < WI; ++i)
-#pragma unroll
-                    for (int j = 0; j < 2; ++j)
-                        acc[i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(opb[j], opa[i], acc[i][j], 0, 0, 0);
-            }
+                for (int j = 0; j < 2; ++j) acc[i][j] = mfma_fp4(opb[j], opa[i], acc[i][j]);
         }
+        // keep the operands of one step live at a time (no hoisting of the
+        // next steps' spreads above these MFMAs)
+        __builtin_amdgcn_sched_barrier(0);
     }
 }
 
@@ -1451,13 +1460,9 @@ __device__ void gemm_tiles(Next next, uint32_t *lds) {
     constexpr int TM = 64 * WI;
     uint32_t *sA[2] = {lds, lds + TM * kPitch};
     uint32_t *sB[2] = {lds + 2 * TM * kPitch, lds + 2 * TM * kPitch + kTile * kPitch};
-    const int tid = threadIdx.x, lane = tid & 63;
-    const int h = lane >> 5;
+    const int tid = threadIdx.x;
     const int lrow = tid >> 1, lw = (tid & 1) * 4;
     const int brow = (lrow & ~31) | mfma_row_of_brow(lrow & 31);   // LDS row of this thread's B row
-    uint32_t msk[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) msk[j] = 0x01010101u << (4 * h + j);
     auto advance = [&](const GemmChunk &c) {
         GemmChunk n = c;
         if (!c.valid) return n;
@@ -1491,7 +1496,7 @@ __device__ void gemm_tiles(Next next, uint32_t *lds) {
     load(c0, r0);
     GemmChunk c1 = advance(c0);
     load(c1, r1);
-    v16i acc[WI][2];
+    v16f acc[WI][2];
     // one pipeline step: stage chunk c0 (in r) into LDS buffer `buf`, start
     // loading chunk c0+2 into r, multiply, finish a tile
     auto step = [&](GemmStage<WI> &r, int buf) {
@@ -1503,7 +1508,7 @@ __device__ void gemm_tiles(Next next, uint32_t *lds) {
         const GemmChunk c2 = advance(c1);
         load(c2, r);
         const bool fresh = c0.kc == c0.T.kw0;
-        gemm_chunk<WI>(sA[buf], sB[buf], msk, acc, fresh);
+        gemm_chunk<WI>(sA[buf], sB[buf], acc, fresh);
         if (c0.kc + kChunk >= c0.T.kw1) gemm_epilogue<WI>(c0.T, acc);
         c0 = c1;
         c1 = c2;
@@ -1516,8 +1521,8 @@ __device__ void gemm_tiles(Next next, uint32_t *lds) {
 }
 
 // ---- direct path: no LDS, no barriers.  Each wave loads the two A rows
-// and two B rows its lanes multiply (lanes l and l + 32 read the same
-// words) straight into registers, one K chunk ahead, and runs its 64 x 64
+// and two B rows its lanes multiply (lane half h reads words 4h .. 4h + 3
+// of each chunk) straight into registers, one K chunk ahead, and runs its 64 x 64
 // quadrant of the tile on its own.
 struct GemmRows {
     const PA_G uint32_t *a[2], *b[2];
@@ -1549,44 +1554,37 @@ struct GemmChunkD {
     bool valid;
 };
 
-// MFMAs of one K chunk held in registers: a4[i][h4] = words 4*h4 .. 4*h4+3
-// of this lane's A row i (b4 likewise for B).
-__device__ __forceinline__ void gemm_chunk_regs(const uint4 (&a4)[2][2], const uint4 (&b4)[2][2],
-                                                const uint32_t *msk, v16i (&acc)[2][2], bool fresh) {
-    const v16i zero = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+// MFMAs of one K chunk held in registers: a4[i] = words 4h .. 4h + 3 of this
+// lane's A row i (h = lane half; b4 likewise for B); step q multiplies words
+// q and 4 + q.
+__device__ __forceinline__ void gemm_chunk_regs(const uint4 (&a4)[2], const uint4 (&b4)[2], v16f (&acc)[2][2],
+                                                bool fresh) {
+    const v16f zero = {};
 #pragma unroll
-    for (int q = 0; q < kChunk; ++q) {
+    for (int q = 0; q < 4; ++q) {
         v4i opa[2], opb[2];
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
-            const uint4 &w = a4[i][q >> 2];
-            const uint32_t x = (q & 3) == 0 ? w.x : (q & 3) == 1 ? w.y : (q & 3) == 2 ? w.z : w.w;
-            opa[i] = spread(x, msk);
-            const uint4 &v = b4[i][q >> 2];
-            const uint32_t y = (q & 3) == 0 ? v.x : (q & 3) == 1 ? v.y : (q & 3) == 2 ? v.z : v.w;
-            opb[i] = spread(y, msk);
+            opa[i] = spread_fp4(q == 0 ? a4[i].x : q == 1 ? a4[i].y : q == 2 ? a4[i].z : a4[i].w);
+            opb[i] = spread_fp4(q == 0 ? b4[i].x : q == 1 ? b4[i].y : q == 2 ? b4[i].z : b4[i].w);
         }
         if (q == 0 && fresh) {
 #pragma unroll
             for (int i = 0; i < 2; ++i)
 #pragma unroll
-                for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(opb[j], opa[i], zero, 0, 0, 0);
+                for (int j = 0; j < 2; ++j) acc[i][j] = mfma_fp4(opb[j], opa[i], zero);
         } else {
 #pragma unroll
             for (int i = 0; i < 2; ++i)
 #pragma unroll
-                for (int j = 0; j < 2; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(opb[j], opa[i], acc[i][j], 0, 0, 0);
+                for (int j = 0; j < 2; ++j) acc[i][j] = mfma_fp4(opb[j], opa[i], acc[i][j]);
         }
     }
 }
 
 template <class Next>
 __device__ void gemm_tiles_direct(Next next) {
-    const int h = (threadIdx.x & 63) >> 5;
-    uint32_t msk[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) msk[j] = 0x01010101u << (4 * h + j);
+    const int h4 = ((threadIdx.x & 63) >> 5) * 4;
     auto advance = [&](const GemmChunkD &c) {
         GemmChunkD n = c;
         if (!c.valid) return n;
@@ -1600,29 +1598,27 @@ __device__ void gemm_tiles_direct(Next next) {
         }
         return n;
     };
-    auto load = [&](const GemmChunkD &c, uint4 (&a4)[2][2], uint4 (&b4)[2][2]) {
+    auto load = [&](const GemmChunkD &c, uint4 (&a4)[2], uint4 (&b4)[2]) {
         if (!c.valid) return;
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-            for (int h4 = 0; h4 < 2; ++h4) {
-                a4[i][h4] = load_row4(c.R.a[i], c.kc + 4 * h4, c.T.kw1, c.R.a_ok[i], c.T.vec4);
-                b4[i][h4] = load_row4(c.R.b[i], c.kc + 4 * h4, c.T.kw1, c.R.b_ok[i], c.T.vec4);
-            }
+        for (int i = 0; i < 2; ++i) {
+            a4[i] = load_row4(c.R.a[i], c.kc + h4, c.T.kw1, c.R.a_ok[i], c.T.vec4);
+            b4[i] = load_row4(c.R.b[i], c.kc + h4, c.T.kw1, c.R.b_ok[i], c.T.vec4);
+        }
     };
     GemmChunkD c0;
     c0.valid = next(c0.T);
     if (!c0.valid) return;
     c0.R = gemm_rows(c0.T);
     c0.kc = c0.T.kw0;
-    uint4 A0[2][2], B0[2][2], A1[2][2], B1[2][2];
+    uint4 A0[2], B0[2], A1[2], B1[2];
     load(c0, A0, B0);
-    v16i acc[2][2];
+    v16f acc[2][2];
     // chunk c0 is in (Ac, Bc); load the next chunk into (An, Bn), multiply
-    auto step = [&](uint4 (&Ac)[2][2], uint4 (&Bc)[2][2], uint4 (&An)[2][2], uint4 (&Bn)[2][2]) {
+    auto step = [&](uint4 (&Ac)[2], uint4 (&Bc)[2], uint4 (&An)[2], uint4 (&Bn)[2]) {
         const GemmChunkD c1 = advance(c0);
         load(c1, An, Bn);
-        gemm_chunk_regs(Ac, Bc, msk, acc, c0.kc == c0.T.kw0);
+        gemm_chunk_regs(Ac, Bc, acc, c0.kc == c0.T.kw0);
         if (c0.kc + kChunk >= c0.T.kw1) gemm_epilogue<2>(c0.T, acc);
         c0 = c1;
         return c0.valid;
@@ -1633,16 +1629,186 @@ __device__ void gemm_tiles_direct(Next next) {
     }
 }
 
+// Stores of output words that no later kernel of the launch reads:
+// non-temporal, so the streamed output does not evict the operand rows that
+// are re-read from L2 (the sparse pass's B rows, the resident MFMA path's B
+// tiles).
+__device__ __forceinline__ void store_words4(PA_G uint32_t *p, int64_t c, int64_t n, bool vec4, uint4 v) {
+    if (c + 3 < n) {
+        if (vec4) {
+            __builtin_nontemporal_store(u32x4{v.x, v.y, v.z, v.w}, reinterpret_cast<PA_G u32x4 *>(p + c));
+        } else {
+            __builtin_nontemporal_store(u32x2{v.x, v.y}, reinterpret_cast<PA_G u32x2 *>(p + c));
+            __builtin_nontemporal_store(u32x2{v.z, v.w}, reinterpret_cast<PA_G u32x2 *>(p + c + 2));
+        }
+    } else if (c < n) {
+        __builtin_nontemporal_store(u32x2{v.x, v.y}, reinterpret_cast<PA_G u32x2 *>(p + c));
+    }
+}
+
+// ---- resident path: contractions with K <= 256 bits (one chunk, so no K
+// split), 256 x 128 output tiles (4 waves of 128 x 64: 4 x 2 blocks).  Each
+// workgroup runs a contiguous range of tiles (XCD-aware: each XCD owns a
+// contiguous eighth of the tiles, split among its workgroups) in which
+// consecutive tiles mostly share their A rows (tile columns vary fastest).
+// Each wave keeps the fp4 operands of its 128 A rows (4 blocks x 4 steps) in
+// registers for as long as the rows stay the same, loaded straight from
+// global memory when they change; only the 128 B rows of a tile are staged
+// in LDS (double-buffered, loaded one tile ahead) and spread per tile.
+// The output bits of a group of 8 consecutive column tiles (128 bytes of
+// each of the 256 rows) are gathered in LDS and written out as whole
+// 128-byte lines with non-temporal stores: pieces of lines written from
+// different places at different times cost several times their bytes in
+// HBM writes.
+constexpr int kResGroup = 8;                     // column tiles per output group
+constexpr int kResPitch = 4 * kResGroup + 4;     // LDS words per staged output row (16-byte aligned rows)
+constexpr int kResLdsWords = 2 * kTile * kPitch + 256 * kResPitch;
+
+// Contiguous item range [lo, hi) of this workgroup among n items: the
+// XCD-aware split (workgroups go to the 8 XCDs round-robin; XCD x owns items
+// [x per, (x + 1) per), shared evenly by its workgroups).
+__device__ __forceinline__ void res_range(int64_t n, int64_t &lo, int64_t &hi) {
+    const int64_t per = (n + 7) >> 3;
+    const int64_t nwg = ((int64_t)gridDim.x + 7 - (blockIdx.x & 7)) >> 3;   // workgroups on this XCD
+    const int64_t k = blockIdx.x >> 3, span = (per + nwg - 1) / nwg;
+    lo = min(n, (int64_t)(blockIdx.x & 7) * per + k * span);
+    hi = min(min(n, (int64_t)((blockIdx.x & 7) + 1) * per), lo + span);
+}
+
+// Epilogue into the LDS output group: for each row block i the lane halves
+// trade block halves (v_permlane32_swap), so that lane half h holds the
+// whole 32-bit word of block column h of its row, written to word
+// 4 tt + 2 wn + h of the staged row (tt = the tile's place in its group).
+__device__ __forceinline__ void gemm_epilogue_res(v16f (&acc)[4][2], uint32_t *sC, int tt) {
+    const int lane = threadIdx.x & 63, h = lane >> 5, l32 = lane & 31;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int wm = wave >> 1, wn = wave & 1;
+    uint32_t *dst = sC + (wm * 128 + l32) * kResPitch + 4 * tt + 2 * wn + h;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const uint32_t v0 = block_bits16(acc[i][0]), v1 = block_bits16(acc[i][1]);
+        // lanes 32..63 of v0 trade places with lanes 0..31 of v1
+        const auto sw = __builtin_amdgcn_permlane32_swap(v0, v1, false, false);
+        dst[i * 32 * kResPitch] = sw[0] | (sw[1] << 16);
+    }
+}
+
+// The output group being staged: output c, rows m0 .. m0 + 255 (those < M)
+// of rs words each, words gw + w for w in [w0, w1) (the tiles of the group
+// this workgroup computed; gw = the group's first word).
+struct ResGroup {
+    PA_G uint32_t *c;
+    int64_t rs, gw;
+    int32_t m0, M, w0, w1;
+};
+
+// Writes the staged output group, 4 words per thread and step, so that 8
+// consecutive lanes write one 128-byte line.
+__device__ __forceinline__ void res_flush(const ResGroup &G, const uint32_t *sC) {
+    const bool vec4 = (G.rs % 4) == 0;
+#pragma unroll 1
+    for (int idx = threadIdx.x; idx < 256 * kResGroup; idx += 256) {
+        const int r = idx / kResGroup, w = (idx % kResGroup) * 4;
+        if (w < G.w0 || w >= G.w1 || G.m0 + r >= G.M) continue;
+        const uint4 v = *reinterpret_cast<const uint4 *>(&sC[r * kResPitch + w]);
+        store_words4(G.c + (int64_t)(G.m0 + r) * G.rs, G.gw + w, G.rs, vec4, v);
+    }
+}
+
+template <class Next>
+__device__ void gemm_tiles_res(Next next, uint32_t *lds) {
+    // B buffer `buf` at lds + buf * kTile * kPitch (offsets from the LDS
+    // array itself, so that every access stays an LDS access)
+    uint32_t *sC = lds + 2 * kTile * kPitch;
+    const int tid = threadIdx.x, lane = tid & 63, l32 = lane & 31, h4 = (lane >> 5) * 4;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wm = wave >> 1, wn = wave & 1;
+    const int lrow = tid >> 1, lw = (tid & 1) * 4;
+    const int brow = (lrow & ~31) | mfma_row_of_brow(lrow & 31);   // LDS row of this thread's B row
+    const v16f zero = {};
+    GemmTileRef T0, T1;
+    if (!next(T0)) return;
+    // B of the current tile, loaded one tile ahead (the B tiles are L2 hits)
+    uint4 rb = load_row4(T0.b, T0.kw0 + lw, T0.kw1, T0.b_ok, T0.vec4);
+    v4i opa[4][4];                            // A operands of block i, step q
+    const PA_G uint32_t *a_base = nullptr;    // the rows they hold (uniform)
+    int32_t a_m0 = -1;
+    ResGroup G;                               // the staged output group (uniform)
+    G.w0 = G.w1 = 0;                          // none yet
+    v16f acc[4][2];
+    int buf = 0;
+    for (;;) {
+        uint32_t *sB = lds + buf * (kTile * kPitch);
+        *reinterpret_cast<uint4 *>(&sB[brow * kPitch + lw]) = rb;
+        // the A operands, when the rows change
+        if (T0.abase != a_base || T0.m0 != a_m0) {
+            a_base = T0.abase;
+            a_m0 = T0.m0;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int32_t row = T0.m0 + wm * 128 + i * 32 + l32;
+                const bool ok = row < T0.M;
+                const uint4 w = load_row4(T0.abase + (int64_t)(ok ? row : 0) * T0.Kw, h4, T0.kw1, ok, T0.vec4);
+                opa[i][0] = spread_fp4(w.x);
+                opa[i][1] = spread_fp4(w.y);
+                opa[i][2] = spread_fp4(w.z);
+                opa[i][3] = spread_fp4(w.w);
+            }
+        }
+        __syncthreads();                      // B staged; the previous tile's output staged
+        // the output group: flushed when this tile starts another one
+        const int tt = (T0.n0 >> 7) & (kResGroup - 1);   // the tile's place in its group
+        const int64_t gw = (T0.n0 >> 5) & ~(4 * kResGroup - 1);
+        if (!(G.w1 > G.w0 && T0.c == G.c && T0.m0 == G.m0 && gw == G.gw)) {
+            if (G.w1 > G.w0) {
+                res_flush(G, sC);
+                __syncthreads();              // the group is read before it is overwritten
+            }
+            G.c = T0.c;
+            G.rs = (int64_t)T0.No * T0.rwc;
+            G.gw = gw;
+            G.m0 = T0.m0;
+            G.M = T0.M;
+            G.w0 = 4 * tt;
+        }
+        G.w1 = 4 * tt + 4;
+        const bool more = next(T1);
+        if (more) rb = load_row4(T1.b, T1.kw0 + lw, T1.kw1, T1.b_ok, T1.vec4);
+        // B words are read from LDS one step at a time (fewer live registers)
+        const uint32_t *sb = &sB[(wn * 64 + l32) * kPitch + h4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            v4i opb[2];
+#pragma unroll
+            for (int j = 0; j < 2; ++j) opb[j] = spread_fp4(sb[j * 32 * kPitch + q]);
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) acc[i][j] = mfma_fp4(opb[j], opa[i][q], q == 0 ? zero : acc[i][j]);
+        }
+        gemm_epilogue_res(acc, sC, tt);
+        if (!more) break;
+        T0 = T1;
+        buf ^= 1;
+    }
+    __syncthreads();
+    res_flush(G, sC);
+}
+
 // Operand paths of the MFMA contraction (GemmArgs::path): 0 stages 128 x 128
 // tiles in LDS, 1 loads straight into registers, 2 stages 256 x 128 tiles
-// (4 x 2 blocks per wave: fewer operand spreads per MFMA, two waves per SIMD).
+// (4 x 2 blocks per wave: fewer operand spreads per MFMA, two waves per SIMD),
+// 3 keeps the A operands of 256 x 128 tiles in registers (K <= 256 bits).
 constexpr int gemm_occupancy(int path) { return path == 0 ? 3 : 2; }
-constexpr int gemm_lds_of(int path) { return path == 0 ? kGemmLdsWords : path == 2 ? kGemmLdsWordsWide : 1; }
+constexpr int gemm_lds_of(int path) {
+    return path == 0 ? kGemmLdsWords : path == 2 ? kGemmLdsWordsWide : path == 3 ? kResLdsWords : 1;
+}
 
 // Tiles of the canonical GEMM on operand path PATH; next(T) yields the tiles.
 template <int PATH, class Next>
 __device__ __forceinline__ void gemm_run(Next next, uint32_t *lds) {
     if constexpr (PATH == 1) gemm_tiles_direct(next);
+    else if constexpr (PATH == 3) gemm_tiles_res(next, lds);
     else gemm_tiles<PATH == 2 ? 4 : 2>(next, lds);
 }
 
@@ -1662,32 +1828,44 @@ __global__ __launch_bounds__(256, gemm_occupancy(PATH)) void k_gemm_mfma(GemmArg
     // when the sparse pass ran (A sparse enough) there is nothing to do
     if (g.dense && __hip_atomic_load(gp(g.dense), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u) return;
     const int64_t ntiles = g.nbatch * g.tiles_m * g.tiles_n * g.ksplit;
-    const int64_t per = (ntiles + 7) >> 3;
-    int64_t t = blockIdx.x;
-    auto next = [&](GemmTileRef &T) {
-        for (; t < 8 * per; t += gridDim.x) {
-            const int64_t tile = xcd_tile(t, per);
-            if (tile < ntiles) {
-                T = gemm_locate<PATH == 2 ? 4 : 2>(g, tile);
-                t += gridDim.x;
-                return true;
+    if constexpr (PATH == 3) {
+        int64_t t, tend;
+        res_range(ntiles, t, tend);
+        auto next = [&](GemmTileRef &T) {
+            if (t >= tend) return false;
+            T = gemm_locate<4>(g, t++);
+            return true;
+        };
+        gemm_run<PATH>(next, lds);
+    } else {
+        const int64_t per = (ntiles + 7) >> 3;
+        int64_t t = blockIdx.x;
+        auto next = [&](GemmTileRef &T) {
+            for (; t < 8 * per; t += gridDim.x) {
+                const int64_t tile = xcd_tile(t, per);
+                if (tile < ntiles) {
+                    T = gemm_locate<PATH == 2 ? 4 : 2>(g, tile);
+                    t += gridDim.x;
+                    return true;
+                }
             }
-        }
-        return false;
-    };
-    gemm_run<PATH>(next, lds);
+            return false;
+        };
+        gemm_run<PATH>(next, lds);
+    }
 }
 
 // Workgroups of a persistent tile loop: every CU's worth (a multiple of 8),
 // capped by the tiles rounded up to a multiple of 8.
 static int64_t gemm_grid(int64_t ntiles, int path) {
-    static int cached[3] = {0, 0, 0};
+    static int cached[4] = {0, 0, 0, 0};
     if (!cached[path]) {
         int dev = 0, cus = 256, per_cu = 1;
         if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
         const hipError_t e =
-            path == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_gemm_mfma<1>, 256, 0)
+            path == 1   ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_gemm_mfma<1>, 256, 0)
             : path == 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_gemm_mfma<2>, 256, 0)
+            : path == 3 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_gemm_mfma<3>, 256, 0)
                         : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_gemm_mfma<0>, 256, 0);
         if (e != hipSuccess || per_cu < 1) per_cu = 1;
         cached[path] = (cus * per_cu + 7) / 8 * 8;
@@ -1698,11 +1876,13 @@ static int64_t gemm_grid(int64_t ntiles, int path) {
 
 hipError_t launch_gemm(const GemmArgs &g, hipStream_t s) {
     if (g.nbatch == 0 || g.M == 0 || g.No == 0) return hipSuccess;
-    if (g.path < 0 || g.path > 2) return hipErrorInvalidValue;
+    if (g.path < 0 || g.path > 3) return hipErrorInvalidValue;
+    if (g.path == 3 && (g.Kw > kChunk || g.ksplit != 1)) return hipErrorInvalidValue;
     const int64_t nt = g.nbatch * g.tiles_m * g.tiles_n * g.ksplit;
     const dim3 grid((unsigned)gemm_grid(nt, g.path));
     if (g.path == 1) hipLaunchKernelGGL(k_gemm_mfma<1>, grid, dim3(256), 0, s, g);
     else if (g.path == 2) hipLaunchKernelGGL(k_gemm_mfma<2>, grid, dim3(256), 0, s, g);
+    else if (g.path == 3) hipLaunchKernelGGL(k_gemm_mfma<3>, grid, dim3(256), 0, s, g);
     else hipLaunchKernelGGL(k_gemm_mfma<0>, grid, dim3(256), 0, s, g);
     return hipGetLastError();
 }
@@ -1868,22 +2048,6 @@ __device__ __forceinline__ uint4 load_words4(const PA_G uint32_t *p, int64_t c, 
         v.y = t0.y;
     }
     return v;
-}
-
-// Stores of output words that no later kernel of the launch reads:
-// non-temporal, so the streamed output does not evict the rows the pass
-// keeps re-reading from L2.
-__device__ __forceinline__ void store_words4(PA_G uint32_t *p, int64_t c, int64_t n, bool vec4, uint4 v) {
-    if (c + 3 < n) {
-        if (vec4) {
-            __builtin_nontemporal_store(u32x4{v.x, v.y, v.z, v.w}, reinterpret_cast<PA_G u32x4 *>(p + c));
-        } else {
-            __builtin_nontemporal_store(u32x2{v.x, v.y}, reinterpret_cast<PA_G u32x2 *>(p + c));
-            __builtin_nontemporal_store(u32x2{v.z, v.w}, reinterpret_cast<PA_G u32x2 *>(p + c + 2));
-        }
-    } else if (c < n) {
-        __builtin_nontemporal_store(u32x2{v.x, v.y}, reinterpret_cast<PA_G u32x2 *>(p + c));
-    }
 }
 
 // Count step, tile t: the set bits of A words [t K, (t + 1) K) (K =
@@ -2220,6 +2384,42 @@ __global__ __launch_bounds__(256, KIND % 10 == kStepGemm ? gemm_occupancy(KIND /
             active = __ballot(on);
             if (active == 0) return;
         }
+        if constexpr (mode == 3) {
+            // a contiguous range of tiles per workgroup (the resident path
+            // keeps A operands while consecutive tiles share their rows),
+            // run one step at a time with a uniform copy of the step's
+            // arguments (scalar registers, scalar tile decoding)
+            int64_t lo, hi;
+            res_range(t1 - t0, lo, hi);
+            int64_t item = t0 + lo;
+            const int64_t iend = t0 + hi;
+            while (item < iend) {
+                // a scalar binary search (item is uniform)
+                int si = first, sh = first + count - 1;
+                while (si < sh) {
+                    const int mid = (si + sh + 1) >> 1;
+                    if (gp(steps)[mid].tile_base <= item) si = mid;
+                    else sh = mid - 1;
+                }
+                si = __builtin_amdgcn_readfirstlane(si);
+                const PStep &st = steps[si];
+                const int64_t sb = st.tile_base, se = min(iend, sb + st.n_tiles);
+                if ((active >> ((si - first) & 63)) & 1) {
+                    const GemmArgs g = st.gemm;
+                    int64_t t = item - sb;
+                    const int64_t tend = se - sb;
+                    auto next = [&](GemmTileRef &T) {
+                        if (t >= tend) return false;
+                        T = gemm_locate<4>(g, t++);
+                        return true;
+                    };
+                    gemm_run<mode>(next, lds);
+                    __syncthreads();          // the LDS is free for the next step
+                }
+                item = se;
+            }
+            return;
+        }
         // persistent tile loop with cross-tile prefetch, tiles in XCD-aware order
         const int64_t per = (t1 - t0 + 7) >> 3;
         int64_t t = blockIdx.x;
@@ -2318,7 +2518,7 @@ hipError_t launch_group(int kind, int mode, const PStep *d_steps, int first, int
                         int flags, PlotCounters *counters, hipStream_t s) {
     if (t1 <= t0) return hipSuccess;
     const int64_t nt = t1 - t0;
-    if (kind == kStepGemm && (mode < 0 || mode > 2)) return hipErrorInvalidValue;
+    if (kind == kStepGemm && (mode < 0 || mode > 3)) return hipErrorInvalidValue;
     const int64_t cap = kind == kStepGather ? gather_grid() : ((int64_t)1 << 20);
     const dim3 grid((unsigned)(kind == kStepGemm ? gemm_grid(nt, mode) : (nt < cap ? nt : cap)));
 #define PA_GROUP(K) hipLaunchKernelGGL(k_group<K>, grid, dim3(256), 0, s, d_steps, first, count, t0, t1, flags, counters)
@@ -2330,6 +2530,7 @@ hipError_t launch_group(int kind, int mode, const PStep *d_steps, int first, int
         case kStepGemm:
             if (mode == 1) PA_GROUP(kStepGemm + 10);
             else if (mode == 2) PA_GROUP(kStepGemm + 20);
+            else if (mode == 3) PA_GROUP(kStepGemm + 30);
             else PA_GROUP(kStepGemm);
             break;
         case kStepContract:

@@ -147,11 +147,16 @@ static void set_ksplit(GemmArgs &g, int64_t want);
 
 // Default operand path of one MFMA contraction: 256 x 128 tiles (fewer
 // operand spreads and tile set-ups per MFMA) once the output has at least
-// 8192 tiles of 128 x 128, where the extra tiles in flight cost nothing;
-// 128 x 128 tiles below that, where parallelism matters more.
+// 8192 tiles of 128 x 128, where the extra tiles in flight cost nothing --
+// with the A operands kept in registers across tiles when K is one chunk
+// (at most 256 bits) and output rows are at least 1024 bits --; 128 x 128
+// tiles below that, where parallelism matters more.
 static int auto_gemm_path(const GemmArgs &g) {
     const int64_t tiles = g.nbatch * ((g.M + 127) / 128) * ((g.No * g.rwc * 32 + 127) / 128);
-    return tiles >= 8192 ? 2 : 0;
+    if (tiles < 8192) return 0;
+    // the resident path writes output rows in groups of 8 column tiles
+    // (1024 bits): narrower outputs would flush (and reload A) every tile or two
+    return g.Kw <= 8 && g.No * g.rwc * 32 >= 1024 ? 3 : 2;
 }
 
 struct Builder {
@@ -330,7 +335,8 @@ struct Builder {
         g.sB_b = g.No * g.rn * g.Kw;
         g.sC_b = g.M * g.No * g.rwc;
         g.path = P->gemm_path >= 0 ? P->gemm_path : auto_gemm_path(g);
-        const int64_t tm = g.path == 2 ? 256 : 128;   // tile rows of the operand path
+        if (g.path == 3 && g.Kw > 8) g.path = 2;      // the resident path takes one K chunk
+        const int64_t tm = g.path >= 2 ? 256 : 128;   // tile rows of the operand path
         g.tiles_m = (g.M + tm - 1) / tm;
         g.tiles_n = (g.No * g.rwc * 32 + 127) / 128;
         // the K split (and the fill it needs) is set by split_gemms once
@@ -666,16 +672,16 @@ std::string Op::describe() const {
 // Plot tiles: tw words along the packed axis; the rest of the 256 threads
 // spread over ta cells of the fixed axis (n == 3) x tb strips of s walk cells.
 // Operand path of the MFMA kernels for the pa_opts value: 1 stages 128 x 128
-// tiles in LDS, 2 loads straight into registers, 3 stages 256 x 128 tiles;
-// 0 (the default) is -1 here: chosen per contraction by auto_gemm_path.
-static int gemm_path_of(int opt) { return opt == 0 ? -1 : opt == 2 ? 1 : opt == 3 ? 2 : 0; }
+// tiles in LDS, 2 loads straight into registers, 3 stages 256 x 128 tiles,
+// 4 keeps A operands of 256 x 128 tiles in registers (K of at most 256
+// bits, else 3); 0 (the default) is -1 here: chosen per contraction by
+// auto_gemm_path.
+static int gemm_path_of(int opt) { return opt == 0 ? -1 : opt == 2 ? 1 : opt == 3 ? 2 : opt == 4 ? 3 : 0; }
 
 // K split of an MFMA contraction: about `want` parts of whole 256-bit
-// chunks, and enough parts that none has more than 16384 K words (a count
-// gains at most 87380 per K word, so the int32 accumulator stays below 2^31).
+// chunks.  (The fp32 sums cannot overflow: each K bit adds at most 4.)
 static void set_ksplit(GemmArgs &g, int64_t want) {
     int64_t ksplit = std::max<int64_t>(1, std::min<int64_t>(want, (g.Kw + 7) / 8));
-    ksplit = std::max<int64_t>(ksplit, (g.Kw + 16383) / 16384);
     int64_t chunk = (g.Kw + ksplit - 1) / ksplit;
     chunk = (chunk + 7) / 8 * 8;
     ksplit = (g.Kw + chunk - 1) / chunk;
@@ -818,7 +824,7 @@ int build_plan(const pa_system *sys, const int32_t *exposed, int32_t n_exposed, 
     if (o.precision != PA_PLOT_FP32_ESCALATE && o.precision != PA_PLOT_FP64)
         return fail(PA_EINVAL, "opts: unknown precision");
     if (o.persist_wg < 0 || o.plot_strip < 0 || o.contract_units < 0 || o.gemm_split < 0 || o.gemm_path < 0 ||
-        o.gemm_path > 3)
+        o.gemm_path > 4)
         return fail(PA_EINVAL, "opts: negative tuning parameter");
     switch (o.order_policy) {
         case PA_ORDER_GREEDY: rc = plan_greedy(P->si, P->tree); break;
@@ -1322,7 +1328,7 @@ static int run_persist(pa_plan *P, hipStream_t s, int *launches, hipEvent_t befo
     const PStep *d_steps = reinterpret_cast<const PStep *>(base + P->steps_off);
     if (P->single_launch) {
         for (const PStep &st : P->steps_host)
-            if ((st.kind == kStepGemm && (st.gemm.path == 2 || st.gemm.dense)) || st.kind == kStepGather ||
+            if ((st.kind == kStepGemm && (st.gemm.path >= 2 || st.gemm.dense)) || st.kind == kStepGather ||
                 st.kind == kStepCount || (st.kind == kStepPlot && st.plot.rule != kRuleCorner))
                 return fail(PA_EINVAL,
                             "internal: 256-row MFMA tiles, a sparse pass or a centre plot in a single persistent launch");

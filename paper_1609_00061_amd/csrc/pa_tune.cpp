@@ -213,7 +213,7 @@ int autotune(const pa_system *systems, int32_t n_sys, const int32_t *const *expo
         t.gemm_split = sp;
         rc = trial(t);
     }
-    for (int path : {1, 2, 3}) {
+    for (int path : {1, 2, 3, 4}) {
         if (rc || best.ms < 0.0 || path == best.gemm_path) continue;
         pa_tuning t = best;
         t.gemm_path = path;

@@ -235,21 +235,26 @@ def test_gemm_split_target_sets_the_k_split():
 
 
 def test_mfma_operand_path_choice():
-    """Default operand path: 256 x 128 tiles (path 2 in the plan) for the
-    ternary system's two 65536^2 x 256 contractions (262144 tiles of
-    128 x 128 each), 128 x 128 tiles (path 0) for the chain's 1024^3 ones;
-    gemm_path 1/2/3 force paths 0/1/2; a single persistent launch never
-    uses 256-row tiles; out-of-range values are refused."""
+    """Default operand path: 256 x 128 tiles with the A operands kept in
+    registers (path 3 in the plan) for the ternary system's two
+    65536^2 x 256 contractions (262144 tiles of 128 x 128 each, K = 256
+    bits), 128 x 128 tiles (path 0) for the chain's 1024^3 ones; gemm_path
+    1/2/3/4 force paths 0/1/2/3, 4 falling back to 2 when K is longer than
+    256 bits; a single persistent launch never uses 256-row tiles;
+    out-of-range values are refused."""
     paths = lambda d: [o["path"] for o in d["ops"] if o["op"] == "gemm_mfma"]
     c2, c3 = inputs.config2(res=1024), inputs.config3()
-    assert set(paths(pa.describe_plan(c3))) == {2}
+    assert set(paths(pa.describe_plan(c3))) == {3}
     assert set(paths(pa.describe_plan(c2))) == {0}
-    for opt, path in ((1, 0), (2, 1), (3, 2)):
+    for opt, path in ((1, 0), (2, 1), (3, 2), (4, 2)):
         assert set(paths(pa.describe_plan(c2, gemm_path=opt))) == {path}
+    for opt, path in ((1, 0), (2, 1), (3, 2), (4, 3)):
+        assert set(paths(pa.describe_plan(c3, gemm_path=opt, sparse_pass=-1))) == {path}
     assert set(paths(pa.describe_plan(c3, single_launch=True))) == {0}
     assert set(paths(pa.describe_plan(c3, single_launch=True, gemm_path=3))) == {0}
+    assert set(paths(pa.describe_plan(c3, single_launch=True, gemm_path=4))) == {0}
     assert set(paths(pa.describe_plan(c3, single_launch=True, gemm_path=2))) == {1}
-    assert _bad(inputs.config1(), gemm_path=4) == pa.PA_EINVAL
+    assert _bad(inputs.config1(), gemm_path=5) == pa.PA_EINVAL
 
 
 def test_plan_create_rejects_before_touching_the_device():

@@ -66,14 +66,18 @@ def test_projection_without_b():
     _run((0, 1, 2), (), (0,), res, 0.02, 56, b_none=True)
 
 
-@pytest.mark.parametrize("path", [1, 2, 3])
+@pytest.mark.parametrize("path", [1, 2, 3, 4])
 @pytest.mark.parametrize("M,N,K", [(64, 64, 64), (128, 128, 256), (100, 130, 70), (1024, 1024, 1024),
-                                   (33, 1000, 5000), (300, 65, 129), (257, 7, 3000), (600, 300, 520)])
+                                   (33, 1000, 5000), (300, 65, 129), (257, 7, 3000), (600, 300, 520),
+                                   (700, 1500, 256), (513, 900, 200), (2000, 260, 33)])
 def test_mfma_gemm_sizes(M, N, K, path):
-    """Dense canonical layout A[m][k], B[n][k] -> C[m][n] on int8 MFMA, with
-    K chunks staged in LDS (path 1: 128 x 128 tiles, path 3: 256 x 128) or
-    loaded by each wave (path 2): all tile residues, ragged K tails, split K;
-    against integer matmul > 0."""
+    """Dense canonical layout A[m][k], B[n][k] -> C[m][n] on the fp4 MFMA,
+    with K chunks staged in LDS (path 1: 128 x 128 tiles, path 3: 256 x 128),
+    loaded by each wave (path 2), or with A operands kept in registers across
+    the 256 x 128 tiles of a workgroup's range (path 4, K <= 256 bits: several
+    row blocks and many column tiles per workgroup; longer K falls back to
+    3): all tile residues, ragged K tails, split K; against integer
+    matmul > 0."""
     A = inputs.random_bool_array((M, K), 2.0 / K, 91 + M)
     B = inputs.random_bool_array((N, K), 2.0 / K, 92 + N)
     note("gemm", M, N, K, "path", path)
@@ -83,7 +87,7 @@ def test_mfma_gemm_sizes(M, N, K, path):
     assert np.array_equal(got.astype(bool), ref)
 
 
-@pytest.mark.parametrize("path", [1, 2, 3])
+@pytest.mark.parametrize("path", [1, 2, 3, 4])
 def test_mfma_gemm_dense_and_batched(path):
     """Dense inputs (every count large) and a batch index."""
     nb, M, N, K = 3, 200, 150, 600
