@@ -276,13 +276,13 @@ def _ternary(stream, K, W, tuning_arg=None, quick=False):
     return res
 
 
-def _chain(stream, K, W):
-    """The chain workload: autotuned graph replay, its rooflines, the plain
-    path and the single persistent launch."""
+def _chain(stream, K, W, tuning_arg=None):
+    """The chain workload: autotuned (or given) graph replay, its rooflines,
+    the plain path and the single persistent launch."""
     import torch
     from paper_1609_00061_amd import inputs, pa
     s = inputs.config2()
-    tuning = _tuning(None, [s], stream)
+    tuning = _tuning(tuning_arg, [s], stream)
     plan = pa.Plan(s, order=pa.ORDER_EXHAUSTIVE, graph=True, **tuning)
     out = pa.empty_bits(plan.dims)
     torch.cuda.synchronize()
@@ -538,7 +538,7 @@ def main():
     stream = torch.cuda.Stream()
 
     if args.chain_only:
-        res = _chain(stream, K, W)
+        res = _chain(stream, K, W, args.tuning or None)
         res.pop("out"), res.pop("dims")
         _calibration_copy(args.calibration_copy_mib)
         print(json.dumps(res), flush=True)
