@@ -335,6 +335,18 @@ int32_t pa_plan_op_times(pa_plan *plan, double *ms, int32_t *kind, double *macs,
  * groups, or -1 (see pa_last_error). */
 int32_t pa_plan_time_groups(pa_plan *plan, int32_t reps, double *ms, int32_t *kind, double *macs, int32_t cap,
                             void *stream);
+/* Bound of each dependency wait of the single persistent launch
+ * (opts->single_launch), in polls of the producer step's done counter: 2^26
+ * by default (seconds of waiting; the waits end well before in any correct
+ * plan); a negative value makes every wait give up at its first poll.  A wait
+ * that gives up makes every workgroup leave the launch (the kernel ends
+ * normally, the output is incomplete), and the execute call that asks for a
+ * report (pa_plan_execute with rep, pa_batch_execute with a report) returns
+ * PA_EHIP, "persistent executor gave up a dependency wait".  For tests of that
+ * failure path.  Waits for every call in flight on the device, then writes
+ * the bound into the plan's device state (it holds for later executes).
+ * Returns PA_OK, PA_EINVAL (null plan) or PA_EHIP. */
+int pa_plan_set_wait_limit(pa_plan *plan, int64_t polls);
 
 /* ---------------------------------------------------------- batches
  * Many independent systems solved together: each is planned on its own, all
@@ -361,6 +373,8 @@ int32_t pa_batch_op_times(pa_batch *batch, double *ms, int32_t *kind, double *ma
 /* As pa_plan_time_groups, for the batch's merged step table. */
 int32_t pa_batch_time_groups(pa_batch *batch, int32_t reps, double *ms, int32_t *kind, double *macs, int32_t cap,
                              void *stream);
+/* As pa_plan_set_wait_limit, for the batch's single persistent launch. */
+int pa_batch_set_wait_limit(pa_batch *batch, int64_t polls);
 void pa_batch_destroy(pa_batch *batch);
 /* Solve n_sys independent systems: for each, the solution array on its
  * exposed variables, i.e. the generalized array multiplication of its

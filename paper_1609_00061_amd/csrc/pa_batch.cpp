@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstddef>
 #include <cstring>
 #include <limits>
 #include <memory>
@@ -258,6 +259,8 @@ extern "C" int pa_batch_create(const pa_system *systems, int32_t n_sys, const in
     if (rc) return rc;
     HIP_TRY(hipMemset(base + M.counters_off, 0, sizeof(PlotCounters) * (size_t)n_sys));
     HIP_TRY(hipMemset(base + M.state_off, 0, sizeof(PersistState)));
+    HIP_TRY(hipMemcpy(base + M.state_off + offsetof(PersistState, wait_limit), &kDefaultWaitLimit,
+                      sizeof(kDefaultWaitLimit), hipMemcpyHostToDevice));
     HIP_TRY(hipMemset(base + M.done_off, 0, sizeof(unsigned) * std::max<size_t>(1, nsteps)));
     if (opts && opts->timing == 2) {
         M.op_events.resize(M.single_launch ? 2 : std::max<size_t>(2, 2 * M.groups.size()));
@@ -354,6 +357,11 @@ extern "C" int32_t pa_batch_time_groups(pa_batch *B, int32_t reps, double *ms, i
                                         int32_t cap, void *stream) {
     if (!B) return fail(PA_EINVAL, "time_groups: null batch"), -1;
     return time_groups(&B->master, reps, ms, kind, macs, cap, static_cast<hipStream_t>(stream));
+}
+
+extern "C" int pa_batch_set_wait_limit(pa_batch *B, int64_t polls) {
+    if (!B) return fail(PA_EINVAL, "set_wait_limit: null batch");
+    return set_wait_limit(&B->master, polls);
 }
 
 extern "C" void pa_batch_destroy(pa_batch *B) { delete B; }

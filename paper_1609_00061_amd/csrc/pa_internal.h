@@ -152,7 +152,9 @@ struct GemmArgs {
                               // contraction's sparse pass when A is too dense for it
     int path;                 // operand path: 0 = K chunks staged in LDS, 128 x 128 tiles;
                               // 1 = waves load K chunks straight into registers (no LDS);
-                              // 2 = staged in LDS, 256 x 128 tiles (tiles_m counts 256 rows)
+                              // 2 = staged in LDS, 256 x 128 tiles (tiles_m counts 256 rows);
+                              // 3 = 256 x 128 tiles with A operands kept in registers across
+                              //     a workgroup's tiles (K <= 256 bits, no split)
     // divisions of the tile index (below 2^31) and of N coordinates by the
     // padded C row length in bits (below 2^31), checked on the host
     FastDiv fd_ksplit, fd_tiles_n, fd_tiles_m, fd_wc;
@@ -210,7 +212,10 @@ struct PersistState {
     unsigned long long queue;       // next work item
     unsigned int abort;             // set when a dependency wait exceeds its bound
     unsigned int pad;
+    long long wait_limit;           // polls per dependency wait (host-set; < 0: give up at once)
 };
+
+constexpr long long kDefaultWaitLimit = 1ll << 26;
 
 // Kernel launchers (pa_kernels.hip).  All return hipError_t of the launch.
 hipError_t launch_plot(const PlotRel *d_rels, int nrel, int64_t total_tiles, bool center, PlotCounters *d_counters,

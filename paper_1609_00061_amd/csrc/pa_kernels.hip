@@ -2552,13 +2552,13 @@ hipError_t launch_group(int kind, int mode, const PStep *d_steps, int first, int
 // finished (per-step done counters), then runs, then publishes.  Producers
 // always precede consumers in the item order and every taken item is being
 // run by a live workgroup, so the waits end; a bounded spin sets `abort`
-// and every workgroup leaves if a wait ever exceeds ~2^26 polls.
+// and every workgroup leaves if a wait ever exceeds state->wait_limit polls
+// (2^26 unless the host set another bound; a negative bound gives up at the
+// first wait, so that tests reach this path with every kernel exiting).
 // Coherence across XCDs: the publishing thread's agent-scope release (after
 // the workgroup barrier that orders the other waves' completed stores) writes
 // the XCD's L2 back; the waiting thread's agent-scope acquire, once, after the
 // relaxed polls succeed, invalidates the stale lines of its CU and XCD.
-constexpr long long kSpinLimit = 1ll << 26;
-
 __global__ __launch_bounds__(256) void k_persist(const PStep *__restrict__ steps, int nsteps, int64_t n_items,
                                                  PersistState *state, unsigned int *done,
                                                  PlotCounters *counters) {
@@ -2567,6 +2567,7 @@ __global__ __launch_bounds__(256) void k_persist(const PStep *__restrict__ steps
     __shared__ long long s_item;
     __shared__ int s_ok;
     CountSink sink;
+    const long long limit = __hip_atomic_load(&state->wait_limit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     for (;;) {
         if (threadIdx.x == 0)
             s_item = (long long)__hip_atomic_fetch_add(&state->queue, 1ull, __ATOMIC_RELAXED,
@@ -2579,13 +2580,17 @@ __global__ __launch_bounds__(256) void k_persist(const PStep *__restrict__ steps
         if (threadIdx.x == 0) {
             int ok = 1;
             const int nd = steps[si].ndep;
+            if (nd > 0 && limit < 0) {
+                __hip_atomic_store(&state->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ok = 0;
+            }
             for (int j = 0; j < nd && ok; ++j) {
                 const int d = steps[si].dep[j];
                 const unsigned need = (unsigned)steps[d].n_tiles;
                 long long spins = 0;
                 while (__hip_atomic_load(&done[d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
                     if (__hip_atomic_load(&state->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) { ok = 0; break; }
-                    if (++spins > kSpinLimit) {
+                    if (++spins > limit) {
                         __hip_atomic_store(&state->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                         ok = 0;
                         break;

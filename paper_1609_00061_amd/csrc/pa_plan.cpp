@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <utility>
 #include <chrono>
+#include <cstddef>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -1231,6 +1232,8 @@ int upload_plan(pa_plan *P) {
     // counters and executor state start at zero (plot counters only grow)
     HIP_TRY(hipMemset(base + P->counters_off, 0, sizeof(PlotCounters)));
     HIP_TRY(hipMemset(base + P->state_off, 0, sizeof(PersistState)));
+    HIP_TRY(hipMemcpy(base + P->state_off + offsetof(PersistState, wait_limit), &kDefaultWaitLimit,
+                      sizeof(kDefaultWaitLimit), hipMemcpyHostToDevice));
     HIP_TRY(hipMemset(base + P->done_off, 0, sizeof(unsigned) * std::max<size_t>(1, P->steps_host.size())));
     P->uploaded = true;
     return PA_OK;
@@ -1635,6 +1638,24 @@ extern "C" int32_t pa_plan_time_groups(pa_plan *P, int32_t reps, double *ms, int
 }
 
 extern "C" size_t pa_plan_workspace_bytes(const pa_plan *plan) { return plan ? plan->ws_bytes : 0; }
+
+namespace pa {
+// Writes the persistent executor's wait bound into the plan's device state,
+// after every call in flight on the device has finished.
+int set_wait_limit(pa_plan *P, int64_t polls) {
+    if (!P->ws.ptr) return fail(PA_EINVAL, "set_wait_limit: the plan has no device state");
+    const long long v = (long long)polls;
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipMemcpy(static_cast<char *>(P->ws.ptr) + P->state_off + offsetof(PersistState, wait_limit), &v,
+                      sizeof(v), hipMemcpyHostToDevice));
+    return PA_OK;
+}
+}  // namespace pa
+
+extern "C" int pa_plan_set_wait_limit(pa_plan *P, int64_t polls) {
+    if (!P) return fail(PA_EINVAL, "set_wait_limit: null plan");
+    return set_wait_limit(P, polls);
+}
 
 extern "C" void pa_plan_destroy(pa_plan *plan) { delete plan; }
 

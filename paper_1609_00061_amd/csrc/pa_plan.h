@@ -132,6 +132,7 @@ int plan_workspace_cap(size_t *cap);
 int measure_leaf_densities(const pa_system *systems, int32_t n_sys, const pa_opts &o,
                            std::vector<std::vector<double>> &ld);
 int time_groups(pa_plan *P, int32_t reps, double *ms, int32_t *kind, double *macs, int32_t cap, hipStream_t s);
+int set_wait_limit(pa_plan *P, int64_t polls);
 int autotuned_opts(const pa_system *systems, int32_t n_sys, const int32_t *const *exposed, const int32_t *n_exposed,
                    pa_opts &o);
 void make_groups(pa_plan *P);

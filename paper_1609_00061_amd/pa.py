@@ -175,6 +175,8 @@ def load(path: str = LIB_PATH):
         fn.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32),
                        ctypes.POINTER(ctypes.c_double), ctypes.c_int32, vp]
         fn.restype = ctypes.c_int32
+    for fn in (L.pa_plan_set_wait_limit, L.pa_batch_set_wait_limit):
+        fn.argtypes = [vp, ctypes.c_int64]
     L.pa_autotune.argtypes = [ctypes.POINTER(System), ctypes.c_int32, ctypes.POINTER(ctypes.POINTER(ctypes.c_int32)),
                               i32p, ctypes.POINTER(Opts), ctypes.c_int32, ctypes.POINTER(Tuning),
                               ctypes.POINTER(Tuning), ctypes.c_int32, i32p, vp]
@@ -443,6 +445,11 @@ class Plan:
         over `reps` back-to-back launches (plan executed at least once)."""
         return _time_groups(load().pa_plan_time_groups, self.handle, reps, stream)
 
+    def set_wait_limit(self, polls):
+        """Bound of the single persistent launch's dependency waits (negative:
+        give up at once; for tests of the failure path)."""
+        _check(load().pa_plan_set_wait_limit(self.handle, int(polls)))
+
     def __del__(self):
         try:
             if getattr(self, "handle", None) and _lib is not None:
@@ -509,6 +516,10 @@ class Batch:
 
     def time_groups(self, reps=20, stream=None):
         return _time_groups(load().pa_batch_time_groups, self.handle, reps, stream)
+
+    def set_wait_limit(self, polls):
+        """As Plan.set_wait_limit, for the batch's single persistent launch."""
+        _check(load().pa_batch_set_wait_limit(self.handle, int(polls)))
 
     def __del__(self):
         try:

@@ -137,3 +137,46 @@ def test_time_groups_leaves_output_exact():
     outs, _, _ = b.execute(stream=stream)
     assert len(b.time_groups(reps=3, stream=stream)) >= 3
     assert np.array_equal(to_host(outs[0], b.dims[0]), ref)
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_persistent_wait_gives_up_when_forced_from_the_host(graph):
+    """The single persistent launch's bounded dependency wait, made to give
+    up from the host (a negative bound: every wait gives up at its first
+    poll, every workgroup leaves, the kernel ends normally): the execute call
+    with a report returns PA_EHIP; with the default bound written back the
+    same plan (and graph) solves the system again, bit-exact."""
+    import torch
+    s = inputs.config2(res=128)
+    ref = _oracle_solve(s)
+    stream = torch.cuda.Stream()
+    plan = pa.Plan(s, single_launch=True, graph=graph)
+    out = pa.empty_bits(plan.dims)
+    note("forced wait give-up", s.name, "graph", graph)
+    plan.set_wait_limit(-1)
+    with pytest.raises(pa.PaError) as e:
+        plan.execute(out, stream=stream, report=True)
+    assert e.value.code == pa.PA_EHIP and "gave up a dependency wait" in str(e.value)
+    plan.set_wait_limit(1 << 26)
+    _, rep, _ = plan.execute(out, stream=stream, report=True)
+    assert np.array_equal(to_host(out, plan.dims), ref)
+    assert rep["nnz_out"] == int(ref.sum())
+
+
+def test_batch_persistent_wait_gives_up_when_forced_from_the_host():
+    """As above for a batch's single persistent launch (two chains)."""
+    import torch
+    systems = [inputs.config2(res=64), inputs.config2(res=96)]
+    refs = [_oracle_solve(s) for s in systems]
+    stream = torch.cuda.Stream()
+    b = pa.Batch(systems, single_launch=True)
+    outs = b.alloc_outputs()
+    note("forced wait give-up, batch")
+    b.set_wait_limit(-1)
+    with pytest.raises(pa.PaError) as e:
+        b.execute(outs, stream=stream, report=True)
+    assert e.value.code == pa.PA_EHIP
+    b.set_wait_limit(1 << 26)
+    b.execute(outs, stream=stream, report=True)
+    for o, d, ref in zip(outs, b.dims, refs):
+        assert np.array_equal(to_host(o, d), ref)

@@ -92,16 +92,24 @@ def test_planted_corner_roots():
 @pytest.mark.parametrize("which", ["c2", "c3"])
 def test_full_size_relations(which):
     """Every relation of the chain (1024^2) and ternary (256^3) workloads at
-    full size, FP32 with escalation, bit-exact."""
+    full size, FP32 with escalation, bit-exact; then again in audit mode
+    (every corner also evaluated in FP64): the same bits, the same escalated
+    corners, and every FP32/FP64 sign disagreement among them."""
     s = inputs.config2() if which == "c2" else inputs.config3()
-    flagged = 0
+    flagged = disagree = 0
     for rel in s.relations:
         axes = [s.axes[v] for v in rel.vars]
         got, rep = _plot(rel, axes, pa.PLOT_FP32_ESCALATE)
         ref, _ = oracle.plot(rel, s.axes)
         assert np.array_equal(got, ref), rel.vars
         flagged += rep["corners_flagged"]
-    note(which, "flagged corners", flagged)
+        got_a, rep_a = _plot(rel, axes, pa.PLOT_FP32_ESCALATE, audit=True)
+        assert np.array_equal(got_a, ref), rel.vars
+        assert rep_a["corners_disagree_unflagged"] == 0, rel.vars
+        assert rep_a["corners_disagree"] <= rep_a["corners_flagged"]
+        assert rep_a["corners_flagged"] == rep["corners_flagged"]
+        disagree += rep_a["corners_disagree"]
+    note(which, "flagged corners", flagged, "FP32/FP64 disagreements", disagree)
 
 
 EXTREMES = [
