@@ -219,7 +219,8 @@ extern "C" int pa_batch_create(const pa_system *systems, int32_t n_sys, const in
         return at;
     };
     M.steps_off = take(sizeof(PStep) * std::max<size_t>(1, nsteps));
-    M.done_off = take(sizeof(unsigned) * std::max<size_t>(1, nsteps));
+    M.pgroups_off = take(sizeof(PGroup) * std::max<size_t>(1, nsteps));
+    M.levels_off = take(2 * sizeof(int64_t) * std::max<size_t>(1, nsteps));
     M.state_off = take(sizeof(PersistState));
     M.counters_off = take(sizeof(PlotCounters) * (size_t)n_sys);   // one block per system
     M.popcnt_off = take(sizeof(unsigned long long) * (size_t)n_sys);
@@ -261,7 +262,8 @@ extern "C" int pa_batch_create(const pa_system *systems, int32_t n_sys, const in
     HIP_TRY(hipMemset(base + M.state_off, 0, sizeof(PersistState)));
     HIP_TRY(hipMemcpy(base + M.state_off + offsetof(PersistState, wait_limit), &kDefaultWaitLimit,
                       sizeof(kDefaultWaitLimit), hipMemcpyHostToDevice));
-    HIP_TRY(hipMemset(base + M.done_off, 0, sizeof(unsigned) * std::max<size_t>(1, nsteps)));
+    rc = upload_pgroups(&M);
+    if (rc) return rc;
     if (opts && opts->timing == 2) {
         M.op_events.resize(M.single_launch ? 2 : std::max<size_t>(2, 2 * M.groups.size()));
         for (auto &e : M.op_events) HIP_TRY(hipEventCreate(&e));

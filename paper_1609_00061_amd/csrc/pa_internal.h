@@ -217,6 +217,14 @@ struct PersistState {
 
 constexpr long long kDefaultWaitLimit = 1ll << 26;
 
+// One group of the persistent launch: steps first .. first + count - 1 of
+// one kind and mode at one dependency level, items [t0, t1), run in chunks
+// of `chunk` items; its chunks are numbered from cbase in the launch.
+struct PGroup {
+    int kind, mode, first, count, level, pad;
+    int64_t t0, t1, chunk, cbase;
+};
+
 // Kernel launchers (pa_kernels.hip).  All return hipError_t of the launch.
 hipError_t launch_plot(const PlotRel *d_rels, int nrel, int64_t total_tiles, bool center, PlotCounters *d_counters,
                        hipStream_t s);
@@ -240,9 +248,13 @@ hipError_t launch_fill(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
 hipError_t launch_popcount(const uint32_t *p, int64_t n, unsigned long long *out, hipStream_t s);
 hipError_t launch_tile_popcount(const uint32_t *p, int64_t rows, int64_t rw, int tile_rows, int tile_words,
                                 uint32_t *out, hipStream_t s);
-hipError_t launch_persist(const PStep *d_steps, int nsteps, int64_t n_items, PersistState *state,
-                          unsigned int *done, PlotCounters *counters, int n_workgroups, hipStream_t s);
-hipError_t launch_persist_reset(PersistState *state, unsigned int *done, int nsteps, hipStream_t s);
+// The single persistent launch: chunks of the groups (table of ngroups
+// entries, nchunks chunks in all), level_items[L] items in level L,
+// level_done[L] counts the done ones (reset by launch_persist_reset).
+hipError_t launch_persist(const PStep *d_steps, const PGroup *d_groups, int ngroups, int64_t nchunks,
+                          const int64_t *level_items, unsigned long long *level_done, PersistState *state,
+                          PlotCounters *counters, int n_workgroups, hipStream_t s);
+hipError_t launch_persist_reset(PersistState *state, unsigned long long *level_done, int nlevels, hipStream_t s);
 // Steps first..first+count-1 (tiles t0..t1-1) of one kind and mode (plots:
 // mode 1 = centre rule); flags: some of the MFMA contractions among them have
 // a sparse pass (and may be skipped).

@@ -1664,15 +1664,15 @@ constexpr int kResGroup = 8;                     // column tiles per output grou
 constexpr int kResPitch = 4 * kResGroup + 4;     // LDS words per staged output row (16-byte aligned rows)
 constexpr int kResLdsWords = 2 * kTile * kPitch + 256 * kResPitch;
 
-// Contiguous item range [lo, hi) of this workgroup among n items: the
-// XCD-aware split (workgroups go to the 8 XCDs round-robin; XCD x owns items
-// [x per, (x + 1) per), shared evenly by its workgroups).
-__device__ __forceinline__ void res_range(int64_t n, int64_t &lo, int64_t &hi) {
+// Contiguous item range [lo, hi) of workgroup bid of nbid among n items:
+// the XCD-aware split (workgroups go to the 8 XCDs round-robin; XCD x owns
+// items [x per, (x + 1) per), shared evenly by its workgroups).
+__device__ __forceinline__ void res_range(int64_t n, int64_t &lo, int64_t &hi, uint32_t bid, uint32_t nbid) {
     const int64_t per = (n + 7) >> 3;
-    const int64_t nwg = ((int64_t)gridDim.x + 7 - (blockIdx.x & 7)) >> 3;   // workgroups on this XCD
-    const int64_t k = blockIdx.x >> 3, span = (per + nwg - 1) / nwg;
-    lo = min(n, (int64_t)(blockIdx.x & 7) * per + k * span);
-    hi = min(min(n, (int64_t)((blockIdx.x & 7) + 1) * per), lo + span);
+    const int64_t nwg = ((int64_t)nbid + 7 - (bid & 7)) >> 3;   // workgroups on this XCD
+    const int64_t k = bid >> 3, span = (per + nwg - 1) / nwg;
+    lo = min(n, (int64_t)(bid & 7) * per + k * span);
+    hi = min(min(n, (int64_t)((bid & 7) + 1) * per), lo + span);
 }
 
 // Epilogue into the LDS output group: for each row block i the lane halves
@@ -1830,7 +1830,7 @@ __global__ __launch_bounds__(256, gemm_occupancy(PATH)) void k_gemm_mfma(GemmArg
     const int64_t ntiles = g.nbatch * g.tiles_m * g.tiles_n * g.ksplit;
     if constexpr (PATH == 3) {
         int64_t t, tend;
-        res_range(ntiles, t, tend);
+        res_range(ntiles, t, tend, blockIdx.x, gridDim.x);
         auto next = [&](GemmTileRef &T) {
             if (t >= tend) return false;
             T = gemm_locate<4>(g, t++);
@@ -2329,48 +2329,21 @@ __device__ __forceinline__ int find_step(const PStep *steps, int first, int coun
     return lo;
 }
 
-__device__ __forceinline__ void run_tile(const PStep &st, int64_t tile, uint32_t *lds, PlotCount &cnt) {
-    switch (st.kind) {
-        case kStepPlot:
-            plot_tile(st.plot, tile, reinterpret_cast<float *>(lds), reinterpret_cast<double *>(lds + kPlotLineWords),
-                      cnt);
-            break;
-        case kStepGemm: {
-            bool once = true;
-            // the persistent executor runs 128 x 128 tiles only (operand
-            // paths 0 and 1; plans for it never use path 2)
-            auto next = [&](GemmTileRef &T) {
-                if (!once) return false;
-                T = gemm_locate<2>(st.gemm, tile);
-                once = false;
-                return true;
-            };
-            if (st.gemm.path == 1) gemm_run<1>(next, lds);
-            else gemm_run<0>(next, lds);
-            break;
-        }
-        case kStepContract: {
-            const int64_t u0 = tile * st.per_tile;
-            contract_range_any(st.ca, st.mode, u0, min(st.units, u0 + st.per_tile));
-            break;
-        }
-        default: {
-            const int64_t u0 = tile * st.per_tile, u1 = min(st.units, u0 + st.per_tile);
-            for (int64_t i = u0 + threadIdx.x; i < u1; i += blockDim.x) gp(st.fill_ptr)[i] = 0u;
-            break;
-        }
-    }
+// LDS words of a grouped kernel of kind KIND % 10, mode KIND / 10
+template <int KIND>
+constexpr int group_lds_words() {
+    return KIND % 10 == kStepGemm ? gemm_lds_of(KIND / 10) : (KIND % 10 == kStepPlot ? kPlotLdsWords : 1);
 }
 
-// KIND: a StepKind; for contractions the mode is fixed too (kind 2 + 10 * mode).
+// Items [t0, t1) of steps first .. first + count - 1 (one group: the same
+// kind and mode), as workgroup bid of nbid runs its share of them.  KIND:
+// a StepKind; for MFMA contractions and contractions the mode is fixed too
+// (kind + 10 * mode).  lds holds group_lds_words<KIND>() words.
 template <int KIND>
-__global__ __launch_bounds__(256, KIND % 10 == kStepGemm ? gemm_occupancy(KIND / 10) : 1) void k_group(
-    const PStep *__restrict__ steps, int first, int count, int64_t t0, int64_t t1, int flags,
-    PlotCounters *counters) {
+__device__ __forceinline__ void group_run(const PStep *__restrict__ steps, int first, int count, int64_t t0,
+                                          int64_t t1, int flags, PlotCounters *counters, uint32_t *lds,
+                                          uint32_t bid, uint32_t nbid) {
     constexpr int kind = KIND % 10, mode = KIND / 10;
-    // MFMA contractions: the mode is the operand path
-    constexpr int kWords = kind == kStepGemm ? gemm_lds_of(mode) : (kind == kStepPlot ? kPlotLdsWords : 1);
-    __shared__ __attribute__((aligned(16))) uint32_t lds[kWords];
     if (kind == kStepGemm) {
         // with `flags`, a contraction whose sparse pass handled every row is
         // skipped: lane i reads the flag of step first + i (at most 64 steps;
@@ -2390,7 +2363,7 @@ __global__ __launch_bounds__(256, KIND % 10 == kStepGemm ? gemm_occupancy(KIND /
             // run one step at a time with a uniform copy of the step's
             // arguments (scalar registers, scalar tile decoding)
             int64_t lo, hi;
-            res_range(t1 - t0, lo, hi);
+            res_range(t1 - t0, lo, hi, bid, nbid);
             int64_t item = t0 + lo;
             const int64_t iend = t0 + hi;
             while (item < iend) {
@@ -2422,16 +2395,16 @@ __global__ __launch_bounds__(256, KIND % 10 == kStepGemm ? gemm_occupancy(KIND /
         }
         // persistent tile loop with cross-tile prefetch, tiles in XCD-aware order
         const int64_t per = (t1 - t0 + 7) >> 3;
-        int64_t t = blockIdx.x;
+        int64_t t = bid;
         auto next = [&](GemmTileRef &T) {
-            for (; t < 8 * per; t += gridDim.x) {
+            for (; t < 8 * per; t += nbid) {
                 const int64_t item = t0 + xcd_tile(t, per);
                 if (item < t1) {
                     const int si = find_step(steps, first, count, item);
                     if (!((active >> ((si - first) & 63)) & 1)) continue;
                     const PStep &st = steps[si];
                     T = gemm_locate<mode == 2 ? 4 : 2>(st.gemm, item - st.tile_base);
-                    t += gridDim.x;
+                    t += nbid;
                     return true;
                 }
             }
@@ -2447,7 +2420,7 @@ __global__ __launch_bounds__(256, KIND % 10 == kStepGemm ? gemm_occupancy(KIND /
         // decision word) and starts the loads of its next tile's A row
         // before working on the current one
         const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-        const int64_t slots = (t1 - t0) * 4, stride = (int64_t)gridDim.x * 4;
+        const int64_t slots = (t1 - t0) * 4, stride = (int64_t)nbid * 4;
         int si = -1;
         int64_t wt = 0;
         // the first slot at or after gi holding a wave-tile (slots if none)
@@ -2460,7 +2433,7 @@ __global__ __launch_bounds__(256, KIND % 10 == kStepGemm ? gemm_occupancy(KIND /
             }
             return gi;
         };
-        int64_t gi = seek((int64_t)blockIdx.x * 4 + wave);
+        int64_t gi = seek((int64_t)bid * 4 + wave);
         RowBits rb;
         if (gi < slots) rb = gather_row_issue(steps[si].gather, wt);
         int decided = -1;
@@ -2481,7 +2454,7 @@ __global__ __launch_bounds__(256, KIND % 10 == kStepGemm ? gemm_occupancy(KIND /
         return;
     }
     CountSink sink;
-    for (int64_t item = t0 + blockIdx.x; item < t1; item += gridDim.x) {
+    for (int64_t item = t0 + bid; item < t1; item += nbid) {
         const PStep &st = steps[find_step(steps, first, count, item)];
         if (kind == kStepPlot && st.kind == kStepPlot) {
             sink.use(st.plot, counters);
@@ -2499,6 +2472,22 @@ __global__ __launch_bounds__(256, KIND % 10 == kStepGemm ? gemm_occupancy(KIND /
         __syncthreads();
     }
     if (kind == kStepPlot) sink.finish();
+}
+
+
+// Minimum waves per SIMD of a grouped kernel: the MFMA paths' own, else
+// left to the compiler.
+template <int KIND>
+constexpr int group_occupancy() {
+    return KIND % 10 == kStepGemm ? gemm_occupancy(KIND / 10) : 1;
+}
+
+template <int KIND>
+__global__ __launch_bounds__(256, group_occupancy<KIND>()) void k_group(
+    const PStep *__restrict__ steps, int first, int count, int64_t t0, int64_t t1, int flags,
+    PlotCounters *counters) {
+    __shared__ __attribute__((aligned(16))) uint32_t lds[group_lds_words<KIND>()];
+    group_run<KIND>(steps, first, count, t0, t1, flags, counters, lds, blockIdx.x, gridDim.x);
 }
 
 // Workgroups of the persistent sparse-pass loop: every CU's worth.
@@ -2547,81 +2536,112 @@ hipError_t launch_group(int kind, int mode, const PStep *d_steps, int first, int
 }
 
 // ------------------------------------------------- persistent executor
-// Every workgroup takes work items (tiles) from a global counter, in step
-// order; a tile first waits until every tile of its step's producer steps has
-// finished (per-step done counters), then runs, then publishes.  Producers
-// always precede consumers in the item order and every taken item is being
-// run by a live workgroup, so the waits end; a bounded spin sets `abort`
-// and every workgroup leaves if a wait ever exceeds state->wait_limit polls
-// (2^26 unless the host set another bound; a negative bound gives up at the
-// first wait, so that tests reach this path with every kernel exiting).
-// Coherence across XCDs: the publishing thread's agent-scope release (after
-// the workgroup barrier that orders the other waves' completed stores) writes
-// the XCD's L2 back; the waiting thread's agent-scope acquire, once, after the
-// relaxed polls succeed, invalidates the stale lines of its CU and XCD.
-__global__ __launch_bounds__(256) void k_persist(const PStep *__restrict__ steps, int nsteps, int64_t n_items,
-                                                 PersistState *state, unsigned int *done,
-                                                 PlotCounters *counters) {
-    __shared__ __attribute__((aligned(16))) uint32_t lds[kGemmLdsWords > kPlotLdsWords ? kGemmLdsWords
-                                                                                       : kPlotLdsWords];
-    __shared__ long long s_item;
+// One launch runs the whole step table.  The grouped executor's launches
+// become chunks of work: chunk c of group g is items t0 + c chunk .. of that
+// group (at most `chunk` of them), run by one workgroup with the grouped
+// kernel's own tile loop (group_run).  Workgroups take chunks from one
+// counter in table order, i.e. by ascending dependency level.  Before its
+// first chunk of a level L > 0 a workgroup waits until every item of level
+// L - 1 is done (one done counter per level): every step depends on lower
+// levels only, the levels finish in order, and every chunk of a lower level
+// was taken earlier by a running workgroup, so the waits end whether or not
+// all workgroups are resident at once.  A wait is bounded by
+// state->wait_limit polls (2^26 unless the host set another bound; a
+// negative bound gives up at the first wait, so that tests reach this path
+// with every kernel exiting): then `abort` is set and every workgroup leaves.
+// Coherence across XCDs: after a chunk, the workgroup barrier orders its
+// waves' stores and one thread's agent-scope release (the done-count add)
+// writes them back from the XCD's L2; the waiting thread's agent-scope
+// acquire, once its polls succeed, invalidates the stale lines of its CU and
+// XCD before the workgroup reads the level's inputs.
+constexpr int kPersistLdsWords = kGemmLdsWords > kPlotLdsWords ? kGemmLdsWords : kPlotLdsWords;
+
+__global__ __launch_bounds__(256, 2) void k_persist(const PStep *__restrict__ steps,
+                                                    const PGroup *__restrict__ groups, int ngroups,
+                                                    int64_t nchunks, const int64_t *__restrict__ level_items,
+                                                    unsigned long long *level_done, PersistState *state,
+                                                    PlotCounters *counters) {
+    __shared__ __attribute__((aligned(16))) uint32_t lds[kPersistLdsWords];
+    __shared__ long long s_chunk;
     __shared__ int s_ok;
-    CountSink sink;
     const long long limit = __hip_atomic_load(&state->wait_limit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int known = -1;       // levels up to `known` are complete (uniform)
     for (;;) {
         if (threadIdx.x == 0)
-            s_item = (long long)__hip_atomic_fetch_add(&state->queue, 1ull, __ATOMIC_RELAXED,
+            s_chunk = (long long)__hip_atomic_fetch_add(&state->queue, 1ull, __ATOMIC_RELAXED,
                                                         __HIP_MEMORY_SCOPE_AGENT);
         __syncthreads();
-        const int64_t item = s_item;
-        if (item >= n_items) break;
-        const int si = find_step(steps, 0, nsteps, item);
-        const int64_t tile = item - steps[si].tile_base;
-        if (threadIdx.x == 0) {
-            int ok = 1;
-            const int nd = steps[si].ndep;
-            if (nd > 0 && limit < 0) {
-                __hip_atomic_store(&state->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                ok = 0;
-            }
-            for (int j = 0; j < nd && ok; ++j) {
-                const int d = steps[si].dep[j];
-                const unsigned need = (unsigned)steps[d].n_tiles;
-                long long spins = 0;
-                while (__hip_atomic_load(&done[d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
-                    if (__hip_atomic_load(&state->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) { ok = 0; break; }
-                    if (++spins > limit) {
-                        __hip_atomic_store(&state->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        ok = 0;
-                        break;
-                    }
-                    __builtin_amdgcn_s_sleep(2);
-                }
-            }
-            if (nd > 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            s_ok = ok;
+        const int64_t c = s_chunk;
+        if (c >= nchunks) break;
+        // the group of chunk c: a scalar binary search over the chunk bases
+        int gi = 0, gh = ngroups - 1;
+        while (gi < gh) {
+            const int mid = (gi + gh + 1) >> 1;
+            if (gp(groups)[mid].cbase <= c) gi = mid;
+            else gh = mid - 1;
         }
-        __syncthreads();
-        if (!s_ok) break;
-        if (steps[si].kind == kStepPlot) sink.use(steps[si].plot, counters);
-        run_tile(steps[si], tile, lds, sink.cnt);
+        gi = __builtin_amdgcn_readfirstlane(gi);
+        const PA_G PGroup *g = gp(groups) + gi;
+        const int level = g->level;
+        if (level > 0 && known < level - 1) {
+            if (threadIdx.x == 0) {
+                int ok = 1;
+                const unsigned long long need = (unsigned long long)gp(level_items)[level - 1];
+                long long spins = 0;
+                if (limit < 0) ok = 0;
+                while (ok && __hip_atomic_load(&level_done[level - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
+                                 need) {
+                    if (__hip_atomic_load(&state->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) ok = 0;
+                    else if (++spins > limit) ok = 0;
+                    else __builtin_amdgcn_s_sleep(1);
+                }
+                if (!ok) __hip_atomic_store(&state->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                s_ok = ok;
+            }
+            __syncthreads();
+            if (!s_ok) break;
+            known = level - 1;
+        }
+        const int64_t i0 = g->t0 + (c - g->cbase) * g->chunk;
+        const int64_t i1 = min(g->t1, i0 + g->chunk);
+        const int first = g->first, count = g->count;
+        switch (g->kind + 10 * g->mode) {
+            case kStepPlot: group_run<kStepPlot>(steps, first, count, i0, i1, 0, counters, lds, 0u, 1u); break;
+            case kStepGemm: group_run<kStepGemm>(steps, first, count, i0, i1, 0, counters, lds, 0u, 1u); break;
+            case kStepGemm + 10:
+                group_run<kStepGemm + 10>(steps, first, count, i0, i1, 0, counters, lds, 0u, 1u);
+                break;
+            case kStepContract + 10 * kModeStreamK:
+                group_run<kStepContract + 10 * kModeStreamK>(steps, first, count, i0, i1, 0, counters, lds, 0u, 1u);
+                break;
+            case kStepContract + 10 * kModeStreamW:
+                group_run<kStepContract + 10 * kModeStreamW>(steps, first, count, i0, i1, 0, counters, lds, 0u, 1u);
+                break;
+            case kStepContract + 10 * kModeBits:
+                group_run<kStepContract + 10 * kModeBits>(steps, first, count, i0, i1, 0, counters, lds, 0u, 1u);
+                break;
+            default: group_run<kStepFill>(steps, first, count, i0, i1, 0, counters, lds, 0u, 1u); break;
+        }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         __syncthreads();
-        if (threadIdx.x == 0) __hip_atomic_fetch_add(&done[si], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        if (threadIdx.x == 0)
+            __hip_atomic_fetch_add(&level_done[level], (unsigned long long)(i1 - i0), __ATOMIC_RELEASE,
+                                   __HIP_MEMORY_SCOPE_AGENT);
     }
-    sink.finish();
 }
 
-__global__ void k_persist_reset(PersistState *state, unsigned int *done, int nsteps) {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nsteps; i += gridDim.x * blockDim.x) done[i] = 0u;
+__global__ void k_persist_reset(PersistState *state, unsigned long long *level_done, int nlevels) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nlevels; i += gridDim.x * blockDim.x) level_done[i] = 0ull;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         state->queue = 0ull;
         state->abort = 0u;
     }
 }
 
-hipError_t launch_persist_reset(PersistState *state, unsigned int *done, int nsteps, hipStream_t s) {
-    hipLaunchKernelGGL(k_persist_reset, grid_for(nsteps > 0 ? nsteps : 1), dim3(256), 0, s, state, done, nsteps);
+hipError_t launch_persist_reset(PersistState *state, unsigned long long *level_done, int nlevels, hipStream_t s) {
+    hipLaunchKernelGGL(k_persist_reset, grid_for(nlevels > 0 ? nlevels : 1), dim3(256), 0, s, state, level_done,
+                       nlevels);
     return hipGetLastError();
 }
 
@@ -2636,11 +2656,12 @@ int persist_default_workgroups() {
     return cached;
 }
 
-hipError_t launch_persist(const PStep *d_steps, int nsteps, int64_t n_items, PersistState *state,
-                          unsigned int *done, PlotCounters *counters, int n_workgroups, hipStream_t s) {
-    if (n_items <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_persist, dim3((unsigned)n_workgroups), dim3(256), 0, s, d_steps, nsteps, n_items, state,
-                       done, counters);
+hipError_t launch_persist(const PStep *d_steps, const PGroup *d_groups, int ngroups, int64_t nchunks,
+                          const int64_t *level_items, unsigned long long *level_done, PersistState *state,
+                          PlotCounters *counters, int n_workgroups, hipStream_t s) {
+    if (nchunks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_persist, dim3((unsigned)n_workgroups), dim3(256), 0, s, d_steps, d_groups, ngroups, nchunks,
+                       level_items, level_done, state, counters);
     return hipGetLastError();
 }
 

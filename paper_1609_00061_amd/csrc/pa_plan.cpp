@@ -891,7 +891,8 @@ int build_plan(const pa_system *sys, const int32_t *exposed, int32_t n_exposed, 
     P->counters_off = take(sizeof(PlotCounters));
     P->popcnt_off = take(64);
     P->steps_off = take(sizeof(PStep) * std::max<size_t>(1, nsteps));
-    P->done_off = take(sizeof(unsigned) * std::max<size_t>(1, nsteps));
+    P->pgroups_off = take(sizeof(PGroup) * std::max<size_t>(1, nsteps));
+    P->levels_off = take(2 * sizeof(int64_t) * std::max<size_t>(1, nsteps));
     P->state_off = take(sizeof(PersistState));
     int64_t corners = 0;     // points evaluated: corners, or centres under the centre rule
     for (const auto &it : P->plots) {
@@ -1192,6 +1193,43 @@ void make_groups(pa_plan *P) {
     }
 }
 
+int persist_default_workgroups();
+
+int upload_pgroups(pa_plan *P) {
+    const int64_t wg = std::max<int64_t>(1, P->persist_wg > 0 ? P->persist_wg : persist_default_workgroups());
+    std::vector<PGroup> pg;
+    std::vector<int64_t> lv;          // items per level, then (zeroed) done counters
+    int64_t cbase = 0;
+    int nlev = 0;
+    for (const auto &g : P->groups) {
+        PGroup x;
+        std::memset(&x, 0, sizeof(x));
+        x.kind = g.kind;
+        x.mode = g.mode;
+        x.first = g.first;
+        x.count = g.count;
+        x.level = P->step_level[g.first];
+        x.t0 = g.t0;
+        x.t1 = g.t1;
+        const int64_t n = g.t1 - g.t0;
+        x.chunk = std::max<int64_t>(1, (n + wg - 1) / wg);
+        x.cbase = cbase;
+        cbase += (n + x.chunk - 1) / x.chunk;
+        nlev = std::max(nlev, x.level + 1);
+        if ((int)lv.size() < nlev) lv.resize(nlev, 0);
+        lv[x.level] += n;
+        pg.push_back(x);
+    }
+    P->n_pgroups = (int)pg.size();
+    P->n_levels = nlev;
+    P->n_chunks = cbase;
+    lv.resize(2 * std::max(1, nlev), 0);
+    char *base = static_cast<char *>(P->ws.ptr);
+    if (!pg.empty()) HIP_TRY(hipMemcpy(base + P->pgroups_off, pg.data(), pg.size() * sizeof(PGroup), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(base + P->levels_off, lv.data(), lv.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+    return PA_OK;
+}
+
 static void patch_outputs(pa_plan *P, const std::vector<void *> &outs) {
     for (const auto &ref : P->step_out_refs) {
         PStep &s = P->steps_host[ref.first];
@@ -1234,7 +1272,8 @@ int upload_plan(pa_plan *P) {
     HIP_TRY(hipMemset(base + P->state_off, 0, sizeof(PersistState)));
     HIP_TRY(hipMemcpy(base + P->state_off + offsetof(PersistState, wait_limit), &kDefaultWaitLimit,
                       sizeof(kDefaultWaitLimit), hipMemcpyHostToDevice));
-    HIP_TRY(hipMemset(base + P->done_off, 0, sizeof(unsigned) * std::max<size_t>(1, P->steps_host.size())));
+    rc = upload_pgroups(P);
+    if (rc) return rc;
     P->uploaded = true;
     return PA_OK;
 }
@@ -1314,19 +1353,18 @@ static int run_plots(pa_plan *P, hipStream_t s, int *launches) {
     return PA_OK;
 }
 
-int persist_default_workgroups();
-
 static int run_persist(pa_plan *P, hipStream_t s, int *launches, hipEvent_t before = nullptr) {
     char *base = static_cast<char *>(P->ws.ptr);
     PersistState *state = reinterpret_cast<PersistState *>(base + P->state_off);
-    unsigned *done = reinterpret_cast<unsigned *>(base + P->done_off);
+    const int64_t *level_items = reinterpret_cast<const int64_t *>(base + P->levels_off);
+    unsigned long long *level_done =
+        reinterpret_cast<unsigned long long *>(base + P->levels_off) + std::max(1, P->n_levels);
     PlotCounters *cnt = reinterpret_cast<PlotCounters *>(base + P->counters_off);
-    const int nsteps = (int)P->steps_host.size();
     int64_t wg = P->persist_wg > 0 ? P->persist_wg : persist_default_workgroups();
-    wg = std::max<int64_t>(1, std::min<int64_t>(wg, P->n_items));
+    wg = std::max<int64_t>(1, std::min<int64_t>(wg, P->n_chunks));
     // the plot counters only ever grow (a report takes the difference of
     // two reads), so the grouped executor needs no reset launch
-    if (P->single_launch) HIP_TRY(launch_persist_reset(state, done, nsteps, s));
+    if (P->single_launch) HIP_TRY(launch_persist_reset(state, level_done, P->n_levels, s));
     if (before) HIP_TRY(hipEventRecord(before, s));
     const PStep *d_steps = reinterpret_cast<const PStep *>(base + P->steps_off);
     if (P->single_launch) {
@@ -1335,7 +1373,8 @@ static int run_persist(pa_plan *P, hipStream_t s, int *launches, hipEvent_t befo
                 st.kind == kStepCount || (st.kind == kStepPlot && st.plot.rule != kRuleCorner))
                 return fail(PA_EINVAL,
                             "internal: 256-row MFMA tiles, a sparse pass or a centre plot in a single persistent launch");
-        HIP_TRY(launch_persist(d_steps, nsteps, P->n_items, state, done, cnt, (int)wg, s));
+        HIP_TRY(launch_persist(d_steps, reinterpret_cast<const PGroup *>(base + P->pgroups_off), P->n_pgroups,
+                               P->n_chunks, level_items, level_done, state, cnt, (int)wg, s));
         *launches += 2;
     } else {
         const bool ev = P->op_events.size() == 2 * P->groups.size() && before;

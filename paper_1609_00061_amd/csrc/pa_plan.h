@@ -136,6 +136,10 @@ int set_wait_limit(pa_plan *P, int64_t polls);
 int autotuned_opts(const pa_system *systems, int32_t n_sys, const int32_t *const *exposed, const int32_t *n_exposed,
                    pa_opts &o);
 void make_groups(pa_plan *P);
+// The single persistent launch's tables from the groups: chunk sizes (about
+// one chunk per workgroup and group), chunk bases, items per level; written
+// to the workspace.
+int upload_pgroups(pa_plan *P);
 struct ContractLayouts {
     std::vector<int64_t> res;          // length per variable label (-1: unused)
     std::vector<int> av, bv, ov;       // variables of A, B and the output
@@ -159,7 +163,7 @@ struct pa_plan {
     std::vector<pa::Layout> buf_layout;
     size_t tables_off = 0, tables_bytes = 0, ws_bytes = 0;
     size_t plotrel_off = 0, plotrel1_off = 0, counters_off = 0, popcnt_off = 0;
-    size_t steps_off = 0, done_off = 0, state_off = 0;
+    size_t steps_off = 0, pgroups_off = 0, levels_off = 0, state_off = 0;
     std::vector<pa::PlotRel> plotrel_host;    // records with prefix tile bases (fused launch)
     std::vector<pa::PlotRel> plotrel1_dev;    // device-pointer records with zero tile bases
     std::vector<pa::PStep> steps_host;        // persistent executor (device pointers, output patched)
@@ -174,6 +178,10 @@ struct pa_plan {
         int flags;         // MFMA steps of the group that follow a sparse pass
     };
     std::vector<Group> groups;                // level-synchronous executor
+    // the single persistent launch's group table (device, at pgroups_off),
+    // and per level its item count then its done counter (at levels_off)
+    int n_pgroups = 0, n_levels = 0;
+    int64_t n_chunks = 0;
     std::vector<double> step_macs;            // per sorted step (0 for plots and fills)
     std::vector<void *> last_outs;
     hipGraph_t graph_h = nullptr;
