@@ -36,6 +36,8 @@ FP4_DENSE_PEAK_TOPS = 10100.0      # MI355X dense fp4 MFMA, 10.1 PFLOP/s (the Bo
 INT8_DENSE_PEAK_TOPS = 5000.0      # MI355X dense int8 MFMA, 5.0 POP/s (for comparison only)
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 HBM_PEAK_GBS = 8000.0
+# LDS read bandwidth: 128 bytes per clock per CU, 256 CUs at 2.4 GHz
+LDS_PEAK_GBS = 128 * 256 * 2.4
 METRIC = "pixel-array solves/sec + bool-contraction TOPS vs plain GPU path, bit-exact"
 TERNARY = ("4 random trivariate cubics over 6 variables (every pair sharing one), N(0,1) coefficients "
            "(seed 160900061), [-3,3]^6 at 256 cells/axis, (v1, v4) exposed, 4 latent")
@@ -117,13 +119,39 @@ def _measured_traffic(name):
     return {k: v["hbm_bytes_per_launch"] for k, v in t.get("kernels", {}).items()}
 
 
+def _set_bits(system, rel):
+    """Set cells of a relation's plot (on the device; counted with a byte
+    table on the host)."""
+    import numpy as np
+    from paper_1609_00061_amd import pa
+    r = system.relations[rel]
+    t, dims, _ = pa.plot_relation(r, [system.axes[v] for v in r.vars])
+    table = np.array([bin(i).count("1") for i in range(256)], dtype=np.int64)
+    return int(table[t.cpu().numpy().view(np.uint8)].sum())
+
+
 def _work_of(system, d):
     """Algorithmic work per op of a plan description: bytes for the HBM-bound
     kernels (streamed operands; sparse-pass output words written plus A and the
-    second plot of B read once), Boolean ops (2 per MAC) for MFMA contractions."""
+    second plot of B read once; row lists: A read, heads and meta words
+    written), Boolean ops (2 per MAC) for MFMA contractions, and for a fused
+    pass pair the LDS bytes it gathers (one 256-byte row per set bit of an A
+    row and 8-wide block of the other output variable)."""
     words = [b["words"] for b in d["buffers"]]
-    out = {"stream_bytes": 0.0, "sparse_bytes": 0.0, "gemm_ops": 0.0, "sparse_macs": 0.0}
+    out = {"stream_bytes": 0.0, "sparse_bytes": 0.0, "gemm_ops": 0.0, "sparse_macs": 0.0, "list_bytes": 0.0,
+           "fused_lds_bytes": 0.0, "fused_macs": 0.0}
+    rel_of_buf = {p["buf"]: p["rel"] for p in d["plots"]}
+    lists = [o for o in d["ops"] if o["op"] == "row_list"]
     for o in d["ops"]:
+        if o["op"] == "row_list":
+            groups = o["rows"] // 8
+            out["list_bytes"] += 4.0 * (words[o["a"]] + groups * (32 + 16))
+        elif o["op"] == "fused_pass_pair":
+            lx = [l for l in lists if l["c"] == o["lists"] and l["lbase"] == 0][0]
+            ly = [l for l in lists if l["c"] == o["lists"] and l["lbase"] == o["kx"]][0]
+            bx, by = _set_bits(system, rel_of_buf[lx["a"]]), _set_bits(system, rel_of_buf[ly["a"]])
+            out["fused_lds_bytes"] += 256.0 * (bx * ((o["n_p"] + 7) // 8) + by * ((o["n_q"] + 7) // 8))
+            out["fused_macs"] += o["dense_macs"]
         if o["op"] in ("stream_k", "stream_w"):
             out["stream_bytes"] += 4.0 * (words[o["a"]] + (words[o["b"]] if o["b"] >= 0 else 0))
         elif o["op"] == "sparse_pass":
@@ -153,7 +181,9 @@ def _rooflines(plan, system, d, stream, reps, traffic):
              pa.OPKIND_GEMM: ("gemm", "k_group<1|11|21|31> (fp4-MFMA Boolean contraction tiles)", "mfma"),
              pa.OPKIND_STREAM_K: ("stream", "k_group<12> (word-streamed contraction)", "hbm"),
              pa.OPKIND_STREAM_W: ("stream_w", "k_group<22> (word-streamed contraction, broadcast)", "hbm"),
-             pa.OPKIND_COUNT: ("count", "k_group<5> (set-bit count of A)", None)}
+             pa.OPKIND_COUNT: ("count", "k_group<5> (set-bit count of A)", None),
+             pa.OPKIND_ROWLIST: ("row_list", "k_group<6> (row lists of the set bits of A)", "hbm"),
+             pa.OPKIND_FUSED: ("fused", "k_fused_group (fused pass pair: LDS row gathers)", "lds")}
     roof = {}
     for kind, a in by.items():
         if kind not in names:
@@ -180,6 +210,15 @@ def _rooflines(plan, system, d, stream, reps, traffic):
             ach = b / (avg * 1e-3) / 1e9
             ent.update(achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS, bytes_per_launch=b,
                        effective_tops=2.0 * w["sparse_macs"] / (a["ms"] * 1e-3) / 1e12)
+        elif kind == pa.OPKIND_ROWLIST:
+            b = w["list_bytes"] / a["launches"]
+            ach = b / (avg * 1e-3) / 1e9
+            ent.update(achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS, bytes_per_launch=b)
+        elif kind == pa.OPKIND_FUSED:
+            b = w["fused_lds_bytes"] / a["launches"]
+            ach = b / (avg * 1e-3) / 1e9
+            ent.update(achieved=ach, peak=LDS_PEAK_GBS, unit="GB/s", frac=ach / LDS_PEAK_GBS, lds_bytes_per_launch=b,
+                       effective_tops=2.0 * w["fused_macs"] / (a["ms"] * 1e-3) / 1e12)
         elif kind in (pa.OPKIND_STREAM_K, pa.OPKIND_STREAM_W):
             b = w["stream_bytes"] / a["launches"]
             ach = b / (avg * 1e-3) / 1e9

@@ -208,8 +208,15 @@ typedef struct {
                                  the fallback for every such contraction, 2 = the
                                  pass alone (no count, no MFMA kernel; B's first
                                  plot is dropped when nothing else reads it) for
-                                 every such contraction, -1 = never.  Not used by
-                                 the plain path or a single persistent launch.    */
+                                 every such contraction, 3 = as 2, and two passes
+                                 read only by one streamed contraction (output
+                                 out[p][q] = OR over s, t of X[q][s][p][t] AND
+                                 Y[p][s][q][t], t packed and at most 256 bits)
+                                 are fused with it: lists of the set bits of the
+                                 A operands, then one step that gathers the rows
+                                 of both plots in LDS; the pass outputs are never
+                                 stored.  -1 = never.  Not used by the plain path
+                                 or a single persistent launch.                  */
     int32_t sparse_max_density; /* 0..1024 set bits per 1024 bits of A (0: 64)     */
     int32_t plot_rule;        /* PA_RULE_* (0: corners)                           */
     int32_t measure_density;  /* 1: plan creation plots every relation once on the
@@ -321,7 +328,8 @@ void pa_plan_destroy(pa_plan *plan);
  * eqn naive_cost; 0 for plots and fills).  Waits for the events.  Returns
  * the number of ops, or -1 if the plan does not record op timings. */
 enum { PA_OPKIND_BITS = 0, PA_OPKIND_STREAM_K = 1, PA_OPKIND_STREAM_W = 2, PA_OPKIND_GEMM = 10,
-       PA_OPKIND_FILL = 20, PA_OPKIND_GATHER = 25, PA_OPKIND_COUNT = 26, PA_OPKIND_PLOT = 30, PA_OPKIND_PERSIST = 40 };
+       PA_OPKIND_FILL = 20, PA_OPKIND_GATHER = 25, PA_OPKIND_COUNT = 26, PA_OPKIND_ROWLIST = 27, PA_OPKIND_FUSED = 28,
+       PA_OPKIND_PLOT = 30, PA_OPKIND_PERSIST = 40 };
 int32_t pa_plan_op_times(pa_plan *plan, double *ms, int32_t *kind, double *macs, int32_t cap);
 
 /* Kernel duration of every grouped launch of a plan on the default
@@ -472,8 +480,8 @@ int32_t pa_plan_step_samples(pa_plan *plan, float *features, float *log2_us, int
  * 2048 work items), then the MFMA operand path (LDS-staged 128x128 or
  * 256x128 tiles, direct, or resident A operands), then (when
  * opts->sparse_pass is 0) the sparse
- * pass alone for every contraction whose B is a plot, each
- * from the best so far.  Every candidate is a batch built
+ * pass alone for every contraction whose B is a plot, then the same with
+ * pass pairs fused (sparse_pass 3), each from the best so far.  Every candidate is a batch built
  * with opts (graph capture included if opts->graph), executed once untimed,
  * then reps times between two events on `stream`.  Candidates that exceed
  * the workspace cap are skipped.  best gets the fastest; tried (may be NULL)
@@ -482,8 +490,9 @@ int32_t pa_plan_step_samples(pa_plan *plan, float *features, float *log2_us, int
  * tuning; synchronizes the stream. */
 typedef struct {
     int32_t single_launch, persist_wg, plot_strip, contract_units, gemm_split, gemm_path;
-    int32_t sparse_pass;      /* as in pa_opts: opts->sparse_pass, or 2 when that was
-                                 0 and the pass alone was faster                  */
+    int32_t sparse_pass;      /* as in pa_opts: opts->sparse_pass, or 2 or 3 when
+                                 that was 0 and the pass alone (3: with fused
+                                 pass pairs) was faster                           */
     double ms;                /* milliseconds per execution of the whole workload */
 } pa_tuning;
 int pa_autotune(const pa_system *systems, int32_t n_sys, const int32_t *const *exposed, const int32_t *n_exposed,

@@ -277,8 +277,7 @@ extern "C" int pa_batch_create(const pa_system *systems, int32_t n_sys, const in
 // contraction is counted).
 static int counted_steps(const pa_plan &P) {
     int steps = 0;
-    for (const auto &op : P.ops)
-        if (op.kind != OP_FILL && op.kind != OP_COUNT && !(op.kind == OP_GATHER && op.flag >= 0) && op.b != -1) ++steps;
+    for (const auto &op : P.ops) steps += counted_steps_of(op);
     return steps;
 }
 

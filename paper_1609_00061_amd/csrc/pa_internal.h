@@ -187,6 +187,55 @@ struct GatherArgs {
 
 constexpr int64_t kCountTileWords = 8192;    // A words per tile of a count step (4 partial sums)
 
+// Two sparse passes read only by one streamed contraction (mode K), fused
+// so that their outputs are never stored.  With output out[p][q] (q packed),
+// latent entries s and the packed latent variable t (words w):
+//   out[p][q] = OR_{s, w} X[q][s][p][w] AND Y[p][s][q][w]
+//   X[q][s][p][.] = OR over set bits k of AX row (q, s) of BtX[k][p][.]
+//   Y[p][s][q][.] = OR over set bits k of AY row (p, s) of BtY[k][q][.]
+// (eqn GAM for the contraction, the two passes its operands).  A row-list
+// step turns every A row into the list of its set bits; a fused tile
+// stages the rows of BtX for 8 p and of BtY for 8 q in LDS and gathers.
+//
+// Row lists: rows are taken in groups of 8 consecutive values of the row's
+// output variable o (o-block ob) for one s: group g = ob * n_s + s, list
+// row 8 g + i for o = 8 ob + i.  A list row holds its set bits k as the LDS
+// word offsets 64 (lbase + k) of their rows (16 bits each), four to a
+// batch, padded with the all-zero row zrow: batches 0 and 1 in the head (32
+// words per group: batch 0 of row i in words 2i, 2i + 1, batch 1 in words
+// 16 + 2i, 17 + 2i), the rest in the tail (tb batches of 2 words per row).
+// Per group 16 meta words: bit i of word 0 is set when row i has more than
+// one batch, word 8 + i holds the number of its batches after the first
+// (bits 0..5) and the word offset of its tail batches in the tail (bits
+// 6..31).  Rows with o >= n_o have no set bits.
+struct RowListArgs {
+    const uint32_t *A;        // the pass's A operand: row (o, s) at (o ro + s rs) Kw words
+    uint32_t *head, *tail, *meta;   // per group: 32 words, 8 tb batches of 2 words, 16 words
+    int64_t n_o, n_s, ro, rs;
+    int64_t Kw, rwk, rkp;     // A row words; bit b of word w = ko rwk + wp is k = ko rkp + 32 wp + b
+    int lbase, zrow;
+    int64_t tb;               // tail batches per list row
+    int64_t n_rows;           // 8 ceil(n_o / 8) n_s list rows
+};
+
+constexpr int kFusedRows = 513;                        // LDS rows of a fused tile: BtX, BtY, the zero row
+constexpr int kFusedLdsWords = kFusedRows * 64 + 12;   // 64 words per row, the tile's 8 output words, 4 counters
+
+// A fused tile: 8 p (block pb) x 32 q (word qw of the output rows, four
+// 8-q blocks in turn); tile = pb n_qw + qw.  Bt rows hold n_o x rwt words
+// (rwt <= 8: the o-th 8-word slot of a staged LDS row is padded with zeros).
+struct FusedArgs {
+    const uint32_t *BtX, *BtY;
+    const uint32_t *headX, *tailX, *metaX, *headY, *tailY, *metaY;
+    uint32_t *C;
+    int64_t n_p, n_q, n_s;
+    int64_t btX_rw, btY_rw;   // Bt row words: n_p rwt, n_q rwt
+    int rwt, kX, kY;          // words of t; LDS rows of BtX (0..kX-1) and BtY (kX..kX+kY-1)
+    int64_t tbX, tbY;         // tail batches per list row of X, Y
+    int64_t c_rw;             // output row words
+    int64_t n_qw, n_tiles;    // ceil(n_q / 32); ceil(n_p / 8) n_qw
+};
+
 // Wave-tiles of a sparse pass (2048 words of one output row each).
 __host__ __device__ inline int64_t gather_wave_tiles(const GatherArgs &g) { return g.rows * g.chunks; }
 
@@ -194,7 +243,10 @@ __host__ __device__ inline int64_t gather_wave_tiles(const GatherArgs &g) { retu
 // fill or a sparse pass, cut into tiles.  Steps are listed so that every
 // step's producers come earlier; a tile starts once all tiles of the step's
 // producers are done.
-enum StepKind { kStepPlot = 0, kStepGemm = 1, kStepContract = 2, kStepFill = 3, kStepGather = 4, kStepCount = 5 };
+enum StepKind {
+    kStepPlot = 0, kStepGemm = 1, kStepContract = 2, kStepFill = 3, kStepGather = 4, kStepCount = 5,
+    kStepList = 6, kStepFused = 7
+};
 
 struct PStep {
     int kind, mode;
@@ -205,6 +257,8 @@ struct PStep {
     GemmArgs gemm;
     ContractArgs ca;
     GatherArgs gather;              // sparse pass: tiles of 4 wave-tiles; count: of kCountTileWords words
+    RowListArgs list;               // row lists: tiles of 256 list rows
+    FusedArgs fused;                // fused pass pair: one tile per workgroup of 1024 threads
     uint32_t *fill_ptr;
 };
 
@@ -244,6 +298,10 @@ hipError_t launch_gemm_count(const GemmArgs &g, hipStream_t s);
 hipError_t launch_count_bits(const ContractArgs &a, int64_t n_elems, hipStream_t s);
 hipError_t launch_gather(const GatherArgs &g, hipStream_t s);
 hipError_t launch_count(const GatherArgs &g, hipStream_t s);
+hipError_t launch_row_list(const RowListArgs &l, hipStream_t s);
+// One fused step (a one-step table in device memory, tile_base 0; C
+// replaces its output pointer).
+hipError_t launch_fused(const PStep *d_step, int64_t n_tiles, uint32_t *C, hipStream_t s);
 hipError_t launch_fill(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
 hipError_t launch_popcount(const uint32_t *p, int64_t n, unsigned long long *out, hipStream_t s);
 hipError_t launch_tile_popcount(const uint32_t *p, int64_t rows, int64_t rw, int tile_rows, int tile_words,

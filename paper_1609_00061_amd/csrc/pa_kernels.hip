@@ -2241,6 +2241,253 @@ hipError_t launch_gather(const GatherArgs &g, hipStream_t s) {
     return hipGetLastError();
 }
 
+// -------------------------------------------------------- fused pass pair
+// Row lists (one thread per list row, 256 per tile): the set bits of the A
+// row, in increasing order, as LDS word offsets 64 (lbase + k); the first
+// eight in the head, the rest in the tail; unused entries of the last batch
+// name the zero row.  The group's meta words: bit i of word 0 is set when
+// row i has more than one batch, word 8 + i holds the number of row i's
+// batches after the first (bits 0..5) and its tail's word offset (bits
+// 6..31).
+__device__ __forceinline__ void row_list_tile(const RowListArgs &L, int64_t tile) {
+    const int64_t r = tile * 256 + threadIdx.x;
+    const bool valid = r < L.n_rows;
+    const int64_t g = r >> 3, ob = g / L.n_s, s = g - ob * L.n_s, o = ob * 8 + (r & 7);
+    const uint64_t Z = (uint32_t)L.zrow * 64u;
+    const uint64_t zz = Z | (Z << 16) | (Z << 32) | (Z << 48);
+    uint64_t lo = zz, hi = zz;              // entries 0..3, 4..7
+    PA_G uint32_t *tail = gp(L.tail) + r * L.tb * 2;
+    int cnt = 0;
+    uint32_t pend = 0;                      // an even tail entry waiting for its pair
+    auto put = [&](uint32_t e) {
+        if (cnt < 4) {
+            const int sh = 16 * cnt;
+            lo = (lo & ~(0xffffull << sh)) | ((uint64_t)e << sh);
+        } else if (cnt < 8) {
+            const int sh = 16 * (cnt - 4);
+            hi = (hi & ~(0xffffull << sh)) | ((uint64_t)e << sh);
+        } else if (((cnt - 8) & 1) == 0) {
+            pend = e;
+        } else {
+            tail[(cnt - 8) >> 1] = pend | (e << 16);
+        }
+        ++cnt;
+    };
+    if (valid && o < L.n_o) {
+        const PA_G uint32_t *row = gp(L.A) + (o * L.ro + s * L.rs) * L.Kw;
+        for (int64_t w = 0; w < L.Kw; ++w) {
+            uint32_t x = row[w];
+            const int64_t ko = w / L.rwk;
+            const uint32_t kb = (uint32_t)(L.lbase + ko * L.rkp + (w - ko * L.rwk) * 32);
+            while (x) {
+                put((kb + (uint32_t)__builtin_ctz(x)) * 64u);
+                x &= x - 1;
+            }
+        }
+    }
+    const int n = cnt;
+    if (n > 8)
+        while (cnt & 3) put((uint32_t)Z);          // pad the last tail batch
+    const uint32_t nx = n > 4 ? (uint32_t)((n + 3) / 4 - 1) : 0u;
+    // rows r of a group are 8 consecutive lanes (tiles hold whole groups)
+    const uint64_t more = __ballot(n > 4);
+    if (!valid) return;
+    // batch 0 of the group's 8 rows in words 0..15, batch 1 in 16..31
+    PA_G uint32_t *hd = gp(L.head) + g * 32 + (r & 7) * 2;
+    *reinterpret_cast<PA_G u32x2 *>(hd) = u32x2{(uint32_t)lo, (uint32_t)(lo >> 32)};
+    *reinterpret_cast<PA_G u32x2 *>(hd + 16) = u32x2{(uint32_t)hi, (uint32_t)(hi >> 32)};
+    gp(L.meta)[g * 16 + 8 + (r & 7)] = nx | (uint32_t)(r * L.tb * 2) << 6;
+    if ((r & 7) == 0) gp(L.meta)[g * 16] = (uint32_t)(more >> (__lane_id() & ~7)) & 0xffu;
+}
+
+__global__ __launch_bounds__(256) void k_row_list(RowListArgs L, int64_t n_tiles) {
+    for (int64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) row_list_tile(L, t);
+}
+
+hipError_t launch_row_list(const RowListArgs &l, hipStream_t s) {
+    const int64_t nt = (l.n_rows + 255) / 256;
+    if (nt <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_row_list, dim3((unsigned)(nt < (1 << 20) ? nt : (1 << 20))), dim3(256), 0, s, l, nt);
+    return hipGetLastError();
+}
+
+// LDS rows row0 .. row0 + K - 1 of a fused tile: word 8 ol + w of row
+// row0 + k is Bt[k][o0 + ol][w] (zero for o0 + ol >= n_o or w >= rwt).
+// 1024 threads; the loads of four rounds are issued before their stores.
+__device__ __forceinline__ void fused_stage(uint32_t *lds, const uint32_t *bt, int64_t bt_rw, int K, int64_t o0,
+                                            int64_t n_o, int rwt, int row0) {
+    const int tid = threadIdx.x;
+    if (rwt == 8) {
+        // 16 groups of 4 words per row: group c covers o0 + c / 2, words 4 (c & 1) ..
+        const int n = K * 16;
+        for (int i0 = 0; i0 < n; i0 += 4096) {
+            u32x4 v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int i = i0 + u * 1024 + tid;
+                const int k = i >> 4, c = i & 15;
+                v[u] = u32x4{0u, 0u, 0u, 0u};
+                if (i < n && o0 + (c >> 1) < n_o)
+                    v[u] = *reinterpret_cast<const PA_G u32x4 *>(gp(bt) + (int64_t)k * bt_rw + o0 * 8 + 4 * c);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int i = i0 + u * 1024 + tid;
+                if (i < n) *reinterpret_cast<u32x4 *>(lds + (row0 + (i >> 4)) * 64 + 4 * (i & 15)) = v[u];
+            }
+        }
+        return;
+    }
+    const int n = K * 64;
+    for (int i0 = 0; i0 < n; i0 += 4096) {
+        uint32_t v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int i = i0 + u * 1024 + tid;
+            const int k = i >> 6, ol = (i >> 3) & 7, w = i & 7;
+            v[u] = 0u;
+            if (i < n && w < rwt && o0 + ol < n_o) v[u] = gp(bt)[(int64_t)k * bt_rw + (o0 + ol) * rwt + w];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int i = i0 + u * 1024 + tid;
+            if (i < n) lds[(row0 + (i >> 6)) * 64 + (i & 63)] = v[u];
+        }
+    }
+}
+
+// OR of the four LDS rows at the word offsets in the 16-bit halves of w0
+// and w1, word `lane` of each.
+__device__ __forceinline__ uint32_t fused_batch(const uint32_t *lds, int lane, uint32_t w0, uint32_t w1) {
+    return lds[(w0 & 0xffffu) + lane] | lds[(w0 >> 16) + lane] | lds[(w1 & 0xffffu) + lane] | lds[(w1 >> 16) + lane];
+}
+
+// The rows of eight lists of one group: c[i] = OR of the LDS rows of list
+// row i, word `lane`.  The group's 32 head words are lanes b .. b + 31 of
+// hw and its 16 meta words lanes m .. m + 15 of mw (loaded one latent entry
+// ahead with vector loads, read out with v_readlane); the tails (rows of
+// more than eight set bits) through scalar loads from tl.  Batch 0 of every
+// row first (32 reads in flight), then the later batches of the rows that
+// have them.
+template <int B, int M>
+__device__ __forceinline__ void fused_rows(const uint32_t *lds, int lane, uint32_t hw, uint32_t mw,
+                                           const PA_K uint32_t *tl, uint32_t (&c)[8]) {
+    uint32_t r[8][4];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const uint32_t w0 = __builtin_amdgcn_readlane(hw, B + 2 * i), w1 = __builtin_amdgcn_readlane(hw, B + 2 * i + 1);
+        r[i][0] = lds[(w0 & 0xffffu) + lane];
+        r[i][1] = lds[(w0 >> 16) + lane];
+        r[i][2] = lds[(w1 & 0xffffu) + lane];
+        r[i][3] = lds[(w1 >> 16) + lane];
+    }
+    __builtin_amdgcn_sched_group_barrier(0x100, 32, 0);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) c[i] = r[i][0] | r[i][1] | r[i][2] | r[i][3];
+    const uint32_t m = __builtin_amdgcn_readlane(mw, M);
+    if (m == 0u) return;
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+        if (m & (1u << i)) {
+            c[i] |= fused_batch(lds, lane, __builtin_amdgcn_readlane(hw, B + 16 + 2 * i),
+                                __builtin_amdgcn_readlane(hw, B + 17 + 2 * i));
+            const uint32_t w = __builtin_amdgcn_readlane(mw, M + 8 + i), nx = w & 63u;
+            const PA_K uint32_t *t = tl + (w >> 6);
+            for (uint32_t b = 2; b <= nx; ++b) c[i] |= fused_batch(lds, lane, t[2 * (b - 2)], t[2 * (b - 2) + 1]);
+        }
+}
+
+// Transpose of an 8 x 8 block held as c[j] in lane group a = lane / 8 (each
+// of the group's 8 lanes holds its own word): afterwards c[j] of group a is
+// the former c[a] of group j.  Index bit 0 trades with lane bit 3 (DPP
+// rotation by 8 within rows of 16 lanes, written to one half of each row),
+// bit 1 with lane bit 4 (v_permlane16_swap), bit 2 with lane bit 5
+// (v_permlane32_swap).
+__device__ __forceinline__ void fused_transpose8(uint32_t (&c)[8]) {
+#pragma unroll
+    for (int j = 0; j < 8; j += 2) {
+        const int a = (int)c[j], b = (int)c[j + 1];
+        c[j] = (uint32_t)__builtin_amdgcn_update_dpp(a, b, 0x128, 0xf, 0xc, false);
+        c[j + 1] = (uint32_t)__builtin_amdgcn_update_dpp(b, a, 0x128, 0xf, 0x3, false);
+    }
+#pragma unroll
+    for (int j : {0, 1, 4, 5}) {
+        const auto sw = __builtin_amdgcn_permlane16_swap(c[j], c[j + 2], false, false);
+        c[j] = sw[0];
+        c[j + 2] = sw[1];
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const auto sw = __builtin_amdgcn_permlane32_swap(c[j], c[j + 4], false, false);
+        c[j] = sw[0];
+        c[j + 4] = sw[1];
+    }
+}
+
+// One fused tile (1024 threads, 16 waves): 8 p x 32 q of the output.  BtX's
+// rows for the tile's 8 p are staged once, BtY's for each 8-q block in
+// turn; the waves split the latent entries s.  For one s a wave gathers
+// X[q][s][p][w] as x[q] in lane (p, w) and Y[p][s][q][w] as y[p] in lane
+// (q, w), transposes y to lane (p, w) and keeps the OR of x[q] AND y[q].
+__device__ __forceinline__ void fused_tile(const FusedArgs &f, int64_t tile, uint32_t *lds) {
+    const int64_t pb = tile / f.n_qw, qw = tile - pb * f.n_qw, p0 = pb * 8;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    uint32_t *out = lds + kFusedRows * 64;     // 8 output words, then 4 latent-entry counters
+    fused_stage(lds, f.BtX, f.btX_rw, f.kX, p0, f.n_p, f.rwt, 0);
+    if (tid < 64) lds[(f.kX + f.kY) * 64 + tid] = 0u;
+    if (tid < 12) out[tid] = 0u;
+    for (int j = 0; j < 4; ++j) {
+        const int64_t qb = qw * 4 + j;
+        if (qb * 8 >= f.n_q) break;
+        fused_stage(lds, f.BtY, f.btY_rw, f.kY, qb * 8, f.n_q, f.rwt, f.kX);
+        __syncthreads();
+        uint32_t acc[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
+        // the waves take latent entries from a counter, the next one while
+        // working on the current
+        auto grab = [&]() {
+            uint32_t v = 0;
+            if (lane == 0) v = atomicAdd(out + 8 + j, 1u);
+            return (int64_t)__builtin_amdgcn_readfirstlane(v);
+        };
+        // lane l < 32 loads head word l of Y's group, lane 32 + l word l of
+        // X's; lanes 0..15 and 16..31 the meta words of Y's and X's
+        auto fetch = [&](int64_t s, uint32_t &hw, uint32_t &mw) {
+            const int64_t gx = qb * f.n_s + s, gy = pb * f.n_s + s;
+            hw = lane < 32 ? gp(f.headY)[gy * 32 + lane] : gp(f.headX)[gx * 32 + lane - 32];
+            mw = lane < 16 ? gp(f.metaY)[gy * 16 + lane] : gp(f.metaX)[gx * 16 + ((lane - 16) & 15)];
+        };
+        int64_t s = grab();
+        uint32_t hw = 0, mw = 0;
+        if (s < f.n_s) fetch(s, hw, mw);
+        while (s < f.n_s) {
+            const int64_t sn = grab();
+            uint32_t hn = 0, mn = 0;
+            if (sn < f.n_s) fetch(sn, hn, mn);
+            uint32_t x[8], y[8];
+            fused_rows<0, 0>(lds, lane, hw, mw, (const PA_K uint32_t *)f.tailY, y);
+            fused_rows<32, 16>(lds, lane, hw, mw, (const PA_K uint32_t *)f.tailX, x);
+            fused_transpose8(y);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) acc[i] |= x[i] & y[i];
+            s = sn;
+            hw = hn;
+            mw = mn;
+        }
+        uint32_t bits = 0;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) bits |= (acc[i] != 0u ? 1u : 0u) << i;
+        if (bits) atomicOr(out + (lane >> 3), bits << (8 * j));
+        __syncthreads();
+    }
+    if (tid < 8 && p0 + tid < f.n_p) {
+        PA_G uint32_t *row = gp(f.C) + (p0 + tid) * f.c_rw;
+        row[qw] = out[tid];
+        if (qw == f.n_qw - 1)
+            for (int64_t w = qw + 1; w < f.c_rw; ++w) row[w] = 0u;
+    }
+}
+
 // ------------------------------------------------------------ fill, count
 __global__ void k_fill(uint32_t *p, int64_t n, uint32_t v) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -2465,6 +2712,8 @@ __device__ __forceinline__ void group_run(const PStep *__restrict__ steps, int f
             contract_range<mode>(st.ca, u0, min(st.units, u0 + st.per_tile));
         } else if (kind == kStepCount) {
             count_tile(st.gather, item - st.tile_base);
+        } else if (kind == kStepList) {
+            row_list_tile(st.list, item - st.tile_base);
         } else {
             const int64_t u0 = (item - st.tile_base) * st.per_tile, u1 = min(st.units, u0 + st.per_tile);
             for (int64_t i = u0 + threadIdx.x; i < u1; i += blockDim.x) gp(st.fill_ptr)[i] = 0u;
@@ -2488,6 +2737,28 @@ __global__ __launch_bounds__(256, group_occupancy<KIND>()) void k_group(
     PlotCounters *counters) {
     __shared__ __attribute__((aligned(16))) uint32_t lds[group_lds_words<KIND>()];
     group_run<KIND>(steps, first, count, t0, t1, flags, counters, lds, blockIdx.x, gridDim.x);
+}
+
+// Fused pass pairs of one level: one tile per workgroup of 1024 threads,
+// with a uniform copy of its step's arguments (C, when not null, replaces
+// their output pointer: one step launched on its own).
+__global__ __launch_bounds__(1024, 1) void k_fused_group(const PStep *__restrict__ steps, int first, int count,
+                                                         int64_t t0, int64_t t1, uint32_t *C) {
+    __shared__ __attribute__((aligned(16))) uint32_t lds[kFusedLdsWords];
+    for (int64_t item = t0 + blockIdx.x; item < t1; item += gridDim.x) {
+        const int si = __builtin_amdgcn_readfirstlane(find_step(steps, first, count, item));
+        FusedArgs f = steps[si].fused;
+        if (C) f.C = C;
+        fused_tile(f, item - steps[si].tile_base, lds);
+        __syncthreads();
+    }
+}
+
+hipError_t launch_fused(const PStep *d_step, int64_t n_tiles, uint32_t *C, hipStream_t s) {
+    if (n_tiles <= 0) return hipSuccess;
+    const unsigned grid = (unsigned)(n_tiles < (1 << 20) ? n_tiles : (1 << 20));
+    hipLaunchKernelGGL(k_fused_group, dim3(grid), dim3(1024), 0, s, d_step, 0, 1, (int64_t)0, n_tiles, C);
+    return hipGetLastError();
 }
 
 // Workgroups of the persistent sparse-pass loop: every CU's worth.
@@ -2529,6 +2800,11 @@ hipError_t launch_group(int kind, int mode, const PStep *d_steps, int first, int
             break;
         case kStepGather: PA_GROUP(kStepGather); break;
         case kStepCount: PA_GROUP(kStepCount); break;
+        case kStepList: PA_GROUP(kStepList); break;
+        case kStepFused:
+            hipLaunchKernelGGL(k_fused_group, grid, dim3(1024), 0, s, d_steps, first, count, t0, t1,
+                               static_cast<uint32_t *>(nullptr));
+            break;
         default: PA_GROUP(kStepFill); break;
     }
 #undef PA_GROUP

@@ -365,7 +365,7 @@ struct Builder {
         const double macs = mask_cost(list_mask(la.vars) | list_mask(lb.vars), P->si);
         int mode = 0;         // 0: MFMA only, 1: pass with MFMA fallback, 2: pass only
         if (b_plot && P->sparse_pass >= 0) {
-            if (P->sparse_pass >= 1) mode = P->sparse_pass;
+            if (P->sparse_pass >= 1) mode = std::min(P->sparse_pass, 2);
             else if (macs >= 4294967296.0) mode = 1;
         }
         if (mode == 0) {
@@ -650,6 +650,19 @@ std::string Op::describe() const {
         s << "{\"op\":\"sparse_count\",\"a\":" << a << ",\"flag\":" << flag << ",\"words\":" << gg.rows * gg.Kw << "}";
         return s.str();
     }
+    if (kind == OP_LIST) {
+        s << "{\"op\":\"row_list\",\"a\":" << a << ",\"c\":" << c << ",\"a_vars\":" << join(la.vars)
+          << ",\"n_o\":" << rl.n_o << ",\"n_s\":" << rl.n_s << ",\"rows\":" << rl.n_rows << ",\"lbase\":" << rl.lbase
+          << ",\"zrow\":" << rl.zrow << ",\"tail_batches\":" << rl.tb << "}";
+        return s.str();
+    }
+    if (kind == OP_FUSED) {
+        s << "{\"op\":\"fused_pass_pair\",\"lists\":" << a << ",\"btx\":" << b << ",\"bty\":" << flag
+          << ",\"c\":" << c << ",\"c_vars\":" << join(lc.vars) << ",\"n_p\":" << fu.n_p << ",\"n_q\":" << fu.n_q
+          << ",\"n_s\":" << fu.n_s << ",\"rwt\":" << fu.rwt << ",\"kx\":" << fu.kX << ",\"ky\":" << fu.kY
+          << ",\"tiles\":" << fu.n_tiles << ",\"macs\":" << macs << ",\"dense_macs\":" << dense_macs << "}";
+        return s.str();
+    }
     if (kind == OP_GATHER) {
         s << "{\"op\":\"sparse_pass\",\"a\":" << a << ",\"bt\":" << b << ",\"c\":" << c << ",\"flag\":" << flag
           << ",\"a_vars\":" << join(la.vars) << ",\"bt_vars\":" << join(lb.vars) << ",\"c_vars\":" << join(lc.vars)
@@ -782,6 +795,209 @@ static void plot_tiling(PlotRel &R, int strip) {
 
 static int64_t contract_units_of(const ContractArgs &a, int mode) { return contract_units(a, mode); }
 
+static int check_contract_bounds(const ContractArgs &a, int64_t a_words, int64_t b_words, int64_t c_words, bool has_b);
+static int check_gemm_bounds(const GemmArgs &g, int64_t a_words, int64_t b_words, int64_t c_words);
+static int check_gather_bounds(const GatherArgs &g, int64_t a_words, int64_t bt_words, int64_t c_words);
+static int check_list_bounds(const Op &op, int64_t a_words, int64_t list_words);
+static int check_fused_bounds(const Op &op, int64_t list_words, int64_t btx_words, int64_t bty_words,
+                              int64_t c_words);
+
+// Every step's index ranges against its buffers, on the host at plan time
+// (the same checks run again when the steps get their device pointers).
+static int validate_ops(const pa_plan *P) {
+    auto words = [&](int id, const Layout &l) { return id == kBufOutput ? l.words : P->buf_words[id]; };
+    for (const Op &op : P->ops) {
+        int rc = PA_OK;
+        switch (op.kind) {
+            case OP_FILL: break;
+            case OP_GEMM: rc = check_gemm_bounds(op.ga, op.la.words, op.lb.words, op.lc.words); break;
+            case OP_COUNT: rc = check_gather_bounds(op.gg, op.la.words, -1, -1); break;
+            case OP_GATHER: rc = check_gather_bounds(op.gg, op.la.words, op.lb.words, op.lc.words); break;
+            case OP_LIST: rc = check_list_bounds(op, op.la.words, words(op.c, op.lc)); break;
+            case OP_FUSED:
+                rc = check_fused_bounds(op, words(op.a, op.la), words(op.b, op.lb), words(op.flag, op.lb),
+                                        words(op.c, op.lc));
+                break;
+            default:
+                rc = check_contract_bounds(op.ca, op.la.words, op.lb.words, op.lc.words, op.b >= 0);
+                break;
+        }
+        if (rc) return rc;
+    }
+    return PA_OK;
+}
+
+// One of the two passes of a fusable pair: its output C[r0][r1][o_col][t]
+// (rows: the output variable o_row and the latent entry variable s of the
+// streamed step, in either order; no batch variables), A rows in C's row
+// order, kall latent bits (at most 256).
+struct PassSide {
+    int op = -1, o_row = -1, o_col = -1, s = -1;
+    int64_t ro = 0, rs = 0, kall = 0;
+};
+
+static bool pass_side(const Op &G, int op, int p, int q, int t, PassSide &sd) {
+    const Layout &lc = G.lc;
+    if (G.kind != OP_GATHER || G.flag >= 0 || lc.vars.size() != 4 || lc.vars[3] != t) return false;
+    if (G.gg.rows != G.gg.M || G.gg.rows != lc.dims[0] * lc.dims[1] || G.gg.Nw != lc.dims[2] * lc.rw) return false;
+    if (G.la.vars.size() < 3 || G.la.vars[0] != lc.vars[0] || G.la.vars[1] != lc.vars[1]) return false;
+    sd.op = op;
+    sd.o_col = lc.vars[2];
+    if (lc.vars[0] == p || lc.vars[0] == q) {
+        sd.o_row = lc.vars[0];
+        sd.s = lc.vars[1];
+        sd.ro = lc.dims[1];
+        sd.rs = 1;
+    } else if (lc.vars[1] == p || lc.vars[1] == q) {
+        sd.o_row = lc.vars[1];
+        sd.s = lc.vars[0];
+        sd.ro = 1;
+        sd.rs = lc.dims[1];
+    } else {
+        return false;
+    }
+    if (sd.s == p || sd.s == q || sd.s == t || sd.o_col == sd.o_row || (sd.o_col != p && sd.o_col != q)) return false;
+    if (G.gg.rwk < 1 || G.gg.Kw % G.gg.rwk) return false;
+    sd.kall = G.gg.Kw / G.gg.rwk * G.gg.rkp;
+    return sd.kall >= 1 && sd.kall <= 256;
+}
+
+// Fuses each streamed contraction (mode K) whose two operands are written
+// by sparse passes alone and read by nothing else, in the pattern
+// out[p][q] = OR_{s, t} X[q][s][p][t] AND Y[p][s][q][t] (t packed, at most
+// 256 bits): the two passes and the contraction become two row-list steps
+// and one fused step, and the pass outputs are never stored.
+static void fuse_pass_pairs(pa_plan *P) {
+    auto writer = [&](int buf) {
+        for (size_t i = 0; i < P->ops.size(); ++i)
+            if (P->ops[i].c == buf) return (int)i;
+        return -1;
+    };
+    auto readers = [&](int buf) {
+        int n = 0;
+        for (const Op &op : P->ops)
+            for (int id : {op.a, op.b, op.flag})
+                if (id == buf) ++n;
+        return n;
+    };
+    for (size_t si = 0; si < P->ops.size();) {
+        const Op S = P->ops[si++];
+        if (S.kind != OP_CONTRACT || S.mode != kModeStreamK || S.a < 0 || S.b < 0 || S.a == S.b) continue;
+        if (S.lc.vars.size() != 2 || S.la.vars.size() != 4 || S.lb.vars.size() != 4) continue;
+        const int p = S.lc.vars[0], q = S.lc.vars[1], t = S.la.vars[3];
+        if (S.lb.vars[3] != t || t == p || t == q || S.la.rw > 8) continue;
+        const int ia = writer(S.a), ib = writer(S.b);
+        if (ia < 0 || ib < 0 || readers(S.a) != 1 || readers(S.b) != 1) continue;
+        PassSide A, B;
+        if (!pass_side(P->ops[ia], ia, p, q, t, A) || !pass_side(P->ops[ib], ib, p, q, t, B)) continue;
+        PassSide X, Y;
+        if (A.o_row == q && B.o_row == p) {
+            X = A;
+            Y = B;
+        } else if (A.o_row == p && B.o_row == q) {
+            X = B;
+            Y = A;
+        } else {
+            continue;
+        }
+        if (X.s != Y.s) continue;
+        const Op &GX = P->ops[X.op], &GY = P->ops[Y.op];
+        const int64_t n_p = S.lc.dims[0], n_q = S.lc.dims[1], n_s = P->si.res[X.s];
+        const int64_t rwt = GX.lc.rw;
+        if (GY.lc.rw != rwt || rwt > 8 || X.kall + Y.kall + 1 > kFusedRows) continue;
+        // list buffer: per operand the heads, the meta words and the tails
+        const int64_t gX = (n_q + 7) / 8 * n_s, gY = (n_p + 7) / 8 * n_s;
+        const int64_t tbX = std::max<int64_t>(1, (X.kall + 3) / 4 - 2), tbY = std::max<int64_t>(1, (Y.kall + 3) / 4 - 2);
+        if (gX * 8 >= ((int64_t)1 << 31) || gY * 8 >= ((int64_t)1 << 31)) continue;
+        int64_t off = 0;
+        auto region = [&](int64_t words) {
+            const int64_t at = off;
+            off += (words + 63) / 64 * 64;
+            return at;
+        };
+        int64_t sub[6];
+        sub[0] = region(gX * 32);
+        sub[1] = region(gX * 8 * tbX * 2);
+        sub[2] = region(gX * 16);
+        sub[3] = region(gY * 32);
+        sub[4] = region(gY * 8 * tbY * 2);
+        sub[5] = region(gY * 16);
+        Layout ll;
+        ll.rw = off;
+        ll.words = off;
+        P->buf_layout.push_back(ll);
+        P->buf_words.push_back(off);
+        P->buf_off.push_back(-1);
+        const int lbuf = (int)P->buf_layout.size() - 1;
+        const int zrow = (int)(X.kall + Y.kall);
+        auto list_op = [&](const Op &G, const PassSide &sd, int64_t n_o, int lbase, int64_t tb, int k0) {
+            Op L;
+            L.kind = OP_LIST;
+            L.a = G.a;
+            L.c = lbuf;
+            L.la = G.la;
+            L.lc = ll;
+            L.node = S.node;
+            L.rl.n_o = n_o;
+            L.rl.n_s = n_s;
+            L.rl.ro = sd.ro;
+            L.rl.rs = sd.rs;
+            L.rl.Kw = G.gg.Kw;
+            L.rl.rwk = G.gg.rwk;
+            L.rl.rkp = G.gg.rkp;
+            L.rl.lbase = lbase;
+            L.rl.zrow = zrow;
+            L.rl.tb = tb;
+            L.rl.n_rows = (n_o + 7) / 8 * 8 * n_s;
+            L.sub[0] = sub[k0];
+            L.sub[1] = sub[k0 + 1];
+            L.sub[2] = sub[k0 + 2];
+            return L;
+        };
+        const Op LX = list_op(GX, X, n_q, 0, tbX, 0), LY = list_op(GY, Y, n_p, (int)X.kall, tbY, 3);
+        Op F;
+        F.kind = OP_FUSED;
+        F.a = lbuf;
+        F.b = GX.b;
+        F.flag = GY.b;
+        F.c = S.c;
+        F.la = ll;
+        F.lb = GX.lb;
+        F.lc = S.lc;
+        F.node = S.node;
+        F.macs = GX.macs + GY.macs + S.macs;
+        F.dense_macs = GX.dense_macs + GY.dense_macs + S.macs;
+        FusedArgs &f = F.fu;
+        f.n_p = n_p;
+        f.n_q = n_q;
+        f.n_s = n_s;
+        f.btX_rw = GX.gg.Nw;
+        f.btY_rw = GY.gg.Nw;
+        f.rwt = (int)rwt;
+        f.kX = (int)X.kall;
+        f.kY = (int)Y.kall;
+        f.tbX = tbX;
+        f.tbY = tbY;
+        f.c_rw = S.lc.rw;
+        f.n_qw = (n_q + 31) / 32;
+        f.n_tiles = (n_p + 7) / 8 * f.n_qw;
+        for (int k = 0; k < 6; ++k) F.sub[k] = sub[k];
+        std::vector<Op> ops;
+        for (size_t k = 0; k < P->ops.size(); ++k) {
+            if ((int)k == X.op || (int)k == Y.op) continue;
+            if (k + 1 == si) {
+                ops.push_back(LX);
+                ops.push_back(LY);
+                ops.push_back(F);
+            } else {
+                ops.push_back(P->ops[k]);
+            }
+        }
+        P->ops.swap(ops);
+        si = 0;              // indices moved: look again from the start
+    }
+}
+
 int build_plan(const pa_system *sys, const int32_t *exposed, int32_t n_exposed, const pa_opts *opts, pa_plan *P) {
     auto t0 = std::chrono::steady_clock::now();
     int rc = build_sysinfo(sys, exposed, n_exposed, P->si);
@@ -819,9 +1035,10 @@ int build_plan(const pa_system *sys, const int32_t *exposed, int32_t n_exposed, 
     if (P->single_launch && P->gemm_path != 1) P->gemm_path = 0;
     // the sparse pass: not in the plain path nor in a single persistent launch
     P->sparse_pass = (P->plain || P->single_launch) ? -1 : o.sparse_pass;
+    P->fuse_passes = P->sparse_pass == 3;
     P->sparse_max_density = o.sparse_max_density > 0 ? o.sparse_max_density : 64;
-    if (o.sparse_pass < -1 || o.sparse_pass > 2 || o.sparse_max_density < 0 || o.sparse_max_density > 1024)
-        return fail(PA_EINVAL, "opts: sparse_pass must be -1..2 and sparse_max_density 0..1024");
+    if (o.sparse_pass < -1 || o.sparse_pass > 3 || o.sparse_max_density < 0 || o.sparse_max_density > 1024)
+        return fail(PA_EINVAL, "opts: sparse_pass must be -1..3 and sparse_max_density 0..1024");
     if (o.precision != PA_PLOT_FP32_ESCALATE && o.precision != PA_PLOT_FP64)
         return fail(PA_EINVAL, "opts: unknown precision");
     if (o.persist_wg < 0 || o.plot_strip < 0 || o.contract_units < 0 || o.gemm_split < 0 || o.gemm_path < 0 ||
@@ -847,24 +1064,25 @@ int build_plan(const pa_system *sys, const int32_t *exposed, int32_t n_exposed, 
         return g_err.empty() ? fail(PA_EINVAL, "internal: root not written to output") : PA_EINVAL;
     for (auto &op : P->ops)
         if (op.kind == OP_CONTRACT) finish_contract(op, op.b >= 0 || op.b == kBufOutput);
+    if (P->fuse_passes) fuse_pass_pairs(P);
     split_gemms(P);
-    // a plot that no step reads (the first plot of B in a contraction left to
-    // the sparse pass alone) is dropped, and its buffer takes no space
+    // a buffer that no step reads or writes (the first plot of B in a
+    // contraction left to the sparse pass alone, the outputs of fused passes)
+    // takes no space, and a plot that no step reads is dropped
     {
         std::vector<char> read(P->buf_layout.size(), 0);
         for (const auto &op : P->ops)
             for (int id : {op.a, op.b, op.c, op.flag})
                 if (id >= 0) read[id] = 1;
+        for (size_t id = 0; id < read.size(); ++id)
+            if (!read[id]) P->buf_words[id] = 0;
         std::vector<PlotItem> kept;
-        for (const auto &it : P->plots) {
-            if (it.buf >= 0 && !read[it.buf]) {
-                P->buf_words[it.buf] = 0;
-                continue;
-            }
-            kept.push_back(it);
-        }
+        for (const auto &it : P->plots)
+            if (it.buf < 0 || read[it.buf]) kept.push_back(it);
         P->plots.swap(kept);
     }
+    rc = validate_ops(P);
+    if (rc) return rc;
     P->total_macs = 0.0;
     for (const auto &op : P->ops)
         if (op.kind != OP_FILL) P->total_macs += op.macs;
@@ -901,8 +1119,10 @@ int build_plan(const pa_system *sys, const int32_t *exposed, int32_t n_exposed, 
         corners += cn;
     }
     P->corners = corners;
-    for (auto &op : P->ops)
+    for (auto &op : P->ops) {
         if (!op.ktab.empty()) op.ktab_off = (int64_t)take(op.ktab.size() * sizeof(int64_t));
+        if (op.kind == OP_FUSED) op.fargs_off = (int64_t)take(sizeof(PStep));
+    }
     for (size_t i = 0; i < P->buf_layout.size(); ++i) P->buf_off[i] = (int64_t)take(P->buf_words[i] * 4);
     P->ws_bytes = off;
     P->tables_bytes = T.size();
@@ -992,7 +1212,7 @@ static int check_gemm_bounds(const GemmArgs &g, int64_t a_words, int64_t b_words
     const int64_t ma = g.nbatch * g.sA_b, mb = g.nbatch * g.sB_b, mc = g.nbatch * g.sC_b;
     if (g.sA_b != g.M * g.Kw || g.sB_b != g.No * g.rn * g.Kw || g.sC_b != g.M * g.No * g.rwc || g.Kw % 2 ||
         g.rwc != row_words_of(g.rn) || ma > a_words || mb > b_words || mc > c_words || g.kchunk % 8 ||
-        g.kchunk > 16384 || (int64_t)g.ksplit * g.kchunk < g.Kw)
+        (int64_t)g.ksplit * g.kchunk < g.Kw)
         return fail(PA_EINVAL, "internal: GEMM would index outside its buffers");
     // the kernels decode tile indices and N coordinates in 32 bits
     const int64_t lim = (int64_t)1 << 31;
@@ -1016,6 +1236,39 @@ static int check_gather_bounds(const GatherArgs &g, int64_t a_words, int64_t bt_
     return PA_OK;
 }
 
+// Buffer sizes of a row-list step (its A and list buffer) and of a fused
+// step (BtX, BtY, the list buffer, the output).
+static int check_list_bounds(const Op &op, int64_t a_words, int64_t list_words) {
+    const RowListArgs &l = op.rl;
+    const int64_t groups = (l.n_o + 7) / 8 * l.n_s;
+    if (l.n_o < 1 || l.n_s < 1 || l.Kw < 1 || l.rwk < 1 || l.Kw % l.rwk || l.rkp < 1 || l.rkp > 32 * l.rwk ||
+        l.n_rows != groups * 8 || ((l.n_o - 1) * l.ro + (l.n_s - 1) * l.rs + 1) * l.Kw > a_words ||
+        l.lbase < 0 || l.lbase + l.Kw / l.rwk * l.rkp > l.zrow || l.zrow >= kFusedRows || l.tb < 1 ||
+        op.sub[0] + groups * 32 > list_words || op.sub[1] + l.n_rows * l.tb * 2 > list_words ||
+        op.sub[2] + groups * 16 > list_words || (l.Kw / l.rwk * l.rkp + 3) / 4 - 2 > l.tb)
+        return fail(PA_EINVAL, "internal: row-list step would index outside its buffers");
+    // list rows are 32-bit; tail offsets are 26-bit fields of the meta words
+    if (l.n_rows >= ((int64_t)1 << 31) || l.n_rows * l.tb * 2 >= ((int64_t)1 << 26))
+        return fail(PA_EUNSUPPORTED, "row-list step too large for one launch");
+    return PA_OK;
+}
+
+static int check_fused_bounds(const Op &op, int64_t list_words, int64_t btx_words, int64_t bty_words,
+                              int64_t c_words) {
+    const FusedArgs &f = op.fu;
+    const int64_t gX = (f.n_q + 7) / 8 * f.n_s, gY = (f.n_p + 7) / 8 * f.n_s;
+    if (f.n_p < 1 || f.n_q < 1 || f.n_s < 1 || f.rwt < 1 || f.rwt > 8 || f.kX < 1 || f.kY < 1 ||
+        f.kX + f.kY + 1 > kFusedRows || f.btX_rw < f.n_p * f.rwt || f.btY_rw < f.n_q * f.rwt ||
+        (int64_t)f.kX * f.btX_rw > btx_words || (int64_t)f.kY * f.btY_rw > bty_words ||
+        f.n_qw != (f.n_q + 31) / 32 || f.c_rw < f.n_qw || f.n_p * f.c_rw > c_words ||
+        f.n_tiles != (f.n_p + 7) / 8 * f.n_qw || op.sub[0] + gX * 32 > list_words ||
+        op.sub[1] + gX * 8 * f.tbX * 2 > list_words || op.sub[2] + gX * 16 > list_words ||
+        op.sub[3] + gY * 32 > list_words || op.sub[4] + gY * 8 * f.tbY * 2 > list_words ||
+        op.sub[5] + gY * 16 > list_words)
+        return fail(PA_EINVAL, "internal: fused step would index outside its buffers");
+    return PA_OK;
+}
+
 // Partial sums in the count buffer `buf` of a sparse pass (the decision word
 // follows them).
 static int64_t sparse_nparts_of(const pa_plan *P, int buf) {
@@ -1028,6 +1281,42 @@ static uint32_t *buf_ptr(pa_plan *P, int id, void *out) {
     if (id == kBufOutput) return static_cast<uint32_t *>(out);
     if (id < 0) return nullptr;
     return reinterpret_cast<uint32_t *>(static_cast<char *>(P->ws.ptr) + P->buf_off[id]);
+}
+
+static int64_t buf_words_of(const pa_plan *P, int id, const Layout &l) {
+    return id == kBufOutput ? l.words : P->buf_words[id];
+}
+
+// Arguments of a row-list or fused step with its buffer pointers (bounds
+// checked); out is the caller's output.
+static int list_args(pa_plan *P, const Op &op, void *out, RowListArgs &l) {
+    int rc = check_list_bounds(op, op.la.words, P->buf_words[op.c]);
+    if (rc) return rc;
+    l = op.rl;
+    l.A = buf_ptr(P, op.a, out);
+    uint32_t *lb = buf_ptr(P, op.c, out);
+    l.head = lb + op.sub[0];
+    l.tail = lb + op.sub[1];
+    l.meta = lb + op.sub[2];
+    return PA_OK;
+}
+
+static int fused_args(pa_plan *P, const Op &op, void *out, FusedArgs &f) {
+    int rc = check_fused_bounds(op, P->buf_words[op.a], P->buf_words[op.b], P->buf_words[op.flag],
+                                buf_words_of(P, op.c, op.lc));
+    if (rc) return rc;
+    f = op.fu;
+    f.BtX = buf_ptr(P, op.b, out);
+    f.BtY = buf_ptr(P, op.flag, out);
+    const uint32_t *lb = buf_ptr(P, op.a, out);
+    f.headX = lb + op.sub[0];
+    f.tailX = lb + op.sub[1];
+    f.metaX = lb + op.sub[2];
+    f.headY = lb + op.sub[3];
+    f.tailY = lb + op.sub[4];
+    f.metaY = lb + op.sub[5];
+    f.C = buf_ptr(P, op.c, out);
+    return PA_OK;
 }
 
 // Persistent step list: plots, then ops, sorted by level (a step's level is
@@ -1049,6 +1338,7 @@ static int build_steps(pa_plan *P) {
         level.push_back(0);
     }
     std::vector<int> out_refs;
+    std::map<int, std::vector<int>> list_steps;     // list buffer -> its row-list steps
     int fill_for_next = -1;
     for (size_t oi = 0; oi < P->ops.size(); ++oi) {
         const Op &op = P->ops[oi];
@@ -1091,6 +1381,25 @@ static int build_steps(pa_plan *P) {
                 if (op.c == kBufOutput) out_refs.push_back((int)st.size());
             }
             if (op.flag >= 0) producer[op.flag] = (int)st.size();
+        } else if (op.kind == OP_LIST) {
+            int rc = list_args(P, op, nullptr, s.list);
+            if (rc) return rc;
+            s.kind = kStepList;
+            s.n_tiles = (op.rl.n_rows + 255) / 256;
+            dep(op.a);
+            list_steps[op.c].push_back((int)st.size());
+        } else if (op.kind == OP_FUSED) {
+            int rc = fused_args(P, op, nullptr, s.fused);
+            if (rc) return rc;
+            s.kind = kStepFused;
+            s.n_tiles = op.fu.n_tiles;
+            for (int ls : list_steps[op.a]) {
+                s.dep[s.ndep++] = ls;
+                lv = std::max(lv, level[ls] + 1);
+            }
+            dep(op.b);
+            dep(op.flag);
+            if (op.c == kBufOutput) out_refs.push_back((int)st.size());
         } else if (op.kind == OP_GEMM) {
             int rc = check_gemm_bounds(op.ga, op.la.words, op.lb.words, op.lc.words);
             if (rc) return rc;
@@ -1237,6 +1546,7 @@ static void patch_outputs(pa_plan *P, const std::vector<void *> &outs) {
         if (s.kind == kStepGemm) s.gemm.C = o;
         else if (s.kind == kStepContract) s.ca.C = o;
         else if (s.kind == kStepGather) s.gather.C = o;
+        else if (s.kind == kStepFused) s.fused.C = o;
         else if (s.kind == kStepFill) s.fill_ptr = o;
     }
 }
@@ -1265,6 +1575,17 @@ int upload_plan(pa_plan *P) {
         if (op.ktab_off >= 0)
             HIP_TRY(hipMemcpy(base + op.ktab_off, op.ktab.data(), op.ktab.size() * sizeof(int64_t),
                               hipMemcpyHostToDevice));
+    for (const auto &op : P->ops)
+        if (op.kind == OP_FUSED) {
+            // the per-op launch's one-step table (its output pointer is passed apart)
+            PStep st;
+            std::memset(&st, 0, sizeof(st));
+            st.kind = kStepFused;
+            st.n_tiles = op.fu.n_tiles;
+            int rc = fused_args(P, op, nullptr, st.fused);
+            if (rc) return rc;
+            HIP_TRY(hipMemcpy(base + op.fargs_off, &st, sizeof(st), hipMemcpyHostToDevice));
+        }
     int rc = build_steps(P);
     if (rc) return rc;
     // counters and executor state start at zero (plot counters only grow)
@@ -1304,6 +1625,19 @@ static int run_ops(pa_plan *P, void *out, hipStream_t s, int *launches) {
             g.C = buf_ptr(P, op0.c, out);
             g.dense = op0.flag >= 0 ? buf_ptr(P, op0.flag, out) + sparse_nparts_of(P, op0.flag) : nullptr;
             HIP_TRY(launch_gemm(g, s));
+            ++*launches;
+        } else if (op0.kind == OP_LIST) {
+            RowListArgs l;
+            int rc = list_args(P, op0, out, l);
+            if (rc) return rc;
+            HIP_TRY(launch_row_list(l, s));
+            ++*launches;
+        } else if (op0.kind == OP_FUSED) {
+            FusedArgs f;
+            int rc = fused_args(P, op0, out, f);
+            if (rc) return rc;
+            HIP_TRY(launch_fused(reinterpret_cast<const PStep *>(static_cast<char *>(P->ws.ptr) + op0.fargs_off),
+                                 op0.fu.n_tiles, f.C, s));
             ++*launches;
         } else if (op0.kind == OP_COUNT || op0.kind == OP_GATHER) {
             const bool pass = op0.kind == OP_GATHER;
@@ -1370,7 +1704,8 @@ static int run_persist(pa_plan *P, hipStream_t s, int *launches, hipEvent_t befo
     if (P->single_launch) {
         for (const PStep &st : P->steps_host)
             if ((st.kind == kStepGemm && (st.gemm.path >= 2 || st.gemm.dense)) || st.kind == kStepGather ||
-                st.kind == kStepCount || (st.kind == kStepPlot && st.plot.rule != kRuleCorner))
+                st.kind == kStepCount || st.kind == kStepList || st.kind == kStepFused ||
+                (st.kind == kStepPlot && st.plot.rule != kRuleCorner))
                 return fail(PA_EINVAL,
                             "internal: 256-row MFMA tiles, a sparse pass or a centre plot in a single persistent launch");
         HIP_TRY(launch_persist(d_steps, reinterpret_cast<const PGroup *>(base + P->pgroups_off), P->n_pgroups,
@@ -1586,6 +1921,32 @@ pa_plan::~pa_plan() {
     if (graph_h) (void)hipGraphDestroy(graph_h);
 }
 
+// PA_OPKIND_* of an op, and of a group of steps (kind, mode).
+static int op_kind_code(const Op &op) {
+    switch (op.kind) {
+        case OP_GEMM: return PA_OPKIND_GEMM;
+        case OP_FILL: return PA_OPKIND_FILL;
+        case OP_GATHER: return PA_OPKIND_GATHER;
+        case OP_COUNT: return PA_OPKIND_COUNT;
+        case OP_LIST: return PA_OPKIND_ROWLIST;
+        case OP_FUSED: return PA_OPKIND_FUSED;
+        default: return op.mode;
+    }
+}
+
+static int step_kind_code(int kind, int mode) {
+    switch (kind) {
+        case kStepPlot: return PA_OPKIND_PLOT;
+        case kStepGemm: return PA_OPKIND_GEMM;
+        case kStepFill: return PA_OPKIND_FILL;
+        case kStepGather: return PA_OPKIND_GATHER;
+        case kStepCount: return PA_OPKIND_COUNT;
+        case kStepList: return PA_OPKIND_ROWLIST;
+        case kStepFused: return PA_OPKIND_FUSED;
+        default: return mode;
+    }
+}
+
 extern "C" int32_t pa_plan_op_times(pa_plan *P, double *ms, int32_t *kind, double *macs, int32_t cap) {
     if (!P || P->op_events.empty() || !P->op_events_recorded) return fail(PA_EINVAL, "op_times: no op timings"), -1;
     const bool per_op = P->per_op;
@@ -1603,21 +1964,12 @@ extern "C" int32_t pa_plan_op_times(pa_plan *P, double *ms, int32_t *kind, doubl
             mc = 0.0;
             if (i > 0) {
                 const Op &op = P->ops[i - 1];
-                k = op.kind == OP_GEMM     ? PA_OPKIND_GEMM
-                    : op.kind == OP_FILL   ? PA_OPKIND_FILL
-                    : op.kind == OP_GATHER ? PA_OPKIND_GATHER
-                    : op.kind == OP_COUNT  ? PA_OPKIND_COUNT
-                                           : op.mode;
-                mc = (op.kind == OP_FILL || op.kind == OP_COUNT) ? 0.0 : op.macs;
+                k = op_kind_code(op);
+                mc = (op.kind == OP_FILL || op.kind == OP_COUNT || op.kind == OP_LIST) ? 0.0 : op.macs;
             }
         } else if (groups) {
             const auto &g = P->groups[i];
-            k = g.kind == kStepPlot     ? PA_OPKIND_PLOT
-                : g.kind == kStepGemm   ? PA_OPKIND_GEMM
-                : g.kind == kStepFill   ? PA_OPKIND_FILL
-                : g.kind == kStepGather ? PA_OPKIND_GATHER
-                : g.kind == kStepCount  ? PA_OPKIND_COUNT
-                                        : g.mode;
+            k = step_kind_code(g.kind, g.mode);
             mc = 0.0;
             for (int j = g.first; j < g.first + g.count; ++j) mc += P->step_macs[j];
         }
@@ -1652,13 +2004,7 @@ int time_groups(pa_plan *P, int32_t reps, double *ms, int32_t *kind, double *mac
             rc = fail(PA_EHIP, "time_groups: event timing failed");
         if (!rc && gi < cap) {
             if (ms) ms[gi] = (double)t / reps;
-            if (kind)
-                kind[gi] = g.kind == kStepPlot     ? PA_OPKIND_PLOT
-                           : g.kind == kStepGemm   ? PA_OPKIND_GEMM
-                           : g.kind == kStepFill   ? PA_OPKIND_FILL
-                           : g.kind == kStepGather ? PA_OPKIND_GATHER
-                           : g.kind == kStepCount  ? PA_OPKIND_COUNT
-                                                   : g.mode;
+            if (kind) kind[gi] = step_kind_code(g.kind, g.mode);
             double mc = 0.0;
             for (int j = g.first; j < g.first + g.count; ++j) mc += P->step_macs[j];
             if (macs) macs[gi] = mc;
@@ -1749,8 +2095,7 @@ extern "C" int pa_plan_execute(pa_plan *P, pa_bitarray *out, pa_report *rep, voi
         rep->nnz_out = (int64_t)nnz;
         rep->n_launches = launches;
         int steps = 0;
-        for (const auto &op : P->ops)
-            if (op.kind != OP_FILL && op.kind != OP_COUNT && !(op.kind == OP_GATHER && op.flag >= 0) && op.b != -1) ++steps;
+        for (const auto &op : P->ops) steps += counted_steps_of(op);
         rep->n_steps = steps;
         rep->cost_macs = P->tree.cost;
         for (size_t i = 0; i < P->tree.merges.size() && i < 2 * PA_MAX_RELATIONS; ++i) rep->merges[i] = P->tree.merges[i];

@@ -83,7 +83,7 @@ int plan_exhaustive(const SysInfo &si, Tree &t);
 int plan_learned(const SysInfo &si, const pa_model *model, Tree &t);
 
 // ---------------------------------------------------------------- op list
-enum OpKind { OP_CONTRACT = 0, OP_GEMM = 1, OP_FILL = 2, OP_GATHER = 3, OP_COUNT = 4 };
+enum OpKind { OP_CONTRACT = 0, OP_GEMM = 1, OP_FILL = 2, OP_GATHER = 3, OP_COUNT = 4, OP_LIST = 5, OP_FUSED = 6 };
 
 constexpr int kBufOutput = -2;
 
@@ -94,6 +94,14 @@ struct Op {
     int flag = -1;                // sparse pass (OP_COUNT, OP_GATHER: b is the Bt plot) and its
                                   // MFMA contraction: the two-word buffer of A's set-bit count
     GatherArgs gg{};              // OP_COUNT, OP_GATHER (pointers patched at execution)
+    // OP_LIST (a: the pass's A, c: the list buffer) and OP_FUSED (a: the list
+    // buffer, b: BtX, flag: BtY); pointers patched at execution from word
+    // offsets into the list buffer: OP_LIST head, tail, meta in sub[0..2],
+    // OP_FUSED X's in sub[0..2] and Y's in sub[3..5]
+    RowListArgs rl{};
+    FusedArgs fu{};
+    int64_t sub[6] = {0, 0, 0, 0, 0, 0};
+    int64_t fargs_off = -1;       // OP_FUSED: byte offset of a one-step table in the workspace (per-op launches)
     Layout la, lb, lc;
     std::vector<int> kvars;
     ContractArgs ca{};            // pointers patched at execution
@@ -107,6 +115,18 @@ struct Op {
     int node = -1;
     std::string describe() const;
 };
+
+// Pairwise contractions an op computes, as counted in reports: a fused
+// pass pair computes three (its two passes and their streamed contraction);
+// projections of one operand, fills, count and row-list steps, and a sparse
+// pass whose MFMA contraction is counted, none.
+inline int counted_steps_of(const Op &op) {
+    if (op.kind == OP_FUSED) return 3;
+    if (op.kind == OP_FILL || op.kind == OP_COUNT || op.kind == OP_LIST || (op.kind == OP_GATHER && op.flag >= 0) ||
+        op.b == -1)
+        return 0;
+    return 1;
+}
 
 struct PlotItem {
     int rel = -1;
@@ -172,6 +192,7 @@ struct pa_plan {
     int64_t n_items = 0;
     int per_op = 0, graph = 0, single_launch = 0, persist_wg = 0, plot_strip = 0, contract_units = 0, gemm_split = 512, gemm_path = 0;
     int sparse_pass = 0, sparse_max_density = 64;
+    bool fuse_passes = false;          // sparse_pass 3: pairs of passes fused into their streamed step
     struct Group {
         int kind, mode, first, count;
         int64_t t0, t1;

@@ -220,10 +220,12 @@ int autotune(const pa_system *systems, int32_t n_sys, const int32_t *const *expo
         rc = trial(t);
     }
     // 4) the sparse pass alone (exact whatever the density; faster when the
-    // plotted operands are sparse and the contractions large)
-    if (!rc && best.ms >= 0.0 && base.sparse_pass == 0) {
+    // plotted operands are sparse and the contractions large), then with
+    // pairs of passes fused into the streamed contraction that reads them
+    for (int sp : {2, 3}) {
+        if (rc || best.ms < 0.0 || base.sparse_pass != 0) break;
         pa_tuning t = best;
-        t.sparse_pass = 2;
+        t.sparse_pass = sp;
         rc = trial(t);
     }
     for (void *p : bufs) (void)hipFree(p);

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libpa.so")
 PA_OK, PA_EINVAL, PA_ENOMEM, PA_EHIP, PA_EUNSUPPORTED = 0, 1, 2, 3, 4
 ORDER_GREEDY, ORDER_EXHAUSTIVE, ORDER_LEARNED, ORDER_GIVEN = 0, 1, 2, 3
 OPKIND_BITS, OPKIND_STREAM_K, OPKIND_STREAM_W, OPKIND_GEMM, OPKIND_FILL = 0, 1, 2, 10, 20
-OPKIND_GATHER, OPKIND_COUNT, OPKIND_PLOT, OPKIND_PERSIST = 25, 26, 30, 40
+OPKIND_GATHER, OPKIND_COUNT, OPKIND_ROWLIST, OPKIND_FUSED, OPKIND_PLOT, OPKIND_PERSIST = 25, 26, 27, 28, 30, 40
 PLOT_FP32_ESCALATE, PLOT_FP64 = 0, 1
 RULE_CORNER, RULE_CENTER = 0, 1
 TARGET_EQ, TARGET_LE, TARGET_LT = 0, 1, 2

@@ -126,10 +126,61 @@ def test_sparse_pass_plan():
     for kw in (dict(plain=True), dict(single_launch=True), dict(sparse_pass=-1)):
         for s in (inputs.config2(), inputs.config3()):
             assert not [o for o in pa.describe_plan(s, **kw)["ops"] if o["op"].startswith("sparse")], kw
-    assert _bad(inputs.config1(), sparse_pass=3) == pa.PA_EINVAL
+    assert _bad(inputs.config1(), sparse_pass=4) == pa.PA_EINVAL
     assert _bad(inputs.config1(), sparse_pass=-2) == pa.PA_EINVAL
     assert _bad(inputs.config1(), sparse_max_density=-1) == pa.PA_EINVAL
     assert _bad(inputs.config1(), sparse_max_density=1025) == pa.PA_EINVAL
+
+
+def _fused_system(res, seed=1, c0=0.0):
+    """Four ternary relations wired as the ternary workload (every pair of
+    relations shares one variable, (v0, v3) exposed) at the resolutions
+    `res`; c0 is added to every constant coefficient."""
+    rng = inputs.SplitMix64(seed)
+    rels = [inputs.random_relation(rng, st) for st in [(0, 1, 2), (2, 3, 4), (4, 5, 0), (1, 3, 5)]]
+    for r in rels:
+        r.coef[0] = r.coef[0] + c0
+    return inputs.System([(-3.0, 3.0, r) for r in res], rels, (0, 3), name=f"fused{res}")
+
+
+def test_fused_pass_pair_plan():
+    """sparse_pass = 3 fuses the ternary workload's two passes and their
+    streamed contraction: two row-list steps (one per pass, 65536 list rows,
+    LDS rows 0..255 and 256..511, zero row 512) and one fused step of
+    256 tiles of 8 x 32 outputs; the 2 x 512 MiB pass outputs are gone from
+    the workspace, and the fused step counts the MACs of all three."""
+    s = inputs.config3()
+    d2, d3 = pa.describe_plan(s, sparse_pass=2), pa.describe_plan(s, sparse_pass=3)
+    assert _kernels(d3) == ["row_list", "row_list", "fused_pass_pair"]
+    lx, ly, f = d3["ops"]
+    assert lx["rows"] == ly["rows"] == 65536 and lx["lbase"] == 0 and ly["lbase"] == 256
+    assert lx["zrow"] == ly["zrow"] == 512 and lx["tail_batches"] == ly["tail_batches"] == 62
+    assert (f["n_p"], f["n_q"], f["n_s"], f["rwt"], f["kx"], f["ky"], f["tiles"]) == (256, 256, 256, 8, 256, 256, 256)
+    assert f["lists"] == lx["c"] == ly["c"] and f["c"] == -2 and f["c_vars"] == [0, 3]
+    assert f["macs"] == sum(o.get("dense_macs", 0) for o in d2["ops"] if o["op"] == "sparse_pass") + \
+        [o for o in d2["ops"] if o["op"] == "stream_k"][0]["macs"]
+    assert d2["workspace_bytes"] > 2 * 2 ** 29 and d3["workspace_bytes"] < 80 * 2 ** 20
+    # uneven resolutions: the packed latent variable of 5 .. 256 bits, ragged
+    # 8-blocks and 32-bit output words, either pass in the X role
+    for res in ([31, 5, 255, 9, 17, 40], [37, 29, 200, 45, 33, 51], [24, 33, 33, 9, 5, 256],
+                [129, 255, 256, 13, 24, 255]):
+        d = pa.describe_plan(_fused_system(res), sparse_pass=3)
+        assert _kernels(d) == ["row_list", "row_list", "fused_pass_pair"], res
+    # no pattern, no fusion: the chain's passes feed MFMA contractions
+    assert _kernels(pa.describe_plan(inputs.config2(), sparse_pass=3)) == \
+        _kernels(pa.describe_plan(inputs.config2(), sparse_pass=2))
+
+
+def test_large_k_mfma_plan_is_valid():
+    """A random hypergraph at 128 whose greedy tree has an MFMA contraction of
+    65536 K words in one part: plans are checked against their buffers at
+    planning time, and such a K range is valid (fp32 sums of non-negative
+    products cannot round a positive sum to zero)."""
+    rng = inputs.SplitMix64(9011)
+    g = inputs.random_hypergraph(rng, res=128)
+    d = pa.describe_plan(g, order=pa.ORDER_GREEDY)
+    big = [o for o in d["ops"] if o["op"] == "gemm_mfma" and o["Kw"] > 16384]
+    assert big and big[0]["ksplit"] == 1
 
 
 def test_exhaustive_prefers_parallel_trees_on_ties():

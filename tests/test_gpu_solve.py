@@ -203,8 +203,8 @@ def test_c3_full_size_exact():
     entry by entry with the oracle (plots, then the cluster tree
     {{R1, R2}, {R3, R4}} multiplied pairwise), for the default plan (sparse
     pass with MFMA fallback), the MFMA kernel alone on both operand paths,
-    the fallback taken (density threshold 1/1024), the pass alone, and the
-    plain path."""
+    the fallback taken (density threshold 1/1024), the pass alone, the two
+    passes fused with the streamed contraction, and the plain path."""
     s = inputs.config3()
     note("c3 full: oracle plots and pairwise solve")
     plots = _oracle_plots(s)
@@ -215,7 +215,8 @@ def test_c3_full_size_exact():
     note("c3 full: oracle nnz", int(ref.sum()))
     assert [o["op"] for o in pa.describe_plan(s)["ops"]].count("sparse_pass") == 2
     for kw in (dict(), dict(sparse_pass=-1), dict(sparse_pass=-1, gemm_path=2), dict(sparse_max_density=1),
-               dict(sparse_pass=2), dict(plain=True, order=pa.ORDER_GREEDY)):
+               dict(sparse_pass=2), dict(sparse_pass=3), dict(sparse_pass=3, per_op=True),
+               dict(plain=True, order=pa.ORDER_GREEDY)):
         got, rep = _solve(s, **kw)
         note("c3 full", kw, "nnz", int(got.sum()), "flagged", rep["corners_flagged"])
         assert np.array_equal(got, ref), kw
