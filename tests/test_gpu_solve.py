@@ -61,10 +61,19 @@ def test_random_hypergraphs_all_policies(seed):
         assert np.array_equal(got, ref), order
         outs.append(got)
     # a deliberately poor given order (left to right) gives the same bits,
-    # or is refused with PA_ENOMEM when its intermediates cannot fit
+    # or is refused: when planned if an intermediate has more rows than the
+    # kernels index (PA_EUNSUPPORTED), with PA_ENOMEM when its intermediates
+    # cannot fit
     n = len(s.relations)
     merges = [0, 1] + [x for t in range(1, n - 1) for x in (n + t - 1, t + 1)]
-    need = pa.describe_plan(s, order=pa.ORDER_GIVEN, given=merges)["workspace_bytes"]
+    d = pa.describe_plan(s, order=pa.ORDER_GIVEN, given=merges)
+    if "error" in d:
+        assert d["error"] == pa.PA_EUNSUPPORTED
+        with pytest.raises(pa.PaError) as e:
+            _solve(s, order=pa.ORDER_GIVEN, given=merges)
+        assert e.value.code == pa.PA_EUNSUPPORTED
+        return
+    need = d["workspace_bytes"]
     if need < 2 ** 30:
         got, _ = _solve(s, order=pa.ORDER_GIVEN, given=merges)
         assert np.array_equal(got, ref)
