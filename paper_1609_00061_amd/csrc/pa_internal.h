@@ -219,11 +219,11 @@ struct RowListArgs {
 };
 
 constexpr int kFusedRows = 513;                        // LDS rows of a fused tile: BtX, BtY, the zero row
-constexpr int kFusedLdsWords = kFusedRows * 64 + 12;   // 64 words per row, the tile's 8 output words, 4 counters
+constexpr int kFusedLdsWords = kFusedRows * 64 + 9;    // 64 words per row, the tile's 8 output bytes, a counter
 
-// A fused tile: 8 p (block pb) x 32 q (word qw of the output rows, four
-// 8-q blocks in turn); tile = pb n_qw + qw.  Bt rows hold n_o x rwt words
-// (rwt <= 8: the o-th 8-word slot of a staged LDS row is padded with zeros).
+// A fused tile: 8 p (block pb) x 8 q (block qb); tile = pb n_qb + qb.  Bt
+// rows hold n_o x rwt words (rwt <= 8: the o-th 8-word slot of a staged LDS
+// row is padded with zeros).
 struct FusedArgs {
     const uint32_t *BtX, *BtY;
     const uint32_t *headX, *tailX, *metaX, *headY, *tailY, *metaY;
@@ -233,7 +233,7 @@ struct FusedArgs {
     int rwt, kX, kY;          // words of t; LDS rows of BtX (0..kX-1) and BtY (kX..kX+kY-1)
     int64_t tbX, tbY;         // tail batches per list row of X, Y
     int64_t c_rw;             // output row words
-    int64_t n_qw, n_tiles;    // ceil(n_q / 32); ceil(n_p / 8) n_qw
+    int64_t n_qb, n_tiles;    // ceil(n_q / 8); ceil(n_p / 8) n_qb
 };
 
 // Wave-tiles of a sparse pass (2048 words of one output row each).

@@ -2424,67 +2424,63 @@ __device__ __forceinline__ void fused_transpose8(uint32_t (&c)[8]) {
     }
 }
 
-// One fused tile (1024 threads, 16 waves): 8 p x 32 q of the output.  BtX's
-// rows for the tile's 8 p are staged once, BtY's for each 8-q block in
-// turn; the waves split the latent entries s.  For one s a wave gathers
-// X[q][s][p][w] as x[q] in lane (p, w) and Y[p][s][q][w] as y[p] in lane
-// (q, w), transposes y to lane (p, w) and keeps the OR of x[q] AND y[q].
+// One fused tile (1024 threads, 16 waves): 8 p x 8 q of the output (tile =
+// pb n_qb + qb; many more tiles than CUs, so that the dispatcher balances
+// tiles of uneven density).  The rows of BtX for the tile's 8 p and of BtY
+// for its 8 q are staged in LDS; the waves take latent entries s from a
+// counter.  For one s a wave gathers X[q][s][p][w] as x[q] in lane (p, w)
+// and Y[p][s][q][w] as y[p] in lane (q, w), transposes y to lane (p, w) and
+// keeps the OR of x[q] AND y[q].  The tile writes byte qb of its 8 output
+// rows (the tile of the last q block also zeroes the row's padding bytes).
 __device__ __forceinline__ void fused_tile(const FusedArgs &f, int64_t tile, uint32_t *lds) {
-    const int64_t pb = tile / f.n_qw, qw = tile - pb * f.n_qw, p0 = pb * 8;
+    const int64_t pb = tile / f.n_qb, qb = tile - pb * f.n_qb, p0 = pb * 8;
     const int tid = threadIdx.x, lane = tid & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    uint32_t *out = lds + kFusedRows * 64;     // 8 output words, then 4 latent-entry counters
+    uint32_t *out = lds + kFusedRows * 64;     // 8 output bytes (a word each), the latent-entry counter
     fused_stage(lds, f.BtX, f.btX_rw, f.kX, p0, f.n_p, f.rwt, 0);
+    fused_stage(lds, f.BtY, f.btY_rw, f.kY, qb * 8, f.n_q, f.rwt, f.kX);
     if (tid < 64) lds[(f.kX + f.kY) * 64 + tid] = 0u;
-    if (tid < 12) out[tid] = 0u;
-    for (int j = 0; j < 4; ++j) {
-        const int64_t qb = qw * 4 + j;
-        if (qb * 8 >= f.n_q) break;
-        fused_stage(lds, f.BtY, f.btY_rw, f.kY, qb * 8, f.n_q, f.rwt, f.kX);
-        __syncthreads();
-        uint32_t acc[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
-        // the waves take latent entries from a counter, the next one while
-        // working on the current
-        auto grab = [&]() {
-            uint32_t v = 0;
-            if (lane == 0) v = atomicAdd(out + 8 + j, 1u);
-            return (int64_t)__builtin_amdgcn_readfirstlane(v);
-        };
-        // lane l < 32 loads head word l of Y's group, lane 32 + l word l of
-        // X's; lanes 0..15 and 16..31 the meta words of Y's and X's
-        auto fetch = [&](int64_t s, uint32_t &hw, uint32_t &mw) {
-            const int64_t gx = qb * f.n_s + s, gy = pb * f.n_s + s;
-            hw = lane < 32 ? gp(f.headY)[gy * 32 + lane] : gp(f.headX)[gx * 32 + lane - 32];
-            mw = lane < 16 ? gp(f.metaY)[gy * 16 + lane] : gp(f.metaX)[gx * 16 + ((lane - 16) & 15)];
-        };
-        int64_t s = grab();
-        uint32_t hw = 0, mw = 0;
-        if (s < f.n_s) fetch(s, hw, mw);
-        while (s < f.n_s) {
-            const int64_t sn = grab();
-            uint32_t hn = 0, mn = 0;
-            if (sn < f.n_s) fetch(sn, hn, mn);
-            uint32_t x[8], y[8];
-            fused_rows<0, 0>(lds, lane, hw, mw, (const PA_K uint32_t *)f.tailY, y);
-            fused_rows<32, 16>(lds, lane, hw, mw, (const PA_K uint32_t *)f.tailX, x);
-            fused_transpose8(y);
+    if (tid < 9) out[tid] = 0u;
+    __syncthreads();
+    uint32_t acc[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
+    auto grab = [&]() {
+        uint32_t v = 0;
+        if (lane == 0) v = atomicAdd(out + 8, 1u);
+        return (int64_t)__builtin_amdgcn_readfirstlane(v);
+    };
+    // lane l < 32 loads head word l of Y's group, lane 32 + l word l of X's;
+    // lanes 0..15 and 16..31 the meta words of Y's and X's
+    auto fetch = [&](int64_t s, uint32_t &hw, uint32_t &mw) {
+        const int64_t gx = qb * f.n_s + s, gy = pb * f.n_s + s;
+        hw = lane < 32 ? gp(f.headY)[gy * 32 + lane] : gp(f.headX)[gx * 32 + lane - 32];
+        mw = lane < 16 ? gp(f.metaY)[gy * 16 + lane] : gp(f.metaX)[gx * 16 + ((lane - 16) & 15)];
+    };
+    int64_t s = grab();
+    uint32_t hw = 0, mw = 0;
+    if (s < f.n_s) fetch(s, hw, mw);
+    while (s < f.n_s) {
+        const int64_t sn = grab();
+        uint32_t hn = 0, mn = 0;
+        if (sn < f.n_s) fetch(sn, hn, mn);
+        uint32_t x[8], y[8];
+        fused_rows<0, 0>(lds, lane, hw, mw, (const PA_K uint32_t *)f.tailY, y);
+        fused_rows<32, 16>(lds, lane, hw, mw, (const PA_K uint32_t *)f.tailX, x);
+        fused_transpose8(y);
 #pragma unroll
-            for (int i = 0; i < 8; ++i) acc[i] |= x[i] & y[i];
-            s = sn;
-            hw = hn;
-            mw = mn;
-        }
-        uint32_t bits = 0;
-#pragma unroll
-        for (int i = 0; i < 8; ++i) bits |= (acc[i] != 0u ? 1u : 0u) << i;
-        if (bits) atomicOr(out + (lane >> 3), bits << (8 * j));
-        __syncthreads();
+        for (int i = 0; i < 8; ++i) acc[i] |= x[i] & y[i];
+        s = sn;
+        hw = hn;
+        mw = mn;
     }
+    uint32_t bits = 0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) bits |= (acc[i] != 0u ? 1u : 0u) << i;
+    if (bits) atomicOr(out + (lane >> 3), bits);
+    __syncthreads();
     if (tid < 8 && p0 + tid < f.n_p) {
-        PA_G uint32_t *row = gp(f.C) + (p0 + tid) * f.c_rw;
-        row[qw] = out[tid];
-        if (qw == f.n_qw - 1)
-            for (int64_t w = qw + 1; w < f.c_rw; ++w) row[w] = 0u;
+        PA_G uint8_t *row = reinterpret_cast<PA_G uint8_t *>(gp(f.C) + (p0 + tid) * f.c_rw);
+        row[qb] = (uint8_t)out[tid];
+        if (qb == f.n_qb - 1)
+            for (int64_t b = qb + 1; b < 4 * f.c_rw; ++b) row[b] = 0;
     }
 }
 

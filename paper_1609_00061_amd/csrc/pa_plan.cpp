@@ -979,8 +979,8 @@ static void fuse_pass_pairs(pa_plan *P) {
         f.tbX = tbX;
         f.tbY = tbY;
         f.c_rw = S.lc.rw;
-        f.n_qw = (n_q + 31) / 32;
-        f.n_tiles = (n_p + 7) / 8 * f.n_qw;
+        f.n_qb = (n_q + 7) / 8;
+        f.n_tiles = (n_p + 7) / 8 * f.n_qb;
         for (int k = 0; k < 6; ++k) F.sub[k] = sub[k];
         std::vector<Op> ops;
         for (size_t k = 0; k < P->ops.size(); ++k) {
@@ -1260,8 +1260,8 @@ static int check_fused_bounds(const Op &op, int64_t list_words, int64_t btx_word
     if (f.n_p < 1 || f.n_q < 1 || f.n_s < 1 || f.rwt < 1 || f.rwt > 8 || f.kX < 1 || f.kY < 1 ||
         f.kX + f.kY + 1 > kFusedRows || f.btX_rw < f.n_p * f.rwt || f.btY_rw < f.n_q * f.rwt ||
         (int64_t)f.kX * f.btX_rw > btx_words || (int64_t)f.kY * f.btY_rw > bty_words ||
-        f.n_qw != (f.n_q + 31) / 32 || f.c_rw < f.n_qw || f.n_p * f.c_rw > c_words ||
-        f.n_tiles != (f.n_p + 7) / 8 * f.n_qw || op.sub[0] + gX * 32 > list_words ||
+        f.n_qb != (f.n_q + 7) / 8 || 4 * f.c_rw < f.n_qb || f.n_p * f.c_rw > c_words ||
+        f.n_tiles != (f.n_p + 7) / 8 * f.n_qb || op.sub[0] + gX * 32 > list_words ||
         op.sub[1] + gX * 8 * f.tbX * 2 > list_words || op.sub[2] + gX * 16 > list_words ||
         op.sub[3] + gY * 32 > list_words || op.sub[4] + gY * 8 * f.tbY * 2 > list_words ||
         op.sub[5] + gY * 16 > list_words)

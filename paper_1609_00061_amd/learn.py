@@ -87,7 +87,7 @@ def collect_samples(systems: Sequence, n_random: int = 3, reps: int = 3, seed: i
             try:
                 plan = pa.Plan(s, per_op=True, timing=2, **dict(kw, measure_density=measure_density))
             except pa.PaError as e:          # a tree whose intermediates exceed the workspace cap
-                if e.code == pa.PA_ENOMEM:
+                if e.code in (pa.PA_ENOMEM, pa.PA_EUNSUPPORTED):   # or the kernels' 32-bit indexing
                     continue
                 raise
             out = pa.empty_bits(plan.dims)
@@ -178,7 +178,7 @@ def time_policies(systems: Sequence, model, policies=("greedy", "exhaustive", "l
                                    verify_order=(p == "learned_verified"), measure_density=measure_density and learned)
                 res[p]["plan_ms"].append(1e3 * (time.perf_counter() - t0))
         except pa.PaError as e:              # some policy's tree does not fit the workspace cap
-            if e.code != pa.PA_ENOMEM:
+            if e.code not in (pa.PA_ENOMEM, pa.PA_EUNSUPPORTED):   # or the kernels' 32-bit indexing
                 raise
             for p in plans:
                 res[p]["plan_ms"].pop()

@@ -147,7 +147,7 @@ def test_fused_pass_pair_plan():
     """sparse_pass = 3 fuses the ternary workload's two passes and their
     streamed contraction: two row-list steps (one per pass, 65536 list rows,
     LDS rows 0..255 and 256..511, zero row 512) and one fused step of
-    256 tiles of 8 x 32 outputs; the 2 x 512 MiB pass outputs are gone from
+    1024 tiles of 8 x 8 outputs; the 2 x 512 MiB pass outputs are gone from
     the workspace, and the fused step counts the MACs of all three."""
     s = inputs.config3()
     d2, d3 = pa.describe_plan(s, sparse_pass=2), pa.describe_plan(s, sparse_pass=3)
@@ -155,7 +155,7 @@ def test_fused_pass_pair_plan():
     lx, ly, f = d3["ops"]
     assert lx["rows"] == ly["rows"] == 65536 and lx["lbase"] == 0 and ly["lbase"] == 256
     assert lx["zrow"] == ly["zrow"] == 512 and lx["tail_batches"] == ly["tail_batches"] == 62
-    assert (f["n_p"], f["n_q"], f["n_s"], f["rwt"], f["kx"], f["ky"], f["tiles"]) == (256, 256, 256, 8, 256, 256, 256)
+    assert (f["n_p"], f["n_q"], f["n_s"], f["rwt"], f["kx"], f["ky"], f["tiles"]) == (256, 256, 256, 8, 256, 256, 1024)
     assert f["lists"] == lx["c"] == ly["c"] and f["c"] == -2 and f["c_vars"] == [0, 3]
     assert f["macs"] == sum(o.get("dense_macs", 0) for o in d2["ops"] if o["op"] == "sparse_pass") + \
         [o for o in d2["ops"] if o["op"] == "stream_k"][0]["macs"]
