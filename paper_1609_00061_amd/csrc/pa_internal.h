@@ -200,14 +200,19 @@ constexpr int64_t kCountTileWords = 8192;    // A words per tile of a count step
 // Row lists: rows are taken in groups of 8 consecutive values of the row's
 // output variable o (o-block ob) for one s: group g = ob * n_s + s, list
 // row 8 g + i for o = 8 ob + i.  A list row holds its set bits k as the LDS
-// word offsets 64 (lbase + k) of their rows (16 bits each), four to a
-// batch, padded with the all-zero row zrow: batches 0 and 1 in the head (32
-// words per group: batch 0 of row i in words 2i, 2i + 1, batch 1 in words
-// 16 + 2i, 17 + 2i), the rest in the tail (tb batches of 2 words per row).
-// Per group 16 meta words: bit i of word 0 is set when row i has more than
-// one batch, word 8 + i holds the number of its batches after the first
-// (bits 0..5) and the word offset of its tail batches in the tail (bits
-// 6..31).  Rows with o >= n_o have no set bits.
+// word offsets 64 (lbase + k) of their rows (16 bits each), padded with the
+// all-zero row zrow: batch 0 (kListB0 entries; two measured no faster on
+// the ternary workload, whose rows mostly hold two set bits: the rows with
+// more cost a branch and a wait each) and batch 1 (four) in the head (32 words per
+// group: batch 0 of row i in words kListB0/2 i .., batch 1 in words
+// 4 kListB0 + 2i, 4 kListB0 + 2i + 1), the rest in the tail (tb batches of
+// four entries, 2 words each, per row).  Per group 16 meta words: bit i of
+// word 0 is set when row i has more than kListB0 set bits, word 8 + i holds
+// the number of its batches after the first (bits 0..6) and the word
+// offset of its tail batches in the tail (bits 7..31).  Rows with o >= n_o
+// have no set bits.
+constexpr int kListB0 = 4;    // entries in batch 0 of a list row (2 or 4)
+
 struct RowListArgs {
     const uint32_t *A;        // the pass's A operand: row (o, s) at (o ro + s rs) Kw words
     uint32_t *head, *tail, *meta;   // per group: 32 words, 8 tb batches of 2 words, 16 words

@@ -2243,33 +2243,34 @@ hipError_t launch_gather(const GatherArgs &g, hipStream_t s) {
 
 // -------------------------------------------------------- fused pass pair
 // Row lists (one thread per list row, 256 per tile): the set bits of the A
-// row, in increasing order, as LDS word offsets 64 (lbase + k); the first
-// eight in the head, the rest in the tail; unused entries of the last batch
-// name the zero row.  The group's meta words: bit i of word 0 is set when
-// row i has more than one batch, word 8 + i holds the number of row i's
-// batches after the first (bits 0..5) and its tail's word offset (bits
-// 6..31).
+// row, in increasing order, as LDS word offsets 64 (lbase + k): the first
+// kListB0 in batch 0, the next four in batch 1 (both in the head), the rest
+// in the tail in batches of four; unused entries of a batch name the zero
+// row.  The group's meta words: bit i of word 0 is set when row i has more
+// than kListB0 set bits, word 8 + i holds the number of row i's batches
+// after the first (bits 0..6) and its tail's word offset (bits 7..31).
 __device__ __forceinline__ void row_list_tile(const RowListArgs &L, int64_t tile) {
+    constexpr int B0 = kListB0;
     const int64_t r = tile * 256 + threadIdx.x;
     const bool valid = r < L.n_rows;
     const int64_t g = r >> 3, ob = g / L.n_s, s = g - ob * L.n_s, o = ob * 8 + (r & 7);
     const uint64_t Z = (uint32_t)L.zrow * 64u;
     const uint64_t zz = Z | (Z << 16) | (Z << 32) | (Z << 48);
-    uint64_t lo = zz, hi = zz;              // entries 0..3, 4..7
+    uint64_t b0 = zz, b1 = zz;              // entries 0 .. B0 - 1, B0 .. B0 + 3
     PA_G uint32_t *tail = gp(L.tail) + r * L.tb * 2;
     int cnt = 0;
     uint32_t pend = 0;                      // an even tail entry waiting for its pair
     auto put = [&](uint32_t e) {
-        if (cnt < 4) {
+        if (cnt < B0) {
             const int sh = 16 * cnt;
-            lo = (lo & ~(0xffffull << sh)) | ((uint64_t)e << sh);
-        } else if (cnt < 8) {
-            const int sh = 16 * (cnt - 4);
-            hi = (hi & ~(0xffffull << sh)) | ((uint64_t)e << sh);
-        } else if (((cnt - 8) & 1) == 0) {
+            b0 = (b0 & ~(0xffffull << sh)) | ((uint64_t)e << sh);
+        } else if (cnt < B0 + 4) {
+            const int sh = 16 * (cnt - B0);
+            b1 = (b1 & ~(0xffffull << sh)) | ((uint64_t)e << sh);
+        } else if (((cnt - B0 - 4) & 1) == 0) {
             pend = e;
         } else {
-            tail[(cnt - 8) >> 1] = pend | (e << 16);
+            tail[(cnt - B0 - 4) >> 1] = pend | (e << 16);
         }
         ++cnt;
     };
@@ -2286,18 +2287,22 @@ __device__ __forceinline__ void row_list_tile(const RowListArgs &L, int64_t tile
         }
     }
     const int n = cnt;
-    if (n > 8)
-        while (cnt & 3) put((uint32_t)Z);          // pad the last tail batch
-    const uint32_t nx = n > 4 ? (uint32_t)((n + 3) / 4 - 1) : 0u;
+    if (n > B0 + 4)
+        while ((cnt - B0) & 3) put((uint32_t)Z);          // pad the last tail batch
+    const uint32_t nx = n > B0 ? 1u + (uint32_t)((max(n - B0 - 4, 0) + 3) / 4) : 0u;
     // rows r of a group are 8 consecutive lanes (tiles hold whole groups)
-    const uint64_t more = __ballot(n > 4);
+    const uint64_t more = __ballot(n > B0);
     if (!valid) return;
-    // batch 0 of the group's 8 rows in words 0..15, batch 1 in 16..31
-    PA_G uint32_t *hd = gp(L.head) + g * 32 + (r & 7) * 2;
-    *reinterpret_cast<PA_G u32x2 *>(hd) = u32x2{(uint32_t)lo, (uint32_t)(lo >> 32)};
-    *reinterpret_cast<PA_G u32x2 *>(hd + 16) = u32x2{(uint32_t)hi, (uint32_t)(hi >> 32)};
-    gp(L.meta)[g * 16 + 8 + (r & 7)] = nx | (uint32_t)(r * L.tb * 2) << 6;
-    if ((r & 7) == 0) gp(L.meta)[g * 16] = (uint32_t)(more >> (__lane_id() & ~7)) & 0xffu;
+    PA_G uint32_t *hd = gp(L.head) + g * 32;
+    const int i = (int)(r & 7);
+    if (B0 == 2) {
+        hd[i] = (uint32_t)b0;
+    } else {
+        *reinterpret_cast<PA_G u32x2 *>(hd + 2 * i) = u32x2{(uint32_t)b0, (uint32_t)(b0 >> 32)};
+    }
+    *reinterpret_cast<PA_G u32x2 *>(hd + 4 * B0 + 2 * i) = u32x2{(uint32_t)b1, (uint32_t)(b1 >> 32)};
+    gp(L.meta)[g * 16 + 8 + i] = nx | (uint32_t)(r * L.tb * 2) << 7;
+    if (i == 0) gp(L.meta)[g * 16] = (uint32_t)(more >> (__lane_id() & ~7)) & 0xffu;
 }
 
 __global__ __launch_bounds__(256) void k_row_list(RowListArgs L, int64_t n_tiles) {
@@ -2366,33 +2371,39 @@ __device__ __forceinline__ uint32_t fused_batch(const uint32_t *lds, int lane, u
 // row i, word `lane`.  The group's 32 head words are lanes b .. b + 31 of
 // hw and its 16 meta words lanes m .. m + 15 of mw (loaded one latent entry
 // ahead with vector loads, read out with v_readlane); the tails (rows of
-// more than eight set bits) through scalar loads from tl.  Batch 0 of every
-// row first (32 reads in flight), then the later batches of the rows that
-// have them.
+// more than kListB0 + 4 set bits) through scalar loads from tl.  Batch 0 of
+// every row first (all its reads in flight), then the later batches of the
+// rows that have them.
 template <int B, int M>
 __device__ __forceinline__ void fused_rows(const uint32_t *lds, int lane, uint32_t hw, uint32_t mw,
                                            const PA_K uint32_t *tl, uint32_t (&c)[8]) {
-    uint32_t r[8][4];
+    constexpr int B0 = kListB0;
+    uint32_t r[8][B0];
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-        const uint32_t w0 = __builtin_amdgcn_readlane(hw, B + 2 * i), w1 = __builtin_amdgcn_readlane(hw, B + 2 * i + 1);
-        r[i][0] = lds[(w0 & 0xffffu) + lane];
-        r[i][1] = lds[(w0 >> 16) + lane];
-        r[i][2] = lds[(w1 & 0xffffu) + lane];
-        r[i][3] = lds[(w1 >> 16) + lane];
-    }
-    __builtin_amdgcn_sched_group_barrier(0x100, 32, 0);
 #pragma unroll
-    for (int i = 0; i < 8; ++i) c[i] = r[i][0] | r[i][1] | r[i][2] | r[i][3];
+        for (int h = 0; h < B0 / 2; ++h) {
+            const uint32_t w = __builtin_amdgcn_readlane(hw, B + (B0 / 2) * i + h);
+            r[i][2 * h] = lds[(w & 0xffffu) + lane];
+            r[i][2 * h + 1] = lds[(w >> 16) + lane];
+        }
+    }
+    __builtin_amdgcn_sched_group_barrier(0x100, 8 * B0, 0);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        c[i] = r[i][0] | r[i][1];
+#pragma unroll
+        for (int h = 2; h < B0; ++h) c[i] |= r[i][h];
+    }
     const uint32_t m = __builtin_amdgcn_readlane(mw, M);
     if (m == 0u) return;
 #pragma unroll
     for (int i = 0; i < 8; ++i)
         if (m & (1u << i)) {
-            c[i] |= fused_batch(lds, lane, __builtin_amdgcn_readlane(hw, B + 16 + 2 * i),
-                                __builtin_amdgcn_readlane(hw, B + 17 + 2 * i));
-            const uint32_t w = __builtin_amdgcn_readlane(mw, M + 8 + i), nx = w & 63u;
-            const PA_K uint32_t *t = tl + (w >> 6);
+            c[i] |= fused_batch(lds, lane, __builtin_amdgcn_readlane(hw, B + 4 * B0 + 2 * i),
+                                __builtin_amdgcn_readlane(hw, B + 4 * B0 + 2 * i + 1));
+            const uint32_t w = __builtin_amdgcn_readlane(mw, M + 8 + i), nx = w & 127u;
+            const PA_K uint32_t *t = tl + (w >> 7);
             for (uint32_t b = 2; b <= nx; ++b) c[i] |= fused_batch(lds, lane, t[2 * (b - 2)], t[2 * (b - 2) + 1]);
         }
 }

@@ -907,7 +907,9 @@ static void fuse_pass_pairs(pa_plan *P) {
         if (GY.lc.rw != rwt || rwt > 8 || X.kall + Y.kall + 1 > kFusedRows) continue;
         // list buffer: per operand the heads, the meta words and the tails
         const int64_t gX = (n_q + 7) / 8 * n_s, gY = (n_p + 7) / 8 * n_s;
-        const int64_t tbX = std::max<int64_t>(1, (X.kall + 3) / 4 - 2), tbY = std::max<int64_t>(1, (Y.kall + 3) / 4 - 2);
+        // tail batches: the entries after batches 0 and 1, four to a batch
+        const int64_t tbX = std::max<int64_t>(1, (X.kall - kListB0 - 4 + 3) / 4),
+                      tbY = std::max<int64_t>(1, (Y.kall - kListB0 - 4 + 3) / 4);
         if (gX * 8 >= ((int64_t)1 << 31) || gY * 8 >= ((int64_t)1 << 31)) continue;
         int64_t off = 0;
         auto region = [&](int64_t words) {
@@ -1245,10 +1247,10 @@ static int check_list_bounds(const Op &op, int64_t a_words, int64_t list_words) 
         l.n_rows != groups * 8 || ((l.n_o - 1) * l.ro + (l.n_s - 1) * l.rs + 1) * l.Kw > a_words ||
         l.lbase < 0 || l.lbase + l.Kw / l.rwk * l.rkp > l.zrow || l.zrow >= kFusedRows || l.tb < 1 ||
         op.sub[0] + groups * 32 > list_words || op.sub[1] + l.n_rows * l.tb * 2 > list_words ||
-        op.sub[2] + groups * 16 > list_words || (l.Kw / l.rwk * l.rkp + 3) / 4 - 2 > l.tb)
+        op.sub[2] + groups * 16 > list_words || (l.Kw / l.rwk * l.rkp - kListB0 - 4 + 3) / 4 > l.tb)
         return fail(PA_EINVAL, "internal: row-list step would index outside its buffers");
-    // list rows are 32-bit; tail offsets are 26-bit fields of the meta words
-    if (l.n_rows >= ((int64_t)1 << 31) || l.n_rows * l.tb * 2 >= ((int64_t)1 << 26))
+    // list rows are 32-bit; tail offsets are 25-bit fields of the meta words
+    if (l.n_rows >= ((int64_t)1 << 31) || l.n_rows * l.tb * 2 >= ((int64_t)1 << 25))
         return fail(PA_EUNSUPPORTED, "row-list step too large for one launch");
     return PA_OK;
 }
