@@ -221,6 +221,7 @@ struct RowListArgs {
     int lbase, zrow;
     int64_t tb;               // tail batches per list row
     int64_t n_rows;           // 8 ceil(n_o / 8) n_s list rows
+    FastDiv fd_s;             // division by n_s (of group indices below 2^31)
 };
 
 constexpr int kFusedRows = 513;                        // LDS rows of a fused tile: BtX, BtY, the zero row

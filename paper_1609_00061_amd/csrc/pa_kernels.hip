@@ -2253,7 +2253,7 @@ __device__ __forceinline__ void row_list_tile(const RowListArgs &L, int64_t tile
     constexpr int B0 = kListB0;
     const int64_t r = tile * 256 + threadIdx.x;
     const bool valid = r < L.n_rows;
-    const int64_t g = r >> 3, ob = g / L.n_s, s = g - ob * L.n_s, o = ob * 8 + (r & 7);
+    const int64_t g = r >> 3, ob = fdiv((uint32_t)g, L.fd_s), s = g - ob * L.n_s, o = ob * 8 + (r & 7);
     const uint64_t Z = (uint32_t)L.zrow * 64u;
     const uint64_t zz = Z | (Z << 16) | (Z << 32) | (Z << 48);
     uint64_t b0 = zz, b1 = zz;              // entries 0 .. B0 - 1, B0 .. B0 + 3
@@ -2276,14 +2276,30 @@ __device__ __forceinline__ void row_list_tile(const RowListArgs &L, int64_t tile
     };
     if (valid && o < L.n_o) {
         const PA_G uint32_t *row = gp(L.A) + (o * L.ro + s * L.rs) * L.Kw;
-        for (int64_t w = 0; w < L.Kw; ++w) {
-            uint32_t x = row[w];
-            const int64_t ko = w / L.rwk;
-            const uint32_t kb = (uint32_t)(L.lbase + ko * L.rkp + (w - ko * L.rwk) * 32);
+        const uint32_t rwk = (uint32_t)L.rwk, rkp = (uint32_t)L.rkp;
+        auto bits = [&](int64_t w, uint32_t x) {
+            const uint32_t ko = (uint32_t)w / rwk;
+            const uint32_t kb = (uint32_t)L.lbase + ko * rkp + ((uint32_t)w - ko * rwk) * 32u;
             while (x) {
                 put((kb + (uint32_t)__builtin_ctz(x)) * 64u);
                 x &= x - 1;
             }
+        };
+        if (L.Kw <= 8) {
+            // rows of at most 8 words (an even count: rows are padded to 64
+            // bits): every load issued before any word is used
+            u32x2 v[4];
+#pragma unroll
+            for (int h = 0; h < 4; ++h)
+                v[h] = 2 * h < L.Kw ? *reinterpret_cast<const PA_G u32x2 *>(row + 2 * h) : u32x2{0u, 0u};
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                if (2 * h >= L.Kw) break;
+                bits(2 * h, v[h].x);
+                bits(2 * h + 1, v[h].y);
+            }
+        } else {
+            for (int64_t w = 0; w < L.Kw; ++w) bits(w, row[w]);
         }
     }
     const int n = cnt;

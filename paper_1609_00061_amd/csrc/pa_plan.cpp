@@ -951,6 +951,7 @@ static void fuse_pass_pairs(pa_plan *P) {
             L.rl.zrow = zrow;
             L.rl.tb = tb;
             L.rl.n_rows = (n_o + 7) / 8 * 8 * n_s;
+            L.rl.fd_s = make_fastdiv((uint64_t)n_s);
             L.sub[0] = sub[k0];
             L.sub[1] = sub[k0 + 1];
             L.sub[2] = sub[k0 + 2];
