@@ -600,8 +600,10 @@ def main():
         "dtype": "u32",
         "data": "synthetic",
         "config": {"workload": TERNARY, "plotting": "fp32 + fp64 escalation",
-                   "contraction": "bit-packed Boolean: sparse row-gather pass (u32 word OR) with fp4-MFMA "
-                                  "fallback (fp32 accumulation, sum>0), word-streamed final contraction",
+                   "contraction": "bit-packed Boolean, as the autotuner plans it: the two r^5 contractions and "
+                                  "the final one fused (row lists of set bits, LDS-staged row gathers, u32 word "
+                                  "AND/OR), or sparse row-gather passes with a word-streamed final step, or fp4-MFMA "
+                                  "(fp32 accumulation, sum>0)",
                    "order": "exhaustive naive-cost cluster tree",
                    "executor": "one grouped launch per tree level and kernel kind, hipGraph replay, tiles " +
                                ("given" if args.tuning else "autotuned"),
