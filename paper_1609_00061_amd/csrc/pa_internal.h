@@ -199,45 +199,39 @@ constexpr int64_t kCountTileWords = 8192;    // A words per tile of a count step
 //
 // Row lists: rows are taken in groups of 8 consecutive values of the row's
 // output variable o (o-block ob) for one s: group g = ob * n_s + s, list
-// row 8 g + i for o = 8 ob + i.  A list row holds its set bits k as the LDS
-// word offsets 64 (lbase + k) of their rows (16 bits each), padded with the
-// all-zero row zrow: batch 0 (kListB0 entries; two measured no faster on
-// the ternary workload, whose rows mostly hold two set bits: the rows with
-// more cost a branch and a wait each) and batch 1 (four) in the head (32 words per
-// group: batch 0 of row i in words kListB0/2 i .., batch 1 in words
-// 4 kListB0 + 2i, 4 kListB0 + 2i + 1), the rest in the tail (tb batches of
-// four entries, 2 words each, per row).  Per group 16 meta words: bit i of
-// word 0 is set when row i has more than kListB0 set bits, word 8 + i holds
-// the number of its batches after the first (bits 0..6) and the word
-// offset of its tail batches in the tail (bits 7..31).  Rows with o >= n_o
-// have no set bits.
-constexpr int kListB0 = 4;    // entries in batch 0 of a list row (2 or 4)
-
+// row 8 g + i for o = 8 ob + i.  List row r holds its set bits k as the LDS
+// byte offsets kFusedRowBytes (lbase + k) of their rows, in entries
+// r cap .. r cap + m - 1, m the largest count of the group's rows rounded up
+// to an even count (the group's meta word), padded with the all-zero row
+// zrow.  Rows with o >= n_o have no set bits.
 struct RowListArgs {
     const uint32_t *A;        // the pass's A operand: row (o, s) at (o ro + s rs) Kw words
-    uint32_t *head, *tail, *meta;   // per group: 32 words, 8 tb batches of 2 words, 16 words
+    uint32_t *ent, *meta;     // cap entries per list row; one word per group
     int64_t n_o, n_s, ro, rs;
     int64_t Kw, rwk, rkp;     // A row words; bit b of word w = ko rwk + wp is k = ko rkp + 32 wp + b
     int lbase, zrow;
-    int64_t tb;               // tail batches per list row
+    int64_t cap;              // entries per list row: the latent bits rounded up to a multiple of 4
     int64_t n_rows;           // 8 ceil(n_o / 8) n_s list rows
     FastDiv fd_s;             // division by n_s (of group indices below 2^31)
 };
 
 constexpr int kFusedRows = 513;                        // LDS rows of a fused tile: BtX, BtY, the zero row
-constexpr int kFusedLdsWords = kFusedRows * 64 + 9;    // 64 words per row, the tile's 8 output bytes, a counter
+// LDS row pitch in words: 8 words of t x 8 values
+constexpr int kFusedPitch = 64;
+constexpr uint32_t kFusedRowBytes = 4u * kFusedPitch;
+constexpr int kFusedLdsWords = kFusedRows * kFusedPitch + 9;   // rows, the tile's 8 output bytes, a counter
 
 // A fused tile: 8 p (block pb) x 8 q (block qb); tile = pb n_qb + qb.  Bt
 // rows hold n_o x rwt words (rwt <= 8: the o-th 8-word slot of a staged LDS
 // row is padded with zeros).
 struct FusedArgs {
     const uint32_t *BtX, *BtY;
-    const uint32_t *headX, *tailX, *metaX, *headY, *tailY, *metaY;
+    const uint32_t *entX, *metaX, *entY, *metaY;
     uint32_t *C;
     int64_t n_p, n_q, n_s;
     int64_t btX_rw, btY_rw;   // Bt row words: n_p rwt, n_q rwt
     int rwt, kX, kY;          // words of t; LDS rows of BtX (0..kX-1) and BtY (kX..kX+kY-1)
-    int64_t tbX, tbY;         // tail batches per list row of X, Y
+    int64_t capX, capY;       // list entries per row of X, Y
     int64_t c_rw;             // output row words
     int64_t n_qb, n_tiles;    // ceil(n_q / 8); ceil(n_p / 8) n_qb
 };

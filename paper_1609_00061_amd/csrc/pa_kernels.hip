@@ -2242,83 +2242,45 @@ hipError_t launch_gather(const GatherArgs &g, hipStream_t s) {
 }
 
 // -------------------------------------------------------- fused pass pair
-// Row lists (one thread per list row, 256 per tile): the set bits of the A
-// row, in increasing order, as LDS word offsets 64 (lbase + k): the first
-// kListB0 in batch 0, the next four in batch 1 (both in the head), the rest
-// in the tail in batches of four; unused entries of a batch name the zero
-// row.  The group's meta words: bit i of word 0 is set when row i has more
-// than kListB0 set bits, word 8 + i holds the number of row i's batches
-// after the first (bits 0..6) and its tail's word offset (bits 7..31).
+// Row lists (one thread per list row, 256 per tile): the set bits k of the A
+// row, in increasing order, as the LDS byte offsets kFusedRowBytes (lbase + k)
+// of their rows, entries 0 .. m - 1 of the list row (m: the largest count of
+// the row's group of 8, rounded up to an even count), padded with the zero
+// row; m is the group's meta word.
 __device__ __forceinline__ void row_list_tile(const RowListArgs &L, int64_t tile) {
-    constexpr int B0 = kListB0;
     const int64_t r = tile * 256 + threadIdx.x;
     const bool valid = r < L.n_rows;
     const int64_t g = r >> 3, ob = fdiv((uint32_t)g, L.fd_s), s = g - ob * L.n_s, o = ob * 8 + (r & 7);
-    const uint64_t Z = (uint32_t)L.zrow * 64u;
-    const uint64_t zz = Z | (Z << 16) | (Z << 32) | (Z << 48);
-    uint64_t b0 = zz, b1 = zz;              // entries 0 .. B0 - 1, B0 .. B0 + 3
-    PA_G uint32_t *tail = gp(L.tail) + r * L.tb * 2;
-    int cnt = 0;
-    uint32_t pend = 0;                      // an even tail entry waiting for its pair
-    auto put = [&](uint32_t e) {
-        if (cnt < B0) {
-            const int sh = 16 * cnt;
-            b0 = (b0 & ~(0xffffull << sh)) | ((uint64_t)e << sh);
-        } else if (cnt < B0 + 4) {
-            const int sh = 16 * (cnt - B0);
-            b1 = (b1 & ~(0xffffull << sh)) | ((uint64_t)e << sh);
-        } else if (((cnt - B0 - 4) & 1) == 0) {
-            pend = e;
-        } else {
-            tail[(cnt - B0 - 4) >> 1] = pend | (e << 16);
-        }
-        ++cnt;
-    };
-    if (valid && o < L.n_o) {
-        const PA_G uint32_t *row = gp(L.A) + (o * L.ro + s * L.rs) * L.Kw;
-        const uint32_t rwk = (uint32_t)L.rwk, rkp = (uint32_t)L.rkp;
-        auto bits = [&](int64_t w, uint32_t x) {
-            const uint32_t ko = (uint32_t)w / rwk;
-            const uint32_t kb = (uint32_t)L.lbase + ko * rkp + ((uint32_t)w - ko * rwk) * 32u;
-            while (x) {
-                put((kb + (uint32_t)__builtin_ctz(x)) * 64u);
-                x &= x - 1;
-            }
-        };
-        if (L.Kw <= 8) {
-            // rows of at most 8 words (an even count: rows are padded to 64
-            // bits): every load issued before any word is used
-            u32x2 v[4];
-#pragma unroll
-            for (int h = 0; h < 4; ++h)
-                v[h] = 2 * h < L.Kw ? *reinterpret_cast<const PA_G u32x2 *>(row + 2 * h) : u32x2{0u, 0u};
-#pragma unroll
-            for (int h = 0; h < 4; ++h) {
-                if (2 * h >= L.Kw) break;
-                bits(2 * h, v[h].x);
-                bits(2 * h + 1, v[h].y);
-            }
-        } else {
-            for (int64_t w = 0; w < L.Kw; ++w) bits(w, row[w]);
-        }
-    }
-    const int n = cnt;
-    if (n > B0 + 4)
-        while ((cnt - B0) & 3) put((uint32_t)Z);          // pad the last tail batch
-    const uint32_t nx = n > B0 ? 1u + (uint32_t)((max(n - B0 - 4, 0) + 3) / 4) : 0u;
-    // rows r of a group are 8 consecutive lanes (tiles hold whole groups)
-    const uint64_t more = __ballot(n > B0);
+    const uint32_t Z = (uint32_t)L.zrow * kFusedRowBytes;
+    PA_G uint32_t *ent = gp(L.ent) + r * L.cap;
+    const PA_G uint32_t *row = gp(L.A) + (o * L.ro + s * L.rs) * L.Kw;
+    const bool has = valid && o < L.n_o;
+    const uint32_t rwk = (uint32_t)L.rwk, rkp = (uint32_t)L.rkp;
+    // pass 1: the count; pass 2 writes the entries (rows hold few set bits:
+    // the second read of the row comes from L1)
+    auto word = [&](uint32_t w) { return has ? row[w] : 0u; };
+    uint32_t cnt = 0;
+    for (uint32_t w = 0; w < (uint32_t)L.Kw; ++w) cnt += __builtin_popcount(word(w));
+    // the largest count of the group's 8 rows (8 consecutive lanes)
+    uint32_t mx = cnt;
+    mx = max(mx, (uint32_t)__shfl_xor((int)mx, 1));
+    mx = max(mx, (uint32_t)__shfl_xor((int)mx, 2));
+    mx = max(mx, (uint32_t)__shfl_xor((int)mx, 4));
+    const uint32_t m = (mx + 1u) & ~1u;
     if (!valid) return;
-    PA_G uint32_t *hd = gp(L.head) + g * 32;
-    const int i = (int)(r & 7);
-    if (B0 == 2) {
-        hd[i] = (uint32_t)b0;
-    } else {
-        *reinterpret_cast<PA_G u32x2 *>(hd + 2 * i) = u32x2{(uint32_t)b0, (uint32_t)(b0 >> 32)};
+    uint32_t n = 0;
+    auto put = [&](uint32_t e) { ent[n++] = e; };
+    for (uint32_t w = 0; w < (uint32_t)L.Kw; ++w) {
+        uint32_t x = word(w);
+        const uint32_t ko = w / rwk;
+        const uint32_t kb = (uint32_t)L.lbase + ko * rkp + (w - ko * rwk) * 32u;
+        while (x) {
+            put((kb + (uint32_t)__builtin_ctz(x)) * kFusedRowBytes);
+            x &= x - 1;
+        }
     }
-    *reinterpret_cast<PA_G u32x2 *>(hd + 4 * B0 + 2 * i) = u32x2{(uint32_t)b1, (uint32_t)(b1 >> 32)};
-    gp(L.meta)[g * 16 + 8 + i] = nx | (uint32_t)(r * L.tb * 2) << 7;
-    if (i == 0) gp(L.meta)[g * 16] = (uint32_t)(more >> (__lane_id() & ~7)) & 0xffu;
+    while (n < m) put(Z);
+    if ((r & 7) == 0) gp(L.meta)[g] = m;
 }
 
 __global__ __launch_bounds__(256) void k_row_list(RowListArgs L, int64_t n_tiles) {
@@ -2332,9 +2294,11 @@ hipError_t launch_row_list(const RowListArgs &l, hipStream_t s) {
     return hipGetLastError();
 }
 
-// LDS rows row0 .. row0 + K - 1 of a fused tile: word 8 ol + w of row
-// row0 + k is Bt[k][o0 + ol][w] (zero for o0 + ol >= n_o or w >= rwt).
-// 1024 threads; the loads of four rounds are issued before their stores.
+// LDS rows row0 .. row0 + K - 1 of a fused tile (kFusedPitch words apart):
+// word 8 w + ol of row row0 + k is Bt[k][o0 + ol][w] (zero for o0 + ol >= n_o
+// or w >= rwt), so that the 8 values of word w of a row are 32 contiguous
+// bytes.  1024 threads; the loads of four rounds are issued before their
+// stores.
 __device__ __forceinline__ void fused_stage(uint32_t *lds, const uint32_t *bt, int64_t bt_rw, int K, int64_t o0,
                                             int64_t n_o, int rwt, int row0) {
     const int tid = threadIdx.x;
@@ -2354,7 +2318,15 @@ __device__ __forceinline__ void fused_stage(uint32_t *lds, const uint32_t *bt, i
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int i = i0 + u * 1024 + tid;
-                if (i < n) *reinterpret_cast<u32x4 *>(lds + (row0 + (i >> 4)) * 64 + 4 * (i & 15)) = v[u];
+                if (i < n) {
+                    // words 4 (c & 1) .. + 3 of value c / 2
+                    const int c = i & 15;
+                    uint32_t *d = lds + (row0 + (i >> 4)) * kFusedPitch + 32 * (c & 1) + (c >> 1);
+                    d[0] = v[u].x;
+                    d[8] = v[u].y;
+                    d[16] = v[u].z;
+                    d[24] = v[u].w;
+                }
             }
         }
         return;
@@ -2372,56 +2344,73 @@ __device__ __forceinline__ void fused_stage(uint32_t *lds, const uint32_t *bt, i
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int i = i0 + u * 1024 + tid;
-            if (i < n) lds[(row0 + (i >> 6)) * 64 + (i & 63)] = v[u];
+            if (i < n) lds[(row0 + (i >> 6)) * kFusedPitch + 8 * (i & 7) + ((i >> 3) & 7)] = v[u];
         }
     }
 }
 
-// OR of the four LDS rows at the word offsets in the 16-bit halves of w0
-// and w1, word `lane` of each.
-__device__ __forceinline__ uint32_t fused_batch(const uint32_t *lds, int lane, uint32_t w0, uint32_t w1) {
-    return lds[(w0 & 0xffffu) + lane] | lds[(w0 >> 16) + lane] | lds[(w1 & 0xffffu) + lane] | lds[(w1 >> 16) + lane];
+// N list entries (LDS row byte offsets, one set per lane group) gathered
+// into c: c[v] |= value v of word w (w = lane & 7) of each row, 32
+// contiguous bytes read with two 16-byte loads; all loads are issued before
+// any is used.
+template <int N>
+__device__ __forceinline__ void fused_gather(const uint32_t *lds, uint32_t w32, const uint32_t (&e)[N],
+                                             uint32_t (&c)[8]) {
+    const char *base = reinterpret_cast<const char *>(lds);
+    u32x4 r[N][2];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        const char *p = base + e[j] + w32;
+        r[j][0] = *reinterpret_cast<const u32x4 *>(p);
+        r[j][1] = *reinterpret_cast<const u32x4 *>(p + 16);
+    }
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        c[0] |= r[j][0].x;
+        c[1] |= r[j][0].y;
+        c[2] |= r[j][0].z;
+        c[3] |= r[j][0].w;
+        c[4] |= r[j][1].x;
+        c[5] |= r[j][1].y;
+        c[6] |= r[j][1].z;
+        c[7] |= r[j][1].w;
+    }
 }
 
-// The rows of eight lists of one group: c[i] = OR of the LDS rows of list
-// row i, word `lane`.  The group's 32 head words are lanes b .. b + 31 of
-// hw and its 16 meta words lanes m .. m + 15 of mw (loaded one latent entry
-// ahead with vector loads, read out with v_readlane); the tails (rows of
-// more than kListB0 + 4 set bits) through scalar loads from tl.  Batch 0 of
-// every row first (all its reads in flight), then the later batches of the
-// rows that have them.
-template <int B, int M>
-__device__ __forceinline__ void fused_rows(const uint32_t *lds, int lane, uint32_t hw, uint32_t mw,
-                                           const PA_K uint32_t *tl, uint32_t (&c)[8]) {
-    constexpr int B0 = kListB0;
-    uint32_t r[8][B0];
+// The list rows of one group, one per lane group (row a for lanes 8a ..
+// 8a + 7): c[v] = OR over the entries of the lane group's row of value v of
+// word w of its LDS row.  e0, e1 hold the row's entries 0..3 and 4..7
+// (loaded one latent entry ahead), m the group's (even) entry count;
+// entries beyond 8 are loaded here.
+__device__ __forceinline__ void fused_rows(const uint32_t *lds, uint32_t w32, const u32x4 &e0, const u32x4 &e1,
+                                           uint32_t m, const PA_G uint32_t *ent, uint32_t (&c)[8]) {
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-#pragma unroll
-        for (int h = 0; h < B0 / 2; ++h) {
-            const uint32_t w = __builtin_amdgcn_readlane(hw, B + (B0 / 2) * i + h);
-            r[i][2 * h] = lds[(w & 0xffffu) + lane];
-            r[i][2 * h + 1] = lds[(w >> 16) + lane];
-        }
-    }
-    __builtin_amdgcn_sched_group_barrier(0x100, 8 * B0, 0);
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        c[i] = r[i][0] | r[i][1];
-#pragma unroll
-        for (int h = 2; h < B0; ++h) c[i] |= r[i][h];
-    }
-    const uint32_t m = __builtin_amdgcn_readlane(mw, M);
+    for (int v = 0; v < 8; ++v) c[v] = 0u;
     if (m == 0u) return;
-#pragma unroll
-    for (int i = 0; i < 8; ++i)
-        if (m & (1u << i)) {
-            c[i] |= fused_batch(lds, lane, __builtin_amdgcn_readlane(hw, B + 4 * B0 + 2 * i),
-                                __builtin_amdgcn_readlane(hw, B + 4 * B0 + 2 * i + 1));
-            const uint32_t w = __builtin_amdgcn_readlane(mw, M + 8 + i), nx = w & 127u;
-            const PA_K uint32_t *t = tl + (w >> 7);
-            for (uint32_t b = 2; b <= nx; ++b) c[i] |= fused_batch(lds, lane, t[2 * (b - 2)], t[2 * (b - 2) + 1]);
-        }
+    if (m == 2u) {
+        const uint32_t e[2] = {e0.x, e0.y};
+        fused_gather<2>(lds, w32, e, c);
+        return;
+    }
+    {
+        const uint32_t e[4] = {e0.x, e0.y, e0.z, e0.w};
+        fused_gather<4>(lds, w32, e, c);
+    }
+    if (m == 4u) return;
+    if (m == 6u) {
+        const uint32_t e[2] = {e1.x, e1.y};
+        fused_gather<2>(lds, w32, e, c);
+        return;
+    }
+    {
+        const uint32_t e[4] = {e1.x, e1.y, e1.z, e1.w};
+        fused_gather<4>(lds, w32, e, c);
+    }
+    for (uint32_t j = 8; j < m; j += 2) {
+        const u32x2 t = *reinterpret_cast<const PA_G u32x2 *>(ent + j);
+        const uint32_t e[2] = {t.x, t.y};
+        fused_gather<2>(lds, w32, e, c);
+    }
 }
 
 // Transpose of an 8 x 8 block held as c[j] in lane group a = lane / 8 (each
@@ -2452,20 +2441,24 @@ __device__ __forceinline__ void fused_transpose8(uint32_t (&c)[8]) {
 }
 
 // One fused tile (1024 threads, 16 waves): 8 p x 8 q of the output (tile =
-// pb n_qb + qb; many more tiles than CUs, so that the dispatcher balances
-// tiles of uneven density).  The rows of BtX for the tile's 8 p and of BtY
-// for its 8 q are staged in LDS; the waves take latent entries s from a
-// counter.  For one s a wave gathers X[q][s][p][w] as x[q] in lane (p, w)
-// and Y[p][s][q][w] as y[p] in lane (q, w), transposes y to lane (p, w) and
-// keeps the OR of x[q] AND y[q].  The tile writes byte qb of its 8 output
-// rows (the tile of the last q block also zeroes the row's padding bytes).
+// pb n_qb + qb).  The rows of BtX for the tile's 8 p and of BtY for its 8 q
+// are staged in LDS; the waves take latent entries s from a counter.  For
+// one s, lane (a, w) gathers from the rows of its lane group's list rows:
+// x[p] = X[q = a][s][p][w] from AX row (a, s) and y[q] = Y[p = a][s][q][w]
+// from AY row (a, s) (the 8 values of word w of an LDS row are contiguous:
+// two 16-byte loads per entry, each pass of 8 lanes reading one row's 256
+// bytes, free of bank conflicts); x is transposed to lane (p, w) and the OR
+// of x[q] AND y[q] kept.  The next s's list entries come with vector loads one s
+// ahead.  The tile writes byte qb of its 8 output rows (the tile of the
+// last q block also zeroes the row's padding bytes).
 __device__ __forceinline__ void fused_tile(const FusedArgs &f, int64_t tile, uint32_t *lds) {
     const int64_t pb = tile / f.n_qb, qb = tile - pb * f.n_qb, p0 = pb * 8;
     const int tid = threadIdx.x, lane = tid & 63;
-    uint32_t *out = lds + kFusedRows * 64;     // 8 output bytes (a word each), the latent-entry counter
+    const uint32_t w32 = (uint32_t)(lane & 7) * 32u;
+    uint32_t *out = lds + kFusedRows * kFusedPitch;     // 8 output bytes (a word each), the latent-entry counter
     fused_stage(lds, f.BtX, f.btX_rw, f.kX, p0, f.n_p, f.rwt, 0);
     fused_stage(lds, f.BtY, f.btY_rw, f.kY, qb * 8, f.n_q, f.rwt, f.kX);
-    if (tid < 64) lds[(f.kX + f.kY) * 64 + tid] = 0u;
+    if (tid < 64) lds[(f.kX + f.kY) * kFusedPitch + tid] = 0u;
     if (tid < 9) out[tid] = 0u;
     __syncthreads();
     uint32_t acc[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
@@ -2474,29 +2467,41 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &f, int64_t tile, uin
         if (lane == 0) v = atomicAdd(out + 8, 1u);
         return (int64_t)__builtin_amdgcn_readfirstlane(v);
     };
-    // lane l < 32 loads head word l of Y's group, lane 32 + l word l of X's;
-    // lanes 0..15 and 16..31 the meta words of Y's and X's
-    auto fetch = [&](int64_t s, uint32_t &hw, uint32_t &mw) {
+    // the list rows of lane group a: AX row (q = a, s) of group (qb, s) and
+    // AY row (p = a, s) of group (pb, s); the groups' entry counts
+    const int a = lane >> 3;
+    struct Lists {
+        u32x4 x0, x1, y0, y1;
+        uint32_t mx, my;
+    };
+    auto fetch = [&](int64_t s, Lists &l) {
         const int64_t gx = qb * f.n_s + s, gy = pb * f.n_s + s;
-        hw = lane < 32 ? gp(f.headY)[gy * 32 + lane] : gp(f.headX)[gx * 32 + lane - 32];
-        mw = lane < 16 ? gp(f.metaY)[gy * 16 + lane] : gp(f.metaX)[gx * 16 + ((lane - 16) & 15)];
+        const PA_G uint32_t *ex = gp(f.entX) + (gx * 8 + a) * f.capX, *ey = gp(f.entY) + (gy * 8 + a) * f.capY;
+        l.x0 = *reinterpret_cast<const PA_G u32x4 *>(ex);
+        l.x1 = f.capX > 4 ? *reinterpret_cast<const PA_G u32x4 *>(ex + 4) : u32x4{0u, 0u, 0u, 0u};
+        l.y0 = *reinterpret_cast<const PA_G u32x4 *>(ey);
+        l.y1 = f.capY > 4 ? *reinterpret_cast<const PA_G u32x4 *>(ey + 4) : u32x4{0u, 0u, 0u, 0u};
+        l.mx = gp(f.metaX)[gx];
+        l.my = gp(f.metaY)[gy];
     };
     int64_t s = grab();
-    uint32_t hw = 0, mw = 0;
-    if (s < f.n_s) fetch(s, hw, mw);
+    Lists cur{};
+    if (s < f.n_s) fetch(s, cur);
     while (s < f.n_s) {
         const int64_t sn = grab();
-        uint32_t hn = 0, mn = 0;
-        if (sn < f.n_s) fetch(sn, hn, mn);
+        Lists nxt{};
+        if (sn < f.n_s) fetch(sn, nxt);
+        const int64_t gx = qb * f.n_s + s, gy = pb * f.n_s + s;
         uint32_t x[8], y[8];
-        fused_rows<0, 0>(lds, lane, hw, mw, (const PA_K uint32_t *)f.tailY, y);
-        fused_rows<32, 16>(lds, lane, hw, mw, (const PA_K uint32_t *)f.tailX, x);
-        fused_transpose8(y);
+        fused_rows(lds, w32, cur.y0, cur.y1, __builtin_amdgcn_readfirstlane(cur.my),
+                   gp(f.entY) + (gy * 8 + a) * f.capY, y);
+        fused_rows(lds, w32, cur.x0, cur.x1, __builtin_amdgcn_readfirstlane(cur.mx),
+                   gp(f.entX) + (gx * 8 + a) * f.capX, x);
+        fused_transpose8(x);
 #pragma unroll
         for (int i = 0; i < 8; ++i) acc[i] |= x[i] & y[i];
         s = sn;
-        hw = hn;
-        mw = mn;
+        cur = nxt;
     }
     uint32_t bits = 0;
 #pragma unroll

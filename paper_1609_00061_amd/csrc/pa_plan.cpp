@@ -653,7 +653,7 @@ std::string Op::describe() const {
     if (kind == OP_LIST) {
         s << "{\"op\":\"row_list\",\"a\":" << a << ",\"c\":" << c << ",\"a_vars\":" << join(la.vars)
           << ",\"n_o\":" << rl.n_o << ",\"n_s\":" << rl.n_s << ",\"rows\":" << rl.n_rows << ",\"lbase\":" << rl.lbase
-          << ",\"zrow\":" << rl.zrow << ",\"tail_batches\":" << rl.tb << "}";
+          << ",\"zrow\":" << rl.zrow << ",\"cap\":" << rl.cap << "}";
         return s.str();
     }
     if (kind == OP_FUSED) {
@@ -907,9 +907,8 @@ static void fuse_pass_pairs(pa_plan *P) {
         if (GY.lc.rw != rwt || rwt > 8 || X.kall + Y.kall + 1 > kFusedRows) continue;
         // list buffer: per operand the heads, the meta words and the tails
         const int64_t gX = (n_q + 7) / 8 * n_s, gY = (n_p + 7) / 8 * n_s;
-        // tail batches: the entries after batches 0 and 1, four to a batch
-        const int64_t tbX = std::max<int64_t>(1, (X.kall - kListB0 - 4 + 3) / 4),
-                      tbY = std::max<int64_t>(1, (Y.kall - kListB0 - 4 + 3) / 4);
+        // list entries per row: the latent bits, rounded up to a multiple of 4
+        const int64_t capX = (X.kall + 3) / 4 * 4, capY = (Y.kall + 3) / 4 * 4;
         if (gX * 8 >= ((int64_t)1 << 31) || gY * 8 >= ((int64_t)1 << 31)) continue;
         int64_t off = 0;
         auto region = [&](int64_t words) {
@@ -917,13 +916,11 @@ static void fuse_pass_pairs(pa_plan *P) {
             off += (words + 63) / 64 * 64;
             return at;
         };
-        int64_t sub[6];
-        sub[0] = region(gX * 32);
-        sub[1] = region(gX * 8 * tbX * 2);
-        sub[2] = region(gX * 16);
-        sub[3] = region(gY * 32);
-        sub[4] = region(gY * 8 * tbY * 2);
-        sub[5] = region(gY * 16);
+        int64_t sub[6] = {0, 0, 0, 0, 0, 0};
+        sub[0] = region(gX * 8 * capX);
+        sub[1] = region(gX);
+        sub[2] = region(gY * 8 * capY);
+        sub[3] = region(gY);
         Layout ll;
         ll.rw = off;
         ll.words = off;
@@ -932,7 +929,7 @@ static void fuse_pass_pairs(pa_plan *P) {
         P->buf_off.push_back(-1);
         const int lbuf = (int)P->buf_layout.size() - 1;
         const int zrow = (int)(X.kall + Y.kall);
-        auto list_op = [&](const Op &G, const PassSide &sd, int64_t n_o, int lbase, int64_t tb, int k0) {
+        auto list_op = [&](const Op &G, const PassSide &sd, int64_t n_o, int lbase, int64_t cap, int k0) {
             Op L;
             L.kind = OP_LIST;
             L.a = G.a;
@@ -949,15 +946,14 @@ static void fuse_pass_pairs(pa_plan *P) {
             L.rl.rkp = G.gg.rkp;
             L.rl.lbase = lbase;
             L.rl.zrow = zrow;
-            L.rl.tb = tb;
+            L.rl.cap = cap;
             L.rl.n_rows = (n_o + 7) / 8 * 8 * n_s;
             L.rl.fd_s = make_fastdiv((uint64_t)n_s);
             L.sub[0] = sub[k0];
             L.sub[1] = sub[k0 + 1];
-            L.sub[2] = sub[k0 + 2];
             return L;
         };
-        const Op LX = list_op(GX, X, n_q, 0, tbX, 0), LY = list_op(GY, Y, n_p, (int)X.kall, tbY, 3);
+        const Op LX = list_op(GX, X, n_q, 0, capX, 0), LY = list_op(GY, Y, n_p, (int)X.kall, capY, 2);
         Op F;
         F.kind = OP_FUSED;
         F.a = lbuf;
@@ -979,12 +975,12 @@ static void fuse_pass_pairs(pa_plan *P) {
         f.rwt = (int)rwt;
         f.kX = (int)X.kall;
         f.kY = (int)Y.kall;
-        f.tbX = tbX;
-        f.tbY = tbY;
+        f.capX = capX;
+        f.capY = capY;
         f.c_rw = S.lc.rw;
         f.n_qb = (n_q + 7) / 8;
         f.n_tiles = (n_p + 7) / 8 * f.n_qb;
-        for (int k = 0; k < 6; ++k) F.sub[k] = sub[k];
+        for (int k = 0; k < 4; ++k) F.sub[k] = sub[k];
         std::vector<Op> ops;
         for (size_t k = 0; k < P->ops.size(); ++k) {
             if ((int)k == X.op || (int)k == Y.op) continue;
@@ -1246,12 +1242,11 @@ static int check_list_bounds(const Op &op, int64_t a_words, int64_t list_words) 
     const int64_t groups = (l.n_o + 7) / 8 * l.n_s;
     if (l.n_o < 1 || l.n_s < 1 || l.Kw < 1 || l.rwk < 1 || l.Kw % l.rwk || l.rkp < 1 || l.rkp > 32 * l.rwk ||
         l.n_rows != groups * 8 || ((l.n_o - 1) * l.ro + (l.n_s - 1) * l.rs + 1) * l.Kw > a_words ||
-        l.lbase < 0 || l.lbase + l.Kw / l.rwk * l.rkp > l.zrow || l.zrow >= kFusedRows || l.tb < 1 ||
-        op.sub[0] + groups * 32 > list_words || op.sub[1] + l.n_rows * l.tb * 2 > list_words ||
-        op.sub[2] + groups * 16 > list_words || (l.Kw / l.rwk * l.rkp - kListB0 - 4 + 3) / 4 > l.tb)
+        l.lbase < 0 || l.lbase + l.Kw / l.rwk * l.rkp > l.zrow || l.zrow >= kFusedRows || l.cap % 4 ||
+        l.cap < l.Kw / l.rwk * l.rkp || op.sub[0] + l.n_rows * l.cap > list_words || op.sub[1] + groups > list_words)
         return fail(PA_EINVAL, "internal: row-list step would index outside its buffers");
-    // list rows are 32-bit; tail offsets are 25-bit fields of the meta words
-    if (l.n_rows >= ((int64_t)1 << 31) || l.n_rows * l.tb * 2 >= ((int64_t)1 << 25))
+    // list rows are 32-bit
+    if (l.n_rows >= ((int64_t)1 << 31))
         return fail(PA_EUNSUPPORTED, "row-list step too large for one launch");
     return PA_OK;
 }
@@ -1264,10 +1259,9 @@ static int check_fused_bounds(const Op &op, int64_t list_words, int64_t btx_word
         f.kX + f.kY + 1 > kFusedRows || f.btX_rw < f.n_p * f.rwt || f.btY_rw < f.n_q * f.rwt ||
         (int64_t)f.kX * f.btX_rw > btx_words || (int64_t)f.kY * f.btY_rw > bty_words ||
         f.n_qb != (f.n_q + 7) / 8 || 4 * f.c_rw < f.n_qb || f.n_p * f.c_rw > c_words ||
-        f.n_tiles != (f.n_p + 7) / 8 * f.n_qb || op.sub[0] + gX * 32 > list_words ||
-        op.sub[1] + gX * 8 * f.tbX * 2 > list_words || op.sub[2] + gX * 16 > list_words ||
-        op.sub[3] + gY * 32 > list_words || op.sub[4] + gY * 8 * f.tbY * 2 > list_words ||
-        op.sub[5] + gY * 16 > list_words)
+        f.n_tiles != (f.n_p + 7) / 8 * f.n_qb || f.capX % 4 || f.capY % 4 || f.capX < f.kX || f.capY < f.kY ||
+        op.sub[0] + gX * 8 * f.capX > list_words || op.sub[1] + gX > list_words ||
+        op.sub[2] + gY * 8 * f.capY > list_words || op.sub[3] + gY > list_words)
         return fail(PA_EINVAL, "internal: fused step would index outside its buffers");
     return PA_OK;
 }
@@ -1298,9 +1292,8 @@ static int list_args(pa_plan *P, const Op &op, void *out, RowListArgs &l) {
     l = op.rl;
     l.A = buf_ptr(P, op.a, out);
     uint32_t *lb = buf_ptr(P, op.c, out);
-    l.head = lb + op.sub[0];
-    l.tail = lb + op.sub[1];
-    l.meta = lb + op.sub[2];
+    l.ent = lb + op.sub[0];
+    l.meta = lb + op.sub[1];
     return PA_OK;
 }
 
@@ -1312,12 +1305,10 @@ static int fused_args(pa_plan *P, const Op &op, void *out, FusedArgs &f) {
     f.BtX = buf_ptr(P, op.b, out);
     f.BtY = buf_ptr(P, op.flag, out);
     const uint32_t *lb = buf_ptr(P, op.a, out);
-    f.headX = lb + op.sub[0];
-    f.tailX = lb + op.sub[1];
-    f.metaX = lb + op.sub[2];
-    f.headY = lb + op.sub[3];
-    f.tailY = lb + op.sub[4];
-    f.metaY = lb + op.sub[5];
+    f.entX = lb + op.sub[0];
+    f.metaX = lb + op.sub[1];
+    f.entY = lb + op.sub[2];
+    f.metaY = lb + op.sub[3];
     f.C = buf_ptr(P, op.c, out);
     return PA_OK;
 }

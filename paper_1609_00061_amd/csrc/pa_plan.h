@@ -96,8 +96,8 @@ struct Op {
     GatherArgs gg{};              // OP_COUNT, OP_GATHER (pointers patched at execution)
     // OP_LIST (a: the pass's A, c: the list buffer) and OP_FUSED (a: the list
     // buffer, b: BtX, flag: BtY); pointers patched at execution from word
-    // offsets into the list buffer: OP_LIST head, tail, meta in sub[0..2],
-    // OP_FUSED X's in sub[0..2] and Y's in sub[3..5]
+    // offsets into the list buffer: OP_LIST entries and meta words in
+    // sub[0..1], OP_FUSED X's in sub[0..1] and Y's in sub[2..3]
     RowListArgs rl{};
     FusedArgs fu{};
     int64_t sub[6] = {0, 0, 0, 0, 0, 0};
