@@ -2295,10 +2295,12 @@ hipError_t launch_row_list(const RowListArgs &l, hipStream_t s) {
 }
 
 // LDS rows row0 .. row0 + K - 1 of a fused tile (kFusedPitch words apart):
-// word 8 w + ol of row row0 + k is Bt[k][o0 + ol][w] (zero for o0 + ol >= n_o
-// or w >= rwt), so that the 8 values of word w of a row are 32 contiguous
-// bytes.  1024 threads; the loads of four rounds are issued before their
-// stores.
+// word 32 (ol / 4) + 4 w + ol % 4 of row row0 + k is Bt[k][o0 + ol][w]
+// (zero for o0 + ol >= n_o or w >= rwt): values 0..3 of word w are the 16
+// bytes at 16 w, values 4..7 those at 128 + 16 w, so that 8 lanes reading
+// one row's word w = 0..7 cover 128 contiguous bytes with each of their two
+// 16-byte loads.  1024 threads; the loads of four rounds are issued before
+// their stores.
 __device__ __forceinline__ void fused_stage(uint32_t *lds, const uint32_t *bt, int64_t bt_rw, int K, int64_t o0,
                                             int64_t n_o, int rwt, int row0) {
     const int tid = threadIdx.x;
@@ -2319,13 +2321,13 @@ __device__ __forceinline__ void fused_stage(uint32_t *lds, const uint32_t *bt, i
             for (int u = 0; u < 4; ++u) {
                 const int i = i0 + u * 1024 + tid;
                 if (i < n) {
-                    // words 4 (c & 1) .. + 3 of value c / 2
-                    const int c = i & 15;
-                    uint32_t *d = lds + (row0 + (i >> 4)) * kFusedPitch + 32 * (c & 1) + (c >> 1);
+                    // words 4 (c & 1) .. + 3 of value o = c / 2
+                    const int c = i & 15, o = c >> 1;
+                    uint32_t *d = lds + (row0 + (i >> 4)) * kFusedPitch + 32 * (o >> 2) + 16 * (c & 1) + (o & 3);
                     d[0] = v[u].x;
-                    d[8] = v[u].y;
-                    d[16] = v[u].z;
-                    d[24] = v[u].w;
+                    d[4] = v[u].y;
+                    d[8] = v[u].z;
+                    d[12] = v[u].w;
                 }
             }
         }
@@ -2344,25 +2346,33 @@ __device__ __forceinline__ void fused_stage(uint32_t *lds, const uint32_t *bt, i
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int i = i0 + u * 1024 + tid;
-            if (i < n) lds[(row0 + (i >> 6)) * kFusedPitch + 8 * (i & 7) + ((i >> 3) & 7)] = v[u];
+            if (i < n) {
+                const int o = (i >> 3) & 7;
+                lds[(row0 + (i >> 6)) * kFusedPitch + 32 * (o >> 2) + 4 * (i & 7) + (o & 3)] = v[u];
+            }
         }
     }
 }
 
 // N list entries (LDS row byte offsets, one set per lane group) gathered
-// into c: c[v] |= value v of word w (w = lane & 7) of each row, 32
-// contiguous bytes read with two 16-byte loads; all loads are issued before
-// any is used.
+// into c with two 16-byte loads per entry, at byte offsets o0 and o0 ^ 128
+// of the row.  Lane (a, w) (a = lane / 8, w = lane & 7) reads the half of word w's
+// values that holds values 4 (a & 1) .. + 3 first: c[v] |= value v ^ 4 (a &
+// 1) of word w.  A 16-byte read is served in passes of 16 lanes, each
+// pass taking 4 lanes from each of 4 lane groups, two groups of each
+// parity; with the halves alternating by group parity the 16 lanes of a
+// pass read 16 distinct 16-byte slots of the 64 banks.  All loads are issued
+// before any is used.
 template <int N>
-__device__ __forceinline__ void fused_gather(const uint32_t *lds, uint32_t w32, const uint32_t (&e)[N],
+__device__ __forceinline__ void fused_gather(const uint32_t *lds, uint32_t o0, const uint32_t (&e)[N],
                                              uint32_t (&c)[8]) {
     const char *base = reinterpret_cast<const char *>(lds);
     u32x4 r[N][2];
 #pragma unroll
     for (int j = 0; j < N; ++j) {
-        const char *p = base + e[j] + w32;
-        r[j][0] = *reinterpret_cast<const u32x4 *>(p);
-        r[j][1] = *reinterpret_cast<const u32x4 *>(p + 16);
+        const uint32_t b = e[j] + o0;
+        r[j][0] = *reinterpret_cast<const u32x4 *>(base + b);
+        r[j][1] = *reinterpret_cast<const u32x4 *>(base + (b ^ 128u));
     }
 #pragma unroll
     for (int j = 0; j < N; ++j) {
@@ -2378,47 +2388,50 @@ __device__ __forceinline__ void fused_gather(const uint32_t *lds, uint32_t w32, 
 }
 
 // The list rows of one group, one per lane group (row a for lanes 8a ..
-// 8a + 7): c[v] = OR over the entries of the lane group's row of value v of
-// word w of its LDS row.  e0, e1 hold the row's entries 0..3 and 4..7
-// (loaded one latent entry ahead), m the group's (even) entry count;
-// entries beyond 8 are loaded here.
-__device__ __forceinline__ void fused_rows(const uint32_t *lds, uint32_t w32, const u32x4 &e0, const u32x4 &e1,
+// 8a + 7): c[v] = OR over the entries of the lane group's row of value
+// v ^ 4 (a & 1) of word w of its LDS row.  e0, e1 hold the row's entries
+// 0..3 and 4..7 (loaded one latent entry ahead), m the group's (even) entry
+// count; entries beyond 8 are loaded here.
+__device__ __forceinline__ void fused_rows(const uint32_t *lds, uint32_t o0, const u32x4 &e0, const u32x4 &e1,
                                            uint32_t m, const PA_G uint32_t *ent, uint32_t (&c)[8]) {
 #pragma unroll
     for (int v = 0; v < 8; ++v) c[v] = 0u;
     if (m == 0u) return;
     if (m == 2u) {
         const uint32_t e[2] = {e0.x, e0.y};
-        fused_gather<2>(lds, w32, e, c);
+        fused_gather<2>(lds, o0, e, c);
         return;
     }
     {
         const uint32_t e[4] = {e0.x, e0.y, e0.z, e0.w};
-        fused_gather<4>(lds, w32, e, c);
+        fused_gather<4>(lds, o0, e, c);
     }
     if (m == 4u) return;
     if (m == 6u) {
         const uint32_t e[2] = {e1.x, e1.y};
-        fused_gather<2>(lds, w32, e, c);
+        fused_gather<2>(lds, o0, e, c);
         return;
     }
     {
         const uint32_t e[4] = {e1.x, e1.y, e1.z, e1.w};
-        fused_gather<4>(lds, w32, e, c);
+        fused_gather<4>(lds, o0, e, c);
     }
     for (uint32_t j = 8; j < m; j += 2) {
         const u32x2 t = *reinterpret_cast<const PA_G u32x2 *>(ent + j);
         const uint32_t e[2] = {t.x, t.y};
-        fused_gather<2>(lds, w32, e, c);
+        fused_gather<2>(lds, o0, e, c);
     }
 }
 
 // Transpose of an 8 x 8 block held as c[j] in lane group a = lane / 8 (each
-// of the group's 8 lanes holds its own word): afterwards c[j] of group a is
-// the former c[a] of group j.  Index bit 0 trades with lane bit 3 (DPP
-// rotation by 8 within rows of 16 lanes, written to one half of each row),
-// bit 1 with lane bit 4 (v_permlane16_swap), bit 2 with lane bit 5
-// (v_permlane32_swap).
+// of the group's 8 lanes holds its own word), whose odd groups hold their
+// values with halves exchanged (c[j] of group a is value j ^ 4 (a & 1), as
+// fused_gather leaves them): afterwards c[j] of group a is value a of group
+// j.  Index bit 0 trades with lane bit 3 (DPP rotation by 8 within rows of
+// 16 lanes, written to one half of each row), bit 1 with lane bit 4
+// (v_permlane16_swap), bit 2 with lane bit 5 (v_permlane32_swap).  After the
+// first two steps index bit 0 is the source group's parity, so the last
+// step undoes the exchange by swapping the operands of the odd registers.
 __device__ __forceinline__ void fused_transpose8(uint32_t (&c)[8]) {
 #pragma unroll
     for (int j = 0; j < 8; j += 2) {
@@ -2434,7 +2447,8 @@ __device__ __forceinline__ void fused_transpose8(uint32_t (&c)[8]) {
     }
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-        const auto sw = __builtin_amdgcn_permlane32_swap(c[j], c[j + 4], false, false);
+        const auto sw = (j & 1) ? __builtin_amdgcn_permlane32_swap(c[j + 4], c[j], false, false)
+                                : __builtin_amdgcn_permlane32_swap(c[j], c[j + 4], false, false);
         c[j] = sw[0];
         c[j + 4] = sw[1];
     }
@@ -2445,16 +2459,18 @@ __device__ __forceinline__ void fused_transpose8(uint32_t (&c)[8]) {
 // are staged in LDS; the waves take latent entries s from a counter.  For
 // one s, lane (a, w) gathers from the rows of its lane group's list rows:
 // x[p] = X[q = a][s][p][w] from AX row (a, s) and y[q] = Y[p = a][s][q][w]
-// from AY row (a, s) (the 8 values of word w of an LDS row are contiguous:
-// two 16-byte loads per entry, each pass of 8 lanes reading one row's 256
-// bytes, free of bank conflicts); x is transposed to lane (p, w) and the OR
-// of x[q] AND y[q] kept.  The next s's list entries come with vector loads one s
-// ahead.  The tile writes byte qb of its 8 output rows (the tile of the
+// from AY row (a, s) (two 16-byte loads per entry, free of bank conflicts,
+// odd lane groups taking the halves of a word's values in the other order);
+// x is transposed to lane (p, w), the halves of y put back in order, and the
+// OR of x[q] AND y[q] kept.  The next s's list entries
+// come with vector loads one s ahead.  The tile writes byte qb of its 8 output rows (the tile of the
 // last q block also zeroes the row's padding bytes).
 __device__ __forceinline__ void fused_tile(const FusedArgs &f, int64_t tile, uint32_t *lds) {
     const int64_t pb = tile / f.n_qb, qb = tile - pb * f.n_qb, p0 = pb * 8;
     const int tid = threadIdx.x, lane = tid & 63;
-    const uint32_t w32 = (uint32_t)(lane & 7) * 32u;
+    // the 16-byte slot of word w in a row that holds values 4 (a & 1) .. + 3
+    const uint32_t o0 = (uint32_t)(lane & 7) * 16u + (uint32_t)(lane & 8) * 16u;
+    const bool odd = (lane & 8) != 0;
     uint32_t *out = lds + kFusedRows * kFusedPitch;     // 8 output bytes (a word each), the latent-entry counter
     fused_stage(lds, f.BtX, f.btX_rw, f.kX, p0, f.n_p, f.rwt, 0);
     fused_stage(lds, f.BtY, f.btY_rw, f.kY, qb * 8, f.n_q, f.rwt, f.kX);
@@ -2487,17 +2503,27 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &f, int64_t tile, uin
     int64_t s = grab();
     Lists cur{};
     if (s < f.n_s) fetch(s, cur);
+    // the first lists arrive before the loop, so that within it only the
+    // lists of the next s are in flight (s_waitcnt vmcnt(0)): the loop's
+    // wait for the current lists then lets the prefetch stay outstanding
+    __builtin_amdgcn_s_waitcnt(0x0F70);
     while (s < f.n_s) {
         const int64_t sn = grab();
         Lists nxt{};
         if (sn < f.n_s) fetch(sn, nxt);
         const int64_t gx = qb * f.n_s + s, gy = pb * f.n_s + s;
         uint32_t x[8], y[8];
-        fused_rows(lds, w32, cur.y0, cur.y1, __builtin_amdgcn_readfirstlane(cur.my),
+        fused_rows(lds, o0, cur.y0, cur.y1, __builtin_amdgcn_readfirstlane(cur.my),
                    gp(f.entY) + (gy * 8 + a) * f.capY, y);
-        fused_rows(lds, w32, cur.x0, cur.x1, __builtin_amdgcn_readfirstlane(cur.mx),
+        fused_rows(lds, o0, cur.x0, cur.x1, __builtin_amdgcn_readfirstlane(cur.mx),
                    gp(f.entX) + (gx * 8 + a) * f.capX, x);
         fused_transpose8(x);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const uint32_t lo = y[i], hi = y[i + 4];
+            y[i] = odd ? hi : lo;
+            y[i + 4] = odd ? lo : hi;
+        }
 #pragma unroll
         for (int i = 0; i < 8; ++i) acc[i] |= x[i] & y[i];
         s = sn;
