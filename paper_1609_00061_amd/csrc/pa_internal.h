@@ -219,7 +219,10 @@ constexpr int kFusedRows = 513;                        // LDS rows of a fused ti
 // LDS row pitch in words: 8 words of t x 8 values
 constexpr int kFusedPitch = 64;
 constexpr uint32_t kFusedRowBytes = 4u * kFusedPitch;
-constexpr int kFusedLdsWords = kFusedRows * kFusedPitch + 9;   // rows, the tile's 8 output bytes, a counter
+// a header row (the latent-entry counter at LDS address 0, where ds_append
+// finds it with M0 = 0, then the tile's 8 output bytes, a word each), then
+// the rows
+constexpr int kFusedLdsWords = (kFusedRows + 1) * kFusedPitch;
 
 // A fused tile: 8 p (block pb) x 8 q (block qb); tile = pb n_qb + qb.  Bt
 // rows hold n_o x rwt words (rwt <= 8: the o-th 8-word slot of a staged LDS

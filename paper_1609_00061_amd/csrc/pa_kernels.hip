@@ -2471,20 +2471,23 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &f, int64_t tile, uin
     // the 16-byte slot of word w in a row that holds values 4 (a & 1) .. + 3
     const uint32_t o0 = (uint32_t)(lane & 7) * 16u + (uint32_t)(lane & 8) * 16u;
     const bool odd = (lane & 8) != 0;
-    uint32_t *out = lds + kFusedRows * kFusedPitch;     // 8 output bytes (a word each), the latent-entry counter
-    fused_stage(lds, f.BtX, f.btX_rw, f.kX, p0, f.n_p, f.rwt, 0);
-    fused_stage(lds, f.BtY, f.btY_rw, f.kY, qb * 8, f.n_q, f.rwt, f.kX);
-    if (tid < 64) lds[(f.kX + f.kY) * kFusedPitch + tid] = 0u;
-    if (tid < 9) out[tid] = 0u;
+    // header: the latent-entry counter (word 0), 8 output bytes (a word each)
+    uint32_t *cnt = lds, *out = lds + 8, *rows = lds + kFusedPitch;
+    fused_stage(rows, f.BtX, f.btX_rw, f.kX, p0, f.n_p, f.rwt, 0);
+    fused_stage(rows, f.BtY, f.btY_rw, f.kY, qb * 8, f.n_q, f.rwt, f.kX);
+    if (tid < 64) rows[(f.kX + f.kY) * kFusedPitch + tid] = 0u;
+    if (tid < 16) lds[tid] = 0u;
     __syncthreads();
     uint32_t acc[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
-    auto grab = [&]() {
-        uint32_t v = 0;
-        if (lane == 0) v = atomicAdd(out + 8, 1u);
-        return (int64_t)__builtin_amdgcn_readfirstlane(v);
-    };
+    // latent entries s come from the counter two ahead: the increment for
+    // the s after next is issued as a step starts and its value read as the
+    // step ends.  ds_append adds the number of active lanes (64: every wave
+    // is whole here) and returns the former value.
+    auto grab_issue = [&]() { return __builtin_amdgcn_ds_append((__attribute__((address_space(3))) int *)cnt); };
+    auto grab_read = [&](int v) { return (int64_t)((uint32_t)__builtin_amdgcn_readfirstlane(v) >> 6); };
     // the list rows of lane group a: AX row (q = a, s) of group (qb, s) and
-    // AY row (p = a, s) of group (pb, s); the groups' entry counts
+    // AY row (p = a, s) of group (pb, s) (rows cap >= 8 words apart, so that
+    // entries 0..7 are always in the buffer); the groups' entry counts
     const int a = lane >> 3;
     struct Lists {
         u32x4 x0, x1, y0, y1;
@@ -2494,29 +2497,21 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &f, int64_t tile, uin
         const int64_t gx = qb * f.n_s + s, gy = pb * f.n_s + s;
         const PA_G uint32_t *ex = gp(f.entX) + (gx * 8 + a) * f.capX, *ey = gp(f.entY) + (gy * 8 + a) * f.capY;
         l.x0 = *reinterpret_cast<const PA_G u32x4 *>(ex);
-        l.x1 = f.capX > 4 ? *reinterpret_cast<const PA_G u32x4 *>(ex + 4) : u32x4{0u, 0u, 0u, 0u};
+        l.x1 = *reinterpret_cast<const PA_G u32x4 *>(ex + 4);
         l.y0 = *reinterpret_cast<const PA_G u32x4 *>(ey);
-        l.y1 = f.capY > 4 ? *reinterpret_cast<const PA_G u32x4 *>(ey + 4) : u32x4{0u, 0u, 0u, 0u};
+        l.y1 = *reinterpret_cast<const PA_G u32x4 *>(ey + 4);
         l.mx = gp(f.metaX)[gx];
         l.my = gp(f.metaY)[gy];
     };
-    int64_t s = grab();
-    Lists cur{};
-    if (s < f.n_s) fetch(s, cur);
-    // the first lists arrive before the loop, so that within it only the
-    // lists of the next s are in flight (s_waitcnt vmcnt(0)): the loop's
-    // wait for the current lists then lets the prefetch stay outstanding
-    __builtin_amdgcn_s_waitcnt(0x0F70);
-    while (s < f.n_s) {
-        const int64_t sn = grab();
-        Lists nxt{};
-        if (sn < f.n_s) fetch(sn, nxt);
+    // one step: s with lists c (in hand), the lists of sn into n (sn past
+    // the end fetches the last s's, unused); returns the s after sn
+    auto step = [&](int64_t s, int64_t sn, const Lists &c, Lists &n) {
+        const int snn = grab_issue();
+        fetch(sn < f.n_s ? sn : f.n_s - 1, n);
         const int64_t gx = qb * f.n_s + s, gy = pb * f.n_s + s;
         uint32_t x[8], y[8];
-        fused_rows(lds, o0, cur.y0, cur.y1, __builtin_amdgcn_readfirstlane(cur.my),
-                   gp(f.entY) + (gy * 8 + a) * f.capY, y);
-        fused_rows(lds, o0, cur.x0, cur.x1, __builtin_amdgcn_readfirstlane(cur.mx),
-                   gp(f.entX) + (gx * 8 + a) * f.capX, x);
+        fused_rows(rows, o0, c.y0, c.y1, __builtin_amdgcn_readfirstlane(c.my), gp(f.entY) + (gy * 8 + a) * f.capY, y);
+        fused_rows(rows, o0, c.x0, c.x1, __builtin_amdgcn_readfirstlane(c.mx), gp(f.entX) + (gx * 8 + a) * f.capX, x);
         fused_transpose8(x);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -2526,7 +2521,21 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &f, int64_t tile, uin
         }
 #pragma unroll
         for (int i = 0; i < 8; ++i) acc[i] |= x[i] & y[i];
+        return grab_read(snn);
+    };
+    int64_t s = grab_read(grab_issue());
+    int64_t sn = grab_read(grab_issue());
+    Lists cur;
+    if (s < f.n_s) fetch(s, cur);
+    // the first lists arrive before the loop (s_waitcnt vmcnt(0)), so that
+    // within it only the lists of the next s are in flight while a step
+    // works
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+    while (s < f.n_s) {
+        Lists nxt;
+        const int64_t snn = step(s, sn, cur, nxt);
         s = sn;
+        sn = snn;
         cur = nxt;
     }
     uint32_t bits = 0;

@@ -907,8 +907,9 @@ static void fuse_pass_pairs(pa_plan *P) {
         if (GY.lc.rw != rwt || rwt > 8 || X.kall + Y.kall + 1 > kFusedRows) continue;
         // list buffer: per operand the heads, the meta words and the tails
         const int64_t gX = (n_q + 7) / 8 * n_s, gY = (n_p + 7) / 8 * n_s;
-        // list entries per row: the latent bits, rounded up to a multiple of 4
-        const int64_t capX = (X.kall + 3) / 4 * 4, capY = (Y.kall + 3) / 4 * 4;
+        // list entries per row: the latent bits, rounded up to a multiple of 4,
+        // at least 8 (the fused step always loads entries 0..7)
+        const int64_t capX = std::max<int64_t>(8, (X.kall + 3) / 4 * 4), capY = std::max<int64_t>(8, (Y.kall + 3) / 4 * 4);
         if (gX * 8 >= ((int64_t)1 << 31) || gY * 8 >= ((int64_t)1 << 31)) continue;
         int64_t off = 0;
         auto region = [&](int64_t words) {
@@ -1259,7 +1260,8 @@ static int check_fused_bounds(const Op &op, int64_t list_words, int64_t btx_word
         f.kX + f.kY + 1 > kFusedRows || f.btX_rw < f.n_p * f.rwt || f.btY_rw < f.n_q * f.rwt ||
         (int64_t)f.kX * f.btX_rw > btx_words || (int64_t)f.kY * f.btY_rw > bty_words ||
         f.n_qb != (f.n_q + 7) / 8 || 4 * f.c_rw < f.n_qb || f.n_p * f.c_rw > c_words ||
-        f.n_tiles != (f.n_p + 7) / 8 * f.n_qb || f.capX % 4 || f.capY % 4 || f.capX < f.kX || f.capY < f.kY ||
+        f.n_tiles != (f.n_p + 7) / 8 * f.n_qb || f.capX % 4 || f.capY % 4 || f.capX < std::max<int64_t>(8, f.kX) ||
+        f.capY < std::max<int64_t>(8, f.kY) ||
         op.sub[0] + gX * 8 * f.capX > list_words || op.sub[1] + gX > list_words ||
         op.sub[2] + gY * 8 * f.capY > list_words || op.sub[3] + gY > list_words)
         return fail(PA_EINVAL, "internal: fused step would index outside its buffers");
