@@ -199,14 +199,17 @@ constexpr int64_t kCountTileWords = 8192;    // A words per tile of a count step
 //
 // Row lists: rows are taken in groups of 8 consecutive values of the row's
 // output variable o (o-block ob) for one s: group g = ob * n_s + s, list
-// row 8 g + i for o = 8 ob + i.  List row r holds its set bits k as the LDS
-// byte offsets kFusedRowBytes (lbase + k) of their rows, in entries
-// r cap .. r cap + m - 1, m the largest count of the group's rows rounded up
-// to an even count (the group's meta word), padded with the all-zero row
-// zrow.  Rows with o >= n_o have no set bits.
+// row 8 g + i for o = 8 ob + i.  List row r holds its set bits k as the
+// 16-bit LDS row indices lbase + k, in any order, in entries r cap .. r cap +
+// m - 1, m the largest count of the group's rows rounded up to an even count
+// (the group's meta word), padded with the all-zero row zrow up to m (cap is
+// a multiple of 8: every list row starts 16-byte aligned and its entries
+// 0..7 are one 16-byte load; those from m on are never read).  Rows with
+// o >= n_o have no set bits.
 struct RowListArgs {
     const uint32_t *A;        // the pass's A operand: row (o, s) at (o ro + s rs) Kw words
-    uint32_t *ent, *meta;     // cap entries per list row; one word per group
+    uint16_t *ent;            // cap entries per list row
+    uint32_t *meta;           // one word per group
     int64_t n_o, n_s, ro, rs;
     int64_t Kw, rwk, rkp;     // A row words; bit b of word w = ko rwk + wp is k = ko rkp + 32 wp + b
     int lbase, zrow;
@@ -214,6 +217,8 @@ struct RowListArgs {
     int64_t n_rows;           // 8 ceil(n_o / 8) n_s list rows
     FastDiv fd_s;             // division by n_s (of group indices below 2^31)
 };
+
+constexpr int kListRowsPerTile = 32;                  // a row-list tile: 256 threads, 8 to a row
 
 constexpr int kFusedRows = 513;                        // LDS rows of a fused tile: BtX, BtY, the zero row
 // LDS row pitch in words: 8 words of t x 8 values
@@ -229,7 +234,8 @@ constexpr int kFusedLdsWords = (kFusedRows + 1) * kFusedPitch;
 // row is padded with zeros).
 struct FusedArgs {
     const uint32_t *BtX, *BtY;
-    const uint32_t *entX, *metaX, *entY, *metaY;
+    const uint16_t *entX, *entY;
+    const uint32_t *metaX, *metaY;
     uint32_t *C;
     int64_t n_p, n_q, n_s;
     int64_t btX_rw, btY_rw;   // Bt row words: n_p rwt, n_q rwt

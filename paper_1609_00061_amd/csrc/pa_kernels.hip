@@ -2247,40 +2247,52 @@ hipError_t launch_gather(const GatherArgs &g, hipStream_t s) {
 // of their rows, entries 0 .. m - 1 of the list row (m: the largest count of
 // the row's group of 8, rounded up to an even count), padded with the zero
 // row; m is the group's meta word.
+// One tile: kListRowsPerTile list rows, 8 lanes to a row (lane l takes the
+// row's words l, l + 8, ..), so that a wave holds one group of 8 rows.  The
+// lanes' counts give the row's count, the group's largest and each lane's
+// first entry; every lane writes the entries of its own set bits, and the
+// row's lanes together pad the row with the zero row up to m.
 __device__ __forceinline__ void row_list_tile(const RowListArgs &L, int64_t tile) {
-    const int64_t r = tile * 256 + threadIdx.x;
-    const bool valid = r < L.n_rows;
+    const int lane = (int)(threadIdx.x & 63), l = lane & 7;
+    const int64_t r = tile * kListRowsPerTile + (threadIdx.x >> 3);
+    const bool valid = r < L.n_rows;   // whole waves: n_rows is a multiple of 8
     const int64_t g = r >> 3, ob = fdiv((uint32_t)g, L.fd_s), s = g - ob * L.n_s, o = ob * 8 + (r & 7);
-    const uint32_t Z = (uint32_t)L.zrow * kFusedRowBytes;
-    PA_G uint32_t *ent = gp(L.ent) + r * L.cap;
-    const PA_G uint32_t *row = gp(L.A) + (o * L.ro + s * L.rs) * L.Kw;
     const bool has = valid && o < L.n_o;
-    const uint32_t rwk = (uint32_t)L.rwk, rkp = (uint32_t)L.rkp;
-    // pass 1: the count; pass 2 writes the entries (rows hold few set bits:
-    // the second read of the row comes from L1)
-    auto word = [&](uint32_t w) { return has ? row[w] : 0u; };
+    const PA_G uint32_t *row = gp(L.A) + (o * L.ro + s * L.rs) * L.Kw;
+    const uint32_t Kw = (uint32_t)L.Kw, rwk = (uint32_t)L.rwk, rkp = (uint32_t)L.rkp;
     uint32_t cnt = 0;
-    for (uint32_t w = 0; w < (uint32_t)L.Kw; ++w) cnt += __builtin_popcount(word(w));
-    // the largest count of the group's 8 rows (8 consecutive lanes)
-    uint32_t mx = cnt;
-    mx = max(mx, (uint32_t)__shfl_xor((int)mx, 1));
-    mx = max(mx, (uint32_t)__shfl_xor((int)mx, 2));
-    mx = max(mx, (uint32_t)__shfl_xor((int)mx, 4));
+    if (has)
+        for (uint32_t w = (uint32_t)l; w < Kw; w += 8) cnt += __builtin_popcount(row[w]);
+    uint32_t rc = cnt;
+    rc += (uint32_t)__shfl_xor((int)rc, 1);
+    rc += (uint32_t)__shfl_xor((int)rc, 2);
+    rc += (uint32_t)__shfl_xor((int)rc, 4);
+    uint32_t mx = rc;
+    mx = max(mx, (uint32_t)__shfl_xor((int)mx, 8));
+    mx = max(mx, (uint32_t)__shfl_xor((int)mx, 16));
+    mx = max(mx, (uint32_t)__shfl_xor((int)mx, 32));
     const uint32_t m = (mx + 1u) & ~1u;
-    if (!valid) return;
-    uint32_t n = 0;
-    auto put = [&](uint32_t e) { ent[n++] = e; };
-    for (uint32_t w = 0; w < (uint32_t)L.Kw; ++w) {
-        uint32_t x = word(w);
-        const uint32_t ko = w / rwk;
-        const uint32_t kb = (uint32_t)L.lbase + ko * rkp + (w - ko * rwk) * 32u;
-        while (x) {
-            put((kb + (uint32_t)__builtin_ctz(x)) * kFusedRowBytes);
-            x &= x - 1;
-        }
+    uint32_t inc = cnt;
+#pragma unroll
+    for (int d = 1; d < 8; d <<= 1) {
+        const uint32_t t = (uint32_t)__shfl_up((int)inc, d, 8);
+        if (l >= d) inc += t;
     }
-    while (n < m) put(Z);
-    if ((r & 7) == 0) gp(L.meta)[g] = m;
+    if (!valid) return;
+    PA_G uint16_t *ent = gp(L.ent) + r * L.cap;
+    uint32_t pos = inc - cnt;
+    if (has)
+        for (uint32_t w = (uint32_t)l; w < Kw; w += 8) {
+            uint32_t x = row[w];
+            const uint32_t ko = w / rwk;
+            const uint32_t kb = (uint32_t)L.lbase + ko * rkp + (w - ko * rwk) * 32u;
+            while (x) {
+                ent[pos++] = (uint16_t)(kb + (uint32_t)__builtin_ctz(x));
+                x &= x - 1;
+            }
+        }
+    for (uint32_t e = rc + (uint32_t)l; e < m; e += 8) ent[e] = (uint16_t)L.zrow;
+    if (lane == 0) gp(L.meta)[g] = m;
 }
 
 __global__ __launch_bounds__(256) void k_row_list(RowListArgs L, int64_t n_tiles) {
@@ -2288,7 +2300,7 @@ __global__ __launch_bounds__(256) void k_row_list(RowListArgs L, int64_t n_tiles
 }
 
 hipError_t launch_row_list(const RowListArgs &l, hipStream_t s) {
-    const int64_t nt = (l.n_rows + 255) / 256;
+    const int64_t nt = (l.n_rows + kListRowsPerTile - 1) / kListRowsPerTile;
     if (nt <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_row_list, dim3((unsigned)(nt < (1 << 20) ? nt : (1 << 20))), dim3(256), 0, s, l, nt);
     return hipGetLastError();
@@ -2354,25 +2366,32 @@ __device__ __forceinline__ void fused_stage(uint32_t *lds, const uint32_t *bt, i
     }
 }
 
-// N list entries (LDS row byte offsets, one set per lane group) gathered
-// into c with two 16-byte loads per entry, at byte offsets o0 and o0 ^ 128
-// of the row.  Lane (a, w) (a = lane / 8, w = lane & 7) reads the half of word w's
-// values that holds values 4 (a & 1) .. + 3 first: c[v] |= value v ^ 4 (a &
-// 1) of word w.  A 16-byte read is served in passes of 16 lanes, each
-// pass taking 4 lanes from each of 4 lane groups, two groups of each
-// parity; with the halves alternating by group parity the 16 lanes of a
-// pass read 16 distinct 16-byte slots of the 64 banks.  All loads are issued
-// before any is used.
+// The LDS byte addresses of the two list entries (16-bit row indices) in
+// word e, each plus o0 (< 256, the lane's slot): (index << 8) | o0, built
+// with one byte permutation each.
+__device__ __forceinline__ uint32_t fused_addr_lo(uint32_t e, uint32_t o0) {
+    return __builtin_amdgcn_perm(e, o0, 0x0c050400u);
+}
+__device__ __forceinline__ uint32_t fused_addr_hi(uint32_t e, uint32_t o0) {
+    return __builtin_amdgcn_perm(e, o0, 0x0c070600u);
+}
+
+// N rows gathered into c with two 16-byte loads per row, at LDS byte
+// addresses b and b ^ 128 (b = row start + o0).  Lane (a, w) (a = lane / 8,
+// w = lane & 7) has o0 at the half of word w's values that holds values
+// 4 (a & 1) .. + 3: c[v] |= value v ^ 4 (a & 1) of word w.  A 16-byte read
+// is served in passes of 16 lanes, each pass taking 4 lanes from each of 4
+// lane groups, two groups of each parity; with the halves alternating by
+// group parity the 16 lanes of a pass read 16 distinct 16-byte slots of
+// the 64 banks.  All loads are issued before any is used.
 template <int N>
-__device__ __forceinline__ void fused_gather(const uint32_t *lds, uint32_t o0, const uint32_t (&e)[N],
-                                             uint32_t (&c)[8]) {
+__device__ __forceinline__ void fused_gather(const uint32_t *lds, const uint32_t (&b)[N], uint32_t (&c)[8]) {
     const char *base = reinterpret_cast<const char *>(lds);
     u32x4 r[N][2];
 #pragma unroll
     for (int j = 0; j < N; ++j) {
-        const uint32_t b = e[j] + o0;
-        r[j][0] = *reinterpret_cast<const u32x4 *>(base + b);
-        r[j][1] = *reinterpret_cast<const u32x4 *>(base + (b ^ 128u));
+        r[j][0] = *reinterpret_cast<const u32x4 *>(base + b[j]);
+        r[j][1] = *reinterpret_cast<const u32x4 *>(base + (b[j] ^ 128u));
     }
 #pragma unroll
     for (int j = 0; j < N; ++j) {
@@ -2389,37 +2408,40 @@ __device__ __forceinline__ void fused_gather(const uint32_t *lds, uint32_t o0, c
 
 // The list rows of one group, one per lane group (row a for lanes 8a ..
 // 8a + 7): c[v] = OR over the entries of the lane group's row of value
-// v ^ 4 (a & 1) of word w of its LDS row.  e0, e1 hold the row's entries
-// 0..3 and 4..7 (loaded one latent entry ahead), m the group's (even) entry
-// count; entries beyond 8 are loaded here.
-__device__ __forceinline__ void fused_rows(const uint32_t *lds, uint32_t o0, const u32x4 &e0, const u32x4 &e1,
-                                           uint32_t m, const PA_G uint32_t *ent, uint32_t (&c)[8]) {
+// v ^ 4 (a & 1) of word w of its LDS row.  e holds the row's entries 0..7
+// (loaded one latent entry ahead), m the group's (even) entry count, ent the
+// row's entries as words (two to a word), of which those beyond 8 are
+// loaded here.
+__device__ __forceinline__ void fused_rows(const uint32_t *lds, uint32_t o0, const u32x4 &e, uint32_t m,
+                                           const PA_G uint32_t *ent, uint32_t (&c)[8]) {
 #pragma unroll
     for (int v = 0; v < 8; ++v) c[v] = 0u;
     if (m == 0u) return;
     if (m == 2u) {
-        const uint32_t e[2] = {e0.x, e0.y};
-        fused_gather<2>(lds, o0, e, c);
+        const uint32_t b[2] = {fused_addr_lo(e.x, o0), fused_addr_hi(e.x, o0)};
+        fused_gather<2>(lds, b, c);
         return;
     }
     {
-        const uint32_t e[4] = {e0.x, e0.y, e0.z, e0.w};
-        fused_gather<4>(lds, o0, e, c);
+        const uint32_t b[4] = {fused_addr_lo(e.x, o0), fused_addr_hi(e.x, o0), fused_addr_lo(e.y, o0),
+                               fused_addr_hi(e.y, o0)};
+        fused_gather<4>(lds, b, c);
     }
     if (m == 4u) return;
     if (m == 6u) {
-        const uint32_t e[2] = {e1.x, e1.y};
-        fused_gather<2>(lds, o0, e, c);
+        const uint32_t b[2] = {fused_addr_lo(e.z, o0), fused_addr_hi(e.z, o0)};
+        fused_gather<2>(lds, b, c);
         return;
     }
     {
-        const uint32_t e[4] = {e1.x, e1.y, e1.z, e1.w};
-        fused_gather<4>(lds, o0, e, c);
+        const uint32_t b[4] = {fused_addr_lo(e.z, o0), fused_addr_hi(e.z, o0), fused_addr_lo(e.w, o0),
+                               fused_addr_hi(e.w, o0)};
+        fused_gather<4>(lds, b, c);
     }
-    for (uint32_t j = 8; j < m; j += 2) {
-        const u32x2 t = *reinterpret_cast<const PA_G u32x2 *>(ent + j);
-        const uint32_t e[2] = {t.x, t.y};
-        fused_gather<2>(lds, o0, e, c);
+    for (uint32_t j = 4; j < m / 2; ++j) {
+        const uint32_t t = ent[j];
+        const uint32_t b[2] = {fused_addr_lo(t, o0), fused_addr_hi(t, o0)};
+        fused_gather<2>(lds, b, c);
     }
 }
 
@@ -2486,20 +2508,20 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &f, int64_t tile, uin
     auto grab_issue = [&]() { return __builtin_amdgcn_ds_append((__attribute__((address_space(3))) int *)cnt); };
     auto grab_read = [&](int v) { return (int64_t)((uint32_t)__builtin_amdgcn_readfirstlane(v) >> 6); };
     // the list rows of lane group a: AX row (q = a, s) of group (qb, s) and
-    // AY row (p = a, s) of group (pb, s) (rows cap >= 8 words apart, so that
-    // entries 0..7 are always in the buffer); the groups' entry counts
+    // AY row (p = a, s) of group (pb, s) (entries 0..7 one 16-byte load);
+    // the groups' entry counts
     const int a = lane >> 3;
     struct Lists {
-        u32x4 x0, x1, y0, y1;
+        u32x4 x, y;
         uint32_t mx, my;
+    };
+    auto list_row = [&](const uint16_t *ent, int64_t g, int64_t cap) {
+        return reinterpret_cast<const PA_G uint32_t *>(gp(ent) + (g * 8 + a) * cap);
     };
     auto fetch = [&](int64_t s, Lists &l) {
         const int64_t gx = qb * f.n_s + s, gy = pb * f.n_s + s;
-        const PA_G uint32_t *ex = gp(f.entX) + (gx * 8 + a) * f.capX, *ey = gp(f.entY) + (gy * 8 + a) * f.capY;
-        l.x0 = *reinterpret_cast<const PA_G u32x4 *>(ex);
-        l.x1 = *reinterpret_cast<const PA_G u32x4 *>(ex + 4);
-        l.y0 = *reinterpret_cast<const PA_G u32x4 *>(ey);
-        l.y1 = *reinterpret_cast<const PA_G u32x4 *>(ey + 4);
+        l.x = *reinterpret_cast<const PA_G u32x4 *>(list_row(f.entX, gx, f.capX));
+        l.y = *reinterpret_cast<const PA_G u32x4 *>(list_row(f.entY, gy, f.capY));
         l.mx = gp(f.metaX)[gx];
         l.my = gp(f.metaY)[gy];
     };
@@ -2510,8 +2532,8 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &f, int64_t tile, uin
         fetch(sn < f.n_s ? sn : f.n_s - 1, n);
         const int64_t gx = qb * f.n_s + s, gy = pb * f.n_s + s;
         uint32_t x[8], y[8];
-        fused_rows(rows, o0, c.y0, c.y1, __builtin_amdgcn_readfirstlane(c.my), gp(f.entY) + (gy * 8 + a) * f.capY, y);
-        fused_rows(rows, o0, c.x0, c.x1, __builtin_amdgcn_readfirstlane(c.mx), gp(f.entX) + (gx * 8 + a) * f.capX, x);
+        fused_rows(rows, o0, c.y, __builtin_amdgcn_readfirstlane(c.my), list_row(f.entY, gy, f.capY), y);
+        fused_rows(rows, o0, c.x, __builtin_amdgcn_readfirstlane(c.mx), list_row(f.entX, gx, f.capX), x);
         fused_transpose8(x);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {

@@ -907,9 +907,9 @@ static void fuse_pass_pairs(pa_plan *P) {
         if (GY.lc.rw != rwt || rwt > 8 || X.kall + Y.kall + 1 > kFusedRows) continue;
         // list buffer: per operand the heads, the meta words and the tails
         const int64_t gX = (n_q + 7) / 8 * n_s, gY = (n_p + 7) / 8 * n_s;
-        // list entries per row: the latent bits, rounded up to a multiple of 4,
-        // at least 8 (the fused step always loads entries 0..7)
-        const int64_t capX = std::max<int64_t>(8, (X.kall + 3) / 4 * 4), capY = std::max<int64_t>(8, (Y.kall + 3) / 4 * 4);
+        // 16-bit list entries per row: the latent bits, at least 8 (the fused
+        // step always loads entries 0..7), rounded up to a multiple of 8
+        const int64_t capX = (std::max<int64_t>(8, X.kall) + 7) / 8 * 8, capY = (std::max<int64_t>(8, Y.kall) + 7) / 8 * 8;
         if (gX * 8 >= ((int64_t)1 << 31) || gY * 8 >= ((int64_t)1 << 31)) continue;
         int64_t off = 0;
         auto region = [&](int64_t words) {
@@ -918,9 +918,9 @@ static void fuse_pass_pairs(pa_plan *P) {
             return at;
         };
         int64_t sub[6] = {0, 0, 0, 0, 0, 0};
-        sub[0] = region(gX * 8 * capX);
+        sub[0] = region(gX * 8 * capX / 2);
         sub[1] = region(gX);
-        sub[2] = region(gY * 8 * capY);
+        sub[2] = region(gY * 8 * capY / 2);
         sub[3] = region(gY);
         Layout ll;
         ll.rw = off;
@@ -1243,8 +1243,9 @@ static int check_list_bounds(const Op &op, int64_t a_words, int64_t list_words) 
     const int64_t groups = (l.n_o + 7) / 8 * l.n_s;
     if (l.n_o < 1 || l.n_s < 1 || l.Kw < 1 || l.rwk < 1 || l.Kw % l.rwk || l.rkp < 1 || l.rkp > 32 * l.rwk ||
         l.n_rows != groups * 8 || ((l.n_o - 1) * l.ro + (l.n_s - 1) * l.rs + 1) * l.Kw > a_words ||
-        l.lbase < 0 || l.lbase + l.Kw / l.rwk * l.rkp > l.zrow || l.zrow >= kFusedRows || l.cap % 4 ||
-        l.cap < l.Kw / l.rwk * l.rkp || op.sub[0] + l.n_rows * l.cap > list_words || op.sub[1] + groups > list_words)
+        l.lbase < 0 || l.lbase + l.Kw / l.rwk * l.rkp > l.zrow || l.zrow >= kFusedRows || l.cap % 8 ||
+        l.cap < l.Kw / l.rwk * l.rkp || op.sub[0] + l.n_rows * l.cap / 2 > list_words ||
+        op.sub[1] + groups > list_words)
         return fail(PA_EINVAL, "internal: row-list step would index outside its buffers");
     // list rows are 32-bit
     if (l.n_rows >= ((int64_t)1 << 31))
@@ -1260,10 +1261,9 @@ static int check_fused_bounds(const Op &op, int64_t list_words, int64_t btx_word
         f.kX + f.kY + 1 > kFusedRows || f.btX_rw < f.n_p * f.rwt || f.btY_rw < f.n_q * f.rwt ||
         (int64_t)f.kX * f.btX_rw > btx_words || (int64_t)f.kY * f.btY_rw > bty_words ||
         f.n_qb != (f.n_q + 7) / 8 || 4 * f.c_rw < f.n_qb || f.n_p * f.c_rw > c_words ||
-        f.n_tiles != (f.n_p + 7) / 8 * f.n_qb || f.capX % 4 || f.capY % 4 || f.capX < std::max<int64_t>(8, f.kX) ||
-        f.capY < std::max<int64_t>(8, f.kY) ||
-        op.sub[0] + gX * 8 * f.capX > list_words || op.sub[1] + gX > list_words ||
-        op.sub[2] + gY * 8 * f.capY > list_words || op.sub[3] + gY > list_words)
+        f.n_tiles != (f.n_p + 7) / 8 * f.n_qb || f.capX % 8 || f.capY % 8 || f.capX < f.kX || f.capY < f.kY ||
+        op.sub[0] + gX * 8 * f.capX / 2 > list_words || op.sub[1] + gX > list_words ||
+        op.sub[2] + gY * 8 * f.capY / 2 > list_words || op.sub[3] + gY > list_words)
         return fail(PA_EINVAL, "internal: fused step would index outside its buffers");
     return PA_OK;
 }
@@ -1294,7 +1294,7 @@ static int list_args(pa_plan *P, const Op &op, void *out, RowListArgs &l) {
     l = op.rl;
     l.A = buf_ptr(P, op.a, out);
     uint32_t *lb = buf_ptr(P, op.c, out);
-    l.ent = lb + op.sub[0];
+    l.ent = reinterpret_cast<uint16_t *>(lb + op.sub[0]);
     l.meta = lb + op.sub[1];
     return PA_OK;
 }
@@ -1307,9 +1307,9 @@ static int fused_args(pa_plan *P, const Op &op, void *out, FusedArgs &f) {
     f.BtX = buf_ptr(P, op.b, out);
     f.BtY = buf_ptr(P, op.flag, out);
     const uint32_t *lb = buf_ptr(P, op.a, out);
-    f.entX = lb + op.sub[0];
+    f.entX = reinterpret_cast<const uint16_t *>(lb + op.sub[0]);
     f.metaX = lb + op.sub[1];
-    f.entY = lb + op.sub[2];
+    f.entY = reinterpret_cast<const uint16_t *>(lb + op.sub[2]);
     f.metaY = lb + op.sub[3];
     f.C = buf_ptr(P, op.c, out);
     return PA_OK;
@@ -1381,7 +1381,7 @@ static int build_steps(pa_plan *P) {
             int rc = list_args(P, op, nullptr, s.list);
             if (rc) return rc;
             s.kind = kStepList;
-            s.n_tiles = (op.rl.n_rows + 255) / 256;
+            s.n_tiles = (op.rl.n_rows + kListRowsPerTile - 1) / kListRowsPerTile;
             dep(op.a);
             list_steps[op.c].push_back((int)st.size());
         } else if (op.kind == OP_FUSED) {
