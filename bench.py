@@ -36,8 +36,10 @@ FP4_DENSE_PEAK_TOPS = 10100.0      # MI355X dense fp4 MFMA, 10.1 PFLOP/s (the Bo
 INT8_DENSE_PEAK_TOPS = 5000.0      # MI355X dense int8 MFMA, 5.0 POP/s (for comparison only)
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 HBM_PEAK_GBS = 8000.0
-# LDS read bandwidth: 128 bytes per clock per CU, 256 CUs at 2.4 GHz
-LDS_PEAK_GBS = 128 * 256 * 2.4
+# LDS read bandwidth: 64 banks of 4 bytes per CU, 256 bytes per clock (a
+# 16-lane pass of 16-byte reads per clock), 256 CUs at 2.4 GHz; the fused
+# step's roofline also reports the rate pa.lds_read_rate() measures
+LDS_PEAK_GBS = 256 * 256 * 2.4
 METRIC = "pixel-array solves/sec + bool-contraction TOPS vs plain GPU path, bit-exact"
 TERNARY = ("4 random trivariate cubics over 6 variables (every pair sharing one), N(0,1) coefficients "
            "(seed 160900061), [-3,3]^6 at 256 cells/axis, (v1, v4) exposed, 4 latent")
@@ -145,7 +147,9 @@ def _work_of(system, d):
     for o in d["ops"]:
         if o["op"] == "row_list":
             groups = o["rows"] // 8
-            out["list_bytes"] += 4.0 * (words[o["a"]] + groups * (32 + 16))
+            # A read; per list row its 8-entry head (16 bytes), per group its
+            # meta word written
+            out["list_bytes"] += 4.0 * (words[o["a"]] + groups * (8 * 4 + 1))
         elif o["op"] == "fused_pass_pair":
             lx = [l for l in lists if l["c"] == o["lists"] and l["lbase"] == 0][0]
             ly = [l for l in lists if l["c"] == o["lists"] and l["lbase"] == o["kx"]][0]
@@ -217,7 +221,9 @@ def _rooflines(plan, system, d, stream, reps, traffic):
         elif kind == pa.OPKIND_FUSED:
             b = w["fused_lds_bytes"] / a["launches"]
             ach = b / (avg * 1e-3) / 1e9
+            meas = pa.lds_read_rate(stream) / 1e9
             ent.update(achieved=ach, peak=LDS_PEAK_GBS, unit="GB/s", frac=ach / LDS_PEAK_GBS, lds_bytes_per_launch=b,
+                       lds_read_rate_measured=meas, frac_of_measured=ach / meas,
                        effective_tops=2.0 * w["fused_macs"] / (a["ms"] * 1e-3) / 1e12)
         elif kind in (pa.OPKIND_STREAM_K, pa.OPKIND_STREAM_W):
             b = w["stream_bytes"] / a["launches"]

@@ -534,6 +534,17 @@ int pa_popcount(const pa_bitarray *a, int64_t *count, void *stream);
  * word.  EINVAL: tile sizes < 1, or tile_rows * tile_words * 32 >= 2^32. */
 int pa_tile_popcount(const pa_bitarray *a, int32_t tile_rows, int32_t tile_words, uint32_t *counts, void *stream);
 
+/* Measured LDS read rate of the current device, the reference of the
+ * LDS-bound fused pass pair's roofline: one workgroup of 1024 threads per CU,
+ * every lane reading its own 16-byte slot of a 64 KiB LDS array (free of
+ * bank conflicts, 8 independent reads per iteration, 4096 iterations); one
+ * warm-up launch, then one launch timed with HIP events on stream.
+ * *bytes_per_second (host) receives CUs x 1024 x 4096 x 128 bytes / the
+ * timed launch's duration.  Uses the library's small internal workspace
+ * (4 KiB per CU).  Returns PA_OK, PA_EINVAL (null output), PA_ENOMEM or
+ * PA_EHIP. */
+int pa_lds_read_rate(double *bytes_per_second, void *stream);
+
 /* Thread-local message describing the last error. */
 const char *pa_last_error(void);
 

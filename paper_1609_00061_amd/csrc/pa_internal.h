@@ -313,6 +313,9 @@ hipError_t launch_row_list(const RowListArgs &l, hipStream_t s);
 hipError_t launch_fused(const PStep *d_step, int64_t n_tiles, uint32_t *C, hipStream_t s);
 hipError_t launch_fill(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
 hipError_t launch_popcount(const uint32_t *p, int64_t n, unsigned long long *out, hipStream_t s);
+// LDS read-rate reference: blocks workgroups of 1024 threads, each reading
+// iters x 8 x 16 KiB of LDS; out holds blocks x 1024 words.
+hipError_t launch_lds_rate(uint32_t *out, int blocks, int iters, hipStream_t s);
 hipError_t launch_tile_popcount(const uint32_t *p, int64_t rows, int64_t rw, int tile_rows, int tile_words,
                                 uint32_t *out, hipStream_t s);
 // The single persistent launch: chunks of the groups (table of ngroups

@@ -2573,6 +2573,42 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &f, int64_t tile, uin
     }
 }
 
+// ------------------------------------------------- LDS read-rate reference
+// One workgroup of 1024 threads per CU; every lane reads its own 16-byte slot
+// of a 64 KiB LDS array (free of bank conflicts), 8 independent reads per
+// iteration, folded into one word per lane that is written out (so that the
+// reads stay).  The measured rate is the reference of the LDS-bound fused
+// step's roofline.
+__global__ __launch_bounds__(1024, 1) void k_lds_rate(uint32_t *out, int iters) {
+    __shared__ __attribute__((aligned(16))) u32x4 lds[4096];
+    const int tid = threadIdx.x, lane = tid & 63;
+    for (int i = tid; i < 4096; i += 1024) lds[i] = u32x4{(uint32_t)i, (uint32_t)i + 1u, (uint32_t)i + 2u, (uint32_t)i + 3u};
+    __syncthreads();
+    const char *base = reinterpret_cast<const char *>(lds);
+    const uint32_t w = (uint32_t)(tid >> 6);
+    uint32_t acc0 = 0u, acc1 = 0u;
+    for (int it = 0; it < iters; ++it) {
+        const uint32_t blk = ((uint32_t)it * 8u + w) & 63u;
+        uint32_t v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            // 1 KiB block (blk + 8 j) mod 64, slot lane
+            const u32x4 a = *reinterpret_cast<const u32x4 *>(base + ((blk + 8u * (uint32_t)j) & 63u) * 1024u +
+                                                             (uint32_t)lane * 16u);
+            v[j] = a.x ^ a.y ^ a.z ^ a.w;
+        }
+        acc0 ^= v[0] ^ v[1] ^ v[2] ^ v[3];
+        acc1 ^= v[4] ^ v[5] ^ v[6] ^ v[7];
+    }
+    gp(out)[(int64_t)blockIdx.x * 1024 + tid] = acc0 + acc1;
+}
+
+hipError_t launch_lds_rate(uint32_t *out, int blocks, int iters, hipStream_t s) {
+    if (blocks <= 0 || iters <= 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_lds_rate, dim3((unsigned)blocks), dim3(1024), 0, s, out, iters);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------ fill, count
 __global__ void k_fill(uint32_t *p, int64_t n, uint32_t v) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)

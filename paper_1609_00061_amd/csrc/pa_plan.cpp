@@ -2232,6 +2232,40 @@ extern "C" int pa_popcount(const pa_bitarray *a, int64_t *count, void *stream) {
     return PA_OK;
 }
 
+extern "C" int pa_lds_read_rate(double *bytes_per_second, void *stream) {
+    if (!bytes_per_second) return fail(PA_EINVAL, "lds_read_rate: null output");
+    int dev = 0, cus = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    if (cus < 1) return fail(PA_EINVAL, "lds_read_rate: no compute units");
+    constexpr int kIters = 4096;
+    auto &S = scratch();
+    std::lock_guard<std::mutex> lk(S.mu);
+    int rc = S.ws.ensure((size_t)cus * 1024 * 4);
+    if (rc) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    uint32_t *out = static_cast<uint32_t *>(S.ws.ptr);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(PA_EHIP, "lds_read_rate: hipEventCreate failed");
+    }
+    float ms = 0.f;
+    hipError_t e = launch_lds_rate(out, cus, kIters, s);     // warm-up
+    if (e == hipSuccess) e = hipEventRecord(e0, s);
+    if (e == hipSuccess) e = launch_lds_rate(out, cus, kIters, s);
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return fail(PA_EHIP, std::string("lds_read_rate: ") + hipGetErrorString(e));
+    if (!(ms > 0.f)) return fail(PA_EHIP, "lds_read_rate: no elapsed time");
+    *bytes_per_second = (double)cus * 1024.0 * kIters * 8.0 * 16.0 / (ms * 1e-3);
+    return PA_OK;
+}
+
 extern "C" int pa_tile_popcount(const pa_bitarray *a, int32_t tile_rows, int32_t tile_words, uint32_t *counts,
                                 void *stream) {
     if (!a || !counts || !a->data || a->ndim < 0 || a->ndim > PA_MAX_DIMS) return fail(PA_EINVAL, "tile_popcount: bad args");

@@ -137,6 +137,7 @@ def load(path: str = LIB_PATH):
                                   ctypes.POINTER(BitArray), ctypes.POINTER(Report), vp]
     L.pa_popcount.argtypes = [ctypes.POINTER(BitArray), ctypes.POINTER(ctypes.c_int64), vp]
     L.pa_tile_popcount.argtypes = [ctypes.POINTER(BitArray), ctypes.c_int32, ctypes.c_int32, vp, vp]
+    L.pa_lds_read_rate.argtypes = [ctypes.POINTER(ctypes.c_double), vp]
     L.pa_plan_op_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32),
                                    ctypes.POINTER(ctypes.c_double), ctypes.c_int32]
     L.pa_plan_op_times.restype = ctypes.c_int32
@@ -709,6 +710,14 @@ def popcount(t, dims) -> int:
     ba = bitarray(t, dims)
     _check(L.pa_popcount(ctypes.byref(ba), ctypes.byref(c), _stream_ptr()))
     return int(c.value)
+
+
+def lds_read_rate(stream=None) -> float:
+    """Measured LDS read rate of the current device in bytes/s (conflict-free
+    16-byte reads, one 1024-thread workgroup per CU)."""
+    r = ctypes.c_double(0.0)
+    _check(load().pa_lds_read_rate(ctypes.byref(r), _stream_ptr(stream)))
+    return float(r.value)
 
 
 def tile_popcount(t, dims, tile_rows, tile_words, stream=None):
