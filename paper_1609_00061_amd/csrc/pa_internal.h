@@ -201,8 +201,8 @@ constexpr int64_t kCountTileWords = 8192;    // A words per tile of a count step
 // output variable o (o-block ob) for one s: group g = ob * n_s + s, list
 // row 8 g + i for o = 8 ob + i.  List row r holds its set bits k as the
 // 16-bit LDS row indices lbase + k, in any order, in entries r cap .. r cap +
-// m - 1, m the largest count of the group's rows rounded up to an even count
-// (the group's meta word), padded with the all-zero row zrow up to m (cap is
+// m - 1, m the largest count of the group's rows (the group's meta word),
+// padded with the all-zero row zrow up to m (cap is
 // a multiple of 8: every list row starts 16-byte aligned and its entries
 // 0..7 are one 16-byte load; those from m on are never read).  Rows with
 // o >= n_o have no set bits.

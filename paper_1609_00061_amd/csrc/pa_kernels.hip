@@ -2242,11 +2242,9 @@ hipError_t launch_gather(const GatherArgs &g, hipStream_t s) {
 }
 
 // -------------------------------------------------------- fused pass pair
-// Row lists (one thread per list row, 256 per tile): the set bits k of the A
-// row, in increasing order, as the LDS byte offsets kFusedRowBytes (lbase + k)
-// of their rows, entries 0 .. m - 1 of the list row (m: the largest count of
-// the row's group of 8, rounded up to an even count), padded with the zero
-// row; m is the group's meta word.
+// Row lists: the set bits k of the A row as the 16-bit LDS row indices
+// lbase + k, entries 0 .. m - 1 of the list row (m: the largest count of the
+// row's group of 8), padded with the zero row; m is the group's meta word.
 // One tile: kListRowsPerTile list rows, 8 lanes to a row (lane l takes the
 // row's words l, l + 8, ..), so that a wave holds one group of 8 rows.  The
 // lanes' counts give the row's count, the group's largest and each lane's
@@ -2271,7 +2269,7 @@ __device__ __forceinline__ void row_list_tile(const RowListArgs &L, int64_t tile
     mx = max(mx, (uint32_t)__shfl_xor((int)mx, 8));
     mx = max(mx, (uint32_t)__shfl_xor((int)mx, 16));
     mx = max(mx, (uint32_t)__shfl_xor((int)mx, 32));
-    const uint32_t m = (mx + 1u) & ~1u;
+    const uint32_t m = mx;
     uint32_t inc = cnt;
 #pragma unroll
     for (int d = 1; d < 8; d <<= 1) {
@@ -2366,6 +2364,47 @@ __device__ __forceinline__ void fused_stage(uint32_t *lds, const uint32_t *bt, i
     }
 }
 
+// Both operands' rows when t has 8 words (BtX rows 0 .. kX - 1 for values
+// o0x .., BtY rows kX .. kX + kY - 1 for values o0y ..), laid out as in
+// fused_stage; each round issues the loads of both before any store, so
+// that the two stagings share one wait.
+__device__ __forceinline__ void fused_stage8_pair(uint32_t *lds, const uint32_t *btx, int64_t btx_rw, int KX,
+                                                  int64_t o0x, int64_t n_ox, const uint32_t *bty, int64_t bty_rw,
+                                                  int KY, int64_t o0y, int64_t n_oy) {
+    const int tid = threadIdx.x;
+    const int nx = KX * 16, ny = KY * 16, n = nx > ny ? nx : ny;
+    auto load = [&](const uint32_t *bt, int64_t bt_rw, int64_t o0, int64_t n_o, int nn, int i) {
+        const int k = i >> 4, c = i & 15;
+        if (i < nn && o0 + (c >> 1) < n_o)
+            return *reinterpret_cast<const PA_G u32x4 *>(gp(bt) + (int64_t)k * bt_rw + o0 * 8 + 4 * c);
+        return u32x4{0u, 0u, 0u, 0u};
+    };
+    auto store = [&](int row0, int nn, int i, const u32x4 &v) {
+        if (i < nn) {
+            // words 4 (c & 1) .. + 3 of value o = c / 2
+            const int c = i & 15, o = c >> 1;
+            uint32_t *d = lds + (row0 + (i >> 4)) * kFusedPitch + 32 * (o >> 2) + 16 * (c & 1) + (o & 3);
+            d[0] = v.x;
+            d[4] = v.y;
+            d[8] = v.z;
+            d[12] = v.w;
+        }
+    };
+    for (int i0 = 0; i0 < n; i0 += 4096) {
+        u32x4 vx[4], vy[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            vx[u] = load(btx, btx_rw, o0x, n_ox, nx, i0 + u * 1024 + tid);
+            vy[u] = load(bty, bty_rw, o0y, n_oy, ny, i0 + u * 1024 + tid);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            store(0, nx, i0 + u * 1024 + tid, vx[u]);
+            store(KX, ny, i0 + u * 1024 + tid, vy[u]);
+        }
+    }
+}
+
 // The LDS byte addresses of the two list entries (16-bit row indices) in
 // word e, each plus o0 (< 256, the lane's slot): (index << 8) | o0, built
 // with one byte permutation each.
@@ -2384,7 +2423,7 @@ __device__ __forceinline__ uint32_t fused_addr_hi(uint32_t e, uint32_t o0) {
 // lane groups, two groups of each parity; with the halves alternating by
 // group parity the 16 lanes of a pass read 16 distinct 16-byte slots of
 // the 64 banks.  All loads are issued before any is used.
-template <int N>
+template <int N, bool First = false>
 __device__ __forceinline__ void fused_gather(const uint32_t *lds, const uint32_t (&b)[N], uint32_t (&c)[8]) {
     const char *base = reinterpret_cast<const char *>(lds);
     u32x4 r[N][2];
@@ -2393,8 +2432,20 @@ __device__ __forceinline__ void fused_gather(const uint32_t *lds, const uint32_t
         r[j][0] = *reinterpret_cast<const u32x4 *>(base + b[j]);
         r[j][1] = *reinterpret_cast<const u32x4 *>(base + (b[j] ^ 128u));
     }
+    // First: c is set from these rows (no prior value to OR with)
 #pragma unroll
     for (int j = 0; j < N; ++j) {
+        if (First && j == 0) {
+            c[0] = r[0][0].x;
+            c[1] = r[0][0].y;
+            c[2] = r[0][0].z;
+            c[3] = r[0][0].w;
+            c[4] = r[0][1].x;
+            c[5] = r[0][1].y;
+            c[6] = r[0][1].z;
+            c[7] = r[0][1].w;
+            continue;
+        }
         c[0] |= r[j][0].x;
         c[1] |= r[j][0].y;
         c[2] |= r[j][0].z;
@@ -2409,39 +2460,49 @@ __device__ __forceinline__ void fused_gather(const uint32_t *lds, const uint32_t
 // The list rows of one group, one per lane group (row a for lanes 8a ..
 // 8a + 7): c[v] = OR over the entries of the lane group's row of value
 // v ^ 4 (a & 1) of word w of its LDS row.  e holds the row's entries 0..7
-// (loaded one latent entry ahead), m the group's (even) entry count, ent the
-// row's entries as words (two to a word), of which those beyond 8 are
-// loaded here.
+// (loaded one latent entry ahead), m the group's entry count (uniform), ent
+// the row's entries as words (two to a word), of which those beyond 8 are
+// loaded here.  Whole pairs first, then an odd last entry alone.
 __device__ __forceinline__ void fused_rows(const uint32_t *lds, uint32_t o0, const u32x4 &e, uint32_t m,
                                            const PA_G uint32_t *ent, uint32_t (&c)[8]) {
+    const uint32_t mp = m >> 1;
+    if (mp == 0u) {
+        if (m == 0u) {
 #pragma unroll
-    for (int v = 0; v < 8; ++v) c[v] = 0u;
-    if (m == 0u) return;
-    if (m == 2u) {
+            for (int v = 0; v < 8; ++v) c[v] = 0u;
+        } else {
+            const uint32_t b[1] = {fused_addr_lo(e.x, o0)};
+            fused_gather<1, true>(lds, b, c);
+        }
+        return;
+    }
+    if (mp == 1u) {
         const uint32_t b[2] = {fused_addr_lo(e.x, o0), fused_addr_hi(e.x, o0)};
-        fused_gather<2>(lds, b, c);
-        return;
+        fused_gather<2, true>(lds, b, c);
+    } else {
+        {
+            const uint32_t b[4] = {fused_addr_lo(e.x, o0), fused_addr_hi(e.x, o0), fused_addr_lo(e.y, o0),
+                                   fused_addr_hi(e.y, o0)};
+            fused_gather<4, true>(lds, b, c);
+        }
+        if (mp == 3u) {
+            const uint32_t b[2] = {fused_addr_lo(e.z, o0), fused_addr_hi(e.z, o0)};
+            fused_gather<2>(lds, b, c);
+        } else if (mp >= 4u) {
+            const uint32_t b[4] = {fused_addr_lo(e.z, o0), fused_addr_hi(e.z, o0), fused_addr_lo(e.w, o0),
+                                   fused_addr_hi(e.w, o0)};
+            fused_gather<4>(lds, b, c);
+            for (uint32_t j = 4; j < mp; ++j) {
+                const uint32_t t = ent[j];
+                const uint32_t bb[2] = {fused_addr_lo(t, o0), fused_addr_hi(t, o0)};
+                fused_gather<2>(lds, bb, c);
+            }
+        }
     }
-    {
-        const uint32_t b[4] = {fused_addr_lo(e.x, o0), fused_addr_hi(e.x, o0), fused_addr_lo(e.y, o0),
-                               fused_addr_hi(e.y, o0)};
-        fused_gather<4>(lds, b, c);
-    }
-    if (m == 4u) return;
-    if (m == 6u) {
-        const uint32_t b[2] = {fused_addr_lo(e.z, o0), fused_addr_hi(e.z, o0)};
-        fused_gather<2>(lds, b, c);
-        return;
-    }
-    {
-        const uint32_t b[4] = {fused_addr_lo(e.z, o0), fused_addr_hi(e.z, o0), fused_addr_lo(e.w, o0),
-                               fused_addr_hi(e.w, o0)};
-        fused_gather<4>(lds, b, c);
-    }
-    for (uint32_t j = 4; j < m / 2; ++j) {
-        const uint32_t t = ent[j];
-        const uint32_t b[2] = {fused_addr_lo(t, o0), fused_addr_hi(t, o0)};
-        fused_gather<2>(lds, b, c);
+    if (m & 1u) {
+        const uint32_t t = mp == 1u ? e.y : mp == 2u ? e.z : mp == 3u ? e.w : ent[mp];
+        const uint32_t b[1] = {fused_addr_lo(t, o0)};
+        fused_gather<1>(lds, b, c);
     }
 }
 
@@ -2495,8 +2556,12 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &f, int64_t tile, uin
     const bool odd = (lane & 8) != 0;
     // header: the latent-entry counter (word 0), 8 output bytes (a word each)
     uint32_t *cnt = lds, *out = lds + 8, *rows = lds + kFusedPitch;
-    fused_stage(rows, f.BtX, f.btX_rw, f.kX, p0, f.n_p, f.rwt, 0);
-    fused_stage(rows, f.BtY, f.btY_rw, f.kY, qb * 8, f.n_q, f.rwt, f.kX);
+    if (f.rwt == 8) {
+        fused_stage8_pair(rows, f.BtX, f.btX_rw, f.kX, p0, f.n_p, f.BtY, f.btY_rw, f.kY, qb * 8, f.n_q);
+    } else {
+        fused_stage(rows, f.BtX, f.btX_rw, f.kX, p0, f.n_p, f.rwt, 0);
+        fused_stage(rows, f.BtY, f.btY_rw, f.kY, qb * 8, f.n_q, f.rwt, f.kX);
+    }
     if (tid < 64) rows[(f.kX + f.kY) * kFusedPitch + tid] = 0u;
     if (tid < 16) lds[tid] = 0u;
     __syncthreads();
@@ -2515,13 +2580,16 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &f, int64_t tile, uin
         u32x4 x, y;
         uint32_t mx, my;
     };
-    auto list_row = [&](const uint16_t *ent, int64_t g, int64_t cap) {
-        return reinterpret_cast<const PA_G uint32_t *>(gp(ent) + (g * 8 + a) * cap);
+    // a list row: its group's first row (uniform) plus the lane group's
+    // byte offset
+    const uint32_t offX = (uint32_t)a * (uint32_t)f.capX * 2u, offY = (uint32_t)a * (uint32_t)f.capY * 2u;
+    auto list_row = [&](const uint16_t *ent, int64_t g, int64_t cap, uint32_t off) {
+        return reinterpret_cast<const PA_G uint32_t *>(reinterpret_cast<const PA_G char *>(gp(ent) + g * 8 * cap) + off);
     };
     auto fetch = [&](int64_t s, Lists &l) {
         const int64_t gx = qb * f.n_s + s, gy = pb * f.n_s + s;
-        l.x = *reinterpret_cast<const PA_G u32x4 *>(list_row(f.entX, gx, f.capX));
-        l.y = *reinterpret_cast<const PA_G u32x4 *>(list_row(f.entY, gy, f.capY));
+        l.x = *reinterpret_cast<const PA_G u32x4 *>(list_row(f.entX, gx, f.capX, offX));
+        l.y = *reinterpret_cast<const PA_G u32x4 *>(list_row(f.entY, gy, f.capY, offY));
         l.mx = gp(f.metaX)[gx];
         l.my = gp(f.metaY)[gy];
     };
@@ -2532,8 +2600,8 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &f, int64_t tile, uin
         fetch(sn < f.n_s ? sn : f.n_s - 1, n);
         const int64_t gx = qb * f.n_s + s, gy = pb * f.n_s + s;
         uint32_t x[8], y[8];
-        fused_rows(rows, o0, c.y, __builtin_amdgcn_readfirstlane(c.my), list_row(f.entY, gy, f.capY), y);
-        fused_rows(rows, o0, c.x, __builtin_amdgcn_readfirstlane(c.mx), list_row(f.entX, gx, f.capX), x);
+        fused_rows(rows, o0, c.y, __builtin_amdgcn_readfirstlane(c.my), list_row(f.entY, gy, f.capY, offY), y);
+        fused_rows(rows, o0, c.x, __builtin_amdgcn_readfirstlane(c.mx), list_row(f.entX, gx, f.capX, offX), x);
         fused_transpose8(x);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
