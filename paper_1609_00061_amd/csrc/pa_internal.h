@@ -12,11 +12,18 @@ constexpr int kMaxA = PA_MAX_ARITY;
 constexpr int kDense = (kMaxD + 1) * (kMaxD + 1) * (kMaxD + 1);
 constexpr int kMaxDim = PA_MAX_DIMS;
 constexpr int kLineFloats = kMaxD + 2;          // a_0..a_d, E per corner line
-constexpr int kMaxTileLines = 160;              // LDS line table capacity of one plot tile
+constexpr int kMaxTileLines = 160;              // corner lines of a plot tile with one line per thread
+// corner lines of a trivariate corner tile whose threads walk the fixed axis
+// (lines built in rounds; their FP64 coordinates are not kept in LDS)
+constexpr int kMaxWalkLines = 648;
+constexpr int kMaxWalkFixed = 4;                // fixed-axis cells a thread of such a tile walks
+constexpr int kMaxWalkStrip = 8;                // walk-axis cells of its strip
 // LDS of a plot tile: the line table (floats), then as doubles the
 // declared-order coefficient table and the FP64 coordinates (two per line)
 // of the tile's corner lines
-constexpr int kPlotLineWords = (kMaxTileLines * kLineFloats + 1) / 2 * 2;
+// (for the fixed-axis-walking tiles also each thread's cell masks of its
+// previous fixed-axis line: 2 (kMaxWalkStrip + 1) words per thread)
+constexpr int kPlotLineWords = (kMaxWalkLines * kLineFloats + 2 * (kMaxWalkStrip + 1) * 256 + 1) / 2 * 2;
 constexpr int kPlotLdsWords = kPlotLineWords + 2 * (kDense + 2 * kMaxTileLines);
 static_assert(kMaxTileLines <= 256, "one corner line per thread of a 256-thread plot tile");
 
@@ -56,6 +63,7 @@ struct PlotRel {
     uint32_t *out;
     PlotCounters *counters;    // escalation counters of the relation's system (null: the launch's)
     int tw, ta, tb, s;
+    int walk_fixed;            // trivariate corner tiles: a thread walks ta fixed-axis cells (tw x tb threads)
     int64_t tiles_w, tiles_walk, tiles_fixed, n_tiles;
     int64_t tile_base;         // prefix over relations of n_tiles (multi-relation launches)
 };

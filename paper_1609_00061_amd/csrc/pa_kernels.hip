@@ -702,12 +702,111 @@ __device__ void center_tile(const PlotRel &R, int64_t tile, float *lines, double
     }
 }
 
+// A trivariate corner tile whose threads walk the fixed axis (R.walk_fixed):
+// tw words x tb strips of s cell rows along the walk axis x ta cells of the
+// fixed axis.  A thread owns one 32-cell word of one strip and walks the
+// tile's ta fixed-axis cells: it evaluates each of the (ta + 1) x (s + 1)
+// corner lines bounding them once (a line between two fixed-axis cells
+// serves both), keeping the previous fixed-axis line's cell masks in
+// registers.  The tile stages the coefficient table and the FP32 restriction
+// and bound of each of its corner lines in LDS (built in rounds of one line
+// per thread); a line's FP64 coordinates, which only the escalated corners
+// use, are formed again where needed.
+__device__ void plot_tile3w(const PlotRel &R, int64_t tile, float *lines, double *tabs, PlotCount &cnt) {
+    const PlotView V = plot_view(R);
+    const double coefs = load_coefs(V);
+    const int tid = threadIdx.x;
+    const int tw_n = R.tw, ta = R.ta, tb = R.tb, s = R.s;
+    const uint32_t tiles_w = (uint32_t)R.tiles_w, tiles_walk = (uint32_t)R.tiles_walk;
+    uint32_t t = (uint32_t)tile;
+    const int64_t t_w = t % tiles_w;
+    t /= tiles_w;
+    const int64_t t_walk = t % tiles_walk;
+    const int64_t t_fixed = t / tiles_walk;
+    const int rwalk = V.rwalk, rp = V.rp;
+    const int span = tb * s;
+    const int64_t b0 = t_walk * span, a0 = t_fixed * ta;
+    const int nwl = span + 1, nlines = nwl * (ta + 1);
+    const int twi = tid % tw_n, strip = tid / tw_n;
+    const int64_t w = t_w * tw_n + twi;
+    const int64_t cs = b0 + (int64_t)strip * s;
+    const bool active = strip < tb && w < V.row_words && cs < rwalk;
+    const bool pad = w * 32 >= rp;
+    const int k0 = (int)(w * 32);
+    const int kmax = pad ? 0 : min(32, rp - k0);
+    float xv[33];
+    const int kb = (active && !pad) ? k0 : 0;
+#pragma unroll
+    for (int kk = 0; kk < 33; ++kk) xv[kk] = (float)corner_coord(V.lop, V.stp, kb + kk);
+    double *cdl = tabs;
+    store_coefs(coefs, cdl);
+    __syncthreads();
+    if (V.mode == PA_PLOT_FP32_ESCALATE)
+        for (int li = tid; li < nlines; li += (int)blockDim.x) {
+            const int lf = li / nwl, lw = li - lf * nwl;
+            const int64_t ia = a0 + lf, ib = b0 + lw;
+            if (ia <= V.res0 && ib <= rwalk)
+                line_coefs(V, cdl, corner_coord(V.lo0, V.st0, ia), corner_coord(V.lo1, V.st1, ib),
+                           lines + li * kLineFloats);
+        }
+    __syncthreads();
+    if (!active) return;
+    const uint32_t vmask = pad ? 0u : (kmax == 32 ? 0xffffffffu : ((1u << kmax) - 1u));
+    const int nc = (int)(min((int64_t)rwalk, cs + s) - cs);         // cell rows of the strip, 1..s
+    const int na = (int)min((int64_t)ta, (int64_t)V.res0 - a0);     // fixed-axis cells of the tile, 1..ta
+    // cell masks (some corner f <= 0 / f >= 0; corners i and i + 1 of cell
+    // i) of this thread's walk lines cs + j on the previous fixed-axis line,
+    // in LDS after the line table (2 (kMaxWalkStrip + 1) words per thread)
+    uint32_t *prev = reinterpret_cast<uint32_t *>(lines + kMaxWalkLines * kLineFloats) + tid;
+    constexpr int kPrevStride = 256;
+    for (int lf = 0; lf <= na; ++lf) {
+        // the last fixed-axis line of a tile belongs to the next tile, except
+        // at the end of the axis; the first walk line of a strip to the
+        // previous strip, except at 0
+        const bool own_f = lf < na || a0 + lf == V.res0;
+        const double y0 = corner_coord(V.lo0, V.st0, a0 + lf);
+        const int64_t row_base = (a0 + lf - 1) * V.res1;
+        uint32_t ql = 0u, qg = 0u;        // this fixed-axis line's masks at walk line j - 1
+        for (int j = 0; j <= nc; ++j) {
+            uint32_t l = 0u, g = 0u;
+            if (!pad) {
+                const int li = lf * nwl + (int)(cs - b0) + j;
+                const double yl[2] = {y0, corner_coord(V.lo1, V.st1, cs + j)};
+                Corners LE, GE;
+                eval_line(V, lines + li * kLineFloats, xv, yl, cdl, k0, kmax, own_f && (j > 0 || cs == 0), LE, GE,
+                          cnt);
+                apply_target(V.target, LE, GE);
+                l = LE.lo | __builtin_amdgcn_alignbit(LE.hi, LE.lo, 1);
+                g = GE.lo | __builtin_amdgcn_alignbit(GE.hi, GE.lo, 1);
+            }
+            if (lf > 0 && j > 0) {
+                // fixed-axis cell a0 + lf - 1, walk row cs + j - 1
+                const uint32_t pl0 = prev[2 * (j - 1) * kPrevStride], pg0 = prev[(2 * (j - 1) + 1) * kPrevStride];
+                const uint32_t pl1 = prev[2 * j * kPrevStride], pg1 = prev[(2 * j + 1) * kPrevStride];
+                V.out[(row_base + cs + j - 1) * V.row_words + w] = (pl0 | pl1 | ql | l) & (pg0 | pg1 | qg | g) & vmask;
+            }
+            if (j > 0) {
+                prev[2 * (j - 1) * kPrevStride] = ql;
+                prev[(2 * (j - 1) + 1) * kPrevStride] = qg;
+            }
+            ql = l;
+            qg = g;
+        }
+        prev[2 * nc * kPrevStride] = ql;
+        prev[(2 * nc + 1) * kPrevStride] = qg;
+    }
+}
+
 // One plot tile.  lines: kMaxTileLines * kLineFloats floats of LDS; tabs:
 // the declared-order coefficient table (kDense doubles of LDS), then the FP64
 // coordinates of the tile's corner lines (two per line).
 __device__ void plot_tile(const PlotRel &R, int64_t tile, float *lines, double *tabs, PlotCount &cnt) {
     if (R.n == 2) {
         plot_tile2(R, tile, lines, tabs, cnt);
+        return;
+    }
+    if (R.walk_fixed) {
+        plot_tile3w(R, tile, lines, tabs, cnt);
         return;
     }
     const PlotView V = plot_view(R);

@@ -770,6 +770,27 @@ static void plot_tiling(PlotRel &R, int strip) {
     R.tw = (int)std::min<int64_t>(32, R.row_words);
     const int ts = 256 / R.tw;
     R.s = std::max(1, strip);
+    R.walk_fixed = 0;
+    if (n == 3 && R.rule == kRuleCorner) {
+        // a thread per word and strip, walking up to kMaxWalkFixed cells of
+        // the fixed axis: each corner line it evaluates serves the cells on
+        // both sides of it
+        R.walk_fixed = 1;
+        R.tb = ts;
+        R.ta = kMaxWalkFixed;
+        R.s = std::min(R.s, kMaxWalkStrip);
+        auto wl = [&]() { return ((int64_t)R.tb * R.s + 1) * (R.ta + 1); };
+        while (wl() > kMaxWalkLines) {
+            if (R.s > 1) --R.s;
+            else if (R.ta > 1) --R.ta;
+            else --R.tb;
+        }
+        R.tiles_w = (R.row_words + R.tw - 1) / R.tw;
+        R.tiles_walk = (R.res[1] + (int64_t)R.tb * R.s - 1) / ((int64_t)R.tb * R.s);
+        R.tiles_fixed = (R.res[0] + R.ta - 1) / R.ta;
+        R.n_tiles = R.tiles_w * R.tiles_walk * R.tiles_fixed;
+        return;
+    }
     if (n == 1) {
         R.ta = 1;
         R.tb = 1;
