@@ -805,10 +805,6 @@ __device__ void plot_tile(const PlotRel &R, int64_t tile, float *lines, double *
         plot_tile2(R, tile, lines, tabs, cnt);
         return;
     }
-    if (R.walk_fixed) {
-        plot_tile3w(R, tile, lines, tabs, cnt);
-        return;
-    }
     const PlotView V = plot_view(R);
     // the only loads of the tile (coefficients), issued first
     const double coefs = load_coefs(V);
@@ -914,15 +910,18 @@ __device__ void plot_tile(const PlotRel &R, int64_t tile, float *lines, double *
     }
 }
 
-// A plot tile of the rule CENTER selects at compile time (corner tiles, or
-// the centre tiles of the sample-in-center plot), so that each kernel holds
-// the registers of one rule only.  Plots of one plan share its rule; the
-// single persistent launch runs corner tiles only (centre-rule plans use
-// the grouped executor).
-template <bool CENTER>
+// A plot tile of the kind MODE selects at compile time, so that each kernel
+// holds the registers of its tiles only: 0 corner tiles other than the
+// fixed-axis-walking trivariate ones, 1 the centre tiles of the
+// sample-in-center plot, 2 the fixed-axis-walking trivariate corner tiles,
+// -1 any corner tile (the one-relation plotting launch and the single
+// persistent launch, which runs corner tiles only: centre-rule plans use the
+// grouped executor).  The step of a relation carries its mode.
+template <int MODE>
 __device__ __forceinline__ void plot_tile_rule(const PlotRel &R, int64_t tile, float *lines, double *tabs,
                                                PlotCount &cnt) {
-    if (CENTER) center_tile(R, tile, lines, tabs, cnt);
+    if (MODE == 1) center_tile(R, tile, lines, tabs, cnt);
+    else if (MODE == 2 || (MODE == -1 && R.walk_fixed)) plot_tile3w(R, tile, lines, tabs, cnt);
     else plot_tile(R, tile, lines, tabs, cnt);
 }
 
@@ -966,7 +965,7 @@ __global__ __launch_bounds__(256) void k_plot(const PlotRel *__restrict__ rels, 
     for (int64_t tile = blockIdx.x; tile < total_tiles; tile += gridDim.x) {
         const PlotRel &R = rels[find_rel(rels, nrel, tile)];
         sink.use(R, counters);
-        plot_tile_rule<CENTER>(R, tile - R.tile_base, reinterpret_cast<float *>(lds),
+        plot_tile_rule<CENTER ? 1 : -1>(R, tile - R.tile_base, reinterpret_cast<float *>(lds),
                   reinterpret_cast<double *>(lds + kPlotLineWords), sink.cnt);
         __syncthreads();
     }
@@ -2993,7 +2992,8 @@ __device__ __forceinline__ void group_run(const PStep *__restrict__ steps, int f
         const PStep &st = steps[find_step(steps, first, count, item)];
         if (kind == kStepPlot && st.kind == kStepPlot) {
             sink.use(st.plot, counters);
-            plot_tile_rule<mode == 1>(st.plot, item - st.tile_base, reinterpret_cast<float *>(lds),
+            // mode 3: any corner tile (the single persistent launch)
+            plot_tile_rule<mode == 3 ? -1 : mode>(st.plot, item - st.tile_base, reinterpret_cast<float *>(lds),
                       reinterpret_cast<double *>(lds + kPlotLineWords), sink.cnt);
         } else if (kind == kStepContract) {
             const int64_t u0 = (item - st.tile_base) * st.per_tile;
@@ -3073,6 +3073,7 @@ hipError_t launch_group(int kind, int mode, const PStep *d_steps, int first, int
     switch (kind) {
         case kStepPlot:
             if (mode == 1) PA_GROUP(kStepPlot + 10);      // centre-rule plots
+            else if (mode == 2) PA_GROUP(kStepPlot + 20); // fixed-axis-walking trivariate corner plots
             else PA_GROUP(kStepPlot);
             break;
         case kStepGemm:
@@ -3171,7 +3172,10 @@ __global__ __launch_bounds__(256, 2) void k_persist(const PStep *__restrict__ st
         const int64_t i1 = min(g->t1, i0 + g->chunk);
         const int first = g->first, count = g->count;
         switch (g->kind + 10 * g->mode) {
-            case kStepPlot: group_run<kStepPlot>(steps, first, count, i0, i1, 0, counters, lds, 0u, 1u); break;
+            case kStepPlot:
+            case kStepPlot + 20:
+                group_run<kStepPlot + 30>(steps, first, count, i0, i1, 0, counters, lds, 0u, 1u);
+                break;
             case kStepGemm: group_run<kStepGemm>(steps, first, count, i0, i1, 0, counters, lds, 0u, 1u); break;
             case kStepGemm + 10:
                 group_run<kStepGemm + 10>(steps, first, count, i0, i1, 0, counters, lds, 0u, 1u);

@@ -1347,7 +1347,9 @@ static int build_steps(pa_plan *P) {
         PStep s;
         std::memset(&s, 0, sizeof(s));
         s.kind = kStepPlot;
-        s.mode = P->plotrel1_dev[i].rule == kRuleCenter ? 1 : 0;    // one kernel per plotting rule
+        // one kernel per kind of plot tile: corner, centre rule, or the
+        // fixed-axis-walking trivariate corner tiles
+        s.mode = P->plotrel1_dev[i].rule == kRuleCenter ? 1 : (P->plotrel1_dev[i].walk_fixed ? 2 : 0);
         s.plot = P->plotrel1_dev[i];
         s.n_tiles = s.plot.n_tiles;
         producer[P->plots[i].buf] = (int)st.size();
