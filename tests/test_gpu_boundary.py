@@ -1,8 +1,9 @@
 """GPU tests of the C ABI's whole-system entry points, called directly:
 pa_solve_system and pa_solve_batch against the oracle with their reports,
 pa_workspace_bytes against the plans it sizes (and a caller-owned workspace
-of exactly that size), and repeated executions of one plan into new outputs
-on a non-blocking stream without synchronizing in between."""
+of exactly that size), repeated executions of one plan into new outputs on a
+non-blocking stream without synchronizing in between, and the LDS read-rate
+reference."""
 import numpy as np
 import pytest
 
@@ -107,3 +108,18 @@ def test_new_outputs_without_sync(graph):
     torch.cuda.synchronize()
     for o in outs:
         assert np.array_equal(to_host(o, p.dims), ref)
+
+
+def test_lds_read_rate():
+    """pa_lds_read_rate (the reference of the fused step's LDS roofline): a
+    finite positive rate, at most the device's LDS read capacity of 256
+    bytes per clock per CU at a 2.4 GHz clock (with headroom for a higher
+    clock); a null output pointer is refused with PA_EINVAL."""
+    import ctypes
+    import torch
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    r = pa.lds_read_rate()
+    note("lds read rate", r, "bytes/s on", cus, "CUs")
+    assert 0.0 < r < 256.0 * cus * 3.0e9
+    L = pa.load()
+    assert L.pa_lds_read_rate(None, None) == pa.PA_EINVAL
