@@ -2407,40 +2407,13 @@ hipError_t launch_row_list(const RowListArgs &l, hipStream_t s) {
 // (zero for o0 + ol >= n_o or w >= rwt): values 0..3 of word w are the 16
 // bytes at 16 w, values 4..7 those at 128 + 16 w, so that 8 lanes reading
 // one row's word w = 0..7 cover 128 contiguous bytes with each of their two
-// 16-byte loads.  1024 threads; the loads of four rounds are issued before
-// their stores.
+// 16-byte loads.  This stages t of fewer than 8 words (one word per lane, a
+// wave writing one row: 64 distinct banks); fused_stage8_pair stages t of 8
+// words.  1024 threads; the loads of four rounds are issued before their
+// stores.
 __device__ __forceinline__ void fused_stage(uint32_t *lds, const uint32_t *bt, int64_t bt_rw, int K, int64_t o0,
                                             int64_t n_o, int rwt, int row0) {
     const int tid = threadIdx.x;
-    if (rwt == 8) {
-        // 16 groups of 4 words per row: group c covers o0 + c / 2, words 4 (c & 1) ..
-        const int n = K * 16;
-        for (int i0 = 0; i0 < n; i0 += 4096) {
-            u32x4 v[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int i = i0 + u * 1024 + tid;
-                const int k = i >> 4, c = i & 15;
-                v[u] = u32x4{0u, 0u, 0u, 0u};
-                if (i < n && o0 + (c >> 1) < n_o)
-                    v[u] = *reinterpret_cast<const PA_G u32x4 *>(gp(bt) + (int64_t)k * bt_rw + o0 * 8 + 4 * c);
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int i = i0 + u * 1024 + tid;
-                if (i < n) {
-                    // words 4 (c & 1) .. + 3 of value o = c / 2
-                    const int c = i & 15, o = c >> 1;
-                    uint32_t *d = lds + (row0 + (i >> 4)) * kFusedPitch + 32 * (o >> 2) + 16 * (c & 1) + (o & 3);
-                    d[0] = v[u].x;
-                    d[4] = v[u].y;
-                    d[8] = v[u].z;
-                    d[12] = v[u].w;
-                }
-            }
-        }
-        return;
-    }
     const int n = K * 64;
     for (int i0 = 0; i0 < n; i0 += 4096) {
         uint32_t v[4];
