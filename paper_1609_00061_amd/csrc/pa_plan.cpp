@@ -2181,9 +2181,17 @@ extern "C" int64_t pa_plan_describe(const pa_system *sys, const int32_t *exposed
         }
         s << "]"
           << ",\"plots\":[";
-        for (size_t i = 0; i < P->plots.size(); ++i)
+        for (size_t i = 0; i < P->plots.size(); ++i) {
             s << (i ? "," : "") << "{\"rel\":" << P->plots[i].rel << ",\"buf\":" << P->plots[i].buf
-              << ",\"vars\":" << join(P->plots[i].layout.vars) << "}";
+              << ",\"vars\":" << join(P->plots[i].layout.vars);
+            if (i < P->plotrel_host.size()) {
+                // the plotting tiles: words x strips x fixed-axis cells, rows per strip
+                const PlotRel &R = P->plotrel_host[i];
+                s << ",\"tiles\":" << R.n_tiles << ",\"tile\":[" << R.tw << "," << R.tb << "," << R.ta << "," << R.s
+                  << "],\"walk_fixed\":" << R.walk_fixed;
+            }
+            s << "}";
+        }
         s << "],\"ops\":[";
         for (size_t i = 0; i < P->ops.size(); ++i) s << (i ? "," : "") << P->ops[i].describe();
         s << "],\"buffers\":[";

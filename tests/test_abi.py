@@ -143,6 +143,35 @@ def _fused_system(res, seed=1, c0=0.0):
     return inputs.System([(-3.0, 3.0, r) for r in res], rels, (0, 3), name=f"fused{res}")
 
 
+def test_plot_tilings():
+    """Plot tiles as planned (Sec. 3.2 plotting; host logic): trivariate
+    corner plots walk the fixed axis (a thread per 32-cell word and strip of
+    s rows, ta fixed-axis cells each, tw x tb = 256 threads), with s capped
+    so that the tile's (tb s + 1)(ta + 1) corner lines fit the 648-line
+    table; centre-rule and bivariate plots keep their one-line-per-thread
+    tiles.  Tile counts cover every cell exactly once (ceil divisions)."""
+    c3 = inputs.config3()
+    for strip, s_exp in ((1, 1), (2, 2), (4, 4), (8, 4)):
+        for p in pa.describe_plan(c3, plot_strip=strip)["plots"]:
+            tw, tb, ta, s = p["tile"]
+            assert p["walk_fixed"] == 1 and (tw, tb, ta, s) == (8, 32, 4, s_exp), (strip, p)
+            assert (tb * s + 1) * (ta + 1) <= 648
+            # 256 cells per axis: 1 word block x ceil(256 / (tb s)) x 256 / ta
+            assert p["tiles"] == -(-256 // (tb * s)) * (256 // ta), p
+    ragged = inputs.System([(-3.0, 3.0, r) for r in (30, 65, 31)],
+                           [inputs.random_relation(inputs.SplitMix64(5), (0, 1, 2))], (0, 2), name="ragged")
+    p = pa.describe_plan(ragged, plot_strip=4)["plots"][0]
+    tw, tb, ta, s = p["tile"]
+    assert p["walk_fixed"] == 1 and tw * tb <= 256 and (tb * s + 1) * (ta + 1) <= 648, p
+    res = {v: ragged.axes[v][2] for v in range(3)}
+    fixed, walk = res[p["vars"][0]], res[p["vars"][1]]
+    words = -(-res[p["vars"][2]] // 32)
+    assert p["tiles"] == -(-words // tw) * -(-walk // (tb * s)) * -(-fixed // ta), p
+    centre = pa.describe_plan(c3, plot_rule=pa.RULE_CENTER, tolerance=0.01)["plots"][0]
+    assert centre["walk_fixed"] == 0
+    assert all(p["walk_fixed"] == 0 for p in pa.describe_plan(inputs.config2())["plots"])
+
+
 def test_fused_pass_pair_plan():
     """sparse_pass = 3 fuses the ternary workload's two passes and their
     streamed contraction: two row-list steps (one per pass, 65536 list rows,
