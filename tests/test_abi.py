@@ -196,6 +196,14 @@ def test_fused_pass_pair_plan():
                 [129, 255, 256, 13, 24, 255]):
         d = pa.describe_plan(_fused_system(res), sparse_pass=3)
         assert _kernels(d) == ["row_list", "row_list", "fused_pass_pair"], res
+        lx, ly, f = d["ops"]
+        # 16-bit entries: a list row holds every latent bit, at least 8 entries
+        # (one 16-byte load), 16-byte aligned; the LDS rows of both operands
+        # and the zero row fit the tile's 513
+        for l, k in ((lx, f["kx"]), (ly, f["ky"])):
+            assert l["cap"] % 8 == 0 and l["cap"] >= max(8, k), (res, l)
+        assert lx["lbase"] == 0 and ly["lbase"] == f["kx"] and lx["zrow"] == f["kx"] + f["ky"] <= 512, res
+        assert f["tiles"] == -(-f["n_p"] // 8) * -(-f["n_q"] // 8), res
     # no pattern, no fusion: the chain's passes feed MFMA contractions
     assert _kernels(pa.describe_plan(inputs.config2(), sparse_pass=3)) == \
         _kernels(pa.describe_plan(inputs.config2(), sparse_pass=2))
