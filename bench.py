@@ -571,7 +571,7 @@ def main():
                     help="after the run, copy a buffer of this size 3 times (scales HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported "
               f"(independent systems would shard round-robin across GPUs without communication)", file=sys.stderr)
         sys.exit(2)
 

@@ -72,7 +72,7 @@ typedef enum {
     PA_EINVAL = 1,            /* invalid argument (see each entry point)          */
     PA_ENOMEM = 2,            /* workspace too small, allocation or size cap hit  */
     PA_EHIP = 3,              /* HIP runtime error (no device, launch failure...) */
-    PA_EUNSUPPORTED = 4       /* valid but outside what this build implements     */
+    PA_EUNSUPPORTED = 4       /* valid but outside what the library implements    */
 } pa_status;
 
 /* One variable's discretization: a port's bounds and resolution

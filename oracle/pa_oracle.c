@@ -16,8 +16,8 @@
  *     Horner with correctly rounded fma; this sequence *is* the definition of
  *     the FP64 value that every implementation must reproduce bit for bit);
  *   - the corner sign-change plot: a pixel (closed cell) is set iff among its
- *     2^n corners one has f <= 0 and one has f >= 0 (the plotting method of
- *     this build; the paper allows any sufficiently fast and accurate plotting
+ *     2^n corners one has f <= 0 and one has f >= 0 (the corner plotting
+ *     method of the library; the paper allows any sufficiently fast and accurate plotting
  *     method, Sec. 3.6); a NaN corner counts as neither;
  *   - generalized array multiplication (Alg. "Generalized array
  *     multiplication", eqn GAM): A'(e') = OR over link entries e projecting to
